@@ -1,0 +1,192 @@
+"""Seeded synthetic workloads shaped like the paper's test problems.
+
+This module is shared by the CPU oracle, the tests and the benchmark.  It only
+*describes* problems (grids, region maps, per-region cross sections, parameter
+draws) and synthesises the source input; it holds none of the solver's
+arithmetic (no transport operator, no sweep, no Krylov, no ROM).
+
+A problem is a plain dict:
+
+  dim            1 (slab) or 2 (X-Y)
+  nx, ny         cells per direction (ny == 1 in 1D)
+  box            (x0, x1, y0, y1)   (y0, y1 unused in 1D)
+  quad           ('gl', n)                    1D Gauss-Legendre S_n
+                 ('cl', n_theta, n_z, folded) Chebyshev-Legendre product rule
+  region         int32 [ncell]  region id of each cell, cell = k*nx + i
+  sigma_t        float64 [R]    total cross section per region
+  sigma_s        float64 [R]    scattering cross section per region
+  source         float64 [ncell*nloc] DG moments of the isotropic source
+  inflow         float          isotropic constant inflow value g
+  mu             float64 [d]    the parameter the problem was made from
+
+DG moment convention (the library's layout): dof = cell*nloc + p + 2*q, with
+the per-cell orthonormal tensor Legendre basis e_p(x) e_q(y),
+e_0 = 1/sqrt(h), e_1 = sqrt(3) s / sqrt(h), s in [-1, 1] the local coordinate.
+The source moments are the L2 projection of G computed with a 4x4 (4 in 1D)
+Gauss-Legendre rule per cell; that rule is part of the workload definition.
+"""
+import numpy as np
+
+__all__ = [
+    "source_moments", "cfg1", "cfg2", "cfg3_mu", "cfg3_problem", "cfg3_train_test",
+    "cfg4_batch", "tiny_2d", "tiny_1d", "CFG3_BOX_LO", "CFG3_BOX_HI", "cfg3_box_centre",
+]
+
+_GL4_X, _GL4_W = np.polynomial.legendre.leggauss(4)
+
+
+def source_moments(func, dim, nx, ny, box):
+    """DG moments of func(x, y) on the uniform grid (4-point rule per axis)."""
+    x0, x1, y0, y1 = box
+    hx = (x1 - x0) / nx
+    if dim == 1:
+        xc = x0 + (np.arange(nx) + 0.5) * hx
+        X = xc[:, None] + 0.5 * hx * _GL4_X[None, :]
+        F = func(X, np.zeros_like(X))
+        w = 0.5 * hx * _GL4_W
+        m0 = (F * w).sum(1) / np.sqrt(hx)
+        m1 = (F * w * np.sqrt(3.0) * _GL4_X).sum(1) / np.sqrt(hx)
+        return np.stack([m0, m1], 1).reshape(-1)
+    hy = (y1 - y0) / ny
+    xc = x0 + (np.arange(nx) + 0.5) * hx
+    yc = y0 + (np.arange(ny) + 0.5) * hy
+    # points [ky, ix, gy, gx]
+    X = xc[None, :, None, None] + 0.5 * hx * _GL4_X[None, None, None, :]
+    Y = yc[:, None, None, None] + 0.5 * hy * _GL4_X[None, None, :, None]
+    X, Y = np.broadcast_arrays(X, Y)
+    F = func(X, Y)
+    wx = 0.5 * hx * _GL4_W
+    wy = 0.5 * hy * _GL4_W
+    W = wy[:, None] * wx[None, :]
+    bx = [np.ones(4), np.sqrt(3.0) * _GL4_X]
+    out = np.empty((ny, nx, 4))
+    for q in range(2):
+        for p in range(2):
+            B = bx[q][:, None] * bx[p][None, :]
+            out[:, :, p + 2 * q] = (F * (W * B)[None, None]).sum((2, 3)) / np.sqrt(hx * hy)
+    return out.reshape(-1)
+
+
+def _block_regions(nx, ny, nbx, nby):
+    """Region id of each cell for an nbx x nby block layout (region = by*nbx + bx)."""
+    i = np.arange(nx)
+    k = np.arange(ny)
+    bx = (i * nbx) // nx
+    by = (k * nby) // ny
+    return (by[:, None] * nbx + bx[None, :]).reshape(-1).astype(np.int32)
+
+
+def cfg1(seed=1, nx=128, n_ord=16):
+    """1D slab [0,1], P1 DG, S16 GL; sigma_s = mu1 on [0,.5), mu2 on [.5,1];
+    sigma_a = 0.1, G = 1, zero inflow.  mu1, mu2 ~ U[1, 100]."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(1.0, 100.0, size=2)
+    region = (np.arange(nx) * 2 // nx).astype(np.int32)
+    sig_a = 0.1
+    sigma_s = mu.copy()
+    sigma_t = sigma_s + sig_a
+    box = (0.0, 1.0, 0.0, 1.0)
+    G = source_moments(lambda x, y: np.ones_like(x), 1, nx, 1, box)
+    return dict(dim=1, nx=nx, ny=1, box=box, quad=("gl", n_ord), region=region,
+                sigma_t=sigma_t, sigma_s=sigma_s, source=G, inflow=0.0, mu=mu)
+
+
+def cfg2(seed=2, n=64, n_theta=16, n_z=16, width=0.1):
+    """2D [0,1]^2, Q1 DG, CL(16,16) folded (128 ordinates); 4x4 blocks with
+    sigma_s ~ 10^U[-1,2], sigma_a ~ U[0,1]; Gaussian source of width 0.1 at
+    the centre; zero inflow."""
+    rng = np.random.default_rng(seed)
+    sig_s = 10.0 ** rng.uniform(-1.0, 2.0, size=16)
+    sig_a = rng.uniform(0.0, 1.0, size=16)
+    box = (0.0, 1.0, 0.0, 1.0)
+    G = source_moments(lambda x, y: np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / width ** 2),
+                       2, n, n, box)
+    return dict(dim=2, nx=n, ny=n, box=box, quad=("cl", n_theta, n_z, True),
+                region=_block_regions(n, n, 4, 4), sigma_t=sig_s + sig_a, sigma_s=sig_s,
+                source=G, inflow=0.0, mu=np.concatenate([sig_s, sig_a]))
+
+
+# ---- parametric checkerboard family (configs 3, 4, 5) -------------------------------
+# mu = (mu1, mu2, mu3, mu4): scattering levels of the two checkerboard colours
+# (log10 mu1, log10 mu2 ~ U[0, 2]), absorption (U[0, 1]) and source width
+# (U[0.05, 0.2]).  The box used for normalisation is in (log10 mu1, log10 mu2,
+# mu3, mu4) coordinates.
+CFG3_BOX_LO = np.array([0.0, 0.0, 0.0, 0.05])
+CFG3_BOX_HI = np.array([2.0, 2.0, 1.0, 0.20])
+
+
+def cfg3_mu(rng, n):
+    u = rng.uniform(size=(n, 4))
+    z = CFG3_BOX_LO + u * (CFG3_BOX_HI - CFG3_BOX_LO)
+    return np.stack([10.0 ** z[:, 0], 10.0 ** z[:, 1], z[:, 2], z[:, 3]], 1)
+
+
+def cfg3_box_centre():
+    z = 0.5 * (CFG3_BOX_LO + CFG3_BOX_HI)
+    return np.array([10.0 ** z[0], 10.0 ** z[1], z[2], z[3]])
+
+
+def cfg3_problem(mu, n=96, n_theta=16, n_z=16):
+    """Checkerboard of 4x4 blocks: colour A (bx+by even) scatters with mu1,
+    colour B with mu2; sigma_a = mu3 everywhere; G = exp(-|x-c|^2/mu4^2)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    blocks = _block_regions(n, n, 4, 4)
+    bx = blocks % 4
+    by = blocks // 4
+    region = ((bx + by) % 2).astype(np.int32)
+    sigma_s = np.array([mu[0], mu[1]])
+    sigma_t = sigma_s + mu[2]
+    box = (0.0, 1.0, 0.0, 1.0)
+    w = mu[3]
+    G = source_moments(lambda x, y: np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / w ** 2),
+                       2, n, n, box)
+    return dict(dim=2, nx=n, ny=n, box=box, quad=("cl", n_theta, n_z, True),
+                region=region, sigma_t=sigma_t, sigma_s=sigma_s, source=G, inflow=0.0,
+                mu=mu)
+
+
+def cfg3_train_test(n_train=64, n_test=256, seed_train=30, seed_test=31):
+    """Training set = box centre followed by n_train-1 draws; test set = n_test draws."""
+    tr = np.concatenate([cfg3_box_centre()[None], cfg3_mu(np.random.default_rng(seed_train),
+                                                            n_train - 1)], 0)
+    te = cfg3_mu(np.random.default_rng(seed_test), n_test)
+    return tr, te
+
+
+def cfg4_batch(seed=4, n_inst=512):
+    """Uneven batch: grid in {32,64,96,128}^2, ordinates in {64, 128}; mu as config 3.
+    64 ordinates = CL(16, 8) folded, 128 = CL(16, 16) folded."""
+    rng = np.random.default_rng(seed)
+    grids = rng.choice([32, 64, 96, 128], size=n_inst)
+    nords = rng.choice([64, 128], size=n_inst)
+    mus = cfg3_mu(rng, n_inst)
+    return [(int(g), int(no), m) for g, no, m in zip(grids, nords, mus)]
+
+
+def tiny_2d(seed=0, nx=3, ny=3, quad=("cl", 4, 2, False), n_regions=2, inflow=0.0,
+            smooth_source=True):
+    """Small random 2D problem for brute-force checks."""
+    rng = np.random.default_rng(seed)
+    region = rng.integers(0, n_regions, size=nx * ny).astype(np.int32)
+    sig_s = rng.uniform(0.5, 3.0, size=n_regions)
+    sig_a = rng.uniform(0.1, 1.0, size=n_regions)
+    box = (0.0, 1.0, 0.0, 1.5)
+    if smooth_source:
+        G = source_moments(lambda x, y: 1.0 + np.sin(2 * x) * np.cos(3 * y), 2, nx, ny, box)
+    else:
+        G = rng.uniform(-1, 1, size=nx * ny * 4)
+    return dict(dim=2, nx=nx, ny=ny, box=box, quad=quad, region=region,
+                sigma_t=sig_s + sig_a, sigma_s=sig_s, source=G, inflow=inflow,
+                mu=np.concatenate([sig_s, sig_a]))
+
+
+def tiny_1d(seed=0, nx=4, n_ord=4, n_regions=2, inflow=0.0):
+    rng = np.random.default_rng(seed)
+    region = rng.integers(0, n_regions, size=nx).astype(np.int32)
+    sig_s = rng.uniform(0.5, 3.0, size=n_regions)
+    sig_a = rng.uniform(0.1, 1.0, size=n_regions)
+    box = (0.0, 1.0, 0.0, 1.0)
+    G = source_moments(lambda x, y: 1.0 + x * x, 1, nx, 1, box)
+    return dict(dim=1, nx=nx, ny=1, box=box, quad=("gl", n_ord), region=region,
+                sigma_t=sig_s + sig_a, sigma_s=sig_s, source=G, inflow=inflow,
+                mu=np.concatenate([sig_s, sig_a]))

@@ -1,0 +1,233 @@
+"""Pins of the oracle's quadrature, DG operators and transport sweep against
+facts fixed by the paper and by mathematics (closed forms, invariants,
+conservation, brute force)."""
+import numpy as np
+import pytest
+
+from oracle import dg
+from oracle import transport as tr
+from oracle.quadrature import chebyshev_legendre, slab_gl
+from synth import tiny_1d, tiny_2d
+
+
+# ---------------------------------------------------------------- quadrature (section 2.1)
+@pytest.mark.parametrize("nt,nz,folded", [(4, 2, False), (16, 16, True), (16, 8, True), (30, 6, False)])
+def test_cl_moments(nt, nz, folded):
+    ox, oy, w = chebyshev_legendre(nt, nz, folded)
+    assert len(w) == nt * (nz // 2 if folded else nz)
+    assert abs(w.sum() - 1.0) < 1e-14                      # normalised rule
+    assert abs((w * ox).sum()) < 1e-14 and abs((w * oy).sum()) < 1e-14
+    # (1/4pi) int Omega_x^2 = (1/4pi) int Omega_y^2 = 1/3 (exact for nz >= 2)
+    assert abs((w * ox ** 2).sum() - 1 / 3) < 1e-14
+    assert abs((w * oy ** 2).sum() - 1 / 3) < 1e-14
+    assert np.all(ox ** 2 + oy ** 2 <= 1 + 1e-14)
+
+
+def test_cl_ordering_and_angles():
+    ox, oy, w = chebyshev_legendre(4, 2)
+    th = np.arctan2(oy, ox) % (2 * np.pi)
+    # j = (j2 - 1) N_theta + j1 with theta_j1 = (2 j1 - 1) pi / N_theta
+    np.testing.assert_allclose(th[:4], (2 * np.arange(1, 5) - 1) * np.pi / 4, atol=1e-14)
+    np.testing.assert_allclose(th[4:], th[:4], atol=1e-14)
+
+
+def test_gl_exactness():
+    x, _, w = slab_gl(8)
+    for k in range(16):  # exact up to degree 2n-1 = 15; (1/2) int_{-1}^{1} x^k
+        exact = 0.0 if k % 2 else 1.0 / (k + 1)
+        assert abs((w * x ** k).sum() - exact) < 1e-14
+
+
+def test_folded_rule_same_transport():
+    base = tiny_2d(seed=3, nx=3, ny=3, quad=("cl", 4, 4, False))
+    fold = dict(base, quad=("cl", 4, 4, True))
+    Pa, Pb = tr.Problem(base), tr.Problem(fold)
+    q = np.random.default_rng(0).standard_normal(Pa.ndof)
+    np.testing.assert_allclose(tr.T_apply(Pa, q), tr.T_apply(Pb, q), rtol=1e-13, atol=1e-14)
+
+
+# ---------------------------------------------------------------- DG operators (2.2-2.3, App. A)
+@pytest.mark.parametrize("spec", [tiny_1d(nx=5, n_ord=4), tiny_2d(nx=4, ny=3)])
+def test_mass_is_identity_in_orthonormal_basis(spec):
+    m = dg.Mesh.of(spec)
+    np.testing.assert_allclose(dg.mass_local(m), np.eye(m.nloc), atol=1e-14)
+
+
+@pytest.mark.parametrize("spec", [tiny_1d(nx=5, n_ord=4), tiny_2d(nx=4, ny=3, quad=("cl", 6, 2, False))])
+def test_appA_identity(spec):
+    """App. A: D_j = sum_e Omega_e (D_C^e - sgn(Omega_e)/2 D_J^e), which holds
+    when D_C, D_J include both boundary faces; D_C is then skew-symmetric."""
+    P = tr.Problem(spec)
+    m = P.mesh
+    ops = [dg.central_and_jump(m, e) for e in range(m.dim)]
+    for j in range(P.nord):
+        om = [P.ox[j], P.oy[j]]
+        R = sum(om[e] * (ops[e][0] - np.sign(om[e]) / 2 * ops[e][1]) for e in range(m.dim))
+        assert abs(P.D(j) - R).max() < 1e-13
+    for DC, DJ in ops:
+        assert abs(DC + DC.T).max() < 1e-13
+        assert abs(DJ - DJ.T).max() < 1e-13
+
+
+def test_appA_printed_face_range_breaks_identity():
+    """With the face sum printed in App. A (omitting x_{1/2}) the identity
+    fails on the first cell, which motivates including both boundary faces."""
+    P = tr.Problem(tiny_1d(nx=5, n_ord=4))
+    DC, DJ = dg.central_and_jump(P.mesh, 0, include_boundary_faces=False)
+    j = int(np.argmin(P.ox))          # x_{1/2} is the outflow face for Omega_x < 0
+    R = P.ox[j] * (DC + 0.5 * DJ)
+    assert abs(P.D(j) - R).max() > 1e-3
+
+
+def test_advection_block_closed_form():
+    """Quadrature-assembled 1D upwind block for Omega = +1 equals the hand-derived
+    (1/h)[[1, sqrt3], [-sqrt3, 3]] in the orthonormal Legendre basis; the
+    coupling to the upwind neighbour is -(1/h)[[1, sqrt3], [-sqrt3, -3]]."""
+    m = dg.Mesh(1, 4, 1, (0.0, 2.0, 0.0, 1.0))
+    D = dg.advection(m, 1.0, 0.0).toarray()
+    h = 0.5
+    r3 = np.sqrt(3.0)
+    np.testing.assert_allclose(D[2:4, 2:4], np.array([[1, r3], [-r3, 3]]) / h, atol=1e-13)
+    np.testing.assert_allclose(D[2:4, 0:2], -np.array([[1, r3], [-r3, -3]]) / h, atol=1e-13)
+    assert np.all(D[0:2, 2:] == 0)  # first cell depends on nothing downstream
+
+
+# ---------------------------------------------------------------- sweep (section 3.1)
+def test_sweep_mms_bilinear_reproduced():
+    """Upwind DG reproduces any continuous bilinear psi* exactly when the
+    source is Omega.grad psi* + sigma_t psi* and the inflow is psi*."""
+    spec = tiny_2d(seed=1, nx=5, ny=4, quad=("cl", 6, 2, False), n_regions=3)
+    P = tr.Problem(spec)
+    m = P.mesh
+    sig = P.sig_t_cell
+    coef = np.random.default_rng(2).standard_normal((P.nord, 4))
+    q = np.empty((P.nord, P.ndof))
+    exact = np.empty((P.nord, P.ndof))
+    for j in range(P.nord):
+        a, b, c, d = coef[j]
+        f = lambda x, y: a + b * x + c * y + d * x * y
+        src = lambda x, y: (P.ox[j] * (b + d * y) + P.oy[j] * (c + d * x)
+                            + sig[:, None] * f(x, y))
+        q[j] = dg.project(m, src) + P.gbc(j, f)
+        exact[j] = dg.project(m, f)
+    _, psi = tr.sweep(P, q, store_psi=True)
+    np.testing.assert_allclose(psi, exact, rtol=0, atol=1e-12 * np.abs(exact).max())
+
+
+def test_sweep_constant_state():
+    spec = tiny_2d(seed=4, nx=4, ny=4, quad=("cl", 8, 2, True), inflow=0.0)
+    spec = dict(spec, sigma_s=np.zeros(2), sigma_t=np.array([2.0, 2.0]))
+    spec["source"] = dg.project(dg.Mesh.of(spec), lambda x, y: 3.0 + 0 * x)
+    spec["inflow"] = 1.5
+    P = tr.Problem(spec)
+    phi = tr.b_tilde(P)
+    np.testing.assert_allclose(phi, dg.project(P.mesh, lambda x, y: 1.5 + 0 * x), atol=1e-13)
+
+
+def test_sweep_pure_absorber_second_order():
+    """Pure absorber slab, G = 1, zero inflow: psi(x, mu) = (1 - exp(-s x/mu))/s
+    for mu > 0 (mirror for mu < 0).  The DG error decays at least like h^2."""
+    errs = []
+    s = 3.0
+    for nx in (16, 32, 64, 128):
+        spec = dict(dim=1, nx=nx, ny=1, box=(0.0, 1.0, 0.0, 1.0), quad=("gl", 4),
+                    region=np.zeros(nx, np.int32), sigma_t=np.array([s]), sigma_s=np.array([0.0]),
+                    source=None, inflow=0.0)
+        m = dg.Mesh.of(spec)
+        spec["source"] = dg.project(m, lambda x, y: np.ones_like(x))
+        P = tr.Problem(spec)
+        _, psi = tr.sweep(P, P.G, store_psi=True)
+        e = 0.0
+        for j in range(P.nord):
+            mu = P.ox[j]
+            ex = (lambda x, y, mu=mu: (1 - np.exp(-s * x / mu)) / s) if mu > 0 else \
+                 (lambda x, y, mu=mu: (1 - np.exp(-s * (1 - x) / -mu)) / s)
+            e = max(e, np.linalg.norm(psi[j] - dg.project(m, ex)))
+        errs.append(e)
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8) and 1.9 < rates[-1] < 3.1, rates
+
+
+def _boundary_outflow(P, psi_j, j):
+    """sum over boundary faces of int (Omega.n)^+ psi_j, by evaluating the DG
+    function on the faces (independent of the assembled matrices)."""
+    m = P.mesh
+    gx, gw = np.polynomial.legendre.leggauss(3)
+    r3 = np.sqrt(3.0)
+    out = 0.0
+    ox, oy = P.ox[j], P.oy[j]
+    c = psi_j.reshape(m.ny, m.nx, m.nloc)
+    if m.dim == 1:
+        if ox > 0:
+            out += ox * (c[0, -1, 0] + r3 * c[0, -1, 1]) / np.sqrt(m.hx)
+        else:
+            out += -ox * (c[0, 0, 0] - r3 * c[0, 0, 1]) / np.sqrt(m.hx)
+        return out
+
+    def trace(cc, sx, sy):
+        return (cc[..., 0] + r3 * sx * cc[..., 1] + r3 * sy * cc[..., 2]
+                + 3 * sx * sy * cc[..., 3]) / np.sqrt(m.hx * m.hy)
+    for g, w in zip(gx, gw):
+        if ox > 0:
+            out += ox * w * m.hy / 2 * trace(c[:, -1], 1.0, g).sum()
+        elif ox < 0:
+            out += -ox * w * m.hy / 2 * trace(c[:, 0], -1.0, g).sum()
+        if oy > 0:
+            out += oy * w * m.hx / 2 * trace(c[-1, :], g, 1.0).sum()
+        elif oy < 0:
+            out += -oy * w * m.hx / 2 * trace(c[0, :], g, -1.0).sum()
+    return out
+
+
+@pytest.mark.parametrize("spec", [tiny_1d(nx=6, n_ord=8, inflow=0.7),
+                                  tiny_2d(seed=5, nx=5, ny=4, quad=("cl", 8, 4, True), inflow=0.4)])
+def test_sweep_particle_balance(spec):
+    """sum_j w_j outflow_j + int sigma_t phi = int q + inflow (one sweep with
+    q = Sigma_s phi_in + G), from integrating the DG equation with eta = 1."""
+    P = tr.Problem(spec)
+    m = P.mesh
+    vol = np.sqrt(m.hx * m.hy)        # int over a cell of eta_0 is sqrt(|T|)
+    phi_in = np.random.default_rng(7).uniform(0, 1, P.ndof)
+    q0 = P.Ss @ phi_in + P.G
+    qs = np.stack([q0 + P.gbc(j) for j in range(P.nord)])
+    phi, psi = tr.sweep(P, qs, store_psi=True)
+    outflow = sum(P.w[j] * _boundary_outflow(P, psi[j], j) for j in range(P.nord))
+    absorb = (P.sig_t_cell * phi.reshape(-1, m.nloc)[:, 0]).sum() * vol
+    src = q0.reshape(-1, m.nloc)[:, 0].sum() * vol
+    inflow = sum(P.w[j] * P.gbc(j).reshape(-1, m.nloc)[:, 0].sum() * vol for j in range(P.nord))
+    assert abs(outflow + absorb - src - inflow) < 1e-12 * (abs(src) + abs(inflow))
+
+
+def test_sweep_residual():
+    P = tr.Problem(tiny_2d(seed=6, nx=6, ny=5, quad=("cl", 8, 2, True)))
+    q = np.random.default_rng(1).standard_normal(P.ndof)
+    _, psi = tr.sweep(P, q, store_psi=True)
+    for j in range(P.nord):
+        r = (P.D(j) + P.St) @ psi[j] - q
+        assert np.linalg.norm(r) < 1e-13 * np.linalg.norm(q)
+
+
+# ---------------------------------------------------------------- systems (2.3, 3.2)
+@pytest.mark.parametrize("spec", [tiny_1d(nx=4, n_ord=4, inflow=0.3),
+                                  tiny_2d(seed=2, nx=3, ny=3, quad=("cl", 4, 2, False), inflow=0.2)])
+def test_memory_efficient_system_equals_coupled(spec):
+    """phi = Q A^{-1} b (fully coupled system) equals A~^{-1} b~ (brute force)."""
+    P = tr.Problem(spec)
+    A, b = tr.full_system(P)
+    psi = np.linalg.solve(A.toarray(), b).reshape(P.nord, -1)
+    phi = tr.scalar_flux(P, psi)
+    At = tr.dense_A_tilde(P)
+    np.testing.assert_allclose(np.linalg.solve(At, tr.b_tilde(P)), phi, rtol=1e-12, atol=1e-14)
+
+
+def test_infinite_medium_equilibrium():
+    """Uniform medium with inflow g = G / sigma_a: phi == G / sigma_a exactly."""
+    spec = tiny_2d(seed=8, nx=4, ny=4, quad=("cl", 8, 2, True))
+    spec = dict(spec, sigma_s=np.array([2.0, 2.0]), sigma_t=np.array([2.5, 2.5]))
+    m = dg.Mesh.of(spec)
+    spec["source"] = dg.project(m, lambda x, y: 0.8 + 0 * x)
+    spec["inflow"] = 0.8 / 0.5
+    P = tr.Problem(spec)
+    At = tr.dense_A_tilde(P)
+    phi = np.linalg.solve(At, tr.b_tilde(P))
+    np.testing.assert_allclose(phi, dg.project(m, lambda x, y: 1.6 + 0 * x), atol=1e-12)

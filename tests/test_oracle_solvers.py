@@ -1,0 +1,197 @@
+"""Pins of the oracle's FGMRES, DSA, ROMSAD, greedy and MLP against library
+routines, exactness properties and identities fixed by the paper."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import dsa, mlp, rom
+from oracle import fgmres as fg
+from oracle import transport as tr
+from synth import tiny_1d, tiny_2d
+
+
+def _At(P):
+    return lambda x: tr.A_tilde_apply(P, x)
+
+
+# ---------------------------------------------------------------- FGMRES (Alg. 1)
+def test_fgmres_identity_matches_library_gmres():
+    """Unpreconditioned: residual history equals scipy's GMRES on the dense A~."""
+    P = tr.Problem(tiny_2d(seed=1, nx=3, ny=3, quad=("cl", 4, 2, False)))
+    At = tr.dense_A_tilde(P)
+    b = tr.b_tilde(P)
+    res = fg.fgmres(_At(P), b, lambda j, v: v, m=36, rtol=1e-12)
+    hist = []
+    spla.gmres(At, b, rtol=1e-12, restart=36, maxiter=1,
+               callback=lambda r: hist.append(r), callback_type="pr_norm")
+    n = min(len(hist), len(res.history))
+    assert n >= 5
+    np.testing.assert_allclose(res.history[:n], hist[:n], rtol=1e-5, atol=1e-11)
+    np.testing.assert_allclose(At @ res.x, b, rtol=0, atol=1e-11 * np.linalg.norm(b))
+
+
+def test_fgmres_linear_preconditioner_is_right_gmres():
+    """With M_j = M fixed, FGMRES = right-preconditioned GMRES (section 4.2)."""
+    P = tr.Problem(tiny_2d(seed=2, nx=3, ny=3, quad=("cl", 4, 2, False)))
+    At = tr.dense_A_tilde(P)
+    b = tr.b_tilde(P)
+    Minv = np.eye(P.ndof) + 0.3 * np.random.default_rng(3).standard_normal((P.ndof, P.ndof)) / P.ndof
+    res = fg.fgmres(_At(P), b, lambda j, v: Minv @ v, m=36, rtol=1e-12)
+    hist = []
+    spla.gmres(At @ Minv, b, rtol=1e-12, restart=36, maxiter=1,
+               callback=lambda r: hist.append(r), callback_type="pr_norm")
+    n = min(len(hist), len(res.history))
+    np.testing.assert_allclose(res.history[:n], hist[:n], rtol=1e-5, atol=1e-11)
+
+
+def test_flexible_arnoldi_relation_and_sweep_count():
+    """A~ Z_j = V_{j+1} H~_j with orthonormal V; zero initial guess costs
+    1 + iterations sweeps (b~ plus one per step), plus the true-residual check."""
+    P = tr.Problem(tiny_2d(seed=4, nx=4, ny=3, quad=("cl", 4, 2, True)))
+    b = tr.b_tilde(P)
+    rng = np.random.default_rng(5)
+    pc = lambda j, v: v + 0.1 * j * np.tanh(v) + 0.01 * rng.standard_normal(v.shape)  # nonlinear
+    res = fg.fgmres(_At(P), b, pc, m=5, rtol=1e-30, max_cycles=1, keep_first=True)
+    fc = res.first_cycle
+    V = np.stack(fc["V"], 1)
+    Z = np.stack(fc["Z"], 1)
+    AZ = np.stack([tr.A_tilde_apply(P, z) for z in fc["Z"]], 1)
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() < 1e-9   # MGS, residual ~1e-6
+    np.testing.assert_allclose(AZ, V @ fc["H"], atol=1e-12 * np.abs(AZ).max())
+    assert res.a_applies == res.iterations + 1  # steps + final true residual
+    assert all(np.diff(res.history) <= 1e-15)
+
+
+# ---------------------------------------------------------------- DSA (App. A)
+@pytest.mark.parametrize("spec", [tiny_1d(nx=7, n_ord=2), tiny_2d(seed=3, nx=4, ny=3, quad=("cl", 3, 2, False))])
+def test_fc_dsa_exact_when_p1_is_exact(spec):
+    """S2 in 1D and CL(3,2) in X-Y: the P1 ansatz spans every angular flux,
+    so FC-DSA is the ideal correction: M_DSA^{-1} A~ = I, and GMRES-DSA
+    converges in one step."""
+    P = tr.Problem(spec)
+    D = dsa.DSA(P)
+    At = tr.dense_A_tilde(P)
+    Minv = np.stack([D.apply(e) for e in np.eye(P.ndof)], 1)
+    assert np.abs(Minv @ At - np.eye(P.ndof)).max() < 1e-12
+    res = fg.fgmres(_At(P), tr.b_tilde(P), lambda j, v: D.apply(v), m=10, rtol=1e-12)
+    assert res.iterations == 1
+
+
+@pytest.mark.parametrize("spec", [tiny_1d(nx=8, n_ord=8), tiny_2d(seed=6, nx=5, ny=5, quad=("cl", 8, 4, True))])
+def test_fc_dsa_two_constructions_agree_and_contract(spec):
+    """Moments of the assembled upwind D_j == App. A's D_C / D_J form; the
+    error propagator I - M^{-1} A~ contracts (spectral radius well below 1)."""
+    P = tr.Problem(spec)
+    A1, _ = dsa.fc_system(P)
+    A2, _ = dsa.fc_system_appA(P)
+    assert abs(A1 - A2).max() < 1e-12 * abs(A1).max()
+    D = dsa.DSA(P)
+    At = tr.dense_A_tilde(P)
+    E = np.eye(P.ndof) - np.stack([D.apply(e) for e in np.eye(P.ndof)], 1) @ At
+    rho = max(abs(np.linalg.eigvals(E)))
+    assert rho < 0.35
+
+
+# ---------------------------------------------------------------- ROMSAD (section 4)
+def _family(n=5, nx=4, ny=4, quad=("cl", 4, 2, True)):
+    specs = []
+    for k in range(n):
+        s = dict(tiny_2d(seed=0, nx=nx, ny=ny, quad=quad))
+        s["sigma_s"] = s["sigma_s"] * (1 + 0.4 * k)
+        s["sigma_t"] = s["sigma_s"] + 0.3
+        specs.append(s)
+    return specs
+
+
+def test_xi_recurrence_identities():
+    """A~ xi^(l) = v^(l) (eq. of xi) and T Sigma_s xi = xi - v (eq. of the
+    density relation)."""
+    P = tr.Problem(_family()[1])
+    D = dsa.DSA(P)
+    res = fg.fgmres(_At(P), tr.b_tilde(P), lambda j, v: D.apply(v), m=40, rtol=1e-13, keep_first=True)
+    xis = rom.xi_recurrence(res.first_cycle, res.x, 3)
+    assert len(xis) == 3
+    for l, xi in enumerate(xis):
+        v = res.first_cycle["V"][l]
+        assert np.linalg.norm(tr.A_tilde_apply(P, xi) - v) < 1e-10
+        assert np.linalg.norm(tr.T_apply(P, P.Ss @ xi) - (xi - v)) < 1e-10
+
+
+def test_rom_exact_when_span_contains_ideal_correction():
+    """If U_r spans the ideal correction delta psi(v), M_ROM^{-1} v = A~^{-1} v."""
+    P = tr.Problem(_family()[2])
+    v = np.random.default_rng(9).standard_normal(P.ndof)
+    At = tr.dense_A_tilde(P)
+    xi = np.linalg.solve(At, v)
+    dpsi = rom.snapshot_corrections(P, [xi])[0]
+    U, _ = rom.mgs_truncate(np.zeros((0, P.nord, P.ndof)), dpsi)
+    z = v + rom.rom_correction(P, U, v)
+    np.testing.assert_allclose(z, xi, rtol=0, atol=1e-11 * np.abs(xi).max())
+
+
+def test_mgs_truncation():
+    rng = np.random.default_rng(1)
+    U = np.zeros((0, 3, 10))
+    a, b = rng.standard_normal((3, 10)), rng.standard_normal((3, 10))
+    U, added1 = rom.mgs_truncate(U, a)
+    U, added2 = rom.mgs_truncate(U, b)
+    U, added3 = rom.mgs_truncate(U, 2.0 * a - 0.5 * b)   # in the span: truncated
+    assert (added1, added2, added3) == (True, True, False)
+    G = np.einsum("inm,knm->ik", U, U)
+    assert np.abs(G - np.eye(2)).max() < 1e-14
+
+
+def test_greedy_rank_affine_and_sampled_residual():
+    """r = k * window when nothing is truncated; U orthonormal; the affine
+    region-wise reduced operator equals the dense projection; the ROM is
+    exact on sampled parameters (FGMRES-ROMSAD converges in one step)."""
+    specs = _family(5)
+    U, rep = rom.greedy(specs, window=2, eps_rom=0.0, n_giter=3)
+    assert rep.r_history == [2, 4, 6] and rep.truncated == 0
+    assert len(set(rep.sampled)) == 3 and rep.sampled[0] == 0
+    assert np.abs(np.einsum("inm,knm->ik", U, U) - np.eye(6)).max() < 1e-8
+    assert all(np.diff(rep.max_residual) < 0)
+    P = tr.Problem(specs[rep.sampled[1]])
+    Ar = rom.reduced_operator(P, U)
+    AD, G, S = rom.affine_terms(P, U, 2)
+    Aff = AD + sum(P.spec["sigma_t"][R] * G[R] - P.spec["sigma_s"][R] * S[R] for R in range(2))
+    assert np.abs(Ar - Aff).max() < 1e-12 * np.abs(Ar).max()
+    R = rom.Romsad(P, U, dsa.DSA(P), window=2)
+    res = fg.fgmres(_At(P), tr.b_tilde(P), R, m=20, rtol=1e-8)
+    assert res.iterations == 1
+    b = tr.b_tilde(P)
+    assert rom.residual_indicator(P, U, P.Ss @ b) < 1e-7 * np.linalg.norm(P.Ss @ b)
+
+
+# ---------------------------------------------------------------- MLP
+def test_mlp_backward_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    params = mlp.init([5, 7, 6, 3], rng)
+    X = rng.standard_normal((4, 5))
+    Y = rng.standard_normal((4, 3))
+    out, cache = mlp.forward(params, X)
+    grads = mlp.backward(params, cache, out, Y)
+    h = 1e-6
+    for li in range(len(params)):
+        for k in range(2):
+            p = params[li][k]
+            flat = p.reshape(-1)
+            for idx in rng.choice(flat.size, size=min(5, flat.size), replace=False):
+                old = flat[idx]
+                flat[idx] = old + h
+                lp = mlp.mse(mlp.forward(params, X)[0], Y)
+                flat[idx] = old - h
+                lm = mlp.mse(mlp.forward(params, X)[0], Y)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - grads[li][k].reshape(-1)[idx]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_gelu_special_values():
+    # gelu(0) = 0, gelu'(0) = 1/2, gelu(x) -> x for large x, -> 0 for very negative x
+    assert mlp.gelu(np.array(0.0)) == 0.0
+    assert abs(mlp.gelu_grad(np.array(0.0)) - 0.5) < 1e-15
+    assert abs(mlp.gelu(np.array(10.0)) - 10.0) < 1e-12
+    assert abs(mlp.gelu(np.array(-10.0))) < 1e-12
+    # gelu(1) = Phi(1) = 0.8413447460685429 (standard normal CDF at 1)
+    assert abs(mlp.gelu(np.array(1.0)) - 0.8413447460685429) < 1e-15
