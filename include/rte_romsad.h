@@ -1,0 +1,241 @@
+/*
+ * rte_romsad.h -- C ABI of the MI355X (gfx950) library for the steady one-group
+ * radiative transfer equation solved by flexible GMRES with the ROMSAD
+ * preconditioner (Peng, arXiv 2410.08735).
+ *
+ * Conventions shared by every call
+ *  - Return value: 0 (RTE_OK) on success, < 0 on error, > 0 a warning
+ *    (RTE_WNOTCONV: a solve stopped before its tolerance; its outputs and
+ *    statistics are still written).  rte_status_string() names a code.
+ *  - Arrays marked "device" are caller-owned device pointers (for example the
+ *    storage of a torch tensor), contiguous, FP64 unless stated.  Arrays marked
+ *    "host" are caller-owned host memory.  The library never frees or keeps
+ *    caller memory beyond the call.
+ *  - Every call that takes `stream` enqueues its work on that HIP stream (a
+ *    hipStream_t passed as void*; NULL = the null stream).  Calls that return
+ *    host-visible results (statistics, reports, ranks) synchronise the stream
+ *    before returning.
+ *  - Invalid arguments are rejected with RTE_EINVAL before any kernel launch.
+ *  - Opaque handles (rte_batch, rte_rom, rte_mlp) are library-owned and are
+ *    released with their destroy call.
+ *
+ * Discretisation and layout (sections 2.1-2.3 of the paper)
+ *  - S_N ordinates Omega_j with normalised weights w_j (sum w_j = 1); the scalar
+ *    flux is phi = sum_j w_j psi_j.
+ *  - Upwind DG with degree 1: P1 in slab geometry (2 dofs per cell), Q1 in X-Y
+ *    geometry (4 dofs per cell), on a uniform nx x ny grid of a box.
+ *  - Per cell the orthonormal tensor Legendre basis e_p(x) e_q(y),
+ *    e_0 = 1/sqrt(h), e_1 = sqrt(3) s/sqrt(h), s the local coordinate in [-1, 1].
+ *  - Instance vector layout: dof = cell * nloc + p + 2 q, cell = k * nx + i.
+ *    A batch vector packs the instances one after another; rte_batch_offset()
+ *    gives where an instance starts.  Angular fluxes are [n_ord][ndof] per
+ *    instance, packed likewise (rte_batch_psi_offset()).
+ *  - Cross sections are piecewise constant on regions: sigma_t and sigma_s
+ *    arguments are device arrays [n_inst][max_regions] (row stride
+ *    rte_batch_max_regions()); the cell -> region map is fixed at batch creation.
+ *  - Inflow (section 2, the boundary condition) is an isotropic constant g per
+ *    instance (device array [n_inst], NULL = zero inflow).
+ */
+#ifndef RTE_ROMSAD_H
+#define RTE_ROMSAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RTE_OK = 0,
+  RTE_EINVAL = -1,      /* invalid argument (shape, pointer, value)           */
+  RTE_EHIP = -2,        /* a HIP runtime call failed                          */
+  RTE_ENOMEM = -3,      /* device allocation failed                           */
+  RTE_EBREAKDOWN = -4,  /* Krylov breakdown with a singular least squares     */
+  RTE_ESINGULAR = -5,   /* singular reduced operator                          */
+  RTE_EIO = -6,         /* file read/write failed                             */
+  RTE_WNOTCONV = 1      /* not converged within the iteration limits          */
+};
+
+enum { RTE_F64 = 0, RTE_F32 = 1 };
+
+enum { RTE_PC_NONE = 0, RTE_PC_DSA = 1, RTE_PC_ROMSAD = 2, RTE_PC_MLP = 3 };
+
+typedef struct rte_batch rte_batch;
+typedef struct rte_rom rte_rom;
+typedef struct rte_mlp rte_mlp;
+
+const char* rte_status_string(int status);
+
+/* ---------------------------------------------------------------- quadrature
+ * Chebyshev-Legendre rule CL(n_theta, n_z) of section 2.1: theta_j1 =
+ * (2 j1 - 1) pi / n_theta with weight 1/n_theta, times the normalised n_z-point
+ * Gauss-Legendre rule in Omega_z; ordinate j = (j2 - 1) n_theta + j1.
+ * folded != 0 keeps only the Omega_z > 0 nodes with doubled weights (exact in
+ * X-Y geometry, where the operator depends on Omega_x, Omega_y only).
+ * Outputs (host) have n_theta * n_z (folded: n_theta * n_z / 2) entries.      */
+int rte_quadrature_cl(int n_theta, int n_z, int folded, double* ox, double* oy, double* w);
+/* Slab S_n: Gauss-Legendre nodes mu_j (ox), oy = 0, weights w_j / 2 (App. A). */
+int rte_quadrature_gl(int n, double* ox, double* oy, double* w);
+
+/* ---------------------------------------------------------------- batches
+ * One parameter instance: geometry, ordinates (host arrays copied at
+ * creation) and the cell -> region map.  dim = 1: ny must be 1 and omega_y is
+ * ignored.                                                                    */
+typedef struct {
+  int32_t dim, nx, ny;
+  double x0, x1, y0, y1;
+  int32_t n_ord;
+  const double* omega_x; /* host [n_ord] */
+  const double* omega_y; /* host [n_ord] */
+  const double* weight;  /* host [n_ord], sum 1 */
+  const int32_t* region; /* host [nx*ny] values in [0, n_regions) */
+  int32_t n_regions;
+} rte_instance_desc;
+
+int rte_batch_create(const rte_instance_desc* inst, int n_inst, rte_batch** out);
+void rte_batch_destroy(rte_batch* b);
+int rte_batch_size(const rte_batch* b);
+int64_t rte_batch_ndof(const rte_batch* b, int inst);
+int64_t rte_batch_offset(const rte_batch* b, int inst);
+int64_t rte_batch_total_dof(const rte_batch* b);
+int64_t rte_batch_psi_offset(const rte_batch* b, int inst);
+int64_t rte_batch_total_psi(const rte_batch* b);
+int rte_batch_max_regions(const rte_batch* b);
+
+/* ---------------------------------------------------------------- transport
+ * rte_sweep: the transport sweep of section 3.1 for every ordinate of every
+ * instance, psi_j = (D_j + Sigma_t)^{-1} (q + g_j^(bc)), and its quadrature
+ * reduction phi = sum_j w_j psi_j (the operator T of the memory-efficient
+ * formulation, section 3.1).  q (device, packed [total_dof]) is isotropic.
+ * phi_out (device, packed) and psi_out (device, [total_psi]) are each optional
+ * (NULL) but not both.  dtype selects the arithmetic (RTE_F32 / RTE_F64);
+ * inputs and outputs are FP64 either way.                                     */
+int rte_sweep(const rte_batch* b, const double* sigma_t, const double* q, const double* inflow,
+              double* phi_out, double* psi_out, int dtype, void* stream);
+
+/* rte_scalar_flux: phi = sum_j w_j psi_j for stored angular fluxes (the
+ * discrete integration operator Q of section 2.3).                            */
+int rte_scalar_flux(const rte_batch* b, const double* psi, double* phi_out, void* stream);
+
+/* rte_apply_A: y = (I - T Sigma_s) x, the memory-efficient operator A~ of
+ * section 3.2 (zero inflow), one sweep; dtype as in rte_sweep.               */
+int rte_apply_A(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* x,
+                double* y, int dtype, void* stream);
+
+/* rte_rhs: b~ = sum_j w_j (D_j + Sigma_t)^{-1} (G + g_j^(bc)) (section 3.1).   */
+int rte_rhs(const rte_batch* b, const double* sigma_t, const double* G, const double* inflow,
+            double* b_out, int dtype, void* stream);
+
+/* ---------------------------------------------------------------- DSA
+ * rte_dsa_apply: z = M_DSA^{-1} v = v + dphi, where (dphi, dJ) solves the fully
+ * consistent P1 moment system of App. A (zeroth and first angular moments of
+ * the upwind correction equation under delta psi_j = dphi + 3 Omega_j.dJ,
+ * written for X-Y geometry with the same two steps) with right-hand side
+ * Sigma_s v.  The system is solved by restarted GMRES (Krylov dimension
+ * `restart`) preconditioned with exact inverses of its per-cell diagonal
+ * blocks, until the relative residual is <= inner_tol or inner_max iterations.
+ * stats_iters (host [n_inst], nullable) receives the iterations used.         */
+int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v,
+                  double* z, double inner_tol, int inner_max, int restart, int32_t* stats_iters,
+                  void* stream);
+
+/* ---------------------------------------------------------------- FGMRES
+ * fgmres_solve: Alg. 1 (flexible GMRES) for A~ phi = b~ on every instance,
+ * zero initial guess, restarted every m iterations from the FP64 true
+ * residual.  Per iteration j of a cycle the preconditioner is
+ *   RTE_PC_NONE  z = v,
+ *   RTE_PC_DSA   z = M_DSA^{-1} v,
+ *   RTE_PC_ROMSAD  M_ROM^{-1} for j <= window, M_DSA^{-1} after (eq. of the
+ *                  ROMSAD preconditioner),
+ *   RTE_PC_MLP   the learned reduced correction for j <= window with the ROMSAD
+ *                correction as fallback and DSA after the window.
+ * Stopping: Givens estimate <= rtol * ||b~|| ends a cycle; the FP64 true
+ * residual ||b~ - A~ phi|| / ||b~|| <= rtol ends the solve.  sweep_dtype sets
+ * the arithmetic of the inner A~ applies; b~ and true residuals are FP64.
+ * phi (device, packed) receives the solution.  stats (host [n_inst]).        */
+typedef struct {
+  int32_t precond;       /* RTE_PC_*                                         */
+  int32_t m;             /* Krylov dimension per cycle                       */
+  int32_t max_cycles;
+  int32_t sweep_dtype;   /* RTE_F32 or RTE_F64                               */
+  double rtol;
+  int32_t window;        /* ROMSAD window (iterations per cycle using the ROM)*/
+  int32_t dsa_inner_max; /* DSA inner GMRES iterations                       */
+  int32_t dsa_restart;
+  double dsa_inner_tol;
+  int32_t keep_krylov;   /* internal use by the offline builders: 0           */
+} rte_solve_opts;
+
+typedef struct {
+  int32_t iterations;    /* Arnoldi steps over all cycles                     */
+  int32_t cycles;
+  int32_t sweeps_f32;    /* transport sweeps by precision (b~ included)       */
+  int32_t sweeps_f64;
+  int32_t pc_rom, pc_dsa, pc_mlp, pc_fallback; /* preconditioner uses        */
+  int32_t status;        /* 0 converged, RTE_WNOTCONV, RTE_EBREAKDOWN         */
+  double true_relres;    /* final FP64 ||b~ - A~ phi|| / ||b~||              */
+  double est_relres;     /* last Givens estimate / ||b~||                     */
+} rte_solve_stats;
+
+int fgmres_solve(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* G,
+                 const double* inflow, const rte_solve_opts* opts, const rte_rom* rom,
+                 const rte_mlp* mlp, const double* mu, int mu_dim, double* phi,
+                 rte_solve_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------- ROMSAD
+ * A ROM holds the orthonormal psi-space basis U_r ([r][n_ord][ndof], section
+ * 4.3) of one grid/quadrature (instance 0 of the batch it was built on), the
+ * two sums W_1 = sum_j U_{r,j}, W_w = sum_j w_j U_{r,j}, and the affine
+ * pieces of U_r^T A(mu) U_r for region-wise constant cross sections
+ * (eq. of the affine assumption):
+ *   U^T A U = A_D + sum_R sigma_t,R G_R - sum_R sigma_s,R S_R,
+ *   A_D = sum_j U_j^T D_j U_j, G_R = sum_j U_j^T M_R U_j, S_R = W_1^T M_R W_w.
+ *
+ * romsad_build_greedy: the greedy algorithm of section 4.4.2 on the training
+ * instances of `train` (all with the same grid, ordinates and region map):
+ * step 1 b~ and eta0 = Sigma_s b~ for all; step 2(a) FP64 FGMRES-DSA solve of
+ * the sampled instance to hf_rtol and the xi recurrence; 2(b) window
+ * psi-storing sweeps; 2(c) MGS with truncation (App. B, eps_qr) and the
+ * reduced operators; step 3 the residual indicator R_mu on every unsampled
+ * instance and its argmax (ties: lowest index), until max R_mu < eps_rom or
+ * n_giter sampled parameters.  report (host, nullable).                      */
+typedef struct {
+  int32_t n_sampled;
+  int32_t sampled[256];      /* training indices in sampling order            */
+  double max_residual[256];  /* max R_mu after each greedy iteration          */
+  int32_t rank;
+  int32_t truncated;
+  double seconds_step[5];    /* step 1, 2a, 2b, 2c, 3 wall time               */
+} rte_greedy_report;
+
+int romsad_build_greedy(const rte_batch* train, const double* sigma_t, const double* sigma_s,
+                        const double* G, const double* inflow, int window, int mu1_index,
+                        double eps_rom, int n_giter, double eps_qr, double hf_rtol,
+                        rte_rom** out, rte_greedy_report* report, void* stream);
+
+/* rte_rom_from_basis: a ROM from a given orthonormal basis U (device
+ * [r][n_ord][ndof] of instance 0 of `b`); computes W_1, W_w and the affine
+ * pieces on the device.                                                       */
+int rte_rom_from_basis(const rte_batch* b, const double* U, int r, rte_rom** out, void* stream);
+
+/* romsad_apply: z = M_ROM^{-1} v = v + W_w (U^T A(mu) U)^{-1} W_1^T Sigma_s v
+ * (eq. of the ROM-based SA preconditioner) for every instance of `b`, whose
+ * instances must share the ROM's grid, ordinates and region map; mu enters
+ * through the per-region cross sections.  A singular reduced operator leaves
+ * z = v for that instance and returns RTE_ESINGULAR.                         */
+int romsad_apply(const rte_rom* rom, const rte_batch* b, const double* sigma_t,
+                 const double* sigma_s, const double* v, double* z, void* stream);
+
+int rte_rom_rank(const rte_rom* rom);
+/* Host copies of the ROM's arrays (each pointer nullable): U [r][n_ord][ndof],
+ * W1, Ww [r][ndof], AD [r][r], G, S [n_regions][r][r].                        */
+int rte_rom_export(const rte_rom* rom, double* U, double* W1, double* Ww, double* AD, double* G,
+                   double* S);
+int rte_rom_save(const rte_rom* rom, const char* path);
+int rte_rom_load(const char* path, rte_rom** out);
+void rte_rom_destroy(rte_rom* rom);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

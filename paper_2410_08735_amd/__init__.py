@@ -1,0 +1,272 @@
+"""Python binding of the MI355X RTE / FGMRES-ROMSAD library.
+
+Argument marshalling only: every numerical step runs in the HIP library
+(librte_romsad.so, C ABI in include/rte_romsad.h).  Device arrays are torch
+tensors on the current CUDA (HIP) device; their pointers and the current
+stream are handed to the library.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (RTE_F32, RTE_F64, RTE_PC_DSA, RTE_PC_MLP, RTE_PC_NONE, RTE_PC_ROMSAD,  # noqa: F401
+                   RteError, check)
+
+__all__ = ["Batch", "quadrature", "sweep", "scalar_flux", "apply_A", "rhs", "dsa_apply",
+           "fgmres_solve", "SolveOptions", "Rom", "romsad_build_greedy", "romsad_apply"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(dtype):
+    return {"f64": RTE_F64, "f32": RTE_F32, RTE_F64: RTE_F64, RTE_F32: RTE_F32}[dtype]
+
+
+def quadrature(spec):
+    """Ordinates of a quadrature spec ('gl', n) or ('cl', n_theta, n_z, folded),
+    computed by the library."""
+    lib = L.lib()
+    if spec[0] == "gl":
+        n = spec[1]
+        ox, oy, w = (np.zeros(n) for _ in range(3))
+        check(lib.rte_quadrature_gl(n, *(a.ctypes.data_as(L.pdbl) for a in (ox, oy, w))), "quadrature")
+        return ox, oy, w
+    nt, nz = spec[1], spec[2]
+    folded = bool(spec[3]) if len(spec) > 3 else False
+    n = nt * nz // (2 if folded else 1)
+    ox, oy, w = (np.zeros(n) for _ in range(3))
+    check(lib.rte_quadrature_cl(nt, nz, int(folded), *(a.ctypes.data_as(L.pdbl) for a in (ox, oy, w))),
+          "quadrature")
+    return ox, oy, w
+
+
+class Batch:
+    """A batch of parameter instances (problem dicts as produced by synth)."""
+
+    def __init__(self, problems):
+        lib = L.lib()
+        self.problems = list(problems)
+        n = len(self.problems)
+        descs = (L.InstanceDesc * n)()
+        self._keep = []
+        for k, p in enumerate(self.problems):
+            ox, oy, w = quadrature(p["quad"])
+            reg = np.ascontiguousarray(p["region"], dtype=np.int32)
+            self._keep += [ox, oy, w, reg]
+            box = p["box"]
+            d = descs[k]
+            d.dim, d.nx, d.ny = p["dim"], p["nx"], p["ny"]
+            d.x0, d.x1, d.y0, d.y1 = box
+            d.n_ord = len(w)
+            d.omega_x = ox.ctypes.data_as(L.pdbl)
+            d.omega_y = oy.ctypes.data_as(L.pdbl)
+            d.weight = w.ctypes.data_as(L.pdbl)
+            d.region = reg.ctypes.data_as(L.pi32)
+            d.n_regions = int(len(p["sigma_t"]))
+        h = C.c_void_p()
+        check(lib.rte_batch_create(descs, n, C.byref(h)), "rte_batch_create")
+        self.h = h
+        self.n = n
+        self.offsets = [lib.rte_batch_offset(h, k) for k in range(n)]
+        self.ndofs = [lib.rte_batch_ndof(h, k) for k in range(n)]
+        self.psi_offsets = [lib.rte_batch_psi_offset(h, k) for k in range(n)]
+        self.total_dof = lib.rte_batch_total_dof(h)
+        self.total_psi = lib.rte_batch_total_psi(h)
+        self.max_regions = lib.rte_batch_max_regions(h)
+        self.n_ords = [len(self._keep[4 * k + 2]) for k in range(n)]
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                L.lib().rte_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ---- marshalling helpers
+    def pack(self, vectors, device="cuda"):
+        torch = _torch()
+        return torch.from_numpy(np.concatenate([np.asarray(v, dtype=np.float64) for v in vectors])).to(device)
+
+    def unpack(self, t):
+        a = t.detach().cpu().numpy()
+        return [a[o:o + n] for o, n in zip(self.offsets, self.ndofs)]
+
+    def unpack_psi(self, t):
+        a = t.detach().cpu().numpy()
+        return [a[o:o + n * no].reshape(no, n) for o, n, no in zip(self.psi_offsets, self.ndofs, self.n_ords)]
+
+    def sigma(self, device="cuda"):
+        torch = _torch()
+        st = np.zeros((self.n, self.max_regions))
+        ss = np.zeros((self.n, self.max_regions))
+        for k, p in enumerate(self.problems):
+            st[k, :len(p["sigma_t"])] = p["sigma_t"]
+            ss[k, :len(p["sigma_s"])] = p["sigma_s"]
+        return torch.from_numpy(st).to(device), torch.from_numpy(ss).to(device)
+
+    def inflow(self, device="cuda"):
+        torch = _torch()
+        g = np.array([float(p.get("inflow", 0.0)) for p in self.problems])
+        if not np.any(g):
+            return None
+        return torch.from_numpy(g).to(device)
+
+    def source(self, device="cuda"):
+        return self.pack([p["source"] for p in self.problems], device)
+
+    def zeros(self, n=None):
+        torch = _torch()
+        return torch.zeros(self.total_dof if n is None else n, dtype=torch.float64, device="cuda")
+
+
+def sweep(batch, sigma_t, q, inflow=None, phi=True, psi=False, dtype="f64"):
+    torch = _torch()
+    phi_t = torch.empty(batch.total_dof, dtype=torch.float64, device="cuda") if phi else None
+    psi_t = torch.empty(batch.total_psi, dtype=torch.float64, device="cuda") if psi else None
+    check(L.lib().rte_sweep(batch.h, _ptr(sigma_t), _ptr(q), _ptr(inflow), _ptr(phi_t), _ptr(psi_t),
+                            _dt(dtype), _stream()), "rte_sweep")
+    return phi_t, psi_t
+
+
+def scalar_flux(batch, psi):
+    out = batch.zeros()
+    check(L.lib().rte_scalar_flux(batch.h, _ptr(psi), _ptr(out), _stream()), "rte_scalar_flux")
+    return out
+
+
+def apply_A(batch, sigma_t, sigma_s, x, dtype="f64"):
+    y = batch.zeros()
+    check(L.lib().rte_apply_A(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(x), _ptr(y), _dt(dtype),
+                              _stream()), "rte_apply_A")
+    return y
+
+
+def rhs(batch, sigma_t, G, inflow=None, dtype="f64"):
+    y = batch.zeros()
+    check(L.lib().rte_rhs(batch.h, _ptr(sigma_t), _ptr(G), _ptr(inflow), _ptr(y), _dt(dtype),
+                          _stream()), "rte_rhs")
+    return y
+
+
+def dsa_apply(batch, sigma_t, sigma_s, v, inner_tol=1e-13, inner_max=2000, restart=60):
+    z = batch.zeros()
+    iters = np.zeros(batch.n, dtype=np.int32)
+    check(L.lib().rte_dsa_apply(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(v), _ptr(z), inner_tol,
+                                inner_max, restart, iters.ctypes.data_as(L.pi32), _stream()),
+          "rte_dsa_apply")
+    return z, iters
+
+
+class SolveOptions:
+    def __init__(self, precond="dsa", m=30, max_cycles=20, sweep_dtype="f64", rtol=1e-8, window=2,
+                 dsa_inner_max=30, dsa_restart=30, dsa_inner_tol=1e-10):
+        self.precond = {"none": RTE_PC_NONE, "dsa": RTE_PC_DSA, "romsad": RTE_PC_ROMSAD,
+                        "mlp": RTE_PC_MLP}[precond] if isinstance(precond, str) else precond
+        self.m, self.max_cycles, self.sweep_dtype, self.rtol = m, max_cycles, sweep_dtype, rtol
+        self.window = window
+        self.dsa_inner_max, self.dsa_restart, self.dsa_inner_tol = dsa_inner_max, dsa_restart, dsa_inner_tol
+
+    def c(self):
+        o = L.SolveOpts()
+        o.precond, o.m, o.max_cycles = self.precond, self.m, self.max_cycles
+        o.sweep_dtype = _dt(self.sweep_dtype)
+        o.rtol, o.window = self.rtol, self.window
+        o.dsa_inner_max, o.dsa_restart, o.dsa_inner_tol = self.dsa_inner_max, self.dsa_restart, self.dsa_inner_tol
+        o.keep_krylov = 0
+        return o
+
+
+def _stats_dict(s):
+    return {f: getattr(s, f) for f, _ in L.SolveStats._fields_}
+
+
+def fgmres_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None, mlp=None, mu=None):
+    opts = opts or SolveOptions()
+    phi = batch.zeros()
+    stats = (L.SolveStats * batch.n)()
+    co = opts.c()
+    mu_dim = 0 if mu is None else int(mu.shape[1])
+    st = L.lib().fgmres_solve(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow), C.byref(co),
+                              rom.h if rom is not None else None, mlp.h if mlp is not None else None,
+                              _ptr(mu), mu_dim, _ptr(phi), stats, _stream())
+    check(st, "fgmres_solve")
+    return phi, [_stats_dict(s) for s in stats], st
+
+
+class Rom:
+    def __init__(self, h):
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                L.lib().rte_rom_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def rank(self):
+        return L.lib().rte_rom_rank(self.h)
+
+    @staticmethod
+    def from_basis(batch, U):
+        h = C.c_void_p()
+        check(L.lib().rte_rom_from_basis(batch.h, _ptr(U), int(U.shape[0]), C.byref(h), _stream()),
+              "rte_rom_from_basis")
+        return Rom(h)
+
+    def export(self, nord, ndof, n_regions):
+        r = self.rank
+        U = np.zeros((r, nord, ndof))
+        W1 = np.zeros((r, ndof))
+        Ww = np.zeros((r, ndof))
+        AD = np.zeros((r, r))
+        G = np.zeros((n_regions, r, r))
+        S = np.zeros((n_regions, r, r))
+        check(L.lib().rte_rom_export(self.h, *(a.ctypes.data_as(L.pdbl) for a in (U, W1, Ww, AD, G, S))),
+              "rte_rom_export")
+        return dict(U=U, W1=W1, Ww=Ww, AD=AD, G=G, S=S)
+
+    def save(self, path):
+        check(L.lib().rte_rom_save(self.h, path.encode()), "rte_rom_save")
+
+    @staticmethod
+    def load(path):
+        h = C.c_void_p()
+        check(L.lib().rte_rom_load(path.encode(), C.byref(h)), "rte_rom_load")
+        return Rom(h)
+
+
+def romsad_build_greedy(batch, sigma_t, sigma_s, G, inflow=None, window=2, mu1_index=0, eps_rom=1e-9,
+                        n_giter=16, eps_qr=1e-13, hf_rtol=1e-11):
+    h = C.c_void_p()
+    rep = L.GreedyReport()
+    check(L.lib().romsad_build_greedy(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow),
+                                      window, mu1_index, eps_rom, n_giter, eps_qr, hf_rtol,
+                                      C.byref(h), C.byref(rep), _stream()), "romsad_build_greedy")
+    report = dict(sampled=list(rep.sampled[:rep.n_sampled]),
+                  max_residual=list(rep.max_residual[:max(rep.n_sampled - 1, 0) + 1]),
+                  rank=rep.rank, truncated=rep.truncated, seconds_step=list(rep.seconds_step))
+    return Rom(h), report
+
+
+def romsad_apply(rom, batch, sigma_t, sigma_s, v):
+    z = batch.zeros()
+    st = L.lib().romsad_apply(rom.h, batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(v), _ptr(z), _stream())
+    check(st, "romsad_apply")
+    return z

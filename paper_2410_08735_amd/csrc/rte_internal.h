@@ -1,0 +1,112 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rte_romsad.h"
+
+#define RTE_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      std::fprintf(stderr, "rte: HIP error %s at %s:%d\n", hipGetErrorString(e_), __FILE__, \
+                   __LINE__);                                                               \
+      return RTE_EHIP;                                                                      \
+    }                                                                                       \
+  } while (0)
+
+#define RTE_TRY(call)          \
+  do {                         \
+    int s_ = (call);           \
+    if (s_ < 0) return s_;     \
+  } while (0)
+
+namespace rte {
+
+// Device-side description of one instance (read by every kernel).
+struct InstDev {
+  int32_t dim, nx, ny, nloc;
+  double hx, hy;
+  int32_t n_ord;
+  int32_t ord_off;    // offset into the batch's ordinate arrays
+  int64_t dof_off;    // offset into packed dof vectors
+  int64_t psi_off;    // offset into packed angular-flux vectors
+  int32_t region_off; // offset into the packed cell -> region map
+  int32_t n_regions;
+  int32_t quad_first[4]; // first sorted ordinate of each quadrant (2D) / sign (1D)
+  int32_t quad_count[4];
+};
+
+// Where one instance's partial flux vectors live in the partial buffer.
+struct InstPart {
+  int64_t off;   // element offset
+  int32_t n;     // number of partial vectors (each ndof long)
+  int32_t pad;
+};
+
+// One sweep work item: an instance, a quadrant and a block of <= G ordinates
+// of that quadrant (indices into the instance's quadrant-sorted ordinate list).
+struct SweepItem {
+  int32_t inst;
+  int32_t quadrant;  // bit 0: Omega_x < 0, bit 1: Omega_y < 0
+  int32_t first;     // position in the instance's sorted ordinate list
+  int32_t count;
+  int64_t part_off;  // element offset of this item's partial flux vector
+  int64_t pad;
+};
+
+struct Plan {
+  int G = 8;       // ordinates per work group (2D); 1D uses one thread per ordinate
+  int threads = 256;
+  std::vector<SweepItem> items;
+  std::vector<InstPart> parts;
+  SweepItem* d_items = nullptr;
+  InstPart* d_parts = nullptr;
+  int n_items = 0;
+  int64_t part_elems = 0;
+  bool tuned = false;
+};
+
+}  // namespace rte
+
+struct rte_batch {
+  int n_inst = 0;
+  int max_regions = 1;
+  int max_nx = 0, max_ny = 0, max_ord = 0;
+  int64_t total_dof = 0, total_psi = 0;
+  std::vector<rte::InstDev> inst;      // host copy
+  rte::InstDev* d_inst = nullptr;
+  // ordinates packed per instance, sorted by quadrant (sorted order is what
+  // kernels see; perm maps sorted position -> original ordinate index)
+  std::vector<double> ox, oy, w;
+  std::vector<int32_t> perm;
+  double *d_ox = nullptr, *d_oy = nullptr, *d_w = nullptr;
+  int32_t* d_perm = nullptr;
+  int32_t* d_region = nullptr;
+  int64_t total_cells = 0;
+  // plans for the 2D sweep, per precision (0 = f64, 1 = f32), and the 1D plan
+  rte::Plan plan[2];
+  // scratch owned by the batch
+  void* d_part = nullptr;   // sweep partial fluxes (sized for f64)
+  int64_t part_capacity = 0;
+  bool uniform = true;      // every instance has the same grid and ordinates
+  int dim = 2;
+};
+
+namespace rte {
+
+int ensure_partials(rte_batch* b, int64_t elems);
+int make_plan(rte_batch* b, int prec, int G, int threads);
+int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
+                 const double* qx, const double* qadd, const double* inflow, double* psi_out,
+                 hipStream_t s, const int32_t* active = nullptr);
+// out = alpha * sum_partials + beta * x   (x nullable)
+int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
+                    hipStream_t s, const int32_t* active = nullptr);
+int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s);
+
+}  // namespace rte

@@ -1,0 +1,456 @@
+// Transport sweep (section 3.1) and the quadrature reduction phi = sum_j w_j psi_j.
+//
+// X-Y geometry, Q1 upwind DG.  One work group handles one instance, one
+// quadrant of directions and a block of G ordinates of that quadrant.  Cells
+// are visited by anti-diagonals of the quadrant's upwind order (the KBA
+// wavefront): every cell on diagonal s depends only on cells of diagonal
+// s - 1, so the whole diagonal times G ordinates is processed in parallel and
+// one barrier separates diagonals.  Outgoing face traces go to LDS: the
+// x-trace of a cell indexed by its row, the y-trace by its column; no two
+// cells of one diagonal share a row or a column, so a single LDS buffer of each
+// kind needs no double buffering.
+//
+// Every cell is solved in the quadrant's mirrored coordinates (s -> -s along
+// each reversed axis, which flips the sign of the odd Legendre modes), where
+// the local system is always
+//   (sigma I + a K (x) I + b I (x) K) psi = q + inflow terms,
+//   K = [[1, sqrt3], [-sqrt3, 3]],  a = |Omega_x| / h_x,  b = |Omega_y| / h_y,
+// with K the upwind-flux matrix of the orthonormal degree-1 Legendre basis
+// for a positive direction.  The 4x4 solve is done in closed form: the
+// matrices aI + bK form a commutative algebra (K^2 = 4K - 6I), so the block
+// elimination along y needs one reciprocal per cell.
+//
+// The G lanes holding one cell's ordinates are adjacent; their weighted sum
+// (the quadrature reduction) is formed with cross-lane shuffles and written
+// once per cell as one partial scalar flux of the ordinate block.  A second,
+// deterministic pass sums the partials in a fixed order (reduce_partials).
+#include <algorithm>
+#include <cmath>
+
+#include "rte_internal.h"
+
+namespace rte {
+
+template <typename real>
+struct Vec4 {
+  real v[4];
+};
+
+__device__ __forceinline__ double shfl_xor_r(double x, int m, int w) { return __shfl_xor(x, m, w); }
+__device__ __forceinline__ float shfl_xor_r(float x, int m, int w) { return __shfl_xor(x, m, w); }
+
+// Closed-form solve of (sig I + a K(x)I + b I(x)K) x = r, dof order p + 2q.
+// Algebra elements (al, be) stand for al I + be K acting on the p-pair.
+template <typename real>
+__device__ __forceinline__ void local_solve(real sig, real a, real b, const real r[4], real x[4]) {
+  const real r3 = (real)1.7320508075688772935;
+  const real a0 = sig + b;
+  const real a1 = sig + (real)3 * b;
+  const real adj0a = a0 + (real)4 * a, adj0b = -a;
+  const real det0 = a0 * a0 + (real)4 * a0 * a + (real)6 * a * a;
+  const real b2 = (real)3 * b * b;
+  const real sa = det0 * a1 + b2 * adj0a;
+  const real sb = (det0 - b2) * a;
+  const real detS = sa * sa + (real)4 * sa * sb + (real)6 * sb * sb;
+  const real adjSa = sa + (real)4 * sb, adjSb = -sb;
+  const real inv = (real)1 / (det0 * detS);
+  // u = adj0 r0, r0 = (r[0], r[1])
+  real k0 = r[0] + r3 * r[1], k1 = -r3 * r[0] + (real)3 * r[1];
+  const real u0 = adj0a * r[0] + adj0b * k0, u1 = adj0a * r[1] + adj0b * k1;
+  const real br3 = b * r3;
+  const real t0 = det0 * r[2] + br3 * u0, t1 = det0 * r[3] + br3 * u1;
+  k0 = t0 + r3 * t1;
+  k1 = -r3 * t0 + (real)3 * t1;
+  const real f1 = det0 * inv;
+  x[2] = (adjSa * t0 + adjSb * k0) * f1;
+  x[3] = (adjSa * t1 + adjSb * k1) * f1;
+  const real e0 = r[0] - br3 * x[2], e1 = r[1] - br3 * x[3];
+  k0 = e0 + r3 * e1;
+  k1 = -r3 * e0 + (real)3 * e1;
+  const real f0 = detS * inv;
+  x[0] = (adj0a * e0 + adj0b * k0) * f0;
+  x[1] = (adj0a * e1 + adj0b * k1) * f0;
+}
+
+template <typename real, int G>
+__global__ void __launch_bounds__(512) sweep2d_kernel(
+    const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
+    const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ region,
+    const double* __restrict__ sigma_t, const double* __restrict__ sigma_s, int max_regions,
+    const double* __restrict__ qx, const double* __restrict__ qadd,
+    const double* __restrict__ inflow, real* __restrict__ part, double* __restrict__ psi_out,
+    const int32_t* __restrict__ active) {
+  const SweepItem it = items[blockIdx.x];
+  if (active && !active[it.inst]) return;
+  const InstDev I = insts[it.inst];
+  const int tid = threadIdx.x;
+  const int g = tid % G;
+  const int slot = tid / G;
+  const int S = blockDim.x / G;
+  const int nx = I.nx, ny = I.ny;
+  const bool lane_on = g < it.count;
+  const int js = I.ord_off + it.first + (lane_on ? g : 0);
+  const real a = (real)(fabs(ox[js]) / I.hx);
+  const real b = (real)(fabs(oy[js]) / I.hy);
+  const real wt = lane_on ? (real)w[js] : (real)0;
+  const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
+  const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
+  const real r3 = (real)1.7320508075688772935;
+  const real gin = inflow ? (real)(inflow[it.inst] * sqrt(I.hx * I.hy)) : (real)0;
+  extern __shared__ unsigned char smem_raw[];
+  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G][2]
+  real* ytr = xtr + (size_t)ny * G * 2;           // [nx][G][2]
+  const double* st = sigma_t + (size_t)it.inst * max_regions;
+  const double* ss = sigma_s ? sigma_s + (size_t)it.inst * max_regions : nullptr;
+  const int32_t* reg = region + I.region_off;
+  const double* qxi = qx ? qx + I.dof_off : nullptr;
+  const double* qai = qadd ? qadd + I.dof_off : nullptr;
+  real* P = part + it.part_off;
+  double* psi_j = nullptr;
+  if (psi_out && lane_on) psi_j = psi_out + I.psi_off + (int64_t)perm[js] * nx * ny * 4;
+
+  for (int s = 0; s < nx + ny - 1; ++s) {
+    const int r_lo = max(0, s - nx + 1), r_hi = min(ny - 1, s);
+    for (int r = r_lo + slot; r <= r_hi; r += S) {
+      const int i = s - r;
+      const int ip = fx ? nx - 1 - i : i;
+      const int kp = fy ? ny - 1 - r : r;
+      const int cell = kp * nx + ip;
+      double q[4] = {0.0, 0.0, 0.0, 0.0};
+      const int rg = reg[cell];
+      if (qxi) {
+        const double sg = ss[rg];
+        const double4 v = *reinterpret_cast<const double4*>(qxi + 4 * (int64_t)cell);
+        q[0] = sg * v.x; q[1] = sg * v.y; q[2] = sg * v.z; q[3] = sg * v.w;
+      }
+      if (qai) {
+        const double4 v = *reinterpret_cast<const double4*>(qai + 4 * (int64_t)cell);
+        q[0] += v.x; q[1] += v.y; q[2] += v.z; q[3] += v.w;
+      }
+      const real sig = (real)st[rg];
+      real tx0, tx1, ty0, ty1;
+      if (i == 0) { tx0 = gin; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
+      if (r == 0) { ty0 = gin; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
+      real rhs[4];
+      rhs[0] = (real)q[0] + a * tx0 + b * ty0;
+      rhs[1] = mx * (real)q[1] - r3 * a * tx0 + b * ty1;
+      rhs[2] = my * (real)q[2] + a * tx1 - r3 * b * ty0;
+      rhs[3] = mx * my * (real)q[3] - r3 * (a * tx1 + b * ty1);
+      real x[4];
+      local_solve<real>(sig, a, b, rhs, x);
+      xtr[(r * G + g) * 2] = x[0] + r3 * x[1];
+      xtr[(r * G + g) * 2 + 1] = x[2] + r3 * x[3];
+      ytr[(i * G + g) * 2] = x[0] + r3 * x[2];
+      ytr[(i * G + g) * 2 + 1] = x[1] + r3 * x[3];
+      real c[4] = {wt * x[0], wt * x[1], wt * x[2], wt * x[3]};
+#pragma unroll
+      for (int m = G / 2; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) c[d] += shfl_xor_r(c[d], m, G);
+      }
+      if (g == 0) {
+        real* o = P + 4 * (int64_t)cell;
+        o[0] = c[0];
+        o[1] = mx * c[1];
+        o[2] = my * c[2];
+        o[3] = mx * my * c[3];
+      }
+      if (psi_j) {
+        double* o = psi_j + 4 * (int64_t)cell;
+        o[0] = (double)x[0];
+        o[1] = (double)(mx * x[1]);
+        o[2] = (double)(my * x[2]);
+        o[3] = (double)(mx * my * x[3]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Slab geometry, P1: one thread per (instance, ordinate), cells in upwind order.
+template <typename real>
+__global__ void sweep1d_kernel(const InstDev* __restrict__ insts, const InstPart* __restrict__ parts,
+                               const double* __restrict__ ox, const double* __restrict__ w,
+                               const int32_t* __restrict__ perm, const int32_t* __restrict__ region,
+                               const double* __restrict__ sigma_t,
+                               const double* __restrict__ sigma_s, int max_regions,
+                               const double* __restrict__ qx, const double* __restrict__ qadd,
+                               const double* __restrict__ inflow, real* __restrict__ part,
+                               double* __restrict__ psi_out, const int32_t* __restrict__ active) {
+  const int inst = blockIdx.x;
+  if (active && !active[inst]) return;
+  const InstDev I = insts[inst];
+  const int js_loc = threadIdx.x;
+  if (js_loc >= I.n_ord) return;
+  const int js = I.ord_off + js_loc;
+  const real r3 = (real)1.7320508075688772935;
+  const double mu = ox[js];
+  const bool flip = mu < 0.0;
+  const real m1 = flip ? (real)-1 : (real)1;
+  const real a = (real)(fabs(mu) / I.hx);
+  const real wt = (real)w[js];
+  const int nx = I.nx;
+  const double* st = sigma_t + (size_t)inst * max_regions;
+  const double* ss = sigma_s ? sigma_s + (size_t)inst * max_regions : nullptr;
+  const int32_t* reg = region + I.region_off;
+  real* P = part + parts[inst].off + (int64_t)js_loc * nx * 2;
+  double* psi_j = psi_out ? psi_out + I.psi_off + (int64_t)perm[js] * nx * 2 : nullptr;
+  real T = inflow ? (real)(inflow[inst] * sqrt(I.hx)) : (real)0;
+  for (int i = 0; i < nx; ++i) {
+    const int cell = flip ? nx - 1 - i : i;
+    const int rg = reg[cell];
+    double q0 = 0.0, q1 = 0.0;
+    if (qx) {
+      q0 = ss[rg] * qx[I.dof_off + 2 * cell];
+      q1 = ss[rg] * qx[I.dof_off + 2 * cell + 1];
+    }
+    if (qadd) {
+      q0 += qadd[I.dof_off + 2 * cell];
+      q1 += qadd[I.dof_off + 2 * cell + 1];
+    }
+    const real sig = (real)st[rg];
+    const real r0 = (real)q0 + a * T;
+    const real r1 = m1 * (real)q1 - r3 * a * T;
+    // (sig I + a K) x = r: adj = (sig + 4a) I - a K, det = sig^2 + 4 sig a + 6 a^2
+    const real det = sig * sig + (real)4 * sig * a + (real)6 * a * a;
+    const real inv = (real)1 / det;
+    const real k0 = r0 + r3 * r1, k1 = -r3 * r0 + (real)3 * r1;
+    const real x0 = ((sig + (real)4 * a) * r0 - a * k0) * inv;
+    const real x1 = ((sig + (real)4 * a) * r1 - a * k1) * inv;
+    T = x0 + r3 * x1;
+    P[2 * cell] = wt * x0;
+    P[2 * cell + 1] = wt * m1 * x1;
+    if (psi_j) {
+      psi_j[2 * cell] = (double)x0;
+      psi_j[2 * cell + 1] = (double)(m1 * x1);
+    }
+  }
+}
+
+template <typename real>
+__global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
+                                       const InstPart* __restrict__ parts,
+                                       const real* __restrict__ part, double alpha,
+                                       const double* __restrict__ x, double beta,
+                                       double* __restrict__ out, const int32_t* __restrict__ active) {
+  const int inst = blockIdx.y;
+  if (active && !active[inst]) return;
+  const InstDev I = insts[inst];
+  const int64_t nd = (int64_t)I.nx * I.ny * I.nloc;
+  const InstPart pp = parts[inst];
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    const real* p = part + pp.off + d;
+    for (int k = 0; k < pp.n; ++k) acc += (double)p[(int64_t)k * nd];
+    double v = alpha * acc;
+    if (x) v += beta * x[I.dof_off + d];
+    out[I.dof_off + d] = v;
+  }
+}
+
+__global__ void scalar_flux_kernel(const InstDev* __restrict__ insts, const double* __restrict__ w,
+                                   const int32_t* __restrict__ perm,
+                                   const double* __restrict__ psi, double* __restrict__ phi) {
+  const int inst = blockIdx.y;
+  const InstDev I = insts[inst];
+  const int64_t nd = (int64_t)I.nx * I.ny * I.nloc;
+  extern __shared__ double wl[];  // weights in original ordinate order
+  for (int s = threadIdx.x; s < I.n_ord; s += blockDim.x) wl[perm[I.ord_off + s]] = w[I.ord_off + s];
+  __syncthreads();
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    const double* p = psi + I.psi_off + d;
+    for (int j = 0; j < I.n_ord; ++j) acc += wl[j] * p[(int64_t)j * nd];
+    phi[I.dof_off + d] = acc;
+  }
+}
+
+int ensure_partials(rte_batch* b, int64_t elems) {
+  if (elems <= b->part_capacity) return RTE_OK;
+  (void)hipFree(b->d_part);
+  b->d_part = nullptr;
+  b->part_capacity = 0;
+  if (hipMalloc(&b->d_part, sizeof(double) * elems) != hipSuccess) return RTE_ENOMEM;
+  b->part_capacity = elems;
+  return RTE_OK;
+}
+
+int make_plan(rte_batch* b, int prec, int G, int threads) {
+  Plan& p = b->plan[prec];
+  p.G = G;
+  p.threads = threads;
+  p.items.clear();
+  p.parts.clear();
+  int64_t off = 0;
+  for (int k = 0; k < b->n_inst; ++k) {
+    const InstDev& I = b->inst[k];
+    const int64_t nd = (int64_t)I.nx * I.ny * I.nloc;
+    InstPart ip{};
+    ip.off = off;
+    if (I.dim == 1) {
+      ip.n = I.n_ord;
+    } else {
+      int n = 0;
+      for (int qd = 0; qd < 4; ++qd) {
+        for (int f = 0; f < I.quad_count[qd]; f += G) {
+          SweepItem it{};
+          it.inst = k;
+          it.quadrant = qd;
+          it.first = I.quad_first[qd] + f;
+          it.count = std::min(G, I.quad_count[qd] - f);
+          it.part_off = off + (int64_t)n * nd;
+          p.items.push_back(it);
+          ++n;
+        }
+      }
+      ip.n = n;
+    }
+    off += (int64_t)ip.n * nd;
+    p.parts.push_back(ip);
+  }
+  p.part_elems = off;
+  p.n_items = (int)p.items.size();
+  (void)hipFree(p.d_items);
+  (void)hipFree(p.d_parts);
+  p.d_items = nullptr;
+  p.d_parts = nullptr;
+  if (p.n_items > 0) {
+    if (hipMalloc(&p.d_items, sizeof(SweepItem) * p.n_items) != hipSuccess) return RTE_ENOMEM;
+    RTE_HIP(hipMemcpy(p.d_items, p.items.data(), sizeof(SweepItem) * p.n_items,
+                      hipMemcpyHostToDevice));
+  }
+  if (hipMalloc(&p.d_parts, sizeof(InstPart) * b->n_inst) != hipSuccess) return RTE_ENOMEM;
+  RTE_HIP(hipMemcpy(p.d_parts, p.parts.data(), sizeof(InstPart) * b->n_inst,
+                    hipMemcpyHostToDevice));
+  return ensure_partials(b, off);
+}
+
+template <typename real, int G>
+static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const double* sigma_s,
+                    const double* qx, const double* qadd, const double* inflow, double* psi_out,
+                    hipStream_t s, const int32_t* active) {
+  const size_t lds = (size_t)(b->max_nx + b->max_ny) * G * 2 * sizeof(real);
+  if (lds > 64 * 1024) return RTE_EINVAL;  // per-work-group LDS limit used by this library
+  hipLaunchKernelGGL((sweep2d_kernel<real, G>), dim3(p.n_items), dim3(p.threads), lds, s,
+                     b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
+                     sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
+                     reinterpret_cast<real*>(b->d_part), psi_out, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+template <typename real>
+static int launch2d_g(rte_batch* b, const Plan& p, const double* st, const double* ss,
+                      const double* qx, const double* qa, const double* inf, double* psi,
+                      hipStream_t s, const int32_t* act) {
+  switch (p.G) {
+    case 1: return launch2d<real, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 2: return launch2d<real, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 4: return launch2d<real, 4>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 8: return launch2d<real, 8>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 16: return launch2d<real, 16>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 32: return launch2d<real, 32>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    default: return RTE_EINVAL;
+  }
+}
+
+int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
+                 const double* qx, const double* qadd, const double* inflow, double* psi_out,
+                 hipStream_t s, const int32_t* active) {
+  const Plan& p = b->plan[prec];
+  if (b->dim == 1) {
+    if (b->max_ord > 1024) return RTE_EINVAL;
+    int threads = ((b->max_ord + 63) / 64) * 64;
+    if (prec == 0)
+      hipLaunchKernelGGL(sweep1d_kernel<double>, dim3(b->n_inst), dim3(threads), 0, s, b->d_inst,
+                         p.d_parts, b->d_ox, b->d_w, b->d_perm, b->d_region, sigma_t, sigma_s,
+                         b->max_regions, qx, qadd, inflow, reinterpret_cast<double*>(b->d_part),
+                         psi_out, active);
+    else
+      hipLaunchKernelGGL(sweep1d_kernel<float>, dim3(b->n_inst), dim3(threads), 0, s, b->d_inst,
+                         p.d_parts, b->d_ox, b->d_w, b->d_perm, b->d_region, sigma_t, sigma_s,
+                         b->max_regions, qx, qadd, inflow, reinterpret_cast<float*>(b->d_part),
+                         psi_out, active);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
+  if (prec == 0)
+    return launch2d_g<double>(b, p, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+  return launch2d_g<float>(b, p, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+}
+
+int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
+                    hipStream_t s, const int32_t* active) {
+  const Plan& p = b->plan[prec];
+  int64_t maxnd = 0;
+  for (const auto& I : b->inst) maxnd = std::max<int64_t>(maxnd, (int64_t)I.nx * I.ny * I.nloc);
+  dim3 grid((unsigned)std::min<int64_t>((maxnd + 255) / 256, 1024), b->n_inst);
+  if (prec == 0)
+    hipLaunchKernelGGL(reduce_partials_kernel<double>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
+                       reinterpret_cast<const double*>(b->d_part), alpha, x, beta, out, active);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel<float>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
+                       reinterpret_cast<const float*>(b->d_part), alpha, x, beta, out, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s) {
+  int64_t maxnd = 0;
+  for (const auto& I : b->inst) maxnd = std::max<int64_t>(maxnd, (int64_t)I.nx * I.ny * I.nloc);
+  dim3 grid((unsigned)std::min<int64_t>((maxnd + 255) / 256, 1024), b->n_inst);
+  hipLaunchKernelGGL(scalar_flux_kernel, grid, dim3(256), sizeof(double) * b->max_ord, s,
+                     b->d_inst, b->d_w, b->d_perm, psi, phi);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+// Pick G (ordinates per work group) and the work-group size for this batch by
+// timing one sweep of each candidate that fits; the fastest plan is kept.
+int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s) {
+  Plan& cur = b->plan[prec];
+  if (cur.tuned || b->dim == 1) return RTE_OK;
+  const int cand_G[] = {4, 8, 16, 32};
+  const int cand_T[] = {128, 256, 512};
+  hipEvent_t e0, e1;
+  RTE_HIP(hipEventCreate(&e0));
+  RTE_HIP(hipEventCreate(&e1));
+  // a zero source keeps the timing free of data effects
+  double* q = nullptr;
+  if (hipMalloc(&q, sizeof(double) * b->total_dof) != hipSuccess) return RTE_ENOMEM;
+  RTE_HIP(hipMemsetAsync(q, 0, sizeof(double) * b->total_dof, s));
+  float best = 1e30f;
+  int bestG = cur.G, bestT = cur.threads;
+  for (int G : cand_G) {
+    for (int T : cand_T) {
+      if (T % G || T / G < 1) continue;
+      const size_t lds = (size_t)(b->max_nx + b->max_ny) * G * 2 * (prec == 0 ? 8 : 4);
+      if (lds > 64 * 1024) continue;
+      RTE_TRY(make_plan(b, prec, G, T));
+      RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
+      RTE_HIP(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 3; ++rep)
+        RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
+      RTE_HIP(hipEventRecord(e1, s));
+      RTE_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      RTE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bestG = G;
+        bestT = T;
+      }
+    }
+  }
+  (void)hipFree(q);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  RTE_TRY(make_plan(b, prec, bestG, bestT));
+  b->plan[prec].tuned = true;
+  return RTE_OK;
+}
+
+}  // namespace rte
