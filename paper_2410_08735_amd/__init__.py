@@ -225,9 +225,13 @@ class Rom:
 
     @staticmethod
     def from_basis(batch, U):
+        """U: device tensor holding r basis vectors of instance 0's psi-space."""
+        npsi = batch.ndofs[0] * batch.n_ords[0]
+        if U.numel() % npsi:
+            raise ValueError("basis size is not a multiple of the psi-space size")
         h = C.c_void_p()
-        check(L.lib().rte_rom_from_basis(batch.h, _ptr(U), int(U.shape[0]), C.byref(h), _stream()),
-              "rte_rom_from_basis")
+        check(L.lib().rte_rom_from_basis(batch.h, _ptr(U.contiguous()), int(U.numel() // npsi),
+                                         C.byref(h), _stream()), "rte_rom_from_basis")
         return Rom(h)
 
     def export(self, nord, ndof, n_regions):

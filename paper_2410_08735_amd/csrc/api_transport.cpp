@@ -1,9 +1,6 @@
 // C-ABI entry points for the transport operators (sections 2.3, 3.1, 3.2).
 #include "rte_internal.h"
 
-namespace rte {
-int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s);
-}
 
 static inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 

@@ -224,6 +224,9 @@ extern "C" int rte_batch_create(const rte_instance_desc* desc, int n_inst, rte_b
 
 extern "C" void rte_batch_destroy(rte_batch* b) {
   if (!b) return;
+  rte::dsa_forget(b);
+  rte::fgmres_forget(b);
+  rte::rom_scratch_forget(b);
   (void)hipFree(b->d_inst);
   (void)hipFree(b->d_ox);
   (void)hipFree(b->d_oy);

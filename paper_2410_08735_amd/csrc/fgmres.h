@@ -1,0 +1,39 @@
+// Batched flexible GMRES driver (Alg. 1).
+#pragma once
+#include "rom.h"
+
+namespace rte {
+
+struct SolveCtx {
+  const rte_solve_opts* opts;
+  const double *sigma_t, *sigma_s, *G, *inflow;
+  const rte_rom* rom;
+  const rte_mlp* mlp;
+  const double* mu;
+  int mu_dim;
+  const int32_t* init_active;  // device mask of instances to solve (nullable = all)
+  int keep;                    // record cycle 0's first `keep` Krylov vectors
+};
+
+struct Fgmres {
+  rte_batch* b = nullptr;
+  int m = 0;
+  Krylov K;
+  double *btil = nullptr, *r = nullptr, *bnorm = nullptr, *tolabs = nullptr, *rnorm = nullptr;
+  int32_t *cyc = nullptr, *flags = nullptr;
+  // record of cycle 0 (xi recurrence): Z_0..Z_{w-1}, H block [(w+1) x w], beta
+  double *recZ = nullptr, *recH = nullptr, *recBeta = nullptr;
+  int rec_w = 0;
+  std::vector<int32_t> rec_jdone;
+  int init(rte_batch* b, int m);
+  void release();
+  void rec_release();
+  int precondition(int jj, const double* v, double* z, const SolveCtx& c, hipStream_t s,
+                   std::vector<int32_t>& which);
+  int solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s);
+};
+
+Fgmres* fgmres_for(rte_batch* b, int m);
+void fgmres_forget(rte_batch* b);
+
+}  // namespace rte

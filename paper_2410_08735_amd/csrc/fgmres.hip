@@ -1,0 +1,270 @@
+// Flexible GMRES (Alg. 1) over a batch of instances, restarted from FP64 true
+// residuals (the flexible outer iteration acts as refinement for FP32 sweeps).
+#include <algorithm>
+#include <cmath>
+
+#include "fgmres.h"
+
+namespace rte {
+
+int Fgmres::init(rte_batch* batch, int m_) {
+  b = batch;
+  m = m_;
+  std::vector<int64_t> lens(b->n_inst);
+  for (int k = 0; k < b->n_inst; ++k) lens[k] = rte_batch_ndof(b, k);
+  RTE_TRY(K.init(lens, m, true));
+  const int64_t tot = b->total_dof;
+  const int n = b->n_inst;
+  if (hipMalloc(&btil, sizeof(double) * tot) != hipSuccess ||
+      hipMalloc(&r, sizeof(double) * tot) != hipSuccess ||
+      hipMalloc(&bnorm, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&tolabs, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&rnorm, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&cyc, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&flags, sizeof(int32_t) * n) != hipSuccess)
+    return RTE_ENOMEM;
+  return RTE_OK;
+}
+
+void Fgmres::release() {
+  K.release();
+  for (void* p : {(void*)btil, (void*)r, (void*)bnorm, (void*)tolabs, (void*)rnorm, (void*)cyc,
+                  (void*)flags})
+    (void)hipFree(p);
+  btil = r = bnorm = tolabs = rnorm = nullptr;
+  cyc = flags = nullptr;
+  rec_release();
+}
+
+void Fgmres::rec_release() {
+  (void)hipFree(recZ);
+  (void)hipFree(recH);
+  (void)hipFree(recBeta);
+  recZ = recH = recBeta = nullptr;
+  rec_w = 0;
+}
+
+__global__ void k_tolabs(int n, const double* __restrict__ bnorm, double rtol, double* __restrict__ tol) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) tol[b] = rtol * bnorm[b];
+}
+
+__global__ void k_copy_h(int n, const double* __restrict__ H, int m, double* __restrict__ out, int w,
+                         const double* __restrict__ scal, double* __restrict__ beta) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  for (int i = 0; i <= w; ++i)
+    for (int j = 0; j < w; ++j)
+      out[((int64_t)b * (w + 1) + i) * w + j] = (j < m && i <= m) ? H[(int64_t)b * (m + 1) * m + (int64_t)i * m + j] : 0.0;
+  beta[b] = scal[b * 8 + 0];
+}
+
+int Fgmres::precondition(int jj, const double* v, double* z, const SolveCtx& c, hipStream_t s,
+                         std::vector<int32_t>& which) {
+  const rte_solve_opts& o = *c.opts;
+  int kind = o.precond;
+  if ((kind == RTE_PC_ROMSAD || kind == RTE_PC_MLP) && (jj > o.window || !c.rom)) kind = RTE_PC_DSA;
+  if (kind == RTE_PC_MLP && !c.mlp) kind = RTE_PC_ROMSAD;
+  which.assign(b->n_inst, kind);
+  switch (kind) {
+    case RTE_PC_NONE:
+      return kcopy(K.sp, v, z, K.active, s);
+    case RTE_PC_DSA:
+      return dsa_apply(b, c.sigma_t, c.sigma_s, v, z, o.dsa_inner_tol, o.dsa_inner_max,
+                       o.dsa_restart, K.active, nullptr, s);
+    case RTE_PC_ROMSAD: {
+      int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, K.active, s);
+      return st == RTE_ESINGULAR ? RTE_OK : st;
+    }
+    case RTE_PC_MLP: {
+      RTE_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * b->n_inst, s));
+      RTE_TRY(mlp_precond(c.mlp, c.rom, b, c.sigma_t, c.sigma_s, c.mu, c.mu_dim, v, z, K.active, s,
+                          flags));
+      std::vector<int32_t> fb(b->n_inst);
+      RTE_HIP(hipMemcpyAsync(fb.data(), flags, sizeof(int32_t) * b->n_inst, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < b->n_inst; ++q)
+        if (fb[q]) which[q] = -RTE_PC_ROMSAD;  // fell back to the ROM solve
+      return RTE_OK;
+    }
+  }
+  return RTE_EINVAL;
+}
+
+int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s) {
+  const rte_solve_opts& o = *c.opts;
+  const int n = b->n_inst;
+  const int pin = o.sweep_dtype == RTE_F32 ? 1 : 0;
+  RTE_TRY(autotune_sweep(b, 0, c.sigma_t, s));
+  if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s));
+  for (int q = 0; q < n; ++q) stats[q] = rte_solve_stats{};
+  std::vector<int32_t> live(n, 1);
+  if (c.init_active) {
+    RTE_HIP(hipMemcpyAsync(live.data(), c.init_active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+  }
+  RTE_HIP(hipMemcpyAsync(cyc, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  // b~ = T G~ (FP64) and ||b~||
+  RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, c.G, c.inflow, nullptr, s, cyc));
+  RTE_TRY(reduce_partials(b, 0, 1.0, nullptr, 0.0, btil, s, cyc));
+  for (int q = 0; q < n; ++q)
+    if (live[q]) stats[q].sweeps_f64 += 1;
+  RTE_TRY(knorm(K.sp, btil, K.partA, bnorm, 1, cyc, s));
+  hipLaunchKernelGGL(k_tolabs, dim3((n + 63) / 64), dim3(64), 0, s, n, bnorm, o.rtol, tolabs);
+  RTE_HIP(hipMemsetAsync(phi, 0, sizeof(double) * b->total_dof, s));
+  RTE_TRY(kcopy(K.sp, btil, r, cyc, s));
+  std::vector<double> bn(n), rn(n), sc(8 * n);
+  RTE_HIP(hipMemcpyAsync(bn.data(), bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  RTE_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> conv(n, 0);
+  for (int q = 0; q < n; ++q) {
+    if (!live[q] || bn[q] == 0.0) {
+      conv[q] = 1;
+      stats[q].true_relres = 0.0;
+    }
+  }
+  std::vector<int32_t> act(n), which;
+  bool recorded = false;
+  for (int cycle = 0; cycle < o.max_cycles; ++cycle) {
+    std::vector<int32_t> cm(n);
+    int n_live = 0;
+    for (int q = 0; q < n; ++q) {
+      cm[q] = conv[q] ? 0 : 1;
+      n_live += cm[q];
+    }
+    if (!n_live) break;
+    RTE_HIP(hipMemcpyAsync(cyc, cm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    RTE_HIP(hipMemcpyAsync(K.active, cyc, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    RTE_TRY(kstart(K, r, tolabs, s));
+    act = cm;
+    for (int q = 0; q < n; ++q) stats[q].cycles += cm[q];
+    for (int j = 0; j < m; ++j) {
+      // the active mask after kstart / the previous step decides who iterates
+      RTE_HIP(hipMemcpyAsync(act.data(), K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipStreamSynchronize(s));
+      bool any = false;
+      for (int q = 0; q < n; ++q) any = any || act[q];
+      if (!any) break;
+      RTE_TRY(precondition(j + 1, K.v(j), K.z(j), c, s, which));
+      // w = A~ z_j = z_j - T Sigma_s z_j
+      RTE_TRY(sweep_launch(b, pin, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s,
+                           K.active));
+      RTE_TRY(reduce_partials(b, pin, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active));
+      RTE_TRY(arnoldi_mgs(K, j, s));
+      for (int q = 0; q < n; ++q) {
+        if (!act[q]) continue;
+        stats[q].iterations += 1;
+        if (pin) stats[q].sweeps_f32 += 1; else stats[q].sweeps_f64 += 1;
+        const int k = which[q];
+        if (k == RTE_PC_DSA) stats[q].pc_dsa += 1;
+        else if (k == RTE_PC_ROMSAD) stats[q].pc_rom += 1;
+        else if (k == RTE_PC_MLP) stats[q].pc_mlp += 1;
+        else if (k == -RTE_PC_ROMSAD) { stats[q].pc_rom += 1; stats[q].pc_fallback += 1; }
+      }
+    }
+    if (c.keep && !recorded) {
+      // keep cycle 0's preconditioned vectors and Hessenberg block for the xi recurrence
+      rec_release();
+      rec_w = std::min(c.keep, m);
+      if (hipMalloc(&recZ, sizeof(double) * rec_w * b->total_dof) != hipSuccess ||
+          hipMalloc(&recH, sizeof(double) * n * (rec_w + 1) * rec_w) != hipSuccess ||
+          hipMalloc(&recBeta, sizeof(double) * n) != hipSuccess)
+        return RTE_ENOMEM;
+      RTE_HIP(hipMemcpyAsync(recZ, K.Z, sizeof(double) * rec_w * b->total_dof,
+                             hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_copy_h, dim3((n + 63) / 64), dim3(64), 0, s, n, K.H, m, recH, rec_w,
+                         K.scal, recBeta);
+      RTE_HIP(hipMemcpyAsync(rec_jdone.data(), K.jdone, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+      recorded = true;
+    }
+    // phi += Z y ; r = b~ - A~ phi in FP64
+    RTE_TRY(kylov_solve_update(K, K.Z, phi, s));
+    RTE_TRY(sweep_launch(b, 0, c.sigma_t, c.sigma_s, phi, nullptr, nullptr, nullptr, s, cyc));
+    RTE_TRY(reduce_partials(b, 0, 1.0, btil, 1.0, r, s, cyc, phi, -1.0));
+    RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
+    RTE_HIP(hipMemcpyAsync(rn.data(), rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipMemcpyAsync(sc.data(), K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    bool all = true;
+    for (int q = 0; q < n; ++q) {
+      if (!cm[q]) continue;
+      stats[q].sweeps_f64 += 1;
+      stats[q].true_relres = rn[q] / bn[q];
+      stats[q].est_relres = sc[8 * q + 2] / bn[q];
+      if (stats[q].true_relres <= o.rtol) conv[q] = 1;
+      all = all && conv[q];
+    }
+    if (all) break;
+  }
+  int ret = RTE_OK;
+  for (int q = 0; q < n; ++q) {
+    stats[q].status = conv[q] ? RTE_OK : RTE_WNOTCONV;
+    if (!conv[q]) ret = RTE_WNOTCONV;
+  }
+  return ret;
+}
+
+struct FgCache {
+  rte_batch* b;
+  int m;
+  Fgmres* f;
+};
+static std::vector<FgCache> g_fg;
+
+Fgmres* fgmres_for(rte_batch* b, int m) {
+  for (auto& c : g_fg)
+    if (c.b == b && c.m == m) return c.f;
+  auto* f = new Fgmres();
+  f->rec_jdone.assign(b->n_inst, 0);
+  if (f->init(b, m) != RTE_OK) {
+    f->release();
+    delete f;
+    return nullptr;
+  }
+  g_fg.push_back({b, m, f});
+  return f;
+}
+
+void fgmres_forget(rte_batch* b) {
+  for (size_t i = 0; i < g_fg.size();) {
+    if (g_fg[i].b == b) {
+      g_fg[i].f->release();
+      delete g_fg[i].f;
+      g_fg.erase(g_fg.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+}  // namespace rte
+
+extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const double* sigma_s,
+                            const double* G, const double* inflow, const rte_solve_opts* opts,
+                            const rte_rom* rom, const rte_mlp* mlp, const double* mu, int mu_dim,
+                            double* phi, rte_solve_stats* stats, void* stream) {
+  auto* b = const_cast<rte_batch*>(cb);
+  if (!b || !sigma_t || !sigma_s || !G || !opts || !phi || !stats) return RTE_EINVAL;
+  const rte_solve_opts& o = *opts;
+  if (o.m < 1 || o.m > 500 || o.max_cycles < 1 || !(o.rtol > 0.0) ||
+      (o.sweep_dtype != RTE_F32 && o.sweep_dtype != RTE_F64) || o.precond < RTE_PC_NONE ||
+      o.precond > RTE_PC_MLP || o.window < 0 || o.dsa_inner_max < 1 || o.dsa_restart < 1 ||
+      o.dsa_restart > 500)
+    return RTE_EINVAL;
+  if ((o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && !rom) return RTE_EINVAL;
+  if (rom && !rte::rom_matches(rom, b)) return RTE_EINVAL;
+  if (o.precond == RTE_PC_MLP && (!mlp || !mu || mu_dim < 1)) return RTE_EINVAL;
+  rte::Fgmres* f = rte::fgmres_for(b, o.m);
+  if (!f) return RTE_ENOMEM;
+  rte::SolveCtx c{};
+  c.opts = opts;
+  c.sigma_t = sigma_t;
+  c.sigma_s = sigma_s;
+  c.G = G;
+  c.inflow = inflow;
+  c.rom = rom;
+  c.mlp = mlp;
+  c.mu = mu;
+  c.mu_dim = mu_dim;
+  return f->solve(c, phi, stats, reinterpret_cast<hipStream_t>(stream));
+}

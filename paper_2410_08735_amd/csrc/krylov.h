@@ -1,0 +1,70 @@
+// Batched FP64 Krylov building blocks (Arnoldi with modified Gram-Schmidt,
+// Givens least squares, solution update) over a family of per-instance
+// vectors packed one after another.
+#pragma once
+#include "rte_internal.h"
+
+namespace rte {
+
+constexpr int KCHUNK = 4096;   // elements per work group in reductions
+constexpr int KTHREADS = 256;
+
+// A family of per-instance vectors: instance b occupies [off[b], off[b]+len[b]).
+struct Space {
+  int n = 0;
+  std::vector<int64_t> off, len;
+  int64_t total = 0, max_len = 0;
+  int64_t* d_off = nullptr;
+  int64_t* d_len = nullptr;
+  int max_chunks() const { return (int)((max_len + KCHUNK - 1) / KCHUNK); }
+  int init(const std::vector<int64_t>& lens);
+  void release();
+};
+
+// Workspace of one batched (F)GMRES cycle of dimension m.
+struct Krylov {
+  Space sp;
+  int m = 0;
+  bool flexible = true;
+  double* V = nullptr;      // (m + 1) vectors of sp.total
+  double* Z = nullptr;      // m vectors (flexible only)
+  double* H = nullptr;      // [n][(m + 1) * m] Arnoldi coefficients, H[i * m + j]
+  double* R = nullptr;      // [n][(m + 1) * m] rotated copy (upper triangular)
+  double* cs = nullptr;     // [n][m]
+  double* sn = nullptr;     // [n][m]
+  double* g = nullptr;      // [n][m + 1]
+  double* y = nullptr;      // [n][m]
+  double* partA = nullptr;  // [n][max_chunks]
+  double* partB = nullptr;
+  double* scal = nullptr;   // [n][8]: 0 beta, 1 tol_abs, 2 est, 3 wnorm_pre, 4 tmp
+  int32_t* active = nullptr;  // [n] 1 = iterate in this cycle
+  int32_t* jdone = nullptr;   // [n] columns built in this cycle
+  int init(const std::vector<int64_t>& lens, int m, bool flexible);
+  void release();
+  double* v(int j) const { return V + (int64_t)j * sp.total; }
+  double* z(int j) const { return Z + (int64_t)j * sp.total; }
+};
+
+// out[b] = ||x_b||_2 (device, indexed scal-style with stride), masked
+int knorm(const Space& sp, const double* x, double* part, double* out, int out_stride,
+          const int32_t* active, hipStream_t s);
+// out[b] = <x_b, y_b>
+int kdot(const Space& sp, const double* x, const double* y, double* part, double* out,
+         int out_stride, const int32_t* active, hipStream_t s);
+// y = x / s[b*stride] (zero if the divisor is zero)
+int kscale(const Space& sp, const double* x, const double* sc, int stride, double* y,
+           const int32_t* active, hipStream_t s);
+// y = a*x + b*y (scalars)
+int kaxpby(const Space& sp, double a, const double* x, double bcoef, double* y,
+           const int32_t* active, hipStream_t s);
+int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hipStream_t s);
+// Arnoldi step j: w (= V[j+1] slot) orthogonalised against V[0..j] by MGS,
+// H[:, j] filled, w normalised, Givens rotation applied, est and active updated.
+int arnoldi_mgs(Krylov& K, int j, hipStream_t s);
+// y = R^{-1} g per instance (jdone columns); X += sum_i y_i * basis_i
+int kylov_solve_update(Krylov& K, const double* basis, double* X, hipStream_t s);
+// start a cycle: V[0] = r / ||r||, g = (beta, 0, ...), tol_abs = rtol * bnorm
+int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s);
+int fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
+
+}  // namespace rte

@@ -1,0 +1,374 @@
+// Batched FP64 Krylov kernels: reductions are two-level and deterministic
+// (per-work-group partial sums, then a fixed-order sum per instance), every
+// kernel skips instances whose mask entry is 0.
+#include <algorithm>
+#include <cmath>
+
+#include "krylov.h"
+
+namespace rte {
+
+int Space::init(const std::vector<int64_t>& lens) {
+  n = (int)lens.size();
+  len = lens;
+  off.resize(n);
+  total = 0;
+  max_len = 0;
+  for (int b = 0; b < n; ++b) {
+    off[b] = total;
+    total += lens[b];
+    max_len = std::max(max_len, lens[b]);
+  }
+  if (hipMalloc(&d_off, sizeof(int64_t) * n) != hipSuccess ||
+      hipMalloc(&d_len, sizeof(int64_t) * n) != hipSuccess)
+    return RTE_ENOMEM;
+  RTE_HIP(hipMemcpy(d_off, off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice));
+  RTE_HIP(hipMemcpy(d_len, len.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice));
+  return RTE_OK;
+}
+
+void Space::release() {
+  (void)hipFree(d_off);
+  (void)hipFree(d_len);
+  d_off = d_len = nullptr;
+}
+
+int Krylov::init(const std::vector<int64_t>& lens, int m_, bool flex) {
+  RTE_TRY(sp.init(lens));
+  m = m_;
+  flexible = flex;
+  const int n = sp.n;
+  const int mc = sp.max_chunks();
+  auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+  bool ok = al((void**)&V, sizeof(double) * (m + 1) * sp.total) &&
+            (!flex || al((void**)&Z, sizeof(double) * m * sp.total)) &&
+            al((void**)&H, sizeof(double) * n * (m + 1) * m) &&
+            al((void**)&R, sizeof(double) * n * (m + 1) * m) &&
+            al((void**)&cs, sizeof(double) * n * m) && al((void**)&sn, sizeof(double) * n * m) &&
+            al((void**)&g, sizeof(double) * n * (m + 1)) && al((void**)&y, sizeof(double) * n * m) &&
+            al((void**)&partA, sizeof(double) * n * mc) &&
+            al((void**)&partB, sizeof(double) * n * mc) &&
+            al((void**)&scal, sizeof(double) * n * 8) && al((void**)&active, sizeof(int32_t) * n) &&
+            al((void**)&jdone, sizeof(int32_t) * n);
+  if (!ok) return RTE_ENOMEM;
+  RTE_HIP(hipMemset(H, 0, sizeof(double) * n * (m + 1) * m));
+  RTE_HIP(hipMemset(scal, 0, sizeof(double) * n * 8));
+  return RTE_OK;
+}
+
+void Krylov::release() {
+  for (void* p : {(void*)V, (void*)Z, (void*)H, (void*)R, (void*)cs, (void*)sn, (void*)g, (void*)y,
+                  (void*)partA, (void*)partB, (void*)scal, (void*)active, (void*)jdone})
+    (void)hipFree(p);
+  V = Z = H = R = cs = sn = g = y = partA = partB = scal = nullptr;
+  active = jdone = nullptr;
+  sp.release();
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+__global__ void k_dot_part(const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                           const double* __restrict__ x, const double* __restrict__ y,
+                           double* __restrict__ part, int maxc, const int32_t* __restrict__ active) {
+  __shared__ double sh[KTHREADS / 64];
+  const int b = blockIdx.y, c = blockIdx.x;
+  if (active && !active[b]) return;
+  const int64_t n = len[b], base = off[b], start = (int64_t)c * KCHUNK;
+  if (start >= n) return;
+  const int64_t end = min(n, start + (int64_t)KCHUNK);
+  double acc = 0.0;
+  for (int64_t e = start + threadIdx.x; e < end; e += blockDim.x) {
+    const double xv = x[base + e];
+    acc += xv * (y ? y[base + e] : xv);
+  }
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part[(int64_t)b * maxc + c] = acc;
+}
+
+__global__ void k_finish(int n, const int64_t* __restrict__ len, const double* __restrict__ part,
+                         int maxc, double* __restrict__ out, int stride, int take_sqrt,
+                         const int32_t* __restrict__ active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || (active && !active[b])) return;
+  const int nc = (int)((len[b] + KCHUNK - 1) / KCHUNK);
+  double t = 0.0;
+  for (int c = 0; c < nc; ++c) t += part[(int64_t)b * maxc + c];
+  out[(int64_t)b * stride] = take_sqrt ? sqrt(t) : t;
+}
+
+__global__ void k_scale(const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                        const double* __restrict__ x, const double* __restrict__ sc, int stride,
+                        double* __restrict__ y, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int64_t n = len[b], base = off[b];
+  const double d = sc[(int64_t)b * stride];
+  const double f = d != 0.0 ? 1.0 / d : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[base + e] = x[base + e] * f;
+}
+
+__global__ void k_axpby(const int64_t* __restrict__ off, const int64_t* __restrict__ len, double a,
+                        const double* __restrict__ x, double bc, double* __restrict__ y,
+                        const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int64_t n = len[b], base = off[b];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[base + e] = a * x[base + e] + (bc == 0.0 ? 0.0 : bc * y[base + e]);
+}
+
+// One MGS projection: h = <w, v_i> (from the partial sums of the previous
+// pass), w -= h v_i, then partial sums of <w, v_{i+1}> (or <w, w> at the end).
+__global__ void k_mgs_step(const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                           double* __restrict__ w, const double* __restrict__ vi,
+                           const double* __restrict__ vnext, const double* __restrict__ part_in,
+                           double* __restrict__ part_out, int maxc, double* __restrict__ H, int m,
+                           int i, int j, const int32_t* __restrict__ active) {
+  __shared__ double sh[KTHREADS / 64];
+  __shared__ double hs;
+  const int b = blockIdx.y, c = blockIdx.x;
+  if (active && !active[b]) return;
+  const int64_t n = len[b], base = off[b], start = (int64_t)c * KCHUNK;
+  if (start >= n) return;
+  const int nc = (int)((n + KCHUNK - 1) / KCHUNK);
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < nc; ++k) t += part_in[(int64_t)b * maxc + k];
+    hs = t;
+    if (c == 0) H[(int64_t)b * (m + 1) * m + (int64_t)i * m + j] = t;
+  }
+  __syncthreads();
+  const double h = hs;
+  const int64_t end = min(n, start + (int64_t)KCHUNK);
+  double acc = 0.0;
+  for (int64_t e = start + threadIdx.x; e < end; e += blockDim.x) {
+    const double wv = w[base + e] - h * vi[base + e];
+    w[base + e] = wv;
+    acc += wv * (vnext ? vnext[base + e] : wv);
+  }
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part_out[(int64_t)b * maxc + c] = acc;
+}
+
+// H[j+1][j] = ||w|| from the final partials; scal[4] = ||w||.
+__global__ void k_arnoldi_tail(int n, const int64_t* __restrict__ len, const double* __restrict__ part,
+                               int maxc, double* __restrict__ H, int m, int j,
+                               double* __restrict__ scal, const int32_t* __restrict__ active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || !active[b]) return;
+  const int nc = (int)((len[b] + KCHUNK - 1) / KCHUNK);
+  double t = 0.0;
+  for (int c = 0; c < nc; ++c) t += part[(int64_t)b * maxc + c];
+  const double nw = sqrt(t);
+  H[(int64_t)b * (m + 1) * m + (int64_t)(j + 1) * m + j] = nw;
+  scal[b * 8 + 4] = nw;
+}
+
+// Givens update of column j; est = |g_{j+1}|; stop the instance when
+// est <= tol_abs or on a (lucky) breakdown H_{j+1,j} <= 1e-14 ||w_before||.
+__global__ void k_givens(int n, const double* __restrict__ H, double* __restrict__ R,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         int m, int j, double* __restrict__ scal, int32_t* __restrict__ active,
+                         int32_t* __restrict__ jdone) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || !active[b]) return;
+  const double* Hb = H + (int64_t)b * (m + 1) * m;
+  double* Rb = R + (int64_t)b * (m + 1) * m;
+  double* c = cs + (int64_t)b * m;
+  double* s = sn + (int64_t)b * m;
+  double* gb = g + (int64_t)b * (m + 1);
+  double colsq = 0.0;
+  for (int i = 0; i <= j + 1; ++i) {
+    Rb[i * m + j] = Hb[i * m + j];
+    colsq += Hb[i * m + j] * Hb[i * m + j];
+  }
+  for (int k = 0; k < j; ++k) {
+    const double a = Rb[k * m + j], bb = Rb[(k + 1) * m + j];
+    Rb[k * m + j] = c[k] * a + s[k] * bb;
+    Rb[(k + 1) * m + j] = -s[k] * a + c[k] * bb;
+  }
+  const double a = Rb[j * m + j], bb = Rb[(j + 1) * m + j];
+  const double rho = hypot(a, bb);
+  double cj = 1.0, sj = 0.0;
+  if (rho > 0.0) {
+    cj = a / rho;
+    sj = bb / rho;
+  }
+  c[j] = cj;
+  s[j] = sj;
+  Rb[j * m + j] = rho;
+  Rb[(j + 1) * m + j] = 0.0;
+  const double gj = gb[j];
+  gb[j] = cj * gj;
+  gb[j + 1] = -sj * gj;
+  const double est = fabs(gb[j + 1]);
+  scal[b * 8 + 2] = est;
+  jdone[b] = j + 1;
+  const bool breakdown = Hb[(j + 1) * m + j] <= 1e-14 * sqrt(colsq);
+  if (est <= scal[b * 8 + 1] || breakdown || rho == 0.0) active[b] = 0;
+}
+
+__global__ void k_backsolve(int n, const double* __restrict__ R, const double* __restrict__ g, int m,
+                            const int32_t* __restrict__ jdone, double* __restrict__ y,
+                            const int32_t* __restrict__ incycle) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || (incycle && !incycle[b])) return;
+  const int jd = jdone[b];
+  const double* Rb = R + (int64_t)b * (m + 1) * m;
+  const double* gb = g + (int64_t)b * (m + 1);
+  double* yb = y + (int64_t)b * m;
+  for (int i = jd - 1; i >= 0; --i) {
+    double t = gb[i];
+    for (int k = i + 1; k < jd; ++k) t -= Rb[i * m + k] * yb[k];
+    const double d = Rb[i * m + i];
+    yb[i] = d != 0.0 ? t / d : 0.0;
+  }
+}
+
+__global__ void k_update(const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                         int64_t total, const double* __restrict__ basis, const double* __restrict__ y,
+                         int m, const int32_t* __restrict__ jdone, double* __restrict__ X,
+                         const int32_t* __restrict__ incycle) {
+  const int b = blockIdx.y;
+  if (incycle && !incycle[b]) return;
+  const int jd = jdone[b];
+  if (jd == 0) return;
+  const int64_t n = len[b], base = off[b];
+  const double* yb = y + (int64_t)b * m;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = X[base + e];
+    for (int i = 0; i < jd; ++i) acc += yb[i] * basis[(int64_t)i * total + base + e];
+    X[base + e] = acc;
+  }
+}
+
+__global__ void k_start(int n, double* __restrict__ scal, double* __restrict__ g, int m,
+                        const double* __restrict__ tol_abs, int32_t* __restrict__ active,
+                        int32_t* __restrict__ jdone) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  jdone[b] = 0;
+  if (!active[b]) return;
+  const double beta = scal[b * 8 + 0];
+  scal[b * 8 + 1] = tol_abs[b];
+  scal[b * 8 + 2] = beta;
+  double* gb = g + (int64_t)b * (m + 1);
+  gb[0] = beta;
+  for (int i = 1; i <= m; ++i) gb[i] = 0.0;
+  if (beta <= tol_abs[b]) active[b] = 0;
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static dim3 vgrid(const Space& sp) {
+  return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((sp.max_len + 255) / 256, 512)), sp.n);
+}
+
+int fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int knorm(const Space& sp, const double* x, double* part, double* out, int stride,
+          const int32_t* active, hipStream_t s) {
+  const int mc = sp.max_chunks();
+  hipLaunchKernelGGL(k_dot_part, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, x,
+                     (const double*)nullptr, part, mc, active);
+  hipLaunchKernelGGL(k_finish, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, sp.d_len, part, mc, out,
+                     stride, 1, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int kdot(const Space& sp, const double* x, const double* y, double* part, double* out, int stride,
+         const int32_t* active, hipStream_t s) {
+  const int mc = sp.max_chunks();
+  hipLaunchKernelGGL(k_dot_part, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, x, y,
+                     part, mc, active);
+  hipLaunchKernelGGL(k_finish, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, sp.d_len, part, mc, out,
+                     stride, 0, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int kscale(const Space& sp, const double* x, const double* sc, int stride, double* y,
+           const int32_t* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, vgrid(sp), dim3(256), 0, s, sp.d_off, sp.d_len, x, sc, stride, y,
+                     active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int kaxpby(const Space& sp, double a, const double* x, double bc, double* y, const int32_t* active,
+           hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, vgrid(sp), dim3(256), 0, s, sp.d_off, sp.d_len, a, x, bc, y, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hipStream_t s) {
+  return kaxpby(sp, 1.0, x, 0.0, y, active, s);
+}
+
+int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s) {
+  const Space& sp = K.sp;
+  RTE_TRY(knorm(sp, r, K.partA, K.scal + 0, 8, K.active, s));
+  hipLaunchKernelGGL(k_start, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, K.scal, K.g, K.m, tol_abs,
+                     K.active, K.jdone);
+  RTE_HIP(hipGetLastError());
+  return kscale(sp, r, K.scal + 0, 8, K.v(0), K.active, s);
+}
+
+int arnoldi_mgs(Krylov& K, int j, hipStream_t s) {
+  const Space& sp = K.sp;
+  const int mc = sp.max_chunks();
+  double* w = K.v(j + 1);
+  hipLaunchKernelGGL(k_dot_part, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, w, K.v(0),
+                     K.partA, mc, K.active);
+  double* pin = K.partA;
+  double* pout = K.partB;
+  for (int i = 0; i <= j; ++i) {
+    const double* vn = (i < j) ? K.v(i + 1) : nullptr;
+    hipLaunchKernelGGL(k_mgs_step, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, w,
+                       K.v(i), vn, pin, pout, mc, K.H, K.m, i, j, K.active);
+    std::swap(pin, pout);
+  }
+  hipLaunchKernelGGL(k_arnoldi_tail, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, sp.d_len, pin, mc,
+                     K.H, K.m, j, K.scal, K.active);
+  RTE_TRY(kscale(sp, w, K.scal + 4, 8, w, K.active, s));
+  hipLaunchKernelGGL(k_givens, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, K.H, K.R, K.cs, K.sn,
+                     K.g, K.m, j, K.scal, K.active, K.jdone);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int kylov_solve_update(Krylov& K, const double* basis, double* X, hipStream_t s) {
+  const Space& sp = K.sp;
+  hipLaunchKernelGGL(k_backsolve, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, K.R, K.g, K.m,
+                     K.jdone, K.y, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(k_update, vgrid(sp), dim3(256), 0, s, sp.d_off, sp.d_len, sp.total, basis, K.y,
+                     K.m, K.jdone, X, (const int32_t*)nullptr);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+}  // namespace rte

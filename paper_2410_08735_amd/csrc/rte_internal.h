@@ -104,9 +104,17 @@ int make_plan(rte_batch* b, int prec, int G, int threads);
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
                  hipStream_t s, const int32_t* active = nullptr);
-// out = alpha * sum_partials + beta * x   (x nullable)
+// out = alpha * sum_partials + beta * x + gamma * y   (x, y nullable)
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
-                    hipStream_t s, const int32_t* active = nullptr);
+                    hipStream_t s, const int32_t* active = nullptr, const double* y = nullptr,
+                    double gamma = 0.0);
 int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s);
+int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s);
+int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v, double* z,
+              double inner_tol, int inner_max, int restart, const int32_t* active, int32_t* iters,
+              hipStream_t s);
+void dsa_forget(rte_batch* b);
+void fgmres_forget(rte_batch* b);
+void rom_scratch_forget(const rte_batch* b);
 
 }  // namespace rte

@@ -233,6 +233,7 @@ __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
                                        const InstPart* __restrict__ parts,
                                        const real* __restrict__ part, double alpha,
                                        const double* __restrict__ x, double beta,
+                                       const double* __restrict__ y, double gamma,
                                        double* __restrict__ out, const int32_t* __restrict__ active) {
   const int inst = blockIdx.y;
   if (active && !active[inst]) return;
@@ -246,6 +247,7 @@ __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
     for (int k = 0; k < pp.n; ++k) acc += (double)p[(int64_t)k * nd];
     double v = alpha * acc;
     if (x) v += beta * x[I.dof_off + d];
+    if (y) v += gamma * y[I.dof_off + d];
     out[I.dof_off + d] = v;
   }
 }
@@ -383,17 +385,19 @@ int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* si
 }
 
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
-                    hipStream_t s, const int32_t* active) {
+                    hipStream_t s, const int32_t* active, const double* y, double gamma) {
   const Plan& p = b->plan[prec];
   int64_t maxnd = 0;
   for (const auto& I : b->inst) maxnd = std::max<int64_t>(maxnd, (int64_t)I.nx * I.ny * I.nloc);
   dim3 grid((unsigned)std::min<int64_t>((maxnd + 255) / 256, 1024), b->n_inst);
   if (prec == 0)
     hipLaunchKernelGGL(reduce_partials_kernel<double>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
-                       reinterpret_cast<const double*>(b->d_part), alpha, x, beta, out, active);
+                       reinterpret_cast<const double*>(b->d_part), alpha, x, beta, y, gamma, out,
+                       active);
   else
     hipLaunchKernelGGL(reduce_partials_kernel<float>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
-                       reinterpret_cast<const float*>(b->d_part), alpha, x, beta, out, active);
+                       reinterpret_cast<const float*>(b->d_part), alpha, x, beta, y, gamma, out,
+                       active);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }

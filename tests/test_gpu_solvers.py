@@ -1,0 +1,207 @@
+"""GPU parity of DSA, FGMRES, ROMSAD and the greedy builder against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dsa as odsa
+from oracle import fgmres as ofg
+from oracle import rom as orom
+from oracle import transport as tr
+from synth import cfg1, tiny_1d, tiny_2d
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def _family(n=5, nx=5, ny=4, quad=("cl", 8, 4, True), seed=0):
+    specs = []
+    for k in range(n):
+        s = dict(tiny_2d(seed=seed, nx=nx, ny=ny, quad=quad))
+        s["sigma_s"] = s["sigma_s"] * (1 + 0.4 * k)
+        s["sigma_t"] = s["sigma_s"] + 0.3 + 0.05 * k
+        specs.append(s)
+    return specs
+
+
+# ------------------------------------------------------------------ DSA
+@pytest.mark.gpu
+def test_dsa_apply_parity():
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=1, nx=6, ny=5, quad=("cl", 8, 4, True), n_regions=3),
+             tiny_2d(seed=2, nx=4, ny=7, quad=("cl", 3, 2, False), n_regions=2),
+             tiny_2d(seed=3, nx=9, ny=9, quad=("cl", 16, 4, True), n_regions=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(4)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z, iters = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=1e-14, inner_max=3000, restart=60)
+    for k, spec in enumerate(specs):
+        ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
+        assert rel(B.unpack(z)[k], ref) <= 1e-11, (k, rel(B.unpack(z)[k], ref), iters)
+
+
+@pytest.mark.gpu
+def test_dsa_apply_parity_1d():
+    import paper_2410_08735_amd as rt
+    specs = [tiny_1d(seed=1, nx=12, n_ord=8), tiny_1d(seed=2, nx=7, n_ord=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(5)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=1e-14, inner_max=2000, restart=60)
+    for k, spec in enumerate(specs):
+        ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
+        assert rel(B.unpack(z)[k], ref) <= 1e-11
+
+
+# ------------------------------------------------------------------ FGMRES
+def _oracle_solve(spec, precond="dsa", rtol=1e-13, m=60, U=None, window=2):
+    P = tr.Problem(spec)
+    b = tr.b_tilde(P)
+    if precond == "none":
+        pc = lambda j, v: v
+    elif precond == "dsa":
+        D = odsa.DSA(P)
+        pc = lambda j, v: D.apply(v)
+    else:
+        pc = orom.Romsad(P, U, odsa.DSA(P), window)
+    return ofg.fgmres(lambda x: tr.A_tilde_apply(P, x), b, pc, m=m, rtol=rtol)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precond", ["none", "dsa"])
+def test_fgmres_fp64_parity(precond):
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=1, nx=7, ny=6, quad=("cl", 8, 4, True), n_regions=3, inflow=0.2),
+             tiny_2d(seed=2, nx=5, ny=5, quad=("cl", 12, 2, True), n_regions=2),
+             tiny_2d(seed=3, nx=4, ny=6, quad=("cl", 3, 2, False), n_regions=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    opts = rt.SolveOptions(precond=precond, m=60, max_cycles=5, sweep_dtype="f64", rtol=1e-13,
+                           dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    phi, stats, _ = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), opts)
+    for k, spec in enumerate(specs):
+        ref = _oracle_solve(spec, precond)
+        assert stats[k]["status"] == 0 and stats[k]["true_relres"] <= 1e-13
+        assert rel(B.unpack(phi)[k], ref.x) <= 1e-11
+        assert abs(stats[k]["iterations"] - ref.iterations) <= 1, (stats[k], ref.iterations)
+    # CL(3,2): FC-DSA is exact, one iteration
+    if precond == "dsa":
+        assert stats[2]["iterations"] == 1
+
+
+@pytest.mark.gpu
+def test_fgmres_fp32_sweeps_refined_to_1e8():
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=s, nx=12, ny=10, quad=("cl", 16, 4, True), n_regions=2) for s in range(4)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    opts = rt.SolveOptions(precond="dsa", m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8,
+                           dsa_inner_max=200, dsa_restart=30, dsa_inner_tol=1e-10)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), opts)
+    assert ret == 0
+    for k, spec in enumerate(specs):
+        assert stats[k]["true_relres"] <= 1e-8
+        assert stats[k]["sweeps_f32"] >= 1 and stats[k]["sweeps_f64"] >= 2
+        ref = _oracle_solve(spec, "dsa", rtol=1e-13)
+        assert rel(B.unpack(phi)[k], ref.x) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_cfg1_gmres30_dsa():
+    """Slab, 128 P1 cells, S16, GMRES(30)-DSA to 1e-8 (FP64)."""
+    import paper_2410_08735_amd as rt
+    spec = cfg1()
+    B = rt.Batch([spec])
+    st, ss = B.sigma()
+    opts = rt.SolveOptions(precond="dsa", m=30, max_cycles=10, sweep_dtype="f64", rtol=1e-8,
+                           dsa_inner_max=500, dsa_restart=60, dsa_inner_tol=1e-13)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts)
+    assert ret == 0 and stats[0]["true_relres"] <= 1e-8
+    ref = _oracle_solve(spec, "dsa", rtol=1e-8, m=30)
+    assert abs(stats[0]["iterations"] - ref.iterations) <= 1
+    tight = _oracle_solve(spec, "dsa", rtol=1e-13, m=30)
+    assert rel(B.unpack(phi)[0], tight.x) <= 1e-6
+
+
+# ------------------------------------------------------------------ ROMSAD
+@pytest.fixture(scope="module")
+def oracle_rom():
+    specs = _family(5)
+    U, rep = orom.greedy(specs, window=2, eps_rom=0.0, n_giter=3, rtol_hf=1e-11)
+    return specs, U, rep
+
+
+@pytest.mark.gpu
+def test_romsad_apply_and_affine_terms_parity(oracle_rom):
+    import torch
+
+    import paper_2410_08735_amd as rt
+    specs, U, _ = oracle_rom
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    assert rom.rank == U.shape[0]
+    P0 = tr.Problem(specs[0])
+    ex = rom.export(P0.nord, P0.ndof, 2)
+    AD, G, S = orom.affine_terms(P0, U, 2)
+    assert rel(ex["AD"], AD) <= 1e-12 and rel(ex["G"], G) <= 1e-12 and rel(ex["S"], S) <= 1e-12
+    assert rel(ex["W1"], orom.W1(U)) <= 1e-14 and rel(ex["Ww"], orom.Ww(P0, U)) <= 1e-14
+    rng = np.random.default_rng(3)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z = B.unpack(rt.romsad_apply(rom, B, st, ss, B.pack(v)))
+    for k, spec in enumerate(specs):
+        P = tr.Problem(spec)
+        ref = v[k] + orom.rom_correction(P, U, v[k])
+        assert rel(z[k], ref) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_fgmres_romsad_parity(oracle_rom):
+    import torch
+
+    import paper_2410_08735_amd as rt
+    specs, U, rep = oracle_rom
+    test = _family(6, seed=0)[5:] + [dict(_family(5)[1], sigma_s=_family(5)[1]["sigma_s"] * 1.1,
+                                          sigma_t=_family(5)[1]["sigma_t"] * 1.1)]
+    B = rt.Batch(test + [specs[rep.sampled[1]]])
+    st, ss = B.sigma()
+    rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    opts = rt.SolveOptions(precond="romsad", m=40, max_cycles=5, sweep_dtype="f64", rtol=1e-12,
+                           window=2, dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts, rom=rom)
+    assert ret == 0
+    for k, spec in enumerate(B.problems):
+        ref = _oracle_solve(spec, "romsad", rtol=1e-12, U=U)
+        assert rel(B.unpack(phi)[k], ref.x) <= 1e-10
+        assert abs(stats[k]["iterations"] - ref.iterations) <= 1
+        assert stats[k]["pc_rom"] >= 1
+    assert stats[-1]["iterations"] == 1   # sampled parameter: the ROM is exact
+
+
+@pytest.mark.gpu
+def test_greedy_matches_oracle(oracle_rom, tmp_path):
+    import paper_2410_08735_amd as rt
+    specs, U, rep = oracle_rom
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rom, grep = rt.romsad_build_greedy(B, st, ss, B.source(), None, window=2, mu1_index=0,
+                                       eps_rom=0.0, n_giter=3, eps_qr=1e-13, hf_rtol=1e-11)
+    assert grep["sampled"] == rep.sampled, (grep, rep.sampled)
+    assert grep["rank"] == U.shape[0]
+    # same span: M_ROM^{-1} v agrees (invariant under U -> U Q)
+    rng = np.random.default_rng(8)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z = B.unpack(rt.romsad_apply(rom, B, st, ss, B.pack(v)))
+    for k, spec in enumerate(specs):
+        ref = v[k] + orom.rom_correction(tr.Problem(spec), U, v[k])
+        assert rel(z[k], ref) <= 1e-7, rel(z[k], ref)
+    # save / load round trip
+    path = str(tmp_path / "rom.bin")
+    rom.save(path)
+    rom2 = rt.Rom.load(path)
+    z2 = B.unpack(rt.romsad_apply(rom2, B, st, ss, B.pack(v)))
+    for k in range(len(specs)):
+        assert np.array_equal(z[k], z2[k])
