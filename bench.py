@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the FGMRES-ROMSAD hot path on one MI355X.
+
+Workload (the parametric checkerboard family at 96x96 Q1 cells, 128
+ordinates): a greedy ROM (r <= 32) is built offline from 64 training
+parameters, then one step = a batched FGMRES-ROMSAD solve of all 256 test
+parameters to FP64 true relative residual 1e-8, with FP32 sweeps and FP64
+Krylov.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FGMRES solves/s to rel-res 1e-8 (MLP vs ROMSAD vs plain); sweep GDoF/s"
+# FP32 sweep arithmetic per cell and ordinate (closed-form 4x4 upwind solve,
+# inflow terms, outgoing traces, weighted quadrature sum, Sigma_s scaling),
+# counting an FMA as two operations.
+SWEEP_FLOPS_PER_CELL_ORD = 118.0
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak, FLOP/s
+PEAK_FP64_VECTOR = 78.6e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _oracle_solve_one(mu):
+    """CPU baseline worker: one full oracle FGMRES-DSA solve (FP64)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import dsa, fgmres, transport
+    from synth import cfg3_problem
+    P = transport.Problem(cfg3_problem(mu, n=96))
+    b = transport.b_tilde(P)
+    D = dsa.DSA(P)
+    r = fgmres.fgmres(lambda x: transport.A_tilde_apply(P, x), b, lambda j, v: D.apply(v),
+                      m=30, rtol=1e-8)
+    return r.iterations
+
+
+def cpu_baseline(mus, procs):
+    t = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        its = pool.map(_oracle_solve_one, list(mus[:procs]))
+    wall = time.perf_counter() - t
+    return dict(value=procs / wall, unit="solves/s", cores=procs, kind="oracle",
+                sample=f"{procs} test parameters of the same workload, each one full oracle "
+                       f"FGMRES-DSA solve (FP64, sparse-direct sweeps and DSA) to rtol 1e-8 in its "
+                       f"own process ({procs} processes, 1 thread each); wall {wall:.1f} s; "
+                       f"iterations {its}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-test", type=int, default=256)
+    ap.add_argument("--n-train", type=int, default=64)
+    ap.add_argument("--grid", type=int, default=96)
+    ap.add_argument("--n-giter", type=int, default=16)
+    ap.add_argument("--dsa-inner", type=int, default=1, help="V-cycles per DSA application")
+    ap.add_argument("--dsa-restart", type=int, default=0, help="0 = stationary V-cycles")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
+              "part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2410_08735_amd as rt
+    from synth import cfg2, cfg3_problem, cfg3_train_test
+
+    torch.cuda.set_device(0)
+    tr_mu, te_mu = cfg3_train_test(n_train=args.n_train, n_test=args.n_test)
+    n = args.grid
+
+    # ---------------- offline: greedy ROM on the training parameters
+    log(f"building training batch ({len(tr_mu)} x {n}^2 x 128)")
+    Btr = rt.Batch([cfg3_problem(m, n=n) for m in tr_mu])
+    st_tr, ss_tr = Btr.sigma()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rom, grep = rt.romsad_build_greedy(Btr, st_tr, ss_tr, Btr.source(), None, window=2, mu1_index=0,
+                                       eps_rom=1e-9, n_giter=args.n_giter, eps_qr=1e-13,
+                                       hf_rtol=1e-11)
+    torch.cuda.synchronize()
+    offline_s = time.perf_counter() - t
+    log(f"greedy: rank {grep['rank']}, sampled {len(grep['sampled'])}, {offline_s:.1f} s, "
+        f"steps {[round(x, 2) for x in grep['seconds_step']]}")
+    del Btr, st_tr, ss_tr
+
+    # ---------------- test batch resident in HBM
+    B = rt.Batch([cfg3_problem(m, n=n) for m in te_mu])
+    st, ss = B.sigma()
+    G = B.source()
+    common = dict(m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8, window=2,
+                  dsa_inner_max=args.dsa_inner, dsa_restart=args.dsa_restart, dsa_inner_tol=1e-6)
+    opts = rt.SolveOptions(precond="romsad", **common)
+    for _ in range(args.warmup):
+        rt.fgmres_solve(B, st, ss, G, None, opts, rom=rom)
+    torch.cuda.synchronize()
+
+    # ---------------- timed region
+    rt.prof_enable(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ok = 0
+    all_stats = []
+    for _ in range(args.steps):
+        phi, stats, ret = rt.fgmres_solve(B, st, ss, G, None, opts, rom=rom)
+        ok += sum(1 for s in stats if s["true_relres"] <= 1e-8)
+        all_stats = stats
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    launches, sweep_ms, units = rt.prof_read("sweep_f32")
+    rt.prof_enable(False)
+    value = ok / dt
+    avg_launch_ms = sweep_ms / max(launches, 1)
+    achieved = units * SWEEP_FLOPS_PER_CELL_ORD / (sweep_ms * 1e-3) if sweep_ms > 0 else 0.0
+    its = np.array([s["iterations"] for s in all_stats])
+    sw32 = np.array([s["sweeps_f32"] for s in all_stats])
+    sw64 = np.array([s["sweeps_f64"] for s in all_stats])
+    rr = np.array([s["true_relres"] for s in all_stats])
+    log(f"ROMSAD: {value:.2f} solves/s, {dt / args.steps * 1e3:.1f} ms/step, iterations mean "
+        f"{its.mean():.2f} max {its.max()}, max relres {rr.max():.2e}; sweep launches {launches}, "
+        f"avg {avg_launch_ms:.3f} ms, {achieved / 1e12:.2f} TFLOP/s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 sweeps / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": f"checkerboard RTE family, {n}x{n} Q1 cells, CL(16,16) folded "
+                               f"(128 ordinates), {len(te_mu)} test parameters batched, "
+                               f"FGMRES-ROMSAD (greedy ROM r={grep['rank']} from {len(tr_mu)} "
+                               f"training parameters, window 2), FP32 sweeps, FP64 Arnoldi, "
+                               f"rtol 1e-8",
+                   "global_batch": len(te_mu), "precond": "romsad"},
+        "roofline": {"bound": "alu", "kernel": "sweep2d_kernel<float>", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "launches": launches, "avg_launch_ms": avg_launch_ms,
+                     "flops_per_cell_ordinate": SWEEP_FLOPS_PER_CELL_ORD},
+        "romsad": {"iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+                   "sweeps_f32_mean": float(sw32.mean()), "sweeps_f64_mean": float(sw64.mean()),
+                   "max_true_relres": float(rr.max()), "converged": int((rr <= 1e-8).sum())},
+        "offline": {"greedy_s": offline_s, "rank": grep["rank"], "sampled": len(grep["sampled"]),
+                    "seconds_step": grep["seconds_step"]},
+    }
+
+    if not args.no_extras:
+        # plain GMRES-DSA on the same batch and GPU
+        pl = rt.SolveOptions(precond="dsa", **common)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, stats, _ = rt.fgmres_solve(B, st, ss, G, None, pl)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t
+        okp = sum(1 for s in stats if s["true_relres"] <= 1e-8)
+        itp = np.array([s["iterations"] for s in stats])
+        out["plain_dsa"] = {"value": okp / dtp, "unit": "solves/s", "iterations_mean": float(itp.mean()),
+                            "ms_per_step": dtp * 1e3}
+        log(f"plain GMRES-DSA: {okp / dtp:.2f} solves/s, iterations mean {itp.mean():.2f}")
+        # sweep throughput: batched (this workload) and single instance (64^2, 128 ordinates)
+        gd = {}
+        for name, batch, sig in (("batch256_96sq", B, st),):
+            q = G
+            for dt_name in ("f32", "f64"):
+                rt.sweep(batch, sig, q, dtype=dt_name)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                reps = 5
+                for _ in range(reps):
+                    rt.sweep(batch, sig, q, dtype=dt_name)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t) / reps
+                dof = sum(nd * no for nd, no in zip(batch.ndofs, batch.n_ords))
+                gd[f"{name}_{dt_name}"] = dof / el / 1e9
+        B2 = rt.Batch([cfg2()])
+        st2, _ = B2.sigma()
+        q2 = B2.source()
+        for dt_name in ("f32", "f64"):
+            rt.sweep(B2, st2, q2, dtype=dt_name)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(20):
+                rt.sweep(B2, st2, q2, dtype=dt_name)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t) / 20
+            gd[f"single64sq_{dt_name}"] = B2.ndofs[0] * B2.n_ords[0] / el / 1e9
+        out["sweep_gdof_s"] = gd
+        log(f"sweep GDoF/s: {gd}")
+
+    if not args.no_cpu_baseline:
+        procs = max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"CPU baseline: oracle on {procs} processes")
+        out["cpu_baseline"] = cpu_baseline(te_mu, procs)
+        log(f"CPU baseline: {out['cpu_baseline']['value']:.4f} solves/s")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,7 +198,9 @@ int fgmres_solve(const rte_batch* b, const double* sigma_t, const double* sigma_
  * psi-storing sweeps; 2(c) MGS with truncation (App. B, eps_qr) and the
  * reduced operators; step 3 the residual indicator R_mu on every unsampled
  * instance and its argmax (ties: lowest index), until max R_mu < eps_rom or
- * n_giter sampled parameters.  report (host, nullable).                      */
+ * n_giter sampled parameters.  hf_dsa_tol selects the DSA of the 2(a) solves:
+ * 0 = one multigrid V-cycle per application, > 0 = V-cycle-preconditioned
+ * GMRES to that relative tolerance.  report (host, nullable).               */
 typedef struct {
   int32_t n_sampled;
   int32_t sampled[256];      /* training indices in sampling order            */
@@ -211,7 +213,8 @@ typedef struct {
 int romsad_build_greedy(const rte_batch* train, const double* sigma_t, const double* sigma_s,
                         const double* G, const double* inflow, int window, int mu1_index,
                         double eps_rom, int n_giter, double eps_qr, double hf_rtol,
-                        rte_rom** out, rte_greedy_report* report, void* stream);
+                        double hf_dsa_tol, rte_rom** out, rte_greedy_report* report,
+                        void* stream);
 
 /* rte_rom_from_basis: a ROM from a given orthonormal basis U (device
  * [r][n_ord][ndof] of instance 0 of `b`); computes W_1, W_w and the affine
@@ -234,6 +237,17 @@ int rte_rom_export(const rte_rom* rom, double* U, double* W1, double* Ww, double
 int rte_rom_save(const rte_rom* rom, const char* path);
 int rte_rom_load(const char* path, rte_rom** out);
 void rte_rom_destroy(rte_rom* rom);
+
+/* ---------------------------------------------------------------- profiling
+ * HIP-event timing of the library's hot kernels for benchmarking.
+ * rte_prof_enable(1) starts recording (and clears earlier records); every
+ * launch of a profiled kernel is bracketed by two events on its stream.
+ * rte_prof_read synchronises on the recorded events and returns, for one
+ * slot, the number of launches, their summed duration in milliseconds and
+ * the summed work units (sweeps: cell-ordinates processed).
+ * Slots: 0 FP64 sweep, 1 FP32 sweep, 2 DSA operator, 3 Arnoldi MGS, 4 ROM.  */
+int rte_prof_enable(int on);
+int rte_prof_read(int slot, int64_t* launches, double* total_ms, double* total_units);
 
 #ifdef __cplusplus
 }

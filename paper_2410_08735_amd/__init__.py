@@ -257,11 +257,11 @@ class Rom:
 
 
 def romsad_build_greedy(batch, sigma_t, sigma_s, G, inflow=None, window=2, mu1_index=0, eps_rom=1e-9,
-                        n_giter=16, eps_qr=1e-13, hf_rtol=1e-11):
+                        n_giter=16, eps_qr=1e-13, hf_rtol=1e-11, hf_dsa_tol=0.0):
     h = C.c_void_p()
     rep = L.GreedyReport()
     check(L.lib().romsad_build_greedy(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow),
-                                      window, mu1_index, eps_rom, n_giter, eps_qr, hf_rtol,
+                                      window, mu1_index, eps_rom, n_giter, eps_qr, hf_rtol, hf_dsa_tol,
                                       C.byref(h), C.byref(rep), _stream()), "romsad_build_greedy")
     report = dict(sampled=list(rep.sampled[:rep.n_sampled]),
                   max_residual=list(rep.max_residual[:max(rep.n_sampled - 1, 0) + 1]),
@@ -274,3 +274,18 @@ def romsad_apply(rom, batch, sigma_t, sigma_s, v):
     st = L.lib().romsad_apply(rom.h, batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(v), _ptr(z), _stream())
     check(st, "romsad_apply")
     return z
+
+
+def prof_enable(on=True):
+    check(L.lib().rte_prof_enable(1 if on else 0), "rte_prof_enable")
+
+
+PROF_SLOTS = {"sweep_f64": 0, "sweep_f32": 1, "dsa_op": 2, "mgs": 3, "rom": 4}
+
+
+def prof_read(slot):
+    """(launches, total_ms, total_units) recorded for a profiler slot."""
+    n, ms, u = L.i64(), L.dbl(), L.dbl()
+    s = PROF_SLOTS[slot] if isinstance(slot, str) else slot
+    check(L.lib().rte_prof_read(s, C.byref(n), C.byref(ms), C.byref(u)), "rte_prof_read")
+    return n.value, ms.value, u.value

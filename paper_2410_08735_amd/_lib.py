@@ -68,7 +68,7 @@ SIGNATURES = {
     "fgmres_solve": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, C.c_int, vp,
                                C.POINTER(SolveStats), vp]),
     "romsad_build_greedy": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, C.c_int, dbl, C.c_int, dbl, dbl,
-                                      C.POINTER(vp), C.POINTER(GreedyReport), vp]),
+                                      dbl, C.POINTER(vp), C.POINTER(GreedyReport), vp]),
     "rte_rom_from_basis": (C.c_int, [vp, vp, C.c_int, C.POINTER(vp), vp]),
     "romsad_apply": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "rte_rom_rank": (C.c_int, [vp]),
@@ -76,6 +76,8 @@ SIGNATURES = {
     "rte_rom_save": (C.c_int, [vp, C.c_char_p]),
     "rte_rom_load": (C.c_int, [C.c_char_p, C.POINTER(vp)]),
     "rte_rom_destroy": (None, [vp]),
+    "rte_prof_enable": (C.c_int, [C.c_int]),
+    "rte_prof_read": (C.c_int, [C.c_int, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
 }
 
 _lib = None

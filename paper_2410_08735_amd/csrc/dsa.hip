@@ -23,10 +23,14 @@
 // cell; boundary cells simply lack the neighbour couplings.  X-Y operators are
 // tensor products with the identity along the other axis.
 //
-// The system is solved by restarted GMRES preconditioned on the right with
-// the exact inverse of each cell's diagonal block (block Jacobi); the
-// diagonal block depends only on the cell's region, so its inverse is formed
-// once per (instance, region).
+// The system is solved with geometric multigrid: V-cycles over grids coarsened
+// by 2 x 2 cell agglomeration, the same moment system rediscretised on every
+// level with cell-averaged cross sections, red-black block Gauss-Seidel
+// smoothing with exact inverses of the per-cell diagonal blocks, and the
+// natural injection of the coarse degree-1 space into the fine one as
+// prolongation (its transpose restricts).  A DSA application is either a fixed
+// number of V-cycles (a linear preconditioner, the production setting) or
+// restarted GMRES preconditioned by one V-cycle, run to a tolerance.
 #include <algorithm>
 #include <cmath>
 
@@ -206,7 +210,7 @@ __global__ void k_dsa_blockinv(int n_inst, int max_regions, const InstDev* __res
       for (int j = 0; j < 2 * nu; ++j) A[r][j] -= x * A[col][j];
     }
   }
-  double* o = inv + ((int64_t)b * max_regions + rg) * DMAX * DMAX;
+  double* o = inv + ((int64_t)b * max_regions + rg) * nu * nu;  // same stride the stencil reads
   for (int i = 0; i < nu; ++i)
     for (int j = 0; j < nu; ++j) o[i * nu + j] = A[i][nu + j];
 }
@@ -338,80 +342,465 @@ __global__ void k_dsa_out(const InstDev* __restrict__ insts, const DsaStencil* _
   }
 }
 
+// ------------------------------------------------------------------ multigrid
+struct LvlInst {
+  int32_t nx, ny, dim, nloc;
+  double hx, hy;
+  int64_t cell_off;   // first cell of this instance in the level's cell arrays
+};
+
+// Level-0 per-cell cross sections from the region tables.
+__global__ void k_mg_sigma0(const InstDev* __restrict__ insts, const LvlInst* __restrict__ li,
+                            const int32_t* __restrict__ region, const double* __restrict__ sigma_t,
+                            const double* __restrict__ sigma_s, int max_regions,
+                            double* __restrict__ st, double* __restrict__ ss) {
+  const int b = blockIdx.y;
+  const InstDev I = insts[b];
+  const LvlInst L = li[b];
+  const int nc = L.nx * L.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    const int rg = region[I.region_off + c];
+    st[L.cell_off + c] = sigma_t[(int64_t)b * max_regions + rg];
+    ss[L.cell_off + c] = sigma_s[(int64_t)b * max_regions + rg];
+  }
+}
+
+// Coarse cross sections: average over the 2 x 2 (slab: 2) children.
+__global__ void k_mg_sigma_coarsen(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
+                                   const double* __restrict__ stf, const double* __restrict__ ssf,
+                                   double* __restrict__ stc, double* __restrict__ ssc) {
+  const int b = blockIdx.y;
+  const LvlInst F = lf[b], Cc = lc[b];
+  const int nc = Cc.nx * Cc.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    const int I = c % Cc.nx, K = c / Cc.nx;
+    double t = 0.0, u = 0.0;
+    int cnt = 0;
+    for (int dk = 0; dk < (F.dim == 2 ? 2 : 1); ++dk)
+      for (int di = 0; di < 2; ++di) {
+        const int f = (F.dim == 2 ? (2 * K + dk) * F.nx : 0) + 2 * I + di;
+        t += stf[F.cell_off + f];
+        u += ssf[F.cell_off + f];
+        ++cnt;
+      }
+    stc[Cc.cell_off + c] = t / cnt;
+    ssc[Cc.cell_off + c] = u / cnt;
+  }
+}
+
+template <int NU>
+__device__ void invert_block(const double* M, double* out) {
+  double A[NU][2 * NU];
+  for (int i = 0; i < NU; ++i)
+    for (int j = 0; j < NU; ++j) {
+      A[i][j] = M[i * NU + j];
+      A[i][NU + j] = (i == j) ? 1.0 : 0.0;
+    }
+  for (int col = 0; col < NU; ++col) {
+    int piv = col;
+    double best = fabs(A[col][col]);
+    for (int r = col + 1; r < NU; ++r)
+      if (fabs(A[r][col]) > best) {
+        best = fabs(A[r][col]);
+        piv = r;
+      }
+    if (piv != col)
+      for (int j = 0; j < 2 * NU; ++j) {
+        const double tmp = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = tmp;
+      }
+    const double d = A[col][col];
+    const double f = d != 0.0 ? 1.0 / d : 0.0;
+    for (int j = 0; j < 2 * NU; ++j) A[col][j] *= f;
+    for (int r = 0; r < NU; ++r) {
+      if (r == col) continue;
+      const double x = A[r][col];
+      if (x == 0.0) continue;
+      for (int j = 0; j < 2 * NU; ++j) A[r][j] -= x * A[col][j];
+    }
+  }
+  for (int i = 0; i < NU; ++i)
+    for (int j = 0; j < NU; ++j) out[i * NU + j] = A[i][NU + j];
+}
+
+// Per-cell inverse of the diagonal block (coarse levels).
+template <int NU>
+__global__ void k_mg_inv_cells(const LvlInst* __restrict__ li, const DsaStencil* __restrict__ st_,
+                               const double* __restrict__ st, const double* __restrict__ ss,
+                               double* __restrict__ inv, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const LvlInst L = li[b];
+  const DsaStencil& S = st_[b];
+  const int nc = L.nx * L.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    const double t = st[L.cell_off + c], u = ss[L.cell_off + c];
+    double M[NU * NU];
+    for (int q = 0; q < NU * NU; ++q) M[q] = S.blk[0][q] + t * S.St[q] + u * S.Ss[q];
+    invert_block<NU>(M, inv + (L.cell_off + c) * NU * NU);
+  }
+}
+
+__device__ __forceinline__ int lvl_inv_index(int per_cell, int64_t cell_global, int b, int max_regions,
+                                             int rg) {
+  return per_cell ? (int)cell_global : b * max_regions + rg;
+}
+
+// mode 0: y = K x; mode 1: y = b - K x (residual);
+// mode 2 (color c): x_c += inv_c (b - K x)_c for cells with (i + k) % 2 == c.
+template <int NU>
+__global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li,
+                             const DsaStencil* __restrict__ st_, const double* __restrict__ st,
+                             const double* __restrict__ ss, const double* __restrict__ inv,
+                             int per_cell_inv, const int32_t* __restrict__ region0,
+                             const InstDev* __restrict__ insts, int max_regions,
+                             const double* __restrict__ bvec, double* __restrict__ x,
+                             double* __restrict__ y, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const LvlInst L = li[b];
+  __shared__ double blk[7 * NU * NU];
+  const DsaStencil& S = st_[b];
+  for (int q = threadIdx.x; q < NU * NU; q += blockDim.x) {
+#pragma unroll
+    for (int z = 0; z < 5; ++z) blk[z * NU * NU + q] = S.blk[z][q];
+    blk[5 * NU * NU + q] = S.St[q];
+    blk[6 * NU * NU + q] = S.Ss[q];
+  }
+  __syncthreads();
+  const int nc = L.nx * L.ny;
+  const int64_t vo = L.cell_off * NU;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += gridDim.x * blockDim.x) {
+    const int i = cell % L.nx, k = cell / L.nx;
+    if (mode == 2 && ((i + k) & 1) != color) continue;
+    const double t = st[L.cell_off + cell], u = ss[L.cell_off + cell];
+    double acc[NU], xc[NU];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) xc[r] = x[vo + (int64_t)cell * NU + r];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int c = 0; c < NU; ++c)
+        a += (blk[r * NU + c] + t * blk[5 * NU * NU + r * NU + c] + u * blk[6 * NU * NU + r * NU + c]) * xc[c];
+      acc[r] = a;
+    }
+    const int nb[4] = {i > 0 ? cell - 1 : -1, i < L.nx - 1 ? cell + 1 : -1,
+                       k > 0 ? cell - L.nx : -1, k < L.ny - 1 ? cell + L.nx : -1};
+#pragma unroll
+    for (int z = 0; z < 4; ++z) {
+      if (nb[z] < 0) continue;
+      double xn[NU];
+#pragma unroll
+      for (int c = 0; c < NU; ++c) xn[c] = x[vo + (int64_t)nb[z] * NU + c];
+      const double* B = blk + (z + 1) * NU * NU;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) a += B[r * NU + c] * xn[c];
+        acc[r] += a;
+      }
+    }
+    if (mode == 0) {
+#pragma unroll
+      for (int r = 0; r < NU; ++r) y[vo + (int64_t)cell * NU + r] = acc[r];
+    } else if (mode == 1) {
+#pragma unroll
+      for (int r = 0; r < NU; ++r)
+        y[vo + (int64_t)cell * NU + r] = bvec[vo + (int64_t)cell * NU + r] - acc[r];
+    } else {
+      const int rg = per_cell_inv ? 0 : region0[insts[b].region_off + cell];
+      const double* M = inv + (int64_t)lvl_inv_index(per_cell_inv, L.cell_off + cell, b, max_regions, rg) * NU * NU;
+      double res[NU];
+#pragma unroll
+      for (int r = 0; r < NU; ++r) res[r] = bvec[vo + (int64_t)cell * NU + r] - acc[r];
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < NU; ++c) a += M[r * NU + c] * res[c];
+        x[vo + (int64_t)cell * NU + r] = xc[r] + a;
+      }
+    }
+  }
+}
+
+// Degree-1 Legendre injection of a coarse cell's modes into child `side`
+// (0 = low half, 1 = high half), [child mode][coarse mode].
+__device__ __forceinline__ double inj1d(int side, int p, int P) {
+  const double s2 = 1.4142135623730950488, r3 = 1.7320508075688772935;
+  if (p == 0) return P == 0 ? 1.0 / s2 : (side ? r3 / (2.0 * s2) : -r3 / (2.0 * s2));
+  return P == 0 ? 0.0 : 1.0 / (2.0 * s2);
+}
+
+// mode 0: restrict  bc[C] = sum_children P_f^T rf[f]
+// mode 1: prolong   xf[f] += P_f xc[C]
+template <int NU>
+__global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
+                              const double* __restrict__ fine_in, double* __restrict__ fine_out,
+                              const double* __restrict__ coarse_in, double* __restrict__ coarse_out,
+                              const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const LvlInst F = lf[b], Cc = lc[b];
+  const int nl = F.nloc;
+  const int nf = NU / nl;  // fields
+  const int nc = Cc.nx * Cc.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    const int I = c % Cc.nx, K = c / Cc.nx;
+    double acc[NU];
+    if (mode == 0)
+      for (int r = 0; r < NU; ++r) acc[r] = 0.0;
+    else
+      for (int r = 0; r < NU; ++r) acc[r] = coarse_in[(Cc.cell_off + c) * NU + r];
+    for (int dk = 0; dk < (F.dim == 2 ? 2 : 1); ++dk)
+      for (int di = 0; di < 2; ++di) {
+        const int f = (F.dim == 2 ? (2 * K + dk) * F.nx : 0) + 2 * I + di;
+        const int64_t fo = (F.cell_off + f) * NU;
+        for (int fld = 0; fld < nf; ++fld)
+          for (int l = 0; l < nl; ++l) {      // child mode (p + 2q)
+            const int p = l & 1, q = l >> 1;
+            if (mode == 0) {
+              const double rv = fine_in[fo + fld * nl + l];
+              for (int L2 = 0; L2 < nl; ++L2) {  // coarse mode
+                const int P = L2 & 1, Q = L2 >> 1;
+                const double w = inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0);
+                acc[fld * nl + L2] += w * rv;
+              }
+            } else {
+              double v = 0.0;
+              for (int L2 = 0; L2 < nl; ++L2) {
+                const int P = L2 & 1, Q = L2 >> 1;
+                const double w = inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0);
+                v += w * acc[fld * nl + L2];
+              }
+              fine_out[fo + fld * nl + l] += v;
+            }
+          }
+      }
+    if (mode == 0)
+      for (int r = 0; r < NU; ++r) coarse_out[(Cc.cell_off + c) * NU + r] = acc[r];
+  }
+}
+
 // ------------------------------------------------------------------ host side
+struct MgLevel {
+  std::vector<LvlInst> li;
+  LvlInst* d_li = nullptr;
+  int64_t ncell = 0;
+  int max_nx = 0, max_ny = 0;
+  DsaStencil* d_st = nullptr;
+  double *st = nullptr, *ss = nullptr, *inv = nullptr, *x = nullptr, *b = nullptr, *r = nullptr;
+};
+
 struct DsaSolver {
   rte_batch* b = nullptr;
-  int32_t* d_live = nullptr;
-  DsaStencil* d_st = nullptr;
-  double* d_inv = nullptr;
-  Krylov K;
-  double* X = nullptr;     // solution (DSA space)
-  double* T = nullptr;     // temporary (DSA space)
-  double* rhs = nullptr;
-  double* tol = nullptr;   // [n] absolute tolerances
-  double* rn = nullptr;    // [n] rhs norms
+  int nu = 12;
   int restart = 0;
+  std::vector<MgLevel> lv;
+  double* inv0 = nullptr;   // level 0 inverses per (instance, region)
+  double *X = nullptr, *T = nullptr, *rhs = nullptr, *tol = nullptr, *rn = nullptr;
+  int32_t* d_live = nullptr;
+  Krylov K;                 // only with restart >= 1
+  Space sp;                 // DSA space of level 0
+  int nu_smooth = 2, coarse_sweeps = 20;
   int init(rte_batch* batch, int restart_);
   void release();
+  int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);
+  int stencil(int l, int mode, int color, const double* bv, double* x, double* y, const int32_t* act,
+              hipStream_t s);
+  int smooth(int l, int sweeps, bool reverse, const int32_t* act, hipStream_t s);
+  int vcycle(int l, const int32_t* act, hipStream_t s);
+  int precond(const double* in, double* out, const int32_t* act, hipStream_t s);
   int apply(const double* sigma_t, const double* sigma_s, const double* v, double* z, double inner_tol,
-            int inner_max, const int32_t* active, int32_t* iters_host, hipStream_t s);
-  int launch_apply(dim3 cg, hipStream_t s, const double* x, double* y, const double* st,
-                   const double* ss, const int32_t* act) {
-    if (b->dim == 2)
-      hipLaunchKernelGGL(k_dsa_apply<12>, cg, dim3(256), 0, s, b->d_inst, d_st, b->d_region, st, ss,
-                         b->max_regions, K.sp.d_off, x, y, act);
-    else
-      hipLaunchKernelGGL(k_dsa_apply<4>, cg, dim3(256), 0, s, b->d_inst, d_st, b->d_region, st, ss,
-                         b->max_regions, K.sp.d_off, x, y, act);
-    RTE_HIP(hipGetLastError());
-    return RTE_OK;
-  }
-  int launch_jacobi(dim3 cg, hipStream_t s, const double* x, double* y, const int32_t* act) {
-    if (b->dim == 2)
-      hipLaunchKernelGGL(k_dsa_jacobi<12>, cg, dim3(256), 0, s, b->d_inst, d_st, b->d_region, d_inv,
-                         b->max_regions, K.sp.d_off, x, y, act);
-    else
-      hipLaunchKernelGGL(k_dsa_jacobi<4>, cg, dim3(256), 0, s, b->d_inst, d_st, b->d_region, d_inv,
-                         b->max_regions, K.sp.d_off, x, y, act);
-    RTE_HIP(hipGetLastError());
-    return RTE_OK;
+            int inner_max, const int32_t* active, int32_t* iters_host, bool prep, hipStream_t s);
+  dim3 grid(int l) const {
+    const int c = lv[l].max_nx * lv[l].max_ny;
+    return dim3((unsigned)std::max(1, std::min(1024, (c + 255) / 256)), b->n_inst);
   }
 };
 
 int DsaSolver::init(rte_batch* batch, int restart_) {
   b = batch;
   restart = restart_;
-  std::vector<int64_t> lens(b->n_inst);
-  for (int k = 0; k < b->n_inst; ++k) {
-    const auto& I = b->inst[k];
-    lens[k] = (int64_t)I.nx * I.ny * I.nloc * (1 + I.dim);
+  nu = b->dim == 2 ? 12 : 4;
+  const int n = b->n_inst;
+  // levels: coarsen while every instance can be halved
+  int nlev = 1;
+  {
+    bool ok = true;
+    int f = 1;
+    while (ok) {
+      for (const auto& I : b->inst) {
+        const int nx = I.nx / f, ny = I.ny / f;
+        const bool can = (nx % 2 == 0) && nx >= 4 && (I.dim == 1 || (ny % 2 == 0 && ny >= 4));
+        ok = ok && can;
+      }
+      if (ok) {
+        ++nlev;
+        f *= 2;
+      }
+      if (nlev >= 12) break;
+    }
   }
-  RTE_TRY(K.init(lens, restart, false));
-  const int64_t tot = K.sp.total;
-  if (hipMalloc(&d_st, sizeof(DsaStencil) * b->n_inst) != hipSuccess ||
-      hipMalloc(&d_inv, sizeof(double) * b->n_inst * b->max_regions * DMAX * DMAX) != hipSuccess ||
+  lv.resize(nlev);
+  for (int l = 0; l < nlev; ++l) {
+    MgLevel& L = lv[l];
+    L.li.resize(n);
+    int64_t off = 0;
+    for (int k = 0; k < n; ++k) {
+      const auto& I = b->inst[k];
+      const int f = 1 << l;
+      LvlInst q{};
+      q.nx = I.nx / f;
+      q.ny = I.dim == 2 ? I.ny / f : 1;
+      q.dim = I.dim;
+      q.nloc = I.nloc;
+      q.hx = I.hx * f;
+      q.hy = I.dim == 2 ? I.hy * f : 1.0;
+      q.cell_off = off;
+      off += (int64_t)q.nx * q.ny;
+      L.max_nx = std::max(L.max_nx, q.nx);
+      L.max_ny = std::max(L.max_ny, q.ny);
+      L.li[k] = q;
+    }
+    L.ncell = off;
+    if (hipMalloc(&L.d_li, sizeof(LvlInst) * n) != hipSuccess ||
+        hipMalloc(&L.d_st, sizeof(DsaStencil) * n) != hipSuccess ||
+        hipMalloc(&L.st, sizeof(double) * off) != hipSuccess ||
+        hipMalloc(&L.ss, sizeof(double) * off) != hipSuccess ||
+        hipMalloc(&L.x, sizeof(double) * off * nu) != hipSuccess ||
+        hipMalloc(&L.b, sizeof(double) * off * nu) != hipSuccess ||
+        hipMalloc(&L.r, sizeof(double) * off * nu) != hipSuccess ||
+        (l > 0 && hipMalloc(&L.inv, sizeof(double) * off * nu * nu) != hipSuccess))
+      return RTE_ENOMEM;
+    RTE_HIP(hipMemcpy(L.d_li, L.li.data(), sizeof(LvlInst) * n, hipMemcpyHostToDevice));
+    // per-level stencil: the same construction with this level's cell sizes
+    std::vector<InstDev> tmp = b->inst;
+    for (int k = 0; k < n; ++k) {
+      tmp[k].hx = L.li[k].hx;
+      tmp[k].hy = L.li[k].hy;
+    }
+    InstDev* d_tmp = nullptr;
+    if (hipMalloc(&d_tmp, sizeof(InstDev) * n) != hipSuccess) return RTE_ENOMEM;
+    RTE_HIP(hipMemcpy(d_tmp, tmp.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_dsa_setup, dim3((n + 63) / 64), dim3(64), 0, 0, n, d_tmp, b->d_ox, b->d_oy,
+                       b->d_w, L.d_st);
+    RTE_HIP(hipGetLastError());
+    RTE_HIP(hipDeviceSynchronize());
+    (void)hipFree(d_tmp);
+  }
+  std::vector<int64_t> lens(n);
+  for (int k = 0; k < n; ++k) lens[k] = (int64_t)lv[0].li[k].nx * lv[0].li[k].ny * nu;
+  RTE_TRY(sp.init(lens));
+  if (restart > 0) RTE_TRY(K.init(lens, restart, false));
+  const int64_t tot = sp.total;
+  if (hipMalloc(&inv0, sizeof(double) * n * b->max_regions * DMAX * DMAX) != hipSuccess ||
       hipMalloc(&X, sizeof(double) * tot) != hipSuccess ||
       hipMalloc(&T, sizeof(double) * tot) != hipSuccess ||
       hipMalloc(&rhs, sizeof(double) * tot) != hipSuccess ||
-      hipMalloc(&tol, sizeof(double) * b->n_inst) != hipSuccess ||
-      hipMalloc(&rn, sizeof(double) * b->n_inst) != hipSuccess ||
-      hipMalloc(&d_live, sizeof(int32_t) * b->n_inst) != hipSuccess)
+      hipMalloc(&tol, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&rn, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&d_live, sizeof(int32_t) * n) != hipSuccess)
     return RTE_ENOMEM;
-  hipLaunchKernelGGL(k_dsa_setup, dim3((b->n_inst + 63) / 64), dim3(64), 0, 0, b->n_inst, b->d_inst,
-                     b->d_ox, b->d_oy, b->d_w, d_st);
-  RTE_HIP(hipGetLastError());
-  RTE_HIP(hipDeviceSynchronize());
   return RTE_OK;
 }
 
 void DsaSolver::release() {
-  K.release();
-  for (void* p : {(void*)d_st, (void*)d_inv, (void*)X, (void*)T, (void*)rhs, (void*)tol, (void*)rn,
-                  (void*)d_live})
+  if (restart > 0) K.release();
+  sp.release();
+  for (auto& L : lv)
+    for (void* p : {(void*)L.d_li, (void*)L.d_st, (void*)L.st, (void*)L.ss, (void*)L.inv, (void*)L.x,
+                    (void*)L.b, (void*)L.r})
+      (void)hipFree(p);
+  lv.clear();
+  for (void* p : {(void*)inv0, (void*)X, (void*)T, (void*)rhs, (void*)tol, (void*)rn, (void*)d_live})
     (void)hipFree(p);
+  inv0 = X = T = rhs = tol = rn = nullptr;
   d_live = nullptr;
-  d_st = nullptr;
-  d_inv = X = T = rhs = tol = rn = nullptr;
+}
+
+int DsaSolver::prepare(const double* sigma_t, const double* sigma_s, const int32_t* active,
+                       hipStream_t s) {
+  const int n = b->n_inst;
+  const int mr = b->max_regions;
+  hipLaunchKernelGGL(k_mg_sigma0, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, b->d_region, sigma_t,
+                     sigma_s, mr, lv[0].st, lv[0].ss);
+  hipLaunchKernelGGL(k_dsa_blockinv, dim3((n * mr + 63) / 64), dim3(64), 0, s, n, mr, b->d_inst,
+                     lv[0].d_st, sigma_t, sigma_s, inv0);
+  for (size_t l = 1; l < lv.size(); ++l) {
+    hipLaunchKernelGGL(k_mg_sigma_coarsen, grid(l), dim3(256), 0, s, lv[l - 1].d_li, lv[l].d_li,
+                       lv[l - 1].st, lv[l - 1].ss, lv[l].st, lv[l].ss);
+    if (nu == 12)
+      hipLaunchKernelGGL(k_mg_inv_cells<12>, grid(l), dim3(64), 0, s, lv[l].d_li, lv[l].d_st, lv[l].st,
+                         lv[l].ss, lv[l].inv, active);
+    else
+      hipLaunchKernelGGL(k_mg_inv_cells<4>, grid(l), dim3(64), 0, s, lv[l].d_li, lv[l].d_st, lv[l].st,
+                         lv[l].ss, lv[l].inv, active);
+  }
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, double* y,
+                       const int32_t* act, hipStream_t s) {
+  MgLevel& L = lv[l];
+  const double* inv = l == 0 ? inv0 : L.inv;
+  const int per_cell = l == 0 ? 0 : 1;
+  if (nu == 12)
+    hipLaunchKernelGGL(k_mg_stencil<12>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+                       L.ss, inv, per_cell, b->d_region, b->d_inst, b->max_regions, bv, x, y, act);
+  else
+    hipLaunchKernelGGL(k_mg_stencil<4>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+                       L.ss, inv, per_cell, b->d_region, b->d_inst, b->max_regions, bv, x, y, act);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int DsaSolver::smooth(int l, int sweeps, bool reverse, const int32_t* act, hipStream_t s) {
+  for (int k = 0; k < sweeps; ++k) {
+    RTE_TRY(stencil(l, 2, reverse ? 1 : 0, lv[l].b, lv[l].x, nullptr, act, s));
+    RTE_TRY(stencil(l, 2, reverse ? 0 : 1, lv[l].b, lv[l].x, nullptr, act, s));
+  }
+  return RTE_OK;
+}
+
+// x_l = V-cycle approximation of K_l^{-1} b_l (x_l starts at zero)
+int DsaSolver::vcycle(int l, const int32_t* act, hipStream_t s) {
+  MgLevel& L = lv[l];
+  RTE_HIP(hipMemsetAsync(L.x, 0, sizeof(double) * L.ncell * nu, s));
+  if (l == (int)lv.size() - 1) return smooth(l, coarse_sweeps, false, act, s);
+  RTE_TRY(smooth(l, nu_smooth, false, act, s));
+  RTE_TRY(stencil(l, 1, 0, L.b, L.x, L.r, act, s));
+  MgLevel& C = lv[l + 1];
+  const dim3 g = grid(l + 1);
+  if (nu == 12)
+    hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
+                       (const double*)nullptr, C.b, act);
+  else
+    hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
+                       (const double*)nullptr, C.b, act);
+  RTE_HIP(hipGetLastError());
+  RTE_TRY(vcycle(l + 1, act, s));
+  if (nu == 12)
+    hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const double*)nullptr,
+                       L.x, C.x, (double*)nullptr, act);
+  else
+    hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const double*)nullptr,
+                       L.x, C.x, (double*)nullptr, act);
+  RTE_HIP(hipGetLastError());
+  return smooth(l, nu_smooth, true, act, s);
+}
+
+// out = V-cycle(in) on level 0
+int DsaSolver::precond(const double* in, double* out, const int32_t* act, hipStream_t s) {
+  RTE_HIP(hipMemcpyAsync(lv[0].b, in, sizeof(double) * sp.total, hipMemcpyDeviceToDevice, s));
+  RTE_TRY(vcycle(0, act, s));
+  if (out != lv[0].x)
+    RTE_HIP(hipMemcpyAsync(out, lv[0].x, sizeof(double) * sp.total, hipMemcpyDeviceToDevice, s));
+  return RTE_OK;
 }
 
 __global__ void k_scale_tol(int n, const double* __restrict__ rn, double rtol, double* __restrict__ tol) {
@@ -421,86 +810,89 @@ __global__ void k_scale_tol(int n, const double* __restrict__ rn, double rtol, d
 
 int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double* v, double* z,
                      double inner_tol, int inner_max, const int32_t* active, int32_t* iters_host,
-                     hipStream_t s) {
+                     bool prep, hipStream_t s) {
   const int n = b->n_inst;
-  const Space& sp = K.sp;
   const int mr = b->max_regions;
-  const dim3 cg((unsigned)std::max(1, std::min(1024, (b->max_nx * b->max_ny + 255) / 256)), n);
-  hipLaunchKernelGGL(k_dsa_blockinv, dim3((n * mr + 63) / 64), dim3(64), 0, s, n, mr, b->d_inst, d_st,
-                     sigma_t, sigma_s, d_inv);
-  hipLaunchKernelGGL(k_dsa_rhs, cg, dim3(256), 0, s, b->d_inst, d_st, b->d_region, sigma_s, mr,
-                     sp.d_off, v, rhs, active);
+  if (prep) RTE_TRY(prepare(sigma_t, sigma_s, active, s));
+  hipLaunchKernelGGL(k_dsa_rhs, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_region, sigma_s,
+                     mr, sp.d_off, v, rhs, active);
   RTE_HIP(hipGetLastError());
-  std::vector<int32_t> act(n, 1);
-  if (active) RTE_HIP(hipMemcpyAsync(act.data(), active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-  RTE_HIP(hipStreamSynchronize(s));
   std::vector<int32_t> iters(n, 0);
-  // d_live: instances still iterating (converged instances drop out)
-  RTE_HIP(hipMemcpyAsync(d_live, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-  RTE_HIP(hipMemsetAsync(X, 0, sizeof(double) * sp.total, s));
-  RTE_TRY(knorm(sp, rhs, K.partA, rn, 1, d_live, s));
-  hipLaunchKernelGGL(k_scale_tol, dim3((n + 63) / 64), dim3(64), 0, s, n, rn, inner_tol, tol);
-  int done_iters = 0;
-  std::vector<int32_t> jd(n), live_h = act;
-  int status = RTE_OK;
-  while (true) {
-    // residual r = rhs - K X  (first cycle: X = 0 -> r = rhs)
-    if (done_iters == 0) {
-      RTE_TRY(kcopy(sp, rhs, T, d_live, s));
-    } else {
-      RTE_TRY(launch_apply(cg, s, X, T, sigma_t, sigma_s, d_live));
-      RTE_TRY(kaxpby(sp, 1.0, rhs, -1.0, T, d_live, s));
-    }
-    RTE_HIP(hipMemcpyAsync(K.active, d_live, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    RTE_TRY(kstart(K, T, tol, s));
-    int j = 0;
-    for (; j < restart && done_iters + j < inner_max; ++j) {
-      RTE_TRY(launch_jacobi(cg, s, K.v(j), T, K.active));
-      RTE_TRY(launch_apply(cg, s, T, K.v(j + 1), sigma_t, sigma_s, K.active));
-      RTE_TRY(arnoldi_mgs(K, j, s));
-      if ((j + 1) % 8 == 0) {
-        std::vector<int32_t> a(n);
-        RTE_HIP(hipMemcpyAsync(a.data(), K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-        RTE_HIP(hipStreamSynchronize(s));
-        bool any = false;
-        for (int q = 0; q < n; ++q) any = any || a[q];
-        if (!any) {
-          ++j;
-          break;
-        }
+  if (restart == 0) {
+    // stationary: X <- X + V(rhs - K X), inner_max cycles
+    for (int k = 0; k < inner_max; ++k) {
+      if (k == 0) {
+        RTE_TRY(precond(rhs, X, active, s));
+      } else {
+        RTE_TRY(stencil(0, 1, 0, rhs, X, lv[0].b, active, s));
+        RTE_TRY(vcycle(0, active, s));
+        RTE_TRY(kaxpby(sp, 1.0, lv[0].x, 1.0, X, active, s));
       }
     }
-    // X += M^{-1} (V y)
-    RTE_HIP(hipMemsetAsync(T, 0, sizeof(double) * sp.total, s));
-    RTE_TRY(kylov_solve_update(K, K.V, T, s));
-    RTE_TRY(launch_jacobi(cg, s, T, K.v(0), d_live));
-    RTE_TRY(kaxpby(sp, 1.0, K.v(0), 1.0, X, d_live, s));
-    RTE_HIP(hipMemcpyAsync(jd.data(), K.jdone, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    // estimate of each instance: scal[b*8+2]
-    std::vector<double> sc(8 * n), tl(n);
-    RTE_HIP(hipMemcpyAsync(sc.data(), K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
-    RTE_HIP(hipMemcpyAsync(tl.data(), tol, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    for (int q = 0; q < n; ++q) iters[q] = inner_max;
+  } else {
+    std::vector<int32_t> act(n, 1);
+    if (active) RTE_HIP(hipMemcpyAsync(act.data(), active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
-    done_iters += j;
-    bool any = false;
-    for (int q = 0; q < n; ++q) {
-      if (!live_h[q]) continue;
-      iters[q] += jd[q];
-      if (sc[8 * q + 2] <= tl[q]) live_h[q] = 0;
-      any = any || live_h[q];
+    RTE_HIP(hipMemcpyAsync(d_live, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    RTE_HIP(hipMemsetAsync(X, 0, sizeof(double) * sp.total, s));
+    RTE_TRY(knorm(sp, rhs, K.partA, rn, 1, d_live, s));
+    hipLaunchKernelGGL(k_scale_tol, dim3((n + 63) / 64), dim3(64), 0, s, n, rn, inner_tol, tol);
+    int done_iters = 0;
+    std::vector<int32_t> jd(n), live_h = act;
+    while (true) {
+      if (done_iters == 0) {
+        RTE_TRY(kcopy(sp, rhs, T, d_live, s));
+      } else {
+        RTE_TRY(stencil(0, 1, 0, rhs, X, T, d_live, s));
+      }
+      RTE_HIP(hipMemcpyAsync(K.active, d_live, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+      RTE_TRY(kstart(K, T, tol, s));
+      int j = 0;
+      for (; j < restart && done_iters + j < inner_max; ++j) {
+        RTE_TRY(precond(K.v(j), T, K.active, s));
+        RTE_TRY(stencil(0, 0, 0, nullptr, T, K.v(j + 1), K.active, s));
+        RTE_TRY(arnoldi_mgs(K, j, s));
+        if ((j + 1) % 4 == 0) {
+          std::vector<int32_t> a(n);
+          RTE_HIP(hipMemcpyAsync(a.data(), K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+          RTE_HIP(hipStreamSynchronize(s));
+          bool any = false;
+          for (int q = 0; q < n; ++q) any = any || a[q];
+          if (!any) {
+            ++j;
+            break;
+          }
+        }
+      }
+      RTE_HIP(hipMemsetAsync(T, 0, sizeof(double) * sp.total, s));
+      RTE_TRY(kylov_solve_update(K, K.V, T, s));
+      RTE_TRY(precond(T, T, d_live, s));
+      RTE_TRY(kaxpby(sp, 1.0, T, 1.0, X, d_live, s));
+      std::vector<double> sc(8 * n), tl(n);
+      RTE_HIP(hipMemcpyAsync(jd.data(), K.jdone, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipMemcpyAsync(sc.data(), K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipMemcpyAsync(tl.data(), tol, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipStreamSynchronize(s));
+      done_iters += j;
+      bool any = false;
+      for (int q = 0; q < n; ++q) {
+        if (!live_h[q]) continue;
+        iters[q] += jd[q];
+        if (sc[8 * q + 2] <= tl[q]) live_h[q] = 0;
+        any = any || live_h[q];
+      }
+      if (!any || done_iters >= inner_max || j == 0) break;
+      RTE_HIP(hipMemcpyAsync(d_live, live_h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     }
-    if (!any || done_iters >= inner_max || j == 0) break;
-    RTE_HIP(hipMemcpyAsync(d_live, live_h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   }
-  const dim3 vg((unsigned)std::max<int64_t>(1, std::min<int64_t>((sp.max_len + 255) / 256, 1024)), n);
-  (void)vg;
-  RTE_HIP(hipMemcpyAsync(d_live, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_dsa_out, cg, dim3(256), 0, s, b->d_inst, d_st, sp.d_off, X, v, z, d_live);
+  hipLaunchKernelGGL(k_dsa_out, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, sp.d_off, X, v, z, active);
   RTE_HIP(hipGetLastError());
-  RTE_HIP(hipStreamSynchronize(s));
-  if (iters_host)
+  if (iters_host) {
+    RTE_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < n; ++q) iters_host[q] = iters[q];
-  return status;
+  }
+  return RTE_OK;
 }
 
 // registry: one DSA solver per (batch, restart) kept alive with the batch
@@ -538,10 +930,10 @@ void dsa_forget(rte_batch* b) {
 
 int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v, double* z,
               double inner_tol, int inner_max, int restart, const int32_t* active, int32_t* iters,
-              hipStream_t s) {
+              hipStream_t s, bool prepare) {
   DsaSolver* d = dsa_for(b, restart);
   if (!d) return RTE_ENOMEM;
-  return d->apply(sigma_t, sigma_s, v, z, inner_tol, inner_max, active, iters, s);
+  return d->apply(sigma_t, sigma_s, v, z, inner_tol, inner_max, active, iters, prepare, s);
 }
 
 }  // namespace rte
@@ -550,9 +942,9 @@ extern "C" int rte_dsa_apply(const rte_batch* cb, const double* sigma_t, const d
                              const double* v, double* z, double inner_tol, int inner_max, int restart,
                              int32_t* stats_iters, void* stream) {
   auto* b = const_cast<rte_batch*>(cb);
-  if (!b || !sigma_t || !sigma_s || !v || !z || inner_max < 1 || restart < 1 || restart > 500 ||
+  if (!b || !sigma_t || !sigma_s || !v || !z || inner_max < 1 || restart < 0 || restart > 500 ||
       !(inner_tol >= 0.0))
     return RTE_EINVAL;
   return rte::dsa_apply(b, sigma_t, sigma_s, v, z, inner_tol, inner_max, restart, nullptr,
-                        stats_iters, reinterpret_cast<hipStream_t>(stream));
+                        stats_iters, reinterpret_cast<hipStream_t>(stream), true);
 }

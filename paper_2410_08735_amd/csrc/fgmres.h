@@ -24,6 +24,7 @@ struct Fgmres {
   // record of cycle 0 (xi recurrence): Z_0..Z_{w-1}, H block [(w+1) x w], beta
   double *recZ = nullptr, *recH = nullptr, *recBeta = nullptr;
   int rec_w = 0;
+  bool dsa_ready = false;
   std::vector<int32_t> rec_jdone;
   int init(rte_batch* b, int m);
   void release();

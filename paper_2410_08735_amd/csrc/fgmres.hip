@@ -69,9 +69,12 @@ int Fgmres::precondition(int jj, const double* v, double* z, const SolveCtx& c, 
   switch (kind) {
     case RTE_PC_NONE:
       return kcopy(K.sp, v, z, K.active, s);
-    case RTE_PC_DSA:
+    case RTE_PC_DSA: {
+      const bool prep = !dsa_ready;
+      dsa_ready = true;
       return dsa_apply(b, c.sigma_t, c.sigma_s, v, z, o.dsa_inner_tol, o.dsa_inner_max,
-                       o.dsa_restart, K.active, nullptr, s);
+                       o.dsa_restart, K.active, nullptr, s, prep);
+    }
     case RTE_PC_ROMSAD: {
       int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, K.active, s);
       return st == RTE_ESINGULAR ? RTE_OK : st;
@@ -98,6 +101,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   RTE_TRY(autotune_sweep(b, 0, c.sigma_t, s));
   if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s));
   for (int q = 0; q < n; ++q) stats[q] = rte_solve_stats{};
+  dsa_ready = false;  // the DSA hierarchy is rebuilt for this call's cross sections
   std::vector<int32_t> live(n, 1);
   if (c.init_active) {
     RTE_HIP(hipMemcpyAsync(live.data(), c.init_active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
@@ -105,7 +109,8 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   }
   RTE_HIP(hipMemcpyAsync(cyc, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   // b~ = T G~ (FP64) and ||b~||
-  RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, c.G, c.inflow, nullptr, s, cyc));
+  RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, c.G, c.inflow, nullptr, s, cyc,
+                       batch_cell_ordinates(b, live.data())));
   RTE_TRY(reduce_partials(b, 0, 1.0, nullptr, 0.0, btil, s, cyc));
   for (int q = 0; q < n; ++q)
     if (live[q]) stats[q].sweeps_f64 += 1;
@@ -135,7 +140,9 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     if (!n_live) break;
     RTE_HIP(hipMemcpyAsync(cyc, cm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     RTE_HIP(hipMemcpyAsync(K.active, cyc, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    RTE_TRY(kstart(K, r, tolabs, s));
+    // FP32 sweeps cannot reduce the residual much below ~1e-6 of its value at
+    // the start of a cycle; the FP64 true residual then restarts the cycle.
+    RTE_TRY(kstart(K, r, tolabs, s, pin ? 1e-6 : 0.0));
     act = cm;
     for (int q = 0; q < n; ++q) stats[q].cycles += cm[q];
     for (int j = 0; j < m; ++j) {
@@ -148,7 +155,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       RTE_TRY(precondition(j + 1, K.v(j), K.z(j), c, s, which));
       // w = A~ z_j = z_j - T Sigma_s z_j
       RTE_TRY(sweep_launch(b, pin, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s,
-                           K.active));
+                           K.active, batch_cell_ordinates(b, act.data())));
       RTE_TRY(reduce_partials(b, pin, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active));
       RTE_TRY(arnoldi_mgs(K, j, s));
       for (int q = 0; q < n; ++q) {
@@ -179,7 +186,8 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     }
     // phi += Z y ; r = b~ - A~ phi in FP64
     RTE_TRY(kylov_solve_update(K, K.Z, phi, s));
-    RTE_TRY(sweep_launch(b, 0, c.sigma_t, c.sigma_s, phi, nullptr, nullptr, nullptr, s, cyc));
+    RTE_TRY(sweep_launch(b, 0, c.sigma_t, c.sigma_s, phi, nullptr, nullptr, nullptr, s, cyc,
+                         batch_cell_ordinates(b, cm.data())));
     RTE_TRY(reduce_partials(b, 0, 1.0, btil, 1.0, r, s, cyc, phi, -1.0));
     RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
     RTE_HIP(hipMemcpyAsync(rn.data(), rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
@@ -248,7 +256,7 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
   const rte_solve_opts& o = *opts;
   if (o.m < 1 || o.m > 500 || o.max_cycles < 1 || !(o.rtol > 0.0) ||
       (o.sweep_dtype != RTE_F32 && o.sweep_dtype != RTE_F64) || o.precond < RTE_PC_NONE ||
-      o.precond > RTE_PC_MLP || o.window < 0 || o.dsa_inner_max < 1 || o.dsa_restart < 1 ||
+      o.precond > RTE_PC_MLP || o.window < 0 || o.dsa_inner_max < 1 || o.dsa_restart < 0 ||
       o.dsa_restart > 500)
     return RTE_EINVAL;
   if ((o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && !rom) return RTE_EINVAL;

@@ -63,8 +63,9 @@ int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hi
 int arnoldi_mgs(Krylov& K, int j, hipStream_t s);
 // y = R^{-1} g per instance (jdone columns); X += sum_i y_i * basis_i
 int kylov_solve_update(Krylov& K, const double* basis, double* X, hipStream_t s);
-// start a cycle: V[0] = r / ||r||, g = (beta, 0, ...), tol_abs = rtol * bnorm
-int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s);
+// start a cycle: V[0] = r / ||r||, g = (beta, 0, ...); the cycle stops at
+// max(tol_abs, cycle_rel * beta)
+int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s, double cycle_rel = 0.0);
 int fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
 
 }  // namespace rte

@@ -258,19 +258,19 @@ __global__ void k_update(const int64_t* __restrict__ off, const int64_t* __restr
 }
 
 __global__ void k_start(int n, double* __restrict__ scal, double* __restrict__ g, int m,
-                        const double* __restrict__ tol_abs, int32_t* __restrict__ active,
-                        int32_t* __restrict__ jdone) {
+                        const double* __restrict__ tol_abs, double cycle_rel,
+                        int32_t* __restrict__ active, int32_t* __restrict__ jdone) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   jdone[b] = 0;
   if (!active[b]) return;
   const double beta = scal[b * 8 + 0];
-  scal[b * 8 + 1] = tol_abs[b];
+  scal[b * 8 + 1] = fmax(tol_abs[b], cycle_rel * beta);
   scal[b * 8 + 2] = beta;
   double* gb = g + (int64_t)b * (m + 1);
   gb[0] = beta;
   for (int i = 1; i <= m; ++i) gb[i] = 0.0;
-  if (beta <= tol_abs[b]) active[b] = 0;
+  if (beta <= tol_abs[b]) active[b] = 0;  // already converged: no cycle
 }
 
 __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
@@ -329,11 +329,11 @@ int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hi
   return kaxpby(sp, 1.0, x, 0.0, y, active, s);
 }
 
-int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s) {
+int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s, double cycle_rel) {
   const Space& sp = K.sp;
   RTE_TRY(knorm(sp, r, K.partA, K.scal + 0, 8, K.active, s));
   hipLaunchKernelGGL(k_start, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, K.scal, K.g, K.m, tol_abs,
-                     K.active, K.jdone);
+                     cycle_rel, K.active, K.jdone);
   RTE_HIP(hipGetLastError());
   return kscale(sp, r, K.scal + 0, 8, K.v(0), K.active, s);
 }

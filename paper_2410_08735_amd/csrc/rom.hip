@@ -828,10 +828,12 @@ static double now_s() {
 extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, const double* sigma_s,
                                    const double* G, const double* inflow, int window, int mu1_index,
                                    double eps_rom, int n_giter, double eps_qr, double hf_rtol,
-                                   rte_rom** out, rte_greedy_report* rep, void* stream) {
+                                   double hf_dsa_tol, rte_rom** out, rte_greedy_report* rep,
+                                   void* stream) {
   auto* b = const_cast<rte_batch*>(cb);
   if (!b || !sigma_t || !sigma_s || !G || !out || window < 1 || n_giter < 1 || mu1_index < 0 ||
       mu1_index >= b->n_inst || !(eps_qr >= 0.0) || !(hf_rtol > 0.0) || n_giter > 256 ||
+      !(hf_dsa_tol >= 0.0) ||
       (int64_t)n_giter * window > ROM_RMAX || !b->uniform || b->inst[0].n_regions > ROM_REGMAX)
     return RTE_EINVAL;
   hipStream_t s = as_stream(stream);
@@ -910,9 +912,15 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
     o.sweep_dtype = RTE_F64;
     o.rtol = hf_rtol;
     o.window = 0;
-    o.dsa_inner_max = 60;
-    o.dsa_restart = 30;
-    o.dsa_inner_tol = 1e-8;
+    if (hf_dsa_tol > 0.0) {   // V-cycle-preconditioned GMRES to hf_dsa_tol
+      o.dsa_inner_max = 4000;
+      o.dsa_restart = 60;
+      o.dsa_inner_tol = hf_dsa_tol;
+    } else {                  // one multigrid V-cycle per DSA application
+      o.dsa_inner_max = 1;
+      o.dsa_restart = 0;
+      o.dsa_inner_tol = 0.0;
+    }
     SolveCtx c{};
     c.opts = &o;
     c.sigma_t = sigma_t;

@@ -101,18 +101,31 @@ namespace rte {
 
 int ensure_partials(rte_batch* b, int64_t elems);
 int make_plan(rte_batch* b, int prec, int G, int threads);
+// prof_units: cell-ordinates processed by this launch (for the event profiler);
+// negative = every instance of the batch.
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
-                 hipStream_t s, const int32_t* active = nullptr);
+                 hipStream_t s, const int32_t* active = nullptr, double prof_units = -1.0);
+
+// Event profiler: per-slot HIP event pairs around kernel launches.
+enum { PROF_SWEEP_F64 = 0, PROF_SWEEP_F32 = 1, PROF_DSA_OP = 2, PROF_MGS = 3, PROF_ROM = 4,
+       PROF_SLOTS = 5 };
+bool prof_enabled();
+void prof_begin(int slot, hipStream_t s);
+void prof_end(int slot, hipStream_t s, double units);
+double batch_cell_ordinates(const rte_batch* b, const int32_t* host_mask);
 // out = alpha * sum_partials + beta * x + gamma * y   (x, y nullable)
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
                     hipStream_t s, const int32_t* active = nullptr, const double* y = nullptr,
                     double gamma = 0.0);
 int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s);
 int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s);
+// restart == 0: inner_max V-cycles; restart >= 1: V-cycle-preconditioned
+// GMRES(restart) to inner_tol.  prepare = rebuild the sigma-dependent
+// multigrid data (cross sections per level, block inverses).
 int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v, double* z,
               double inner_tol, int inner_max, int restart, const int32_t* active, int32_t* iters,
-              hipStream_t s);
+              hipStream_t s, bool prepare = true);
 void dsa_forget(rte_batch* b);
 void fgmres_forget(rte_batch* b);
 void rom_scratch_forget(const rte_batch* b);

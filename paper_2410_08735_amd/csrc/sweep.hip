@@ -359,9 +359,32 @@ static int launch2d_g(rte_batch* b, const Plan& p, const double* st, const doubl
   }
 }
 
+static int sweep_launch_impl(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
+                             const double* qx, const double* qadd, const double* inflow,
+                             double* psi_out, hipStream_t s, const int32_t* active);
+
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
-                 hipStream_t s, const int32_t* active) {
+                 hipStream_t s, const int32_t* active, double prof_units) {
+  if (!prof_enabled())
+    return sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+  const int slot = prec == 0 ? PROF_SWEEP_F64 : PROF_SWEEP_F32;
+  prof_begin(slot, s);
+  const int st = sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+  prof_end(slot, s, prof_units >= 0.0 ? prof_units : batch_cell_ordinates(b, nullptr));
+  return st;
+}
+
+double batch_cell_ordinates(const rte_batch* b, const int32_t* mask) {
+  double u = 0.0;
+  for (int k = 0; k < b->n_inst; ++k)
+    if (!mask || mask[k]) u += (double)b->inst[k].nx * b->inst[k].ny * b->inst[k].n_ord;
+  return u;
+}
+
+static int sweep_launch_impl(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
+                             const double* qx, const double* qadd, const double* inflow,
+                             double* psi_out, hipStream_t s, const int32_t* active) {
   const Plan& p = b->plan[prec];
   if (b->dim == 1) {
     if (b->max_ord > 1024) return RTE_EINVAL;

@@ -188,7 +188,8 @@ def test_greedy_matches_oracle(oracle_rom, tmp_path):
     B = rt.Batch(specs)
     st, ss = B.sigma()
     rom, grep = rt.romsad_build_greedy(B, st, ss, B.source(), None, window=2, mu1_index=0,
-                                       eps_rom=0.0, n_giter=3, eps_qr=1e-13, hf_rtol=1e-11)
+                                       eps_rom=0.0, n_giter=3, eps_qr=1e-13, hf_rtol=1e-11,
+                                       hf_dsa_tol=1e-13)
     assert grep["sampled"] == rep.sampled, (grep, rep.sampled)
     assert grep["rank"] == U.shape[0]
     # same span: M_ROM^{-1} v agrees (invariant under U -> U Q)
