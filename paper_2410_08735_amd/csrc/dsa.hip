@@ -48,6 +48,10 @@ struct DsaStencil {
   double Ss[DMAX * DMAX];
   double m[2];  // m_x, m_y (right-hand side weights of the first-moment rows)
   int nu;
+  // reflection-symmetric X-Y rules (m = b = bm = t = 0, a_xy = 0, c_xey = c_yex = 0):
+  // the scalars of the structured form used by the fast kernels
+  int sym;
+  double ax, ay, bex, bey, cxx, cxy, cyx, cyy, hx, hy;
 };
 
 __device__ static void axis_ops(double h, double DCs[4], double DCp[4], double DCm[4], double DJs[4],
@@ -114,6 +118,27 @@ __global__ void k_dsa_setup(int n_inst, const InstDev* __restrict__ insts,
   S.nu = nu;
   S.m[0] = m[0];
   S.m[1] = m[1];
+  {
+    const double tz = 1e-13;
+    bool sy = dim == 2 && fabs(m[0]) < tz && fabs(m[1]) < tz && fabs(a[0][1]) < tz && fabs(a[1][0]) < tz;
+    for (int e = 0; e < 2; ++e)
+      for (int f = 0; f < 2; ++f) {
+        sy = sy && fabs(bb[e][f]) < tz && fabs(bm[e][f]) < tz && fabs(c[0][e][1]) < tz &&
+             fabs(c[1][e][0]) < tz;
+        for (int g = 0; g < 2; ++g) sy = sy && fabs(t[e][f][g]) < tz;
+      }
+    S.sym = sy ? 1 : 0;
+    S.ax = a[0][0];
+    S.ay = a[1][1];
+    S.bex = be[0];
+    S.bey = be[1];
+    S.cxx = c[0][0][0];
+    S.cxy = c[0][1][0];
+    S.cyx = c[1][0][1];
+    S.cyy = c[1][1][1];
+    S.hx = I.hx;
+    S.hy = I.hy;
+  }
   for (int z = 0; z < 5; ++z)
     for (int q = 0; q < DMAX * DMAX; ++q) S.blk[z][q] = 0.0;
   for (int q = 0; q < DMAX * DMAX; ++q) S.St[q] = S.Ss[q] = 0.0;
@@ -527,6 +552,202 @@ __global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li
   }
 }
 
+// Structured apply for reflection-symmetric rules.  Along one axis, with
+// R = (1, sqrt3), L = (1, -sqrt3) the end traces (times sqrt h):
+//   D_C: own sqrt3/h [[0, 1], [-1, 0]], upper neighbour R L^T/(2h), lower -L R^T/(2h)
+//   D_J: own -diag(2, 6)/h,          upper neighbour R L^T/h,    lower  L R^T/h,
+// so with P = R (L.x_up)/h and Q = L (R.x_lo)/h:
+//   D_C x = S_C x + (P - Q)/2,  D_J x = S_J x + P + Q.
+__device__ __forceinline__ void axis_cj(const double* Xc, const double* Xhi, const double* Xlo, int axis,
+                                        double ih, double C[4], double J[4]) {
+  const double r3 = 1.7320508075688772935;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int i0 = axis == 0 ? 2 * g : g;
+    const int i1 = axis == 0 ? 2 * g + 1 : g + 2;
+    const double dl = Xhi ? (Xhi[i0] - r3 * Xhi[i1]) * ih : 0.0;
+    const double dr = Xlo ? (Xlo[i0] + r3 * Xlo[i1]) * ih : 0.0;
+    C[i0] = r3 * ih * Xc[i1] + 0.5 * (dl - dr);
+    C[i1] = -r3 * ih * Xc[i0] + 0.5 * r3 * (dl + dr);
+    J[i0] = -2.0 * ih * Xc[i0] + dl + dr;
+    J[i1] = -6.0 * ih * Xc[i1] + r3 * (dl - dr);
+  }
+}
+
+// y = K x for one cell (12 unknowns: phi, J_x, J_y), reflection-symmetric rule.
+__device__ __forceinline__ void sym_cell_apply(const DsaStencil& S, double st, double ss,
+                                               const double* xc, const double* xl, const double* xr,
+                                               const double* xb, const double* xt, double* y) {
+  const double ihx = 1.0 / S.hx, ihy = 1.0 / S.hy;
+  double Cx[4], Jx[4], Cy[4], Jy[4];
+  // phi row and the J rows' phi terms
+  axis_cj(xc, xr, xl, 0, ihx, Cx, Jx);
+  axis_cj(xc, xt, xb, 1, ihy, Cy, Jy);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    y[l] = (st - ss) * xc[l] - S.bex * Jx[l] - S.bey * Jy[l];
+    y[4 + l] = S.ax * Cx[l] + 3.0 * S.ax * st * xc[4 + l];
+    y[8 + l] = S.ay * Cy[l] + 3.0 * S.ay * st * xc[8 + l];
+  }
+  // J_x field: C_x(J_x) into the phi row, D_J^x, D_J^y into its own row
+  axis_cj(xc + 4, xr ? xr + 4 : nullptr, xl ? xl + 4 : nullptr, 0, ihx, Cx, Jx);
+  axis_cj(xc + 4, xt ? xt + 4 : nullptr, xb ? xb + 4 : nullptr, 1, ihy, Cy, Jy);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    y[l] += 3.0 * S.ax * Cx[l];
+    y[4 + l] -= 1.5 * (S.cxx * Jx[l] + S.cxy * Jy[l]);
+  }
+  // J_y field
+  axis_cj(xc + 8, xr ? xr + 8 : nullptr, xl ? xl + 8 : nullptr, 0, ihx, Cx, Jx);
+  axis_cj(xc + 8, xt ? xt + 8 : nullptr, xb ? xb + 8 : nullptr, 1, ihy, Cy, Jy);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    y[l] += 3.0 * S.ay * Cy[l];
+    y[8 + l] -= 1.5 * (S.cyx * Jx[l] + S.cyy * Jy[l]);
+  }
+}
+
+// Exact solve with the cell's diagonal block for a reflection-symmetric rule.
+// The own-cell parts are: phi row diagonal Dphi, J rows diagonal dJx, dJy, and
+// the skew couplings a_xx S_x, a_yy S_y (S = sqrt3/h [[0,1],[-1,0]] along its
+// axis).  Eliminating J_x, J_y leaves a diagonal Schur complement because
+// S dJ^{-1} S is diagonal:
+//   (Dphi + 3 a_xx^2 s_x^2 / dJx[1-p, q] + 3 a_yy^2 s_y^2 / dJy[p, 1-q]) phi
+//       = r_phi - 3 a_xx S_x dJx^{-1} r_Jx - 3 a_yy S_y dJy^{-1} r_Jy.
+__device__ __forceinline__ void sym_block_solve(const DsaStencil& S, double st, double ss,
+                                                const double* r, double* out) {
+  const double ihx = 1.0 / S.hx, ihy = 1.0 / S.hy;
+  const double sx = 1.7320508075688772935 * ihx, sy = 1.7320508075688772935 * ihy;
+  double dphi[4], djx[4], djy[4], tx[4], ty[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const int p = l & 1, q = l >> 1;
+    const double gx = (p ? 6.0 : 2.0) * ihx, gy = (q ? 6.0 : 2.0) * ihy;
+    dphi[l] = (st - ss) + S.bex * gx + S.bey * gy;
+    djx[l] = 3.0 * S.ax * st + 1.5 * (S.cxx * gx + S.cxy * gy);
+    djy[l] = 3.0 * S.ay * st + 1.5 * (S.cyx * gx + S.cyy * gy);
+    tx[l] = r[4 + l] / djx[l];  // dJx^{-1} r_Jx
+    ty[l] = r[8 + l] / djy[l];
+  }
+  // S_x acts on p: (S u)[0,q] = s u[1,q], (S u)[1,q] = -s u[0,q]; S_y likewise on q
+  double rhs[4];
+  rhs[0] = r[0] - 3.0 * S.ax * sx * tx[1] - 3.0 * S.ay * sy * ty[2];
+  rhs[1] = r[1] + 3.0 * S.ax * sx * tx[0] - 3.0 * S.ay * sy * ty[3];
+  rhs[2] = r[2] - 3.0 * S.ax * sx * tx[3] + 3.0 * S.ay * sy * ty[0];
+  rhs[3] = r[3] + 3.0 * S.ax * sx * tx[2] + 3.0 * S.ay * sy * ty[1];
+  const int fx[4] = {1, 0, 3, 2}, fy[4] = {2, 3, 0, 1};  // (1-p, q) and (p, 1-q)
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const double schur = dphi[l] + 3.0 * S.ax * S.ax * sx * sx / djx[fx[l]] +
+                         3.0 * S.ay * S.ay * sy * sy / djy[fy[l]];
+    out[l] = rhs[l] / schur;
+  }
+  // J = dJ^{-1} (r_J - a S phi)
+  out[4] = (r[4] - S.ax * sx * out[1]) / djx[0];
+  out[5] = (r[5] + S.ax * sx * out[0]) / djx[1];
+  out[6] = (r[6] - S.ax * sx * out[3]) / djx[2];
+  out[7] = (r[7] + S.ax * sx * out[2]) / djx[3];
+  out[8] = (r[8] - S.ay * sy * out[2]) / djy[0];
+  out[9] = (r[9] - S.ay * sy * out[3]) / djy[1];
+  out[10] = (r[10] + S.ay * sy * out[0]) / djy[2];
+  out[11] = (r[11] + S.ay * sy * out[1]) / djy[3];
+}
+
+__device__ __forceinline__ void sym_cell_op(int mode, const LvlInst& L, const DsaStencil& S, int cell,
+                                            double st, double ss, const double* __restrict__ inv,
+                                            const double* __restrict__ bvec, double* __restrict__ x,
+                                            double* __restrict__ yv, int64_t vo) {
+  const int i = cell % L.nx, k = cell / L.nx;
+  double xc[12], xl[12], xr[12], xb[12], xt[12], y[12];
+  const double* base = x + vo;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) xc[r] = base[(int64_t)cell * 12 + r];
+  const bool hl = i > 0, hr = i < L.nx - 1, hb = k > 0, ht = k < L.ny - 1;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+    xl[r] = hl ? base[(int64_t)(cell - 1) * 12 + r] : 0.0;
+    xr[r] = hr ? base[(int64_t)(cell + 1) * 12 + r] : 0.0;
+    xb[r] = hb ? base[(int64_t)(cell - L.nx) * 12 + r] : 0.0;
+    xt[r] = ht ? base[(int64_t)(cell + L.nx) * 12 + r] : 0.0;
+  }
+  // absent neighbours contribute zero traces: passing zero vectors is exact
+  sym_cell_apply(S, st, ss, xc, xl, xr, xb, xt, y);
+  if (mode == 0) {
+#pragma unroll
+    for (int r = 0; r < 12; ++r) yv[vo + (int64_t)cell * 12 + r] = y[r];
+  } else if (mode == 1) {
+#pragma unroll
+    for (int r = 0; r < 12; ++r) yv[vo + (int64_t)cell * 12 + r] = bvec[vo + (int64_t)cell * 12 + r] - y[r];
+  } else {
+    double res[12], d[12];
+#pragma unroll
+    for (int r = 0; r < 12; ++r) res[r] = bvec[vo + (int64_t)cell * 12 + r] - y[r];
+    sym_block_solve(S, st, ss, res, d);
+#pragma unroll
+    for (int r = 0; r < 12; ++r) x[vo + (int64_t)cell * 12 + r] = xc[r] + d[r];
+  }
+}
+
+__global__ void k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
+                                 const DsaStencil* __restrict__ st_, const double* __restrict__ st,
+                                 const double* __restrict__ ss, const double* __restrict__ inv,
+                                 int per_cell_inv, const int32_t* __restrict__ region0,
+                                 const InstDev* __restrict__ insts, int max_regions,
+                                 const double* __restrict__ bvec, double* __restrict__ x,
+                                 double* __restrict__ y, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const LvlInst L = li[b];
+  __shared__ DsaStencil Sh;
+  if (threadIdx.x == 0) {
+    // only the scalars of the structured form are used here
+    const DsaStencil& G = st_[b];
+    Sh.ax = G.ax; Sh.ay = G.ay; Sh.bex = G.bex; Sh.bey = G.bey; Sh.cxx = G.cxx; Sh.cxy = G.cxy;
+    Sh.cyx = G.cyx; Sh.cyy = G.cyy; Sh.hx = G.hx; Sh.hy = G.hy;
+  }
+  __syncthreads();
+  const int nc = L.nx * L.ny;
+  const int64_t vo = L.cell_off * 12;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += gridDim.x * blockDim.x) {
+    const int i = cell % L.nx, k = cell / L.nx;
+    if (mode == 2 && ((i + k) & 1) != color) continue;
+    const double t = st[L.cell_off + cell], u = ss[L.cell_off + cell];
+    sym_cell_op(mode, L, Sh, cell, t, u, nullptr, bvec, x, y, vo);
+  }
+}
+
+// Coarsest level: `sweeps` red-black Gauss-Seidel sweeps from x = 0 in one
+// launch, one work group per instance.
+__global__ void k_mg_coarse_sym(int sweeps, const LvlInst* __restrict__ li,
+                                const DsaStencil* __restrict__ st_, const double* __restrict__ st,
+                                const double* __restrict__ ss, const double* __restrict__ inv,
+                                const double* __restrict__ bvec, double* __restrict__ x,
+                                const int32_t* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const LvlInst L = li[b];
+  __shared__ DsaStencil Sh;
+  if (threadIdx.x == 0) {
+    const DsaStencil& G = st_[b];
+    Sh.ax = G.ax; Sh.ay = G.ay; Sh.bex = G.bex; Sh.bey = G.bey; Sh.cxx = G.cxx; Sh.cxy = G.cxy;
+    Sh.cyx = G.cyx; Sh.cyy = G.cyy; Sh.hx = G.hx; Sh.hy = G.hy;
+  }
+  const int nc = L.nx * L.ny;
+  const int64_t vo = L.cell_off * 12;
+  for (int e = threadIdx.x; e < nc * 12; e += blockDim.x) x[vo + e] = 0.0;
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int color = 0; color < 2; ++color) {
+      for (int cell = threadIdx.x; cell < nc; cell += blockDim.x) {
+        const int i = cell % L.nx, k = cell / L.nx;
+        if (((i + k) & 1) != color) continue;
+        sym_cell_op(2, L, Sh, cell, st[L.cell_off + cell], ss[L.cell_off + cell], nullptr, bvec, x,
+                    nullptr, vo);
+      }
+      __syncthreads();
+    }
+}
+
 // Degree-1 Legendre injection of a coarse cell's modes into child `side`
 // (0 = low half, 1 = high half), [child mode][coarse mode].
 __device__ __forceinline__ double inj1d(int side, int p, int P) {
@@ -605,6 +826,7 @@ struct DsaSolver {
   int32_t* d_live = nullptr;
   Krylov K;                 // only with restart >= 1
   Space sp;                 // DSA space of level 0
+  bool sym = false;         // every instance has a reflection-symmetric rule
   int nu_smooth = 2, coarse_sweeps = 20;
   int init(rte_batch* batch, int restart_);
   void release();
@@ -692,6 +914,12 @@ int DsaSolver::init(rte_batch* batch, int restart_) {
     RTE_HIP(hipDeviceSynchronize());
     (void)hipFree(d_tmp);
   }
+  {
+    std::vector<DsaStencil> hs(n);
+    RTE_HIP(hipMemcpy(hs.data(), lv[0].d_st, sizeof(DsaStencil) * n, hipMemcpyDeviceToHost));
+    sym = nu == 12;
+    for (int k = 0; k < n; ++k) sym = sym && hs[k].sym;
+  }
   std::vector<int64_t> lens(n);
   for (int k = 0; k < n; ++k) lens[k] = (int64_t)lv[0].li[k].nx * lv[0].li[k].ny * nu;
   RTE_TRY(sp.init(lens));
@@ -728,11 +956,13 @@ int DsaSolver::prepare(const double* sigma_t, const double* sigma_s, const int32
   const int mr = b->max_regions;
   hipLaunchKernelGGL(k_mg_sigma0, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, b->d_region, sigma_t,
                      sigma_s, mr, lv[0].st, lv[0].ss);
-  hipLaunchKernelGGL(k_dsa_blockinv, dim3((n * mr + 63) / 64), dim3(64), 0, s, n, mr, b->d_inst,
-                     lv[0].d_st, sigma_t, sigma_s, inv0);
+  if (!sym)
+    hipLaunchKernelGGL(k_dsa_blockinv, dim3((n * mr + 63) / 64), dim3(64), 0, s, n, mr, b->d_inst,
+                       lv[0].d_st, sigma_t, sigma_s, inv0);
   for (size_t l = 1; l < lv.size(); ++l) {
     hipLaunchKernelGGL(k_mg_sigma_coarsen, grid(l), dim3(256), 0, s, lv[l - 1].d_li, lv[l].d_li,
                        lv[l - 1].st, lv[l - 1].ss, lv[l].st, lv[l].ss);
+    if (sym) continue;  // block solves are explicit for symmetric rules
     if (nu == 12)
       hipLaunchKernelGGL(k_mg_inv_cells<12>, grid(l), dim3(64), 0, s, lv[l].d_li, lv[l].d_st, lv[l].st,
                          lv[l].ss, lv[l].inv, active);
@@ -749,7 +979,10 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
   MgLevel& L = lv[l];
   const double* inv = l == 0 ? inv0 : L.inv;
   const int per_cell = l == 0 ? 0 : 1;
-  if (nu == 12)
+  if (sym)
+    hipLaunchKernelGGL(k_mg_stencil_sym, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+                       L.ss, inv, per_cell, b->d_region, b->d_inst, b->max_regions, bv, x, y, act);
+  else if (nu == 12)
     hipLaunchKernelGGL(k_mg_stencil<12>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, inv, per_cell, b->d_region, b->d_inst, b->max_regions, bv, x, y, act);
   else
@@ -771,7 +1004,15 @@ int DsaSolver::smooth(int l, int sweeps, bool reverse, const int32_t* act, hipSt
 int DsaSolver::vcycle(int l, const int32_t* act, hipStream_t s) {
   MgLevel& L = lv[l];
   RTE_HIP(hipMemsetAsync(L.x, 0, sizeof(double) * L.ncell * nu, s));
-  if (l == (int)lv.size() - 1) return smooth(l, coarse_sweeps, false, act, s);
+  if (l == (int)lv.size() - 1) {
+    if (sym && l > 0) {  // whole coarsest smoothing in one launch
+      hipLaunchKernelGGL(k_mg_coarse_sym, dim3(b->n_inst), dim3(256), 0, s, coarse_sweeps, L.d_li,
+                         L.d_st, L.st, L.ss, L.inv, L.b, L.x, act);
+      RTE_HIP(hipGetLastError());
+      return RTE_OK;
+    }
+    return smooth(l, coarse_sweeps, false, act, s);
+  }
   RTE_TRY(smooth(l, nu_smooth, false, act, s));
   RTE_TRY(stencil(l, 1, 0, L.b, L.x, L.r, act, s));
   MgLevel& C = lv[l + 1];

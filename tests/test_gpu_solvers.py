@@ -43,6 +43,28 @@ def test_dsa_apply_parity():
 
 
 @pytest.mark.gpu
+def test_dsa_apply_parity_symmetric_rules():
+    """Reflection-symmetric rules only (the structured multigrid path), on grids
+    that coarsen several times."""
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=5, nx=16, ny=8, quad=("cl", 8, 4, True), n_regions=3),
+             tiny_2d(seed=6, nx=12, ny=12, quad=("cl", 16, 4, True), n_regions=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(7)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z, iters = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=1e-14, inner_max=3000, restart=60)
+    for k, spec in enumerate(specs):
+        ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
+        assert rel(B.unpack(z)[k], ref) <= 1e-11, (k, rel(B.unpack(z)[k], ref), iters)
+    # one V-cycle is already a good approximation of the DSA correction
+    z1, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=0.0, inner_max=1, restart=0)
+    for k, spec in enumerate(specs):
+        ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
+        assert rel(B.unpack(z1)[k] - v[k], ref - v[k]) <= 0.5
+
+
+@pytest.mark.gpu
 def test_dsa_apply_parity_1d():
     import paper_2410_08735_amd as rt
     specs = [tiny_1d(seed=1, nx=12, n_ord=8), tiny_1d(seed=2, nx=7, n_ord=2)]
