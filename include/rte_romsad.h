@@ -56,7 +56,7 @@ enum {
   RTE_WNOTCONV = 1      /* not converged within the iteration limits          */
 };
 
-enum { RTE_F64 = 0, RTE_F32 = 1 };
+enum { RTE_F64 = 0, RTE_F32 = 1, RTE_BF16 = 2 };
 
 enum { RTE_PC_NONE = 0, RTE_PC_DSA = 1, RTE_PC_ROMSAD = 2, RTE_PC_MLP = 3 };
 
@@ -237,6 +237,47 @@ int rte_rom_export(const rte_rom* rom, double* U, double* W1, double* Ww, double
 int rte_rom_save(const rte_rom* rom, const char* path);
 int rte_rom_load(const char* path, rte_rom** out);
 void rte_rom_destroy(rte_rom* rom);
+
+/* ---------------------------------------------------------------- learned preconditioner
+ * A GELU MLP (n_in -> width x depth -> n_out) mapping the normalised
+ * parameter and the normalised reduced residual coefficients g / ||g||,
+ * g = W_1^T Sigma_s v, to reduced correction coefficients c / ||g||; inside
+ * fgmres_solve (RTE_PC_MLP) the correction is z = v + W_w c for the first
+ * `window` iterations of a cycle.  Flexible GMRES admits any such nonlinear
+ * preconditioner (section 4.2).  Parameters are FP32, flat, per layer W [out][in]
+ * then b [out]; network outputs are y * scale + shift (output standardisation).
+ * dtype RTE_BF16: products on the matrix cores with bfloat16 operands and FP32
+ * accumulation; RTE_F32: FP32 arithmetic throughout.  All X, Y, T are device
+ * arrays of row-major FP32 rows.                                              */
+int rte_mlp_create(int n_in, int width, int depth, int n_out, rte_mlp** out);
+void rte_mlp_destroy(rte_mlp* m);
+int64_t rte_mlp_num_params(const rte_mlp* m);
+int rte_mlp_set_params(rte_mlp* m, const float* host_params, const float* host_scale,
+                       const float* host_shift);
+int rte_mlp_get_params(const rte_mlp* m, float* host_params, float* host_scale, float* host_shift);
+/* Y [rows][n_out] = network(X [rows][n_in]).                                   */
+int rte_mlp_forward(rte_mlp* m, const float* X, float* Y, int rows, int dtype, void* stream);
+/* Gradient (device [num_params]) and value (host, nullable) of the mean squared
+ * error between network(X) and T over all rows * n_out entries.              */
+int rte_mlp_grad(rte_mlp* m, const float* X, const float* T, int rows, int dtype, float* loss,
+                 float* grad, void* stream);
+/* Adam (lr, 0.9, 0.999, 1e-8) on BF16-matrix-core gradients for `epochs` passes over
+ * n rows in shuffled minibatches (SplitMix64-seeded Fisher-Yates).  standardize != 0
+ * first sets the output shift/scale to T's column mean and standard deviation.
+ * loss_hist (host [epochs], nullable) receives the mean minibatch loss.      */
+int rte_mlp_train(rte_mlp* m, const float* X, const float* T, int n, int epochs, int batch,
+                  float lr, uint64_t seed, int standardize, float* loss_hist, void* stream);
+/* Training data from FGMRES runs (section 4.4.1): solve every instance with
+ * `opts`, recover xi^(l) = A~^{-1} v^(l), l < window, from the first cycle (the
+ * xi recurrence), and emit rows X = [mu, g/||g||] with g = W_1^T Sigma_s v^(l) and
+ * targets T = c_opt / ||g||, c_opt the least-squares coefficients of
+ * xi^(l) - v^(l) (the ideal scalar-flux correction) in span(W_w).  mu: device [n_inst][mu_dim]
+ * (FP64, already normalised).  X: [n_inst*window][mu_dim + r], T:
+ * [n_inst*window][r], valid: device int32 [n_inst*window] (row usable).     */
+int rte_mlp_snapshots(const rte_batch* b, const double* sigma_t, const double* sigma_s,
+                      const double* G, const double* inflow, const rte_rom* rom,
+                      const rte_solve_opts* opts, const double* mu, int mu_dim, float* X,
+                      float* T, int32_t* valid, void* stream);
 
 /* ---------------------------------------------------------------- profiling
  * HIP-event timing of the library's hot kernels for benchmarking.

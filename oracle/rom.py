@@ -188,3 +188,22 @@ def greedy(train_specs, window=2, mu1_index=0, eps_rom=1e-9, n_giter=16, eps_qr=
         k += 1
     rep.sampled = sampled
     return U, rep
+
+
+# ---- training rows of the learned correction (no paper passage) -----------------
+
+def learned_correction_rows(P, U, first_cycle, phi, window, mu_feat):
+    """Rows (x, t) for l < window: x = [mu_feat, g / ||g||], g = W_1^T Sigma_s v^(l);
+    t = c / ||g|| with c the least-squares coefficients of xi^(l) - v^(l) (the ideal
+    scalar flux correction, from the density relation) in span(W_w)."""
+    xis = xi_recurrence(first_cycle, phi, window)
+    w1, ww = W1(U), Ww(P, U)
+    X, T = [], []
+    for l, xi in enumerate(xis):
+        v = first_cycle["V"][l]
+        g = w1 @ (P.Ss @ v)
+        c, *_ = np.linalg.lstsq(ww.T, xi - v, rcond=None)
+        nrm = np.linalg.norm(g)
+        X.append(np.concatenate([mu_feat, g / nrm]))
+        T.append(c / nrm)
+    return np.array(X), np.array(T)

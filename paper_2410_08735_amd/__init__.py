@@ -10,11 +10,12 @@ import ctypes as C
 import numpy as np
 
 from . import _lib as L
-from ._lib import (RTE_F32, RTE_F64, RTE_PC_DSA, RTE_PC_MLP, RTE_PC_NONE, RTE_PC_ROMSAD,  # noqa: F401
-                   RteError, check)
+from ._lib import (RTE_BF16, RTE_F32, RTE_F64, RTE_PC_DSA, RTE_PC_MLP, RTE_PC_NONE,  # noqa: F401
+                   RTE_PC_ROMSAD, RteError, check)
 
 __all__ = ["Batch", "quadrature", "sweep", "scalar_flux", "apply_A", "rhs", "dsa_apply",
-           "fgmres_solve", "SolveOptions", "Rom", "romsad_build_greedy", "romsad_apply"]
+           "fgmres_solve", "SolveOptions", "Rom", "romsad_build_greedy", "romsad_apply", "Mlp",
+           "mlp_snapshots"]
 
 
 def _torch():
@@ -32,7 +33,8 @@ def _stream():
 
 
 def _dt(dtype):
-    return {"f64": RTE_F64, "f32": RTE_F32, RTE_F64: RTE_F64, RTE_F32: RTE_F32}[dtype]
+    return {"f64": RTE_F64, "f32": RTE_F32, "bf16": RTE_BF16, RTE_F64: RTE_F64, RTE_F32: RTE_F32,
+            RTE_BF16: RTE_BF16}[dtype]
 
 
 def quadrature(spec):
@@ -289,3 +291,76 @@ def prof_read(slot):
     s = PROF_SLOTS[slot] if isinstance(slot, str) else slot
     check(L.lib().rte_prof_read(s, C.byref(n), C.byref(ms), C.byref(u)), "rte_prof_read")
     return n.value, ms.value, u.value
+
+
+class Mlp:
+    """GELU MLP handle (n_in -> width x depth -> n_out) living on the device."""
+
+    def __init__(self, n_in, width=256, depth=4, n_out=32):
+        h = C.c_void_p()
+        check(L.lib().rte_mlp_create(n_in, width, depth, n_out, C.byref(h)), "rte_mlp_create")
+        self.h = h
+        self.n_in, self.width, self.depth, self.n_out = n_in, width, depth, n_out
+        self.nparams = L.lib().rte_mlp_num_params(h)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                L.lib().rte_mlp_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_params(self, flat, scale=None, shift=None):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.nparams
+        sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float32)
+        sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float32)
+        check(L.lib().rte_mlp_set_params(self.h, flat.ctypes.data, None if sc is None else sc.ctypes.data,
+                                         None if sh is None else sh.ctypes.data), "rte_mlp_set_params")
+
+    def get_params(self):
+        p = np.zeros(self.nparams, dtype=np.float32)
+        sc = np.zeros(self.n_out, dtype=np.float32)
+        sh = np.zeros(self.n_out, dtype=np.float32)
+        check(L.lib().rte_mlp_get_params(self.h, p.ctypes.data, sc.ctypes.data, sh.ctypes.data),
+              "rte_mlp_get_params")
+        return p, sc, sh
+
+    def forward(self, X, dtype="bf16"):
+        torch = _torch()
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        check(L.lib().rte_mlp_forward(self.h, _ptr(X.contiguous()), _ptr(Y), int(X.shape[0]), _dt(dtype),
+                                      _stream()), "rte_mlp_forward")
+        return Y
+
+    def grad(self, X, T, dtype="bf16"):
+        torch = _torch()
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        loss = C.c_float()
+        check(L.lib().rte_mlp_grad(self.h, _ptr(X.contiguous()), _ptr(T.contiguous()), int(X.shape[0]),
+                                   _dt(dtype), C.byref(loss), _ptr(g), _stream()), "rte_mlp_grad")
+        return loss.value, g
+
+    def train(self, X, T, epochs=50, batch=256, lr=1e-3, seed=0, standardize=True):
+        hist = np.zeros(epochs, dtype=np.float32)
+        check(L.lib().rte_mlp_train(self.h, _ptr(X.contiguous()), _ptr(T.contiguous()), int(X.shape[0]),
+                                    epochs, batch, lr, seed, 1 if standardize else 0, hist.ctypes.data,
+                                    _stream()), "rte_mlp_train")
+        return hist
+
+
+def mlp_snapshots(batch, sigma_t, sigma_s, G, rom, opts, mu, inflow=None):
+    """(X, T, valid) training rows from FGMRES runs on every instance of batch."""
+    torch = _torch()
+    w = opts.window
+    r = rom.rank
+    mu_dim = int(mu.shape[1])
+    X = torch.zeros((batch.n * w, mu_dim + r), dtype=torch.float32, device="cuda")
+    T = torch.zeros((batch.n * w, r), dtype=torch.float32, device="cuda")
+    valid = torch.zeros(batch.n * w, dtype=torch.int32, device="cuda")
+    co = opts.c()
+    check(L.lib().rte_mlp_snapshots(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow), rom.h,
+                                    C.byref(co), _ptr(mu.contiguous()), mu_dim, _ptr(X), _ptr(T), _ptr(valid),
+                                    _stream()), "rte_mlp_snapshots")
+    return X, T, valid

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "librte_romsad.so")
 
 RTE_OK, RTE_EINVAL, RTE_EHIP, RTE_ENOMEM, RTE_EBREAKDOWN, RTE_ESINGULAR, RTE_EIO = 0, -1, -2, -3, -4, -5, -6
 RTE_WNOTCONV = 1
-RTE_F64, RTE_F32 = 0, 1
+RTE_F64, RTE_F32, RTE_BF16 = 0, 1, 2
 RTE_PC_NONE, RTE_PC_DSA, RTE_PC_ROMSAD, RTE_PC_MLP = 0, 1, 2, 3
 
 vp = C.c_void_p
@@ -76,6 +76,17 @@ SIGNATURES = {
     "rte_rom_save": (C.c_int, [vp, C.c_char_p]),
     "rte_rom_load": (C.c_int, [C.c_char_p, C.POINTER(vp)]),
     "rte_rom_destroy": (None, [vp]),
+    "rte_mlp_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+    "rte_mlp_destroy": (None, [vp]),
+    "rte_mlp_num_params": (i64, [vp]),
+    "rte_mlp_set_params": (C.c_int, [vp, vp, vp, vp]),
+    "rte_mlp_get_params": (C.c_int, [vp, vp, vp, vp]),
+    "rte_mlp_forward": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
+    "rte_mlp_grad": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.POINTER(C.c_float), vp, vp]),
+    "rte_mlp_train": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, C.c_uint64, C.c_int,
+                                vp, vp]),
+    "rte_mlp_snapshots": (C.c_int, [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.c_int, vp, vp, vp,
+                                    vp]),
     "rte_prof_enable": (C.c_int, [C.c_int]),
     "rte_prof_read": (C.c_int, [C.c_int, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
 }

@@ -20,9 +20,9 @@ struct Fgmres {
   int m = 0;
   Krylov K;
   double *btil = nullptr, *r = nullptr, *bnorm = nullptr, *tolabs = nullptr, *rnorm = nullptr;
-  int32_t *cyc = nullptr, *flags = nullptr;
+  int32_t *cyc = nullptr, *cyc_step = nullptr, *flags = nullptr;
   // record of cycle 0 (xi recurrence): Z_0..Z_{w-1}, H block [(w+1) x w], beta
-  double *recZ = nullptr, *recH = nullptr, *recBeta = nullptr;
+  double *recZ = nullptr, *recH = nullptr, *recBeta = nullptr, *recV = nullptr;
   int rec_w = 0;
   bool dsa_ready = false;
   std::vector<int32_t> rec_jdone;

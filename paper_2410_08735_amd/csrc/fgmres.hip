@@ -21,6 +21,7 @@ int Fgmres::init(rte_batch* batch, int m_) {
       hipMalloc(&tolabs, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&rnorm, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&cyc, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&cyc_step, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&flags, sizeof(int32_t) * n) != hipSuccess)
     return RTE_ENOMEM;
   return RTE_OK;
@@ -29,10 +30,10 @@ int Fgmres::init(rte_batch* batch, int m_) {
 void Fgmres::release() {
   K.release();
   for (void* p : {(void*)btil, (void*)r, (void*)bnorm, (void*)tolabs, (void*)rnorm, (void*)cyc,
-                  (void*)flags})
+                  (void*)cyc_step, (void*)flags})
     (void)hipFree(p);
   btil = r = bnorm = tolabs = rnorm = nullptr;
-  cyc = flags = nullptr;
+  cyc = cyc_step = flags = nullptr;
   rec_release();
 }
 
@@ -40,7 +41,8 @@ void Fgmres::rec_release() {
   (void)hipFree(recZ);
   (void)hipFree(recH);
   (void)hipFree(recBeta);
-  recZ = recH = recBeta = nullptr;
+  (void)hipFree(recV);
+  recZ = recH = recBeta = recV = nullptr;
   rec_w = 0;
 }
 
@@ -57,6 +59,16 @@ __global__ void k_copy_h(int n, const double* __restrict__ H, int m, double* __r
     for (int j = 0; j < w; ++j)
       out[((int64_t)b * (w + 1) + i) * w + j] = (j < m && i <= m) ? H[(int64_t)b * (m + 1) * m + (int64_t)i * m + j] : 0.0;
   beta[b] = scal[b * 8 + 0];
+}
+
+// The learned correction stalls when a step reduces the Givens estimate by
+// less than half; that instance then uses ROMSAD for the rest of the window.
+__global__ void k_stall_check(int n, const double* __restrict__ scal, const int32_t* __restrict__ was_active,
+                              int32_t* __restrict__ off) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || !was_active[b] || off[b]) return;
+  const double prev = scal[b * 8 + 5], est = scal[b * 8 + 2];
+  if (prev > 0.0 && est > 0.5 * prev) off[b] = 1;
 }
 
 int Fgmres::precondition(int jj, const double* v, double* z, const SolveCtx& c, hipStream_t s,
@@ -80,7 +92,6 @@ int Fgmres::precondition(int jj, const double* v, double* z, const SolveCtx& c, 
       return st == RTE_ESINGULAR ? RTE_OK : st;
     }
     case RTE_PC_MLP: {
-      RTE_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * b->n_inst, s));
       RTE_TRY(mlp_precond(c.mlp, c.rom, b, c.sigma_t, c.sigma_s, c.mu, c.mu_dim, v, z, K.active, s,
                           flags));
       std::vector<int32_t> fb(b->n_inst);
@@ -143,6 +154,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     // FP32 sweeps cannot reduce the residual much below ~1e-6 of its value at
     // the start of a cycle; the FP64 true residual then restarts the cycle.
     RTE_TRY(kstart(K, r, tolabs, s, pin ? 1e-6 : 0.0));
+    RTE_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * n, s));  // learned correction on
     act = cm;
     for (int q = 0; q < n; ++q) stats[q].cycles += cm[q];
     for (int j = 0; j < m; ++j) {
@@ -158,6 +170,11 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
                            K.active, batch_cell_ordinates(b, act.data())));
       RTE_TRY(reduce_partials(b, pin, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active));
       RTE_TRY(arnoldi_mgs(K, j, s));
+      if (o.precond == RTE_PC_MLP && j + 1 <= o.window) {
+        RTE_HIP(hipMemcpyAsync(cyc_step, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_stall_check, dim3((n + 63) / 64), dim3(64), 0, s, n, K.scal, cyc_step, flags);
+        RTE_HIP(hipGetLastError());
+      }
       for (int q = 0; q < n; ++q) {
         if (!act[q]) continue;
         stats[q].iterations += 1;
@@ -174,10 +191,13 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       rec_release();
       rec_w = std::min(c.keep, m);
       if (hipMalloc(&recZ, sizeof(double) * rec_w * b->total_dof) != hipSuccess ||
+          hipMalloc(&recV, sizeof(double) * rec_w * b->total_dof) != hipSuccess ||
           hipMalloc(&recH, sizeof(double) * n * (rec_w + 1) * rec_w) != hipSuccess ||
           hipMalloc(&recBeta, sizeof(double) * n) != hipSuccess)
         return RTE_ENOMEM;
       RTE_HIP(hipMemcpyAsync(recZ, K.Z, sizeof(double) * rec_w * b->total_dof,
+                             hipMemcpyDeviceToDevice, s));
+      RTE_HIP(hipMemcpyAsync(recV, K.V, sizeof(double) * rec_w * b->total_dof,
                              hipMemcpyDeviceToDevice, s));
       hipLaunchKernelGGL(k_copy_h, dim3((n + 63) / 64), dim3(64), 0, s, n, K.H, m, recH, rec_w,
                          K.scal, recBeta);

@@ -216,6 +216,7 @@ __global__ void k_givens(int n, const double* __restrict__ H, double* __restrict
   gb[j] = cj * gj;
   gb[j + 1] = -sj * gj;
   const double est = fabs(gb[j + 1]);
+  scal[b * 8 + 5] = scal[b * 8 + 2];  // previous estimate
   scal[b * 8 + 2] = est;
   jdone[b] = j + 1;
   const bool breakdown = Hb[(j + 1) * m + j] <= 1e-14 * sqrt(colsq);

@@ -42,9 +42,9 @@ bool rom_matches(const rte_rom* rom, const rte_batch* b);
 // z = v + W_w c for given coefficients c [n][rcap] (no solve)
 int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c, double* z,
              const int32_t* active, hipStream_t s);
-// g = W_1^T Sigma_s v  ([n][rcap])
+// g = W^T Sigma_s v  ([n][ROM_GSTRIDE]); W = W_1 when null, Sigma_s = I when null
 int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const double* v,
-                double* g, const int32_t* active, hipStream_t s);
+                double* g, const int32_t* active, hipStream_t s, const double* W = nullptr);
 void rom_scratch_forget(const rte_batch* b);
 constexpr int ROM_GSTRIDE = 64;  // stride of per-instance reduced vectors g, c
 

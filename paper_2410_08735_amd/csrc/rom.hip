@@ -588,14 +588,14 @@ bool rom_matches(const rte_rom* rom, const rte_batch* b) {
 }
 
 int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const double* v, double* g,
-                const int32_t* active, hipStream_t s) {
+                const int32_t* active, hipStream_t s, const double* W) {
   const int r = rom->r;
   const int64_t nd = rom->ndof;
   const int nch = (int)((nd + PJ_CHUNK - 1) / PJ_CHUNK);
   RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * std::max(r, 1));
   if (!sc) return RTE_ENOMEM;
   hipLaunchKernelGGL(k_rom_project, dim3(nch, b->n_inst), dim3(256), 0, s, b->d_inst, b->d_region,
-                     sigma_s, b->max_regions, rom->W1, r, nd, v, sc->part, nch, active);
+                     sigma_s, b->max_regions, W ? W : rom->W1, r, nd, v, sc->part, nch, active);
   hipLaunchKernelGGL(k_rom_gsum, dim3((b->n_inst * r + 63) / 64), dim3(64), 0, s, b->n_inst, r, nch,
                      ROM_RMAX, sc->part, g, active);
   RTE_HIP(hipGetLastError());

@@ -129,5 +129,6 @@ int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const 
 void dsa_forget(rte_batch* b);
 void fgmres_forget(rte_batch* b);
 void rom_scratch_forget(const rte_batch* b);
+void mlp_scratch_forget(const rte_batch* b);
 
 }  // namespace rte

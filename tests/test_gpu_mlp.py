@@ -1,0 +1,164 @@
+"""The learned flexible preconditioner: network forward/backward against the
+FP64 oracle, training, snapshot rows against the oracle, and its use inside
+FGMRES with the ROMSAD fallback."""
+import numpy as np
+import pytest
+
+from oracle import dsa as odsa
+from oracle import fgmres as ofg
+from oracle import mlp as omlp
+from oracle import rom as orom
+from oracle import transport as tr
+from synth import tiny_2d
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32)
+
+
+def _params_f64(params):
+    return [[W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)]
+            for W, b in params]
+
+
+@pytest.mark.gpu
+def test_mlp_forward_and_gradient_parity():
+    import torch
+
+    import paper_2410_08735_amd as rt
+    rng = np.random.default_rng(0)
+    sizes = [36, 256, 256, 256, 256, 32]
+    params = omlp.init(sizes, rng)
+    for W, b in params:
+        b[:] = 0.1 * rng.standard_normal(b.shape)
+    p64 = _params_f64(params)
+    X = rng.standard_normal((70, 36)).astype(np.float32)   # 70 rows: ragged 16-row tiles
+    Y = rng.standard_normal((70, 32)).astype(np.float32)
+    m = rt.Mlp(36, 256, 4, 32)
+    assert m.nparams == 215072
+    m.set_params(_flat(params))
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    ref, cache = omlp.forward(p64, X.astype(np.float64))
+    out32 = m.forward(Xt, "f32").cpu().numpy()
+    out16 = m.forward(Xt, "bf16").cpu().numpy()
+    assert rel(out32, ref) <= 1e-5
+    assert rel(out16, ref) <= 3e-2
+    gref = omlp.backward(p64, cache, ref, Y.astype(np.float64))
+    loss32, g32 = m.grad(Xt, Yt, "f32")
+    loss16, g16 = m.grad(Xt, Yt, "bf16")
+    assert abs(loss32 - omlp.mse(ref, Y)) <= 1e-5 * omlp.mse(ref, Y)
+    gflat = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in gref])
+    assert rel(g32.cpu().numpy(), gflat) <= 1e-4
+    assert rel(g16.cpu().numpy(), gflat) <= 5e-2
+
+
+@pytest.mark.gpu
+def test_mlp_training_reduces_loss():
+    import torch
+
+    import paper_2410_08735_amd as rt
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((12, 8))
+    X = rng.uniform(-1, 1, (4096, 12)).astype(np.float32)
+    T = (np.sin(X @ A) * 5.0 + 2.0).astype(np.float32)
+    m = rt.Mlp(12, 64, 2, 8)
+    m.set_params(_flat(omlp.init([12, 64, 64, 8], rng)))
+    hist = m.train(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), epochs=40, batch=256, lr=2e-3)
+    assert hist[-1] < 0.1 * hist[0], hist
+    _, sc, sh = m.get_params()
+    np.testing.assert_allclose(sh, T.mean(0), rtol=1e-4, atol=1e-4)
+
+
+def _family(n=5, nx=5, ny=4, quad=("cl", 8, 4, True), seed=0):
+    specs = []
+    for k in range(n):
+        s = dict(tiny_2d(seed=seed, nx=nx, ny=ny, quad=quad))
+        s["sigma_s"] = s["sigma_s"] * (1 + 0.4 * k)
+        s["sigma_t"] = s["sigma_s"] + 0.3 + 0.05 * k
+        specs.append(s)
+    return specs
+
+
+@pytest.fixture(scope="module")
+def small_rom():
+    specs = _family(5)
+    U, rep = orom.greedy(specs, window=2, eps_rom=0.0, n_giter=2, rtol_hf=1e-11)
+    return specs, U
+
+
+@pytest.mark.gpu
+def test_snapshot_rows_match_oracle(small_rom):
+    import torch
+
+    import paper_2410_08735_amd as rt
+    specs, U = small_rom
+    tests = [dict(s, sigma_s=s["sigma_s"] * 1.15, sigma_t=s["sigma_t"] * 1.15) for s in specs[:3]]
+    B = rt.Batch(tests)
+    st, ss = B.sigma()
+    rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    mu = np.array([[0.1 * k, 0.2] for k in range(len(tests))])
+    opts = rt.SolveOptions(precond="romsad", m=30, max_cycles=4, sweep_dtype="f64", rtol=1e-12, window=2,
+                           dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    X, T, valid = rt.mlp_snapshots(B, st, ss, B.source(), rom, opts, torch.from_numpy(mu).cuda())
+    X, T, valid = X.cpu().numpy(), T.cpu().numpy(), valid.cpu().numpy()
+    for k, spec in enumerate(tests):
+        P = tr.Problem(spec)
+        R = orom.Romsad(P, U, odsa.DSA(P), 2)
+        res = ofg.fgmres(lambda x: tr.A_tilde_apply(P, x), tr.b_tilde(P), R, m=30, rtol=1e-12, keep_first=True)
+        xr, trow = orom.learned_correction_rows(P, U, res.first_cycle, res.x, 2, mu[k])
+        for l in range(xr.shape[0]):
+            row = 2 * k + l
+            assert valid[row] == 1
+            assert rel(X[row], xr[l]) <= 1e-5
+            # targets pass through FP32 rows and a least-squares solve
+            assert rel(T[row], trow[l]) <= 1e-4, (k, l, rel(T[row], trow[l]))
+
+
+def _first_step_ratio(spec, U, shift):
+    """Oracle: the Givens estimate ratio ||r_1|| / ||r_0|| after one FGMRES step
+    whose preconditioned vector is z = v + W_w (||g|| shift), g = W_1^T Sigma_s v."""
+    P = tr.Problem(spec)
+    b = tr.b_tilde(P)
+    v = b / np.linalg.norm(b)
+    g = orom.W1(U) @ (P.Ss @ v)
+    z = v + orom.Ww(P, U).T @ (np.linalg.norm(g) * shift)
+    w = tr.A_tilde_apply(P, z)
+    return np.linalg.norm(w - np.dot(w, v) * v) / np.linalg.norm(w)
+
+
+@pytest.mark.gpu
+def test_fgmres_mlp_falls_back_when_the_network_stalls(small_rom):
+    import torch
+
+    import paper_2410_08735_amd as rt
+    specs, U = small_rom
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    r = rom.rank
+    # a network with zero weights returns its output shift: pick (on the CPU, with
+    # the oracle) a shift whose correction barely reduces the first residual
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        shift = rng.standard_normal(r)
+        if min(_first_step_ratio(sp, U, shift) for sp in specs) > 0.8:
+            break
+    else:
+        pytest.fail("no stalling correction found")
+    m = rt.Mlp(2 + r, 32, 2, r)
+    m.set_params(np.zeros(m.nparams, np.float32), np.ones(r, np.float32), shift.astype(np.float32))
+    mu = torch.zeros((B.n, 2), dtype=torch.float64, device="cuda")
+    opts = rt.SolveOptions(precond="mlp", m=30, max_cycles=4, sweep_dtype="f64", rtol=1e-10, window=2,
+                           dsa_inner_max=1, dsa_restart=0)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts, rom=rom, mlp=m, mu=mu)
+    assert ret == 0
+    for s in stats:
+        assert s["pc_mlp"] == 1 and s["pc_fallback"] == 1 and s["pc_rom"] == 1, s
+    for k, spec in enumerate(specs):
+        P = tr.Problem(spec)
+        ref = np.linalg.solve(tr.dense_A_tilde(P), tr.b_tilde(P))
+        assert rel(B.unpack(phi)[k], ref) <= 1e-8
