@@ -59,6 +59,105 @@ def cpu_baseline(mus, procs):
                        f"iterations {its}")
 
 
+def _solve_timed(rt, torch, B, st, ss, G, opts, rom=None, mlp=None, mu=None, reps=1):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, stats, _ = rt.fgmres_solve(B, st, ss, G, None, opts, rom=rom, mlp=mlp, mu=mu)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    ok = sum(1 for s in stats if s["true_relres"] <= 1e-8)
+    return dt, ok, stats
+
+
+def learned_leg(args, common):
+    """The learned preconditioner on the 128^2 x 128 workload: a greedy ROM from
+    config-3-law training parameters, correction snapshots from FGMRES-ROMSAD
+    solves on fresh parameters, network training on the GPU, then FGMRES with
+    the network (ROMSAD fallback), FGMRES-ROMSAD and GMRES-DSA on fresh test
+    parameters, all on the same batch and GPU."""
+    import numpy as np
+    import torch
+
+    import paper_2410_08735_amd as rt
+    from synth import cfg3_box_centre, cfg3_features, cfg3_problem, cfg3_sigma, cfg3_sources, cfg5_sets
+    n, nb = args.mlp_grid, args.mlp_batch
+    tr_mu, sn_mu, te_mu = cfg5_sets(n_train=args.n_train, n_snap=args.mlp_snap, n_test=args.mlp_test)
+    out = {"grid": n, "snap_params": len(sn_mu), "test_params": len(te_mu)}
+
+    def inputs(mus):
+        st, ss = cfg3_sigma(mus)
+        G = cfg3_sources(mus, n)
+        f = cfg3_features(mus)
+        return (torch.from_numpy(st).cuda(), torch.from_numpy(ss).cuda(),
+                torch.from_numpy(G.reshape(-1)).cuda(), torch.from_numpy(f).cuda())
+
+    # offline 1: greedy ROM
+    base = cfg3_problem(cfg3_box_centre(), n=n)
+    Btr = rt.Batch([base] * len(tr_mu))
+    st, ss, G, _ = inputs(tr_mu)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rom, grep = rt.romsad_build_greedy(Btr, st, ss, G, None, window=2, mu1_index=0, eps_rom=1e-9,
+                                       n_giter=args.n_giter, eps_qr=1e-13, hf_rtol=1e-11)
+    torch.cuda.synchronize()
+    out["greedy_s"], out["rank"] = time.perf_counter() - t, grep["rank"]
+    del Btr
+    log(f"learned: ROM rank {grep['rank']} at {n}^2 in {out['greedy_s']:.1f} s")
+
+    # offline 2: snapshot rows from FGMRES-ROMSAD solves on fresh parameters
+    B = rt.Batch([base] * nb)
+    snap_opts = rt.SolveOptions(precond="romsad", **common)
+    Xs, Ts = [], []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for b0 in range(0, len(sn_mu) - nb + 1, nb):
+        st, ss, G, f = inputs(sn_mu[b0:b0 + nb])
+        X, T, valid = rt.mlp_snapshots(B, st, ss, G, rom, snap_opts, f)
+        keep = valid.bool()
+        Xs.append(X[keep])
+        Ts.append(T[keep])
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    torch.cuda.synchronize()
+    out["snapshots"], out["snapshot_s"] = int(X.shape[0]), time.perf_counter() - t
+    log(f"learned: {X.shape[0]} snapshot rows in {out['snapshot_s']:.1f} s")
+
+    # offline 3: training on the GPU (BF16 matrix cores, FP32 master weights, Adam)
+    r = rom.rank
+    net = rt.Mlp(4 + r, 256, 4, r)
+    net.init(seed=7)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    hist = net.train(X, T, epochs=args.mlp_epochs, batch=256, lr=args.mlp_lr, seed=11)
+    torch.cuda.synchronize()
+    out["train_s"], out["epochs"] = time.perf_counter() - t, args.mlp_epochs
+    out["loss_first_last"] = [float(hist[0]), float(hist[-1])]
+    log(f"learned: trained {args.mlp_epochs} epochs in {out['train_s']:.1f} s, loss {hist[0]:.3e} -> "
+        f"{hist[-1]:.3e}")
+
+    # online: the three preconditioners on the same fresh test batch
+    Bt = B if len(te_mu) == nb else rt.Batch([base] * len(te_mu))
+    st, ss, G, f = inputs(te_mu)
+    res = {}
+    for name, pc, kw in (("mlp", "mlp", dict(rom=rom, mlp=net, mu=f)), ("romsad", "romsad", dict(rom=rom)),
+                         ("plain_dsa", "dsa", {})):
+        opts = rt.SolveOptions(precond=pc, **common)
+        rt.fgmres_solve(Bt, st, ss, G, None, opts, **kw)  # warm-up (autotune, DSA hierarchy)
+        dt, ok, stats = _solve_timed(rt, torch, Bt, st, ss, G, opts, reps=args.steps, **kw)
+        its = np.array([s["iterations"] for s in stats])
+        rr = np.array([s["true_relres"] for s in stats])
+        res[name] = {"value": ok / dt, "unit": "solves/s", "ms_per_step": dt * 1e3, "converged": ok,
+                     "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+                     "max_true_relres": float(rr.max())}
+        if name == "mlp":
+            res[name]["fallbacks"] = int(sum(s["pc_fallback"] for s in stats))
+            res[name]["mlp_applies"] = int(sum(s["pc_mlp"] for s in stats))
+        log(f"learned: {name}: {ok / dt:.1f} solves/s, iterations mean {its.mean():.2f} max {its.max()}, "
+            f"converged {ok}/{len(stats)}")
+    out.update(res)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +169,14 @@ def main():
     ap.add_argument("--n-giter", type=int, default=16)
     ap.add_argument("--dsa-inner", type=int, default=1, help="V-cycles per DSA application")
     ap.add_argument("--dsa-restart", type=int, default=0, help="0 = stationary V-cycles")
+    ap.add_argument("--mlp-grid", type=int, default=128)
+    ap.add_argument("--mlp-batch", type=int, default=1024)
+    ap.add_argument("--mlp-snap", type=int, default=10240, help="snapshot parameters (2 rows each)")
+    ap.add_argument("--mlp-test", type=int, default=1024)
+    ap.add_argument("--mlp-epochs", type=int, default=60)
+    ap.add_argument("--mlp-lr", type=float, default=1e-3)
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--only-mlp", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
@@ -85,6 +192,11 @@ def main():
     from synth import cfg2, cfg3_problem, cfg3_train_test
 
     torch.cuda.set_device(0)
+    common = dict(m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8, window=2,
+                  dsa_inner_max=args.dsa_inner, dsa_restart=args.dsa_restart, dsa_inner_tol=1e-6)
+    if args.only_mlp:
+        print(json.dumps({"learned": learned_leg(args, common)}), flush=True)
+        return
     tr_mu, te_mu = cfg3_train_test(n_train=args.n_train, n_test=args.n_test)
     n = args.grid
 
@@ -107,8 +219,6 @@ def main():
     B = rt.Batch([cfg3_problem(m, n=n) for m in te_mu])
     st, ss = B.sigma()
     G = B.source()
-    common = dict(m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8, window=2,
-                  dsa_inner_max=args.dsa_inner, dsa_restart=args.dsa_restart, dsa_inner_tol=1e-6)
     opts = rt.SolveOptions(precond="romsad", **common)
     for _ in range(args.warmup):
         rt.fgmres_solve(B, st, ss, G, None, opts, rom=rom)
@@ -204,6 +314,11 @@ def main():
             gd[f"single64sq_{dt_name}"] = B2.ndofs[0] * B2.n_ords[0] / el / 1e9
         out["sweep_gdof_s"] = gd
         log(f"sweep GDoF/s: {gd}")
+
+    if not args.no_mlp:
+        del B, st, ss, G, phi
+        torch.cuda.empty_cache()
+        out["learned"] = learned_leg(args, common)
 
     if not args.no_cpu_baseline:
         procs = max(1, min(16, len(os.sched_getaffinity(0))))

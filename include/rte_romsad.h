@@ -251,6 +251,10 @@ void rte_rom_destroy(rte_rom* rom);
  * arrays of row-major FP32 rows.                                              */
 int rte_mlp_create(int n_in, int width, int depth, int n_out, rte_mlp** out);
 void rte_mlp_destroy(rte_mlp* m);
+/* Glorot-uniform weights from a SplitMix64 stream seeded by `seed`, zero biases,
+ * output scale 1 and shift 0, Adam moments cleared (a new network starts at
+ * zero and must be initialised or given parameters before training).  Blocking. */
+int rte_mlp_init(rte_mlp* m, uint64_t seed);
 int64_t rte_mlp_num_params(const rte_mlp* m);
 int rte_mlp_set_params(rte_mlp* m, const float* host_params, const float* host_scale,
                        const float* host_shift);

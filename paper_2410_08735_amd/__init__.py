@@ -311,6 +311,9 @@ class Mlp:
         except Exception:
             pass
 
+    def init(self, seed=0):
+        check(L.lib().rte_mlp_init(self.h, seed), "rte_mlp_init")
+
     def set_params(self, flat, scale=None, shift=None):
         flat = np.ascontiguousarray(flat, dtype=np.float32)
         assert flat.size == self.nparams

@@ -78,6 +78,7 @@ SIGNATURES = {
     "rte_rom_destroy": (None, [vp]),
     "rte_mlp_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
     "rte_mlp_destroy": (None, [vp]),
+    "rte_mlp_init": (C.c_int, [vp, C.c_uint64]),
     "rte_mlp_num_params": (i64, [vp]),
     "rte_mlp_set_params": (C.c_int, [vp, vp, vp, vp]),
     "rte_mlp_get_params": (C.c_int, [vp, vp, vp, vp]),

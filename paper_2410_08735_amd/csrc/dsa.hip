@@ -12,7 +12,9 @@
 //     + 3 sum_f [sum_e (a_ef DC^e - b_ef DJ^e / 2) + m_f st] dJ_f = ss v
 //   [sum_e (a_de DC^e - bm_de DJ^e / 2) + m_d (st - ss)] dphi
 //     + 3 sum_f [sum_e (t_def DC^e - c_def DJ^e / 2) + a_df st] dJ_f = m_d ss v.
-// Unknowns per cell (cell-major): [dphi(nloc), dJ_x(nloc) (, dJ_y(nloc))].
+// Unknowns per cell: [dphi(nloc), dJ_x(nloc) (, dJ_y(nloc))], stored unknown-major
+// per instance (unknown u of cell c at u * ncell + c) so that neighbouring
+// threads read neighbouring cells.
 //
 // D_C, D_J along one axis, orthonormal P1 basis on cells of width h (traces
 // R = (1, sqrt3)/sqrt h at the right end, L = (1, -sqrt3)/sqrt h at the left):
@@ -240,94 +242,6 @@ __global__ void k_dsa_blockinv(int n_inst, int max_regions, const InstDev* __res
     for (int j = 0; j < nu; ++j) o[i * nu + j] = A[i][nu + j];
 }
 
-// y = K x (matrix-free), one thread per cell.
-template <int NU>
-__global__ void k_dsa_apply(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
-                            const int32_t* __restrict__ region, const double* __restrict__ sigma_t,
-                            const double* __restrict__ sigma_s, int max_regions,
-                            const int64_t* __restrict__ off, const double* __restrict__ x,
-                            double* __restrict__ y, const int32_t* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const InstDev I = insts[b];
-  __shared__ double blk[7 * NU * NU];
-  const DsaStencil& S = st_[b];
-  constexpr int nu = NU;
-  for (int q = threadIdx.x; q < nu * nu; q += blockDim.x) {
-    for (int z = 0; z < 5; ++z) blk[z * nu * nu + q] = S.blk[z][q];
-    blk[5 * nu * nu + q] = S.St[q];
-    blk[6 * nu * nu + q] = S.Ss[q];
-  }
-  __syncthreads();
-  const int ncell = I.nx * I.ny;
-  const double* xb = x + off[b];
-  double* yb = y + off[b];
-  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
-    const int i = cell % I.nx, k = cell / I.nx;
-    const int rg = region[I.region_off + cell];
-    const double ts = sigma_t[(int64_t)b * max_regions + rg];
-    const double ss = sigma_s[(int64_t)b * max_regions + rg];
-    double acc[NU];
-    double xc[NU];
-#pragma unroll
-    for (int r = 0; r < nu; ++r) xc[r] = xb[(int64_t)cell * nu + r];
-#pragma unroll
-    for (int r = 0; r < nu; ++r) {
-      double t = 0.0;
-#pragma unroll
-      for (int c = 0; c < nu; ++c)
-        t += (blk[r * nu + c] + ts * blk[5 * nu * nu + r * nu + c] + ss * blk[6 * nu * nu + r * nu + c]) * xc[c];
-      acc[r] = t;
-    }
-    const int nb[4] = {i > 0 ? cell - 1 : -1, i < I.nx - 1 ? cell + 1 : -1,
-                       k > 0 ? cell - I.nx : -1, k < I.ny - 1 ? cell + I.nx : -1};
-    for (int z = 0; z < 4; ++z) {
-      if (nb[z] < 0) continue;
-      const double* xn = xb + (int64_t)nb[z] * nu;
-#pragma unroll
-      for (int c = 0; c < nu; ++c) xc[c] = xn[c];
-      const double* B = blk + (z + 1) * nu * nu;
-#pragma unroll
-      for (int r = 0; r < nu; ++r) {
-        double t = 0.0;
-#pragma unroll
-        for (int c = 0; c < nu; ++c) t += B[r * nu + c] * xc[c];
-        acc[r] += t;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < nu; ++r) yb[(int64_t)cell * nu + r] = acc[r];
-  }
-}
-
-// y = blockdiag(inv[region]) x
-template <int NU>
-__global__ void k_dsa_jacobi(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
-                             const int32_t* __restrict__ region, const double* __restrict__ inv,
-                             int max_regions, const int64_t* __restrict__ off,
-                             const double* __restrict__ x, double* __restrict__ y,
-                             const int32_t* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const InstDev I = insts[b];
-  constexpr int nu = NU;
-  const int ncell = I.nx * I.ny;
-  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
-    const int rg = region[I.region_off + cell];
-    const double* M = inv + ((int64_t)b * max_regions + rg) * DMAX * DMAX;
-    double xc[NU];
-#pragma unroll
-    for (int c = 0; c < nu; ++c) xc[c] = x[off[b] + (int64_t)cell * nu + c];
-#pragma unroll
-    for (int r = 0; r < nu; ++r) {
-      double t = 0.0;
-#pragma unroll
-      for (int c = 0; c < nu; ++c) t += M[r * nu + c] * xc[c];
-      y[off[b] + (int64_t)cell * nu + r] = t;
-    }
-  }
-}
-
 // rhs = [ss v, m_x ss v (, m_y ss v)] per cell
 __global__ void k_dsa_rhs(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
                           const int32_t* __restrict__ region, const double* __restrict__ sigma_s,
@@ -338,14 +252,14 @@ __global__ void k_dsa_rhs(const InstDev* __restrict__ insts, const DsaStencil* _
   if (active && !active[b]) return;
   const InstDev I = insts[b];
   const DsaStencil& S = st_[b];
-  const int nl = I.nloc, nu = S.nu;
+  const int nl = I.nloc;
   const int ncell = I.nx * I.ny;
   for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
     const double ss = sigma_s[(int64_t)b * max_regions + region[I.region_off + cell]];
     for (int l = 0; l < nl; ++l) {
       const double sv = ss * v[I.dof_off + (int64_t)cell * nl + l];
-      rhs[off[b] + (int64_t)cell * nu + l] = sv;
-      for (int d = 0; d < I.dim; ++d) rhs[off[b] + (int64_t)cell * nu + (1 + d) * nl + l] = S.m[d] * sv;
+      rhs[off[b] + (int64_t)l * ncell + cell] = sv;
+      for (int d = 0; d < I.dim; ++d) rhs[off[b] + (int64_t)((1 + d) * nl + l) * ncell + cell] = S.m[d] * sv;
     }
   }
 }
@@ -358,12 +272,12 @@ __global__ void k_dsa_out(const InstDev* __restrict__ insts, const DsaStencil* _
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const InstDev I = insts[b];
-  const int nl = I.nloc, nu = st_[b].nu;
-  const int64_t nd = (int64_t)I.nx * I.ny * nl;
+  const int nl = I.nloc;
+  const int64_t ncell = (int64_t)I.nx * I.ny, nd = ncell * nl;
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd;
        d += (int64_t)gridDim.x * blockDim.x) {
     const int64_t cell = d / nl, l = d % nl;
-    z[I.dof_off + d] = v[I.dof_off + d] + u[off[b] + cell * nu + l];
+    z[I.dof_off + d] = v[I.dof_off + d] + u[off[b] + l * ncell + cell];
   }
 }
 
@@ -475,7 +389,7 @@ __device__ __forceinline__ int lvl_inv_index(int per_cell, int64_t cell_global, 
 // mode 0: y = K x; mode 1: y = b - K x (residual);
 // mode 2 (color c): x_c += inv_c (b - K x)_c for cells with (i + k) % 2 == c.
 template <int NU>
-__global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li,
+__global__ void __launch_bounds__(256) k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li,
                              const DsaStencil* __restrict__ st_, const double* __restrict__ st,
                              const double* __restrict__ ss, const double* __restrict__ inv,
                              int per_cell_inv, const int32_t* __restrict__ region0,
@@ -502,7 +416,7 @@ __global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li
     const double t = st[L.cell_off + cell], u = ss[L.cell_off + cell];
     double acc[NU], xc[NU];
 #pragma unroll
-    for (int r = 0; r < NU; ++r) xc[r] = x[vo + (int64_t)cell * NU + r];
+    for (int r = 0; r < NU; ++r) xc[r] = x[vo + (int64_t)r * nc + cell];
 #pragma unroll
     for (int r = 0; r < NU; ++r) {
       double a = 0.0;
@@ -518,7 +432,7 @@ __global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li
       if (nb[z] < 0) continue;
       double xn[NU];
 #pragma unroll
-      for (int c = 0; c < NU; ++c) xn[c] = x[vo + (int64_t)nb[z] * NU + c];
+      for (int c = 0; c < NU; ++c) xn[c] = x[vo + (int64_t)c * nc + nb[z]];
       const double* B = blk + (z + 1) * NU * NU;
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
@@ -530,23 +444,23 @@ __global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li
     }
     if (mode == 0) {
 #pragma unroll
-      for (int r = 0; r < NU; ++r) y[vo + (int64_t)cell * NU + r] = acc[r];
+      for (int r = 0; r < NU; ++r) y[vo + (int64_t)r * nc + cell] = acc[r];
     } else if (mode == 1) {
 #pragma unroll
       for (int r = 0; r < NU; ++r)
-        y[vo + (int64_t)cell * NU + r] = bvec[vo + (int64_t)cell * NU + r] - acc[r];
+        y[vo + (int64_t)r * nc + cell] = bvec[vo + (int64_t)r * nc + cell] - acc[r];
     } else {
       const int rg = per_cell_inv ? 0 : region0[insts[b].region_off + cell];
       const double* M = inv + (int64_t)lvl_inv_index(per_cell_inv, L.cell_off + cell, b, max_regions, rg) * NU * NU;
       double res[NU];
 #pragma unroll
-      for (int r = 0; r < NU; ++r) res[r] = bvec[vo + (int64_t)cell * NU + r] - acc[r];
+      for (int r = 0; r < NU; ++r) res[r] = bvec[vo + (int64_t)r * nc + cell] - acc[r];
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
         double a = 0.0;
 #pragma unroll
         for (int c = 0; c < NU; ++c) a += M[r * NU + c] * res[c];
-        x[vo + (int64_t)cell * NU + r] = xc[r] + a;
+        x[vo + (int64_t)r * nc + cell] = xc[r] + a;
       }
     }
   }
@@ -558,15 +472,16 @@ __global__ void k_mg_stencil(int mode, int color, const LvlInst* __restrict__ li
 //   D_J: own -diag(2, 6)/h,          upper neighbour R L^T/h,    lower  L R^T/h,
 // so with P = R (L.x_up)/h and Q = L (R.x_lo)/h:
 //   D_C x = S_C x + (P - Q)/2,  D_J x = S_J x + P + Q.
-__device__ __forceinline__ void axis_cj(const double* Xc, const double* Xhi, const double* Xlo, int axis,
+// Absent neighbours are passed as zeros (no coupling across the boundary).
+__device__ __forceinline__ void axis_cj(const double Xc[4], const double Xhi[4], const double Xlo[4], int axis,
                                         double ih, double C[4], double J[4]) {
   const double r3 = 1.7320508075688772935;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int i0 = axis == 0 ? 2 * g : g;
     const int i1 = axis == 0 ? 2 * g + 1 : g + 2;
-    const double dl = Xhi ? (Xhi[i0] - r3 * Xhi[i1]) * ih : 0.0;
-    const double dr = Xlo ? (Xlo[i0] + r3 * Xlo[i1]) * ih : 0.0;
+    const double dl = (Xhi[i0] - r3 * Xhi[i1]) * ih;
+    const double dr = (Xlo[i0] + r3 * Xlo[i1]) * ih;
     C[i0] = r3 * ih * Xc[i1] + 0.5 * (dl - dr);
     C[i1] = -r3 * ih * Xc[i0] + 0.5 * r3 * (dl + dr);
     J[i0] = -2.0 * ih * Xc[i0] + dl + dr;
@@ -574,36 +489,84 @@ __device__ __forceinline__ void axis_cj(const double* Xc, const double* Xhi, con
   }
 }
 
-// y = K x for one cell (12 unknowns: phi, J_x, J_y), reflection-symmetric rule.
-__device__ __forceinline__ void sym_cell_apply(const DsaStencil& S, double st, double ss,
-                                               const double* xc, const double* xl, const double* xr,
-                                               const double* xb, const double* xt, double* y) {
-  const double ihx = 1.0 / S.hx, ihy = 1.0 / S.hy;
-  double Cx[4], Jx[4], Cy[4], Jy[4];
-  // phi row and the J rows' phi terms
-  axis_cj(xc, xr, xl, 0, ihx, Cx, Jx);
-  axis_cj(xc, xt, xb, 1, ihy, Cy, Jy);
+// The scalars of the structured form (one set per instance and level).
+struct SymCoef {
+  double ax, ay, bex, bey, cxx, cxy, cyx, cyy, ihx, ihy;
+};
+
+__device__ __forceinline__ SymCoef sym_coef(const DsaStencil& G) {
+  SymCoef c;
+  c.ax = G.ax; c.ay = G.ay; c.bex = G.bex; c.bey = G.bey;
+  c.cxx = G.cxx; c.cxy = G.cxy; c.cyx = G.cyx; c.cyy = G.cyy;
+  c.ihx = 1.0 / G.hx; c.ihy = 1.0 / G.hy;
+  return c;
+}
+
+// A cell of an instance's level grid and which neighbours it has.
+struct CellPos {
+  int cell, nx;
+  int64_t nc;
+  bool hl, hr, hb, ht;
+};
+
+__device__ __forceinline__ CellPos cell_pos(int i, int k, int nx, int ny) {
+  CellPos p;
+  p.cell = k * nx + i;
+  p.nx = nx;
+  p.nc = (int64_t)nx * ny;
+  p.hl = i > 0;
+  p.hr = i < nx - 1;
+  p.hb = k > 0;
+  p.ht = k < ny - 1;
+  return p;
+}
+
+// Field f (4 unknowns) of a cell and of its four neighbours (zeros where absent).
+__device__ __forceinline__ void load_field(const double* __restrict__ x, const CellPos& P, int f, double c[4],
+                                           double l[4], double r[4], double b[4], double t[4]) {
 #pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    y[l] = (st - ss) * xc[l] - S.bex * Jx[l] - S.bey * Jy[l];
-    y[4 + l] = S.ax * Cx[l] + 3.0 * S.ax * st * xc[4 + l];
-    y[8 + l] = S.ay * Cy[l] + 3.0 * S.ay * st * xc[8 + l];
+  for (int m = 0; m < 4; ++m) {
+    const double* q = x + (int64_t)(4 * f + m) * P.nc + P.cell;
+    c[m] = q[0];
+    l[m] = P.hl ? q[-1] : 0.0;
+    r[m] = P.hr ? q[1] : 0.0;
+    b[m] = P.hb ? q[-P.nx] : 0.0;
+    t[m] = P.ht ? q[P.nx] : 0.0;
   }
-  // J_x field: C_x(J_x) into the phi row, D_J^x, D_J^y into its own row
-  axis_cj(xc + 4, xr ? xr + 4 : nullptr, xl ? xl + 4 : nullptr, 0, ihx, Cx, Jx);
-  axis_cj(xc + 4, xt ? xt + 4 : nullptr, xb ? xb + 4 : nullptr, 1, ihy, Cy, Jy);
+}
+
+// y = K x for one cell (12 unknowns: phi, J_x, J_y), reflection-symmetric rule,
+// one field at a time to keep few values live.
+__device__ __forceinline__ void sym_cell_apply(const SymCoef& S, double st, double ss,
+                                               const double* __restrict__ x, const CellPos& P, double y[12]) {
+  double c[4], l[4], r[4], b[4], t[4], Cx[4], Jx[4], Cy[4], Jy[4];
+  // phi: its own row, and the J rows' D_C phi terms
+  load_field(x, P, 0, c, l, r, b, t);
+  axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
+  axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    y[l] += 3.0 * S.ax * Cx[l];
-    y[4 + l] -= 1.5 * (S.cxx * Jx[l] + S.cxy * Jy[l]);
+  for (int m = 0; m < 4; ++m) {
+    y[m] = (st - ss) * c[m] - S.bex * Jx[m] - S.bey * Jy[m];
+    y[4 + m] = S.ax * Cx[m];
+    y[8 + m] = S.ay * Cy[m];
   }
-  // J_y field
-  axis_cj(xc + 8, xr ? xr + 8 : nullptr, xl ? xl + 8 : nullptr, 0, ihx, Cx, Jx);
-  axis_cj(xc + 8, xt ? xt + 8 : nullptr, xb ? xb + 8 : nullptr, 1, ihy, Cy, Jy);
+  // J_x: D_C^x J_x into the phi row; sigma_t, D_J^x, D_J^y into its own row
+  load_field(x, P, 1, c, l, r, b, t);
+  axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
+  axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    y[l] += 3.0 * S.ay * Cy[l];
-    y[8 + l] -= 1.5 * (S.cyx * Jx[l] + S.cyy * Jy[l]);
+  for (int m = 0; m < 4; ++m) {
+    y[m] += 3.0 * S.ax * Cx[m];
+    y[4 + m] += 3.0 * S.ax * st * c[m] - 1.5 * (S.cxx * Jx[m] + S.cxy * Jy[m]);
+  }
+  // J_y likewise
+  load_field(x, P, 2, c, l, r, b, t);
+  axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
+  axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    y[m] += 3.0 * S.ay * Cy[m];
+    y[8 + m] += 3.0 * S.ay * st * c[m] - 1.5 * (S.cyx * Jx[m] + S.cyy * Jy[m]);
   }
 }
 
@@ -614,15 +577,14 @@ __device__ __forceinline__ void sym_cell_apply(const DsaStencil& S, double st, d
 // S dJ^{-1} S is diagonal:
 //   (Dphi + 3 a_xx^2 s_x^2 / dJx[1-p, q] + 3 a_yy^2 s_y^2 / dJy[p, 1-q]) phi
 //       = r_phi - 3 a_xx S_x dJx^{-1} r_Jx - 3 a_yy S_y dJy^{-1} r_Jy.
-__device__ __forceinline__ void sym_block_solve(const DsaStencil& S, double st, double ss,
-                                                const double* r, double* out) {
-  const double ihx = 1.0 / S.hx, ihy = 1.0 / S.hy;
-  const double sx = 1.7320508075688772935 * ihx, sy = 1.7320508075688772935 * ihy;
+__device__ __forceinline__ void sym_block_solve(const SymCoef& S, double st, double ss, const double r[12],
+                                                double out[12]) {
+  const double sx = 1.7320508075688772935 * S.ihx, sy = 1.7320508075688772935 * S.ihy;
   double dphi[4], djx[4], djy[4], tx[4], ty[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     const int p = l & 1, q = l >> 1;
-    const double gx = (p ? 6.0 : 2.0) * ihx, gy = (q ? 6.0 : 2.0) * ihy;
+    const double gx = (p ? 6.0 : 2.0) * S.ihx, gy = (q ? 6.0 : 2.0) * S.ihy;
     dphi[l] = (st - ss) + S.bex * gx + S.bey * gy;
     djx[l] = 3.0 * S.ax * st + 1.5 * (S.cxx * gx + S.cxy * gy);
     djy[l] = 3.0 * S.ay * st + 1.5 * (S.cyx * gx + S.cyy * gy);
@@ -635,13 +597,11 @@ __device__ __forceinline__ void sym_block_solve(const DsaStencil& S, double st, 
   rhs[1] = r[1] + 3.0 * S.ax * sx * tx[0] - 3.0 * S.ay * sy * ty[3];
   rhs[2] = r[2] - 3.0 * S.ax * sx * tx[3] + 3.0 * S.ay * sy * ty[0];
   rhs[3] = r[3] + 3.0 * S.ax * sx * tx[2] + 3.0 * S.ay * sy * ty[1];
-  const int fx[4] = {1, 0, 3, 2}, fy[4] = {2, 3, 0, 1};  // (1-p, q) and (p, 1-q)
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const double schur = dphi[l] + 3.0 * S.ax * S.ax * sx * sx / djx[fx[l]] +
-                         3.0 * S.ay * S.ay * sy * sy / djy[fy[l]];
-    out[l] = rhs[l] / schur;
-  }
+  const double kx = 3.0 * S.ax * S.ax * sx * sx, ky = 3.0 * S.ay * S.ay * sy * sy;
+  out[0] = rhs[0] / (dphi[0] + kx / djx[1] + ky / djy[2]);  // (1-p, q) and (p, 1-q) partners
+  out[1] = rhs[1] / (dphi[1] + kx / djx[0] + ky / djy[3]);
+  out[2] = rhs[2] / (dphi[2] + kx / djx[3] + ky / djy[0]);
+  out[3] = rhs[3] / (dphi[3] + kx / djx[2] + ky / djy[1]);
   // J = dJ^{-1} (r_J - a S phi)
   out[4] = (r[4] - S.ax * sx * out[1]) / djx[0];
   out[5] = (r[5] + S.ax * sx * out[0]) / djx[1];
@@ -653,96 +613,103 @@ __device__ __forceinline__ void sym_block_solve(const DsaStencil& S, double st, 
   out[11] = (r[11] + S.ay * sy * out[1]) / djy[3];
 }
 
-__device__ __forceinline__ void sym_cell_op(int mode, const LvlInst& L, const DsaStencil& S, int cell,
-                                            double st, double ss, const double* __restrict__ inv,
-                                            const double* __restrict__ bvec, double* __restrict__ x,
-                                            double* __restrict__ yv, int64_t vo) {
-  const int i = cell % L.nx, k = cell / L.nx;
-  double xc[12], xl[12], xr[12], xb[12], xt[12], y[12];
-  const double* base = x + vo;
-#pragma unroll
-  for (int r = 0; r < 12; ++r) xc[r] = base[(int64_t)cell * 12 + r];
-  const bool hl = i > 0, hr = i < L.nx - 1, hb = k > 0, ht = k < L.ny - 1;
-#pragma unroll
-  for (int r = 0; r < 12; ++r) {
-    xl[r] = hl ? base[(int64_t)(cell - 1) * 12 + r] : 0.0;
-    xr[r] = hr ? base[(int64_t)(cell + 1) * 12 + r] : 0.0;
-    xb[r] = hb ? base[(int64_t)(cell - L.nx) * 12 + r] : 0.0;
-    xt[r] = ht ? base[(int64_t)(cell + L.nx) * 12 + r] : 0.0;
-  }
-  // absent neighbours contribute zero traces: passing zero vectors is exact
-  sym_cell_apply(S, st, ss, xc, xl, xr, xb, xt, y);
-  if (mode == 0) {
-#pragma unroll
-    for (int r = 0; r < 12; ++r) yv[vo + (int64_t)cell * 12 + r] = y[r];
-  } else if (mode == 1) {
-#pragma unroll
-    for (int r = 0; r < 12; ++r) yv[vo + (int64_t)cell * 12 + r] = bvec[vo + (int64_t)cell * 12 + r] - y[r];
-  } else {
-    double res[12], d[12];
-#pragma unroll
-    for (int r = 0; r < 12; ++r) res[r] = bvec[vo + (int64_t)cell * 12 + r] - y[r];
-    sym_block_solve(S, st, ss, res, d);
-#pragma unroll
-    for (int r = 0; r < 12; ++r) x[vo + (int64_t)cell * 12 + r] = xc[r] + d[r];
-  }
+// Red-black index: work item t of colour `color` -> (i, k), for even nx
+// (nx / 2 cells of each colour per row).
+__device__ __forceinline__ void rb_cell(int t, int nx, int color, int& i, int& k) {
+  const int h = nx >> 1;
+  k = t / h;
+  i = 2 * (t - k * h) + ((k + color) & 1);
 }
 
-__global__ void k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
+// mode 0: y = K x; mode 1: y = b - K x;
+// mode 2 (colour c): x_c += D_c^{-1} (b - K x)_c on cells with (i + k) % 2 == c;
+// mode 3: the first colour-0 half sweep from x = 0 (x = D^{-1} b on colour 0,
+//         x = 0 on colour 1), reading no x.
+__global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
                                  const DsaStencil* __restrict__ st_, const double* __restrict__ st,
-                                 const double* __restrict__ ss, const double* __restrict__ inv,
-                                 int per_cell_inv, const int32_t* __restrict__ region0,
-                                 const InstDev* __restrict__ insts, int max_regions,
-                                 const double* __restrict__ bvec, double* __restrict__ x,
-                                 double* __restrict__ y, const int32_t* __restrict__ active) {
+                                 const double* __restrict__ ss, const double* __restrict__ bvec,
+                                 double* __restrict__ x, double* __restrict__ y,
+                                 const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const LvlInst L = li[b];
-  __shared__ DsaStencil Sh;
-  if (threadIdx.x == 0) {
-    // only the scalars of the structured form are used here
-    const DsaStencil& G = st_[b];
-    Sh.ax = G.ax; Sh.ay = G.ay; Sh.bex = G.bex; Sh.bey = G.bey; Sh.cxx = G.cxx; Sh.cxy = G.cxy;
-    Sh.cyx = G.cyx; Sh.cyy = G.cyy; Sh.hx = G.hx; Sh.hy = G.hy;
-  }
-  __syncthreads();
-  const int nc = L.nx * L.ny;
+  const SymCoef S = sym_coef(st_[b]);
+  const int nx = L.nx, ny = L.ny, nc = nx * ny;
   const int64_t vo = L.cell_off * 12;
-  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += gridDim.x * blockDim.x) {
-    const int i = cell % L.nx, k = cell / L.nx;
-    if (mode == 2 && ((i + k) & 1) != color) continue;
-    const double t = st[L.cell_off + cell], u = ss[L.cell_off + cell];
-    sym_cell_op(mode, L, Sh, cell, t, u, nullptr, bvec, x, y, vo);
+  const double* __restrict__ bb = bvec ? bvec + vo : nullptr;
+  double* __restrict__ xb = x + vo;
+  const bool compact = mode == 2 && (nx & 1) == 0;
+  const int nwork = compact ? nc / 2 : nc;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nwork; t += gridDim.x * blockDim.x) {
+    int i, k;
+    if (compact) {
+      rb_cell(t, nx, color, i, k);
+    } else {
+      i = t % nx;
+      k = t / nx;
+      if (mode == 2 && ((i + k) & 1) != color) continue;
+    }
+    const CellPos P = cell_pos(i, k, nx, ny);
+    const double tt = st[L.cell_off + P.cell], uu = ss[L.cell_off + P.cell];
+    if (mode == 3) {
+      double r[12], d[12];
+      const bool red = ((i + k) & 1) == 0;
+#pragma unroll
+      for (int q = 0; q < 12; ++q) r[q] = red ? bb[(int64_t)q * nc + P.cell] : 0.0;
+      if (red) sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = red ? d[q] : 0.0;
+      continue;
+    }
+    double yy[12];
+    sym_cell_apply(S, tt, uu, xb, P, yy);
+    if (mode == 0) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) y[vo + (int64_t)q * nc + P.cell] = yy[q];
+    } else if (mode == 1) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) y[vo + (int64_t)q * nc + P.cell] = bb[(int64_t)q * nc + P.cell] - yy[q];
+    } else {
+      double r[12], d[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + P.cell] - yy[q];
+      sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] += d[q];
+    }
   }
 }
 
 // Coarsest level: `sweeps` red-black Gauss-Seidel sweeps from x = 0 in one
 // launch, one work group per instance.
-__global__ void k_mg_coarse_sym(int sweeps, const LvlInst* __restrict__ li,
+__global__ void __launch_bounds__(256) k_mg_coarse_sym(int sweeps, const LvlInst* __restrict__ li,
                                 const DsaStencil* __restrict__ st_, const double* __restrict__ st,
-                                const double* __restrict__ ss, const double* __restrict__ inv,
-                                const double* __restrict__ bvec, double* __restrict__ x,
-                                const int32_t* __restrict__ active) {
+                                const double* __restrict__ ss, const double* __restrict__ bvec,
+                                double* __restrict__ x, const int32_t* __restrict__ active) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const LvlInst L = li[b];
-  __shared__ DsaStencil Sh;
-  if (threadIdx.x == 0) {
-    const DsaStencil& G = st_[b];
-    Sh.ax = G.ax; Sh.ay = G.ay; Sh.bex = G.bex; Sh.bey = G.bey; Sh.cxx = G.cxx; Sh.cxy = G.cxy;
-    Sh.cyx = G.cyx; Sh.cyy = G.cyy; Sh.hx = G.hx; Sh.hy = G.hy;
-  }
-  const int nc = L.nx * L.ny;
+  const SymCoef S = sym_coef(st_[b]);
+  const int nx = L.nx, ny = L.ny, nc = nx * ny;
   const int64_t vo = L.cell_off * 12;
-  for (int e = threadIdx.x; e < nc * 12; e += blockDim.x) x[vo + e] = 0.0;
+  const double* __restrict__ bb = bvec + vo;
+  double* __restrict__ xb = x + vo;
+  for (int e = threadIdx.x; e < nc * 12; e += blockDim.x) xb[e] = 0.0;
   __syncthreads();
   for (int sw = 0; sw < sweeps; ++sw)
     for (int color = 0; color < 2; ++color) {
       for (int cell = threadIdx.x; cell < nc; cell += blockDim.x) {
-        const int i = cell % L.nx, k = cell / L.nx;
+        const int i = cell % nx, k = cell / nx;
         if (((i + k) & 1) != color) continue;
-        sym_cell_op(2, L, Sh, cell, st[L.cell_off + cell], ss[L.cell_off + cell], nullptr, bvec, x,
-                    nullptr, vo);
+        const CellPos P = cell_pos(i, k, nx, ny);
+        const double tt = st[L.cell_off + cell], uu = ss[L.cell_off + cell];
+        double yy[12], r[12], d[12];
+        sym_cell_apply(S, tt, uu, xb, P, yy);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + cell] - yy[q];
+        sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + cell] += d[q];
       }
       __syncthreads();
     }
@@ -775,16 +742,16 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
     if (mode == 0)
       for (int r = 0; r < NU; ++r) acc[r] = 0.0;
     else
-      for (int r = 0; r < NU; ++r) acc[r] = coarse_in[(Cc.cell_off + c) * NU + r];
+      for (int r = 0; r < NU; ++r) acc[r] = coarse_in[Cc.cell_off * NU + (int64_t)r * nc + c];
     for (int dk = 0; dk < (F.dim == 2 ? 2 : 1); ++dk)
       for (int di = 0; di < 2; ++di) {
         const int f = (F.dim == 2 ? (2 * K + dk) * F.nx : 0) + 2 * I + di;
-        const int64_t fo = (F.cell_off + f) * NU;
+        const int64_t fo = F.cell_off * NU + f, nfc = (int64_t)F.nx * F.ny;
         for (int fld = 0; fld < nf; ++fld)
           for (int l = 0; l < nl; ++l) {      // child mode (p + 2q)
             const int p = l & 1, q = l >> 1;
             if (mode == 0) {
-              const double rv = fine_in[fo + fld * nl + l];
+              const double rv = fine_in[fo + (fld * nl + l) * nfc];
               for (int L2 = 0; L2 < nl; ++L2) {  // coarse mode
                 const int P = L2 & 1, Q = L2 >> 1;
                 const double w = inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0);
@@ -797,12 +764,55 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
                 const double w = inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0);
                 v += w * acc[fld * nl + L2];
               }
-              fine_out[fo + fld * nl + l] += v;
+              fine_out[fo + (fld * nl + l) * nfc] += v;
             }
           }
       }
     if (mode == 0)
-      for (int r = 0; r < NU; ++r) coarse_out[(Cc.cell_off + c) * NU + r] = acc[r];
+      for (int r = 0; r < NU; ++r) coarse_out[Cc.cell_off * NU + (int64_t)r * nc + c] = acc[r];
+  }
+}
+
+// Residual and restriction in one pass (reflection-symmetric rules): each
+// coarse cell forms b - K x on its 2 x 2 children and accumulates P_f^T of it.
+__global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
+                                     const DsaStencil* __restrict__ st_f, const double* __restrict__ st,
+                                     const double* __restrict__ ss, const double* __restrict__ bvec,
+                                     const double* __restrict__ x, double* __restrict__ coarse_b,
+                                     const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const LvlInst F = lf[b], Cc = lc[b];
+  const SymCoef S = sym_coef(st_f[b]);
+  const int nfx = F.nx, nfy = F.ny, nfc = nfx * nfy, ncc = Cc.nx * Cc.ny;
+  const int64_t vf = F.cell_off * 12;
+  const double* __restrict__ xb = x + vf;
+  const double* __restrict__ bb = bvec + vf;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc; c += gridDim.x * blockDim.x) {
+    const int I = c % Cc.nx, K = c / Cc.nx;
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+#pragma unroll 1
+    for (int ch = 0; ch < 4; ++ch) {  // children one at a time keeps few values live
+        const int di = ch & 1, dk = ch >> 1;
+        const int i = 2 * I + di, k = 2 * K + dk;
+        const CellPos P = cell_pos(i, k, nfx, nfy);
+        double yy[12];
+        sym_cell_apply(S, st[F.cell_off + P.cell], ss[F.cell_off + P.cell], xb, P, yy);
+#pragma unroll
+        for (int fld = 0; fld < 3; ++fld)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            const double rv = bb[(int64_t)(4 * fld + l) * nfc + P.cell] - yy[4 * fld + l];
+            const int p = l & 1, q = l >> 1;
+#pragma unroll
+            for (int L2 = 0; L2 < 4; ++L2)
+              acc[4 * fld + L2] += inj1d(di, p, L2 & 1) * inj1d(dk, q, L2 >> 1) * rv;
+          }
+      }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) coarse_b[Cc.cell_off * 12 + (int64_t)q * ncc + c] = acc[q];
   }
 }
 
@@ -833,8 +843,9 @@ struct DsaSolver {
   int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);
   int stencil(int l, int mode, int color, const double* bv, double* x, double* y, const int32_t* act,
               hipStream_t s);
-  int smooth(int l, int sweeps, bool reverse, const int32_t* act, hipStream_t s);
-  int vcycle(int l, const int32_t* act, hipStream_t s);
+  int smooth(int l, int sweeps, bool reverse, bool from_zero, const double* bv, double* x,
+             const int32_t* act, hipStream_t s);
+  int vcycle(int l, const double* bv, double* x, const int32_t* act, hipStream_t s);
   int precond(const double* in, double* out, const int32_t* act, hipStream_t s);
   int apply(const double* sigma_t, const double* sigma_s, const double* v, double* z, double inner_tol,
             int inner_max, const int32_t* active, int32_t* iters_host, bool prep, hipStream_t s);
@@ -981,7 +992,7 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
   const int per_cell = l == 0 ? 0 : 1;
   if (sym)
     hipLaunchKernelGGL(k_mg_stencil_sym, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
-                       L.ss, inv, per_cell, b->d_region, b->d_inst, b->max_regions, bv, x, y, act);
+                       L.ss, bv, x, y, act);
   else if (nu == 12)
     hipLaunchKernelGGL(k_mg_stencil<12>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, inv, per_cell, b->d_region, b->d_inst, b->max_regions, bv, x, y, act);
@@ -992,56 +1003,68 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
   return RTE_OK;
 }
 
-int DsaSolver::smooth(int l, int sweeps, bool reverse, const int32_t* act, hipStream_t s) {
+// `sweeps` red-black sweeps on x (colour 0 first, or colour 1 first if reverse);
+// from_zero: x holds no values yet and the first half sweep starts from zero.
+int DsaSolver::smooth(int l, int sweeps, bool reverse, bool from_zero, const double* bv, double* x,
+                      const int32_t* act, hipStream_t s) {
   for (int k = 0; k < sweeps; ++k) {
-    RTE_TRY(stencil(l, 2, reverse ? 1 : 0, lv[l].b, lv[l].x, nullptr, act, s));
-    RTE_TRY(stencil(l, 2, reverse ? 0 : 1, lv[l].b, lv[l].x, nullptr, act, s));
+    if (k == 0 && from_zero && sym && !reverse) {
+      RTE_TRY(stencil(l, 3, 0, bv, x, nullptr, act, s));
+    } else {
+      if (k == 0 && from_zero) RTE_HIP(hipMemsetAsync(x, 0, sizeof(double) * lv[l].ncell * nu, s));
+      RTE_TRY(stencil(l, 2, reverse ? 1 : 0, bv, x, nullptr, act, s));
+    }
+    RTE_TRY(stencil(l, 2, reverse ? 0 : 1, bv, x, nullptr, act, s));
   }
   return RTE_OK;
 }
 
-// x_l = V-cycle approximation of K_l^{-1} b_l (x_l starts at zero)
-int DsaSolver::vcycle(int l, const int32_t* act, hipStream_t s) {
+// x = V-cycle approximation of K_l^{-1} bv (bv and x must not alias)
+int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hipStream_t s) {
   MgLevel& L = lv[l];
-  RTE_HIP(hipMemsetAsync(L.x, 0, sizeof(double) * L.ncell * nu, s));
   if (l == (int)lv.size() - 1) {
     if (sym && l > 0) {  // whole coarsest smoothing in one launch
       hipLaunchKernelGGL(k_mg_coarse_sym, dim3(b->n_inst), dim3(256), 0, s, coarse_sweeps, L.d_li,
-                         L.d_st, L.st, L.ss, L.inv, L.b, L.x, act);
+                         L.d_st, L.st, L.ss, bv, x, act);
       RTE_HIP(hipGetLastError());
       return RTE_OK;
     }
-    return smooth(l, coarse_sweeps, false, act, s);
+    return smooth(l, coarse_sweeps, false, true, bv, x, act, s);
   }
-  RTE_TRY(smooth(l, nu_smooth, false, act, s));
-  RTE_TRY(stencil(l, 1, 0, L.b, L.x, L.r, act, s));
+  RTE_TRY(smooth(l, nu_smooth, false, true, bv, x, act, s));
   MgLevel& C = lv[l + 1];
   const dim3 g = grid(l + 1);
-  if (nu == 12)
-    hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
-                       (const double*)nullptr, C.b, act);
-  else
-    hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
-                       (const double*)nullptr, C.b, act);
+  if (sym) {
+    hipLaunchKernelGGL(k_mg_resrestrict_sym, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss, bv, x,
+                       C.b, act);
+  } else {
+    RTE_TRY(stencil(l, 1, 0, bv, x, L.r, act, s));
+    if (nu == 12)
+      hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
+                         (const double*)nullptr, C.b, act);
+    else
+      hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
+                         (const double*)nullptr, C.b, act);
+  }
   RTE_HIP(hipGetLastError());
-  RTE_TRY(vcycle(l + 1, act, s));
+  RTE_TRY(vcycle(l + 1, C.b, C.x, act, s));
   if (nu == 12)
     hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const double*)nullptr,
-                       L.x, C.x, (double*)nullptr, act);
+                       x, C.x, (double*)nullptr, act);
   else
     hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const double*)nullptr,
-                       L.x, C.x, (double*)nullptr, act);
+                       x, C.x, (double*)nullptr, act);
   RTE_HIP(hipGetLastError());
-  return smooth(l, nu_smooth, true, act, s);
+  return smooth(l, nu_smooth, true, false, bv, x, act, s);
 }
 
-// out = V-cycle(in) on level 0
+// out = V-cycle(in) on level 0 (in and out may alias)
 int DsaSolver::precond(const double* in, double* out, const int32_t* act, hipStream_t s) {
-  RTE_HIP(hipMemcpyAsync(lv[0].b, in, sizeof(double) * sp.total, hipMemcpyDeviceToDevice, s));
-  RTE_TRY(vcycle(0, act, s));
-  if (out != lv[0].x)
-    RTE_HIP(hipMemcpyAsync(out, lv[0].x, sizeof(double) * sp.total, hipMemcpyDeviceToDevice, s));
-  return RTE_OK;
+  if (in == out) {
+    RTE_HIP(hipMemcpyAsync(lv[0].b, in, sizeof(double) * sp.total, hipMemcpyDeviceToDevice, s));
+    in = lv[0].b;
+  }
+  return vcycle(0, in, out, act, s);
 }
 
 __global__ void k_scale_tol(int n, const double* __restrict__ rn, double rtol, double* __restrict__ tol) {
@@ -1066,7 +1089,7 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
         RTE_TRY(precond(rhs, X, active, s));
       } else {
         RTE_TRY(stencil(0, 1, 0, rhs, X, lv[0].b, active, s));
-        RTE_TRY(vcycle(0, active, s));
+        RTE_TRY(vcycle(0, lv[0].b, lv[0].x, active, s));
         RTE_TRY(kaxpby(sp, 1.0, lv[0].x, 1.0, X, active, s));
       }
     }

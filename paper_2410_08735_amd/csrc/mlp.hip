@@ -131,6 +131,18 @@ __global__ void k_mse_grad(int rows, int cols, const float* __restrict__ Y, cons
   if (threadIdx.x == 0) loss[blockIdx.x] = sh[0];
 }
 
+// acc[0] += scale * sum(parts[0..255]): the epoch's mean loss stays on the device
+__global__ void k_loss_acc(const float* __restrict__ parts, float* __restrict__ acc, float scale) {
+  __shared__ float sh[256];
+  sh[threadIdx.x] = parts[threadIdx.x];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += scale * sh[0];
+}
+
 __global__ void k_gelu_back(int64_t n, const float* __restrict__ Z, float* __restrict__ d) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     d[i] *= gelu_grad_f(Z[i]);
@@ -484,6 +496,30 @@ static uint64_t splitmix64(uint64_t& x) {
   return z ^ (z >> 31);
 }
 
+// Glorot-uniform weights U(-a, a), a = sqrt(6 / (fan_in + fan_out)), zero biases,
+// unit output scale, zero shift and a fresh Adam state.
+extern "C" int rte_mlp_init(rte_mlp* m, uint64_t seed) {
+  if (!m) return RTE_EINVAL;
+  std::vector<float> p(m->nparams, 0.f);
+  uint64_t st = seed;
+  for (size_t l = 0; l + 1 < m->dims.size(); ++l) {
+    const int fi = m->dims[l], fo = m->dims[l + 1];
+    const double a = std::sqrt(6.0 / (fi + fo));
+    for (int64_t e = 0; e < (int64_t)fi * fo; ++e) {
+      const double u = (double)(splitmix64(st) >> 11) * 0x1.0p-53;  // [0, 1)
+      p[m->woff[l] + e] = (float)((2.0 * u - 1.0) * a);
+    }
+  }
+  std::vector<float> one(m->n_out, 1.f), zero(m->n_out, 0.f);
+  RTE_HIP(hipMemcpy(m->P, p.data(), sizeof(float) * m->nparams, hipMemcpyHostToDevice));
+  RTE_HIP(hipMemset(m->M, 0, sizeof(float) * m->nparams));
+  RTE_HIP(hipMemset(m->V, 0, sizeof(float) * m->nparams));
+  RTE_HIP(hipMemcpy(m->yscale, one.data(), sizeof(float) * m->n_out, hipMemcpyHostToDevice));
+  RTE_HIP(hipMemcpy(m->yshift, zero.data(), sizeof(float) * m->n_out, hipMemcpyHostToDevice));
+  m->adam_t = 0;
+  return RTE_OK;
+}
+
 extern "C" int rte_mlp_train(rte_mlp* m, const float* X, const float* T, int n, int epochs, int batch, float lr,
                              uint64_t seed, int standardize, float* loss_hist, void* stream) {
   if (!m || !X || !T || n < 1 || epochs < 1 || batch < 1 || !(lr > 0.f)) return RTE_EINVAL;
@@ -494,28 +530,32 @@ extern "C" int rte_mlp_train(rte_mlp* m, const float* X, const float* T, int n, 
     hipLaunchKernelGGL(k_col_stats, dim3((m->n_out + 63) / 64), dim3(64), 0, s, n, m->n_out, T, m->yshift,
                        m->yscale);
   float* Tb = nullptr;
+  float* hist = nullptr;
   int32_t* idx = nullptr;
   if (hipMalloc(&Tb, sizeof(float) * (size_t)batch * m->n_out) != hipSuccess ||
-      hipMalloc(&idx, sizeof(int32_t) * n) != hipSuccess) {
+      hipMalloc(&idx, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&hist, sizeof(float) * epochs) != hipSuccess) {
     (void)hipFree(Tb);
+    (void)hipFree(idx);
     return RTE_ENOMEM;
   }
   std::vector<int32_t> perm(n);
   uint64_t st = seed;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  int status = RTE_OK;
+  const int nb = n / batch;
+  int status = hipMemsetAsync(hist, 0, sizeof(float) * epochs, s) == hipSuccess ? RTE_OK : RTE_EHIP;
   for (int ep = 0; ep < epochs && status == RTE_OK; ++ep) {
     for (int i = 0; i < n; ++i) perm[i] = i;
     for (int i = n - 1; i > 0; --i) {  // Fisher-Yates
       const int j = (int)(splitmix64(st) % (uint64_t)(i + 1));
       std::swap(perm[i], perm[j]);
     }
-    if (hipMemcpyAsync(idx, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess) {
+    // the permutation is pageable host memory: the copy completes before it returns
+    if (hipMemcpyAsync(idx, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
       status = RTE_EHIP;
       break;
     }
-    double ep_loss = 0.0;
-    int nb = 0;
     for (int b0 = 0; b0 + batch <= n; b0 += batch) {
       hipLaunchKernelGGL(k_gather_rows, dim3(256), dim3(256), 0, s, batch, m->n_in, idx + b0, X, m->H[0]);
       hipLaunchKernelGGL(k_gather_rows, dim3(256), dim3(256), 0, s, batch, m->n_out, idx + b0, T, Tb);
@@ -525,22 +565,16 @@ extern "C" int rte_mlp_train(rte_mlp* m, const float* X, const float* T, int n, 
       const float c1 = 1.f - std::pow(b1, (float)m->adam_t), c2 = 1.f - std::pow(b2, (float)m->adam_t);
       hipLaunchKernelGGL(k_adam, dim3(1024), dim3(256), 0, s, m->nparams, m->P, m->G, m->M, m->V, lr, b1, b2, eps,
                          c1, c2);
-      if (loss_hist) {
-        std::vector<float> lb(256);
-        if (hipMemcpyAsync(lb.data(), m->lossbuf, sizeof(float) * 256, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-          status = RTE_EHIP;
-          break;
-        }
-        double t = 0.0;
-        for (float v : lb) t += v;
-        ep_loss += t / ((double)batch * m->n_out);
-        ++nb;
-      }
+      hipLaunchKernelGGL(k_loss_acc, dim3(1), dim3(256), 0, s, m->lossbuf, hist + ep,
+                         1.f / ((float)batch * m->n_out * nb));
     }
-    if (loss_hist) loss_hist[ep] = (float)(nb ? ep_loss / nb : 0.0);
   }
+  if (status == RTE_OK && hipGetLastError() != hipSuccess) status = RTE_EHIP;
+  if (status == RTE_OK && loss_hist &&
+      hipMemcpyAsync(loss_hist, hist, sizeof(float) * epochs, hipMemcpyDeviceToHost, s) != hipSuccess)
+    status = RTE_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess && status == RTE_OK) status = RTE_EHIP;
+  (void)hipFree(hist);
   (void)hipFree(Tb);
   (void)hipFree(idx);
   return status;

@@ -30,6 +30,7 @@ import numpy as np
 __all__ = [
     "source_moments", "cfg1", "cfg2", "cfg3_mu", "cfg3_problem", "cfg3_train_test",
     "cfg4_batch", "tiny_2d", "tiny_1d", "CFG3_BOX_LO", "CFG3_BOX_HI", "cfg3_box_centre",
+    "cfg3_sigma", "cfg3_sources", "cfg3_features", "cfg5_sets",
 ]
 
 _GL4_X, _GL4_W = np.polynomial.legendre.leggauss(4)
@@ -151,6 +152,52 @@ def cfg3_train_test(n_train=64, n_test=256, seed_train=30, seed_test=31):
                                                             n_train - 1)], 0)
     te = cfg3_mu(np.random.default_rng(seed_test), n_test)
     return tr, te
+
+
+def cfg3_sigma(mus):
+    """Per-region (sigma_t, sigma_s) [n, 2] of config-3 parameters (regions 0 = A, 1 = B)."""
+    mus = np.atleast_2d(np.asarray(mus, dtype=np.float64))
+    ss = mus[:, :2].copy()
+    return ss + mus[:, 2:3], ss
+
+
+def cfg3_sources(mus, n=96):
+    """Source moments [len(mus), n*n*4] of config-3 parameters.  The Gaussian
+    factorises in x and y, so each moment is a product of two 1D projections;
+    equal to source_moments of the same Gaussian up to rounding."""
+    mus = np.atleast_2d(np.asarray(mus, dtype=np.float64))
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    X = c[:, None] + 0.5 * h * _GL4_X[None, :]                    # [cell, gauss]
+    w = 0.5 * h * _GL4_W
+    basis = np.stack([np.ones(4), np.sqrt(3.0) * _GL4_X])         # [p, gauss]
+    out = np.empty((len(mus), n, n, 4))
+    for k, mu in enumerate(mus):
+        f = np.exp(-((X - 0.5) ** 2) / mu[3] ** 2)                  # same factor in x and y
+        m = (f[:, None, :] * (w * basis)[None]).sum(2) / np.sqrt(h)  # [cell, p]
+        for q in range(2):
+            for p in range(2):
+                out[k, :, :, p + 2 * q] = m[:, q][:, None] * m[:, p][None, :]
+    return out.reshape(len(mus), -1)
+
+
+def cfg3_features(mus):
+    """Parameter features in [0, 1]^4 for the learned correction:
+    (log10 mu1, log10 mu2, mu3, mu4) mapped linearly from the parameter box."""
+    mus = np.atleast_2d(np.asarray(mus, dtype=np.float64))
+    z = np.stack([np.log10(mus[:, 0]), np.log10(mus[:, 1]), mus[:, 2], mus[:, 3]], 1)
+    return (z - CFG3_BOX_LO) / (CFG3_BOX_HI - CFG3_BOX_LO)
+
+
+def cfg5_sets(n_train=64, n_snap=10240, n_test=1024, seed_train=50, seed_snap=52, seed_test=51):
+    """Config-3 parameter law for the learned-preconditioner workload: ROM
+    training set (box centre + draws), snapshot-generation parameters, and
+    fresh test parameters."""
+    tr = np.concatenate([cfg3_box_centre()[None], cfg3_mu(np.random.default_rng(seed_train),
+                                                            n_train - 1)], 0)
+    sn = cfg3_mu(np.random.default_rng(seed_snap), n_snap)
+    te = cfg3_mu(np.random.default_rng(seed_test), n_test)
+    return tr, sn, te
 
 
 def cfg4_batch(seed=4, n_inst=512):
