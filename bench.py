@@ -27,6 +27,16 @@ METRIC = "FGMRES solves/s to rel-res 1e-8 (MLP vs ROMSAD vs plain); sweep GDoF/s
 SWEEP_FLOPS_PER_CELL_ORD = 118.0
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak, FLOP/s
 PEAK_FP64_VECTOR = 78.6e12
+PEAK_HBM = 8.0e12             # MI355X published HBM3E bandwidth, B/s
+# HBM bytes per launch of the FP32 sweep at the default workload (96^2, 256
+# instances), from the FETCH_SIZE / WRITE_SIZE counter passes scaled by a
+# 512 MiB copy (profiles/sweep2d_f32_cfg3_96sq_b256_hbm_traffic.md); valid for
+# the kernel version those passes measured.
+SWEEP_F32_TRAFFIC_BYTES = 1.2255e9
+# Algorithmic HBM bytes per cell and instance of one sweep: read the 4 source
+# moments (FP64, 32 B), write the 4 scalar-flux moments (FP64, 32 B), and the
+# cell's cross-section data (8 B).  Angular fluxes never leave the chip.
+SWEEP_ALG_BYTES_PER_CELL = 72.0
 
 
 def log(*a):
@@ -178,6 +188,9 @@ def main():
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--only-mlp", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="after the timed region, copy 512 MiB device-to-device between markers 3 and 4 "
+                         "(calibrates hardware byte counters)")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -226,6 +239,7 @@ def main():
 
     # ---------------- timed region
     rt.prof_enable(True)
+    rt.prof_mark(1)  # kernel-trace boundary of the timed region
     torch.cuda.synchronize()
     t = time.perf_counter()
     ok = 0
@@ -236,6 +250,16 @@ def main():
         all_stats = stats
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    rt.prof_mark(2)
+    if args.pmc_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        rt.prof_mark(3)
+        dst.copy_(src)
+        rt.prof_mark(4)
+        torch.cuda.synchronize()
+        del src, dst
     launches, sweep_ms, units = rt.prof_read("sweep_f32")
     rt.prof_enable(False)
     value = ok / dt
@@ -262,7 +286,12 @@ def main():
                    "global_batch": len(te_mu), "precond": "romsad"},
         "roofline": {"bound": "alu", "kernel": "sweep2d_kernel<float>", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR,
+                     "traffic": SWEEP_F32_TRAFFIC_BYTES if (n == 96 and len(te_mu) == 256) else None,
+                     "traffic_unit": "B per launch",
+                     "hbm_algorithmic_GBps": (sum(nd // 4 for nd in B.ndofs) * SWEEP_ALG_BYTES_PER_CELL /
+                                              (avg_launch_ms * 1e-3) / 1e9) if avg_launch_ms > 0 else 0.0,
+                     "hbm_peak_GBps": PEAK_HBM / 1e9,
                      "launches": launches, "avg_launch_ms": avg_launch_ms,
                      "flops_per_cell_ordinate": SWEEP_FLOPS_PER_CELL_ORD},
         "romsad": {"iterations_mean": float(its.mean()), "iterations_max": int(its.max()),

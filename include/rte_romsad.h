@@ -293,6 +293,9 @@ int rte_mlp_snapshots(const rte_batch* b, const double* sigma_t, const double* s
  * Slots: 0 FP64 sweep, 1 FP32 sweep, 2 DSA operator, 3 Arnoldi MGS, 4 ROM.  */
 int rte_prof_enable(int on);
 int rte_prof_read(int slot, int64_t* launches, double* total_ms, double* total_units);
+/* Enqueues an empty kernel (rte::k_region_marker, argument id) on `stream`, so
+ * that an external kernel trace can locate a region between two marks.      */
+int rte_prof_mark(int id, void* stream);
 
 #ifdef __cplusplus
 }

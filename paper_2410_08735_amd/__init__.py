@@ -285,6 +285,11 @@ def prof_enable(on=True):
 PROF_SLOTS = {"sweep_f64": 0, "sweep_f32": 1, "dsa_op": 2, "mgs": 3, "rom": 4}
 
 
+def prof_mark(mark_id=0):
+    """Enqueue an empty marker kernel (visible in kernel traces) on the current stream."""
+    check(L.lib().rte_prof_mark(int(mark_id), _stream()), "rte_prof_mark")
+
+
 def prof_read(slot):
     """(launches, total_ms, total_units) recorded for a profiler slot."""
     n, ms, u = L.i64(), L.dbl(), L.dbl()

@@ -89,6 +89,7 @@ SIGNATURES = {
     "rte_mlp_snapshots": (C.c_int, [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.c_int, vp, vp, vp,
                                     vp]),
     "rte_prof_enable": (C.c_int, [C.c_int]),
+    "rte_prof_mark": (C.c_int, [C.c_int, vp]),
     "rte_prof_read": (C.c_int, [C.c_int, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),
 }
 

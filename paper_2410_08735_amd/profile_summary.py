@@ -1,0 +1,91 @@
+"""Summarise a rocprofv3 kernel trace (``--kernel-trace --output-format csv``).
+
+    python -m paper_2410_08735_amd.profile_summary <prefix>_kernel_trace.csv [top]
+    python -m paper_2410_08735_amd.profile_summary <prefix>_counter_collection.csv [top]
+
+For a kernel trace: two markdown tables, the kernels between the first two
+region markers (``rte::k_region_marker``, enqueued by ``rte_prof_mark``
+around a timed region) and the kernels of the whole process.  For a counter
+collection (``--pmc``): the mean counter value per dispatch of each kernel in
+the timed region, and of the copy between the third and fourth markers.
+Kernel names are shortened to their qualified name and template arguments.
+"""
+import collections
+import csv
+import sys
+
+MARKER = "k_region_marker"
+
+
+def _short(name):
+    depth, out = 0, []
+    for ch in name:  # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    s = "".join(out)
+    return s[5:] if s.startswith("void ") else s
+
+
+def _table(rows, title, top):
+    agg = collections.defaultdict(lambda: [0, 0])
+    for r in rows:
+        a = agg[_short(r["Kernel_Name"])]
+        a[0] += 1
+        a[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    tot = sum(v[1] for v in agg.values()) or 1
+    lines = [f"### {title}", "",
+             f"busy {tot / 1e6:.2f} ms in {sum(v[0] for v in agg.values())} dispatches", "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for name, (c, ns) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"| `{name}` | {c} | {ns / 1e6:.3f} | {ns / c / 1e3:.1f} | {100 * ns / tot:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
+def summarise(path, top=25):
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    marks = [i for i, r in enumerate(rows) if MARKER in r["Kernel_Name"]]
+    body = [r for r in rows if MARKER not in r["Kernel_Name"]]
+    out = []
+    if len(marks) >= 2:
+        region = [r for r in rows[marks[0] + 1:marks[1]] if MARKER not in r["Kernel_Name"]]
+        span = int(rows[marks[1]]["Start_Timestamp"]) - int(rows[marks[0]]["End_Timestamp"])
+        out.append(_table(region, f"timed region (between markers, {span / 1e6:.2f} ms wall on the GPU)", top))
+    out.append(_table(body, "whole process", top))
+    return "\n".join(out)
+
+
+def summarise_counters(path, top=25):
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+    marks = [i for i, r in enumerate(rows) if MARKER in r["Kernel_Name"]]
+    out = []
+    for title, (a, b) in (("timed region (markers 1-2)", (0, 1)), ("copy probe (markers 3-4)", (2, 3))):
+        if len(marks) <= b:
+            continue
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        disp = collections.defaultdict(set)
+        for r in rows[marks[a] + 1:marks[b]]:
+            if MARKER in r["Kernel_Name"]:
+                continue
+            k = _short(r["Kernel_Name"])
+            agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            disp[k].add(r["Dispatch_Id"])
+        names = sorted({c for v in agg.values() for c in v})
+        out += [f"### {title}", "", "| kernel | dispatches | " + " | ".join(f"mean {c} per dispatch" for c in names)
+                + " |", "|---|---:|" + "---:|" * len(names)]
+        order = sorted(agg, key=lambda k: -sum(sum(v) for v in agg[k].values()))[:top]
+        for k in order:
+            vals = [sum(agg[k][c]) / len(disp[k]) if agg[k][c] else 0.0 for c in names]
+            out.append(f"| `{k}` | {len(disp[k])} | " + " | ".join(f"{v:.1f}" for v in vals) + " |")
+        out.append("")
+    return "\n".join(out)
+
+
+if __name__ == "__main__":
+    top = int(sys.argv[2]) if len(sys.argv) > 2 else 25
+    if sys.argv[1].endswith("counter_collection.csv"):
+        print(summarise_counters(sys.argv[1], top))
+    else:
+        print(summarise(sys.argv[1], top))

@@ -231,3 +231,13 @@ def test_infinite_medium_equilibrium():
     At = tr.dense_A_tilde(P)
     phi = np.linalg.solve(At, tr.b_tilde(P))
     np.testing.assert_allclose(phi, dg.project(m, lambda x, y: 1.6 + 0 * x), atol=1e-12)
+
+
+def test_separable_source_generator_matches_quadrature_projection():
+    """The factorised config-3 source moments equal the 4x4 Gauss projection."""
+    from synth import cfg3_problem, cfg3_sources, cfg3_train_test
+    _, te = cfg3_train_test(n_test=3)
+    for mu in te:
+        a = cfg3_problem(mu, n=12)["source"]
+        b = cfg3_sources(mu[None], 12)[0]
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()

@@ -163,6 +163,48 @@ def test_greedy_rank_affine_and_sampled_residual():
     assert rom.residual_indicator(P, U, P.Ss @ b) < 1e-7 * np.linalg.norm(P.Ss @ b)
 
 
+def test_learned_rows_exact_on_a_sampled_parameter():
+    """Training rows: on a parameter whose own snapshots span U, xi - v is the
+    density-relation correction W_w^T U^T dpsi, so the least-squares target
+    reproduces it exactly; features carry the unit vector g / ||g||."""
+    specs = _family(4)
+    U, rep = rom.greedy(specs, window=2, eps_rom=0.0, n_giter=2)
+    P = tr.Problem(specs[rep.sampled[1]])
+    D = dsa.DSA(P)
+    res = fg.fgmres(_At(P), tr.b_tilde(P), lambda j, v: D.apply(v), m=60, rtol=1e-11, keep_first=True)
+    mu = np.array([0.3, 0.7])
+    X, T = rom.learned_correction_rows(P, U, res.first_cycle, res.x, 2, mu)
+    xis = rom.xi_recurrence(res.first_cycle, res.x, 2)
+    ww = rom.Ww(P, U)
+    for l in range(2):
+        v = res.first_cycle["V"][l]
+        g = rom.W1(U) @ (P.Ss @ v)
+        np.testing.assert_allclose(X[l, :2], mu)
+        assert abs(np.linalg.norm(X[l, 2:]) - 1.0) < 1e-14
+        c = T[l] * np.linalg.norm(g)
+        err = np.linalg.norm(ww.T @ c - (xis[l] - v)) / np.linalg.norm(xis[l] - v)
+        assert err < 1e-8, err
+
+
+def test_learned_rows_are_least_squares_fits():
+    """Off the sampled set the target is the least-squares fit: its residual is
+    orthogonal to every column of W_w (a transposed operand breaks this)."""
+    specs = _family(4)
+    U, _ = rom.greedy(specs, window=2, eps_rom=0.0, n_giter=2)
+    spec = dict(specs[1], sigma_s=specs[1]["sigma_s"] * 1.3, sigma_t=specs[1]["sigma_t"] * 1.3)
+    P = tr.Problem(spec)
+    D = dsa.DSA(P)
+    res = fg.fgmres(_At(P), tr.b_tilde(P), lambda j, v: D.apply(v), m=60, rtol=1e-11, keep_first=True)
+    X, T = rom.learned_correction_rows(P, U, res.first_cycle, res.x, 2, np.zeros(1))
+    xis = rom.xi_recurrence(res.first_cycle, res.x, 2)
+    ww = rom.Ww(P, U)
+    for l in range(2):
+        v = res.first_cycle["V"][l]
+        g = rom.W1(U) @ (P.Ss @ v)
+        resid = ww.T @ (T[l] * np.linalg.norm(g)) - (xis[l] - v)
+        assert np.abs(ww @ resid).max() < 1e-10 * np.linalg.norm(ww) * np.linalg.norm(xis[l] - v)
+
+
 # ---------------------------------------------------------------- MLP
 def test_mlp_backward_matches_finite_differences():
     rng = np.random.default_rng(0)
