@@ -187,6 +187,8 @@ def main():
     ap.add_argument("--mlp-lr", type=float, default=1e-3)
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--only-mlp", action="store_true")
+    ap.add_argument("--window-cycles", type=int, default=1,
+                    help="restart cycles that use the ROM window (0 = every cycle)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true",
                     help="after the timed region, copy 512 MiB device-to-device between markers 3 and 4 "
@@ -206,7 +208,8 @@ def main():
 
     torch.cuda.set_device(0)
     common = dict(m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8, window=2,
-                  dsa_inner_max=args.dsa_inner, dsa_restart=args.dsa_restart, dsa_inner_tol=1e-6)
+                  dsa_inner_max=args.dsa_inner, dsa_restart=args.dsa_restart, dsa_inner_tol=1e-6,
+                  window_cycles=args.window_cycles)
     if args.only_mlp:
         print(json.dumps({"learned": learned_leg(args, common)}), flush=True)
         return

@@ -146,7 +146,8 @@ int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma
  *   RTE_PC_NONE  z = v,
  *   RTE_PC_DSA   z = M_DSA^{-1} v,
  *   RTE_PC_ROMSAD  M_ROM^{-1} for j <= window, M_DSA^{-1} after (eq. of the
- *                  ROMSAD preconditioner),
+ *                  ROMSAD preconditioner); with window_cycles = k >= 1 only
+ *                  the first k cycles open a window,
  *   RTE_PC_MLP   the learned reduced correction for j <= window with the ROMSAD
  *                correction as fallback and DSA after the window.
  * Stopping: Givens estimate <= rtol * ||b~|| ends a cycle; the FP64 true
@@ -164,6 +165,9 @@ typedef struct {
   int32_t dsa_restart;
   double dsa_inner_tol;
   int32_t keep_krylov;   /* internal use by the offline builders: 0           */
+  int32_t window_cycles; /* restart cycles whose first `window` iterations use
+                            the ROM / learned correction: 0 = every cycle,
+                            k >= 1 = the first k cycles only                 */
 } rte_solve_opts;
 
 typedef struct {

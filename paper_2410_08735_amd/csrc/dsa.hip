@@ -243,10 +243,11 @@ __global__ void k_dsa_blockinv(int n_inst, int max_regions, const InstDev* __res
 }
 
 // rhs = [ss v, m_x ss v (, m_y ss v)] per cell
+template <typename real>
 __global__ void k_dsa_rhs(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
                           const int32_t* __restrict__ region, const double* __restrict__ sigma_s,
                           int max_regions, const int64_t* __restrict__ off,
-                          const double* __restrict__ v, double* __restrict__ rhs,
+                          const double* __restrict__ v, real* __restrict__ rhs,
                           const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
@@ -258,15 +259,17 @@ __global__ void k_dsa_rhs(const InstDev* __restrict__ insts, const DsaStencil* _
     const double ss = sigma_s[(int64_t)b * max_regions + region[I.region_off + cell]];
     for (int l = 0; l < nl; ++l) {
       const double sv = ss * v[I.dof_off + (int64_t)cell * nl + l];
-      rhs[off[b] + (int64_t)l * ncell + cell] = sv;
-      for (int d = 0; d < I.dim; ++d) rhs[off[b] + (int64_t)((1 + d) * nl + l) * ncell + cell] = S.m[d] * sv;
+      rhs[off[b] + (int64_t)l * ncell + cell] = (real)sv;
+      for (int d = 0; d < I.dim; ++d)
+        rhs[off[b] + (int64_t)((1 + d) * nl + l) * ncell + cell] = (real)(S.m[d] * sv);
     }
   }
 }
 
 // z = v + dphi (the first nloc unknowns of every cell)
+template <typename real>
 __global__ void k_dsa_out(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
-                          const int64_t* __restrict__ off, const double* __restrict__ u,
+                          const int64_t* __restrict__ off, const real* __restrict__ u,
                           const double* __restrict__ v, double* __restrict__ z,
                           const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
@@ -277,8 +280,19 @@ __global__ void k_dsa_out(const InstDev* __restrict__ insts, const DsaStencil* _
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd;
        d += (int64_t)gridDim.x * blockDim.x) {
     const int64_t cell = d / nl, l = d % nl;
-    z[I.dof_off + d] = v[I.dof_off + d] + u[off[b] + l * ncell + cell];
+    z[I.dof_off + d] = v[I.dof_off + d] + (double)u[off[b] + l * ncell + cell];
   }
+}
+
+// y += x over each active instance's block of the level-0 DSA vector
+template <typename real>
+__global__ void k_dsa_axpy(const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                           const real* __restrict__ x, real* __restrict__ y, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int64_t lo = off[b], n = len[b];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[lo + e] += x[lo + e];
 }
 
 // ------------------------------------------------------------------ multigrid
@@ -473,32 +487,35 @@ __global__ void __launch_bounds__(256) k_mg_stencil(int mode, int color, const L
 // so with P = R (L.x_up)/h and Q = L (R.x_lo)/h:
 //   D_C x = S_C x + (P - Q)/2,  D_J x = S_J x + P + Q.
 // Absent neighbours are passed as zeros (no coupling across the boundary).
-__device__ __forceinline__ void axis_cj(const double Xc[4], const double Xhi[4], const double Xlo[4], int axis,
-                                        double ih, double C[4], double J[4]) {
-  const double r3 = 1.7320508075688772935;
+template <typename real>
+__device__ __forceinline__ void axis_cj(const real Xc[4], const real Xhi[4], const real Xlo[4], int axis,
+                                        real ih, real C[4], real J[4]) {
+  const real r3 = (real)1.7320508075688772935;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int i0 = axis == 0 ? 2 * g : g;
     const int i1 = axis == 0 ? 2 * g + 1 : g + 2;
-    const double dl = (Xhi[i0] - r3 * Xhi[i1]) * ih;
-    const double dr = (Xlo[i0] + r3 * Xlo[i1]) * ih;
-    C[i0] = r3 * ih * Xc[i1] + 0.5 * (dl - dr);
-    C[i1] = -r3 * ih * Xc[i0] + 0.5 * r3 * (dl + dr);
-    J[i0] = -2.0 * ih * Xc[i0] + dl + dr;
-    J[i1] = -6.0 * ih * Xc[i1] + r3 * (dl - dr);
+    const real dl = (Xhi[i0] - r3 * Xhi[i1]) * ih;
+    const real dr = (Xlo[i0] + r3 * Xlo[i1]) * ih;
+    C[i0] = r3 * ih * Xc[i1] + (real)0.5 * (dl - dr);
+    C[i1] = -r3 * ih * Xc[i0] + (real)0.5 * r3 * (dl + dr);
+    J[i0] = (real)-2 * ih * Xc[i0] + dl + dr;
+    J[i1] = (real)-6 * ih * Xc[i1] + r3 * (dl - dr);
   }
 }
 
 // The scalars of the structured form (one set per instance and level).
+template <typename real>
 struct SymCoef {
-  double ax, ay, bex, bey, cxx, cxy, cyx, cyy, ihx, ihy;
+  real ax, ay, bex, bey, cxx, cxy, cyx, cyy, ihx, ihy;
 };
 
-__device__ __forceinline__ SymCoef sym_coef(const DsaStencil& G) {
-  SymCoef c;
-  c.ax = G.ax; c.ay = G.ay; c.bex = G.bex; c.bey = G.bey;
-  c.cxx = G.cxx; c.cxy = G.cxy; c.cyx = G.cyx; c.cyy = G.cyy;
-  c.ihx = 1.0 / G.hx; c.ihy = 1.0 / G.hy;
+template <typename real>
+__device__ __forceinline__ SymCoef<real> sym_coef(const DsaStencil& G) {
+  SymCoef<real> c;
+  c.ax = (real)G.ax; c.ay = (real)G.ay; c.bex = (real)G.bex; c.bey = (real)G.bey;
+  c.cxx = (real)G.cxx; c.cxy = (real)G.cxy; c.cyx = (real)G.cyx; c.cyy = (real)G.cyy;
+  c.ihx = (real)(1.0 / G.hx); c.ihy = (real)(1.0 / G.hy);
   return c;
 }
 
@@ -522,24 +539,26 @@ __device__ __forceinline__ CellPos cell_pos(int i, int k, int nx, int ny) {
 }
 
 // Field f (4 unknowns) of a cell and of its four neighbours (zeros where absent).
-__device__ __forceinline__ void load_field(const double* __restrict__ x, const CellPos& P, int f, double c[4],
-                                           double l[4], double r[4], double b[4], double t[4]) {
+template <typename real>
+__device__ __forceinline__ void load_field(const real* __restrict__ x, const CellPos& P, int f, real c[4],
+                                           real l[4], real r[4], real b[4], real t[4]) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const double* q = x + (int64_t)(4 * f + m) * P.nc + P.cell;
+    const real* q = x + (int64_t)(4 * f + m) * P.nc + P.cell;
     c[m] = q[0];
-    l[m] = P.hl ? q[-1] : 0.0;
-    r[m] = P.hr ? q[1] : 0.0;
-    b[m] = P.hb ? q[-P.nx] : 0.0;
-    t[m] = P.ht ? q[P.nx] : 0.0;
+    l[m] = P.hl ? q[-1] : (real)0;
+    r[m] = P.hr ? q[1] : (real)0;
+    b[m] = P.hb ? q[-P.nx] : (real)0;
+    t[m] = P.ht ? q[P.nx] : (real)0;
   }
 }
 
 // y = K x for one cell (12 unknowns: phi, J_x, J_y), reflection-symmetric rule,
 // one field at a time to keep few values live.
-__device__ __forceinline__ void sym_cell_apply(const SymCoef& S, double st, double ss,
-                                               const double* __restrict__ x, const CellPos& P, double y[12]) {
-  double c[4], l[4], r[4], b[4], t[4], Cx[4], Jx[4], Cy[4], Jy[4];
+template <typename real>
+__device__ __forceinline__ void sym_cell_apply(const SymCoef<real>& S, real st, real ss,
+                                               const real* __restrict__ x, const CellPos& P, real y[12]) {
+  real c[4], l[4], r[4], b[4], t[4], Cx[4], Jx[4], Cy[4], Jy[4];
   // phi: its own row, and the J rows' D_C phi terms
   load_field(x, P, 0, c, l, r, b, t);
   axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
@@ -556,8 +575,8 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef& S, double st, doub
   axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    y[m] += 3.0 * S.ax * Cx[m];
-    y[4 + m] += 3.0 * S.ax * st * c[m] - 1.5 * (S.cxx * Jx[m] + S.cxy * Jy[m]);
+    y[m] += (real)3 * S.ax * Cx[m];
+    y[4 + m] += (real)3 * S.ax * st * c[m] - (real)1.5 * (S.cxx * Jx[m] + S.cxy * Jy[m]);
   }
   // J_y likewise
   load_field(x, P, 2, c, l, r, b, t);
@@ -565,8 +584,8 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef& S, double st, doub
   axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    y[m] += 3.0 * S.ay * Cy[m];
-    y[8 + m] += 3.0 * S.ay * st * c[m] - 1.5 * (S.cyx * Jx[m] + S.cyy * Jy[m]);
+    y[m] += (real)3 * S.ay * Cy[m];
+    y[8 + m] += (real)3 * S.ay * st * c[m] - (real)1.5 * (S.cyx * Jx[m] + S.cyy * Jy[m]);
   }
 }
 
@@ -577,40 +596,44 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef& S, double st, doub
 // S dJ^{-1} S is diagonal:
 //   (Dphi + 3 a_xx^2 s_x^2 / dJx[1-p, q] + 3 a_yy^2 s_y^2 / dJy[p, 1-q]) phi
 //       = r_phi - 3 a_xx S_x dJx^{-1} r_Jx - 3 a_yy S_y dJy^{-1} r_Jy.
-__device__ __forceinline__ void sym_block_solve(const SymCoef& S, double st, double ss, const double r[12],
-                                                double out[12]) {
-  const double sx = 1.7320508075688772935 * S.ihx, sy = 1.7320508075688772935 * S.ihy;
-  double dphi[4], djx[4], djy[4], tx[4], ty[4];
+template <typename real>
+__device__ __forceinline__ void sym_block_solve(const SymCoef<real>& S, real st, real ss, const real r[12],
+                                                real out[12]) {
+  const real r3 = (real)1.7320508075688772935;
+  const real sx = r3 * S.ihx, sy = r3 * S.ihy;
+  real dphi[4], djx[4], djy[4], tx[4], ty[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     const int p = l & 1, q = l >> 1;
-    const double gx = (p ? 6.0 : 2.0) * S.ihx, gy = (q ? 6.0 : 2.0) * S.ihy;
+    const real gx = (real)(p ? 6 : 2) * S.ihx, gy = (real)(q ? 6 : 2) * S.ihy;
     dphi[l] = (st - ss) + S.bex * gx + S.bey * gy;
-    djx[l] = 3.0 * S.ax * st + 1.5 * (S.cxx * gx + S.cxy * gy);
-    djy[l] = 3.0 * S.ay * st + 1.5 * (S.cyx * gx + S.cyy * gy);
+    djx[l] = (real)3 * S.ax * st + (real)1.5 * (S.cxx * gx + S.cxy * gy);
+    djy[l] = (real)3 * S.ay * st + (real)1.5 * (S.cyx * gx + S.cyy * gy);
     tx[l] = r[4 + l] / djx[l];  // dJx^{-1} r_Jx
     ty[l] = r[8 + l] / djy[l];
   }
   // S_x acts on p: (S u)[0,q] = s u[1,q], (S u)[1,q] = -s u[0,q]; S_y likewise on q
-  double rhs[4];
-  rhs[0] = r[0] - 3.0 * S.ax * sx * tx[1] - 3.0 * S.ay * sy * ty[2];
-  rhs[1] = r[1] + 3.0 * S.ax * sx * tx[0] - 3.0 * S.ay * sy * ty[3];
-  rhs[2] = r[2] - 3.0 * S.ax * sx * tx[3] + 3.0 * S.ay * sy * ty[0];
-  rhs[3] = r[3] + 3.0 * S.ax * sx * tx[2] + 3.0 * S.ay * sy * ty[1];
-  const double kx = 3.0 * S.ax * S.ax * sx * sx, ky = 3.0 * S.ay * S.ay * sy * sy;
+  const real ax3 = (real)3 * S.ax * sx, ay3 = (real)3 * S.ay * sy;
+  real rhs[4];
+  rhs[0] = r[0] - ax3 * tx[1] - ay3 * ty[2];
+  rhs[1] = r[1] + ax3 * tx[0] - ay3 * ty[3];
+  rhs[2] = r[2] - ax3 * tx[3] + ay3 * ty[0];
+  rhs[3] = r[3] + ax3 * tx[2] + ay3 * ty[1];
+  const real kx = (real)3 * S.ax * S.ax * sx * sx, ky = (real)3 * S.ay * S.ay * sy * sy;
   out[0] = rhs[0] / (dphi[0] + kx / djx[1] + ky / djy[2]);  // (1-p, q) and (p, 1-q) partners
   out[1] = rhs[1] / (dphi[1] + kx / djx[0] + ky / djy[3]);
   out[2] = rhs[2] / (dphi[2] + kx / djx[3] + ky / djy[0]);
   out[3] = rhs[3] / (dphi[3] + kx / djx[2] + ky / djy[1]);
   // J = dJ^{-1} (r_J - a S phi)
-  out[4] = (r[4] - S.ax * sx * out[1]) / djx[0];
-  out[5] = (r[5] + S.ax * sx * out[0]) / djx[1];
-  out[6] = (r[6] - S.ax * sx * out[3]) / djx[2];
-  out[7] = (r[7] + S.ax * sx * out[2]) / djx[3];
-  out[8] = (r[8] - S.ay * sy * out[2]) / djy[0];
-  out[9] = (r[9] - S.ay * sy * out[3]) / djy[1];
-  out[10] = (r[10] + S.ay * sy * out[0]) / djy[2];
-  out[11] = (r[11] + S.ay * sy * out[1]) / djy[3];
+  const real axs = S.ax * sx, ays = S.ay * sy;
+  out[4] = (r[4] - axs * out[1]) / djx[0];
+  out[5] = (r[5] + axs * out[0]) / djx[1];
+  out[6] = (r[6] - axs * out[3]) / djx[2];
+  out[7] = (r[7] + axs * out[2]) / djx[3];
+  out[8] = (r[8] - ays * out[2]) / djy[0];
+  out[9] = (r[9] - ays * out[3]) / djy[1];
+  out[10] = (r[10] + ays * out[0]) / djy[2];
+  out[11] = (r[11] + ays * out[1]) / djy[3];
 }
 
 // Red-black index: work item t of colour `color` -> (i, k), for even nx
@@ -625,19 +648,20 @@ __device__ __forceinline__ void rb_cell(int t, int nx, int color, int& i, int& k
 // mode 2 (colour c): x_c += D_c^{-1} (b - K x)_c on cells with (i + k) % 2 == c;
 // mode 3: the first colour-0 half sweep from x = 0 (x = D^{-1} b on colour 0,
 //         x = 0 on colour 1), reading no x.
+template <typename real>
 __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
                                  const DsaStencil* __restrict__ st_, const double* __restrict__ st,
-                                 const double* __restrict__ ss, const double* __restrict__ bvec,
-                                 double* __restrict__ x, double* __restrict__ y,
+                                 const double* __restrict__ ss, const real* __restrict__ bvec,
+                                 real* __restrict__ x, real* __restrict__ y,
                                  const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const LvlInst L = li[b];
-  const SymCoef S = sym_coef(st_[b]);
+  const SymCoef<real> S = sym_coef<real>(st_[b]);
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   const int64_t vo = L.cell_off * 12;
-  const double* __restrict__ bb = bvec ? bvec + vo : nullptr;
-  double* __restrict__ xb = x + vo;
+  const real* __restrict__ bb = bvec ? bvec + vo : nullptr;
+  real* __restrict__ xb = x + vo;
   const bool compact = mode == 2 && (nx & 1) == 0;
   const int nwork = compact ? nc / 2 : nc;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nwork; t += gridDim.x * blockDim.x) {
@@ -650,18 +674,18 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
       if (mode == 2 && ((i + k) & 1) != color) continue;
     }
     const CellPos P = cell_pos(i, k, nx, ny);
-    const double tt = st[L.cell_off + P.cell], uu = ss[L.cell_off + P.cell];
+    const real tt = (real)st[L.cell_off + P.cell], uu = (real)ss[L.cell_off + P.cell];
     if (mode == 3) {
-      double r[12], d[12];
+      real r[12], d[12];
       const bool red = ((i + k) & 1) == 0;
 #pragma unroll
-      for (int q = 0; q < 12; ++q) r[q] = red ? bb[(int64_t)q * nc + P.cell] : 0.0;
+      for (int q = 0; q < 12; ++q) r[q] = red ? bb[(int64_t)q * nc + P.cell] : (real)0;
       if (red) sym_block_solve(S, tt, uu, r, d);
 #pragma unroll
-      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = red ? d[q] : 0.0;
+      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = red ? d[q] : (real)0;
       continue;
     }
-    double yy[12];
+    real yy[12];
     sym_cell_apply(S, tt, uu, xb, P, yy);
     if (mode == 0) {
 #pragma unroll
@@ -670,7 +694,7 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
 #pragma unroll
       for (int q = 0; q < 12; ++q) y[vo + (int64_t)q * nc + P.cell] = bb[(int64_t)q * nc + P.cell] - yy[q];
     } else {
-      double r[12], d[12];
+      real r[12], d[12];
 #pragma unroll
       for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + P.cell] - yy[q];
       sym_block_solve(S, tt, uu, r, d);
@@ -682,19 +706,20 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
 
 // Coarsest level: `sweeps` red-black Gauss-Seidel sweeps from x = 0 in one
 // launch, one work group per instance.
+template <typename real>
 __global__ void __launch_bounds__(256) k_mg_coarse_sym(int sweeps, const LvlInst* __restrict__ li,
                                 const DsaStencil* __restrict__ st_, const double* __restrict__ st,
-                                const double* __restrict__ ss, const double* __restrict__ bvec,
-                                double* __restrict__ x, const int32_t* __restrict__ active) {
+                                const double* __restrict__ ss, const real* __restrict__ bvec,
+                                real* __restrict__ x, const int32_t* __restrict__ active) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const LvlInst L = li[b];
-  const SymCoef S = sym_coef(st_[b]);
+  const SymCoef<real> S = sym_coef<real>(st_[b]);
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   const int64_t vo = L.cell_off * 12;
-  const double* __restrict__ bb = bvec + vo;
-  double* __restrict__ xb = x + vo;
-  for (int e = threadIdx.x; e < nc * 12; e += blockDim.x) xb[e] = 0.0;
+  const real* __restrict__ bb = bvec + vo;
+  real* __restrict__ xb = x + vo;
+  for (int e = threadIdx.x; e < nc * 12; e += blockDim.x) xb[e] = (real)0;
   __syncthreads();
   for (int sw = 0; sw < sweeps; ++sw)
     for (int color = 0; color < 2; ++color) {
@@ -702,8 +727,8 @@ __global__ void __launch_bounds__(256) k_mg_coarse_sym(int sweeps, const LvlInst
         const int i = cell % nx, k = cell / nx;
         if (((i + k) & 1) != color) continue;
         const CellPos P = cell_pos(i, k, nx, ny);
-        const double tt = st[L.cell_off + cell], uu = ss[L.cell_off + cell];
-        double yy[12], r[12], d[12];
+        const real tt = (real)st[L.cell_off + cell], uu = (real)ss[L.cell_off + cell];
+        real yy[12], r[12], d[12];
         sym_cell_apply(S, tt, uu, xb, P, yy);
 #pragma unroll
         for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + cell] - yy[q];
@@ -725,10 +750,10 @@ __device__ __forceinline__ double inj1d(int side, int p, int P) {
 
 // mode 0: restrict  bc[C] = sum_children P_f^T rf[f]
 // mode 1: prolong   xf[f] += P_f xc[C]
-template <int NU>
+template <int NU, typename real>
 __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
-                              const double* __restrict__ fine_in, double* __restrict__ fine_out,
-                              const double* __restrict__ coarse_in, double* __restrict__ coarse_out,
+                              const real* __restrict__ fine_in, real* __restrict__ fine_out,
+                              const real* __restrict__ coarse_in, real* __restrict__ coarse_out,
                               const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
@@ -738,9 +763,9 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
   const int nc = Cc.nx * Cc.ny;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
     const int I = c % Cc.nx, K = c / Cc.nx;
-    double acc[NU];
+    real acc[NU];
     if (mode == 0)
-      for (int r = 0; r < NU; ++r) acc[r] = 0.0;
+      for (int r = 0; r < NU; ++r) acc[r] = (real)0;
     else
       for (int r = 0; r < NU; ++r) acc[r] = coarse_in[Cc.cell_off * NU + (int64_t)r * nc + c];
     for (int dk = 0; dk < (F.dim == 2 ? 2 : 1); ++dk)
@@ -751,17 +776,17 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
           for (int l = 0; l < nl; ++l) {      // child mode (p + 2q)
             const int p = l & 1, q = l >> 1;
             if (mode == 0) {
-              const double rv = fine_in[fo + (fld * nl + l) * nfc];
+              const real rv = fine_in[fo + (fld * nl + l) * nfc];
               for (int L2 = 0; L2 < nl; ++L2) {  // coarse mode
                 const int P = L2 & 1, Q = L2 >> 1;
-                const double w = inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0);
+                const real w = (real)(inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0));
                 acc[fld * nl + L2] += w * rv;
               }
             } else {
-              double v = 0.0;
+              real v = (real)0;
               for (int L2 = 0; L2 < nl; ++L2) {
                 const int P = L2 & 1, Q = L2 >> 1;
-                const double w = inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0);
+                const real w = (real)(inj1d(di, p, P) * (F.dim == 2 ? inj1d(dk, q, Q) : 1.0));
                 v += w * acc[fld * nl + L2];
               }
               fine_out[fo + (fld * nl + l) * nfc] += v;
@@ -775,40 +800,41 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
 
 // Residual and restriction in one pass (reflection-symmetric rules): each
 // coarse cell forms b - K x on its 2 x 2 children and accumulates P_f^T of it.
+template <typename real>
 __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
                                      const DsaStencil* __restrict__ st_f, const double* __restrict__ st,
-                                     const double* __restrict__ ss, const double* __restrict__ bvec,
-                                     const double* __restrict__ x, double* __restrict__ coarse_b,
+                                     const double* __restrict__ ss, const real* __restrict__ bvec,
+                                     const real* __restrict__ x, real* __restrict__ coarse_b,
                                      const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const LvlInst F = lf[b], Cc = lc[b];
-  const SymCoef S = sym_coef(st_f[b]);
+  const SymCoef<real> S = sym_coef<real>(st_f[b]);
   const int nfx = F.nx, nfy = F.ny, nfc = nfx * nfy, ncc = Cc.nx * Cc.ny;
   const int64_t vf = F.cell_off * 12;
-  const double* __restrict__ xb = x + vf;
-  const double* __restrict__ bb = bvec + vf;
+  const real* __restrict__ xb = x + vf;
+  const real* __restrict__ bb = bvec + vf;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncc; c += gridDim.x * blockDim.x) {
     const int I = c % Cc.nx, K = c / Cc.nx;
-    double acc[12];
+    real acc[12];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 12; ++q) acc[q] = (real)0;
 #pragma unroll 1
     for (int ch = 0; ch < 4; ++ch) {  // children one at a time keeps few values live
         const int di = ch & 1, dk = ch >> 1;
         const int i = 2 * I + di, k = 2 * K + dk;
         const CellPos P = cell_pos(i, k, nfx, nfy);
-        double yy[12];
-        sym_cell_apply(S, st[F.cell_off + P.cell], ss[F.cell_off + P.cell], xb, P, yy);
+        real yy[12];
+        sym_cell_apply(S, (real)st[F.cell_off + P.cell], (real)ss[F.cell_off + P.cell], xb, P, yy);
 #pragma unroll
         for (int fld = 0; fld < 3; ++fld)
 #pragma unroll
           for (int l = 0; l < 4; ++l) {
-            const double rv = bb[(int64_t)(4 * fld + l) * nfc + P.cell] - yy[4 * fld + l];
+            const real rv = bb[(int64_t)(4 * fld + l) * nfc + P.cell] - yy[4 * fld + l];
             const int p = l & 1, q = l >> 1;
 #pragma unroll
             for (int L2 = 0; L2 < 4; ++L2)
-              acc[4 * fld + L2] += inj1d(di, p, L2 & 1) * inj1d(dk, q, L2 >> 1) * rv;
+              acc[4 * fld + L2] += (real)(inj1d(di, p, L2 & 1) * inj1d(dk, q, L2 >> 1)) * rv;
           }
       }
 #pragma unroll
@@ -837,6 +863,12 @@ struct DsaSolver {
   Krylov K;                 // only with restart >= 1
   Space sp;                 // DSA space of level 0
   bool sym = false;         // every instance has a reflection-symmetric rule
+  // Stationary V-cycles (restart == 0) with structured kernels keep the whole
+  // hierarchy in FP32: a fixed preconditioner needs no more, and the level
+  // sweeps are bound by memory traffic.  Exact solves (restart >= 1) and the
+  // general-rule kernels stay in FP64.
+  bool f32 = false;
+  size_t esz() const { return f32 ? sizeof(float) : sizeof(double); }
   int nu_smooth = 2, coarse_sweeps = 20;
   int init(rte_batch* batch, int restart_);
   void release();
@@ -930,6 +962,7 @@ int DsaSolver::init(rte_batch* batch, int restart_) {
     RTE_HIP(hipMemcpy(hs.data(), lv[0].d_st, sizeof(DsaStencil) * n, hipMemcpyDeviceToHost));
     sym = nu == 12;
     for (int k = 0; k < n; ++k) sym = sym && hs[k].sym;
+    f32 = sym && restart == 0;
   }
   std::vector<int64_t> lens(n);
   for (int k = 0; k < n; ++k) lens[k] = (int64_t)lv[0].li[k].nx * lv[0].li[k].ny * nu;
@@ -990,8 +1023,12 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
   MgLevel& L = lv[l];
   const double* inv = l == 0 ? inv0 : L.inv;
   const int per_cell = l == 0 ? 0 : 1;
-  if (sym)
-    hipLaunchKernelGGL(k_mg_stencil_sym, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+  if (sym && f32)
+    hipLaunchKernelGGL(k_mg_stencil_sym<float>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+                       L.ss, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x),
+                       reinterpret_cast<float*>(y), act);
+  else if (sym)
+    hipLaunchKernelGGL(k_mg_stencil_sym<double>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, bv, x, y, act);
   else if (nu == 12)
     hipLaunchKernelGGL(k_mg_stencil<12>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
@@ -1011,7 +1048,7 @@ int DsaSolver::smooth(int l, int sweeps, bool reverse, bool from_zero, const dou
     if (k == 0 && from_zero && sym && !reverse) {
       RTE_TRY(stencil(l, 3, 0, bv, x, nullptr, act, s));
     } else {
-      if (k == 0 && from_zero) RTE_HIP(hipMemsetAsync(x, 0, sizeof(double) * lv[l].ncell * nu, s));
+      if (k == 0 && from_zero) RTE_HIP(hipMemsetAsync(x, 0, esz() * lv[l].ncell * nu, s));
       RTE_TRY(stencil(l, 2, reverse ? 1 : 0, bv, x, nullptr, act, s));
     }
     RTE_TRY(stencil(l, 2, reverse ? 0 : 1, bv, x, nullptr, act, s));
@@ -1024,8 +1061,13 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
   MgLevel& L = lv[l];
   if (l == (int)lv.size() - 1) {
     if (sym && l > 0) {  // whole coarsest smoothing in one launch
-      hipLaunchKernelGGL(k_mg_coarse_sym, dim3(b->n_inst), dim3(256), 0, s, coarse_sweeps, L.d_li,
-                         L.d_st, L.st, L.ss, bv, x, act);
+      if (f32)
+        hipLaunchKernelGGL(k_mg_coarse_sym<float>, dim3(b->n_inst), dim3(256), 0, s, coarse_sweeps, L.d_li,
+                           L.d_st, L.st, L.ss, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x),
+                           act);
+      else
+        hipLaunchKernelGGL(k_mg_coarse_sym<double>, dim3(b->n_inst), dim3(256), 0, s, coarse_sweeps, L.d_li,
+                           L.d_st, L.st, L.ss, bv, x, act);
       RTE_HIP(hipGetLastError());
       return RTE_OK;
     }
@@ -1034,26 +1076,33 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
   RTE_TRY(smooth(l, nu_smooth, false, true, bv, x, act, s));
   MgLevel& C = lv[l + 1];
   const dim3 g = grid(l + 1);
-  if (sym) {
-    hipLaunchKernelGGL(k_mg_resrestrict_sym, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss, bv, x,
-                       C.b, act);
+  if (sym && f32) {
+    hipLaunchKernelGGL(k_mg_resrestrict_sym<float>, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss,
+                       reinterpret_cast<const float*>(bv), reinterpret_cast<const float*>(x),
+                       reinterpret_cast<float*>(C.b), act);
+  } else if (sym) {
+    hipLaunchKernelGGL(k_mg_resrestrict_sym<double>, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss,
+                       bv, x, C.b, act);
   } else {
     RTE_TRY(stencil(l, 1, 0, bv, x, L.r, act, s));
     if (nu == 12)
-      hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
-                         (const double*)nullptr, C.b, act);
+      hipLaunchKernelGGL((k_mg_transfer<12, double>), g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r,
+                         (double*)nullptr, (const double*)nullptr, C.b, act);
     else
-      hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r, (double*)nullptr,
-                         (const double*)nullptr, C.b, act);
+      hipLaunchKernelGGL((k_mg_transfer<4, double>), g, dim3(256), 0, s, 0, L.d_li, C.d_li, L.r,
+                         (double*)nullptr, (const double*)nullptr, C.b, act);
   }
   RTE_HIP(hipGetLastError());
   RTE_TRY(vcycle(l + 1, C.b, C.x, act, s));
-  if (nu == 12)
-    hipLaunchKernelGGL(k_mg_transfer<12>, g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const double*)nullptr,
-                       x, C.x, (double*)nullptr, act);
+  if (f32)
+    hipLaunchKernelGGL((k_mg_transfer<12, float>), g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const float*)nullptr,
+                       reinterpret_cast<float*>(x), reinterpret_cast<const float*>(C.x), (float*)nullptr, act);
+  else if (nu == 12)
+    hipLaunchKernelGGL((k_mg_transfer<12, double>), g, dim3(256), 0, s, 1, L.d_li, C.d_li,
+                       (const double*)nullptr, x, C.x, (double*)nullptr, act);
   else
-    hipLaunchKernelGGL(k_mg_transfer<4>, g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const double*)nullptr,
-                       x, C.x, (double*)nullptr, act);
+    hipLaunchKernelGGL((k_mg_transfer<4, double>), g, dim3(256), 0, s, 1, L.d_li, C.d_li,
+                       (const double*)nullptr, x, C.x, (double*)nullptr, act);
   RTE_HIP(hipGetLastError());
   return smooth(l, nu_smooth, true, false, bv, x, act, s);
 }
@@ -1061,7 +1110,7 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
 // out = V-cycle(in) on level 0 (in and out may alias)
 int DsaSolver::precond(const double* in, double* out, const int32_t* act, hipStream_t s) {
   if (in == out) {
-    RTE_HIP(hipMemcpyAsync(lv[0].b, in, sizeof(double) * sp.total, hipMemcpyDeviceToDevice, s));
+    RTE_HIP(hipMemcpyAsync(lv[0].b, in, esz() * sp.total, hipMemcpyDeviceToDevice, s));
     in = lv[0].b;
   }
   return vcycle(0, in, out, act, s);
@@ -1078,8 +1127,12 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
   const int n = b->n_inst;
   const int mr = b->max_regions;
   if (prep) RTE_TRY(prepare(sigma_t, sigma_s, active, s));
-  hipLaunchKernelGGL(k_dsa_rhs, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_region, sigma_s,
-                     mr, sp.d_off, v, rhs, active);
+  if (f32)
+    hipLaunchKernelGGL(k_dsa_rhs<float>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_region, sigma_s,
+                       mr, sp.d_off, v, reinterpret_cast<float*>(rhs), active);
+  else
+    hipLaunchKernelGGL(k_dsa_rhs<double>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_region,
+                       sigma_s, mr, sp.d_off, v, rhs, active);
   RTE_HIP(hipGetLastError());
   std::vector<int32_t> iters(n, 0);
   if (restart == 0) {
@@ -1090,7 +1143,13 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
       } else {
         RTE_TRY(stencil(0, 1, 0, rhs, X, lv[0].b, active, s));
         RTE_TRY(vcycle(0, lv[0].b, lv[0].x, active, s));
-        RTE_TRY(kaxpby(sp, 1.0, lv[0].x, 1.0, X, active, s));
+        if (f32)
+          hipLaunchKernelGGL(k_dsa_axpy<float>, grid(0), dim3(256), 0, s, sp.d_off, sp.d_len,
+                             reinterpret_cast<const float*>(lv[0].x), reinterpret_cast<float*>(X), active);
+        else
+          hipLaunchKernelGGL(k_dsa_axpy<double>, grid(0), dim3(256), 0, s, sp.d_off, sp.d_len, lv[0].x, X,
+                             active);
+        RTE_HIP(hipGetLastError());
       }
     }
     for (int q = 0; q < n; ++q) iters[q] = inner_max;
@@ -1150,7 +1209,12 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
       RTE_HIP(hipMemcpyAsync(d_live, live_h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     }
   }
-  hipLaunchKernelGGL(k_dsa_out, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, sp.d_off, X, v, z, active);
+  if (f32)
+    hipLaunchKernelGGL(k_dsa_out<float>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, sp.d_off,
+                       reinterpret_cast<const float*>(X), v, z, active);
+  else
+    hipLaunchKernelGGL(k_dsa_out<double>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, sp.d_off, X, v, z,
+                       active);
   RTE_HIP(hipGetLastError());
   if (iters_host) {
     RTE_HIP(hipStreamSynchronize(s));

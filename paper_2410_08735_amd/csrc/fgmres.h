@@ -29,7 +29,7 @@ struct Fgmres {
   int init(rte_batch* b, int m);
   void release();
   void rec_release();
-  int precondition(int jj, const double* v, double* z, const SolveCtx& c, hipStream_t s,
+  int precondition(int jj, int cycle, const double* v, double* z, const SolveCtx& c, hipStream_t s,
                    std::vector<int32_t>& which);
   int solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s);
 };

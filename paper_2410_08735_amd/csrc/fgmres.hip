@@ -71,11 +71,12 @@ __global__ void k_stall_check(int n, const double* __restrict__ scal, const int3
   if (prev > 0.0 && est > 0.5 * prev) off[b] = 1;
 }
 
-int Fgmres::precondition(int jj, const double* v, double* z, const SolveCtx& c, hipStream_t s,
+int Fgmres::precondition(int jj, int cycle, const double* v, double* z, const SolveCtx& c, hipStream_t s,
                          std::vector<int32_t>& which) {
   const rte_solve_opts& o = *c.opts;
   int kind = o.precond;
-  if ((kind == RTE_PC_ROMSAD || kind == RTE_PC_MLP) && (jj > o.window || !c.rom)) kind = RTE_PC_DSA;
+  const bool in_window = jj <= o.window && (o.window_cycles <= 0 || cycle < o.window_cycles);
+  if ((kind == RTE_PC_ROMSAD || kind == RTE_PC_MLP) && (!in_window || !c.rom)) kind = RTE_PC_DSA;
   if (kind == RTE_PC_MLP && !c.mlp) kind = RTE_PC_ROMSAD;
   which.assign(b->n_inst, kind);
   switch (kind) {
@@ -164,13 +165,13 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       bool any = false;
       for (int q = 0; q < n; ++q) any = any || act[q];
       if (!any) break;
-      RTE_TRY(precondition(j + 1, K.v(j), K.z(j), c, s, which));
+      RTE_TRY(precondition(j + 1, cycle, K.v(j), K.z(j), c, s, which));
       // w = A~ z_j = z_j - T Sigma_s z_j
       RTE_TRY(sweep_launch(b, pin, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s,
                            K.active, batch_cell_ordinates(b, act.data())));
       RTE_TRY(reduce_partials(b, pin, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active));
       RTE_TRY(arnoldi_mgs(K, j, s));
-      if (o.precond == RTE_PC_MLP && j + 1 <= o.window) {
+      if (o.precond == RTE_PC_MLP && j + 1 <= o.window && (o.window_cycles <= 0 || cycle < o.window_cycles)) {
         RTE_HIP(hipMemcpyAsync(cyc_step, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_stall_check, dim3((n + 63) / 64), dim3(64), 0, s, n, K.scal, cyc_step, flags);
         RTE_HIP(hipGetLastError());

@@ -36,8 +36,33 @@ struct Vec4 {
   real v[4];
 };
 
-__device__ __forceinline__ double shfl_xor_r(double x, int m, int w) { return __shfl_xor(x, m, w); }
-__device__ __forceinline__ float shfl_xor_r(float x, int m, int w) { return __shfl_xor(x, m, w); }
+// Cross-lane moves inside a 16-lane DPP row: quad_perm [1,0,3,2] (xor 1),
+// quad_perm [2,3,0,1] (xor 2), row_half_mirror (i <-> 7 - i within 8 lanes) and
+// row_mirror (i <-> 15 - i).  Every lane reads a valid source lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each aligned group of G adjacent lanes; every lane of the group
+// receives the group's sum.  Steps inside a row use DPP; across rows (G = 32)
+// a cross-lane shuffle.
+template <int G, typename real>
+__device__ __forceinline__ real group_sum(real c) {
+  if (G >= 2) c += dpp_move<0xB1>(c);
+  if (G >= 4) c += dpp_move<0x4E>(c);
+  if (G >= 8) c += dpp_move<0x141>(c);
+  if (G >= 16) c += dpp_move<0x140>(c);
+  if (G >= 32) c += __shfl_xor(c, 16, 32);
+  return c;
+}
 
 // Closed-form solve of (sig I + a K(x)I + b I(x)K) x = r, dof order p + 2q.
 // Algebra elements (al, be) stand for al I + be K acting on the p-pair.
@@ -80,8 +105,12 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
     const double* __restrict__ sigma_t, const double* __restrict__ sigma_s, int max_regions,
     const double* __restrict__ qx, const double* __restrict__ qadd,
     const double* __restrict__ inflow, real* __restrict__ part, double* __restrict__ psi_out,
-    const int32_t* __restrict__ active) {
-  const SweepItem it = items[blockIdx.x];
+    const int32_t* __restrict__ active, int n_items, int per_xcd) {
+  // Work groups are dealt to the 8 XCDs round robin; give each XCD a contiguous
+  // run of items, so an instance's ordinate blocks share one L2.
+  const int item = (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+  if (item >= n_items) return;
+  const SweepItem it = items[item];
   if (active && !active[it.inst]) return;
   const InstDev I = insts[it.inst];
   const int tid = threadIdx.x;
@@ -143,12 +172,9 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
       xtr[(r * G + g) * 2 + 1] = x[2] + r3 * x[3];
       ytr[(i * G + g) * 2] = x[0] + r3 * x[2];
       ytr[(i * G + g) * 2 + 1] = x[1] + r3 * x[3];
-      real c[4] = {wt * x[0], wt * x[1], wt * x[2], wt * x[3]};
+      real c[4];
 #pragma unroll
-      for (int m = G / 2; m >= 1; m >>= 1) {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) c[d] += shfl_xor_r(c[d], m, G);
-      }
+      for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(wt * x[d]);
       if (g == 0) {
         real* o = P + 4 * (int64_t)cell;
         o[0] = c[0];
@@ -336,10 +362,11 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
                     hipStream_t s, const int32_t* active) {
   const size_t lds = (size_t)(b->max_nx + b->max_ny) * G * 2 * sizeof(real);
   if (lds > 64 * 1024) return RTE_EINVAL;  // per-work-group LDS limit used by this library
-  hipLaunchKernelGGL((sweep2d_kernel<real, G>), dim3(p.n_items), dim3(p.threads), lds, s,
+  const int per_xcd = (p.n_items + 7) / 8;
+  hipLaunchKernelGGL((sweep2d_kernel<real, G>), dim3(8 * per_xcd), dim3(p.threads), lds, s,
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
                      sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
-                     reinterpret_cast<real*>(b->d_part), psi_out, active);
+                     reinterpret_cast<real*>(b->d_part), psi_out, active, p.n_items, per_xcd);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }
