@@ -842,6 +842,165 @@ __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __res
   }
 }
 
+// ---------------------------------------------------------------- small levels
+// The coarse end of the hierarchy (every level from `first` down) fits in LDS:
+// one work group per instance runs that part of the V-cycle with each level's
+// x and b in shared memory, replacing a chain of small launches.
+constexpr int MG_TAIL_MAX = 10;
+
+struct MgTailLevel {
+  const LvlInst* li;
+  const DsaStencil* st;
+  const double* sigt;
+  const double* sigs;
+};
+
+// One red-black half sweep on an LDS level (from_zero: the colour-0 sweep from
+// x = 0, which also clears colour 1).
+template <typename real>
+__device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const double* __restrict__ st,
+                                const double* __restrict__ ss, const real* bv, real* x, int color,
+                                bool from_zero) {
+  const int nx = L.nx, ny = L.ny, nc = nx * ny;
+  for (int cell = threadIdx.x; cell < nc; cell += blockDim.x) {
+    const int i = cell % nx, k = cell / nx;
+    const bool mine = ((i + k) & 1) == color;
+    if (!mine && !from_zero) continue;
+    const CellPos P = cell_pos(i, k, nx, ny);
+    const real tt = (real)st[L.cell_off + cell], uu = (real)ss[L.cell_off + cell];
+    real r[12], d[12];
+    if (from_zero) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) r[q] = mine ? bv[q * nc + cell] : (real)0;
+      if (mine) sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) x[q * nc + cell] = mine ? d[q] : (real)0;
+    } else {
+      real yy[12];
+      sym_cell_apply(S, tt, uu, x, P, yy);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell] - yy[q];
+      sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) x[q * nc + cell] += d[q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restrict__ tl, int nlev, int nu_smooth,
+                                                     int coarse_sweeps, const real* __restrict__ b_first,
+                                                     real* __restrict__ x_first,
+                                                     const int32_t* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  extern __shared__ unsigned char smem_raw[];
+  real* lds = reinterpret_cast<real*>(smem_raw);
+  __shared__ int off[MG_TAIL_MAX + 1];
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const LvlInst Li = tl[l].li[b];
+      off[l + 1] = off[l] + 2 * 12 * Li.nx * Li.ny;  // x then b
+    }
+  }
+  __syncthreads();
+  {  // load b of the first level
+    const LvlInst L0 = tl[0].li[b];
+    const int n0 = 12 * L0.nx * L0.ny;
+    const real* src = b_first + L0.cell_off * 12;
+    for (int e = threadIdx.x; e < n0; e += blockDim.x) lds[off[0] + n0 + e] = src[e];
+  }
+  __syncthreads();
+  // down: pre-smooth from zero, then residual -> next level's b
+  for (int l = 0; l + 1 < nlev; ++l) {
+    const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
+    const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
+    real* x = lds + off[l];
+    real* bv = x + 12 * nc;
+    for (int k = 0; k < nu_smooth; ++k) {
+      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 0, k == 0);
+      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 1, false);
+    }
+    real* bc = lds + off[l + 1] + 12 * ncc;
+    for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
+      const int I = c % C.nx, K = c / C.nx;
+      real acc[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) acc[q] = (real)0;
+#pragma unroll 1
+      for (int ch = 0; ch < 4; ++ch) {
+        const int di = ch & 1, dk = ch >> 1;
+        const CellPos P = cell_pos(2 * I + di, 2 * K + dk, L.nx, L.ny);
+        real yy[12];
+        sym_cell_apply(S, (real)tl[l].sigt[L.cell_off + P.cell], (real)tl[l].sigs[L.cell_off + P.cell], x, P, yy);
+#pragma unroll
+        for (int fld = 0; fld < 3; ++fld)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const real rv = bv[(4 * fld + m) * nc + P.cell] - yy[4 * fld + m];
+#pragma unroll
+            for (int L2 = 0; L2 < 4; ++L2)
+              acc[4 * fld + L2] += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * rv;
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < 12; ++q) bc[q * ncc + c] = acc[q];
+    }
+    __syncthreads();
+  }
+  {  // coarsest: red-black sweeps from zero
+    const int l = nlev - 1;
+    const LvlInst L = tl[l].li[b];
+    const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    real* x = lds + off[l];
+    real* bv = x + 12 * L.nx * L.ny;
+    for (int k = 0; k < coarse_sweeps; ++k) {
+      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 0, k == 0);
+      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 1, false);
+    }
+  }
+  // up: prolong the correction, post-smooth in reverse colour order
+  for (int l = nlev - 2; l >= 0; --l) {
+    const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
+    const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
+    real* x = lds + off[l];
+    real* bv = x + 12 * nc;
+    const real* xc = lds + off[l + 1];
+    for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
+      const int I = c % C.nx, K = c / C.nx;
+      for (int ch = 0; ch < 4; ++ch) {
+        const int di = ch & 1, dk = ch >> 1;
+        const int f = (2 * K + dk) * L.nx + 2 * I + di;
+#pragma unroll
+        for (int fld = 0; fld < 3; ++fld)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            real v = (real)0;
+#pragma unroll
+            for (int L2 = 0; L2 < 4; ++L2)
+              v += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * xc[(4 * fld + L2) * ncc + c];
+            x[(4 * fld + m) * nc + f] += v;
+          }
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < nu_smooth; ++k) {
+      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 1, false);
+      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 0, false);
+    }
+  }
+  {  // store x of the first level
+    const LvlInst L0 = tl[0].li[b];
+    const int n0 = 12 * L0.nx * L0.ny;
+    real* dst = x_first + L0.cell_off * 12;
+    for (int e = threadIdx.x; e < n0; e += blockDim.x) dst[e] = lds[off[0] + e];
+  }
+}
+
 // ------------------------------------------------------------------ host side
 struct MgLevel {
   std::vector<LvlInst> li;
@@ -869,6 +1028,10 @@ struct DsaSolver {
   // general-rule kernels stay in FP64.
   bool f32 = false;
   size_t esz() const { return f32 ? sizeof(float) : sizeof(double); }
+  // the LDS-resident tail of the hierarchy (structured kernels only)
+  int tail_first = -1;
+  size_t tail_lds = 0;
+  MgTailLevel* d_tail = nullptr;
   int nu_smooth = 2, coarse_sweeps = 20;
   int init(rte_batch* batch, int restart_);
   void release();
@@ -964,6 +1127,23 @@ int DsaSolver::init(rte_batch* batch, int restart_) {
     for (int k = 0; k < n; ++k) sym = sym && hs[k].sym;
     f32 = sym && restart == 0;
   }
+  if (sym) {
+    // first level l >= 1 from which every level's x and b fit in 64 KB of LDS
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    size_t need = 0;
+    for (int l = nlev - 1; l >= 1; --l) {
+      need += (size_t)2 * 12 * lv[l].max_nx * lv[l].max_ny * es;
+      if (need > 60 * 1024 || nlev - l > MG_TAIL_MAX) break;
+      tail_first = l;
+      tail_lds = need;
+    }
+    if (tail_first > 0) {
+      std::vector<MgTailLevel> h;
+      for (int l = tail_first; l < nlev; ++l) h.push_back({lv[l].d_li, lv[l].d_st, lv[l].st, lv[l].ss});
+      if (hipMalloc(&d_tail, sizeof(MgTailLevel) * h.size()) != hipSuccess) return RTE_ENOMEM;
+      RTE_HIP(hipMemcpy(d_tail, h.data(), sizeof(MgTailLevel) * h.size(), hipMemcpyHostToDevice));
+    }
+  }
   std::vector<int64_t> lens(n);
   for (int k = 0; k < n; ++k) lens[k] = (int64_t)lv[0].li[k].nx * lv[0].li[k].ny * nu;
   RTE_TRY(sp.init(lens));
@@ -988,8 +1168,11 @@ void DsaSolver::release() {
                     (void*)L.b, (void*)L.r})
       (void)hipFree(p);
   lv.clear();
-  for (void* p : {(void*)inv0, (void*)X, (void*)T, (void*)rhs, (void*)tol, (void*)rn, (void*)d_live})
+  for (void* p : {(void*)inv0, (void*)X, (void*)T, (void*)rhs, (void*)tol, (void*)rn, (void*)d_live,
+                  (void*)d_tail})
     (void)hipFree(p);
+  d_tail = nullptr;
+  tail_first = -1;
   inv0 = X = T = rhs = tol = rn = nullptr;
   d_live = nullptr;
 }
@@ -1059,6 +1242,17 @@ int DsaSolver::smooth(int l, int sweeps, bool reverse, bool from_zero, const dou
 // x = V-cycle approximation of K_l^{-1} bv (bv and x must not alias)
 int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hipStream_t s) {
   MgLevel& L = lv[l];
+  if (l == tail_first) {
+    const int nt = (int)lv.size() - l;
+    if (f32)
+      hipLaunchKernelGGL(k_mg_tail_sym<float>, dim3(b->n_inst), dim3(256), tail_lds, s, d_tail, nt, nu_smooth,
+                         coarse_sweeps, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x), act);
+    else
+      hipLaunchKernelGGL(k_mg_tail_sym<double>, dim3(b->n_inst), dim3(256), tail_lds, s, d_tail, nt, nu_smooth,
+                         coarse_sweeps, bv, x, act);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   if (l == (int)lv.size() - 1) {
     if (sym && l > 0) {  // whole coarsest smoothing in one launch
       if (f32)
