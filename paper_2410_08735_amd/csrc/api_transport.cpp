@@ -47,3 +47,18 @@ extern "C" int rte_rhs(const rte_batch* cb, const double* sigma_t, const double*
   RTE_TRY(rte::sweep_launch(b, prec, sigma_t, nullptr, nullptr, G, inflow, nullptr, s));
   return rte::reduce_partials(b, prec, 1.0, nullptr, 0.0, b_out, s);
 }
+
+extern "C" int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int threads) {
+  return rte::set_sweep_plan(b, prec_of(dtype), variant, G, threads);
+}
+
+extern "C" int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out) {
+  const int prec = prec_of(dtype);
+  if (!b || prec < 0 || !out) return RTE_EINVAL;
+  const rte::Plan& p = b->plan[prec];
+  out[0] = p.variant;
+  out[1] = p.G;
+  out[2] = p.threads;
+  out[3] = p.tuned ? 1 : 0;
+  return RTE_OK;
+}

@@ -62,6 +62,7 @@ struct SweepItem {
 struct Plan {
   int G = 8;       // ordinates per work group (2D); 1D uses one thread per ordinate
   int threads = 256;
+  int variant = 0;  // 2D kernel: 0 = diagonal-slot order, 1 = row-slot order with source prefetch
   std::vector<SweepItem> items;
   std::vector<InstPart> parts;
   SweepItem* d_items = nullptr;
@@ -101,6 +102,7 @@ namespace rte {
 
 int ensure_partials(rte_batch* b, int64_t elems);
 int make_plan(rte_batch* b, int prec, int G, int threads);
+int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int threads);
 // prof_units: cell-ordinates processed by this launch (for the event profiler);
 // negative = every instance of the batch.
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,

@@ -64,6 +64,10 @@ __device__ __forceinline__ real group_sum(real c) {
   return c;
 }
 
+// 1/x: the hardware reciprocal (1 ulp) in FP32, a correctly rounded division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Closed-form solve of (sig I + a K(x)I + b I(x)K) x = r, dof order p + 2q.
 // Algebra elements (al, be) stand for al I + be K acting on the p-pair.
 template <typename real>
@@ -78,7 +82,7 @@ __device__ __forceinline__ void local_solve(real sig, real a, real b, const real
   const real sb = (det0 - b2) * a;
   const real detS = sa * sa + (real)4 * sa * sb + (real)6 * sb * sb;
   const real adjSa = sa + (real)4 * sb, adjSb = -sb;
-  const real inv = (real)1 / (det0 * detS);
+  const real inv = recip(det0 * detS);
   // u = adj0 r0, r0 = (r[0], r[1])
   real k0 = r[0] + r3 * r[1], k1 = -r3 * r[0] + (real)3 * r[1];
   const real u0 = adj0a * r[0] + adj0b * k0, u1 = adj0a * r[1] + adj0b * k1;
@@ -191,6 +195,144 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
       }
     }
     __syncthreads();
+  }
+}
+
+// LDS-only work-group barrier: this wave's LDS operations complete, then
+// s_barrier.  Global loads stay in flight across it (they feed the next
+// diagonal); the empty asm statements stop the compiler from moving memory
+// accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left open
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+constexpr int SWEEP_SIGMA_TAB = 256;  // regions whose cross sections are staged in LDS
+
+// The same sweep with a fixed row -> slot assignment (row r is handled by slot
+// r mod S), so a slot walks along its rows one cell per diagonal and loads the
+// source of its next cell while the current diagonal is processed: the global
+// load latency leaves the diagonal-to-diagonal dependence chain.  Every slot
+// issues the loads of all its rows on every diagonal (addresses clamped to the
+// grid), so the prefetched registers are plain loop-carried values.  MAXR
+// bounds the rows per slot (ceil(ny / S) <= MAXR); the instance's region cross
+// sections are staged in LDS (n_regions <= SWEEP_SIGMA_TAB).  SCALED: the
+// source is sigma_s * q, else q as is (qsrc must be given).
+template <typename real, int G, int MAXR, bool SCALED>
+__global__ void __launch_bounds__(512) sweep2d_rows_kernel(
+    const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
+    const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ region,
+    const double* __restrict__ sigma_t, const double* __restrict__ sigma_s, int max_regions,
+    const double* __restrict__ qsrc, const double* __restrict__ inflow,
+    real* __restrict__ part, double* __restrict__ psi_out, const int32_t* __restrict__ active, int n_items,
+    int per_xcd) {
+  const int item = (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+  if (item >= n_items) return;
+  const SweepItem it = items[item];
+  if (active && !active[it.inst]) return;
+  const InstDev I = insts[it.inst];
+  const int tid = threadIdx.x;
+  const int g = tid % G;
+  const int slot = tid / G;
+  const int S = blockDim.x / G;
+  const int nx = I.nx, ny = I.ny;
+  const bool lane_on = g < it.count;
+  const int js = I.ord_off + it.first + (lane_on ? g : 0);
+  const real a = (real)(fabs(ox[js]) / I.hx);
+  const real b = (real)(fabs(oy[js]) / I.hy);
+  const real wt = lane_on ? (real)w[js] : (real)0;
+  const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
+  const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
+  const real r3 = (real)1.7320508075688772935;
+  const real gin = inflow ? (real)(inflow[it.inst] * sqrt(I.hx * I.hy)) : (real)0;
+  extern __shared__ unsigned char smem_raw[];
+  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G][2]
+  real* ytr = xtr + (size_t)ny * G * 2;           // [nx][G][2]
+  real* tab = ytr + (size_t)nx * G * 2;           // [2][SWEEP_SIGMA_TAB]: sigma_t, sigma_s
+  {
+    const double* st = sigma_t + (size_t)it.inst * max_regions;
+    const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
+    for (int e = tid; e < I.n_regions; e += blockDim.x) {
+      tab[e] = (real)st[e];
+      tab[SWEEP_SIGMA_TAB + e] = SCALED ? (real)ss[e] : (real)1;
+    }
+  }
+  __syncthreads();
+  const int32_t* reg = region + I.region_off;
+  const double* qi = qsrc + I.dof_off;
+  real* P = part + it.part_off;
+  double* psi_j = nullptr;
+  if (psi_out && lane_on) psi_j = psi_out + I.psi_off + (int64_t)perm[js] * nx * ny * 4;
+  // physical cell of (mirrored column i, mirrored row r), both clamped into the grid
+  auto phys = [&](int i, int r) {
+    i = min(max(i, 0), nx - 1);
+    r = min(r, ny - 1);
+    return (fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 - i : i);
+  };
+
+  double4 qn[MAXR];
+  int rn[MAXR];
+#pragma unroll
+  for (int kk = 0; kk < MAXR; ++kk) {
+    const int c = phys(-kk * S - slot, slot + kk * S);  // the cell each row needs on diagonal 0
+    rn[kk] = reg[c];
+    qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)c);
+  }
+
+  for (int s = 0; s < nx + ny - 1; ++s) {
+#pragma unroll
+    for (int kk = 0; kk < MAXR; ++kk) {
+      const int r = slot + kk * S;
+      const int i = s - r;
+      if (r < ny && i >= 0 && i < nx) {
+        const double4 v = qn[kk];
+        const int rg = rn[kk];
+        const int cell = phys(i, r);
+        const real sig = tab[rg];
+        const real sc = tab[SWEEP_SIGMA_TAB + rg];
+        const real q0 = sc * (real)v.x, q1 = sc * (real)v.y, q2 = sc * (real)v.z, q3 = sc * (real)v.w;
+        real tx0, tx1, ty0, ty1;
+        if (i == 0) { tx0 = gin; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
+        if (r == 0) { ty0 = gin; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
+        real rhs[4];
+        rhs[0] = q0 + a * tx0 + b * ty0;
+        rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
+        rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
+        rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
+        real x[4];
+        local_solve<real>(sig, a, b, rhs, x);
+        xtr[(r * G + g) * 2] = x[0] + r3 * x[1];
+        xtr[(r * G + g) * 2 + 1] = x[2] + r3 * x[3];
+        ytr[(i * G + g) * 2] = x[0] + r3 * x[2];
+        ytr[(i * G + g) * 2 + 1] = x[1] + r3 * x[3];
+        real c[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(wt * x[d]);
+        if (g == 0) {
+          real* o = P + 4 * (int64_t)cell;
+          o[0] = c[0];
+          o[1] = mx * c[1];
+          o[2] = my * c[2];
+          o[3] = mx * my * c[3];
+        }
+        if (psi_j) {
+          double* o = psi_j + 4 * (int64_t)cell;
+          o[0] = (double)x[0];
+          o[1] = (double)(mx * x[1]);
+          o[2] = (double)(my * x[2]);
+          o[3] = (double)(mx * my * x[3]);
+        }
+      }
+      // source of this row's cell on the next diagonal (issued after the last
+      // use of the current one, so it can land in the same registers)
+      const int c = phys(i + 1, r);
+      rn[kk] = reg[c];
+      qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)c);
+    }
+    lds_barrier();
   }
 }
 
@@ -356,13 +498,43 @@ int make_plan(rte_batch* b, int prec, int G, int threads) {
   return ensure_partials(b, off);
 }
 
+// Whether the row-slot kernel can take this batch with G ordinates and T threads.
+static bool rows_variant_fits(const rte_batch* b, int G, int T) {
+  const int slots = T / G;
+  return slots > 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB;
+}
+
 template <typename real, int G>
 static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const double* sigma_s,
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
                     hipStream_t s, const int32_t* active) {
+  const int per_xcd = (p.n_items + 7) / 8;
+  if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, p.threads)) {
+    const int slots = p.threads / G;
+    const int nr = (b->max_ny + slots - 1) / slots;
+    const size_t lds = ((size_t)(b->max_nx + b->max_ny) * G * 2 + 2 * SWEEP_SIGMA_TAB) * sizeof(real);
+    if (lds > 64 * 1024) return RTE_EINVAL;
+    const double* src = qx ? qx : qadd;
+#define RTE_ROWS_LAUNCH(R, SC)                                                                          \
+  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, R, SC>), dim3(8 * per_xcd), dim3(p.threads), lds, s,  \
+                     b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t,   \
+                     sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(b->d_part), psi_out, \
+                     active, p.n_items, per_xcd)
+    if (qx) {
+      if (nr <= 2) RTE_ROWS_LAUNCH(2, true);
+      else if (nr <= 4) RTE_ROWS_LAUNCH(4, true);
+      else RTE_ROWS_LAUNCH(8, true);
+    } else {
+      if (nr <= 2) RTE_ROWS_LAUNCH(2, false);
+      else if (nr <= 4) RTE_ROWS_LAUNCH(4, false);
+      else RTE_ROWS_LAUNCH(8, false);
+    }
+#undef RTE_ROWS_LAUNCH
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   const size_t lds = (size_t)(b->max_nx + b->max_ny) * G * 2 * sizeof(real);
   if (lds > 64 * 1024) return RTE_EINVAL;  // per-work-group LDS limit used by this library
-  const int per_xcd = (p.n_items + 7) / 8;
   hipLaunchKernelGGL((sweep2d_kernel<real, G>), dim3(8 * per_xcd), dim3(p.threads), lds, s,
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
                      sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
@@ -462,6 +634,21 @@ int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s) {
   return RTE_OK;
 }
 
+int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int threads) {
+  if (!b || prec < 0 || prec > 1 || variant < 0 || variant > 1 || threads < 64 || threads > 512 ||
+      threads % 64 || (G != 1 && G != 2 && G != 4 && G != 8 && G != 16 && G != 32) || threads % G)
+    return RTE_EINVAL;
+  if (b->dim == 2) {
+    const size_t lds = ((size_t)(b->max_nx + b->max_ny) * G * 2 + 2 * SWEEP_SIGMA_TAB) * (prec == 0 ? 8 : 4);
+    if (lds > 64 * 1024) return RTE_EINVAL;
+    if (variant == 1 && !rows_variant_fits(b, G, threads)) return RTE_EINVAL;
+  }
+  RTE_TRY(make_plan(b, prec, G, threads));
+  b->plan[prec].variant = variant;
+  b->plan[prec].tuned = true;
+  return RTE_OK;
+}
+
 // Pick G (ordinates per work group) and the work-group size for this batch by
 // timing one sweep of each candidate that fits; the fastest plan is kept.
 int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s) {
@@ -477,25 +664,30 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s)
   if (hipMalloc(&q, sizeof(double) * b->total_dof) != hipSuccess) return RTE_ENOMEM;
   RTE_HIP(hipMemsetAsync(q, 0, sizeof(double) * b->total_dof, s));
   float best = 1e30f;
-  int bestG = cur.G, bestT = cur.threads;
-  for (int G : cand_G) {
-    for (int T : cand_T) {
-      if (T % G || T / G < 1) continue;
-      const size_t lds = (size_t)(b->max_nx + b->max_ny) * G * 2 * (prec == 0 ? 8 : 4);
-      if (lds > 64 * 1024) continue;
-      RTE_TRY(make_plan(b, prec, G, T));
-      RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
-      RTE_HIP(hipEventRecord(e0, s));
-      for (int rep = 0; rep < 3; ++rep)
+  int bestG = cur.G, bestT = cur.threads, bestV = 0;
+  for (int V = 0; V < 2; ++V) {
+    for (int G : cand_G) {
+      for (int T : cand_T) {
+        if (T % G || T / G < 1) continue;
+        if (V == 1 && !rows_variant_fits(b, G, T)) continue;
+        const size_t lds = ((size_t)(b->max_nx + b->max_ny) * G * 2 + 2 * SWEEP_SIGMA_TAB) * (prec == 0 ? 8 : 4);
+        if (lds > 64 * 1024) continue;
+        RTE_TRY(make_plan(b, prec, G, T));
+        b->plan[prec].variant = V;
         RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
-      RTE_HIP(hipEventRecord(e1, s));
-      RTE_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      RTE_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
-        bestG = G;
-        bestT = T;
+        RTE_HIP(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 3; ++rep)
+          RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
+        RTE_HIP(hipEventRecord(e1, s));
+        RTE_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        RTE_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          bestG = G;
+          bestT = T;
+          bestV = V;
+        }
       }
     }
   }
@@ -503,6 +695,7 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s)
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   RTE_TRY(make_plan(b, prec, bestG, bestT));
+  b->plan[prec].variant = bestV;
   b->plan[prec].tuned = true;
   return RTE_OK;
 }
