@@ -244,6 +244,16 @@ int rte_rom_from_basis(const rte_batch* b, const double* U, int r, rte_rom** out
 int romsad_apply(const rte_rom* rom, const rte_batch* b, const double* sigma_t,
                  const double* sigma_s, const double* v, double* z, void* stream);
 
+/* A ROM set serves a batch whose instances have different grids or
+ * quadratures (the uneven-batch pattern): instance k uses
+ * roms[rom_of_instance[k]] (host array [n_inst of b]), which must match its
+ * grid, ordinates and region map (RTE_EINVAL otherwise).  The set is accepted
+ * wherever fgmres_solve / romsad_apply take a ROM for RTE_PC_ROMSAD (not for
+ * the learned correction, export or save); it does not own the member ROMs,
+ * which must outlive it.  Destroy with rte_rom_destroy.                     */
+int rte_rom_set_create(const rte_batch* b, const rte_rom* const* roms, int n_roms,
+                       const int32_t* rom_of_instance, rte_rom** out);
+/* Basis size (the largest member's for a set). */
 int rte_rom_rank(const rte_rom* rom);
 /* Host copies of the ROM's arrays (each pointer nullable): U [r][n_ord][ndof],
  * W1, Ww [r][ndof], AD [r][r], G, S [n_regions][r][r].                        */

@@ -267,6 +267,18 @@ class Rom:
         check(L.lib().rte_rom_load(path.encode(), C.byref(h)), "rte_rom_load")
         return Rom(h)
 
+    @staticmethod
+    def set(batch, roms, rom_of_instance):
+        """A ROM set: instance k of `batch` uses roms[rom_of_instance[k]]."""
+        arr = (C.c_void_p * len(roms))(*[r.h for r in roms])
+        idx = np.ascontiguousarray(rom_of_instance, dtype=np.int32)
+        h = C.c_void_p()
+        check(L.lib().rte_rom_set_create(batch.h, arr, len(roms), idx.ctypes.data_as(L.pi32), C.byref(h)),
+              "rte_rom_set_create")
+        out = Rom(h)
+        out._members = list(roms)  # the members must outlive the set
+        return out
+
 
 def romsad_build_greedy(batch, sigma_t, sigma_s, G, inflow=None, window=2, mu1_index=0, eps_rom=1e-9,
                         n_giter=16, eps_qr=1e-13, hf_rtol=1e-11, hf_dsa_tol=0.0):

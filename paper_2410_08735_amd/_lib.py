@@ -71,6 +71,7 @@ SIGNATURES = {
                                       dbl, C.POINTER(vp), C.POINTER(GreedyReport), vp]),
     "rte_rom_from_basis": (C.c_int, [vp, vp, C.c_int, C.POINTER(vp), vp]),
     "romsad_apply": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+    "rte_rom_set_create": (C.c_int, [vp, C.POINTER(vp), C.c_int, pi32, C.POINTER(vp)]),
     "rte_rom_rank": (C.c_int, [vp]),
     "rte_rom_export": (C.c_int, [vp, pdbl, pdbl, pdbl, pdbl, pdbl, pdbl]),
     "rte_rom_save": (C.c_int, [vp, C.c_char_p]),

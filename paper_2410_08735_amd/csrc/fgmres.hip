@@ -282,6 +282,7 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
     return RTE_EINVAL;
   if ((o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && !rom) return RTE_EINVAL;
   if (rom && !rte::rom_matches(rom, b)) return RTE_EINVAL;
+  if (o.precond == RTE_PC_MLP && rom && rom->is_set()) return RTE_EINVAL;  // one network per ROM basis
   if (o.precond == RTE_PC_MLP && (!mlp || !mu || mu_dim < 1)) return RTE_EINVAL;
   rte::Fgmres* f = rte::fgmres_for(b, o.m);
   if (!f) return RTE_ENOMEM;

@@ -692,7 +692,7 @@ extern "C" int rte_mlp_snapshots(const rte_batch* cb, const double* sigma_t, con
                                  int32_t* valid, void* stream) {
   auto* b = const_cast<rte_batch*>(cb);
   if (!b || !sigma_t || !sigma_s || !G || !rom || !opts || !mu || mu_dim < 0 || !X || !T || !valid ||
-      rom->r < 1 || opts->window < 1 || opts->m < opts->window || !rom_matches(rom, b) ||
+      rom->is_set() || rom->r < 1 || opts->window < 1 || opts->m < opts->window || !rom_matches(rom, b) ||
       opts->precond == RTE_PC_MLP)
     return RTE_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -20,6 +20,11 @@ struct rte_rom {
   double* d_w = nullptr;  // [w | omega_x | omega_y], original ordinate order
   std::vector<double> oyv;
   double hx = 1.0, hy = 1.0;
+  // A ROM set (rte_rom_set_create): per-instance members of a batch with
+  // instances of several grids / quadratures; the members are not owned.
+  std::vector<const rte_rom*> members;
+  std::vector<int32_t> member_of;   // [n_inst of the batch it was made for]
+  bool is_set() const { return !members.empty(); }
 };
 
 // A view of a single MLP network (defined in mlp.hip)

@@ -21,6 +21,13 @@ namespace rte {
 constexpr int ROM_RMAX = 64;     // maximum basis size
 constexpr int ROM_REGMAX = 16;   // maximum number of regions of a ROM
 
+// What the online kernels read of the ROM that serves one instance.
+struct RomDev {
+  const double *W1, *Ww, *AD, *G, *S;
+  int32_t r, ld, nreg, pad;
+  int64_t nd;
+};
+
 // ------------------------------------------------------------------ kernels
 __device__ __forceinline__ double bsum256(double v, double* sh) {
 #pragma unroll
@@ -176,18 +183,27 @@ __global__ void k_place(int r, int rcap, int nreg, const double* __restrict__ d_
   }
 }
 
-// g[b][k] partials: sum over a chunk of W1[k][e] * (sigma_s(cell) v[b][e])
+// g[b][k] partials: sum over a chunk of W[k][e] * (sigma_s(cell) v[b][e]), with
+// W = W_1 (which = 0) or W_w (which = 1) of the instance's ROM.
 constexpr int PJ_CHUNK = 2048;
 __global__ void k_rom_project(const InstDev* __restrict__ insts, const int32_t* __restrict__ region,
                               const double* __restrict__ sigma_s, int max_regions,
-                              const double* __restrict__ W1, int r, int64_t nd,
+                              const RomDev* __restrict__ tab, int which,
                               const double* __restrict__ v, double* __restrict__ part, int nch,
                               const int32_t* __restrict__ active) {
   __shared__ double sh[4];
   const int b = blockIdx.y, c = blockIdx.x;
   if (active && !active[b]) return;
   const InstDev I = insts[b];
+  const RomDev R = tab[b];
+  const double* __restrict__ W = which ? R.Ww : R.W1;
+  const int64_t nd = R.nd;
+  const int r = R.r;
   const int64_t start = (int64_t)c * PJ_CHUNK;
+  if (start >= nd) {  // chunk beyond this instance: zero partials
+    for (int k = threadIdx.x; k < r; k += blockDim.x) part[((int64_t)b * nch + c) * ROM_RMAX + k] = 0.0;
+    return;
+  }
   double sv[PJ_CHUNK / 256];
 #pragma unroll
   for (int q = 0; q < PJ_CHUNK / 256; ++q) {
@@ -204,34 +220,38 @@ __global__ void k_rom_project(const InstDev* __restrict__ insts, const int32_t* 
 #pragma unroll
     for (int q = 0; q < PJ_CHUNK / 256; ++q) {
       const int64_t e = start + threadIdx.x + 256 * q;
-      if (e < nd) acc += W1[(int64_t)k * nd + e] * sv[q];
+      if (e < nd) acc += W[(int64_t)k * nd + e] * sv[q];
     }
     const double t = bsum256(acc, sh);
-    if (threadIdx.x == 0) part[((int64_t)b * nch + c) * r + k] = t;
+    if (threadIdx.x == 0) part[((int64_t)b * nch + c) * ROM_RMAX + k] = t;
   }
 }
 
-__global__ void k_rom_gsum(int n, int r, int nch, int rcap, const double* __restrict__ part,
+__global__ void k_rom_gsum(int n, int nch, const RomDev* __restrict__ tab, const double* __restrict__ part,
                            double* __restrict__ g, const int32_t* __restrict__ active) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n * r) return;
-  const int b = id / r, k = id % r;
-  if (active && !active[b]) return;
+  if (id >= n * ROM_RMAX) return;
+  const int b = id / ROM_RMAX, k = id % ROM_RMAX;
+  if ((active && !active[b]) || k >= tab[b].r) return;
   double t = 0.0;
-  for (int c = 0; c < nch; ++c) t += part[((int64_t)b * nch + c) * r + k];
-  g[(int64_t)b * rcap + k] = t;
+  for (int c = 0; c < nch; ++c) t += part[((int64_t)b * nch + c) * ROM_RMAX + k];
+  g[(int64_t)b * ROM_RMAX + k] = t;
 }
 
 // c = (A_D + sum_R st_R G_R - ss_R S_R)^{-1} g, LU with partial pivoting,
 // one work group of 64 threads per instance.
-__global__ void k_rom_solve(int n, int r, int ld, int nreg, const double* __restrict__ AD,
-                            const double* __restrict__ G, const double* __restrict__ S,
+__global__ void k_rom_solve(int n, const RomDev* __restrict__ tab,
                             const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
                             int max_regions, const double* __restrict__ g, double* __restrict__ c,
                             int gstride, int32_t* __restrict__ singular,
                             const int32_t* __restrict__ active) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
+  const RomDev Rd = tab[b];
+  const int r = Rd.r, ld = Rd.ld, nreg = Rd.nreg;
+  const double* __restrict__ AD = Rd.AD;
+  const double* __restrict__ G = Rd.G;
+  const double* __restrict__ S = Rd.S;
   __shared__ double A[ROM_RMAX][ROM_RMAX + 1];
   __shared__ double rhs[ROM_RMAX];
   __shared__ int piv_s;
@@ -308,14 +328,17 @@ __global__ void k_rom_solve(int n, int r, int ld, int nreg, const double* __rest
 }
 
 // z = v + sum_k c[b][k] Ww[k]
-__global__ void k_rom_lift(const InstDev* __restrict__ insts, const double* __restrict__ Ww, int r,
-                           int rcap, int64_t nd, const double* __restrict__ v,
-                           const double* __restrict__ c, double* __restrict__ z,
+__global__ void k_rom_lift(const InstDev* __restrict__ insts, const RomDev* __restrict__ tab,
+                           const double* __restrict__ v, const double* __restrict__ c, double* __restrict__ z,
                            const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
+  const RomDev R = tab[b];
+  const double* __restrict__ Ww = R.Ww;
+  const int r = R.r;
+  const int64_t nd = R.nd;
   __shared__ double cs[ROM_RMAX];
-  for (int k = threadIdx.x; k < r; k += blockDim.x) cs[k] = c[(int64_t)b * rcap + k];
+  for (int k = threadIdx.x; k < r; k += blockDim.x) cs[k] = c[(int64_t)b * ROM_RMAX + k];
   __syncthreads();
   const InstDev I = insts[b];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nd;
@@ -419,6 +442,11 @@ struct RomScratch {
   double *g = nullptr, *c = nullptr, *part = nullptr;
   int32_t* sing = nullptr;
   int64_t part_elems = 0;
+  // per-instance ROM table of the last ROM used on this batch
+  RomDev* d_tab = nullptr;
+  std::vector<RomDev> h_tab;
+  const rte_rom* tab_rom = nullptr;
+  int64_t tab_key = -1;
 };
 static std::vector<RomScratch> g_rs;
 
@@ -445,6 +473,57 @@ static RomScratch* scratch_for(const rte_batch* b, int64_t part_elems) {
   return &g_rs.back();
 }
 
+static RomDev rom_dev(const rte_rom* m) {
+  RomDev d;
+  d.W1 = m->W1;
+  d.Ww = m->Ww;
+  d.AD = m->AD;
+  d.G = m->G;
+  d.S = m->S;
+  d.r = m->r;
+  d.ld = m->rcap;
+  d.nreg = m->n_regions;
+  d.pad = 0;
+  d.nd = m->ndof;
+  return d;
+}
+
+// The per-instance table of the ROM (or ROM set) serving batch b, rebuilt
+// when the ROM or the rank of any member changed since the last call.
+static const RomDev* rom_table(const rte_rom* rom, RomScratch* sc, const rte_batch* b, hipStream_t s) {
+  int64_t key = 0;
+  if (rom->is_set())
+    for (const rte_rom* m : rom->members) key = key * 131 + m->r + 1;
+  else
+    key = rom->r + 1;
+  if (sc->tab_rom == rom && sc->tab_key == key && sc->d_tab) return sc->d_tab;
+  if (!sc->d_tab && hipMalloc(&sc->d_tab, sizeof(RomDev) * b->n_inst) != hipSuccess) return nullptr;
+  sc->h_tab.resize(b->n_inst);
+  for (int k = 0; k < b->n_inst; ++k)
+    sc->h_tab[k] = rom_dev(rom->is_set() ? rom->members[rom->member_of[k]] : rom);
+  if (hipMemcpyAsync(sc->d_tab, sc->h_tab.data(), sizeof(RomDev) * b->n_inst, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return nullptr;
+  sc->tab_rom = rom;
+  sc->tab_key = key;
+  return sc->d_tab;
+}
+
+static int rom_max_rank(const rte_rom* rom) {
+  if (!rom->is_set()) return rom->r;
+  int r = 0;
+  for (const rte_rom* m : rom->members) r = std::max(r, m->r);
+  return r;
+}
+
+static int64_t rom_max_ndof(const rte_rom* rom) {
+  if (!rom->is_set()) return rom->ndof;
+  int64_t nd = 0;
+  for (const rte_rom* m : rom->members) nd = std::max(nd, m->ndof);
+  return nd;
+}
+
 void rom_scratch_forget(const rte_batch* b) {
   for (size_t i = 0; i < g_rs.size();) {
     if (g_rs[i].b == b) {
@@ -452,6 +531,7 @@ void rom_scratch_forget(const rte_batch* b) {
       (void)hipFree(g_rs[i].c);
       (void)hipFree(g_rs[i].part);
       (void)hipFree(g_rs[i].sing);
+      (void)hipFree(g_rs[i].d_tab);
       g_rs.erase(g_rs.begin() + i);
     } else {
       ++i;
@@ -573,7 +653,25 @@ int rom_add_column(rte_rom* rom, const rte_batch* b, hipStream_t s) {
   return st;
 }
 
+static bool rom_matches_inst(const rte_rom* rom, const rte_batch* b, int k) {
+  const InstDev& I = b->inst[k];
+  if (I.dim != rom->dim || I.nx != rom->nx || I.ny != rom->ny || I.n_ord != rom->n_ord ||
+      I.n_regions > rom->n_regions)
+    return false;
+  for (int s = 0; s < I.n_ord; ++s) {
+    const int j = b->perm[I.ord_off + s];
+    if (b->ox[I.ord_off + s] != rom->ox[j] || b->w[I.ord_off + s] != rom->w[j]) return false;
+  }
+  return true;
+}
+
 bool rom_matches(const rte_rom* rom, const rte_batch* b) {
+  if (rom->is_set()) {
+    if ((int)rom->member_of.size() != b->n_inst) return false;
+    for (int k = 0; k < b->n_inst; ++k)
+      if (!rom_matches_inst(rom->members[rom->member_of[k]], b, k)) return false;
+    return true;
+  }
   for (int k = 0; k < b->n_inst; ++k) {
     const InstDev& I = b->inst[k];
     if (I.dim != rom->dim || I.nx != rom->nx || I.ny != rom->ny || I.n_ord != rom->n_ord ||
@@ -589,25 +687,31 @@ bool rom_matches(const rte_rom* rom, const rte_batch* b) {
 
 int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const double* v, double* g,
                 const int32_t* active, hipStream_t s, const double* W) {
-  const int r = rom->r;
-  const int64_t nd = rom->ndof;
+  const int64_t nd = rom_max_ndof(rom);
   const int nch = (int)((nd + PJ_CHUNK - 1) / PJ_CHUNK);
-  RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * std::max(r, 1));
+  RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * ROM_RMAX);
   if (!sc) return RTE_ENOMEM;
+  const RomDev* tab = rom_table(rom, sc, b, s);
+  if (!tab) return RTE_EHIP;
+  const int which = (W && !rom->is_set() && W == rom->Ww) ? 1 : 0;
+  if (W && !which) return RTE_EINVAL;  // only W_1 or W_w of the ROM itself
   hipLaunchKernelGGL(k_rom_project, dim3(nch, b->n_inst), dim3(256), 0, s, b->d_inst, b->d_region,
-                     sigma_s, b->max_regions, W ? W : rom->W1, r, nd, v, sc->part, nch, active);
-  hipLaunchKernelGGL(k_rom_gsum, dim3((b->n_inst * r + 63) / 64), dim3(64), 0, s, b->n_inst, r, nch,
-                     ROM_RMAX, sc->part, g, active);
+                     sigma_s, b->max_regions, tab, which, v, sc->part, nch, active);
+  hipLaunchKernelGGL(k_rom_gsum, dim3((b->n_inst * ROM_RMAX + 63) / 64), dim3(64), 0, s, b->n_inst, nch, tab,
+                     sc->part, g, active);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }
 
 int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c, double* z,
              const int32_t* active, hipStream_t s) {
-  const int64_t nd = rom->ndof;
+  const int64_t nd = rom_max_ndof(rom);
+  RomScratch* sc = scratch_for(b, 1);
+  if (!sc) return RTE_ENOMEM;
+  const RomDev* tab = rom_table(rom, sc, b, s);
+  if (!tab) return RTE_EHIP;
   dim3 grid((unsigned)std::min<int64_t>((nd + 255) / 256, 256), b->n_inst);
-  hipLaunchKernelGGL(k_rom_lift, grid, dim3(256), 0, s, b->d_inst, rom->Ww, rom->r, ROM_RMAX, nd, v,
-                     c, z, active);
+  hipLaunchKernelGGL(k_rom_lift, grid, dim3(256), 0, s, b->d_inst, tab, v, c, z, active);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }
@@ -615,22 +719,23 @@ int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c,
 int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_t,
                           const double* sigma_s, const double* v, double* z, const int32_t* active,
                           hipStream_t s, double* gout, double* cout, int32_t* singular) {
-  if (rom->r == 0) {
+  if (rom_max_rank(rom) == 0) {
     RTE_HIP(hipMemcpyAsync(z, v, sizeof(double) * b->total_dof, hipMemcpyDeviceToDevice, s));
     return RTE_OK;
   }
-  const int64_t nd = rom->ndof;
+  const int64_t nd = rom_max_ndof(rom);
   const int nch = (int)((nd + PJ_CHUNK - 1) / PJ_CHUNK);
-  RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * rom->r);
+  RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * ROM_RMAX);
   if (!sc) return RTE_ENOMEM;
+  const RomDev* tab = rom_table(rom, sc, b, s);
+  if (!tab) return RTE_EHIP;
   double* g = gout ? gout : sc->g;
   double* c = cout ? cout : sc->c;
   int32_t* sing = singular ? singular : sc->sing;
   RTE_TRY(rom_project(rom, b, sigma_s, v, g, active, s));
   RTE_HIP(hipMemsetAsync(sing, 0, sizeof(int32_t) * b->n_inst, s));
-  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(64), 0, s, b->n_inst, rom->r, rom->rcap,
-                     rom->n_regions, rom->AD, rom->G, rom->S, sigma_t, sigma_s, b->max_regions, g, c,
-                     ROM_RMAX, sing, active);
+  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(64), 0, s, b->n_inst, tab, sigma_t, sigma_s,
+                     b->max_regions, g, c, ROM_RMAX, sing, active);
   RTE_HIP(hipGetLastError());
   return rom_lift(rom, b, v, c, z, active, s);
 }
@@ -684,7 +789,33 @@ extern "C" int romsad_apply(const rte_rom* rom, const rte_batch* cb, const doubl
   return RTE_OK;
 }
 
-extern "C" int rte_rom_rank(const rte_rom* rom) { return rom ? rom->r : -1; }
+extern "C" int rte_rom_rank(const rte_rom* rom) { return rom ? rom_max_rank(rom) : -1; }
+
+extern "C" int rte_rom_set_create(const rte_batch* b, const rte_rom* const* roms, int n_roms,
+                                  const int32_t* rom_of_instance, rte_rom** out) {
+  if (!b || !roms || n_roms < 1 || !rom_of_instance || !out) return RTE_EINVAL;
+  auto* set = new rte_rom();
+  for (int i = 0; i < n_roms; ++i) {
+    if (!roms[i] || roms[i]->is_set()) {
+      delete set;
+      return RTE_EINVAL;
+    }
+    set->members.push_back(roms[i]);
+  }
+  set->member_of.assign(rom_of_instance, rom_of_instance + b->n_inst);
+  for (int k = 0; k < b->n_inst; ++k)
+    if (set->member_of[k] < 0 || set->member_of[k] >= n_roms) {
+      delete set;
+      return RTE_EINVAL;
+    }
+  if (!rom_matches(set, b)) {
+    delete set;
+    return RTE_EINVAL;
+  }
+  set->r = rom_max_rank(set);
+  *out = set;
+  return RTE_OK;
+}
 
 static int copy_mat(double* dst, const double* src, int r, int ld) {
   std::vector<double> tmp((size_t)ld * ld);
@@ -696,7 +827,7 @@ static int copy_mat(double* dst, const double* src, int r, int ld) {
 
 extern "C" int rte_rom_export(const rte_rom* rom, double* U, double* W1, double* Ww, double* AD,
                               double* G, double* S) {
-  if (!rom) return RTE_EINVAL;
+  if (!rom || rom->is_set()) return RTE_EINVAL;
   RTE_HIP(hipDeviceSynchronize());
   const int r = rom->r;
   if (U) RTE_HIP(hipMemcpy(U, rom->U, sizeof(double) * r * rom->npsi, hipMemcpyDeviceToHost));
@@ -713,7 +844,8 @@ extern "C" int rte_rom_export(const rte_rom* rom, double* U, double* W1, double*
 
 extern "C" void rte_rom_destroy(rte_rom* rom) {
   if (!rom) return;
-  rom_free(rom);
+  for (auto& sc : g_rs) sc.tab_rom = nullptr;  // cached per-instance tables may point into it
+  if (!rom->is_set()) rom_free(rom);
   delete rom;
 }
 
@@ -722,7 +854,7 @@ extern "C" void rte_rom_destroy(rte_rom* rom) {
 // region[nx*ny] (int32), then U, DU [r][npsi], W1, Ww [r][ndof], AD [rcap^2],
 // G, S [n_regions][rcap^2].
 extern "C" int rte_rom_save(const rte_rom* rom, const char* path) {
-  if (!rom || !path) return RTE_EINVAL;
+  if (!rom || !path || rom->is_set()) return RTE_EINVAL;
   FILE* f = std::fopen(path, "wb");
   if (!f) return RTE_EIO;
   RTE_HIP(hipDeviceSynchronize());
@@ -1013,9 +1145,16 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
     }
     st = rom_project(rom, b, nullptr, eta0, gq, mask, s);
     if (st != RTE_OK) break;
-    hipLaunchKernelGGL(k_rom_solve, dim3(n), dim3(64), 0, s, n, rom->r, rom->rcap, R, rom->AD, rom->G,
-                       rom->S, sigma_t, sigma_s, b->max_regions, gq, cq, ROM_GSTRIDE,
-                       (int32_t*)nullptr, mask);
+    {
+      RomScratch* rsc = scratch_for(b, 1);
+      const RomDev* tab = rsc ? rom_table(rom, rsc, b, s) : nullptr;
+      if (!tab) {
+        st = RTE_EHIP;
+        break;
+      }
+      hipLaunchKernelGGL(k_rom_solve, dim3(n), dim3(64), 0, s, n, tab, sigma_t, sigma_s, b->max_regions, gq, cq,
+                         ROM_GSTRIDE, (int32_t*)nullptr, mask);
+    }
     // compact c to the unsampled order for the residual kernel
     std::vector<double> ch((size_t)n * ROM_GSTRIDE), cc((size_t)unsampled.size() * ROM_GSTRIDE, 0.0);
     if (hipMemcpyAsync(ch.data(), cq, sizeof(double) * n * ROM_GSTRIDE, hipMemcpyDeviceToHost, s) != hipSuccess ||

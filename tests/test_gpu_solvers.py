@@ -203,6 +203,53 @@ def test_fgmres_romsad_parity(oracle_rom):
     assert stats[-1]["iterations"] == 1   # sampled parameter: the ROM is exact
 
 
+@pytest.fixture(scope="module")
+def oracle_rom_pair():
+    """Two geometries (grid and quadrature), each with its own oracle greedy ROM."""
+    fa = _family(4)
+    fb = _family(4, nx=6, ny=6, quad=("cl", 4, 4, True), seed=2)
+    Ua, _ = orom.greedy(fa, window=2, eps_rom=0.0, n_giter=2, rtol_hf=1e-11)
+    Ub, _ = orom.greedy(fb, window=2, eps_rom=0.0, n_giter=3, rtol_hf=1e-11)
+    return fa, fb, Ua, Ub
+
+
+@pytest.mark.gpu
+def test_rom_set_on_uneven_batch(oracle_rom_pair):
+    """One batch mixing both geometries: romsad_apply and FGMRES-ROMSAD with a
+    ROM set equal the oracle with each instance's own ROM."""
+    import torch
+
+    import paper_2410_08735_amd as rt
+    fa, fb, Ua, Ub = oracle_rom_pair
+    roma = rt.Rom.from_basis(rt.Batch(fa[:1]), torch.from_numpy(Ua.reshape(-1)).cuda())
+    romb = rt.Rom.from_basis(rt.Batch(fb[:1]), torch.from_numpy(Ub.reshape(-1)).cuda())
+    scale = lambda sp, f: dict(sp, sigma_s=sp["sigma_s"] * f, sigma_t=sp["sigma_t"] * f)
+    mixed = [scale(fb[1], 1.2), scale(fa[2], 0.9), fa[0], scale(fb[3], 1.05), scale(fa[1], 1.1)]
+    which = [1, 0, 0, 1, 0]
+    B = rt.Batch(mixed)
+    st, ss = B.sigma()
+    rs = rt.Rom.set(B, [roma, romb], which)
+    assert rs.rank == max(Ua.shape[0], Ub.shape[0])
+    with pytest.raises(rt.RteError):
+        rt.Rom.set(B, [roma, romb], [0, 0, 0, 1, 0])  # instance 0 is not on grid a
+    Us = [Ua, Ub]
+    rng = np.random.default_rng(8)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z = B.unpack(rt.romsad_apply(rs, B, st, ss, B.pack(v)))
+    for k, spec in enumerate(mixed):
+        P = tr.Problem(spec)
+        assert rel(z[k], v[k] + orom.rom_correction(P, Us[which[k]], v[k])) <= 1e-12, k
+    opts = rt.SolveOptions(precond="romsad", m=40, max_cycles=5, sweep_dtype="f64", rtol=1e-12,
+                           window=2, dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts, rom=rs)
+    assert ret == 0
+    for k, spec in enumerate(mixed):
+        ref = _oracle_solve(spec, "romsad", rtol=1e-12, U=Us[which[k]])
+        assert rel(B.unpack(phi)[k], ref.x) <= 1e-10, k
+        assert abs(stats[k]["iterations"] - ref.iterations) <= 1, (k, stats[k], ref.iterations)
+    assert stats[2]["iterations"] == 1   # fa[0] was sampled by its greedy: the ROM is exact
+
+
 @pytest.mark.gpu
 def test_greedy_matches_oracle(oracle_rom, tmp_path):
     import paper_2410_08735_amd as rt
