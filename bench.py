@@ -168,6 +168,65 @@ def learned_leg(args, common):
     return out
 
 
+def uneven_leg(args, common):
+    """The uneven batch: 512 instances on grids of 32^2..128^2 with 64 or 128
+    ordinates (checkerboard law), one greedy ROM per (grid, ordinates) group
+    joined in a ROM set, all instances solved together: every sweep is one
+    launch over the whole batch."""
+    import numpy as np
+    import torch
+
+    import paper_2410_08735_amd as rt
+    from synth import cfg3_box_centre, cfg3_mu, cfg3_problem, cfg4_batch
+    items = cfg4_batch(n_inst=args.uneven_n)
+    groups = sorted({(g, no) for g, no, _ in items})
+    nz = {64: 8, 128: 16}
+    rng = np.random.default_rng(40)
+    roms = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for g, no in groups:
+        tr = np.concatenate([cfg3_box_centre()[None], cfg3_mu(rng, args.n_train - 1)], 0)
+        Btr = rt.Batch([cfg3_problem(m, n=g, n_z=nz[no]) for m in tr])
+        st, ss = Btr.sigma()
+        rom, _ = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=2, mu1_index=0, eps_rom=1e-9,
+                                        n_giter=args.n_giter, eps_qr=1e-13, hf_rtol=1e-11)
+        roms.append(rom)
+        del Btr, st, ss
+    torch.cuda.synchronize()
+    offline = time.perf_counter() - t
+    B = rt.Batch([cfg3_problem(m, n=g, n_z=nz[no]) for g, no, m in items])
+    which = [groups.index((g, no)) for g, no, _ in items]
+    rs = rt.Rom.set(B, roms, which)
+    st, ss = B.sigma()
+    G = B.source()
+    out = {"instances": len(items), "groups": [f"{g}^2 x {no}" for g, no in groups],
+           "dof_total": int(sum(B.ndofs)), "greedy_s_total": offline,
+           "ranks": [r.rank for r in roms]}
+    for name, pc, kw in (("romsad", "romsad", dict(rom=rs)), ("plain_dsa", "dsa", {})):
+        opts = rt.SolveOptions(precond=pc, **common)
+        rt.fgmres_solve(B, st, ss, G, None, opts, **kw)  # warm-up: autotune, DSA hierarchy
+        dt, ok, stats = _solve_timed(rt, torch, B, st, ss, G, opts, reps=args.steps, **kw)
+        its = np.array([s["iterations"] for s in stats])
+        out[name] = {"value": ok / dt, "unit": "solves/s", "ms_per_step": dt * 1e3, "converged": ok,
+                     "iterations_mean": float(its.mean()), "iterations_max": int(its.max())}
+        log(f"uneven: {name}: {ok / dt:.1f} solves/s, iterations mean {its.mean():.2f}, converged {ok}/{len(stats)}")
+    cells_ord = sum(nd // 4 * no for nd, no in zip(B.ndofs, B.n_ords))
+    for dt_name in ("f32", "f64"):
+        rt.sweep(B, st, G, dtype=dt_name)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            rt.sweep(B, st, G, dtype=dt_name)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / 5
+        out[f"sweep_gdof_s_{dt_name}"] = 4 * cells_ord / el / 1e9
+        out[f"sweep_plan_{dt_name}"] = B.sweep_plan(dt_name)
+    log(f"uneven: sweep GDoF/s f32 {out['sweep_gdof_s_f32']:.0f} plan {out['sweep_plan_f32']}, "
+        f"f64 {out['sweep_gdof_s_f64']:.0f} plan {out['sweep_plan_f64']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +245,9 @@ def main():
     ap.add_argument("--mlp-epochs", type=int, default=60)
     ap.add_argument("--mlp-lr", type=float, default=1e-3)
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--uneven-n", type=int, default=512)
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--only-uneven", action="store_true")
     ap.add_argument("--only-mlp", action="store_true")
     ap.add_argument("--window-cycles", type=int, default=1,
                     help="restart cycles that use the ROM window (0 = every cycle)")
@@ -212,6 +274,9 @@ def main():
                   window_cycles=args.window_cycles)
     if args.only_mlp:
         print(json.dumps({"learned": learned_leg(args, common)}), flush=True)
+        return
+    if args.only_uneven:
+        print(json.dumps({"uneven": uneven_leg(args, common)}), flush=True)
         return
     tr_mu, te_mu = cfg3_train_test(n_train=args.n_train, n_test=args.n_test)
     n = args.grid
@@ -347,10 +412,14 @@ def main():
         out["sweep_gdof_s"] = gd
         log(f"sweep GDoF/s: {gd}")
 
-    if not args.no_mlp:
+    if not args.no_mlp or not args.no_uneven:
         del B, st, ss, G, phi
         torch.cuda.empty_cache()
+    if not args.no_mlp:
         out["learned"] = learned_leg(args, common)
+        torch.cuda.empty_cache()
+    if not args.no_uneven:
+        out["uneven"] = uneven_leg(args, common)
 
     if not args.no_cpu_baseline:
         procs = max(1, min(16, len(os.sched_getaffinity(0))))

@@ -275,3 +275,32 @@ def test_greedy_matches_oracle(oracle_rom, tmp_path):
     z2 = B.unpack(rt.romsad_apply(rom2, B, st, ss, B.pack(v)))
     for k in range(len(specs)):
         assert np.array_equal(z[k], z2[k])
+
+
+@pytest.mark.gpu
+def test_full_size_checkerboard_romsad_sampled():
+    """The benchmark's workload at full size (96^2 cells, 128 ordinates, 256 test
+    parameters, greedy ROM from 64 training parameters, FP32 sweeps): every
+    instance reaches true relative residual 1e-8, and for a sampled instance
+    the oracle's own operator confirms the residual of the returned flux."""
+    import paper_2410_08735_amd as rt
+    from synth import cfg3_problem, cfg3_train_test
+    tr_mu, te_mu = cfg3_train_test()
+    Btr = rt.Batch([cfg3_problem(m) for m in tr_mu])
+    st, ss = Btr.sigma()
+    rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=2, n_giter=16)
+    assert rep["rank"] == 32 and rep["sampled"][0] == 0
+    del Btr, st, ss
+    specs = [cfg3_problem(m) for m in te_mu]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    opts = rt.SolveOptions(precond="romsad", m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8, window=2,
+                           dsa_inner_max=1, dsa_restart=0, window_cycles=1)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts, rom=rom)
+    assert ret == 0
+    assert all(s["true_relres"] <= 1e-8 for s in stats)
+    k = 131
+    P = tr.Problem(specs[k])
+    b = tr.b_tilde(P)
+    r = b - tr.A_tilde_apply(P, B.unpack(phi)[k])
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.05e-8
