@@ -179,6 +179,10 @@ typedef struct {
   int32_t window_cycles; /* restart cycles whose first `window` iterations use
                             the ROM / learned correction: 0 = every cycle,
                             k >= 1 = the first k cycles only                 */
+  int32_t use_graph;     /* nonzero: each Krylov index's operator application
+                            (batched sweep + reduction) is captured once into a
+                            HIP graph and replayed; needs a created stream (on
+                            the null stream the operator runs eagerly)       */
 } rte_solve_opts;
 
 typedef struct {

@@ -183,13 +183,14 @@ def dsa_apply(batch, sigma_t, sigma_s, v, inner_tol=1e-13, inner_max=2000, resta
 
 class SolveOptions:
     def __init__(self, precond="dsa", m=30, max_cycles=20, sweep_dtype="f64", rtol=1e-8, window=2,
-                 dsa_inner_max=30, dsa_restart=30, dsa_inner_tol=1e-10, window_cycles=0):
+                 dsa_inner_max=30, dsa_restart=30, dsa_inner_tol=1e-10, window_cycles=0, use_graph=False):
         self.precond = {"none": RTE_PC_NONE, "dsa": RTE_PC_DSA, "romsad": RTE_PC_ROMSAD,
                         "mlp": RTE_PC_MLP}[precond] if isinstance(precond, str) else precond
         self.m, self.max_cycles, self.sweep_dtype, self.rtol = m, max_cycles, sweep_dtype, rtol
         self.window = window
         self.dsa_inner_max, self.dsa_restart, self.dsa_inner_tol = dsa_inner_max, dsa_restart, dsa_inner_tol
         self.window_cycles = window_cycles
+        self.use_graph = use_graph
 
     def c(self):
         o = L.SolveOpts()
@@ -199,6 +200,7 @@ class SolveOptions:
         o.dsa_inner_max, o.dsa_restart, o.dsa_inner_tol = self.dsa_inner_max, self.dsa_restart, self.dsa_inner_tol
         o.keep_krylov = 0
         o.window_cycles = self.window_cycles
+        o.use_graph = 1 if self.use_graph else 0
         return o
 
 

@@ -32,7 +32,8 @@ class InstanceDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("precond", i32), ("m", i32), ("max_cycles", i32), ("sweep_dtype", i32),
                 ("rtol", dbl), ("window", i32), ("dsa_inner_max", i32), ("dsa_restart", i32),
-                ("dsa_inner_tol", dbl), ("keep_krylov", i32), ("window_cycles", i32)]
+                ("dsa_inner_tol", dbl), ("keep_krylov", i32), ("window_cycles", i32),
+                ("use_graph", i32)]
 
 
 class SolveStats(C.Structure):

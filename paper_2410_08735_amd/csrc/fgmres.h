@@ -15,8 +15,17 @@ struct SolveCtx {
   int keep;                    // record cycle 0's first `keep` Krylov vectors
 };
 
+// A captured operator application w = z - T Sigma_s z (sweep + reduction) for
+// one Krylov index, replayed while its arguments and the sweep plan stay the same.
+struct OpGraph {
+  hipGraphExec_t exec = nullptr;
+  const void* key[4] = {nullptr, nullptr, nullptr, nullptr};  // sigma_t, sigma_s, z, w
+  int prec = -1, G = 0, threads = 0, variant = -1;
+};
+
 struct Fgmres {
   rte_batch* b = nullptr;
+  std::vector<OpGraph> graphs;  // [prec * m + j]
   int m = 0;
   Krylov K;
   double *btil = nullptr, *r = nullptr, *bnorm = nullptr, *tolabs = nullptr, *rnorm = nullptr;
@@ -32,6 +41,9 @@ struct Fgmres {
   int precondition(int jj, int cycle, const double* v, double* z, const SolveCtx& c, hipStream_t s,
                    std::vector<int32_t>& which);
   int solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s);
+  int apply_op(int j, int prec, const SolveCtx& c, bool use_graph, const std::vector<int32_t>& act,
+               hipStream_t s);
+  void graphs_release();
 };
 
 Fgmres* fgmres_for(rte_batch* b, int m);

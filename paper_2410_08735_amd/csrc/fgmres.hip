@@ -28,6 +28,7 @@ int Fgmres::init(rte_batch* batch, int m_) {
 }
 
 void Fgmres::release() {
+  graphs_release();
   K.release();
   for (void* p : {(void*)btil, (void*)r, (void*)bnorm, (void*)tolabs, (void*)rnorm, (void*)cyc,
                   (void*)cyc_step, (void*)flags})
@@ -35,6 +36,62 @@ void Fgmres::release() {
   btil = r = bnorm = tolabs = rnorm = nullptr;
   cyc = cyc_step = flags = nullptr;
   rec_release();
+}
+
+void Fgmres::graphs_release() {
+  for (auto& g : graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
+// w = z_j - T Sigma_s z_j into v_{j+1}: one batched sweep and the deterministic
+// partial-flux reduction.  With use_graph the pair is captured once per
+// (precision, j) into a HIP graph and replayed; a new capture is made when the
+// cross-section arrays, the plan or the buffers change.  The kernels read the
+// activity mask from device memory, so a replay follows the current mask.
+int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, const std::vector<int32_t>& act,
+                     hipStream_t s) {
+  const double units = batch_cell_ordinates(b, act.data());
+  if (!use_graph) {
+    RTE_TRY(sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, units));
+    return reduce_partials(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active);
+  }
+  if ((int)graphs.size() < 2 * m) graphs.resize(2 * m);
+  OpGraph& g = graphs[prec * m + j];
+  const Plan& p = b->plan[prec];
+  const void* key[4] = {c.sigma_t, c.sigma_s, K.z(j), K.v(j + 1)};
+  const bool same = g.exec && g.prec == prec && g.G == p.G && g.threads == p.threads && g.variant == p.variant &&
+                    std::equal(key, key + 4, g.key);
+  if (!same) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    RTE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    // no profiler events inside the capture; they are recorded around the launch
+    int st = sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, -2.0);
+    if (st == RTE_OK) st = reduce_partials(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active);
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != RTE_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st != RTE_OK ? st : RTE_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      return RTE_EHIP;
+    }
+    g.prec = prec;
+    g.G = p.G;
+    g.threads = p.threads;
+    g.variant = p.variant;
+    std::copy(key, key + 4, g.key);
+  }
+  const bool prof = prof_enabled();
+  if (prof) prof_begin(prec == 0 ? PROF_SWEEP_F64 : PROF_SWEEP_F32, s);
+  RTE_HIP(hipGraphLaunch(g.exec, s));
+  if (prof) prof_end(prec == 0 ? PROF_SWEEP_F64 : PROF_SWEEP_F32, s, units);
+  return RTE_OK;
 }
 
 void Fgmres::rec_release() {
@@ -167,9 +224,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       if (!any) break;
       RTE_TRY(precondition(j + 1, cycle, K.v(j), K.z(j), c, s, which));
       // w = A~ z_j = z_j - T Sigma_s z_j
-      RTE_TRY(sweep_launch(b, pin, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s,
-                           K.active, batch_cell_ordinates(b, act.data())));
-      RTE_TRY(reduce_partials(b, pin, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active));
+      RTE_TRY(apply_op(j, pin, c, o.use_graph != 0 && s != nullptr, act, s));
       RTE_TRY(arnoldi_mgs(K, j, s));
       if (o.precond == RTE_PC_MLP && j + 1 <= o.window && (o.window_cycles <= 0 || cycle < o.window_cycles)) {
         RTE_HIP(hipMemcpyAsync(cyc_step, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));

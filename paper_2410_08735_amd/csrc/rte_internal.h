@@ -104,7 +104,8 @@ int ensure_partials(rte_batch* b, int64_t elems);
 int make_plan(rte_batch* b, int prec, int G, int threads);
 int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int threads);
 // prof_units: cell-ordinates processed by this launch (for the event profiler);
-// negative = every instance of the batch.
+// -1 = every instance of the batch; below -1.5 = no profiler events (used
+// while a stream is being captured into a graph).
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
                  hipStream_t s, const int32_t* active = nullptr, double prof_units = -1.0);

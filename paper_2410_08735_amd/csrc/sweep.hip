@@ -565,7 +565,7 @@ static int sweep_launch_impl(rte_batch* b, int prec, const double* sigma_t, cons
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
                  hipStream_t s, const int32_t* active, double prof_units) {
-  if (!prof_enabled())
+  if (!prof_enabled() || prof_units < -1.5)
     return sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
   const int slot = prec == 0 ? PROF_SWEEP_F64 : PROF_SWEEP_F32;
   prof_begin(slot, s);
