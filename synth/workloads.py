@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "source_moments", "cfg1", "cfg2", "cfg3_mu", "cfg3_problem", "cfg3_train_test",
     "cfg4_batch", "tiny_2d", "tiny_1d", "CFG3_BOX_LO", "CFG3_BOX_HI", "cfg3_box_centre",
-    "cfg3_sigma", "cfg3_sources", "cfg3_features", "cfg5_sets",
+    "cfg3_sigma", "cfg3_sources", "cfg3_features", "cfg5_sets", "pincell_problem", "pincell_sets",
 ]
 
 _GL4_X, _GL4_W = np.polynomial.legendre.leggauss(4)
@@ -198,6 +198,36 @@ def cfg5_sets(n_train=64, n_snap=10240, n_test=1024, seed_train=50, seed_snap=52
     sn = cfg3_mu(np.random.default_rng(seed_snap), n_snap)
     te = cfg3_mu(np.random.default_rng(seed_test), n_test)
     return tr, sn, te
+
+
+def pincell_problem(mu, n=80, n_theta=30, n_z=6):
+    """The pin-cell problem of section 5.2: [-1,1]^2, zero inflow, source
+    exp(-100 (x^2 + y^2)); outer region (|x| > 0.5 or |y| > 0.5, region 0) a
+    pure scatterer with sigma_s = 100; inner square (region 1) with
+    (sigma_a, sigma_s) = (mu_a, mu_s).  CL(30, 6), z-folded (90 ordinates)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    h = 2.0 / n
+    c = -1.0 + (np.arange(n) + 0.5) * h
+    inner = (np.abs(c)[None, :] <= 0.5) & (np.abs(c)[:, None] <= 0.5)   # [k, i]
+    region = inner.reshape(-1).astype(np.int32)
+    sigma_s = np.array([100.0, mu[1]])
+    sigma_t = np.array([100.0, mu[0] + mu[1]])
+    box = (-1.0, 1.0, -1.0, 1.0)
+    G = source_moments(lambda x, y: np.exp(-100.0 * (x ** 2 + y ** 2)), 2, n, n, box)
+    return dict(dim=2, nx=n, ny=n, box=box, quad=("cl", n_theta, n_z, True), region=region,
+                sigma_t=sigma_t, sigma_s=sigma_s, source=G, inflow=0.0, mu=mu)
+
+
+def pincell_sets(n_test=10, seed=60):
+    """Training: the 5 x 5 uniform grid of (mu_a, mu_s) on [0.05, 0.5]^2, its
+    centre (0.275, 0.275) first; test: n_test uniform draws."""
+    g = np.linspace(0.05, 0.5, 5)
+    grid = [(a, b) for a in g for b in g]
+    centre = (0.275, 0.275)
+    grid.remove(centre)
+    tr = np.array([centre] + grid)
+    te = np.random.default_rng(seed).uniform(0.05, 0.5, size=(n_test, 2))
+    return tr, te
 
 
 def cfg4_batch(seed=4, n_inst=512):

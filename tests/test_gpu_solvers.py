@@ -334,3 +334,36 @@ def test_graph_replayed_operator_matches_eager():
     # on the null stream the option falls back to eager launches
     g0, _, _ = rt.fgmres_solve(B, st, ss, B.source(), None, rt.SolveOptions(use_graph=True, **common))
     assert bool((g0 == eager).all())
+
+
+@pytest.mark.gpu
+def test_pincell_problem_reproduces_the_papers_sweep_counts():
+    """Section 5.2 as specified (80^2, CL(30,6), 5 x 5 training grid, mu_1 at its
+    centre, window 2, eps_ROM 1e-10, rtol 1e-11, exact-solve DSA): the average
+    sweep counts of GMRES-DSA and FGMRES-ROMSAD on 10 fresh parameters are
+    close to the paper's table (differences in the discretisation details and
+    the random test draws allow some slack)."""
+    import json
+
+    import paper_2410_08735_amd as rt
+    from synth import pincell_problem, pincell_sets
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pincell_online.json")))
+    tr_mu, te_mu = pincell_sets()
+    Btr = rt.Batch([pincell_problem(m) for m in tr_mu])
+    st, ss = Btr.sigma()
+    rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=gold["window"], mu1_index=0,
+                                      eps_rom=gold["eps_rom"], n_giter=25, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+    del Btr, st, ss
+    assert gold["greedy_sampled"] - 3 <= len(rep["sampled"]) <= 25
+    assert rep["rank"] == 2 * len(rep["sampled"]) - rep["truncated"]
+    B = rt.Batch([pincell_problem(m) for m in te_mu])
+    st, ss = B.sigma()
+    common = dict(m=60, max_cycles=10, sweep_dtype="f64", rtol=gold["rtol"], window=gold["window"],
+                  dsa_inner_max=1000, dsa_restart=60, dsa_inner_tol=1e-12)
+    n = {}
+    for pc, kw in (("dsa", {}), ("romsad", dict(rom=rom))):
+        _, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, rt.SolveOptions(precond=pc, **common), **kw)
+        assert ret == 0 and all(s["true_relres"] <= gold["rtol"] for s in stats)
+        n[pc] = 1 + np.mean([s["iterations"] for s in stats])
+    assert abs(n["dsa"] - gold["gmres_dsa_nsweep"]) <= 1.5, n
+    assert abs(n["romsad"] - gold["fgmres_romsad_nsweep"]) <= 1.0, n
