@@ -201,6 +201,20 @@ int fgmres_solve(const rte_batch* b, const double* sigma_t, const double* sigma_
                  const rte_mlp* mlp, const double* mu, int mu_dim, double* phi,
                  rte_solve_stats* stats, void* stream);
 
+/* si_solve: source iteration with synthetic acceleration (section 3), the
+ * left-preconditioned Richardson iteration phi <- phi + M_l^{-1} (b~ - A~ phi)
+ * from phi = 0, one batched sweep per iteration.  opts->precond: RTE_PC_NONE
+ * (plain SI), RTE_PC_DSA, or RTE_PC_ROMSAD (M_ROM for the first `window`
+ * iterations, M_DSA after them; rom required).  An instance stops when
+ * ||b~ - A~ phi|| <= rtol ||b~|| (the residual of the iterate it returns);
+ * opts->max_cycles bounds the iterations; m, window_cycles, use_graph and
+ * keep_krylov are ignored.  stats: iterations = preconditioner applications,
+ * true_relres = last residual (computed with sweep_dtype sweeps), status 0 or
+ * RTE_WNOTCONV (also returned when any instance did not converge).          */
+int si_solve(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* G,
+             const double* inflow, const rte_solve_opts* opts, const rte_rom* rom, double* phi,
+             rte_solve_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------- ROMSAD
  * A ROM holds the orthonormal psi-space basis U_r ([r][n_ord][ndof], section
  * 4.3) of one grid/quadrature (instance 0 of the batch it was built on), the

@@ -221,6 +221,18 @@ def fgmres_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None, m
     return phi, [_stats_dict(s) for s in stats], st
 
 
+def si_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None):
+    """Source iteration with synthetic acceleration; opts.max_cycles bounds the iterations."""
+    opts = opts or SolveOptions()
+    phi = batch.zeros()
+    stats = (L.SolveStats * batch.n)()
+    co = opts.c()
+    st = L.lib().si_solve(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow), C.byref(co),
+                          rom.h if rom is not None else None, _ptr(phi), stats, _stream())
+    check(st, "si_solve")
+    return phi, [_stats_dict(s) for s in stats], st
+
+
 class Rom:
     def __init__(self, h):
         self.h = h

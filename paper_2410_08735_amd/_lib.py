@@ -68,6 +68,7 @@ SIGNATURES = {
     "rte_dsa_apply": (C.c_int, [vp, vp, vp, vp, vp, dbl, C.c_int, C.c_int, pi32, vp]),
     "fgmres_solve": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, C.c_int, vp,
                                C.POINTER(SolveStats), vp]),
+    "si_solve": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats), vp]),
     "romsad_build_greedy": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, C.c_int, dbl, C.c_int, dbl, dbl,
                                       dbl, C.POINTER(vp), C.POINTER(GreedyReport), vp]),
     "rte_rom_from_basis": (C.c_int, [vp, vp, C.c_int, C.POINTER(vp), vp]),

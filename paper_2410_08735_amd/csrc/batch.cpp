@@ -228,6 +228,7 @@ extern "C" void rte_batch_destroy(rte_batch* b) {
   rte::fgmres_forget(b);
   rte::rom_scratch_forget(b);
   rte::mlp_scratch_forget(b);
+  rte::si_forget(b);
   (void)hipFree(b->d_inst);
   (void)hipFree(b->d_ox);
   (void)hipFree(b->d_oy);

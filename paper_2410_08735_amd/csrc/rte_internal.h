@@ -133,5 +133,6 @@ void dsa_forget(rte_batch* b);
 void fgmres_forget(rte_batch* b);
 void rom_scratch_forget(const rte_batch* b);
 void mlp_scratch_forget(const rte_batch* b);
+void si_forget(rte_batch* b);
 
 }  // namespace rte

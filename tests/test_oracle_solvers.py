@@ -237,3 +237,39 @@ def test_gelu_special_values():
     assert abs(mlp.gelu(np.array(-10.0))) < 1e-12
     # gelu(1) = Phi(1) = 0.8413447460685429 (standard normal CDF at 1)
     assert abs(mlp.gelu(np.array(1.0)) - 0.8413447460685429) < 1e-15
+
+
+# ---------------------------------------------------------------- SI-SA
+def test_si_with_the_exact_inverse_converges_in_one_step():
+    from oracle import si
+    P = tr.Problem(tiny_2d(seed=4, nx=4, ny=3, quad=("cl", 4, 2, False)))
+    At = tr.dense_A_tilde(P)
+    b = tr.b_tilde(P)
+    res = si.si(_At(P), b, lambda l, r: np.linalg.solve(At, r), rtol=1e-12)
+    assert res.iterations == 1 and res.converged
+    np.testing.assert_allclose(res.x, np.linalg.solve(At, b), rtol=1e-12, atol=1e-14)
+
+
+def test_unaccelerated_si_contracts_by_the_scattering_ratio():
+    """Infinite-medium-like case (uniform c = sigma_s / sigma_t): plain SI
+    reduces the residual by at most c per sweep, and its limit is the dense
+    solution."""
+    from oracle import si
+    spec = tiny_2d(seed=5, nx=5, ny=5, quad=("cl", 8, 4, True), n_regions=1)
+    spec["sigma_t"] = np.array([2.0])
+    spec["sigma_s"] = np.array([1.6])
+    P = tr.Problem(spec)
+    res = si.si(_At(P), tr.b_tilde(P), lambda l, r: r, rtol=1e-10, max_iter=200)
+    assert res.converged
+    ratios = np.array(res.residuals[1:]) / np.array(res.residuals[:-1])
+    assert ratios.max() <= 0.8 + 1e-12
+    np.testing.assert_allclose(res.x, np.linalg.solve(tr.dense_A_tilde(P), tr.b_tilde(P)), rtol=1e-8)
+
+
+def test_si_dsa_exact_for_slab_s2():
+    """1D S2 with fully consistent DSA: M_DSA^{-1} = A~^{-1}, one SI step."""
+    from oracle import si
+    P = tr.Problem(tiny_1d(seed=2, nx=6, n_ord=2))
+    D = dsa.DSA(P)
+    res = si.si(_At(P), tr.b_tilde(P), lambda l, r: D.apply(r), rtol=1e-12)
+    assert res.iterations == 1
