@@ -351,10 +351,11 @@ def test_pincell_problem_reproduces_the_papers_sweep_counts():
     tr_mu, te_mu = pincell_sets()
     Btr = rt.Batch([pincell_problem(m) for m in tr_mu])
     st, ss = Btr.sigma()
+    h = 2.0 / 80  # the paper's eps_ROM refers to a basis sqrt(h_x h_y) times the orthonormal one
     rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=gold["window"], mu1_index=0,
-                                      eps_rom=gold["eps_rom"], n_giter=25, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+                                      eps_rom=gold["eps_rom"] / h, n_giter=25, hf_rtol=1e-11, hf_dsa_tol=1e-12)
     del Btr, st, ss
-    assert gold["greedy_sampled"] - 3 <= len(rep["sampled"]) <= 25
+    assert abs(len(rep["sampled"]) - gold["greedy_sampled"]) <= 1, rep["sampled"]
     assert rep["rank"] == 2 * len(rep["sampled"]) - rep["truncated"]
     B = rt.Batch([pincell_problem(m) for m in te_mu])
     st, ss = B.sigma()
@@ -404,3 +405,44 @@ def test_si_solve_parity(oracle_rom, precond):
         assert stats[k]["true_relres"] <= 1e-11
         if precond != "none":
             assert stats[k]["pc_dsa"] + stats[k]["pc_rom"] == stats[k]["iterations"]
+
+
+@pytest.mark.gpu
+def test_pincell_fgmres_si_comparison_matches_the_paper():
+    """Section 5.2's FGMRES / SI comparison (window 1, eps_ROM 1e-7, hardest test
+    parameter): the sampled count, the relative residual after the first
+    correction of all four solvers, and the sweep counts of GMRES-DSA, SI-DSA
+    and FGMRES-ROMSAD agree with the paper's table.  (The paper reports SI-
+    ROMSAD stagnating; here it converges, which is not asserted either way.)"""
+    import json
+
+    import paper_2410_08735_amd as rt
+    from synth import pincell_problem, pincell_sets
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pincell_compare.json")))
+    tr_mu, _ = pincell_sets()
+    Btr = rt.Batch([pincell_problem(m) for m in tr_mu])
+    st, ss = Btr.sigma()
+    h = 2.0 / 80
+    rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=1, mu1_index=0,
+                                      eps_rom=gold["eps_rom"] / h, n_giter=25, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+    del Btr, st, ss
+    assert len(rep["sampled"]) == gold["greedy_sampled"] and rep["rank"] == gold["rom_dimension"]
+    B = rt.Batch([pincell_problem(gold["mu"])])
+    st, ss = B.sigma()
+    base = dict(m=60, max_cycles=10, sweep_dtype="f64", rtol=1e-11, window=1, dsa_inner_max=1000, dsa_restart=60,
+                dsa_inner_tol=1e-12)
+    got = {}
+    for name, solver, pc, kw in (("gmres_dsa", rt.fgmres_solve, "dsa", {}), ("si_dsa", rt.si_solve, "dsa", {}),
+                                 ("fgmres_romsad", rt.fgmres_solve, "romsad", dict(rom=rom)),
+                                 ("si_romsad", rt.si_solve, "romsad", dict(rom=rom))):
+        _, s1, _ = solver(B, st, ss, B.source(), None, rt.SolveOptions(precond=pc, **dict(base, m=1, max_cycles=1)),
+                          **kw)
+        ref = gold["relres_after_first_correction"][name]
+        assert abs(s1[0]["true_relres"] / ref - 1.0) <= 0.05, (name, s1[0]["true_relres"], ref)
+        if name != "si_romsad":
+            full = dict(base, max_cycles=100) if solver is rt.si_solve else base
+            _, s, _ = solver(B, st, ss, B.source(), None, rt.SolveOptions(precond=pc, **full), **kw)
+            got[name] = 1 + s[0]["iterations"]
+            assert s[0]["true_relres"] <= 1e-11
+    for name, tol in (("gmres_dsa", 1), ("si_dsa", 3), ("fgmres_romsad", 1)):
+        assert abs(got[name] - gold["n_sweep"][name]) <= tol, (name, got[name])
