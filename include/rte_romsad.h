@@ -33,8 +33,10 @@
  *  - Cross sections are piecewise constant on regions: sigma_t and sigma_s
  *    arguments are device arrays [n_inst][max_regions] (row stride
  *    rte_batch_max_regions()); the cell -> region map is fixed at batch creation.
- *  - Inflow (section 2, the boundary condition) is an isotropic constant g per
- *    instance (device array [n_inst], NULL = zero inflow).
+ *  - Inflow (section 2, the boundary condition): an isotropic constant value on
+ *    each side of the domain, device array [n_inst][4] = (left, right, bottom,
+ *    top) (slab: left, right, unused, unused); a side's value enters for the
+ *    directions pointing into the domain there.  NULL = zero inflow.
  */
 #ifndef RTE_ROMSAD_H
 #define RTE_ROMSAD_H

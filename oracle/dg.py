@@ -173,7 +173,8 @@ def advection(mesh, ox, oy):
 
 def inflow_vector(mesh, ox, oy, g):
     """(g_j^(bc))_k = -sum over inflow-boundary faces of int_F g eta_k Omega.n.
-    g is a constant or a callable g(x, y)."""
+    g is a constant, a callable g(x, y), or a dict of per-side constants with
+    keys "L", "R", "B", "T" (missing sides: zero inflow)."""
     out = np.zeros(mesh.ndof)
     i, k = _cells(mesh)
     x0, _, y0, _ = mesh.box
@@ -187,7 +188,10 @@ def inflow_vector(mesh, ox, oy, g):
         for c in np.nonzero(bnd)[0]:
             xs = x0 + (i[c] + 0.5 + 0.5 * fx) * mesh.hx
             ys = (y0 + (k[c] + 0.5 + 0.5 * fy) * mesh.hy) if mesh.dim == 2 else 0 * xs
-            gv = g(xs, ys) if callable(g) else np.full_like(xs, float(g))
+            if isinstance(g, dict):
+                gv = np.full_like(xs, float(g.get(name, 0.0)))
+            else:
+                gv = g(xs, ys) if callable(g) else np.full_like(xs, float(g))
             out[c * mesh.nloc:(c + 1) * mesh.nloc] += -on * (Bown * fw) @ gv
     return out
 

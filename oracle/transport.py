@@ -51,7 +51,10 @@ class Problem:
 
     def gbc(self, j, g=None):
         g = self.g if g is None else g
-        if not callable(g) and float(g) == 0.0:
+        if isinstance(g, dict):
+            if not any(float(v) for v in g.values()):
+                return np.zeros(self.ndof)
+        elif not callable(g) and float(g) == 0.0:
             return np.zeros(self.ndof)
         return dg.inflow_vector(self.mesh, self.ox[j], self.oy[j], g)
 

@@ -129,8 +129,17 @@ class Batch:
         return torch.from_numpy(st).to(device), torch.from_numpy(ss).to(device)
 
     def inflow(self, device="cuda"):
+        """[n][4] per-side inflow (left, right, bottom, top), or None if all zero.
+        A problem's "inflow" is a constant (every side) or a dict keyed by
+        "L", "R", "B", "T"."""
         torch = _torch()
-        g = np.array([float(p.get("inflow", 0.0)) for p in self.problems])
+        g = np.zeros((self.n, 4))
+        for k, p in enumerate(self.problems):
+            v = p.get("inflow", 0.0)
+            if isinstance(v, dict):
+                g[k] = [float(v.get(side, 0.0)) for side in ("L", "R", "B", "T")]
+            else:
+                g[k] = float(v)
         if not np.any(g):
             return None
         return torch.from_numpy(g).to(device)

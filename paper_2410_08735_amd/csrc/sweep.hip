@@ -130,7 +130,12 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
   const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
   const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
   const real r3 = (real)1.7320508075688772935;
-  const real gin = inflow ? (real)(inflow[it.inst] * sqrt(I.hx * I.hy)) : (real)0;
+  // inflow [n_inst][4] = left, right, bottom, top; in mirrored coordinates the
+  // x-inflow face is the left one unless Omega_x < 0, the y-inflow face the
+  // bottom one unless Omega_y < 0
+  const double gsc = sqrt(I.hx * I.hy);
+  const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
+  const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
   real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G][2]
   real* ytr = xtr + (size_t)ny * G * 2;           // [nx][G][2]
@@ -163,8 +168,8 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
       }
       const real sig = (real)st[rg];
       real tx0, tx1, ty0, ty1;
-      if (i == 0) { tx0 = gin; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
-      if (r == 0) { ty0 = gin; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
+      if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
+      if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
       real rhs[4];
       rhs[0] = (real)q[0] + a * tx0 + b * ty0;
       rhs[1] = mx * (real)q[1] - r3 * a * tx0 + b * ty1;
@@ -247,7 +252,12 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
   const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
   const real r3 = (real)1.7320508075688772935;
-  const real gin = inflow ? (real)(inflow[it.inst] * sqrt(I.hx * I.hy)) : (real)0;
+  // inflow [n_inst][4] = left, right, bottom, top; in mirrored coordinates the
+  // x-inflow face is the left one unless Omega_x < 0, the y-inflow face the
+  // bottom one unless Omega_y < 0
+  const double gsc = sqrt(I.hx * I.hy);
+  const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
+  const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
   real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G][2]
   real* ytr = xtr + (size_t)ny * G * 2;           // [nx][G][2]
@@ -295,8 +305,8 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         const real sc = tab[SWEEP_SIGMA_TAB + rg];
         const real q0 = sc * (real)v.x, q1 = sc * (real)v.y, q2 = sc * (real)v.z, q3 = sc * (real)v.w;
         real tx0, tx1, ty0, ty1;
-        if (i == 0) { tx0 = gin; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
-        if (r == 0) { ty0 = gin; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
+        if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
+        if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
         real rhs[4];
         rhs[0] = q0 + a * tx0 + b * ty0;
         rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
@@ -364,7 +374,7 @@ __global__ void sweep1d_kernel(const InstDev* __restrict__ insts, const InstPart
   const int32_t* reg = region + I.region_off;
   real* P = part + parts[inst].off + (int64_t)js_loc * nx * 2;
   double* psi_j = psi_out ? psi_out + I.psi_off + (int64_t)perm[js] * nx * 2 : nullptr;
-  real T = inflow ? (real)(inflow[inst] * sqrt(I.hx)) : (real)0;
+  real T = inflow ? (real)(inflow[4 * inst + (flip ? 1 : 0)] * sqrt(I.hx)) : (real)0;  // left / right
   for (int i = 0; i < nx; ++i) {
     const int cell = flip ? nx - 1 - i : i;
     const int rg = reg[cell];

@@ -31,6 +31,7 @@ __all__ = [
     "source_moments", "cfg1", "cfg2", "cfg3_mu", "cfg3_problem", "cfg3_train_test",
     "cfg4_batch", "tiny_2d", "tiny_1d", "CFG3_BOX_LO", "CFG3_BOX_HI", "cfg3_box_centre",
     "cfg3_sigma", "cfg3_sources", "cfg3_features", "cfg5_sets", "pincell_problem", "pincell_sets",
+    "twomat_problem", "twomat_sets",
 ]
 
 _GL4_X, _GL4_W = np.polynomial.legendre.leggauss(4)
@@ -227,6 +228,37 @@ def pincell_sets(n_test=10, seed=60):
     grid.remove(centre)
     tr = np.array([centre] + grid)
     te = np.random.default_rng(seed).uniform(0.05, 0.5, size=(n_test, 2))
+    return tr, te
+
+
+def twomat_problem(mu, n=64, n_theta=60, n_z=6):
+    """The two-material problem with parametric inflow of section 5.4:
+    [-1,1]^2, no source; inner square (|x|, |y| <= 0.5, region 1) a pure
+    scatterer with sigma_s = mu_s; outer region (region 0) a pure absorber with
+    sigma_a = 1; isotropic inflow mu_bc on the left side only.  CL(60, 6),
+    z-folded (180 ordinates).  (The paper prints sigma_s twice; the second
+    definition is read as sigma_a.)"""
+    mu = np.asarray(mu, dtype=np.float64)
+    h = 2.0 / n
+    c = -1.0 + (np.arange(n) + 0.5) * h
+    inner = (np.abs(c)[None, :] <= 0.5) & (np.abs(c)[:, None] <= 0.5)
+    region = inner.reshape(-1).astype(np.int32)
+    sigma_s = np.array([0.0, mu[0]])
+    sigma_t = np.array([1.0, mu[0]])
+    return dict(dim=2, nx=n, ny=n, box=(-1.0, 1.0, -1.0, 1.0), quad=("cl", n_theta, n_z, True),
+                region=region, sigma_t=sigma_t, sigma_s=sigma_s, source=np.zeros(n * n * 4),
+                inflow={"L": float(mu[1])}, mu=mu)
+
+
+def twomat_sets(n_test=10, seed=70):
+    """Training: mu_s = 1 + j/2 (j = 0..8) x mu_bc = 0.5 + k/10 (k = 0..10), with
+    mu_1 = (3, 1) first; test: n_test uniform draws on [1,5] x [0.5,1.5]."""
+    grid = [(1.0 + j / 2.0, 0.5 + k / 10.0) for j in range(9) for k in range(11)]
+    first = grid.pop(4 * 11 + 5)
+    assert abs(first[0] - 3.0) < 1e-12 and abs(first[1] - 1.0) < 1e-12
+    tr = np.array([first] + grid)
+    rng = np.random.default_rng(seed)
+    te = np.stack([rng.uniform(1.0, 5.0, n_test), rng.uniform(0.5, 1.5, n_test)], 1)
     return tr, te
 
 

@@ -446,3 +446,34 @@ def test_pincell_fgmres_si_comparison_matches_the_paper():
             assert s[0]["true_relres"] <= 1e-11
     for name, tol in (("gmres_dsa", 1), ("si_dsa", 3), ("fgmres_romsad", 1)):
         assert abs(got[name] - gold["n_sweep"][name]) <= tol, (name, got[name])
+
+
+@pytest.mark.gpu
+def test_two_material_problem_reproduces_the_papers_table():
+    """Section 5.4 (left-side parametric inflow, 64^2, CL(60,6), 9 x 11 training
+    grid): greedy sample count and rank, and average sweep counts near the table."""
+    import json
+
+    import paper_2410_08735_amd as rt
+    from synth import twomat_problem, twomat_sets
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "twomat_online.json")))
+    tr_mu, te_mu = twomat_sets()
+    Btr = rt.Batch([twomat_problem(m) for m in tr_mu])
+    st, ss = Btr.sigma()
+    h = 2.0 / 64
+    rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), Btr.inflow(), window=gold["window"], mu1_index=0,
+                                      eps_rom=gold["eps_rom"] / h, n_giter=32, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+    del Btr, st, ss
+    assert len(rep["sampled"]) == gold["greedy_sampled"] and rep["rank"] == gold["rom_dimension"]
+    B = rt.Batch([twomat_problem(m) for m in te_mu])
+    st, ss = B.sigma()
+    common = dict(m=60, max_cycles=10, sweep_dtype="f64", rtol=gold["rtol"], window=gold["window"],
+                  dsa_inner_max=1000, dsa_restart=60, dsa_inner_tol=1e-12)
+    n = {}
+    for pc, kw in (("dsa", {}), ("romsad", dict(rom=rom))):
+        _, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), rt.SolveOptions(precond=pc, **common),
+                                        **kw)
+        assert ret == 0 and all(s["true_relres"] <= gold["rtol"] for s in stats)
+        n[pc] = 1 + np.mean([s["iterations"] for s in stats])
+    assert abs(n["dsa"] - gold["gmres_dsa_nsweep"]) <= 1.0, n
+    assert abs(n["romsad"] - gold["fgmres_romsad_nsweep"]) <= 1.0, n

@@ -52,7 +52,7 @@ def test_invalid_batch_rejected():
 def _uneven_set():
     return [
         tiny_2d(seed=1, nx=13, ny=11, quad=("cl", 8, 4, False), n_regions=3, inflow=0.3),
-        tiny_2d(seed=2, nx=7, ny=9, quad=("cl", 6, 2, False), n_regions=2),
+        dict(tiny_2d(seed=2, nx=7, ny=9, quad=("cl", 6, 2, False), n_regions=2), inflow={"L": 0.7, "T": 0.2}),
         tiny_2d(seed=3, nx=1, ny=1, quad=("cl", 4, 2, True), n_regions=1, inflow=1.0),
         tiny_2d(seed=4, nx=17, ny=5, quad=("cl", 30, 6, False), n_regions=2),  # Omega_x = 0 nodes
     ]
@@ -121,7 +121,7 @@ def test_invalid_sweep_plans_rejected():
 @pytest.mark.gpu
 def test_sweep_parity_1d():
     import paper_2410_08735_amd as rt
-    specs = [tiny_1d(seed=1, nx=9, n_ord=8, inflow=0.5), tiny_1d(seed=2, nx=33, n_ord=16)]
+    specs = [tiny_1d(seed=1, nx=9, n_ord=8, inflow=0.5), dict(tiny_1d(seed=2, nx=33, n_ord=16), inflow={"R": 0.3})]
     B = rt.Batch(specs)
     st, _ = B.sigma()
     rng = np.random.default_rng(3)

@@ -241,3 +241,19 @@ def test_separable_source_generator_matches_quadrature_projection():
         a = cfg3_problem(mu, n=12)["source"]
         b = cfg3_sources(mu[None], 12)[0]
         assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+def test_side_inflow_is_linear_and_matches_constant_inflow():
+    """Per-side inflow: the four sides together give the constant-inflow term,
+    and each side's term is nonzero only for directions entering through it."""
+    from oracle import dg
+    spec = tiny_2d(seed=3, nx=4, ny=3, quad=("cl", 8, 2, False))
+    P = tr.Problem(spec)
+    for j in range(P.nord):
+        parts = [dg.inflow_vector(P.mesh, P.ox[j], P.oy[j], {side: 0.7}) for side in "LRBT"]
+        whole = dg.inflow_vector(P.mesh, P.ox[j], P.oy[j], 0.7)
+        np.testing.assert_allclose(sum(parts), whole, rtol=1e-14, atol=1e-15)
+        assert (np.abs(parts[0]).max() > 0) == (P.ox[j] > 0)
+        assert (np.abs(parts[1]).max() > 0) == (P.ox[j] < 0)
+        assert (np.abs(parts[2]).max() > 0) == (P.oy[j] > 0)
+        assert (np.abs(parts[3]).max() > 0) == (P.oy[j] < 0)
