@@ -39,6 +39,13 @@ SWEEP_F32_TRAFFIC_BYTES = 1.2255e9
 SWEEP_ALG_BYTES_PER_CELL = 72.0
 
 
+def sweep_kernel_name(plan):
+    """The FP32 sweep kernel the autotuned plan launches (as rocprofv3 names it)."""
+    if plan["variant"] == 1:
+        return f"rte::sweep2d_rows_kernel<float, {plan['G']}, *, true> ({plan['threads']} threads)"
+    return f"rte::sweep2d_kernel<float, {plan['G']}> ({plan['threads']} threads)"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -478,7 +485,7 @@ def main():
                                f"training parameters, window 2), FP32 sweeps, FP64 Arnoldi, "
                                f"rtol 1e-8",
                    "global_batch": len(te_mu), "precond": "romsad"},
-        "roofline": {"bound": "alu", "kernel": "sweep2d_kernel<float>", "achieved": achieved / 1e12,
+        "roofline": {"bound": "alu", "kernel": sweep_kernel_name(B.sweep_plan("f32")), "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR,
                      "traffic": SWEEP_F32_TRAFFIC_BYTES if (n == 96 and len(te_mu) == 256) else None,

@@ -858,16 +858,15 @@ struct MgTailLevel {
 // One red-black half sweep on an LDS level (from_zero: the colour-0 sweep from
 // x = 0, which also clears colour 1).
 template <typename real>
-__device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const double* __restrict__ st,
-                                const double* __restrict__ ss, const real* bv, real* x, int color,
-                                bool from_zero) {
+__device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const real* st, const real* ss,
+                                const real* bv, real* x, int color, bool from_zero) {
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   for (int cell = threadIdx.x; cell < nc; cell += blockDim.x) {
     const int i = cell % nx, k = cell / nx;
     const bool mine = ((i + k) & 1) == color;
     if (!mine && !from_zero) continue;
     const CellPos P = cell_pos(i, k, nx, ny);
-    const real tt = (real)st[L.cell_off + cell], uu = (real)ss[L.cell_off + cell];
+    const real tt = st[cell], uu = ss[cell];
     real r[12], d[12];
     if (from_zero) {
 #pragma unroll
@@ -897,15 +896,25 @@ __global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restri
   if (active && !active[b]) return;
   extern __shared__ unsigned char smem_raw[];
   real* lds = reinterpret_cast<real*>(smem_raw);
+  // per level: x [12][nc], b [12][nc], sigma_t [nc], sigma_s [nc]
   __shared__ int off[MG_TAIL_MAX + 1];
   if (threadIdx.x == 0) {
     off[0] = 0;
     for (int l = 0; l < nlev; ++l) {
       const LvlInst Li = tl[l].li[b];
-      off[l + 1] = off[l] + 2 * 12 * Li.nx * Li.ny;  // x then b
+      off[l + 1] = off[l] + 26 * Li.nx * Li.ny;
     }
   }
   __syncthreads();
+  for (int l = 0; l < nlev; ++l) {  // cross sections of every level, once
+    const LvlInst Li = tl[l].li[b];
+    const int nc = Li.nx * Li.ny;
+    real* sg = lds + off[l] + 24 * nc;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      sg[c] = (real)tl[l].sigt[Li.cell_off + c];
+      sg[nc + c] = (real)tl[l].sigs[Li.cell_off + c];
+    }
+  }
   {  // load b of the first level
     const LvlInst L0 = tl[0].li[b];
     const int n0 = 12 * L0.nx * L0.ny;
@@ -920,9 +929,11 @@ __global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restri
     const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
     real* x = lds + off[l];
     real* bv = x + 12 * nc;
+    const real* sgt = x + 24 * nc;
+    const real* sgs = sgt + nc;
     for (int k = 0; k < nu_smooth; ++k) {
-      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 0, k == 0);
-      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 1, false);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, k == 0);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, false);
     }
     real* bc = lds + off[l + 1] + 12 * ncc;
     for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
@@ -935,7 +946,7 @@ __global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restri
         const int di = ch & 1, dk = ch >> 1;
         const CellPos P = cell_pos(2 * I + di, 2 * K + dk, L.nx, L.ny);
         real yy[12];
-        sym_cell_apply(S, (real)tl[l].sigt[L.cell_off + P.cell], (real)tl[l].sigs[L.cell_off + P.cell], x, P, yy);
+        sym_cell_apply(S, sgt[P.cell], sgs[P.cell], x, P, yy);
 #pragma unroll
         for (int fld = 0; fld < 3; ++fld)
 #pragma unroll
@@ -955,11 +966,14 @@ __global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restri
     const int l = nlev - 1;
     const LvlInst L = tl[l].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    const int nc = L.nx * L.ny;
     real* x = lds + off[l];
-    real* bv = x + 12 * L.nx * L.ny;
+    real* bv = x + 12 * nc;
+    const real* sgt = x + 24 * nc;
+    const real* sgs = sgt + nc;
     for (int k = 0; k < coarse_sweeps; ++k) {
-      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 0, k == 0);
-      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 1, false);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, k == 0);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, false);
     }
   }
   // up: prolong the correction, post-smooth in reverse colour order
@@ -988,9 +1002,11 @@ __global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restri
       }
     }
     __syncthreads();
+    const real* sgt = x + 24 * nc;
+    const real* sgs = sgt + nc;
     for (int k = 0; k < nu_smooth; ++k) {
-      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 1, false);
-      tail_half_sweep(S, L, tl[l].sigt, tl[l].sigs, bv, x, 0, false);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, false);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, false);
     }
   }
   {  // store x of the first level
@@ -1128,14 +1144,34 @@ int DsaSolver::init(rte_batch* batch, int restart_) {
     f32 = sym && restart == 0;
   }
   if (sym) {
-    // first level l >= 1 from which every level's x and b fit in 64 KB of LDS
+    // first level l >= 1 from which every level's x, b and cross sections fit
+    // in the work group's LDS
     const size_t es = f32 ? sizeof(float) : sizeof(double);
-    size_t need = 0;
-    for (int l = nlev - 1; l >= 1; --l) {
-      need += (size_t)2 * 12 * lv[l].max_nx * lv[l].max_ny * es;
-      if (need > 60 * 1024 || nlev - l > MG_TAIL_MAX) break;
-      tail_first = l;
-      tail_lds = need;
+    int dev = 0, lds_max = 64 * 1024;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t budget = (size_t)std::max(16 * 1024, std::min(lds_max, 160 * 1024) - 4 * 1024);
+    auto pick = [&](size_t cap) {
+      tail_first = -1;
+      tail_lds = 0;
+      size_t need = 0;
+      for (int l = nlev - 1; l >= 1; --l) {
+        need += (size_t)26 * lv[l].max_nx * lv[l].max_ny * es;
+        if (need > cap || nlev - l > MG_TAIL_MAX) break;
+        tail_first = l;
+        tail_lds = need;
+      }
+    };
+    pick(budget);
+    if (tail_lds > 60 * 1024) {  // beyond the default dynamic LDS limit: opt in, else stay within it
+      const hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail_sym<float>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_lds);
+      const hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail_sym<double>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_lds);
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        pick(60 * 1024);
+      }
     }
     if (tail_first > 0) {
       std::vector<MgTailLevel> h;
