@@ -42,8 +42,8 @@ SWEEP_ALG_BYTES_PER_CELL = 72.0
 def sweep_kernel_name(plan):
     """The FP32 sweep kernel the autotuned plan launches (as rocprofv3 names it)."""
     if plan["variant"] == 1:
-        return f"rte::sweep2d_rows_kernel<float, {plan['G']}, *, true> ({plan['threads']} threads)"
-    return f"rte::sweep2d_kernel<float, {plan['G']}> ({plan['threads']} threads)"
+        return f"rte::sweep2d_rows_kernel<float, {plan['G']}, {plan['opl']}, *, true> ({plan['threads']} threads)"
+    return f"rte::sweep2d_kernel<float, {plan['G']}, {plan['opl']}> ({plan['threads']} threads)"
 
 
 def log(*a):

@@ -105,14 +105,16 @@ int64_t rte_batch_total_psi(const rte_batch* b);
 int rte_batch_max_regions(const rte_batch* b);
 /* The 2D sweep's launch plan per precision (dtype RTE_F64 / RTE_F32): kernel
  * variant (0: work-group slots follow the wavefront diagonal; 1: each slot
- * owns fixed rows and prefetches their next source values), G ordinates per
- * cell group and threads per work group.  The first sweep of a batch times
+ * owns fixed rows and prefetches their next source values), G lanes per cell
+ * group, opl ordinates per lane (a work group sweeps G * opl ordinates of one
+ * quadrant) and threads per work group.  The first sweep of a batch times
  * every admissible plan and keeps the fastest (the autotuner); setting a plan
  * fixes it.  set: RTE_EINVAL for a plan the batch cannot run (G in
- * {1,2,4,8,16,32}, threads a multiple of 64 up to 512 and of G, LDS within
- * 64 KB, variant 1 needs ceil(max_ny / (threads / G)) <= 8 rows per slot and
- * at most 256 regions).  get: out[4] = {variant, G, threads, tuned}.        */
-int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int threads);
+ * {1,2,4,8,16,32}; opl 1, 2 with G in {4,8,16}, or 4 with G in {4,8}; threads a multiple of 64
+ * up to 512 and of G; LDS within 64 KB; variant 1 needs
+ * ceil(max_ny / (threads / G)) <= 8 rows per slot and at most 256 regions).
+ * get: out[5] = {variant, G, opl, threads, tuned}.                          */
+int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int opl, int threads);
 int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out);
 
 /* ---------------------------------------------------------------- transport

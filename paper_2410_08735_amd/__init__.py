@@ -90,13 +90,14 @@ class Batch:
         self.max_regions = lib.rte_batch_max_regions(h)
         self.n_ords = [len(self._keep[4 * k + 2]) for k in range(n)]
 
-    def set_sweep_plan(self, dtype, variant, G, threads):
-        check(L.lib().rte_batch_set_sweep_plan(self.h, _dt(dtype), variant, G, threads), "rte_batch_set_sweep_plan")
+    def set_sweep_plan(self, dtype, variant, G, threads, opl=1):
+        check(L.lib().rte_batch_set_sweep_plan(self.h, _dt(dtype), variant, G, opl, threads),
+              "rte_batch_set_sweep_plan")
 
     def sweep_plan(self, dtype):
-        out = (L.i32 * 4)()
+        out = (L.i32 * 5)()
         check(L.lib().rte_batch_sweep_plan(self.h, _dt(dtype), out), "rte_batch_sweep_plan")
-        return {"variant": out[0], "G": out[1], "threads": out[2], "tuned": bool(out[3])}
+        return {"variant": out[0], "G": out[1], "opl": out[2], "threads": out[3], "tuned": bool(out[4])}
 
     def __del__(self):
         try:

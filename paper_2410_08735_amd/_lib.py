@@ -91,7 +91,7 @@ SIGNATURES = {
                                 vp, vp]),
     "rte_mlp_snapshots": (C.c_int, [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.c_int, vp, vp, vp,
                                     vp]),
-    "rte_batch_set_sweep_plan": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "rte_batch_set_sweep_plan": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "rte_batch_sweep_plan": (C.c_int, [vp, C.c_int, C.POINTER(i32)]),
     "rte_prof_enable": (C.c_int, [C.c_int]),
     "rte_prof_mark": (C.c_int, [C.c_int, vp]),

@@ -48,8 +48,8 @@ extern "C" int rte_rhs(const rte_batch* cb, const double* sigma_t, const double*
   return rte::reduce_partials(b, prec, 1.0, nullptr, 0.0, b_out, s);
 }
 
-extern "C" int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int threads) {
-  return rte::set_sweep_plan(b, prec_of(dtype), variant, G, threads);
+extern "C" int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int opl, int threads) {
+  return rte::set_sweep_plan(b, prec_of(dtype), variant, G, opl, threads);
 }
 
 extern "C" int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out) {
@@ -58,7 +58,8 @@ extern "C" int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out)
   const rte::Plan& p = b->plan[prec];
   out[0] = p.variant;
   out[1] = p.G;
-  out[2] = p.threads;
-  out[3] = p.tuned ? 1 : 0;
+  out[2] = p.opl;
+  out[3] = p.threads;
+  out[4] = p.tuned ? 1 : 0;
   return RTE_OK;
 }

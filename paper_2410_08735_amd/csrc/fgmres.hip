@@ -167,8 +167,8 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   const rte_solve_opts& o = *c.opts;
   const int n = b->n_inst;
   const int pin = o.sweep_dtype == RTE_F32 ? 1 : 0;
-  RTE_TRY(autotune_sweep(b, 0, c.sigma_t, s));
-  if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s));
+  RTE_TRY(autotune_sweep(b, 0, c.sigma_t, s, c.sigma_s));
+  if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s, c.sigma_s));
   for (int q = 0; q < n; ++q) stats[q] = rte_solve_stats{};
   dsa_ready = false;  // the DSA hierarchy is rebuilt for this call's cross sections
   std::vector<int32_t> live(n, 1);

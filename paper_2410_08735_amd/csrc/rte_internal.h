@@ -63,6 +63,7 @@ struct Plan {
   int G = 8;       // ordinates per work group (2D); 1D uses one thread per ordinate
   int threads = 256;
   int variant = 0;  // 2D kernel: 0 = diagonal-slot order, 1 = row-slot order with source prefetch
+  int opl = 1;      // ordinates per lane (2D): a work item holds G * opl ordinates
   std::vector<SweepItem> items;
   std::vector<InstPart> parts;
   SweepItem* d_items = nullptr;
@@ -101,8 +102,8 @@ struct rte_batch {
 namespace rte {
 
 int ensure_partials(rte_batch* b, int64_t elems);
-int make_plan(rte_batch* b, int prec, int G, int threads);
-int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int threads);
+int make_plan(rte_batch* b, int prec, int G, int threads, int opl = 1);
+int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int threads);
 // prof_units: cell-ordinates processed by this launch (for the event profiler);
 // -1 = every instance of the batch; below -1.5 = no profiler events (used
 // while a stream is being captured into a graph).
@@ -121,7 +122,9 @@ double batch_cell_ordinates(const rte_batch* b, const int32_t* host_mask);
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
                     hipStream_t s, const int32_t* active = nullptr, const double* y = nullptr,
                     double gamma = 0.0);
-int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s);
+// sigma_s (nullable): time the plans on the operator's sigma_s-scaled source
+int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
+                   const double* sigma_s = nullptr);
 int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s);
 // restart == 0: inner_max V-cycles; restart >= 1: V-cycle-preconditioned
 // GMRES(restart) to inner_tol.  prepare = rebuild the sigma-dependent

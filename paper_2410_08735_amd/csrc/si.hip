@@ -85,8 +85,8 @@ extern "C" int si_solve(const rte_batch* cb, const double* sigma_t, const double
   if (!w) return RTE_ENOMEM;
   const int n = b->n_inst;
   const int prec = o.sweep_dtype == RTE_F32 ? 1 : 0;
-  RTE_TRY(autotune_sweep(b, 0, sigma_t, s));
-  if (prec == 1) RTE_TRY(autotune_sweep(b, 1, sigma_t, s));
+  RTE_TRY(autotune_sweep(b, 0, sigma_t, s, sigma_s));
+  if (prec == 1) RTE_TRY(autotune_sweep(b, 1, sigma_t, s, sigma_s));
   for (int q = 0; q < n; ++q) stats[q] = rte_solve_stats{};
   // b~ = T G~ (FP64) and its norm
   RTE_TRY(sweep_launch(b, 0, sigma_t, nullptr, nullptr, G, inflow, nullptr, s));

@@ -101,7 +101,88 @@ __device__ __forceinline__ void local_solve(real sig, real a, real b, const real
   x[1] = (adj0a * e1 + adj0b * k1) * f0;
 }
 
+// The ordinates one lane carries (OPL of them: lane g of a cell group holds
+// ordinates g*OPL .. g*OPL+OPL-1 of the work item) and what the sweep needs
+// of each: advection coefficients, quadrature weight, angular-flux output.
+template <typename real, int OPL>
+struct LaneOrds {
+  real a[OPL], b[OPL], wt[OPL];
+  double* psi[OPL];
+};
+
+template <typename real, int G, int OPL>
+__device__ __forceinline__ LaneOrds<real, OPL> lane_ords(const SweepItem& it, const InstDev& I, int g,
+                                                         const double* __restrict__ ox,
+                                                         const double* __restrict__ oy,
+                                                         const double* __restrict__ w,
+                                                         const int32_t* __restrict__ perm, double* psi_out) {
+  LaneOrds<real, OPL> L;
+#pragma unroll
+  for (int o = 0; o < OPL; ++o) {
+    const bool on = g * OPL + o < it.count;
+    const int js = I.ord_off + it.first + (on ? g * OPL + o : 0);
+    L.a[o] = (real)(fabs(ox[js]) / I.hx);
+    L.b[o] = (real)(fabs(oy[js]) / I.hy);
+    L.wt[o] = on ? (real)w[js] : (real)0;
+    L.psi[o] = (psi_out && on) ? psi_out + I.psi_off + (int64_t)perm[js] * I.nx * I.ny * 4 : nullptr;
+  }
+  return L;
+}
+
+// One cell (mirrored column i, row r; physical index cell) for the lane's
+// ordinates: inflow traces from LDS (or the boundary value), the closed-form
+// local solve, outflow traces back to LDS, and the lane's weighted sum c.
+template <typename real, int G, int OPL>
+__device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g, int i, int r, int64_t cell,
+                                            real sig, real q0, real q1, real q2, real q3, real gx, real gy,
+                                            real mx, real my, real* xtr, real* ytr, real c[4]) {
+  const real r3 = (real)1.7320508075688772935;
+  c[0] = c[1] = c[2] = c[3] = (real)0;
+#pragma unroll
+  for (int o = 0; o < OPL; ++o) {
+    const int xo = (r * G * OPL + g * OPL + o) * 2, yo = (i * G * OPL + g * OPL + o) * 2;
+    const real a = L.a[o], b = L.b[o];
+    real tx0, tx1, ty0, ty1;
+    if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; }
+    if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[yo]; ty1 = ytr[yo + 1]; }
+    real rhs[4];
+    rhs[0] = q0 + a * tx0 + b * ty0;
+    rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
+    rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
+    rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
+    real x[4];
+    local_solve<real>(sig, a, b, rhs, x);
+    xtr[xo] = x[0] + r3 * x[1];
+    xtr[xo + 1] = x[2] + r3 * x[3];
+    ytr[yo] = x[0] + r3 * x[2];
+    ytr[yo + 1] = x[1] + r3 * x[3];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) c[d] += L.wt[o] * x[d];
+    if (L.psi[o]) {
+      double* out = L.psi[o] + 4 * cell;
+      out[0] = (double)x[0];
+      out[1] = (double)(mx * x[1]);
+      out[2] = (double)(my * x[2]);
+      out[3] = (double)(mx * my * x[3]);
+    }
+  }
+}
+
+// The group's quadrature sum, written once per cell in physical orientation.
 template <typename real, int G>
+__device__ __forceinline__ void store_partial(real c[4], int g, real mx, real my, real* P, int64_t cell) {
+#pragma unroll
+  for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(c[d]);
+  if (g == 0) {
+    real* o = P + 4 * cell;
+    o[0] = c[0];
+    o[1] = mx * c[1];
+    o[2] = my * c[2];
+    o[3] = mx * my * c[3];
+  }
+}
+
+template <typename real, int G, int OPL>
 __global__ void __launch_bounds__(512) sweep2d_kernel(
     const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
     const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
@@ -122,14 +203,9 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
   const int slot = tid / G;
   const int S = blockDim.x / G;
   const int nx = I.nx, ny = I.ny;
-  const bool lane_on = g < it.count;
-  const int js = I.ord_off + it.first + (lane_on ? g : 0);
-  const real a = (real)(fabs(ox[js]) / I.hx);
-  const real b = (real)(fabs(oy[js]) / I.hy);
-  const real wt = lane_on ? (real)w[js] : (real)0;
+  const LaneOrds<real, OPL> L = lane_ords<real, G, OPL>(it, I, g, ox, oy, w, perm, psi_out);
   const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
   const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
-  const real r3 = (real)1.7320508075688772935;
   // inflow [n_inst][4] = left, right, bottom, top; in mirrored coordinates the
   // x-inflow face is the left one unless Omega_x < 0, the y-inflow face the
   // bottom one unless Omega_y < 0
@@ -137,16 +213,14 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
   const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
   const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
-  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G][2]
-  real* ytr = xtr + (size_t)ny * G * 2;           // [nx][G][2]
+  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G * OPL][2]
+  real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][G * OPL][2]
   const double* st = sigma_t + (size_t)it.inst * max_regions;
   const double* ss = sigma_s ? sigma_s + (size_t)it.inst * max_regions : nullptr;
   const int32_t* reg = region + I.region_off;
   const double* qxi = qx ? qx + I.dof_off : nullptr;
   const double* qai = qadd ? qadd + I.dof_off : nullptr;
   real* P = part + it.part_off;
-  double* psi_j = nullptr;
-  if (psi_out && lane_on) psi_j = psi_out + I.psi_off + (int64_t)perm[js] * nx * ny * 4;
 
   for (int s = 0; s < nx + ny - 1; ++s) {
     const int r_lo = max(0, s - nx + 1), r_hi = min(ny - 1, s);
@@ -166,38 +240,10 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
         const double4 v = *reinterpret_cast<const double4*>(qai + 4 * (int64_t)cell);
         q[0] += v.x; q[1] += v.y; q[2] += v.z; q[3] += v.w;
       }
-      const real sig = (real)st[rg];
-      real tx0, tx1, ty0, ty1;
-      if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
-      if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
-      real rhs[4];
-      rhs[0] = (real)q[0] + a * tx0 + b * ty0;
-      rhs[1] = mx * (real)q[1] - r3 * a * tx0 + b * ty1;
-      rhs[2] = my * (real)q[2] + a * tx1 - r3 * b * ty0;
-      rhs[3] = mx * my * (real)q[3] - r3 * (a * tx1 + b * ty1);
-      real x[4];
-      local_solve<real>(sig, a, b, rhs, x);
-      xtr[(r * G + g) * 2] = x[0] + r3 * x[1];
-      xtr[(r * G + g) * 2 + 1] = x[2] + r3 * x[3];
-      ytr[(i * G + g) * 2] = x[0] + r3 * x[2];
-      ytr[(i * G + g) * 2 + 1] = x[1] + r3 * x[3];
       real c[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(wt * x[d]);
-      if (g == 0) {
-        real* o = P + 4 * (int64_t)cell;
-        o[0] = c[0];
-        o[1] = mx * c[1];
-        o[2] = my * c[2];
-        o[3] = mx * my * c[3];
-      }
-      if (psi_j) {
-        double* o = psi_j + 4 * (int64_t)cell;
-        o[0] = (double)x[0];
-        o[1] = (double)(mx * x[1]);
-        o[2] = (double)(my * x[2]);
-        o[3] = (double)(mx * my * x[3]);
-      }
+      cell_update<real, G, OPL>(L, g, i, r, cell, (real)st[rg], (real)q[0], (real)q[1], (real)q[2], (real)q[3],
+                                gx, gy, mx, my, xtr, ytr, c);
+      store_partial<real, G>(c, g, mx, my, P, cell);
     }
     __syncthreads();
   }
@@ -225,7 +271,7 @@ constexpr int SWEEP_SIGMA_TAB = 256;  // regions whose cross sections are staged
 // bounds the rows per slot (ceil(ny / S) <= MAXR); the instance's region cross
 // sections are staged in LDS (n_regions <= SWEEP_SIGMA_TAB).  SCALED: the
 // source is sigma_s * q, else q as is (qsrc must be given).
-template <typename real, int G, int MAXR, bool SCALED>
+template <typename real, int G, int OPL, int MAXR, bool SCALED>
 __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
     const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
     const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
@@ -244,24 +290,16 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const int slot = tid / G;
   const int S = blockDim.x / G;
   const int nx = I.nx, ny = I.ny;
-  const bool lane_on = g < it.count;
-  const int js = I.ord_off + it.first + (lane_on ? g : 0);
-  const real a = (real)(fabs(ox[js]) / I.hx);
-  const real b = (real)(fabs(oy[js]) / I.hy);
-  const real wt = lane_on ? (real)w[js] : (real)0;
+  const LaneOrds<real, OPL> L = lane_ords<real, G, OPL>(it, I, g, ox, oy, w, perm, psi_out);
   const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
   const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
-  const real r3 = (real)1.7320508075688772935;
-  // inflow [n_inst][4] = left, right, bottom, top; in mirrored coordinates the
-  // x-inflow face is the left one unless Omega_x < 0, the y-inflow face the
-  // bottom one unless Omega_y < 0
   const double gsc = sqrt(I.hx * I.hy);
   const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
   const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
-  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G][2]
-  real* ytr = xtr + (size_t)ny * G * 2;           // [nx][G][2]
-  real* tab = ytr + (size_t)nx * G * 2;           // [2][SWEEP_SIGMA_TAB]: sigma_t, sigma_s
+  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G * OPL][2]
+  real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][G * OPL][2]
+  real* tab = ytr + (size_t)nx * G * OPL * 2;     // [2][SWEEP_SIGMA_TAB]: sigma_t, sigma_s
   {
     const double* st = sigma_t + (size_t)it.inst * max_regions;
     const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
@@ -274,8 +312,6 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const int32_t* reg = region + I.region_off;
   const double* qi = qsrc + I.dof_off;
   real* P = part + it.part_off;
-  double* psi_j = nullptr;
-  if (psi_out && lane_on) psi_j = psi_out + I.psi_off + (int64_t)perm[js] * nx * ny * 4;
   // physical cell of (mirrored column i, mirrored row r), both clamped into the grid
   auto phys = [&](int i, int r) {
     i = min(max(i, 0), nx - 1);
@@ -301,40 +337,11 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         const double4 v = qn[kk];
         const int rg = rn[kk];
         const int cell = phys(i, r);
-        const real sig = tab[rg];
         const real sc = tab[SWEEP_SIGMA_TAB + rg];
-        const real q0 = sc * (real)v.x, q1 = sc * (real)v.y, q2 = sc * (real)v.z, q3 = sc * (real)v.w;
-        real tx0, tx1, ty0, ty1;
-        if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[(r * G + g) * 2]; tx1 = xtr[(r * G + g) * 2 + 1]; }
-        if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[(i * G + g) * 2]; ty1 = ytr[(i * G + g) * 2 + 1]; }
-        real rhs[4];
-        rhs[0] = q0 + a * tx0 + b * ty0;
-        rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
-        rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
-        rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
-        real x[4];
-        local_solve<real>(sig, a, b, rhs, x);
-        xtr[(r * G + g) * 2] = x[0] + r3 * x[1];
-        xtr[(r * G + g) * 2 + 1] = x[2] + r3 * x[3];
-        ytr[(i * G + g) * 2] = x[0] + r3 * x[2];
-        ytr[(i * G + g) * 2 + 1] = x[1] + r3 * x[3];
         real c[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(wt * x[d]);
-        if (g == 0) {
-          real* o = P + 4 * (int64_t)cell;
-          o[0] = c[0];
-          o[1] = mx * c[1];
-          o[2] = my * c[2];
-          o[3] = mx * my * c[3];
-        }
-        if (psi_j) {
-          double* o = psi_j + 4 * (int64_t)cell;
-          o[0] = (double)x[0];
-          o[1] = (double)(mx * x[1]);
-          o[2] = (double)(my * x[2]);
-          o[3] = (double)(mx * my * x[3]);
-        }
+        cell_update<real, G, OPL>(L, g, i, r, cell, tab[rg], sc * (real)v.x, sc * (real)v.y, sc * (real)v.z,
+                                  sc * (real)v.w, gx, gy, mx, my, xtr, ytr, c);
+        store_partial<real, G>(c, g, mx, my, P, cell);
       }
       // source of this row's cell on the next diagonal (issued after the last
       // use of the current one, so it can land in the same registers)
@@ -458,10 +465,12 @@ int ensure_partials(rte_batch* b, int64_t elems) {
   return RTE_OK;
 }
 
-int make_plan(rte_batch* b, int prec, int G, int threads) {
+int make_plan(rte_batch* b, int prec, int G, int threads, int opl) {
   Plan& p = b->plan[prec];
   p.G = G;
+  p.opl = opl;
   p.threads = threads;
+  const int per_item = G * opl;  // ordinates per work item
   p.items.clear();
   p.parts.clear();
   int64_t off = 0;
@@ -475,12 +484,12 @@ int make_plan(rte_batch* b, int prec, int G, int threads) {
     } else {
       int n = 0;
       for (int qd = 0; qd < 4; ++qd) {
-        for (int f = 0; f < I.quad_count[qd]; f += G) {
+        for (int f = 0; f < I.quad_count[qd]; f += per_item) {
           SweepItem it{};
           it.inst = k;
           it.quadrant = qd;
           it.first = I.quad_first[qd] + f;
-          it.count = std::min(G, I.quad_count[qd] - f);
+          it.count = std::min(per_item, I.quad_count[qd] - f);
           it.part_off = off + (int64_t)n * nd;
           p.items.push_back(it);
           ++n;
@@ -508,13 +517,19 @@ int make_plan(rte_batch* b, int prec, int G, int threads) {
   return ensure_partials(b, off);
 }
 
-// Whether the row-slot kernel can take this batch with G ordinates and T threads.
+// Whether the row-slot kernel can take this batch with G lanes per cell and T threads.
 static bool rows_variant_fits(const rte_batch* b, int G, int T) {
   const int slots = T / G;
   return slots > 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB;
 }
 
-template <typename real, int G>
+// LDS bytes of a 2D sweep work group (traces of G * OPL ordinates, and the
+// cross-section table of the row-slot kernel).
+static size_t sweep_lds(const rte_batch* b, int G, int opl, int variant, size_t es) {
+  return ((size_t)(b->max_nx + b->max_ny) * G * opl * 2 + (variant == 1 ? 2 * SWEEP_SIGMA_TAB : 0)) * es;
+}
+
+template <typename real, int G, int OPL>
 static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const double* sigma_s,
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
                     hipStream_t s, const int32_t* active) {
@@ -522,13 +537,13 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
   if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, p.threads)) {
     const int slots = p.threads / G;
     const int nr = (b->max_ny + slots - 1) / slots;
-    const size_t lds = ((size_t)(b->max_nx + b->max_ny) * G * 2 + 2 * SWEEP_SIGMA_TAB) * sizeof(real);
+    const size_t lds = sweep_lds(b, G, OPL, 1, sizeof(real));
     if (lds > 64 * 1024) return RTE_EINVAL;
     const double* src = qx ? qx : qadd;
-#define RTE_ROWS_LAUNCH(R, SC)                                                                          \
-  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, R, SC>), dim3(8 * per_xcd), dim3(p.threads), lds, s,  \
-                     b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t,   \
-                     sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(b->d_part), psi_out, \
+#define RTE_ROWS_LAUNCH(R, SC)                                                                               \
+  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, OPL, R, SC>), dim3(8 * per_xcd), dim3(p.threads), lds, s,  \
+                     b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t,        \
+                     sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(b->d_part), psi_out,      \
                      active, p.n_items, per_xcd)
     if (qx) {
       if (nr <= 2) RTE_ROWS_LAUNCH(2, true);
@@ -543,9 +558,9 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
-  const size_t lds = (size_t)(b->max_nx + b->max_ny) * G * 2 * sizeof(real);
+  const size_t lds = sweep_lds(b, G, OPL, 0, sizeof(real));
   if (lds > 64 * 1024) return RTE_EINVAL;  // per-work-group LDS limit used by this library
-  hipLaunchKernelGGL((sweep2d_kernel<real, G>), dim3(8 * per_xcd), dim3(p.threads), lds, s,
+  hipLaunchKernelGGL((sweep2d_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(p.threads), lds, s,
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
                      sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
                      reinterpret_cast<real*>(b->d_part), psi_out, active, p.n_items, per_xcd);
@@ -553,17 +568,38 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
   return RTE_OK;
 }
 
+// The (G, OPL) pairs that have kernels: G lanes per cell, OPL ordinates per lane.
+static bool plan_shape_ok(int G, int opl) {
+  const bool g_ok = G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32;
+  return g_ok && (opl == 1 || (opl == 2 && G >= 4 && G <= 16) || (opl == 4 && G >= 4 && G <= 8));
+}
+
 template <typename real>
 static int launch2d_g(rte_batch* b, const Plan& p, const double* st, const double* ss,
                       const double* qx, const double* qa, const double* inf, double* psi,
                       hipStream_t s, const int32_t* act) {
+  if (p.opl == 4) {
+    switch (p.G) {
+      case 4: return launch2d<real, 4, 4>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      case 8: return launch2d<real, 8, 4>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      default: return RTE_EINVAL;
+    }
+  }
+  if (p.opl == 2) {
+    switch (p.G) {
+      case 4: return launch2d<real, 4, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      case 8: return launch2d<real, 8, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      case 16: return launch2d<real, 16, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      default: return RTE_EINVAL;
+    }
+  }
   switch (p.G) {
-    case 1: return launch2d<real, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 2: return launch2d<real, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 4: return launch2d<real, 4>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 8: return launch2d<real, 8>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 16: return launch2d<real, 16>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 32: return launch2d<real, 32>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 1: return launch2d<real, 1, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 2: return launch2d<real, 2, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 4: return launch2d<real, 4, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 8: return launch2d<real, 8, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 16: return launch2d<real, 16, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 32: return launch2d<real, 32, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
     default: return RTE_EINVAL;
   }
 }
@@ -644,24 +680,24 @@ int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s) {
   return RTE_OK;
 }
 
-int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int threads) {
+int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int threads) {
   if (!b || prec < 0 || prec > 1 || variant < 0 || variant > 1 || threads < 64 || threads > 512 ||
-      threads % 64 || (G != 1 && G != 2 && G != 4 && G != 8 && G != 16 && G != 32) || threads % G)
+      threads % 64 || !plan_shape_ok(G, opl) || threads % G)
     return RTE_EINVAL;
   if (b->dim == 2) {
-    const size_t lds = ((size_t)(b->max_nx + b->max_ny) * G * 2 + 2 * SWEEP_SIGMA_TAB) * (prec == 0 ? 8 : 4);
-    if (lds > 64 * 1024) return RTE_EINVAL;
+    if (sweep_lds(b, G, opl, variant, prec == 0 ? 8 : 4) > 64 * 1024) return RTE_EINVAL;
     if (variant == 1 && !rows_variant_fits(b, G, threads)) return RTE_EINVAL;
   }
-  RTE_TRY(make_plan(b, prec, G, threads));
+  RTE_TRY(make_plan(b, prec, G, threads, opl));
   b->plan[prec].variant = variant;
   b->plan[prec].tuned = true;
   return RTE_OK;
 }
 
-// Pick G (ordinates per work group) and the work-group size for this batch by
-// timing one sweep of each candidate that fits; the fastest plan is kept.
-int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s) {
+// Pick the plan (kernel variant, G lanes per cell, OPL ordinates per lane,
+// work-group size) for this batch by timing sweeps of each candidate that
+// fits; the fastest plan is kept.
+int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s, const double* sigma_s) {
   Plan& cur = b->plan[prec];
   if (cur.tuned || b->dim == 1) return RTE_OK;
   const int cand_G[] = {4, 8, 16, 32};
@@ -674,29 +710,39 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s)
   if (hipMalloc(&q, sizeof(double) * b->total_dof) != hipSuccess) return RTE_ENOMEM;
   RTE_HIP(hipMemsetAsync(q, 0, sizeof(double) * b->total_dof, s));
   float best = 1e30f;
-  int bestG = cur.G, bestT = cur.threads, bestV = 0;
+  int bestG = cur.G, bestT = cur.threads, bestV = 0, bestO = 1;
   for (int V = 0; V < 2; ++V) {
-    for (int G : cand_G) {
-      for (int T : cand_T) {
-        if (T % G || T / G < 1) continue;
-        if (V == 1 && !rows_variant_fits(b, G, T)) continue;
-        const size_t lds = ((size_t)(b->max_nx + b->max_ny) * G * 2 + 2 * SWEEP_SIGMA_TAB) * (prec == 0 ? 8 : 4);
-        if (lds > 64 * 1024) continue;
-        RTE_TRY(make_plan(b, prec, G, T));
-        b->plan[prec].variant = V;
-        RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
-        RTE_HIP(hipEventRecord(e0, s));
-        for (int rep = 0; rep < 3; ++rep)
-          RTE_TRY(sweep_launch(b, prec, sigma_t, nullptr, nullptr, q, nullptr, nullptr, s));
-        RTE_HIP(hipEventRecord(e1, s));
-        RTE_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        RTE_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-          best = ms;
-          bestG = G;
-          bestT = T;
-          bestV = V;
+    for (int O = 1; O <= 4; O *= 2) {
+      for (int G : cand_G) {
+        if (!plan_shape_ok(G, O) || G * O > 32) continue;
+        for (int T : cand_T) {
+          if (T % G || T / G < 1) continue;
+          if (V == 1 && !rows_variant_fits(b, G, T)) continue;
+          if (sweep_lds(b, G, O, V, prec == 0 ? 8 : 4) > 64 * 1024) continue;
+          RTE_TRY(make_plan(b, prec, G, T, O));
+          b->plan[prec].variant = V;
+          // the operator's form (sigma_s-scaled source) when sigma_s is given
+          const double* qx = sigma_s ? q : nullptr;
+          const double* qa = sigma_s ? nullptr : q;
+          RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, nullptr, -2.0));
+          float ms = 1e30f;
+          for (int trial = 0; trial < 2; ++trial) {  // best of two timings of 3 sweeps
+            RTE_HIP(hipEventRecord(e0, s));
+            for (int rep = 0; rep < 3; ++rep)
+              RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, nullptr, -2.0));
+            RTE_HIP(hipEventRecord(e1, s));
+            RTE_HIP(hipEventSynchronize(e1));
+            float t = 0.f;
+            RTE_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+          }
+          if (ms < best) {
+            best = ms;
+            bestG = G;
+            bestT = T;
+            bestV = V;
+            bestO = O;
+          }
         }
       }
     }
@@ -704,7 +750,7 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s)
   (void)hipFree(q);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  RTE_TRY(make_plan(b, prec, bestG, bestT));
+  RTE_TRY(make_plan(b, prec, bestG, bestT, bestO));
   b->plan[prec].variant = bestV;
   b->plan[prec].tuned = true;
   return RTE_OK;

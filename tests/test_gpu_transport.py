@@ -81,13 +81,16 @@ def test_sweep_parity_uneven_batch(dtype, tol):
         assert rel(psis[k], opsi) <= tol * 10, (k, rel(psis[k], opsi))
 
 
-PLANS = [(0, 4, 128), (0, 16, 512), (0, 32, 256), (1, 8, 512), (1, 16, 64), (1, 32, 64), (1, 4, 256)]
+PLANS = [(0, 4, 1, 128), (0, 16, 1, 512), (0, 32, 1, 256), (1, 8, 1, 512), (1, 16, 1, 64), (1, 32, 1, 64),
+         (1, 4, 1, 256), (0, 8, 2, 256), (0, 16, 2, 512), (1, 4, 2, 128), (1, 16, 2, 64), (0, 4, 4, 256),
+         (1, 8, 4, 512)]
 
 
 @pytest.mark.gpu
 def test_sweep_parity_every_plan():
-    """Both 2D kernel variants, several ordinate-group sizes and work-group sizes
-    (1, 3 and 6 rows per slot for the row-slot kernel), through rte_sweep
+    """Both 2D kernel variants, several lane-group sizes, one or two ordinates
+    per lane, and work-group sizes (1, 3 and 6 rows per slot for the row-slot
+    kernel), through rte_sweep
     (unscaled source, psi stored) and rte_apply_A (sigma_s-scaled source)."""
     import paper_2410_08735_amd as rt
     specs = _uneven_set()
@@ -97,25 +100,26 @@ def test_sweep_parity_every_plan():
     qs = [rng.standard_normal(n) for n in B.ndofs]
     refs = [_oracle_sweep(spec, qs[k]) for k, spec in enumerate(specs)]
     Ax = [tr.A_tilde_apply(tr.Problem(spec), qs[k]) for k, spec in enumerate(specs)]
-    for variant, G, T in PLANS:
+    for variant, G, opl, T in PLANS:
         for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
-            B.set_sweep_plan(dtype, variant, G, T)
-            assert B.sweep_plan(dtype) == {"variant": variant, "G": G, "threads": T, "tuned": True}
+            B.set_sweep_plan(dtype, variant, G, T, opl=opl)
+            assert B.sweep_plan(dtype) == {"variant": variant, "G": G, "opl": opl, "threads": T, "tuned": True}
             phi, psi = rt.sweep(B, st, B.pack(qs), inflow=B.inflow(), phi=True, psi=True, dtype=dtype)
             y = B.unpack(rt.apply_A(B, st, ss, B.pack(qs), dtype=dtype))
             for k in range(len(specs)):
-                assert rel(B.unpack(phi)[k], refs[k][0]) <= tol, (variant, G, T, dtype, k)
-                assert rel(B.unpack_psi(psi)[k], refs[k][1]) <= 10 * tol, (variant, G, T, dtype, k)
-                assert rel(y[k], Ax[k]) <= 10 * tol, (variant, G, T, dtype, k)
+                assert rel(B.unpack(phi)[k], refs[k][0]) <= tol, (variant, G, opl, T, dtype, k)
+                assert rel(B.unpack_psi(psi)[k], refs[k][1]) <= 10 * tol, (variant, G, opl, T, dtype, k)
+                assert rel(y[k], Ax[k]) <= 10 * tol, (variant, G, opl, T, dtype, k)
 
 
 @pytest.mark.gpu
 def test_invalid_sweep_plans_rejected():
     import paper_2410_08735_amd as rt
     B = rt.Batch([tiny_2d(seed=1, nx=40, ny=40, quad=("cl", 8, 4, False))])
-    for bad in [(0, 3, 128), (0, 16, 96), (2, 16, 128), (0, 16, 1024), (1, 32, 64)]:  # last: 20 rows per slot
+    for bad in [(0, 3, 128, 1), (0, 16, 96, 1), (2, 16, 128, 1), (0, 16, 1024, 1), (1, 32, 64, 1),  # 20 rows/slot
+                (0, 32, 256, 2), (0, 8, 256, 3), (0, 16, 256, 4)]:
         with pytest.raises(rt.RteError):
-            B.set_sweep_plan("f64", *bad)
+            B.set_sweep_plan("f64", *bad[:3], opl=bad[3])
 
 
 @pytest.mark.gpu
