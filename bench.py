@@ -29,14 +29,19 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak, FLOP/s
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_HBM = 8.0e12             # MI355X published HBM3E bandwidth, B/s
 # HBM bytes per launch of the FP32 sweep at the default workload (96^2, 256
-# instances), from the FETCH_SIZE / WRITE_SIZE counter passes scaled by a
-# 512 MiB copy (profiles/sweep2d_f32_cfg3_96sq_b256_hbm_traffic.md); valid for
-# the kernel version those passes measured.
-SWEEP_F32_TRAFFIC_BYTES = 1.2255e9
+# instances) for the plans the FETCH_SIZE / WRITE_SIZE counter passes measured
+# (scaled by a 512 MiB copy; profiles/sweep2d_f32_cfg3_96sq_b256_hbm_traffic.md),
+# keyed by (variant, G, ordinates per lane, threads); valid for the kernel
+# version those passes measured.
+SWEEP_F32_TRAFFIC_BYTES = {(1, 8, 2, 512): 4.008e8, (1, 16, 2, 512): 2.710e8}
 # Algorithmic HBM bytes per cell and instance of one sweep: read the 4 source
 # moments (FP64, 32 B), write the 4 scalar-flux moments (FP64, 32 B), and the
 # cell's cross-section data (8 B).  Angular fluxes never leave the chip.
 SWEEP_ALG_BYTES_PER_CELL = 72.0
+
+
+def plan_key(plan):
+    return (plan["variant"], plan["G"], plan["opl"], plan["threads"])
 
 
 def sweep_kernel_name(plan):
@@ -376,6 +381,8 @@ def main():
     ap.add_argument("--only-twomat", action="store_true", help="the paper's two-material problem only")
     ap.add_argument("--only-uneven", action="store_true")
     ap.add_argument("--only-mlp", action="store_true")
+    ap.add_argument("--sweep-plan", type=str, default=None,
+                    help="fix the FP32 sweep plan of the main workload: variant,G,opl,threads (default: autotuned)")
     ap.add_argument("--window-cycles", type=int, default=1,
                     help="restart cycles that use the ROM window (0 = every cycle)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -433,6 +440,9 @@ def main():
     B = rt.Batch([cfg3_problem(m, n=n) for m in te_mu])
     st, ss = B.sigma()
     G = B.source()
+    if args.sweep_plan:
+        v, g, o, t = (int(x) for x in args.sweep_plan.split(","))
+        B.set_sweep_plan("f32", v, g, t, opl=o)
     opts = rt.SolveOptions(precond="romsad", **common)
     for _ in range(args.warmup):
         rt.fgmres_solve(B, st, ss, G, None, opts, rom=rom)
@@ -488,7 +498,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": sweep_kernel_name(B.sweep_plan("f32")), "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR,
-                     "traffic": SWEEP_F32_TRAFFIC_BYTES if (n == 96 and len(te_mu) == 256) else None,
+                     "traffic": (SWEEP_F32_TRAFFIC_BYTES.get(plan_key(B.sweep_plan("f32")))
+                                 if (n == 96 and len(te_mu) == 256) else None),
                      "traffic_unit": "B per launch",
                      "hbm_algorithmic_GBps": (sum(nd // 4 for nd in B.ndofs) * SWEEP_ALG_BYTES_PER_CELL /
                                               (avg_launch_ms * 1e-3) / 1e9) if avg_launch_ms > 0 else 0.0,
