@@ -1048,7 +1048,7 @@ struct DsaSolver {
   int tail_first = -1;
   size_t tail_lds = 0;
   MgTailLevel* d_tail = nullptr;
-  int nu_smooth = 2, coarse_sweeps = 20;
+  int nu_smooth = 2, coarse_sweeps = 6;
   int init(rte_batch* batch, int restart_);
   void release();
   int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);

@@ -726,9 +726,9 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
           const double* qa = sigma_s ? nullptr : q;
           RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, nullptr, -2.0));
           float ms = 1e30f;
-          for (int trial = 0; trial < 2; ++trial) {  // best of two timings of 3 sweeps
+          for (int trial = 0; trial < 3; ++trial) {  // best of three timings of 4 sweeps
             RTE_HIP(hipEventRecord(e0, s));
-            for (int rep = 0; rep < 3; ++rep)
+            for (int rep = 0; rep < 4; ++rep)
               RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, nullptr, -2.0));
             RTE_HIP(hipEventRecord(e1, s));
             RTE_HIP(hipEventSynchronize(e1));
