@@ -705,10 +705,22 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
   hipEvent_t e0, e1;
   RTE_HIP(hipEventCreate(&e0));
   RTE_HIP(hipEventCreate(&e1));
-  // a zero source keeps the timing free of data effects
+  // a zero source keeps the timing free of data effects; large batches are
+  // timed on an evenly strided sample of 256 instances (enough to fill the chip)
   double* q = nullptr;
+  int32_t* mask = nullptr;
   if (hipMalloc(&q, sizeof(double) * b->total_dof) != hipSuccess) return RTE_ENOMEM;
   RTE_HIP(hipMemsetAsync(q, 0, sizeof(double) * b->total_dof, s));
+  const int n = b->n_inst, ns = std::min(n, 256);
+  if (ns < n) {
+    std::vector<int32_t> h(n, 0);
+    for (int k = 0; k < ns; ++k) h[(int64_t)k * n / ns] = 1;
+    if (hipMalloc(&mask, sizeof(int32_t) * n) != hipSuccess) {
+      (void)hipFree(q);
+      return RTE_ENOMEM;
+    }
+    RTE_HIP(hipMemcpy(mask, h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  }
   float best = 1e30f;
   int bestG = cur.G, bestT = cur.threads, bestV = 0, bestO = 1;
   for (int V = 0; V < 2; ++V) {
@@ -724,12 +736,12 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
           // the operator's form (sigma_s-scaled source) when sigma_s is given
           const double* qx = sigma_s ? q : nullptr;
           const double* qa = sigma_s ? nullptr : q;
-          RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, nullptr, -2.0));
+          RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
           float ms = 1e30f;
           for (int trial = 0; trial < 3; ++trial) {  // best of three timings of 4 sweeps
             RTE_HIP(hipEventRecord(e0, s));
             for (int rep = 0; rep < 4; ++rep)
-              RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, nullptr, -2.0));
+              RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
             RTE_HIP(hipEventRecord(e1, s));
             RTE_HIP(hipEventSynchronize(e1));
             float t = 0.f;
@@ -748,6 +760,7 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
     }
   }
   (void)hipFree(q);
+  (void)hipFree(mask);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   RTE_TRY(make_plan(b, prec, bestG, bestT, bestO));
