@@ -589,6 +589,12 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef<real>& S, real st, 
   }
 }
 
+// Reciprocal for the block solves: the hardware approximation (1 ulp) in
+// FP32, where the hierarchy only preconditions; a correctly rounded division
+// in FP64.
+__device__ __forceinline__ float blk_inv(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double blk_inv(double v) { return 1.0 / v; }
+
 // Exact solve with the cell's diagonal block for a reflection-symmetric rule.
 // The own-cell parts are: phi row diagonal Dphi, J rows diagonal dJx, dJy, and
 // the skew couplings a_xx S_x, a_yy S_y (S = sqrt3/h [[0,1],[-1,0]] along its
@@ -601,16 +607,16 @@ __device__ __forceinline__ void sym_block_solve(const SymCoef<real>& S, real st,
                                                 real out[12]) {
   const real r3 = (real)1.7320508075688772935;
   const real sx = r3 * S.ihx, sy = r3 * S.ihy;
-  real dphi[4], djx[4], djy[4], tx[4], ty[4];
+  real dphi[4], ijx[4], ijy[4], tx[4], ty[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     const int p = l & 1, q = l >> 1;
     const real gx = (real)(p ? 6 : 2) * S.ihx, gy = (real)(q ? 6 : 2) * S.ihy;
     dphi[l] = (st - ss) + S.bex * gx + S.bey * gy;
-    djx[l] = (real)3 * S.ax * st + (real)1.5 * (S.cxx * gx + S.cxy * gy);
-    djy[l] = (real)3 * S.ay * st + (real)1.5 * (S.cyx * gx + S.cyy * gy);
-    tx[l] = r[4 + l] / djx[l];  // dJx^{-1} r_Jx
-    ty[l] = r[8 + l] / djy[l];
+    ijx[l] = blk_inv((real)3 * S.ax * st + (real)1.5 * (S.cxx * gx + S.cxy * gy));  // 1 / dJx
+    ijy[l] = blk_inv((real)3 * S.ay * st + (real)1.5 * (S.cyx * gx + S.cyy * gy));
+    tx[l] = r[4 + l] * ijx[l];  // dJx^{-1} r_Jx
+    ty[l] = r[8 + l] * ijy[l];
   }
   // S_x acts on p: (S u)[0,q] = s u[1,q], (S u)[1,q] = -s u[0,q]; S_y likewise on q
   const real ax3 = (real)3 * S.ax * sx, ay3 = (real)3 * S.ay * sy;
@@ -620,20 +626,20 @@ __device__ __forceinline__ void sym_block_solve(const SymCoef<real>& S, real st,
   rhs[2] = r[2] - ax3 * tx[3] + ay3 * ty[0];
   rhs[3] = r[3] + ax3 * tx[2] + ay3 * ty[1];
   const real kx = (real)3 * S.ax * S.ax * sx * sx, ky = (real)3 * S.ay * S.ay * sy * sy;
-  out[0] = rhs[0] / (dphi[0] + kx / djx[1] + ky / djy[2]);  // (1-p, q) and (p, 1-q) partners
-  out[1] = rhs[1] / (dphi[1] + kx / djx[0] + ky / djy[3]);
-  out[2] = rhs[2] / (dphi[2] + kx / djx[3] + ky / djy[0]);
-  out[3] = rhs[3] / (dphi[3] + kx / djx[2] + ky / djy[1]);
+  out[0] = rhs[0] * blk_inv(dphi[0] + kx * ijx[1] + ky * ijy[2]);  // (1-p, q) and (p, 1-q) partners
+  out[1] = rhs[1] * blk_inv(dphi[1] + kx * ijx[0] + ky * ijy[3]);
+  out[2] = rhs[2] * blk_inv(dphi[2] + kx * ijx[3] + ky * ijy[0]);
+  out[3] = rhs[3] * blk_inv(dphi[3] + kx * ijx[2] + ky * ijy[1]);
   // J = dJ^{-1} (r_J - a S phi)
   const real axs = S.ax * sx, ays = S.ay * sy;
-  out[4] = (r[4] - axs * out[1]) / djx[0];
-  out[5] = (r[5] + axs * out[0]) / djx[1];
-  out[6] = (r[6] - axs * out[3]) / djx[2];
-  out[7] = (r[7] + axs * out[2]) / djx[3];
-  out[8] = (r[8] - ays * out[2]) / djy[0];
-  out[9] = (r[9] - ays * out[3]) / djy[1];
-  out[10] = (r[10] + ays * out[0]) / djy[2];
-  out[11] = (r[11] + ays * out[1]) / djy[3];
+  out[4] = (r[4] - axs * out[1]) * ijx[0];
+  out[5] = (r[5] + axs * out[0]) * ijx[1];
+  out[6] = (r[6] - axs * out[3]) * ijx[2];
+  out[7] = (r[7] + axs * out[2]) * ijx[3];
+  out[8] = (r[8] - ays * out[2]) * ijy[0];
+  out[9] = (r[9] - ays * out[3]) * ijy[1];
+  out[10] = (r[10] + ays * out[0]) * ijy[2];
+  out[11] = (r[11] + ays * out[1]) * ijy[3];
 }
 
 // Red-black index: work item t of colour `color` -> (i, k), for even nx

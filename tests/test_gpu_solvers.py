@@ -62,6 +62,13 @@ def test_dsa_apply_parity_symmetric_rules():
     for k, spec in enumerate(specs):
         ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
         assert rel(B.unpack(z1)[k] - v[k], ref - v[k]) <= 0.5
+    # stationary V-cycles in FP32 converge to the exact correction up to FP32 rounding
+    z40, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=0.0, inner_max=40, restart=0)
+    for k, spec in enumerate(specs):
+        ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
+        err = rel(B.unpack(z40)[k] - v[k], ref - v[k])
+        print(f"stationary FP32 V-cycles, instance {k}: rel err {err:.2e}")
+        assert err <= 2e-5, (k, err)
 
 
 @pytest.mark.gpu
