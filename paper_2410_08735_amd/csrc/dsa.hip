@@ -853,6 +853,9 @@ __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __res
 // one work group per instance runs that part of the V-cycle with each level's
 // x and b in shared memory, replacing a chain of small launches.
 constexpr int MG_TAIL_MAX = 10;
+// threads of the tail's work group: a level of up to 32 x 32 cells updates one
+// colour in one pass; FP64 keeps 256 for its larger register footprint
+constexpr int MG_TAIL_THREADS_F32 = 512, MG_TAIL_THREADS_F64 = 256;
 
 struct MgTailLevel {
   const LvlInst* li;
@@ -867,8 +870,18 @@ template <typename real>
 __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const real* st, const real* ss,
                                 const real* bv, real* x, int color, bool from_zero) {
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
-  for (int cell = threadIdx.x; cell < nc; cell += blockDim.x) {
-    const int i = cell % nx, k = cell / nx;
+  // even rows: the threads take only this colour's cells (nc / 2 of them)
+  const bool compact = (nx & 1) == 0;
+  const int nwork = compact ? nc / 2 : nc;
+  for (int t = threadIdx.x; t < nwork; t += blockDim.x) {
+    int i, k;
+    if (compact) {
+      rb_cell(t, nx, color, i, k);
+    } else {
+      i = t % nx;
+      k = t / nx;
+    }
+    const int cell = k * nx + i;
     const bool mine = ((i + k) & 1) == color;
     if (!mine && !from_zero) continue;
     const CellPos P = cell_pos(i, k, nx, ny);
@@ -880,6 +893,12 @@ __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const 
       if (mine) sym_block_solve(S, tt, uu, r, d);
 #pragma unroll
       for (int q = 0; q < 12; ++q) x[q * nc + cell] = mine ? d[q] : (real)0;
+      if (compact) {  // the other colour's cell of this pair starts at zero
+        int io, ko;
+        rb_cell(t, nx, color ^ 1, io, ko);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) x[q * nc + ko * nx + io] = (real)0;
+      }
     } else {
       real yy[12];
       sym_cell_apply(S, tt, uu, x, P, yy);
@@ -893,8 +912,8 @@ __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const 
   __syncthreads();
 }
 
-template <typename real>
-__global__ void __launch_bounds__(256) k_mg_tail_sym(const MgTailLevel* __restrict__ tl, int nlev, int nu_smooth,
+template <typename real, int NT>
+__global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restrict__ tl, int nlev, int nu_smooth,
                                                      int coarse_sweeps, const real* __restrict__ b_first,
                                                      real* __restrict__ x_first,
                                                      const int32_t* __restrict__ active) {
@@ -1170,9 +1189,9 @@ int DsaSolver::init(rte_batch* batch, int restart_) {
     };
     pick(budget);
     if (tail_lds > 60 * 1024) {  // beyond the default dynamic LDS limit: opt in, else stay within it
-      const hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail_sym<float>),
+      const hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail_sym<float, MG_TAIL_THREADS_F32>),
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_lds);
-      const hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail_sym<double>),
+      const hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail_sym<double, MG_TAIL_THREADS_F64>),
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)tail_lds);
       if (e1 != hipSuccess || e2 != hipSuccess) {
         (void)hipGetLastError();
@@ -1287,10 +1306,10 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
   if (l == tail_first) {
     const int nt = (int)lv.size() - l;
     if (f32)
-      hipLaunchKernelGGL(k_mg_tail_sym<float>, dim3(b->n_inst), dim3(256), tail_lds, s, d_tail, nt, nu_smooth,
+      hipLaunchKernelGGL((k_mg_tail_sym<float, MG_TAIL_THREADS_F32>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F32), tail_lds, s, d_tail, nt, nu_smooth,
                          coarse_sweeps, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x), act);
     else
-      hipLaunchKernelGGL(k_mg_tail_sym<double>, dim3(b->n_inst), dim3(256), tail_lds, s, d_tail, nt, nu_smooth,
+      hipLaunchKernelGGL((k_mg_tail_sym<double, MG_TAIL_THREADS_F64>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F64), tail_lds, s, d_tail, nt, nu_smooth,
                          coarse_sweeps, bv, x, act);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
