@@ -38,16 +38,18 @@ struct Vec4 {
 
 // Cross-lane moves inside a 16-lane DPP row: quad_perm [1,0,3,2] (xor 1),
 // quad_perm [2,3,0,1] (xor 2), row_half_mirror (i <-> 7 - i within 8 lanes) and
-// row_mirror (i <-> 15 - i).  Every lane reads a valid source lane.
+// row_mirror (i <-> 15 - i).  Every lane reads a valid source lane, so
+// bound_ctrl (set: it lets the compiler fold a move into the add that uses it)
+// changes no value.
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
   const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -101,6 +103,56 @@ __device__ __forceinline__ void local_solve(real sig, real a, real b, const real
   x[1] = (adj0a * e1 + adj0b * k1) * f0;
 }
 
+// The same solve with its (sigma, a, b)-dependent part precomputed.  Every
+// 2 x 2 block above is al I - be K, and K^2 = 4 K - 6 I, so such blocks commute
+// and each is kept as (al - be, al - 3 be, sqrt3 be):
+//   (al I - be K) v = ((al - be) v0 - sqrt3 be v1, (al - 3 be) v1 + sqrt3 be v0).
+// With M = adj0 / det0 and N = det0 adjS / detS the solve is
+//   v = M r_lo,  s = r_hi + sqrt3 b v,  x_hi = N s,  x_lo = M (r_lo - sqrt3 b x_hi),
+// c[0..2] = M, c[3..5] = N.  Coefficients in FP64 whatever the sweep's precision.
+__device__ __forceinline__ void solve_coef(double sig, double a, double b, double c[6]) {
+  const double r3 = 1.7320508075688772935;
+  const double a0 = sig + b, a1 = sig + 3.0 * b;
+  const double adj0a = a0 + 4.0 * a;
+  const double det0 = a0 * a0 + 4.0 * a0 * a + 6.0 * a * a;
+  const double b2 = 3.0 * b * b;
+  const double sa = det0 * a1 + b2 * adj0a;
+  const double sb = (det0 - b2) * a;
+  const double detS = sa * sa + 4.0 * sa * sb + 6.0 * sb * sb;
+  const double adjSa = sa + 4.0 * sb;
+  const double ma = adj0a / det0, mb = a / det0;
+  const double na = det0 * adjSa / detS, nb = det0 * sb / detS;
+  c[0] = ma - mb;
+  c[1] = ma - 3.0 * mb;
+  c[2] = r3 * mb;
+  c[3] = na - nb;
+  c[4] = na - 3.0 * nb;
+  c[5] = r3 * nb;
+}
+
+template <typename real>
+__device__ __forceinline__ void solve_apply(const real c[6], real br3, const real r[4], real x[4]) {
+  const real v0 = c[0] * r[0] - c[2] * r[1], v1 = c[1] * r[1] + c[2] * r[0];
+  const real s0 = r[2] + br3 * v0, s1 = r[3] + br3 * v1;
+  x[2] = c[3] * s0 - c[5] * s1;
+  x[3] = c[4] * s1 + c[5] * s0;
+  const real e0 = r[0] - br3 * x[2], e1 = r[1] - br3 * x[3];
+  x[0] = c[0] * e0 - c[2] * e1;
+  x[1] = c[1] * e1 + c[2] * e0;
+}
+
+// Two reals, the unit of the coefficient table in LDS.
+template <typename real>
+struct Pair2;
+template <>
+struct Pair2<float> {
+  using T = float2;
+};
+template <>
+struct Pair2<double> {
+  using T = double2;
+};
+
 // The ordinates one lane carries (OPL of them: lane g of a cell group holds
 // ordinates g*OPL .. g*OPL+OPL-1 of the work item) and what the sweep needs
 // of each: advection coefficients, quadrature weight, angular-flux output.
@@ -132,10 +184,18 @@ __device__ __forceinline__ LaneOrds<real, OPL> lane_ords(const SweepItem& it, co
 // One cell (mirrored column i, row r; physical index cell) for the lane's
 // ordinates: inflow traces from LDS (or the boundary value), the closed-form
 // local solve, outflow traces back to LDS, and the lane's weighted sum c.
-template <typename real, int G, int OPL>
+//
+// TAB (the row-slot kernel): the local solve reads its precomputed
+// coefficients (ctab: the three planes of Pair2 entries [plane][region][OPL][G]
+// at this cell's region) instead of forming them from sig, and the trace
+// arrays start out holding the inflow traces, so the first column and row
+// read them like any other.
+template <typename real, int G, int OPL, bool TAB = false>
 __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g, int i, int r, int64_t cell,
                                             real sig, real q0, real q1, real q2, real q3, real gx, real gy,
-                                            real mx, real my, real* xtr, real* ytr, real c[4]) {
+                                            real mx, real my, real* xtr, real* ytr, real c[4],
+                                            const typename Pair2<real>::T* ctab = nullptr,
+                                            int plane_stride = 0) {
   const real r3 = (real)1.7320508075688772935;
   c[0] = c[1] = c[2] = c[3] = (real)0;
 #pragma unroll
@@ -143,15 +203,22 @@ __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g,
     const int xo = (r * G * OPL + g * OPL + o) * 2, yo = (i * G * OPL + g * OPL + o) * 2;
     const real a = L.a[o], b = L.b[o];
     real tx0, tx1, ty0, ty1;
-    if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; }
-    if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[yo]; ty1 = ytr[yo + 1]; }
+    if (TAB || i != 0) { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; } else { tx0 = gx; tx1 = 0; }
+    if (TAB || r != 0) { ty0 = ytr[yo]; ty1 = ytr[yo + 1]; } else { ty0 = gy; ty1 = 0; }
     real rhs[4];
     rhs[0] = q0 + a * tx0 + b * ty0;
     rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
     rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
     rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
     real x[4];
-    local_solve<real>(sig, a, b, rhs, x);
+    if (TAB) {
+      const typename Pair2<real>::T* e = ctab + o * G + g;
+      const typename Pair2<real>::T p0 = e[0], p1 = e[plane_stride], p2 = e[2 * plane_stride];
+      const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
+      solve_apply<real>(cf, r3 * b, rhs, x);
+    } else {
+      local_solve<real>(sig, a, b, rhs, x);
+    }
     xtr[xo] = x[0] + r3 * x[1];
     xtr[xo + 1] = x[2] + r3 * x[3];
     ytr[yo] = x[0] + r3 * x[2];
@@ -261,6 +328,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 constexpr int SWEEP_SIGMA_TAB = 256;  // regions whose cross sections are staged in LDS
+constexpr int SWEEP_COEF_ENTRIES = 512;  // (region, lane ordinate) solve-coefficient entries in LDS
 
 // The same sweep with a fixed row -> slot assignment (row r is handled by slot
 // r mod S), so a slot walks along its rows one cell per diagonal and loads the
@@ -268,9 +336,11 @@ constexpr int SWEEP_SIGMA_TAB = 256;  // regions whose cross sections are staged
 // load latency leaves the diagonal-to-diagonal dependence chain.  Every slot
 // issues the loads of all its rows on every diagonal (addresses clamped to the
 // grid), so the prefetched registers are plain loop-carried values.  MAXR
-// bounds the rows per slot (ceil(ny / S) <= MAXR); the instance's region cross
-// sections are staged in LDS (n_regions <= SWEEP_SIGMA_TAB).  SCALED: the
-// source is sigma_s * q, else q as is (qsrc must be given).
+// bounds the rows per slot (ceil(ny / S) <= MAXR).  Per region the work group
+// stages sigma_s and, for each of its ordinates, the local-solve coefficients
+// (formed once from sigma_t, a and b, instead of once per cell) in LDS
+// (n_regions <= SWEEP_SIGMA_TAB, n_regions * G * OPL <= SWEEP_COEF_ENTRIES).
+// SCALED: the source is sigma_s * q, else q as is (qsrc must be given).
 template <typename real, int G, int OPL, int MAXR, bool SCALED>
 __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
     const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
@@ -299,13 +369,38 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   extern __shared__ unsigned char smem_raw[];
   real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G * OPL][2]
   real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][G * OPL][2]
-  real* tab = ytr + (size_t)nx * G * OPL * 2;     // [2][SWEEP_SIGMA_TAB]: sigma_t, sigma_s
+  real* tab = ytr + (size_t)nx * G * OPL * 2;     // [SWEEP_SIGMA_TAB]: sigma_s
+  using P2 = typename Pair2<real>::T;
+  P2* ctab = reinterpret_cast<P2*>(tab + SWEEP_SIGMA_TAB);  // [3][n_regions][OPL][G]
+  const int nreg = I.n_regions;
+  const int pstride = nreg * OPL * G;
   {
     const double* st = sigma_t + (size_t)it.inst * max_regions;
     const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
-    for (int e = tid; e < I.n_regions; e += blockDim.x) {
-      tab[e] = (real)st[e];
-      tab[SWEEP_SIGMA_TAB + e] = SCALED ? (real)ss[e] : (real)1;
+    for (int e = tid; e < nreg; e += blockDim.x) tab[e] = SCALED ? (real)ss[e] : (real)1;
+    for (int e = tid; e < pstride; e += blockDim.x) {
+      const int rg = e / (G * OPL), j = e % (G * OPL);  // lane j / OPL, its ordinate j % OPL
+      const bool on = j < it.count;
+      const int js = I.ord_off + it.first + (on ? j : 0);
+      double cf[6];
+      solve_coef(st[rg], fabs(ox[js]) / I.hx, fabs(oy[js]) / I.hy, cf);
+      P2* d = ctab + (rg * OPL + j % OPL) * G + j / OPL;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        P2 v;
+        v.x = (real)cf[2 * p];
+        v.y = (real)cf[2 * p + 1];
+        d[p * pstride] = v;
+      }
+    }
+    // inflow traces (g, 0) where each row and column enters the grid
+    for (int e = tid; e < ny * G * OPL; e += blockDim.x) {
+      xtr[2 * e] = gx;
+      xtr[2 * e + 1] = (real)0;
+    }
+    for (int e = tid; e < nx * G * OPL; e += blockDim.x) {
+      ytr[2 * e] = gy;
+      ytr[2 * e + 1] = (real)0;
     }
   }
   __syncthreads();
@@ -337,10 +432,10 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         const double4 v = qn[kk];
         const int rg = rn[kk];
         const int cell = phys(i, r);
-        const real sc = tab[SWEEP_SIGMA_TAB + rg];
+        const real sc = tab[rg];
         real c[4];
-        cell_update<real, G, OPL>(L, g, i, r, cell, tab[rg], sc * (real)v.x, sc * (real)v.y, sc * (real)v.z,
-                                  sc * (real)v.w, gx, gy, mx, my, xtr, ytr, c);
+        cell_update<real, G, OPL, true>(L, g, i, r, cell, (real)0, sc * (real)v.x, sc * (real)v.y, sc * (real)v.z,
+                                  sc * (real)v.w, gx, gy, mx, my, xtr, ytr, c, ctab + rg * OPL * G, pstride);
         store_partial<real, G>(c, g, mx, my, P, cell);
       }
       // source of this row's cell on the next diagonal (issued after the last
@@ -517,16 +612,20 @@ int make_plan(rte_batch* b, int prec, int G, int threads, int opl) {
   return ensure_partials(b, off);
 }
 
-// Whether the row-slot kernel can take this batch with G lanes per cell and T threads.
-static bool rows_variant_fits(const rte_batch* b, int G, int T) {
+// Whether the row-slot kernel can take this batch with G lanes per cell, OPL
+// ordinates per lane and T threads (rows per slot, and the per-region tables).
+static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T) {
   const int slots = T / G;
-  return slots > 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB;
+  return slots > 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB &&
+         b->max_regions * G * opl <= SWEEP_COEF_ENTRIES;
 }
 
-// LDS bytes of a 2D sweep work group (traces of G * OPL ordinates, and the
-// cross-section table of the row-slot kernel).
+// LDS bytes of a 2D sweep work group (traces of G * OPL ordinates; for the
+// row-slot kernel the sigma_s table and the solve coefficients).
 static size_t sweep_lds(const rte_batch* b, int G, int opl, int variant, size_t es) {
-  return ((size_t)(b->max_nx + b->max_ny) * G * opl * 2 + (variant == 1 ? 2 * SWEEP_SIGMA_TAB : 0)) * es;
+  size_t n = (size_t)(b->max_nx + b->max_ny) * G * opl * 2;
+  if (variant == 1) n += SWEEP_SIGMA_TAB + (size_t)6 * b->max_regions * G * opl;
+  return n * es;
 }
 
 template <typename real, int G, int OPL>
@@ -534,7 +633,7 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
                     hipStream_t s, const int32_t* active) {
   const int per_xcd = (p.n_items + 7) / 8;
-  if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, p.threads)) {
+  if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, OPL, p.threads)) {
     const int slots = p.threads / G;
     const int nr = (b->max_ny + slots - 1) / slots;
     const size_t lds = sweep_lds(b, G, OPL, 1, sizeof(real));
@@ -686,7 +785,7 @@ int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int thre
     return RTE_EINVAL;
   if (b->dim == 2) {
     if (sweep_lds(b, G, opl, variant, prec == 0 ? 8 : 4) > 64 * 1024) return RTE_EINVAL;
-    if (variant == 1 && !rows_variant_fits(b, G, threads)) return RTE_EINVAL;
+    if (variant == 1 && !rows_variant_fits(b, G, opl, threads)) return RTE_EINVAL;
   }
   RTE_TRY(make_plan(b, prec, G, threads, opl));
   b->plan[prec].variant = variant;
@@ -705,12 +804,13 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
   hipEvent_t e0, e1;
   RTE_HIP(hipEventCreate(&e0));
   RTE_HIP(hipEventCreate(&e1));
-  // a zero source keeps the timing free of data effects; large batches are
-  // timed on an evenly strided sample of 256 instances (enough to fill the chip)
+  // a constant nonzero source (every byte 0x3F: each entry is 4.8e-4) keeps the
+  // arithmetic as in a solve; large batches are timed on an evenly strided
+  // sample of 256 instances (enough to fill the chip)
   double* q = nullptr;
   int32_t* mask = nullptr;
   if (hipMalloc(&q, sizeof(double) * b->total_dof) != hipSuccess) return RTE_ENOMEM;
-  RTE_HIP(hipMemsetAsync(q, 0, sizeof(double) * b->total_dof, s));
+  RTE_HIP(hipMemsetAsync(q, 0x3F, sizeof(double) * b->total_dof, s));
   const int n = b->n_inst, ns = std::min(n, 256);
   if (ns < n) {
     std::vector<int32_t> h(n, 0);
@@ -721,44 +821,62 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
     }
     RTE_HIP(hipMemcpy(mask, h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   }
-  float best = 1e30f;
-  int bestG = cur.G, bestT = cur.threads, bestV = 0, bestO = 1;
+  struct Cand {
+    int V, O, G, T;
+    float ms;
+  };
+  std::vector<Cand> cands;
+  // the operator's form (sigma_s-scaled source) when sigma_s is given
+  const double* qx = sigma_s ? q : nullptr;
+  const double* qa = sigma_s ? nullptr : q;
+  auto time_plan = [&](const Cand& c, int trials, float& ms) -> int {
+    RTE_TRY(make_plan(b, prec, c.G, c.T, c.O));
+    b->plan[prec].variant = c.V;
+    RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
+    for (int trial = 0; trial < trials; ++trial) {  // best of `trials` timings of 4 sweeps
+      RTE_HIP(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 4; ++rep)
+        RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
+      RTE_HIP(hipEventRecord(e1, s));
+      RTE_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      RTE_HIP(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, t);
+    }
+    return RTE_OK;
+  };
   for (int V = 0; V < 2; ++V) {
     for (int O = 1; O <= 4; O *= 2) {
       for (int G : cand_G) {
         if (!plan_shape_ok(G, O) || G * O > 32) continue;
         for (int T : cand_T) {
           if (T % G || T / G < 1) continue;
-          if (V == 1 && !rows_variant_fits(b, G, T)) continue;
+          if (V == 1 && !rows_variant_fits(b, G, O, T)) continue;
           if (sweep_lds(b, G, O, V, prec == 0 ? 8 : 4) > 64 * 1024) continue;
-          RTE_TRY(make_plan(b, prec, G, T, O));
-          b->plan[prec].variant = V;
-          // the operator's form (sigma_s-scaled source) when sigma_s is given
-          const double* qx = sigma_s ? q : nullptr;
-          const double* qa = sigma_s ? nullptr : q;
-          RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
-          float ms = 1e30f;
-          for (int trial = 0; trial < 3; ++trial) {  // best of three timings of 4 sweeps
-            RTE_HIP(hipEventRecord(e0, s));
-            for (int rep = 0; rep < 4; ++rep)
-              RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
-            RTE_HIP(hipEventRecord(e1, s));
-            RTE_HIP(hipEventSynchronize(e1));
-            float t = 0.f;
-            RTE_HIP(hipEventElapsedTime(&t, e0, e1));
-            ms = std::min(ms, t);
-          }
-          if (ms < best) {
-            best = ms;
-            bestG = G;
-            bestT = T;
-            bestV = V;
-            bestO = O;
-          }
+          Cand c{V, O, G, T, 1e30f};
+          RTE_TRY(time_plan(c, 3, c.ms));
+          cands.push_back(c);
         }
       }
     }
   }
+  // the three fastest again, in turn, so that drift between the first timings
+  // cannot decide between near-equal plans
+  std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& c) { return a.ms < c.ms; });
+  const size_t top = std::min<size_t>(3, cands.size());
+  for (size_t k = 0; k < top; ++k) cands[k].ms = 1e30f;
+  for (int round = 0; round < 4; ++round)
+    for (size_t k = 0; k < top; ++k) RTE_TRY(time_plan(cands[k], 1, cands[k].ms));
+  int bestG = cur.G, bestT = cur.threads, bestV = 0, bestO = 1;
+  float best = 1e30f;
+  for (size_t k = 0; k < top; ++k)
+    if (cands[k].ms < best) {
+      best = cands[k].ms;
+      bestG = cands[k].G;
+      bestT = cands[k].T;
+      bestV = cands[k].V;
+      bestO = cands[k].O;
+    }
   (void)hipFree(q);
   (void)hipFree(mask);
   (void)hipEventDestroy(e0);
