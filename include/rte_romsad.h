@@ -146,10 +146,16 @@ int rte_rhs(const rte_batch* b, const double* sigma_t, const double* G, const do
  * consistent P1 moment system of App. A (zeroth and first angular moments of
  * the upwind correction equation under delta psi_j = dphi + 3 Omega_j.dJ,
  * written for X-Y geometry with the same two steps) with right-hand side
- * Sigma_s v.  The system is solved by restarted GMRES (Krylov dimension
- * `restart`) preconditioned with exact inverses of its per-cell diagonal
- * blocks, until the relative residual is <= inner_tol or inner_max iterations.
- * stats_iters (host [n_inst], nullable) receives the iterations used.         */
+ * Sigma_s v.  restart >= 1: restarted GMRES (Krylov dimension `restart`)
+ * preconditioned with one geometric-multigrid V-cycle per step (2 x 2 cell
+ * agglomeration, red-black block Gauss-Seidel smoothing with exact cell-block
+ * solves), in FP64, until the relative residual is <= inner_tol or inner_max
+ * iterations.  restart = 0: inner_max stationary V-cycle iterations from zero
+ * (inner_tol unused); when every instance has a reflection-symmetric rule the
+ * hierarchy then runs in FP32 (a preconditioner, not an exact solve).
+ * stats_iters (host [n_inst], nullable) receives the iterations used.
+ * Errors: RTE_EINVAL for null pointers, inner_max < 1, restart outside
+ * [0, 500] or a negative / NaN inner_tol.                                     */
 int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v,
                   double* z, double inner_tol, int inner_max, int restart, int32_t* stats_iters,
                   void* stream);

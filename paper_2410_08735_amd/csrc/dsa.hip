@@ -1073,7 +1073,11 @@ struct DsaSolver {
   int tail_first = -1;
   size_t tail_lds = 0;
   MgTailLevel* d_tail = nullptr;
-  int nu_smooth = 2, coarse_sweeps = 6;
+  // smoothing sweeps before and after the coarse correction: nu_smooth on the
+  // LDS-resident levels; on the levels streamed through HBM of the FP32
+  // stationary V-cycle nu_hbm (one sweep there costs more time than the
+  // extra FGMRES iterations it saves), nu_smooth elsewhere
+  int nu_smooth = 2, nu_hbm = 1, coarse_sweeps = 6;
   int init(rte_batch* batch, int restart_);
   void release();
   int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);
@@ -1328,7 +1332,8 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     }
     return smooth(l, coarse_sweeps, false, true, bv, x, act, s);
   }
-  RTE_TRY(smooth(l, nu_smooth, false, true, bv, x, act, s));
+  const int nu = f32 ? nu_hbm : nu_smooth;
+  RTE_TRY(smooth(l, nu, false, true, bv, x, act, s));
   MgLevel& C = lv[l + 1];
   const dim3 g = grid(l + 1);
   if (sym && f32) {
@@ -1359,7 +1364,7 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     hipLaunchKernelGGL((k_mg_transfer<4, double>), g, dim3(256), 0, s, 1, L.d_li, C.d_li,
                        (const double*)nullptr, x, C.x, (double*)nullptr, act);
   RTE_HIP(hipGetLastError());
-  return smooth(l, nu_smooth, true, false, bv, x, act, s);
+  return smooth(l, nu, true, false, bv, x, act, s);
 }
 
 // out = V-cycle(in) on level 0 (in and out may alias)

@@ -184,18 +184,10 @@ __device__ __forceinline__ LaneOrds<real, OPL> lane_ords(const SweepItem& it, co
 // One cell (mirrored column i, row r; physical index cell) for the lane's
 // ordinates: inflow traces from LDS (or the boundary value), the closed-form
 // local solve, outflow traces back to LDS, and the lane's weighted sum c.
-//
-// TAB (the row-slot kernel): the local solve reads its precomputed
-// coefficients (ctab: the three planes of Pair2 entries [plane][region][OPL][G]
-// at this cell's region) instead of forming them from sig, and the trace
-// arrays start out holding the inflow traces, so the first column and row
-// read them like any other.
-template <typename real, int G, int OPL, bool TAB = false>
+template <typename real, int G, int OPL>
 __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g, int i, int r, int64_t cell,
                                             real sig, real q0, real q1, real q2, real q3, real gx, real gy,
-                                            real mx, real my, real* xtr, real* ytr, real c[4],
-                                            const typename Pair2<real>::T* ctab = nullptr,
-                                            int plane_stride = 0) {
+                                            real mx, real my, real* xtr, real* ytr, real c[4]) {
   const real r3 = (real)1.7320508075688772935;
   c[0] = c[1] = c[2] = c[3] = (real)0;
 #pragma unroll
@@ -203,24 +195,62 @@ __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g,
     const int xo = (r * G * OPL + g * OPL + o) * 2, yo = (i * G * OPL + g * OPL + o) * 2;
     const real a = L.a[o], b = L.b[o];
     real tx0, tx1, ty0, ty1;
-    if (TAB || i != 0) { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; } else { tx0 = gx; tx1 = 0; }
-    if (TAB || r != 0) { ty0 = ytr[yo]; ty1 = ytr[yo + 1]; } else { ty0 = gy; ty1 = 0; }
+    if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; }
+    if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[yo]; ty1 = ytr[yo + 1]; }
     real rhs[4];
     rhs[0] = q0 + a * tx0 + b * ty0;
     rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
     rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
     rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
     real x[4];
-    if (TAB) {
-      const typename Pair2<real>::T* e = ctab + o * G + g;
-      const typename Pair2<real>::T p0 = e[0], p1 = e[plane_stride], p2 = e[2 * plane_stride];
-      const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
-      solve_apply<real>(cf, r3 * b, rhs, x);
-    } else {
-      local_solve<real>(sig, a, b, rhs, x);
-    }
+    local_solve<real>(sig, a, b, rhs, x);
     xtr[xo] = x[0] + r3 * x[1];
     xtr[xo + 1] = x[2] + r3 * x[3];
+    ytr[yo] = x[0] + r3 * x[2];
+    ytr[yo + 1] = x[1] + r3 * x[3];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) c[d] += L.wt[o] * x[d];
+    if (L.psi[o]) {
+      double* out = L.psi[o] + 4 * cell;
+      out[0] = (double)x[0];
+      out[1] = (double)(mx * x[1]);
+      out[2] = (double)(my * x[2]);
+      out[3] = (double)(mx * my * x[3]);
+    }
+  }
+}
+
+// The same for the row-slot kernel, where a slot owns whole rows: the x trace
+// passes to the slot's next cell of the row in registers (xt, holding the
+// inflow trace before the first column), the y trace to the next row through
+// LDS (ytr, preloaded with the inflow trace), and the local solve reads its
+// precomputed coefficients (ctab: this cell's region in the three planes of
+// Pair2 entries [plane][region][OPL][G], planes plane_stride apart).
+template <typename real, int G, int OPL>
+__device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, int g, int i, int64_t cell,
+                                                 real q0, real q1, real q2, real q3, real mx, real my,
+                                                 real xt[OPL][2], real* ytr, real c[4],
+                                                 const typename Pair2<real>::T* ctab, int plane_stride) {
+  const real r3 = (real)1.7320508075688772935;
+  c[0] = c[1] = c[2] = c[3] = (real)0;
+#pragma unroll
+  for (int o = 0; o < OPL; ++o) {
+    const int yo = (i * G * OPL + g * OPL + o) * 2;
+    const real a = L.a[o], b = L.b[o];
+    const real tx0 = xt[o][0], tx1 = xt[o][1];
+    const real ty0 = ytr[yo], ty1 = ytr[yo + 1];
+    real rhs[4];
+    rhs[0] = q0 + a * tx0 + b * ty0;
+    rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
+    rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
+    rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
+    const typename Pair2<real>::T* e = ctab + o * G + g;
+    const typename Pair2<real>::T p0 = e[0], p1 = e[plane_stride], p2 = e[2 * plane_stride];
+    const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
+    real x[4];
+    solve_apply<real>(cf, r3 * b, rhs, x);
+    xt[o][0] = x[0] + r3 * x[1];
+    xt[o][1] = x[2] + r3 * x[3];
     ytr[yo] = x[0] + r3 * x[2];
     ytr[yo + 1] = x[1] + r3 * x[3];
 #pragma unroll
@@ -335,7 +365,8 @@ constexpr int SWEEP_COEF_ENTRIES = 512;  // (region, lane ordinate) solve-coeffi
 // source of its next cell while the current diagonal is processed: the global
 // load latency leaves the diagonal-to-diagonal dependence chain.  Every slot
 // issues the loads of all its rows on every diagonal (addresses clamped to the
-// grid), so the prefetched registers are plain loop-carried values.  MAXR
+// grid), so the prefetched registers are plain loop-carried values; the x
+// traces along a row stay in the slot's registers.  MAXR
 // bounds the rows per slot (ceil(ny / S) <= MAXR).  Per region the work group
 // stages sigma_s and, for each of its ordinates, the local-solve coefficients
 // (formed once from sigma_t, a and b, instead of once per cell) in LDS
@@ -367,8 +398,7 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
   const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
-  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G * OPL][2]
-  real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][G * OPL][2]
+  real* ytr = reinterpret_cast<real*>(smem_raw);  // [nx][G * OPL][2]
   real* tab = ytr + (size_t)nx * G * OPL * 2;     // [SWEEP_SIGMA_TAB]: sigma_s
   using P2 = typename Pair2<real>::T;
   P2* ctab = reinterpret_cast<P2*>(tab + SWEEP_SIGMA_TAB);  // [3][n_regions][OPL][G]
@@ -393,11 +423,7 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         d[p * pstride] = v;
       }
     }
-    // inflow traces (g, 0) where each row and column enters the grid
-    for (int e = tid; e < ny * G * OPL; e += blockDim.x) {
-      xtr[2 * e] = gx;
-      xtr[2 * e + 1] = (real)0;
-    }
+    // inflow traces (g, 0) where each column enters the grid
     for (int e = tid; e < nx * G * OPL; e += blockDim.x) {
       ytr[2 * e] = gy;
       ytr[2 * e + 1] = (real)0;
@@ -416,6 +442,14 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
 
   double4 qn[MAXR];
   int rn[MAXR];
+  real xt[MAXR][OPL][2];  // x traces of the slot's rows, the inflow trace first
+#pragma unroll
+  for (int kk = 0; kk < MAXR; ++kk)
+#pragma unroll
+    for (int o = 0; o < OPL; ++o) {
+      xt[kk][o][0] = gx;
+      xt[kk][o][1] = (real)0;
+    }
 #pragma unroll
   for (int kk = 0; kk < MAXR; ++kk) {
     const int c = phys(-kk * S - slot, slot + kk * S);  // the cell each row needs on diagonal 0
@@ -434,8 +468,8 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         const int cell = phys(i, r);
         const real sc = tab[rg];
         real c[4];
-        cell_update<real, G, OPL, true>(L, g, i, r, cell, (real)0, sc * (real)v.x, sc * (real)v.y, sc * (real)v.z,
-                                  sc * (real)v.w, gx, gy, mx, my, xtr, ytr, c, ctab + rg * OPL * G, pstride);
+        cell_update_rows<real, G, OPL>(L, g, i, cell, sc * (real)v.x, sc * (real)v.y, sc * (real)v.z,
+                                       sc * (real)v.w, mx, my, xt[kk], ytr, c, ctab + rg * OPL * G, pstride);
         store_partial<real, G>(c, g, mx, my, P, cell);
       }
       // source of this row's cell on the next diagonal (issued after the last
@@ -620,10 +654,11 @@ static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T) {
          b->max_regions * G * opl <= SWEEP_COEF_ENTRIES;
 }
 
-// LDS bytes of a 2D sweep work group (traces of G * OPL ordinates; for the
-// row-slot kernel the sigma_s table and the solve coefficients).
+// LDS bytes of a 2D sweep work group (traces of G * OPL ordinates: x and y, or
+// y only for the row-slot kernel, which also stages the sigma_s table and the
+// solve coefficients).
 static size_t sweep_lds(const rte_batch* b, int G, int opl, int variant, size_t es) {
-  size_t n = (size_t)(b->max_nx + b->max_ny) * G * opl * 2;
+  size_t n = (size_t)(variant == 1 ? b->max_nx : b->max_nx + b->max_ny) * G * opl * 2;
   if (variant == 1) n += SWEEP_SIGMA_TAB + (size_t)6 * b->max_regions * G * opl;
   return n * es;
 }
