@@ -538,14 +538,15 @@ __device__ __forceinline__ CellPos cell_pos(int i, int k, int nx, int ny) {
   return p;
 }
 
-// Field f (4 unknowns) of a cell and of its four neighbours (zeros where absent).
-template <typename real>
+// Field f (4 unknowns) of a cell and of its four neighbours (zeros where
+// absent; the cell's own values are zeros too unless OWN).
+template <typename real, bool OWN = true>
 __device__ __forceinline__ void load_field(const real* __restrict__ x, const CellPos& P, int f, real c[4],
                                            real l[4], real r[4], real b[4], real t[4]) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const real* q = x + (int64_t)(4 * f + m) * P.nc + P.cell;
-    c[m] = q[0];
+    c[m] = OWN ? q[0] : (real)0;
     l[m] = P.hl ? q[-1] : (real)0;
     r[m] = P.hr ? q[1] : (real)0;
     b[m] = P.hb ? q[-P.nx] : (real)0;
@@ -554,13 +555,14 @@ __device__ __forceinline__ void load_field(const real* __restrict__ x, const Cel
 }
 
 // y = K x for one cell (12 unknowns: phi, J_x, J_y), reflection-symmetric rule,
-// one field at a time to keep few values live.
-template <typename real>
+// one field at a time to keep few values live.  !OWN: the cell's own values
+// are taken as zero (the neighbour coupling only).
+template <typename real, bool OWN = true>
 __device__ __forceinline__ void sym_cell_apply(const SymCoef<real>& S, real st, real ss,
                                                const real* __restrict__ x, const CellPos& P, real y[12]) {
   real c[4], l[4], r[4], b[4], t[4], Cx[4], Jx[4], Cy[4], Jy[4];
   // phi: its own row, and the J rows' D_C phi terms
-  load_field(x, P, 0, c, l, r, b, t);
+  load_field<real, OWN>(x, P, 0, c, l, r, b, t);
   axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
   axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
@@ -570,7 +572,7 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef<real>& S, real st, 
     y[8 + m] = S.ay * Cy[m];
   }
   // J_x: D_C^x J_x into the phi row; sigma_t, D_J^x, D_J^y into its own row
-  load_field(x, P, 1, c, l, r, b, t);
+  load_field<real, OWN>(x, P, 1, c, l, r, b, t);
   axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
   axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
@@ -579,7 +581,7 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef<real>& S, real st, 
     y[4 + m] += (real)3 * S.ax * st * c[m] - (real)1.5 * (S.cxx * Jx[m] + S.cxy * Jy[m]);
   }
   // J_y likewise
-  load_field(x, P, 2, c, l, r, b, t);
+  load_field<real, OWN>(x, P, 2, c, l, r, b, t);
   axis_cj(c, r, l, 0, S.ihx, Cx, Jx);
   axis_cj(c, t, b, 1, S.ihy, Cy, Jy);
 #pragma unroll
@@ -652,8 +654,10 @@ __device__ __forceinline__ void rb_cell(int t, int nx, int color, int& i, int& k
 
 // mode 0: y = K x; mode 1: y = b - K x;
 // mode 2 (colour c): x_c += D_c^{-1} (b - K x)_c on cells with (i + k) % 2 == c;
-// mode 3: the first colour-0 half sweep from x = 0 (x = D^{-1} b on colour 0,
-//         x = 0 on colour 1), reading no x.
+// mode 3: the first colour-0 half sweep from x = 0: x = D^{-1} b on colour 0,
+//         reading no x; colour 1 is left unwritten for mode 4;
+// mode 4: the colour-1 half sweep that follows mode 3: x = D^{-1} (b - K x) on
+//         colour 1 with its own x taken as zero (only colour 0 is read).
 template <typename real>
 __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
                                  const DsaStencil* __restrict__ st_, const double* __restrict__ st,
@@ -668,7 +672,8 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
   const int64_t vo = L.cell_off * 12;
   const real* __restrict__ bb = bvec ? bvec + vo : nullptr;
   real* __restrict__ xb = x + vo;
-  const bool compact = mode == 2 && (nx & 1) == 0;
+  const bool half = mode >= 2;  // one colour per launch
+  const bool compact = half && (nx & 1) == 0;
   const int nwork = compact ? nc / 2 : nc;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nwork; t += gridDim.x * blockDim.x) {
     int i, k;
@@ -677,21 +682,30 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
     } else {
       i = t % nx;
       k = t / nx;
-      if (mode == 2 && ((i + k) & 1) != color) continue;
+      if (half && ((i + k) & 1) != color) continue;
     }
     const CellPos P = cell_pos(i, k, nx, ny);
     const real tt = (real)st[L.cell_off + P.cell], uu = (real)ss[L.cell_off + P.cell];
     if (mode == 3) {
       real r[12], d[12];
-      const bool red = ((i + k) & 1) == 0;
 #pragma unroll
-      for (int q = 0; q < 12; ++q) r[q] = red ? bb[(int64_t)q * nc + P.cell] : (real)0;
-      if (red) sym_block_solve(S, tt, uu, r, d);
+      for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + P.cell];
+      sym_block_solve(S, tt, uu, r, d);
 #pragma unroll
-      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = red ? d[q] : (real)0;
+      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = d[q];
       continue;
     }
     real yy[12];
+    if (mode == 4) {
+      sym_cell_apply<real, false>(S, tt, uu, xb, P, yy);
+      real r[12], d[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + P.cell] - yy[q];
+      sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = d[q];
+      continue;
+    }
     sym_cell_apply(S, tt, uu, xb, P, yy);
     if (mode == 0) {
 #pragma unroll
@@ -806,11 +820,14 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
 
 // Residual and restriction in one pass (reflection-symmetric rules): each
 // coarse cell forms b - K x on its 2 x 2 children and accumulates P_f^T of it.
+// After a red-black half sweep of colour 1 the residual of every colour-1 cell
+// is zero (its neighbours all have colour 0 and did not change since), so with
+// zero_c1 only the two colour-0 children, (0, 0) and (1, 1), are formed.
 template <typename real>
 __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
                                      const DsaStencil* __restrict__ st_f, const double* __restrict__ st,
                                      const double* __restrict__ ss, const real* __restrict__ bvec,
-                                     const real* __restrict__ x, real* __restrict__ coarse_b,
+                                     const real* __restrict__ x, real* __restrict__ coarse_b, int zero_c1,
                                      const int32_t* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
@@ -826,7 +843,7 @@ __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __res
 #pragma unroll
     for (int q = 0; q < 12; ++q) acc[q] = (real)0;
 #pragma unroll 1
-    for (int ch = 0; ch < 4; ++ch) {  // children one at a time keeps few values live
+    for (int ch = 0; ch < 4; ch += zero_c1 ? 3 : 1) {  // children one at a time keeps few values live
         const int di = ch & 1, dk = ch >> 1;
         const int i = 2 * I + di, k = 2 * K + dk;
         const CellPos P = cell_pos(i, k, nfx, nfy);
@@ -864,11 +881,13 @@ struct MgTailLevel {
   const double* sigs;
 };
 
-// One red-black half sweep on an LDS level (from_zero: the colour-0 sweep from
-// x = 0, which also clears colour 1).
+// One red-black half sweep of `color` on an LDS level: mode 0 updates x; mode
+// 1 (colour 0, x = 0 beforehand) sets x = D^{-1} b and leaves colour 1
+// unwritten; mode 2 (colour 1 after mode 1) sets x = D^{-1} (b - K x) with its
+// own x taken as zero.
 template <typename real>
 __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const real* st, const real* ss,
-                                const real* bv, real* x, int color, bool from_zero) {
+                                const real* bv, real* x, int color, int mode) {
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   // even rows: the threads take only this colour's cells (nc / 2 of them)
   const bool compact = (nx & 1) == 0;
@@ -880,36 +899,38 @@ __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const 
     } else {
       i = t % nx;
       k = t / nx;
+      if (((i + k) & 1) != color) continue;
     }
     const int cell = k * nx + i;
-    const bool mine = ((i + k) & 1) == color;
-    if (!mine && !from_zero) continue;
     const CellPos P = cell_pos(i, k, nx, ny);
     const real tt = st[cell], uu = ss[cell];
     real r[12], d[12];
-    if (from_zero) {
+    if (mode == 1) {
 #pragma unroll
-      for (int q = 0; q < 12; ++q) r[q] = mine ? bv[q * nc + cell] : (real)0;
-      if (mine) sym_block_solve(S, tt, uu, r, d);
-#pragma unroll
-      for (int q = 0; q < 12; ++q) x[q * nc + cell] = mine ? d[q] : (real)0;
-      if (compact) {  // the other colour's cell of this pair starts at zero
-        int io, ko;
-        rb_cell(t, nx, color ^ 1, io, ko);
-#pragma unroll
-        for (int q = 0; q < 12; ++q) x[q * nc + ko * nx + io] = (real)0;
-      }
+      for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell];
     } else {
       real yy[12];
-      sym_cell_apply(S, tt, uu, x, P, yy);
+      if (mode == 2)
+        sym_cell_apply<real, false>(S, tt, uu, x, P, yy);
+      else
+        sym_cell_apply(S, tt, uu, x, P, yy);
 #pragma unroll
       for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell] - yy[q];
-      sym_block_solve(S, tt, uu, r, d);
-#pragma unroll
-      for (int q = 0; q < 12; ++q) x[q * nc + cell] += d[q];
     }
+    sym_block_solve(S, tt, uu, r, d);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) x[q * nc + cell] = mode == 0 ? x[q * nc + cell] + d[q] : d[q];
   }
   __syncthreads();
+}
+
+// One red-black sweep of a tail level (colour 0, then colour 1); the first
+// of a smoothing from x = 0 knows x = 0 beforehand in both half sweeps.
+template <typename real>
+__device__ __forceinline__ void tail_sweep(const SymCoef<real>& S, const LvlInst& L, const real* st,
+                                           const real* ss, const real* bv, real* x, bool from_zero) {
+  tail_half_sweep(S, L, st, ss, bv, x, 0, from_zero ? 1 : 0);
+  tail_half_sweep(S, L, st, ss, bv, x, 1, from_zero ? 2 : 0);
 }
 
 template <typename real, int NT>
@@ -956,10 +977,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     real* bv = x + 12 * nc;
     const real* sgt = x + 24 * nc;
     const real* sgs = sgt + nc;
-    for (int k = 0; k < nu_smooth; ++k) {
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, k == 0);
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, false);
-    }
+    for (int k = 0; k < nu_smooth; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
     real* bc = lds + off[l + 1] + 12 * ncc;
     for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
       const int I = c % C.nx, K = c / C.nx;
@@ -967,7 +985,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
 #pragma unroll
       for (int q = 0; q < 12; ++q) acc[q] = (real)0;
 #pragma unroll 1
-      for (int ch = 0; ch < 4; ++ch) {
+      for (int ch = 0; ch < 4; ch += 3) {  // colour-0 children: colour 1 was smoothed last
         const int di = ch & 1, dk = ch >> 1;
         const CellPos P = cell_pos(2 * I + di, 2 * K + dk, L.nx, L.ny);
         real yy[12];
@@ -996,10 +1014,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     real* bv = x + 12 * nc;
     const real* sgt = x + 24 * nc;
     const real* sgs = sgt + nc;
-    for (int k = 0; k < coarse_sweeps; ++k) {
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, k == 0);
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, false);
-    }
+    for (int k = 0; k < coarse_sweeps; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
   }
   // up: prolong the correction, post-smooth in reverse colour order
   for (int l = nlev - 2; l >= 0; --l) {
@@ -1030,8 +1045,8 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     const real* sgt = x + 24 * nc;
     const real* sgs = sgt + nc;
     for (int k = 0; k < nu_smooth; ++k) {
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, false);
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, false);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, 0);
+      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, 0);
     }
   }
   {  // store x of the first level
@@ -1271,12 +1286,14 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
   MgLevel& L = lv[l];
   const double* inv = l == 0 ? inv0 : L.inv;
   const int per_cell = l == 0 ? 0 : 1;
+  dim3 gs = grid(l);
+  if (mode >= 2) gs.x = (gs.x + 1) / 2;  // one colour: half the cells (grid-stride loop either way)
   if (sym && f32)
-    hipLaunchKernelGGL(k_mg_stencil_sym<float>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+    hipLaunchKernelGGL(k_mg_stencil_sym<float>, gs, dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x),
                        reinterpret_cast<float*>(y), act);
   else if (sym)
-    hipLaunchKernelGGL(k_mg_stencil_sym<double>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
+    hipLaunchKernelGGL(k_mg_stencil_sym<double>, gs, dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, bv, x, y, act);
   else if (nu == 12)
     hipLaunchKernelGGL(k_mg_stencil<12>, grid(l), dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
@@ -1293,12 +1310,13 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
 int DsaSolver::smooth(int l, int sweeps, bool reverse, bool from_zero, const double* bv, double* x,
                       const int32_t* act, hipStream_t s) {
   for (int k = 0; k < sweeps; ++k) {
-    if (k == 0 && from_zero && sym && !reverse) {
+    if (k == 0 && from_zero && sym && !reverse) {  // both half sweeps know x = 0 beforehand
       RTE_TRY(stencil(l, 3, 0, bv, x, nullptr, act, s));
-    } else {
-      if (k == 0 && from_zero) RTE_HIP(hipMemsetAsync(x, 0, esz() * lv[l].ncell * nu, s));
-      RTE_TRY(stencil(l, 2, reverse ? 1 : 0, bv, x, nullptr, act, s));
+      RTE_TRY(stencil(l, 4, 1, bv, x, nullptr, act, s));
+      continue;
     }
+    if (k == 0 && from_zero) RTE_HIP(hipMemsetAsync(x, 0, esz() * lv[l].ncell * nu, s));
+    RTE_TRY(stencil(l, 2, reverse ? 1 : 0, bv, x, nullptr, act, s));
     RTE_TRY(stencil(l, 2, reverse ? 0 : 1, bv, x, nullptr, act, s));
   }
   return RTE_OK;
@@ -1337,12 +1355,13 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
   MgLevel& C = lv[l + 1];
   const dim3 g = grid(l + 1);
   if (sym && f32) {
+    // the pre-smoothing ended with a colour-1 half sweep
     hipLaunchKernelGGL(k_mg_resrestrict_sym<float>, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss,
                        reinterpret_cast<const float*>(bv), reinterpret_cast<const float*>(x),
-                       reinterpret_cast<float*>(C.b), act);
+                       reinterpret_cast<float*>(C.b), 1, act);
   } else if (sym) {
     hipLaunchKernelGGL(k_mg_resrestrict_sym<double>, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss,
-                       bv, x, C.b, act);
+                       bv, x, C.b, 1, act);
   } else {
     RTE_TRY(stencil(l, 1, 0, bv, x, L.r, act, s));
     if (nu == 12)
