@@ -342,7 +342,9 @@ int rte_mlp_snapshots(const rte_batch* b, const double* sigma_t, const double* s
  * launch of a profiled kernel is bracketed by two events on its stream.
  * rte_prof_read synchronises on the recorded events and returns, for one
  * slot, the number of launches, their summed duration in milliseconds and
- * the summed work units (sweeps: cell-ordinates processed).
+ * the summed work units (sweeps: cell-ordinates processed).  A launch that
+ * found every instance already converged (FGMRES enqueues a step before it
+ * knows the outcome of the previous one) is not counted.
  * Slots: 0 FP64 sweep, 1 FP32 sweep, 2 DSA operator, 3 Arnoldi MGS, 4 ROM.  */
 int rte_prof_enable(int on);
 int rte_prof_read(int slot, int64_t* launches, double* total_ms, double* total_units);

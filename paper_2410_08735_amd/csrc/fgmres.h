@@ -20,7 +20,7 @@ struct SolveCtx {
 struct OpGraph {
   hipGraphExec_t exec = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};  // sigma_t, sigma_s, z, w
-  int prec = -1, G = 0, threads = 0, variant = -1;
+  int prec = -1, G = 0, threads = 0, variant = -1, opl = 0;
 };
 
 struct Fgmres {
@@ -30,6 +30,10 @@ struct Fgmres {
   Krylov K;
   double *btil = nullptr, *r = nullptr, *bnorm = nullptr, *tolabs = nullptr, *rnorm = nullptr;
   int32_t *cyc = nullptr, *cyc_step = nullptr, *flags = nullptr;
+  // pinned host copies of the activity mask after each Arnoldi step (two in
+  // turn) and the events that mark them complete
+  int32_t* mask_host = nullptr;
+  hipEvent_t mask_ev[2] = {nullptr, nullptr};
   // record of cycle 0 (xi recurrence): Z_0..Z_{w-1}, H block [(w+1) x w], beta
   double *recZ = nullptr, *recH = nullptr, *recBeta = nullptr, *recV = nullptr;
   int rec_w = 0;
@@ -41,8 +45,7 @@ struct Fgmres {
   int precondition(int jj, int cycle, const double* v, double* z, const SolveCtx& c, hipStream_t s,
                    std::vector<int32_t>& which);
   int solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s);
-  int apply_op(int j, int prec, const SolveCtx& c, bool use_graph, const std::vector<int32_t>& act,
-               hipStream_t s);
+  int apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s);
   void graphs_release();
 };
 

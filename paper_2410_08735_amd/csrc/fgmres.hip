@@ -22,8 +22,10 @@ int Fgmres::init(rte_batch* batch, int m_) {
       hipMalloc(&rnorm, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&cyc, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&cyc_step, sizeof(int32_t) * n) != hipSuccess ||
-      hipMalloc(&flags, sizeof(int32_t) * n) != hipSuccess)
+      hipMalloc(&flags, sizeof(int32_t) * n) != hipSuccess ||
+      hipHostMalloc(&mask_host, sizeof(int32_t) * 2 * n) != hipSuccess)
     return RTE_ENOMEM;
+  for (auto& e : mask_ev) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return RTE_OK;
 }
 
@@ -35,6 +37,12 @@ void Fgmres::release() {
     (void)hipFree(p);
   btil = r = bnorm = tolabs = rnorm = nullptr;
   cyc = cyc_step = flags = nullptr;
+  if (mask_host) (void)hipHostFree(mask_host);
+  mask_host = nullptr;
+  for (auto& e : mask_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   rec_release();
 }
 
@@ -49,9 +57,7 @@ void Fgmres::graphs_release() {
 // (precision, j) into a HIP graph and replayed; a new capture is made when the
 // cross-section arrays, the plan or the buffers change.  The kernels read the
 // activity mask from device memory, so a replay follows the current mask.
-int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, const std::vector<int32_t>& act,
-                     hipStream_t s) {
-  const double units = batch_cell_ordinates(b, act.data());
+int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s) {
   if (!use_graph) {
     RTE_TRY(sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, units));
     return reduce_partials(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active);
@@ -61,7 +67,7 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, const s
   const Plan& p = b->plan[prec];
   const void* key[4] = {c.sigma_t, c.sigma_s, K.z(j), K.v(j + 1)};
   const bool same = g.exec && g.prec == prec && g.G == p.G && g.threads == p.threads && g.variant == p.variant &&
-                    std::equal(key, key + 4, g.key);
+                    g.opl == p.opl && std::equal(key, key + 4, g.key);
   if (!same) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
@@ -85,6 +91,7 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, const s
     g.G = p.G;
     g.threads = p.threads;
     g.variant = p.variant;
+    g.opl = p.opl;
     std::copy(key, key + 4, g.key);
   }
   const bool prof = prof_enabled();
@@ -213,23 +220,46 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     // the start of a cycle; the FP64 true residual then restarts the cycle.
     RTE_TRY(kstart(K, r, tolabs, s, pin ? 1e-6 : 0.0));
     RTE_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * n, s));  // learned correction on
-    act = cm;
     for (int q = 0; q < n; ++q) stats[q].cycles += cm[q];
-    for (int j = 0; j < m; ++j) {
-      // the active mask after kstart / the previous step decides who iterates
-      RTE_HIP(hipMemcpyAsync(act.data(), K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-      RTE_HIP(hipStreamSynchronize(s));
-      bool any = false;
-      for (int q = 0; q < n; ++q) any = any || act[q];
-      if (!any) break;
+    // The device activity mask decides who iterates in each step.  The host
+    // enqueues step j before it reads the mask step j - 1 left (copied to
+    // pinned memory behind that step), so the GPU never idles on the read; a
+    // step enqueued after the last instance converged finds nobody active.
+    RTE_HIP(hipMemcpyAsync(act.data(), K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    bool any0 = false;
+    for (int q = 0; q < n; ++q) any0 = any0 || act[q];
+    const bool stall = o.precond == RTE_PC_MLP;
+    for (int j = 0; j < m && any0; ++j) {
+      const bool stall_j = stall && j + 1 <= o.window && (o.window_cycles <= 0 || cycle < o.window_cycles);
+      if (stall_j)  // who is active in this step, for the stall check after it
+        RTE_HIP(hipMemcpyAsync(cyc_step, K.active, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
       RTE_TRY(precondition(j + 1, cycle, K.v(j), K.z(j), c, s, which));
-      // w = A~ z_j = z_j - T Sigma_s z_j
-      RTE_TRY(apply_op(j, pin, c, o.use_graph != 0 && s != nullptr, act, s));
+      // w = A~ z_j = z_j - T Sigma_s z_j (work units of the previous step's mask, corrected below)
+      RTE_TRY(apply_op(j, pin, c, o.use_graph != 0 && s != nullptr, batch_cell_ordinates(b, act.data()), s));
+      const int pslot = pin ? PROF_SWEEP_F32 : PROF_SWEEP_F64;
+      const int pidx = prof_enabled() ? prof_last(pslot) : -1;
       RTE_TRY(arnoldi_mgs(K, j, s));
-      if (o.precond == RTE_PC_MLP && j + 1 <= o.window && (o.window_cycles <= 0 || cycle < o.window_cycles)) {
-        RTE_HIP(hipMemcpyAsync(cyc_step, act.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+      if (stall_j) {
         hipLaunchKernelGGL(k_stall_check, dim3((n + 63) / 64), dim3(64), 0, s, n, K.scal, cyc_step, flags);
         RTE_HIP(hipGetLastError());
+      }
+      int32_t* mh = mask_host + (j & 1) * n;
+      RTE_HIP(hipMemcpyAsync(mh, K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipEventRecord(mask_ev[j & 1], s));
+      if (j > 0) {  // the mask step j ran with, left by step j - 1
+        RTE_HIP(hipEventSynchronize(mask_ev[(j - 1) & 1]));
+        const int32_t* prev = mask_host + ((j - 1) & 1) * n;
+        bool any = false;
+        for (int q = 0; q < n; ++q) {
+          act[q] = prev[q];
+          any = any || act[q];
+        }
+        if (!any) {
+          if (pidx >= 0) prof_set_units(pslot, pidx, -1.0);
+          break;
+        }
+        if (pidx >= 0) prof_set_units(pslot, pidx, batch_cell_ordinates(b, act.data()));
       }
       for (int q = 0; q < n; ++q) {
         if (!act[q]) continue;

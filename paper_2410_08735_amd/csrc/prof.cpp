@@ -40,6 +40,17 @@ void prof_end(int slot, hipStream_t s, double units) {
   S.used++;
 }
 
+int prof_last(int slot) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return (int)g_slot[slot].used - 1;
+}
+
+void prof_set_units(int slot, int idx, double units) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Slot& S = g_slot[slot];
+  if (idx >= 0 && (size_t)idx < S.used) S.units[idx] = units;
+}
+
 // Empty kernel whose only purpose is to appear in kernel traces.
 __global__ void k_region_marker(int) {}
 
@@ -62,14 +73,17 @@ extern "C" int rte_prof_read(int slot, int64_t* launches, double* total_ms, doub
   std::lock_guard<std::mutex> lk(rte::g_mu);
   auto& S = rte::g_slot[slot];
   double ms = 0.0, u = 0.0;
+  int64_t n = 0;
   for (size_t i = 0; i < S.used; ++i) {
     if (hipEventSynchronize(S.b[i]) != hipSuccess) return RTE_EHIP;
+    if (S.units[i] < 0.0) continue;  // withdrawn (a launch that found no work)
     float t = 0.f;
     if (hipEventElapsedTime(&t, S.a[i], S.b[i]) != hipSuccess) return RTE_EHIP;
     ms += t;
     u += S.units[i];
+    ++n;
   }
-  *launches = (int64_t)S.used;
+  *launches = n;
   *total_ms = ms;
   *total_units = u;
   return RTE_OK;

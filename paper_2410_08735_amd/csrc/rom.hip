@@ -227,6 +227,84 @@ __global__ void k_rom_project(const InstDev* __restrict__ insts, const int32_t* 
   }
 }
 
+// The same projection for a batch served by one ROM, on the matrix cores:
+// g[b][k] = sum_e W[k][e] (sigma_s v_b)[e] is the product of the batch's
+// vectors (instances x DoFs) with the basis (DoFs x rank).  A wave takes 16
+// instances and every rank column over PM_DOF DoFs, in steps of 32 DoFs with
+// v_mfma_f64_16x16x4: lane l supplies instance l % 16 (A) and basis row
+// 16 c + l % 16 (B) at DoFs 8 (l / 16) + i of the step for i = 0..7, so each
+// lane reads runs of 8 consecutive DoFs; the accumulator of column block c
+// holds, in lane l and item j, instance l / 16 + 4 j and rank column
+// 16 c + l % 16.  Partial sums per (instance, DoF chunk) as above.
+constexpr int PM_DOF = 512;
+typedef double rom_d4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restrict__ insts,
+                                                          const int32_t* __restrict__ region,
+                                                          const double* __restrict__ sigma_s, int max_regions,
+                                                          const double* __restrict__ W, int r, int64_t nd, int nl,
+                                                          int n, const double* __restrict__ v,
+                                                          double* __restrict__ part, int nch,
+                                                          const int32_t* __restrict__ active) {
+  const int lane = threadIdx.x & 63;
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= nch) return;  // the whole wave
+  const int row = lane & 15, kq = lane >> 4;
+  const int b = blockIdx.y * 16 + row;
+  const bool on = b < n && (!active || active[b]);
+  const double* vb = v;
+  const int32_t* rb = region;
+  const double* sb = nullptr;
+  if (on) {
+    const InstDev I = insts[b];
+    vb = v + I.dof_off;
+    rb = region + I.region_off;
+    if (sigma_s) sb = sigma_s + (int64_t)b * max_regions;
+  }
+  const int ncb = (r + 15) >> 4;
+  rom_d4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = rom_d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t e0 = (int64_t)chunk * PM_DOF;
+  for (int st = 0; st < PM_DOF / 32; ++st) {
+    const int64_t eb = e0 + st * 32 + kq * 8;
+    if (eb - kq * 8 >= nd) break;  // past the end for the whole wave
+    double a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t e = eb + i;
+      double x = 0.0;
+      if (on && e < nd) {
+        x = vb[e];
+        if (sb) x *= sb[rb[e / nl]];
+      }
+      a[i] = x;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c >= ncb) break;
+      const int k = 16 * c + row;
+      double w[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t e = eb + i;
+        w[i] = (k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], w[i], acc[c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= ncb) break;
+    const int k = 16 * c + row;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int bi = blockIdx.y * 16 + kq + 4 * j;
+      if (bi < n && k < r) part[((int64_t)bi * nch + chunk) * ROM_RMAX + k] = acc[c][j];
+    }
+  }
+}
+
 __global__ void k_rom_gsum(int n, int nch, const RomDev* __restrict__ tab, const double* __restrict__ part,
                            double* __restrict__ g, const int32_t* __restrict__ active) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,13 +316,15 @@ __global__ void k_rom_gsum(int n, int nch, const RomDev* __restrict__ tab, const
   g[(int64_t)b * ROM_RMAX + k] = t;
 }
 
-// c = (A_D + sum_R st_R G_R - ss_R S_R)^{-1} g, LU with partial pivoting,
-// one work group of 64 threads per instance.
-__global__ void k_rom_solve(int n, const RomDev* __restrict__ tab,
-                            const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
-                            int max_regions, const double* __restrict__ g, double* __restrict__ c,
-                            int gstride, int32_t* __restrict__ singular,
-                            const int32_t* __restrict__ active) {
+// c = (A_D + sum_R st_R G_R - ss_R S_R)^{-1} g, LU with partial pivoting on
+// the matrix augmented by g, one work group of 256 threads per instance: the
+// pivot search in one wave, row swaps and the elimination over all threads.
+__global__ void __launch_bounds__(256) k_rom_solve(int n, const RomDev* __restrict__ tab,
+                                                   const double* __restrict__ sigma_t,
+                                                   const double* __restrict__ sigma_s, int max_regions,
+                                                   const double* __restrict__ g, double* __restrict__ c,
+                                                   int gstride, int32_t* __restrict__ singular,
+                                                   const int32_t* __restrict__ active) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const RomDev Rd = tab[b];
@@ -252,76 +332,86 @@ __global__ void k_rom_solve(int n, const RomDev* __restrict__ tab,
   const double* __restrict__ AD = Rd.AD;
   const double* __restrict__ G = Rd.G;
   const double* __restrict__ S = Rd.S;
-  __shared__ double A[ROM_RMAX][ROM_RMAX + 1];
-  __shared__ double rhs[ROM_RMAX];
+  __shared__ double A[ROM_RMAX][ROM_RMAX + 1];  // column r holds the right-hand side
+  __shared__ double st_s[ROM_REGMAX], ss_s[ROM_REGMAX];
+  __shared__ double amax_s, cb[ROM_RMAX];
   __shared__ int piv_s;
-  __shared__ double amax_s;
   const int t = threadIdx.x;
-  for (int i = t; i < r; i += blockDim.x) {
-    for (int k = 0; k < r; ++k) {
-      double v = AD[(int64_t)i * ld + k];
-      for (int R = 0; R < nreg; ++R) {
-        const int64_t q = (int64_t)R * ld * ld + (int64_t)i * ld + k;
-        v += sigma_t[(int64_t)b * max_regions + R] * G[q] - sigma_s[(int64_t)b * max_regions + R] * S[q];
-      }
-      A[i][k] = v;
-    }
-    rhs[i] = g[(int64_t)b * gstride + i];
+  for (int R = t; R < nreg; R += blockDim.x) {
+    st_s[R] = sigma_t[(int64_t)b * max_regions + R];
+    ss_s[R] = sigma_s[(int64_t)b * max_regions + R];
   }
   __syncthreads();
-  if (t == 0) {
+  for (int idx = t; idx < r * r; idx += blockDim.x) {
+    const int i = idx / r, k = idx - i * r;
+    double v = AD[(int64_t)i * ld + k];
+    for (int R = 0; R < nreg; ++R) {
+      const int64_t q = (int64_t)R * ld * ld + (int64_t)i * ld + k;
+      v += st_s[R] * G[q] - ss_s[R] * S[q];
+    }
+    A[i][k] = v;
+  }
+  for (int i = t; i < r; i += blockDim.x) A[i][r] = g[(int64_t)b * gstride + i];
+  __syncthreads();
+  if (t < 64) {  // max |A| for the singularity threshold
     double m = 0.0;
-    for (int i = 0; i < r; ++i)
-      for (int k = 0; k < r; ++k) m = fmax(m, fabs(A[i][k]));
-    amax_s = m;
+    for (int idx = t; idx < r * r; idx += 64) m = fmax(m, fabs(A[idx / r][idx % r]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (t == 0) amax_s = m;
   }
   __syncthreads();
   bool sing = false;
   for (int col = 0; col < r; ++col) {
-    if (t == 0) {
-      int p = col;
-      double best = fabs(A[col][col]);
-      for (int i = col + 1; i < r; ++i)
-        if (fabs(A[i][col]) > best) {
-          best = fabs(A[i][col]);
-          p = i;
+    if (t < 64) {  // first row of the largest |A[i][col]|, i >= col
+      const int i = col + t;
+      double best = i < r ? fabs(A[i][col]) : -1.0;
+      int bi = i;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
         }
-      piv_s = p;
-      if (p != col) {
-        for (int k = 0; k < r; ++k) {
-          const double tmp = A[col][k];
-          A[col][k] = A[p][k];
-          A[p][k] = tmp;
-        }
-        const double tmp = rhs[col];
-        rhs[col] = rhs[p];
-        rhs[p] = tmp;
       }
+      if (t == 0) piv_s = bi;
     }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != col)
+      for (int k = t; k <= r; k += blockDim.x) {
+        const double tmp = A[col][k];
+        A[col][k] = A[p][k];
+        A[p][k] = tmp;
+      }
     __syncthreads();
     const double d = A[col][col];
     if (!(fabs(d) > 1e-14 * amax_s)) {
       sing = true;
       break;
     }
-    for (int i = col + 1 + t; i < r; i += blockDim.x) {
-      const double f = A[i][col] / d;
-      for (int k = col + 1; k < r; ++k) A[i][k] -= f * A[col][k];
-      rhs[i] -= f * rhs[col];
-      A[i][col] = 0.0;
+    for (int i = col + 1 + t; i < r; i += blockDim.x) A[i][col] /= d;  // the multipliers
+    __syncthreads();
+    const int w = r - col;  // columns col + 1 .. r (the last is the right-hand side)
+    for (int idx = t; idx < (r - col - 1) * w; idx += blockDim.x) {
+      const int i = col + 1 + idx / w, k = col + 1 + idx % w;
+      A[i][k] -= A[i][col] * A[col][k];
     }
     __syncthreads();
   }
   if (t == 0) {
-    double* cb = c + (int64_t)b * gstride;
+    double* out = c + (int64_t)b * gstride;
     if (sing) {
-      for (int i = 0; i < r; ++i) cb[i] = 0.0;
+      for (int i = 0; i < r; ++i) out[i] = 0.0;
       if (singular) singular[b] = 1;
     } else {
       for (int i = r - 1; i >= 0; --i) {
-        double v = rhs[i];
+        double v = A[i][r];
         for (int k = i + 1; k < r; ++k) v -= A[i][k] * cb[k];
         cb[i] = v / A[i][i];
+        out[i] = cb[i];
       }
     }
   }
@@ -347,6 +437,48 @@ __global__ void k_rom_lift(const InstDev* __restrict__ insts, const RomDev* __re
     for (int k = 0; k < r; ++k) acc += cs[k] * Ww[(int64_t)k * nd + e];
     z[I.dof_off + e] = acc;
   }
+}
+
+// The same lift for a batch served by one ROM: a work group takes 256 DoFs of
+// PL_NB instances and reads each basis value once for all of them (the
+// coefficients are uniform over the group).
+constexpr int PL_NB = 16;
+__global__ void __launch_bounds__(256) k_rom_lift_group(const InstDev* __restrict__ insts,
+                                                        const double* __restrict__ W, int r, int64_t nd, int n,
+                                                        const double* __restrict__ v,
+                                                        const double* __restrict__ c, double* __restrict__ z,
+                                                        const int32_t* __restrict__ active) {
+  __shared__ int64_t off[PL_NB];
+  __shared__ int32_t on[PL_NB];
+  const int b0 = blockIdx.y * PL_NB;
+  if (threadIdx.x < PL_NB) {
+    const int b = b0 + threadIdx.x;
+    const bool o = b < n && (!active || active[b]);
+    on[threadIdx.x] = o;
+    off[threadIdx.x] = o ? insts[b].dof_off : 0;
+  }
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nd) return;
+  double acc[PL_NB];
+#pragma unroll
+  for (int q = 0; q < PL_NB; ++q) acc[q] = 0.0;
+  for (int kb = 0; kb < r; kb += 8) {
+    double w[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) w[kk] = kb + kk < r ? W[(int64_t)(kb + kk) * nd + e] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PL_NB; ++q) {
+      if (b0 + q >= n) break;
+      const double* cq = c + (int64_t)(b0 + q) * ROM_RMAX + kb;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        if (kb + kk < r) acc[q] += cq[kk] * w[kk];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PL_NB; ++q)
+    if (on[q]) z[off[q] + e] = (v ? v[off[q] + e] : 0.0) + acc[q];
 }
 
 // Greedy residual indicator: for every listed parameter (training instance)
@@ -685,16 +817,31 @@ bool rom_matches(const rte_rom* rom, const rte_batch* b) {
   return true;
 }
 
+// partial sums per instance of either projection kernel
+static int64_t rom_part_elems(const rte_batch* b, int64_t nd) {
+  return (int64_t)b->n_inst * ((nd + PM_DOF - 1) / PM_DOF) * ROM_RMAX;
+}
+
 int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const double* v, double* g,
                 const int32_t* active, hipStream_t s, const double* W) {
   const int64_t nd = rom_max_ndof(rom);
   const int nch = (int)((nd + PJ_CHUNK - 1) / PJ_CHUNK);
-  RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * ROM_RMAX);
+  RomScratch* sc = scratch_for(b, rom_part_elems(b, nd));
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
   const int which = (W && !rom->is_set() && W == rom->Ww) ? 1 : 0;
   if (W && !which) return RTE_EINVAL;  // only W_1 or W_w of the ROM itself
+  if (!rom->is_set()) {
+    const int nchm = (int)((nd + PM_DOF - 1) / PM_DOF);
+    hipLaunchKernelGGL(k_rom_project_mfma, dim3((nchm + 3) / 4, (b->n_inst + 15) / 16), dim3(256), 0, s,
+                       b->d_inst, b->d_region, sigma_s, b->max_regions, which ? rom->Ww : rom->W1, rom->r, nd,
+                       b->inst[0].nloc, b->n_inst, v, sc->part, nchm, active);
+    hipLaunchKernelGGL(k_rom_gsum, dim3((b->n_inst * ROM_RMAX + 63) / 64), dim3(64), 0, s, b->n_inst, nchm,
+                       tab, sc->part, g, active);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   hipLaunchKernelGGL(k_rom_project, dim3(nch, b->n_inst), dim3(256), 0, s, b->d_inst, b->d_region,
                      sigma_s, b->max_regions, tab, which, v, sc->part, nch, active);
   hipLaunchKernelGGL(k_rom_gsum, dim3((b->n_inst * ROM_RMAX + 63) / 64), dim3(64), 0, s, b->n_inst, nch, tab,
@@ -710,6 +857,12 @@ int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c,
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
+  if (!rom->is_set()) {
+    hipLaunchKernelGGL(k_rom_lift_group, dim3((unsigned)((nd + 255) / 256), (b->n_inst + PL_NB - 1) / PL_NB),
+                       dim3(256), 0, s, b->d_inst, rom->Ww, rom->r, nd, b->n_inst, v, c, z, active);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   dim3 grid((unsigned)std::min<int64_t>((nd + 255) / 256, 256), b->n_inst);
   hipLaunchKernelGGL(k_rom_lift, grid, dim3(256), 0, s, b->d_inst, tab, v, c, z, active);
   RTE_HIP(hipGetLastError());
@@ -724,8 +877,7 @@ int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_
     return RTE_OK;
   }
   const int64_t nd = rom_max_ndof(rom);
-  const int nch = (int)((nd + PJ_CHUNK - 1) / PJ_CHUNK);
-  RomScratch* sc = scratch_for(b, (int64_t)b->n_inst * nch * ROM_RMAX);
+  RomScratch* sc = scratch_for(b, rom_part_elems(b, nd));
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
@@ -734,7 +886,7 @@ int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_
   int32_t* sing = singular ? singular : sc->sing;
   RTE_TRY(rom_project(rom, b, sigma_s, v, g, active, s));
   RTE_HIP(hipMemsetAsync(sing, 0, sizeof(int32_t) * b->n_inst, s));
-  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(64), 0, s, b->n_inst, tab, sigma_t, sigma_s,
+  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, tab, sigma_t, sigma_s,
                      b->max_regions, g, c, ROM_RMAX, sing, active);
   RTE_HIP(hipGetLastError());
   return rom_lift(rom, b, v, c, z, active, s);
@@ -1152,7 +1304,7 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
         st = RTE_EHIP;
         break;
       }
-      hipLaunchKernelGGL(k_rom_solve, dim3(n), dim3(64), 0, s, n, tab, sigma_t, sigma_s, b->max_regions, gq, cq,
+      hipLaunchKernelGGL(k_rom_solve, dim3(n), dim3(256), 0, s, n, tab, sigma_t, sigma_s, b->max_regions, gq, cq,
                          ROM_GSTRIDE, (int32_t*)nullptr, mask);
     }
     // compact c to the unsampled order for the residual kernel

@@ -117,6 +117,10 @@ enum { PROF_SWEEP_F64 = 0, PROF_SWEEP_F32 = 1, PROF_DSA_OP = 2, PROF_MGS = 3, PR
 bool prof_enabled();
 void prof_begin(int slot, hipStream_t s);
 void prof_end(int slot, hipStream_t s, double units);
+// The index of a slot's most recent record (-1 if none), and a later change of
+// a record's units (units < 0: the record is left out of the totals).
+int prof_last(int slot);
+void prof_set_units(int slot, int idx, double units);
 double batch_cell_ordinates(const rte_batch* b, const int32_t* host_mask);
 // out = alpha * sum_partials + beta * x + gamma * y   (x, y nullable)
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
