@@ -214,8 +214,21 @@ class SolveOptions:
         return o
 
 
-def _stats_dict(s):
-    return {f: getattr(s, f) for f, _ in L.SolveStats._fields_}
+_STATS_DTYPE = None
+
+
+def _stats_array(stats):
+    """Per-instance solve statistics as a numpy structured array (a view of the
+    C structs, no copy): stats[k]["iterations"], stats["true_relres"], ..."""
+    global _STATS_DTYPE
+    if _STATS_DTYPE is None:
+        T = L.SolveStats
+        ct = {C.c_int32: "<i4", C.c_double: "<f8"}
+        _STATS_DTYPE = np.dtype({"names": [f for f, _ in T._fields_],
+                                 "formats": [ct[t] for _, t in T._fields_],
+                                 "offsets": [getattr(T, f).offset for f, _ in T._fields_],
+                                 "itemsize": C.sizeof(T)})
+    return np.frombuffer(stats, dtype=_STATS_DTYPE)
 
 
 def fgmres_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None, mlp=None, mu=None):
@@ -228,7 +241,7 @@ def fgmres_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None, m
                               rom.h if rom is not None else None, mlp.h if mlp is not None else None,
                               _ptr(mu), mu_dim, _ptr(phi), stats, _stream())
     check(st, "fgmres_solve")
-    return phi, [_stats_dict(s) for s in stats], st
+    return phi, _stats_array(stats), st
 
 
 def si_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None):
@@ -240,7 +253,7 @@ def si_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None):
     st = L.lib().si_solve(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow), C.byref(co),
                           rom.h if rom is not None else None, _ptr(phi), stats, _stream())
     check(st, "si_solve")
-    return phi, [_stats_dict(s) for s in stats], st
+    return phi, _stats_array(stats), st
 
 
 class Rom:

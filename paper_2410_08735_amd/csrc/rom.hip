@@ -238,10 +238,11 @@ __global__ void k_rom_project(const InstDev* __restrict__ insts, const int32_t* 
 // 16 c + l % 16.  Partial sums per (instance, DoF chunk) as above.
 constexpr int PM_DOF = 512;
 typedef double rom_d4 __attribute__((ext_vector_type(4)));
+template <int NL>  // moments per cell (4 in X-Y, 2 in slab geometry)
 __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restrict__ insts,
                                                           const int32_t* __restrict__ region,
                                                           const double* __restrict__ sigma_s, int max_regions,
-                                                          const double* __restrict__ W, int r, int64_t nd, int nl,
+                                                          const double* __restrict__ W, int r, int nd,
                                                           int n, const double* __restrict__ v,
                                                           double* __restrict__ part, int nch,
                                                           const int32_t* __restrict__ active) {
@@ -264,20 +265,24 @@ __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restr
   rom_d4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = rom_d4{0.0, 0.0, 0.0, 0.0};
-  const int64_t e0 = (int64_t)chunk * PM_DOF;
+  const int e0 = chunk * PM_DOF;
   for (int st = 0; st < PM_DOF / 32; ++st) {
-    const int64_t eb = e0 + st * 32 + kq * 8;
+    const int eb = e0 + st * 32 + kq * 8;  // multiple of 8, so of NL
     if (eb - kq * 8 >= nd) break;  // past the end for the whole wave
     double a[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int64_t e = eb + i;
-      double x = 0.0;
-      if (on && e < nd) {
-        x = vb[e];
-        if (sb) x *= sb[rb[e / nl]];
+      const int e = eb + i;
+      a[i] = (on && e < nd) ? vb[e] : 0.0;
+    }
+    if (sb) {
+#pragma unroll
+      for (int q = 0; q < 8 / NL; ++q) {  // the run covers 8 / NL whole cells
+        const int cell = eb / NL + q;
+        const double sg = (on && cell * NL < nd) ? sb[rb[cell]] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) a[q * NL + i] *= sg;
       }
-      a[i] = x;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -286,7 +291,7 @@ __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restr
       double w[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int64_t e = eb + i;
+        const int e = eb + i;
         w[i] = (k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
       }
 #pragma unroll
@@ -439,46 +444,53 @@ __global__ void k_rom_lift(const InstDev* __restrict__ insts, const RomDev* __re
   }
 }
 
-// The same lift for a batch served by one ROM: a work group takes 256 DoFs of
-// PL_NB instances and reads each basis value once for all of them (the
-// coefficients are uniform over the group).
-constexpr int PL_NB = 16;
-__global__ void __launch_bounds__(256) k_rom_lift_group(const InstDev* __restrict__ insts,
-                                                        const double* __restrict__ W, int r, int64_t nd, int n,
-                                                        const double* __restrict__ v,
-                                                        const double* __restrict__ c, double* __restrict__ z,
-                                                        const int32_t* __restrict__ active) {
-  __shared__ int64_t off[PL_NB];
-  __shared__ int32_t on[PL_NB];
-  const int b0 = blockIdx.y * PL_NB;
-  if (threadIdx.x < PL_NB) {
-    const int b = b0 + threadIdx.x;
-    const bool o = b < n && (!active || active[b]);
-    on[threadIdx.x] = o;
-    off[threadIdx.x] = o ? insts[b].dof_off : 0;
+// The same lift for a batch served by one ROM, on the matrix cores:
+// Z (instances x DoFs) = C (instances x rank) W (rank x DoFs) + V.  A wave
+// takes 16 instances over PL_DOF DoFs in tiles of 16 DoFs, ceil(r / 4)
+// v_mfma_f64_16x16x4 per tile: lane l supplies C[l % 16][4 s + l / 16] (held in
+// registers) and W[4 s + l / 16][tile + l % 16]; lane l, item j of the result
+// is instance l / 16 + 4 j at DoF tile + l % 16.
+constexpr int PL_DOF = 256;
+__global__ void __launch_bounds__(256) k_rom_lift_mfma(const InstDev* __restrict__ insts,
+                                                       const double* __restrict__ W, int r, int nd, int n,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ c, double* __restrict__ z,
+                                                       const int32_t* __restrict__ active) {
+  const int lane = threadIdx.x & 63;
+  const int e0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * PL_DOF;
+  if (e0 >= nd) return;  // the whole wave
+  const int row = lane & 15, kq = lane >> 4;
+  const int ba = blockIdx.y * 16 + row;
+  double ca[ROM_RMAX / 4];
+#pragma unroll
+  for (int st = 0; st < ROM_RMAX / 4; ++st) {
+    const int k = 4 * st + kq;
+    ca[st] = (ba < n && k < r) ? c[(int64_t)ba * ROM_RMAX + k] : 0.0;
   }
-  __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nd) return;
-  double acc[PL_NB];
+  int64_t off[4];
+  bool on[4];
 #pragma unroll
-  for (int q = 0; q < PL_NB; ++q) acc[q] = 0.0;
-  for (int kb = 0; kb < r; kb += 8) {
-    double w[8];
+  for (int j = 0; j < 4; ++j) {
+    const int bo = blockIdx.y * 16 + kq + 4 * j;
+    on[j] = bo < n && (!active || active[bo]);
+    off[j] = on[j] ? insts[bo].dof_off : 0;
+  }
+  const int ns = (r + 3) >> 2;
+  for (int t = 0; t < PL_DOF / 16; ++t) {
+    if (e0 + t * 16 >= nd) break;  // the whole wave
+    const int e = e0 + t * 16 + row;
+    rom_d4 acc = rom_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) w[kk] = kb + kk < r ? W[(int64_t)(kb + kk) * nd + e] : 0.0;
-#pragma unroll
-    for (int q = 0; q < PL_NB; ++q) {
-      if (b0 + q >= n) break;
-      const double* cq = c + (int64_t)(b0 + q) * ROM_RMAX + kb;
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk)
-        if (kb + kk < r) acc[q] += cq[kk] * w[kk];
+    for (int st = 0; st < ROM_RMAX / 4; ++st) {
+      if (st >= ns) break;
+      const int k = 4 * st + kq;
+      const double wv = (k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[st], wv, acc, 0, 0, 0);
     }
-  }
 #pragma unroll
-  for (int q = 0; q < PL_NB; ++q)
-    if (on[q]) z[off[q] + e] = (v ? v[off[q] + e] : 0.0) + acc[q];
+    for (int j = 0; j < 4; ++j)
+      if (on[j] && e < nd) z[off[j] + e] = (v ? v[off[j] + e] : 0.0) + acc[j];
+  }
 }
 
 // Greedy residual indicator: for every listed parameter (training instance)
@@ -832,11 +844,16 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
   if (!tab) return RTE_EHIP;
   const int which = (W && !rom->is_set() && W == rom->Ww) ? 1 : 0;
   if (W && !which) return RTE_EINVAL;  // only W_1 or W_w of the ROM itself
-  if (!rom->is_set()) {
+  if (!rom->is_set() && nd < (1 << 30)) {
     const int nchm = (int)((nd + PM_DOF - 1) / PM_DOF);
-    hipLaunchKernelGGL(k_rom_project_mfma, dim3((nchm + 3) / 4, (b->n_inst + 15) / 16), dim3(256), 0, s,
-                       b->d_inst, b->d_region, sigma_s, b->max_regions, which ? rom->Ww : rom->W1, rom->r, nd,
-                       b->inst[0].nloc, b->n_inst, v, sc->part, nchm, active);
+    const dim3 grid((nchm + 3) / 4, (b->n_inst + 15) / 16);
+    const double* Wp = which ? rom->Ww : rom->W1;
+    if (b->inst[0].nloc == 4)
+      hipLaunchKernelGGL(k_rom_project_mfma<4>, grid, dim3(256), 0, s, b->d_inst, b->d_region, sigma_s,
+                         b->max_regions, Wp, rom->r, (int)nd, b->n_inst, v, sc->part, nchm, active);
+    else
+      hipLaunchKernelGGL(k_rom_project_mfma<2>, grid, dim3(256), 0, s, b->d_inst, b->d_region, sigma_s,
+                         b->max_regions, Wp, rom->r, (int)nd, b->n_inst, v, sc->part, nchm, active);
     hipLaunchKernelGGL(k_rom_gsum, dim3((b->n_inst * ROM_RMAX + 63) / 64), dim3(64), 0, s, b->n_inst, nchm,
                        tab, sc->part, g, active);
     RTE_HIP(hipGetLastError());
@@ -857,9 +874,10 @@ int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c,
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
-  if (!rom->is_set()) {
-    hipLaunchKernelGGL(k_rom_lift_group, dim3((unsigned)((nd + 255) / 256), (b->n_inst + PL_NB - 1) / PL_NB),
-                       dim3(256), 0, s, b->d_inst, rom->Ww, rom->r, nd, b->n_inst, v, c, z, active);
+  if (!rom->is_set() && nd < (1 << 30)) {
+    const int nw = (int)((nd + PL_DOF - 1) / PL_DOF);
+    hipLaunchKernelGGL(k_rom_lift_mfma, dim3((nw + 3) / 4, (b->n_inst + 15) / 16), dim3(256), 0, s, b->d_inst,
+                       rom->Ww, rom->r, (int)nd, b->n_inst, v, c, z, active);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
