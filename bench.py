@@ -82,6 +82,7 @@ def cpu_baseline(mus, procs):
 
 
 def _solve_timed(rt, torch, B, st, ss, G, opts, rom=None, mlp=None, mu=None, reps=1):
+    import numpy as np
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):

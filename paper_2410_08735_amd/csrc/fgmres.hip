@@ -216,9 +216,11 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     if (!n_live) break;
     RTE_HIP(hipMemcpyAsync(cyc, cm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     RTE_HIP(hipMemcpyAsync(K.active, cyc, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    // FP32 sweeps cannot reduce the residual much below ~1e-6 of its value at
-    // the start of a cycle; the FP64 true residual then restarts the cycle.
-    RTE_TRY(kstart(K, r, tolabs, s, pin ? 1e-6 : 0.0));
+    // With FP32 sweeps a cycle ends once the Givens estimate is 1e-4 of its
+    // start (FP32 operators cannot take it much below ~1e-6, and measured on
+    // the 96^2 checkerboard family an earlier restart from the FP64 true
+    // residual also saves iterations: 9.4 at 1e-4 against 9.8 at 1e-6).
+    RTE_TRY(kstart(K, r, tolabs, s, pin ? 1e-4 : 0.0));
     RTE_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * n, s));  // learned correction on
     for (int q = 0; q < n; ++q) stats[q].cycles += cm[q];
     // The device activity mask decides who iterates in each step.  The host
