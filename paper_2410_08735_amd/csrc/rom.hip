@@ -236,7 +236,7 @@ __global__ void k_rom_project(const InstDev* __restrict__ insts, const int32_t* 
 // lane reads runs of 8 consecutive DoFs; the accumulator of column block c
 // holds, in lane l and item j, instance l / 16 + 4 j and rank column
 // 16 c + l % 16.  Partial sums per (instance, DoF chunk) as above.
-constexpr int PM_DOF = 512;
+constexpr int PM_DOF = 256;
 typedef double rom_d4 __attribute__((ext_vector_type(4)));
 template <int NL>  // moments per cell (4 in X-Y, 2 in slab geometry)
 __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restrict__ insts,
@@ -284,19 +284,21 @@ __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restr
         for (int i = 0; i < NL; ++i) a[q * NL + i] *= sg;
       }
     }
+    double w[4][8];  // every basis value of the step first: the loads overlap
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      if (c >= ncb) break;
       const int k = 16 * c + row;
-      double w[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int e = eb + i;
-        w[i] = (k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
+        w[c][i] = (c < ncb && k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
       }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], w[i], acc[c], 0, 0, 0);
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < ncb)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], w[c][i], acc[c], 0, 0, 0);
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -476,17 +478,20 @@ __global__ void __launch_bounds__(256) k_rom_lift_mfma(const InstDev* __restrict
     off[j] = on[j] ? insts[bo].dof_off : 0;
   }
   const int ns = (r + 3) >> 2;
+#pragma unroll 2
   for (int t = 0; t < PL_DOF / 16; ++t) {
     if (e0 + t * 16 >= nd) break;  // the whole wave
     const int e = e0 + t * 16 + row;
-    rom_d4 acc = rom_d4{0.0, 0.0, 0.0, 0.0};
+    double wv[ROM_RMAX / 4];  // every basis value of the tile first: the loads overlap
 #pragma unroll
     for (int st = 0; st < ROM_RMAX / 4; ++st) {
-      if (st >= ns) break;
       const int k = 4 * st + kq;
-      const double wv = (k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[st], wv, acc, 0, 0, 0);
+      wv[st] = (st < ns && k < r && e < nd) ? W[(int64_t)k * nd + e] : 0.0;
     }
+    rom_d4 acc = rom_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < ROM_RMAX / 4; ++st)
+      if (st < ns) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[st], wv[st], acc, 0, 0, 0);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (on[j] && e < nd) z[off[j] + e] = (v ? v[off[j] + e] : 0.0) + acc[j];
