@@ -818,6 +818,33 @@ __global__ void k_mg_transfer(int mode, const LvlInst* __restrict__ lf, const Lv
   }
 }
 
+// z = v + (x + P x_c) on the scalar-flux unknowns (field 0) of level 0, X-Y:
+// for a single V-cycle without post-smoothing on level 0 the prolongation of
+// the coarse correction and the output pass are one (the current unknowns of
+// level 0 are never needed).
+__global__ void k_dsa_out_prolong(const InstDev* __restrict__ insts, const LvlInst* __restrict__ lf,
+                                  const LvlInst* __restrict__ lc, const float* __restrict__ xf,
+                                  const float* __restrict__ xc, const double* __restrict__ v,
+                                  double* __restrict__ z, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const InstDev I = insts[b];
+  const LvlInst F = lf[b], Cc = lc[b];
+  const int nfc = F.nx * F.ny, ncc = Cc.nx * Cc.ny;
+  const float* __restrict__ xb = xf + F.cell_off * 12;
+  const float* __restrict__ cb = xc + Cc.cell_off * 12;
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < 4 * nfc; d += gridDim.x * blockDim.x) {
+    const int cell = d >> 2, m = d & 3;
+    const int i = cell % F.nx, k = cell / F.nx;
+    const int parent = (k >> 1) * Cc.nx + (i >> 1);
+    float corr = 0.f;
+#pragma unroll
+    for (int L2 = 0; L2 < 4; ++L2)
+      corr += (float)(inj1d(i & 1, m & 1, L2 & 1) * inj1d(k & 1, m >> 1, L2 >> 1)) * cb[L2 * ncc + parent];
+    z[I.dof_off + d] = v[I.dof_off + d] + (double)(xb[m * nfc + cell] + corr);
+  }
+}
+
 // Residual and restriction in one pass (reflection-symmetric rules): each
 // coarse cell forms b - K x on its 2 x 2 children and accumulates P_f^T of it.
 // After a red-black half sweep of colour 1 the residual of every colour-1 cell
@@ -1090,9 +1117,13 @@ struct DsaSolver {
   MgTailLevel* d_tail = nullptr;
   // smoothing sweeps before and after the coarse correction: nu_smooth on the
   // LDS-resident levels; on the levels streamed through HBM of the FP32
-  // stationary V-cycle nu_hbm (one sweep there costs more time than the
-  // extra FGMRES iterations it saves), nu_smooth elsewhere
-  int nu_smooth = 2, nu_hbm = 1, coarse_sweeps = 6;
+  // stationary V-cycle nu_hbm before and after, except none after on the
+  // finest level (a sweep there costs more time than the extra FGMRES
+  // iterations it saves); nu_smooth everywhere in the FP64 hierarchy
+  int nu_smooth = 2, nu_hbm = 1, nu_hbm_finest_post = 0, coarse_sweeps = 6;
+  // set by apply for one FP32 V-cycle: level 0 stops after the coarse
+  // correction, which k_dsa_out_prolong then adds while writing the output
+  bool defer_fine_prolong = false;
   int init(rte_batch* batch, int restart_);
   void release();
   int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);
@@ -1350,8 +1381,10 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     }
     return smooth(l, coarse_sweeps, false, true, bv, x, act, s);
   }
-  const int nu = f32 ? nu_hbm : nu_smooth;
-  RTE_TRY(smooth(l, nu, false, true, bv, x, act, s));
+  // smoothing sweeps before and after the coarse correction on this level
+  const int pre = f32 ? nu_hbm : nu_smooth;
+  const int post = f32 ? (l == 0 ? nu_hbm_finest_post : nu_hbm) : nu_smooth;
+  RTE_TRY(smooth(l, pre, false, true, bv, x, act, s));
   MgLevel& C = lv[l + 1];
   const dim3 g = grid(l + 1);
   if (sym && f32) {
@@ -1373,6 +1406,7 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
   }
   RTE_HIP(hipGetLastError());
   RTE_TRY(vcycle(l + 1, C.b, C.x, act, s));
+  if (l == 0 && defer_fine_prolong) return RTE_OK;
   if (f32)
     hipLaunchKernelGGL((k_mg_transfer<12, float>), g, dim3(256), 0, s, 1, L.d_li, C.d_li, (const float*)nullptr,
                        reinterpret_cast<float*>(x), reinterpret_cast<const float*>(C.x), (float*)nullptr, act);
@@ -1383,7 +1417,7 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     hipLaunchKernelGGL((k_mg_transfer<4, double>), g, dim3(256), 0, s, 1, L.d_li, C.d_li,
                        (const double*)nullptr, x, C.x, (double*)nullptr, act);
   RTE_HIP(hipGetLastError());
-  return smooth(l, nu, true, false, bv, x, act, s);
+  return smooth(l, post, true, false, bv, x, act, s);
 }
 
 // out = V-cycle(in) on level 0 (in and out may alias)
@@ -1414,11 +1448,16 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
                        sigma_s, mr, sp.d_off, v, rhs, active);
   RTE_HIP(hipGetLastError());
   std::vector<int32_t> iters(n, 0);
+  const bool fused_out = restart == 0 && inner_max == 1 && f32 && sym && lv.size() >= 2 &&
+                         nu_hbm_finest_post == 0 && tail_first != 0;
   if (restart == 0) {
     // stationary: X <- X + V(rhs - K X), inner_max cycles
     for (int k = 0; k < inner_max; ++k) {
       if (k == 0) {
-        RTE_TRY(precond(rhs, X, active, s));
+        defer_fine_prolong = fused_out;
+        const int st = precond(rhs, X, active, s);
+        defer_fine_prolong = false;
+        RTE_TRY(st);
       } else {
         RTE_TRY(stencil(0, 1, 0, rhs, X, lv[0].b, active, s));
         RTE_TRY(vcycle(0, lv[0].b, lv[0].x, active, s));
@@ -1488,7 +1527,10 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
       RTE_HIP(hipMemcpyAsync(d_live, live_h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     }
   }
-  if (f32)
+  if (fused_out)
+    hipLaunchKernelGGL(k_dsa_out_prolong, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, lv[1].d_li,
+                       reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(lv[1].x), v, z, active);
+  else if (f32)
     hipLaunchKernelGGL(k_dsa_out<float>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, sp.d_off,
                        reinterpret_cast<const float*>(X), v, z, active);
   else

@@ -57,11 +57,14 @@ def test_dsa_apply_parity_symmetric_rules():
     for k, spec in enumerate(specs):
         ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
         assert rel(B.unpack(z)[k], ref) <= 1e-11, (k, rel(B.unpack(z)[k], ref), iters)
-    # one V-cycle is already a good approximation of the DSA correction
+    # one V-cycle (no post-smoothing on the finest level) already approximates
+    # the DSA correction
     z1, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=0.0, inner_max=1, restart=0)
     for k, spec in enumerate(specs):
         ref = odsa.DSA(tr.Problem(spec)).apply(v[k])
-        assert rel(B.unpack(z1)[k] - v[k], ref - v[k]) <= 0.5
+        err = rel(B.unpack(z1)[k] - v[k], ref - v[k])
+        print(f"one FP32 V-cycle, instance {k}: rel err {err:.3e}")
+        assert err <= 0.6
     # stationary V-cycles in FP32 converge to the exact correction up to FP32 rounding
     z40, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=0.0, inner_max=40, restart=0)
     for k, spec in enumerate(specs):
