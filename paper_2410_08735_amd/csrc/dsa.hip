@@ -658,16 +658,23 @@ __device__ __forceinline__ void rb_cell(int t, int nx, int color, int& i, int& k
 //         reading no x; colour 1 is left unwritten for mode 4;
 // mode 4: the colour-1 half sweep that follows mode 3: x = D^{-1} (b - K x) on
 //         colour 1 with its own x taken as zero (only colour 0 is read).
+// vsrc (modes 3 and 4 on level 0 only, nullable): b is formed from the DG
+// vector v as [ss v, m_x ss v, m_y ss v] instead of read, and mode 3 stores
+// its colour-0 part in bout for the restriction that follows.
 template <typename real>
 __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
                                  const DsaStencil* __restrict__ st_, const double* __restrict__ st,
                                  const double* __restrict__ ss, const real* __restrict__ bvec,
                                  real* __restrict__ x, real* __restrict__ y,
-                                 const int32_t* __restrict__ active) {
+                                 const int32_t* __restrict__ active,
+                                 const double* __restrict__ vsrc = nullptr,
+                                 const InstDev* __restrict__ insts = nullptr, real* __restrict__ bout = nullptr) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const LvlInst L = li[b];
   const SymCoef<real> S = sym_coef<real>(st_[b]);
+  const double* __restrict__ vb = vsrc ? vsrc + insts[b].dof_off : nullptr;
+  const double mxr = st_[b].m[0], myr = st_[b].m[1];
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   const int64_t vo = L.cell_off * 12;
   const real* __restrict__ bb = bvec ? bvec + vo : nullptr;
@@ -686,10 +693,27 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
     }
     const CellPos P = cell_pos(i, k, nx, ny);
     const real tt = (real)st[L.cell_off + P.cell], uu = (real)ss[L.cell_off + P.cell];
-    if (mode == 3) {
-      real r[12], d[12];
+    real r[12];
+    if (vb && mode >= 3) {
+      const double sd = ss[L.cell_off + P.cell];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double sv = sd * vb[4 * P.cell + m];
+        r[m] = (real)sv;
+        r[4 + m] = (real)(mxr * sv);
+        r[8 + m] = (real)(myr * sv);
+      }
+      if (mode == 3 && bout) {
+        real* __restrict__ bo = bout + vo;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) bo[(int64_t)q * nc + P.cell] = r[q];
+      }
+    } else if (mode >= 3) {
 #pragma unroll
       for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + P.cell];
+    }
+    if (mode == 3) {
+      real d[12];
       sym_block_solve(S, tt, uu, r, d);
 #pragma unroll
       for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = d[q];
@@ -698,9 +722,9 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
     real yy[12];
     if (mode == 4) {
       sym_cell_apply<real, false>(S, tt, uu, xb, P, yy);
-      real r[12], d[12];
+      real d[12];
 #pragma unroll
-      for (int q = 0; q < 12; ++q) r[q] = bb[(int64_t)q * nc + P.cell] - yy[q];
+      for (int q = 0; q < 12; ++q) r[q] -= yy[q];
       sym_block_solve(S, tt, uu, r, d);
 #pragma unroll
       for (int q = 0; q < 12; ++q) xb[(int64_t)q * nc + P.cell] = d[q];
@@ -1124,6 +1148,9 @@ struct DsaSolver {
   // set by apply for one FP32 V-cycle: level 0 stops after the coarse
   // correction, which k_dsa_out_prolong then adds while writing the output
   bool defer_fine_prolong = false;
+  // set by apply for that V-cycle too: level 0's first two half sweeps form
+  // the right-hand side from v (the first stores its colour-0 part)
+  const double* rhs_from_v = nullptr;
   int init(rte_batch* batch, int restart_);
   void release();
   int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);
@@ -1319,10 +1346,12 @@ int DsaSolver::stencil(int l, int mode, int color, const double* bv, double* x, 
   const int per_cell = l == 0 ? 0 : 1;
   dim3 gs = grid(l);
   if (mode >= 2) gs.x = (gs.x + 1) / 2;  // one colour: half the cells (grid-stride loop either way)
+  const bool from_v = rhs_from_v && l == 0 && mode >= 3;
   if (sym && f32)
     hipLaunchKernelGGL(k_mg_stencil_sym<float>, gs, dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x),
-                       reinterpret_cast<float*>(y), act);
+                       reinterpret_cast<float*>(y), act, from_v ? rhs_from_v : nullptr, b->d_inst,
+                       from_v ? reinterpret_cast<float*>(const_cast<double*>(bv)) : nullptr);
   else if (sym)
     hipLaunchKernelGGL(k_mg_stencil_sym<double>, gs, dim3(256), 0, s, mode, color, L.d_li, L.d_st, L.st,
                        L.ss, bv, x, y, act);
@@ -1440,7 +1469,11 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
   const int n = b->n_inst;
   const int mr = b->max_regions;
   if (prep) RTE_TRY(prepare(sigma_t, sigma_s, active, s));
-  if (f32)
+  const bool fused_out = restart == 0 && inner_max == 1 && f32 && sym && lv.size() >= 2 &&
+                         nu_hbm_finest_post == 0 && tail_first != 0 && nu_hbm >= 1;
+  if (fused_out) {
+    // the V-cycle forms the right-hand side itself
+  } else if (f32)
     hipLaunchKernelGGL(k_dsa_rhs<float>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_region, sigma_s,
                        mr, sp.d_off, v, reinterpret_cast<float*>(rhs), active);
   else
@@ -1448,15 +1481,15 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
                        sigma_s, mr, sp.d_off, v, rhs, active);
   RTE_HIP(hipGetLastError());
   std::vector<int32_t> iters(n, 0);
-  const bool fused_out = restart == 0 && inner_max == 1 && f32 && sym && lv.size() >= 2 &&
-                         nu_hbm_finest_post == 0 && tail_first != 0;
   if (restart == 0) {
     // stationary: X <- X + V(rhs - K X), inner_max cycles
     for (int k = 0; k < inner_max; ++k) {
       if (k == 0) {
         defer_fine_prolong = fused_out;
+        rhs_from_v = fused_out ? v : nullptr;
         const int st = precond(rhs, X, active, s);
         defer_fine_prolong = false;
+        rhs_from_v = nullptr;
         RTE_TRY(st);
       } else {
         RTE_TRY(stencil(0, 1, 0, rhs, X, lv[0].b, active, s));
