@@ -192,7 +192,9 @@ __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g,
   c[0] = c[1] = c[2] = c[3] = (real)0;
 #pragma unroll
   for (int o = 0; o < OPL; ++o) {
-    const int xo = (r * G * OPL + g * OPL + o) * 2, yo = (i * G * OPL + g * OPL + o) * 2;
+    // trace slots [row or column][o][g][2]: the G lanes of a cell touch one
+    // contiguous run of LDS per ordinate (no bank conflicts within a cell)
+    const int xo = ((r * OPL + o) * G + g) * 2, yo = ((i * OPL + o) * G + g) * 2;
     const real a = L.a[o], b = L.b[o];
     real tx0, tx1, ty0, ty1;
     if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; }
@@ -235,7 +237,7 @@ __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, i
   c[0] = c[1] = c[2] = c[3] = (real)0;
 #pragma unroll
   for (int o = 0; o < OPL; ++o) {
-    const int yo = (i * G * OPL + g * OPL + o) * 2;
+    const int yo = ((i * OPL + o) * G + g) * 2;  // [column][o][g][2], as in cell_update
     const real a = L.a[o], b = L.b[o];
     const real tx0 = xt[o][0], tx1 = xt[o][1];
     const real ty0 = ytr[yo], ty1 = ytr[yo + 1];
@@ -310,8 +312,8 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
   const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
   const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
-  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][G * OPL][2]
-  real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][G * OPL][2]
+  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][OPL][G][2]
+  real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][OPL][G][2]
   const double* st = sigma_t + (size_t)it.inst * max_regions;
   const double* ss = sigma_s ? sigma_s + (size_t)it.inst * max_regions : nullptr;
   const int32_t* reg = region + I.region_off;
@@ -398,7 +400,7 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
   const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
-  real* ytr = reinterpret_cast<real*>(smem_raw);  // [nx][G * OPL][2]
+  real* ytr = reinterpret_cast<real*>(smem_raw);  // [nx][OPL][G][2]
   real* tab = ytr + (size_t)nx * G * OPL * 2;     // [SWEEP_SIGMA_TAB]: sigma_s
   using P2 = typename Pair2<real>::T;
   P2* ctab = reinterpret_cast<P2*>(tab + SWEEP_SIGMA_TAB);  // [3][n_regions][OPL][G]
