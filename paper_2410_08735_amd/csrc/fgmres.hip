@@ -53,14 +53,16 @@ void Fgmres::graphs_release() {
 }
 
 // w = z_j - T Sigma_s z_j into v_{j+1}: one batched sweep and the deterministic
-// partial-flux reduction.  With use_graph the pair is captured once per
+// partial-flux reduction, which also leaves the chunk partials of <w, v_0> in
+// K.partA for the first MGS projection.  With use_graph the pair is captured once per
 // (precision, j) into a HIP graph and replayed; a new capture is made when the
 // cross-section arrays, the plan or the buffers change.  The kernels read the
 // activity mask from device memory, so a replay follows the current mask.
 int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s) {
   if (!use_graph) {
     RTE_TRY(sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, units));
-    return reduce_partials(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active);
+    return reduce_partials_dot(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), K.v(0), K.partA, K.sp.max_chunks(),
+                               KCHUNK, s, K.active);
   }
   if ((int)graphs.size() < 2 * m) graphs.resize(2 * m);
   OpGraph& g = graphs[prec * m + j];
@@ -75,7 +77,9 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double 
     RTE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     // no profiler events inside the capture; they are recorded around the launch
     int st = sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, -2.0);
-    if (st == RTE_OK) st = reduce_partials(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), s, K.active);
+    if (st == RTE_OK)
+      st = reduce_partials_dot(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), K.v(0), K.partA, K.sp.max_chunks(),
+                               KCHUNK, s, K.active);
     const hipError_t e = hipStreamEndCapture(s, &graph);
     if (st != RTE_OK || e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -241,7 +245,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       RTE_TRY(apply_op(j, pin, c, o.use_graph != 0 && s != nullptr, batch_cell_ordinates(b, act.data()), s));
       const int pslot = pin ? PROF_SWEEP_F32 : PROF_SWEEP_F64;
       const int pidx = prof_enabled() ? prof_last(pslot) : -1;
-      RTE_TRY(arnoldi_mgs(K, j, s));
+      RTE_TRY(arnoldi_mgs(K, j, s, true));  // apply_op left <w, v_0> in partA
       if (stall_j) {
         hipLaunchKernelGGL(k_stall_check, dim3((n + 63) / 64), dim3(64), 0, s, n, K.scal, cyc_step, flags);
         RTE_HIP(hipGetLastError());

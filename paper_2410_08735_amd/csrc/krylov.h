@@ -60,7 +60,9 @@ int kaxpby(const Space& sp, double a, const double* x, double bcoef, double* y,
 int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hipStream_t s);
 // Arnoldi step j: w (= V[j+1] slot) orthogonalised against V[0..j] by MGS,
 // H[:, j] filled, w normalised, Givens rotation applied, est and active updated.
-int arnoldi_mgs(Krylov& K, int j, hipStream_t s);
+// first_dot_ready: partA already holds the chunk partials of <w, v_0> (the
+// operator's reduction produced them)
+int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready = false);
 // y = R^{-1} g per instance (jdone columns); X += sum_i y_i * basis_i
 int kylov_solve_update(Krylov& K, const double* basis, double* X, hipStream_t s);
 // start a cycle: V[0] = r / ||r||, g = (beta, 0, ...); the cycle stops at

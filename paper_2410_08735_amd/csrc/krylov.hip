@@ -339,12 +339,13 @@ int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s, dou
   return kscale(sp, r, K.scal + 0, 8, K.v(0), K.active, s);
 }
 
-int arnoldi_mgs(Krylov& K, int j, hipStream_t s) {
+int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready) {
   const Space& sp = K.sp;
   const int mc = sp.max_chunks();
   double* w = K.v(j + 1);
-  hipLaunchKernelGGL(k_dot_part, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, w, K.v(0),
-                     K.partA, mc, K.active);
+  if (!first_dot_ready)
+    hipLaunchKernelGGL(k_dot_part, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, w, K.v(0),
+                       K.partA, mc, K.active);
   double* pin = K.partA;
   double* pout = K.partB;
   for (int i = 0; i <= j; ++i) {

@@ -568,6 +568,45 @@ __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
   }
 }
 
+// reduce_partials_kernel fused with the partial dot products <out, dotv>: one
+// work group per chunk of `chunk` DoFs, threads strided over it, then a
+// wave-shuffle and cross-wave sum (256 threads).
+template <typename real>
+__global__ void __launch_bounds__(256) reduce_partials_dot_kernel(
+    const InstDev* __restrict__ insts, const InstPart* __restrict__ parts, const real* __restrict__ part,
+    double alpha, const double* __restrict__ x, double beta, double* __restrict__ out,
+    const double* __restrict__ dotv, double* __restrict__ dpart, int maxc, int chunk,
+    const int32_t* __restrict__ active) {
+  __shared__ double sh[4];
+  const int inst = blockIdx.y, c = blockIdx.x;
+  if (active && !active[inst]) return;
+  const InstDev I = insts[inst];
+  const int64_t nd = (int64_t)I.nx * I.ny * I.nloc, start = (int64_t)c * chunk;
+  if (start >= nd) return;
+  const int64_t end = min(nd, start + (int64_t)chunk);
+  const InstPart pp = parts[inst];
+  double acc = 0.0;
+  for (int64_t d = start + threadIdx.x; d < end; d += blockDim.x) {
+    double t = 0.0;
+    const real* p = part + pp.off + d;
+    for (int k = 0; k < pp.n; ++k) t += (double)p[(int64_t)k * nd];
+    double v = alpha * t;
+    if (x) v += beta * x[I.dof_off + d];
+    out[I.dof_off + d] = v;
+    acc += v * dotv[I.dof_off + d];
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tsum = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tsum += sh[k];
+    dpart[(int64_t)inst * maxc + c] = tsum;
+  }
+}
+
 __global__ void scalar_flux_kernel(const InstDev* __restrict__ insts, const double* __restrict__ w,
                                    const int32_t* __restrict__ perm,
                                    const double* __restrict__ psi, double* __restrict__ phi) {
@@ -801,6 +840,23 @@ int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, doubl
   else
     hipLaunchKernelGGL(reduce_partials_kernel<float>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
                        reinterpret_cast<const float*>(b->d_part), alpha, x, beta, y, gamma, out,
+                       active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
+int reduce_partials_dot(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
+                        const double* dotv, double* part, int maxc, int chunk, hipStream_t s,
+                        const int32_t* active) {
+  const Plan& p = b->plan[prec];
+  const dim3 grid((unsigned)maxc, b->n_inst);
+  if (prec == 0)
+    hipLaunchKernelGGL(reduce_partials_dot_kernel<double>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
+                       reinterpret_cast<const double*>(b->d_part), alpha, x, beta, out, dotv, part, maxc, chunk,
+                       active);
+  else
+    hipLaunchKernelGGL(reduce_partials_dot_kernel<float>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
+                       reinterpret_cast<const float*>(b->d_part), alpha, x, beta, out, dotv, part, maxc, chunk,
                        active);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
