@@ -58,27 +58,35 @@ def summarise(path, top=25):
 
 
 def summarise_counters(path, top=25):
+    """Mean counter value per dispatch, per kernel, between the timed-region
+    markers and between the copy-probe markers.  A dispatch whose counter sum
+    is below 0.1 % of the kernel's largest did no work (FGMRES enqueues a step
+    before it knows that every instance has converged); such dispatches are
+    counted in their own column and left out of the mean."""
     rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
     marks = [i for i, r in enumerate(rows) if MARKER in r["Kernel_Name"]]
     out = []
     for title, (a, b) in (("timed region (markers 1-2)", (0, 1)), ("copy probe (markers 3-4)", (2, 3))):
         if len(marks) <= b:
             continue
-        agg = collections.defaultdict(lambda: collections.defaultdict(list))
-        disp = collections.defaultdict(set)
+        per = collections.defaultdict(lambda: collections.defaultdict(dict))  # kernel -> dispatch -> counter
         for r in rows[marks[a] + 1:marks[b]]:
             if MARKER in r["Kernel_Name"]:
                 continue
             k = _short(r["Kernel_Name"])
-            agg[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
-            disp[k].add(r["Dispatch_Id"])
-        names = sorted({c for v in agg.values() for c in v})
-        out += [f"### {title}", "", "| kernel | dispatches | " + " | ".join(f"mean {c} per dispatch" for c in names)
-                + " |", "|---|---:|" + "---:|" * len(names)]
-        order = sorted(agg, key=lambda k: -sum(sum(v) for v in agg[k].values()))[:top]
-        for k in order:
-            vals = [sum(agg[k][c]) / len(disp[k]) if agg[k][c] else 0.0 for c in names]
-            out.append(f"| `{k}` | {len(disp[k])} | " + " | ".join(f"{v:.1f}" for v in vals) + " |")
+            d = per[k][r["Dispatch_Id"]]
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        names = sorted({c for v in per.values() for d in v.values() for c in d})
+        out += [f"### {title}", "", "| kernel | dispatches with work | no-work dispatches | "
+                + " | ".join(f"mean {c} per dispatch" for c in names) + " |",
+                "|---|---:|---:|" + "---:|" * len(names)]
+        tot = {k: sum(sum(d.values()) for d in v.values()) for k, v in per.items()}
+        for k in sorted(per, key=lambda k: -tot[k])[:top]:
+            big = max(sum(d.values()) for d in per[k].values())
+            work = [d for d in per[k].values() if sum(d.values()) >= 1e-3 * big]
+            vals = [sum(d.get(c, 0.0) for d in work) / len(work) for c in names]
+            out.append(f"| `{k}` | {len(work)} | {len(per[k]) - len(work)} | "
+                       + " | ".join(f"{v:.1f}" for v in vals) + " |")
         out.append("")
     return "\n".join(out)
 
