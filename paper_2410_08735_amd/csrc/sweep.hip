@@ -544,6 +544,24 @@ __global__ void sweep1d_kernel(const InstDev* __restrict__ insts, const InstPart
   }
 }
 
+// sum_k p[k * nd] in order k = 0, 1, ... (the loads four at a time, so that
+// several are in flight; the additions keep their order)
+template <typename real>
+__device__ __forceinline__ double sum_partials(const real* __restrict__ p, int n, int64_t nd) {
+  double t = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    const real a0 = p[(int64_t)k * nd], a1 = p[(int64_t)(k + 1) * nd];
+    const real a2 = p[(int64_t)(k + 2) * nd], a3 = p[(int64_t)(k + 3) * nd];
+    t += (double)a0;
+    t += (double)a1;
+    t += (double)a2;
+    t += (double)a3;
+  }
+  for (; k < n; ++k) t += (double)p[(int64_t)k * nd];
+  return t;
+}
+
 template <typename real>
 __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
                                        const InstPart* __restrict__ parts,
@@ -558,9 +576,7 @@ __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
   const InstPart pp = parts[inst];
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd;
        d += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    const real* p = part + pp.off + d;
-    for (int k = 0; k < pp.n; ++k) acc += (double)p[(int64_t)k * nd];
+    const double acc = sum_partials(part + pp.off + d, pp.n, nd);
     double v = alpha * acc;
     if (x) v += beta * x[I.dof_off + d];
     if (y) v += gamma * y[I.dof_off + d];
@@ -587,9 +603,7 @@ __global__ void __launch_bounds__(256) reduce_partials_dot_kernel(
   const InstPart pp = parts[inst];
   double acc = 0.0;
   for (int64_t d = start + threadIdx.x; d < end; d += blockDim.x) {
-    double t = 0.0;
-    const real* p = part + pp.off + d;
-    for (int k = 0; k < pp.n; ++k) t += (double)p[(int64_t)k * nd];
+    const double t = sum_partials(part + pp.off + d, pp.n, nd);
     double v = alpha * t;
     if (x) v += beta * x[I.dof_off + d];
     out[I.dof_off + d] = v;
