@@ -2,6 +2,7 @@
 routines, exactness properties and identities fixed by the paper."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from oracle import dsa, mlp, rom
@@ -90,6 +91,38 @@ def test_fc_dsa_two_constructions_agree_and_contract(spec):
     E = np.eye(P.ndof) - np.stack([D.apply(e) for e in np.eye(P.ndof)], 1) @ At
     rho = max(abs(np.linalg.eigvals(E)))
     assert rho < 0.35
+
+
+@pytest.mark.parametrize("spec", [tiny_1d(nx=8, n_ord=8), tiny_2d(seed=6, nx=5, ny=5, quad=("cl", 8, 4, True)),
+                                  tiny_2d(seed=7, nx=4, ny=3, quad=("cl", 6, 3, False))])
+def test_pc_dsa_first_moment_rows_keep_only_the_central_flux(spec):
+    """PC-DSA (App. A, last paragraph) drops the jump operator from the
+    first-moment rows.  Built independently: the central part of the assembled
+    upwind operator, C(Omega) = (D(Omega) - D(-Omega)) / 2 from the operators of
+    the two mirrored directions, replaces D_j in the first-moment rows of the
+    angular-moment construction; this equals the D_C / D_J form with the jump
+    terms dropped, and differs from FC-DSA."""
+    from oracle import dg
+    P = tr.Problem(spec)
+    ax = [0] if P.mesh.dim == 1 else [0, 1]
+    om = {0: P.ox, 1: P.oy}
+    Dn = [dg.advection(P.mesh, -P.ox[j], -P.oy[j]).tocsc() for j in range(P.nord)]
+    C = [0.5 * (P.D(j) - Dn[j]) for j in range(P.nord)]
+    Sa = P.St - P.Ss
+    m = {f: float(np.sum(P.w * om[f])) for f in ax}
+    a = {(d, f): float(np.sum(P.w * om[d] * om[f])) for d in ax for f in ax}
+    E = sum(P.w[j] * P.D(j) for j in range(P.nord))
+    Ef = {f: sum(P.w[j] * om[f][j] * P.D(j) for j in range(P.nord)) for f in ax}
+    rows = [[E + Sa] + [3.0 * (Ef[f] + m[f] * P.St) for f in ax]]
+    for d in ax:
+        Cd = sum(P.w[j] * om[d][j] * C[j] for j in range(P.nord))
+        Cdf = {f: sum(P.w[j] * om[d][j] * om[f][j] * C[j] for j in range(P.nord)) for f in ax}
+        rows.append([Cd + m[d] * Sa] + [3.0 * (Cdf[f] + a[(d, f)] * P.St) for f in ax])
+    K = sp.bmat(rows, format="csc").toarray()
+    Kpc = dsa.fc_system_appA(P, partially_consistent=True)[0].toarray()
+    Kfc = dsa.fc_system_appA(P)[0].toarray()
+    assert np.abs(K - Kpc).max() < 1e-12 * np.abs(Kpc).max()
+    assert np.abs(Kfc - Kpc).max() > 1e-3 * np.abs(Kfc).max()
 
 
 # ---------------------------------------------------------------- ROMSAD (section 4)
