@@ -62,6 +62,11 @@ enum { RTE_F64 = 0, RTE_F32 = 1, RTE_BF16 = 2 };
 
 enum { RTE_PC_NONE = 0, RTE_PC_DSA = 1, RTE_PC_ROMSAD = 2, RTE_PC_MLP = 3 };
 
+/* DSA variants (App. A): fully consistent, or partially consistent (the
+ * first-moment rows keep only the central-flux part of the advection, the
+ * jump part D_J is dropped there).                                           */
+enum { RTE_DSA_FC = 0, RTE_DSA_PC = 1 };
+
 typedef struct rte_batch rte_batch;
 typedef struct rte_rom rte_rom;
 typedef struct rte_mlp rte_mlp;
@@ -146,7 +151,8 @@ int rte_rhs(const rte_batch* b, const double* sigma_t, const double* G, const do
  * consistent P1 moment system of App. A (zeroth and first angular moments of
  * the upwind correction equation under delta psi_j = dphi + 3 Omega_j.dJ,
  * written for X-Y geometry with the same two steps) with right-hand side
- * Sigma_s v.  restart >= 1: restarted GMRES (Krylov dimension `restart`)
+ * Sigma_s v; variant RTE_DSA_PC solves the partially consistent system of the
+ * same appendix instead (no D_J terms in the first-moment rows).  restart >= 1: restarted GMRES (Krylov dimension `restart`)
  * preconditioned with one geometric-multigrid V-cycle per step (2 x 2 cell
  * agglomeration, red-black block Gauss-Seidel smoothing with exact cell-block
  * solves), in FP64, until the relative residual is <= inner_tol or inner_max
@@ -155,10 +161,12 @@ int rte_rhs(const rte_batch* b, const double* sigma_t, const double* G, const do
  * hierarchy then runs in FP32 (a preconditioner, not an exact solve).
  * stats_iters (host [n_inst], nullable) receives the iterations used.
  * Errors: RTE_EINVAL for null pointers, inner_max < 1, restart outside
- * [0, 500] or a negative / NaN inner_tol.                                     */
+ * [0, 500], a negative / NaN inner_tol, an unknown variant, or RTE_DSA_PC with
+ * restart = 0 (the block smoother does not converge on the PC system: PC
+ * solves always run the preconditioned GMRES).                              */
 int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v,
-                  double* z, double inner_tol, int inner_max, int restart, int32_t* stats_iters,
-                  void* stream);
+                  double* z, double inner_tol, int inner_max, int restart, int variant,
+                  int32_t* stats_iters, void* stream);
 
 /* ---------------------------------------------------------------- FGMRES
  * fgmres_solve: Alg. 1 (flexible GMRES) for A~ phi = b~ on every instance,
@@ -193,6 +201,9 @@ typedef struct {
                             (batched sweep + reduction) is captured once into a
                             HIP graph and replayed; needs a created stream (on
                             the null stream the operator runs eagerly)       */
+  int32_t dsa_variant;   /* RTE_DSA_FC or RTE_DSA_PC for every DSA application
+                            (the DSA preconditioner and ROMSAD after the
+                            window); RTE_DSA_PC needs dsa_restart >= 1      */
 } rte_solve_opts;
 
 typedef struct {

@@ -182,18 +182,23 @@ def rhs(batch, sigma_t, G, inflow=None, dtype="f64"):
     return y
 
 
-def dsa_apply(batch, sigma_t, sigma_s, v, inner_tol=1e-13, inner_max=2000, restart=60):
+_DSA_VARIANTS = {"fc": 0, "pc": 1}
+
+
+def dsa_apply(batch, sigma_t, sigma_s, v, inner_tol=1e-13, inner_max=2000, restart=60, variant="fc"):
     z = batch.zeros()
     iters = np.zeros(batch.n, dtype=np.int32)
     check(L.lib().rte_dsa_apply(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(v), _ptr(z), inner_tol,
-                                inner_max, restart, iters.ctypes.data_as(L.pi32), _stream()),
+                                inner_max, restart, _DSA_VARIANTS[variant],
+                                iters.ctypes.data_as(L.pi32), _stream()),
           "rte_dsa_apply")
     return z, iters
 
 
 class SolveOptions:
     def __init__(self, precond="dsa", m=30, max_cycles=20, sweep_dtype="f64", rtol=1e-8, window=2,
-                 dsa_inner_max=30, dsa_restart=30, dsa_inner_tol=1e-10, window_cycles=0, use_graph=False):
+                 dsa_inner_max=30, dsa_restart=30, dsa_inner_tol=1e-10, window_cycles=0, use_graph=False,
+                 dsa_variant="fc"):
         self.precond = {"none": RTE_PC_NONE, "dsa": RTE_PC_DSA, "romsad": RTE_PC_ROMSAD,
                         "mlp": RTE_PC_MLP}[precond] if isinstance(precond, str) else precond
         self.m, self.max_cycles, self.sweep_dtype, self.rtol = m, max_cycles, sweep_dtype, rtol
@@ -201,6 +206,7 @@ class SolveOptions:
         self.dsa_inner_max, self.dsa_restart, self.dsa_inner_tol = dsa_inner_max, dsa_restart, dsa_inner_tol
         self.window_cycles = window_cycles
         self.use_graph = use_graph
+        self.dsa_variant = dsa_variant
 
     def c(self):
         o = L.SolveOpts()
@@ -211,6 +217,7 @@ class SolveOptions:
         o.keep_krylov = 0
         o.window_cycles = self.window_cycles
         o.use_graph = 1 if self.use_graph else 0
+        o.dsa_variant = _DSA_VARIANTS[self.dsa_variant]
         return o
 
 

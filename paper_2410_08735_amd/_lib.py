@@ -33,7 +33,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("precond", i32), ("m", i32), ("max_cycles", i32), ("sweep_dtype", i32),
                 ("rtol", dbl), ("window", i32), ("dsa_inner_max", i32), ("dsa_restart", i32),
                 ("dsa_inner_tol", dbl), ("keep_krylov", i32), ("window_cycles", i32),
-                ("use_graph", i32)]
+                ("use_graph", i32), ("dsa_variant", i32)]
 
 
 class SolveStats(C.Structure):
@@ -65,7 +65,7 @@ SIGNATURES = {
     "rte_scalar_flux": (C.c_int, [vp, vp, vp, vp]),
     "rte_apply_A": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, vp]),
     "rte_rhs": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, vp]),
-    "rte_dsa_apply": (C.c_int, [vp, vp, vp, vp, vp, dbl, C.c_int, C.c_int, pi32, vp]),
+    "rte_dsa_apply": (C.c_int, [vp, vp, vp, vp, vp, dbl, C.c_int, C.c_int, C.c_int, pi32, vp]),
     "fgmres_solve": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, C.c_int, vp,
                                C.POINTER(SolveStats), vp]),
     "si_solve": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, C.POINTER(SolveStats), vp]),

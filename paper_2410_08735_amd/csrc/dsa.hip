@@ -54,6 +54,16 @@ struct DsaStencil {
   // the scalars of the structured form used by the fast kernels
   int sym;
   double ax, ay, bex, bey, cxx, cxy, cyx, cyy, hx, hy;
+  // The smoother's cell blocks are always those of the FC system: bcxx..bcyy
+  // are the FC jump coefficients of the first-moment rows (the structured
+  // form) and blkd the FC self block (general form).  For PC, whose blocks
+  // lack the jump terms in the first-moment rows, red-black block
+  // Gauss-Seidel with its own blocks diverges (dJ couples to the neighbours'
+  // dphi through central fluxes only); with the FC blocks a V(2,2) cycle is
+  // a good GMRES preconditioner for it, though no dependable stationary
+  // iteration, so PC solves always run the Krylov method (restart >= 1).
+  double bcxx, bcxy, bcyx, bcyy;
+  double blkd[DMAX * DMAX];
 };
 
 __device__ static void axis_ops(double h, double DCs[4], double DCp[4], double DCm[4], double DJs[4],
@@ -74,9 +84,11 @@ __device__ static void axis_ops(double h, double DCs[4], double DCp[4], double D
 }
 
 // One thread per instance builds its stencil (moments in a fixed order).
+// pc: the partially consistent variant (App. A, last paragraph), whose
+// first-moment rows keep only the central-flux part of the advection.
 __global__ void k_dsa_setup(int n_inst, const InstDev* __restrict__ insts,
                             const double* __restrict__ ox, const double* __restrict__ oy,
-                            const double* __restrict__ w, DsaStencil* __restrict__ out) {
+                            const double* __restrict__ w, DsaStencil* __restrict__ out, int pc) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_inst) return;
   const InstDev I = insts[b];
@@ -134,21 +146,26 @@ __global__ void k_dsa_setup(int n_inst, const InstDev* __restrict__ insts,
     S.ay = a[1][1];
     S.bex = be[0];
     S.bey = be[1];
-    S.cxx = c[0][0][0];
-    S.cxy = c[0][1][0];
-    S.cyx = c[1][0][1];
-    S.cyy = c[1][1][1];
+    // the jump terms of the first-moment rows (none in PC-DSA)
+    S.cxx = pc ? 0.0 : c[0][0][0];
+    S.cxy = pc ? 0.0 : c[0][1][0];
+    S.cyx = pc ? 0.0 : c[1][0][1];
+    S.cyy = pc ? 0.0 : c[1][1][1];
     S.hx = I.hx;
     S.hy = I.hy;
+    S.bcxx = c[0][0][0];
+    S.bcxy = c[0][1][0];
+    S.bcyx = c[1][0][1];
+    S.bcyy = c[1][1][1];
   }
   for (int z = 0; z < 5; ++z)
     for (int q = 0; q < DMAX * DMAX; ++q) S.blk[z][q] = 0.0;
-  for (int q = 0; q < DMAX * DMAX; ++q) S.St[q] = S.Ss[q] = 0.0;
+  for (int q = 0; q < DMAX * DMAX; ++q) S.St[q] = S.Ss[q] = S.blkd[q] = 0.0;
   // field blocks: coefficient (alpha_C[e], alpha_J[e]) for field row F, column F'
   // F = 0: dphi, F = 1 + d: dJ_d
   for (int F = 0; F <= ne; ++F)
     for (int Fp = 0; Fp <= ne; ++Fp) {
-      double aC[2] = {0, 0}, aJ[2] = {0, 0};
+      double aC[2] = {0, 0}, aJ[2] = {0, 0}, aJf[2] = {0, 0};  // aJf: FC jump weights
       for (int e = 0; e < ne; ++e) {
         if (F == 0 && Fp == 0) {
           aC[e] = m[e];
@@ -160,20 +177,26 @@ __global__ void k_dsa_setup(int n_inst, const InstDev* __restrict__ insts,
         } else if (Fp == 0) {
           const int d = F - 1;
           aC[e] = a[d][e];
-          aJ[e] = -0.5 * bm[d][e];
+          aJf[e] = -0.5 * bm[d][e];
+          aJ[e] = pc ? 0.0 : aJf[e];
         } else {
           const int d = F - 1, f = Fp - 1;
           aC[e] = 3.0 * t[d][e][f];
-          aJ[e] = -1.5 * c[d][e][f];
+          aJf[e] = -1.5 * c[d][e][f];
+          aJ[e] = pc ? 0.0 : aJf[e];
         }
+        if (F == 0) aJf[e] = aJ[e];
       }
       for (int k = 0; k < nl; ++k)
         for (int l = 0; l < nl; ++l) {
           const int row = F * nl + k, col = Fp * nl + l, q = row * nu + col;
-          double self = 0.0;
-          for (int e = 0; e < ne; ++e)
+          double self = 0.0, selff = 0.0;
+          for (int e = 0; e < ne; ++e) {
             self += aC[e] * emb(DCs[e], e, k, l) + aJ[e] * emb(DJs[e], e, k, l);
+            selff += aC[e] * emb(DCs[e], e, k, l) + aJf[e] * emb(DJs[e], e, k, l);
+          }
           S.blk[0][q] = self;
+          S.blkd[q] = selff;
           S.blk[1][q] = aC[0] * emb(DCm[0], 0, k, l) + aJ[0] * emb(DJm[0], 0, k, l);
           S.blk[2][q] = aC[0] * emb(DCp[0], 0, k, l) + aJ[0] * emb(DJp[0], 0, k, l);
           if (dim == 2) {
@@ -210,7 +233,7 @@ __global__ void k_dsa_blockinv(int n_inst, int max_regions, const InstDev* __res
   double A[DMAX][2 * DMAX];
   for (int i = 0; i < nu; ++i)
     for (int j = 0; j < nu; ++j) {
-      A[i][j] = S.blk[0][i * nu + j] + ts * S.St[i * nu + j] + ss * S.Ss[i * nu + j];
+      A[i][j] = S.blkd[i * nu + j] + ts * S.St[i * nu + j] + ss * S.Ss[i * nu + j];
       A[i][nu + j] = (i == j) ? 1.0 : 0.0;
     }
   for (int col = 0; col < nu; ++col) {
@@ -390,7 +413,7 @@ __global__ void k_mg_inv_cells(const LvlInst* __restrict__ li, const DsaStencil*
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
     const double t = st[L.cell_off + c], u = ss[L.cell_off + c];
     double M[NU * NU];
-    for (int q = 0; q < NU * NU; ++q) M[q] = S.blk[0][q] + t * S.St[q] + u * S.Ss[q];
+    for (int q = 0; q < NU * NU; ++q) M[q] = S.blkd[q] + t * S.St[q] + u * S.Ss[q];
     invert_block<NU>(M, inv + (L.cell_off + c) * NU * NU);
   }
 }
@@ -508,6 +531,7 @@ __device__ __forceinline__ void axis_cj(const real Xc[4], const real Xhi[4], con
 template <typename real>
 struct SymCoef {
   real ax, ay, bex, bey, cxx, cxy, cyx, cyy, ihx, ihy;
+  real kxx, kxy, kyx, kyy;  // the block solves' jump coefficients (FC)
 };
 
 template <typename real>
@@ -516,6 +540,7 @@ __device__ __forceinline__ SymCoef<real> sym_coef(const DsaStencil& G) {
   c.ax = (real)G.ax; c.ay = (real)G.ay; c.bex = (real)G.bex; c.bey = (real)G.bey;
   c.cxx = (real)G.cxx; c.cxy = (real)G.cxy; c.cyx = (real)G.cyx; c.cyy = (real)G.cyy;
   c.ihx = (real)(1.0 / G.hx); c.ihy = (real)(1.0 / G.hy);
+  c.kxx = (real)G.bcxx; c.kxy = (real)G.bcxy; c.kyx = (real)G.bcyx; c.kyy = (real)G.bcyy;
   return c;
 }
 
@@ -597,7 +622,8 @@ __device__ __forceinline__ void sym_cell_apply(const SymCoef<real>& S, real st, 
 __device__ __forceinline__ float blk_inv(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double blk_inv(double v) { return 1.0 / v; }
 
-// Exact solve with the cell's diagonal block for a reflection-symmetric rule.
+// Exact solve with the cell's diagonal block for a reflection-symmetric rule
+// (the FC block: jump coefficients kxx..kyy).
 // The own-cell parts are: phi row diagonal Dphi, J rows diagonal dJx, dJy, and
 // the skew couplings a_xx S_x, a_yy S_y (S = sqrt3/h [[0,1],[-1,0]] along its
 // axis).  Eliminating J_x, J_y leaves a diagonal Schur complement because
@@ -615,8 +641,8 @@ __device__ __forceinline__ void sym_block_solve(const SymCoef<real>& S, real st,
     const int p = l & 1, q = l >> 1;
     const real gx = (real)(p ? 6 : 2) * S.ihx, gy = (real)(q ? 6 : 2) * S.ihy;
     dphi[l] = (st - ss) + S.bex * gx + S.bey * gy;
-    ijx[l] = blk_inv((real)3 * S.ax * st + (real)1.5 * (S.cxx * gx + S.cxy * gy));  // 1 / dJx
-    ijy[l] = blk_inv((real)3 * S.ay * st + (real)1.5 * (S.cyx * gx + S.cyy * gy));
+    ijx[l] = blk_inv((real)3 * S.ax * st + (real)1.5 * (S.kxx * gx + S.kxy * gy));  // 1 / dJx
+    ijy[l] = blk_inv((real)3 * S.ay * st + (real)1.5 * (S.kyx * gx + S.kyy * gy));
     tx[l] = r[4 + l] * ijx[l];  // dJx^{-1} r_Jx
     ty[l] = r[8 + l] * ijy[l];
   }
@@ -1151,7 +1177,8 @@ struct DsaSolver {
   // set by apply for that V-cycle too: level 0's first two half sweeps form
   // the right-hand side from v (the first stores its colour-0 part)
   const double* rhs_from_v = nullptr;
-  int init(rte_batch* batch, int restart_);
+  int pc = 0;  // partially consistent variant
+  int init(rte_batch* batch, int restart_, int pc_);
   void release();
   int prepare(const double* sigma_t, const double* sigma_s, const int32_t* active, hipStream_t s);
   int stencil(int l, int mode, int color, const double* bv, double* x, double* y, const int32_t* act,
@@ -1168,7 +1195,8 @@ struct DsaSolver {
   }
 };
 
-int DsaSolver::init(rte_batch* batch, int restart_) {
+int DsaSolver::init(rte_batch* batch, int restart_, int pc_) {
+  pc = pc_;
   b = batch;
   restart = restart_;
   nu = b->dim == 2 ? 12 : 4;
@@ -1233,7 +1261,7 @@ int DsaSolver::init(rte_batch* batch, int restart_) {
     if (hipMalloc(&d_tmp, sizeof(InstDev) * n) != hipSuccess) return RTE_ENOMEM;
     RTE_HIP(hipMemcpy(d_tmp, tmp.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_dsa_setup, dim3((n + 63) / 64), dim3(64), 0, 0, n, d_tmp, b->d_ox, b->d_oy,
-                       b->d_w, L.d_st);
+                       b->d_w, L.d_st, pc);
     RTE_HIP(hipGetLastError());
     RTE_HIP(hipDeviceSynchronize());
     (void)hipFree(d_tmp);
@@ -1577,24 +1605,24 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
   return RTE_OK;
 }
 
-// registry: one DSA solver per (batch, restart) kept alive with the batch
+// registry: one DSA solver per (batch, restart, variant) kept alive with the batch
 struct DsaCache {
   rte_batch* b;
-  int restart;
+  int restart, pc;
   DsaSolver* s;
 };
 static std::vector<DsaCache> g_dsa;
 
-DsaSolver* dsa_for(rte_batch* b, int restart) {
+DsaSolver* dsa_for(rte_batch* b, int restart, int pc) {
   for (auto& c : g_dsa)
-    if (c.b == b && c.restart == restart) return c.s;
+    if (c.b == b && c.restart == restart && c.pc == pc) return c.s;
   auto* s = new DsaSolver();
-  if (s->init(b, restart) != RTE_OK) {
+  if (s->init(b, restart, pc) != RTE_OK) {
     s->release();
     delete s;
     return nullptr;
   }
-  g_dsa.push_back({b, restart, s});
+  g_dsa.push_back({b, restart, pc, s});
   return s;
 }
 
@@ -1612,8 +1640,8 @@ void dsa_forget(rte_batch* b) {
 
 int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v, double* z,
               double inner_tol, int inner_max, int restart, const int32_t* active, int32_t* iters,
-              hipStream_t s, bool prepare) {
-  DsaSolver* d = dsa_for(b, restart);
+              hipStream_t s, bool prepare, int variant) {
+  DsaSolver* d = dsa_for(b, restart, variant == RTE_DSA_PC ? 1 : 0);
   if (!d) return RTE_ENOMEM;
   return d->apply(sigma_t, sigma_s, v, z, inner_tol, inner_max, active, iters, prepare, s);
 }
@@ -1622,11 +1650,12 @@ int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const 
 
 extern "C" int rte_dsa_apply(const rte_batch* cb, const double* sigma_t, const double* sigma_s,
                              const double* v, double* z, double inner_tol, int inner_max, int restart,
-                             int32_t* stats_iters, void* stream) {
+                             int variant, int32_t* stats_iters, void* stream) {
   auto* b = const_cast<rte_batch*>(cb);
   if (!b || !sigma_t || !sigma_s || !v || !z || inner_max < 1 || restart < 0 || restart > 500 ||
-      !(inner_tol >= 0.0))
+      !(inner_tol >= 0.0) || (variant != RTE_DSA_FC && variant != RTE_DSA_PC) ||
+      (variant == RTE_DSA_PC && restart == 0))
     return RTE_EINVAL;
   return rte::dsa_apply(b, sigma_t, sigma_s, v, z, inner_tol, inner_max, restart, nullptr,
-                        stats_iters, reinterpret_cast<hipStream_t>(stream), true);
+                        stats_iters, reinterpret_cast<hipStream_t>(stream), true, variant);
 }

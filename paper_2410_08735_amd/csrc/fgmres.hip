@@ -154,7 +154,7 @@ int Fgmres::precondition(int jj, int cycle, const double* v, double* z, const So
       const bool prep = !dsa_ready;
       dsa_ready = true;
       return dsa_apply(b, c.sigma_t, c.sigma_s, v, z, o.dsa_inner_tol, o.dsa_inner_max,
-                       o.dsa_restart, K.active, nullptr, s, prep);
+                       o.dsa_restart, K.active, nullptr, s, prep, o.dsa_variant);
     }
     case RTE_PC_ROMSAD: {
       int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, K.active, s);
@@ -369,7 +369,8 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
   if (o.m < 1 || o.m > 500 || o.max_cycles < 1 || !(o.rtol > 0.0) ||
       (o.sweep_dtype != RTE_F32 && o.sweep_dtype != RTE_F64) || o.precond < RTE_PC_NONE ||
       o.precond > RTE_PC_MLP || o.window < 0 || o.dsa_inner_max < 1 || o.dsa_restart < 0 ||
-      o.dsa_restart > 500)
+      o.dsa_restart > 500 || (o.dsa_variant != RTE_DSA_FC && o.dsa_variant != RTE_DSA_PC) ||
+      (o.dsa_variant == RTE_DSA_PC && o.dsa_restart == 0))
     return RTE_EINVAL;
   if ((o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && !rom) return RTE_EINVAL;
   if (rom && !rte::rom_matches(rom, b)) return RTE_EINVAL;

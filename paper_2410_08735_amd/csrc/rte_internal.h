@@ -141,7 +141,7 @@ int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s);
 // multigrid data (cross sections per level, block inverses).
 int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v, double* z,
               double inner_tol, int inner_max, int restart, const int32_t* active, int32_t* iters,
-              hipStream_t s, bool prepare = true);
+              hipStream_t s, bool prepare = true, int variant = RTE_DSA_FC);
 void dsa_forget(rte_batch* b);
 void fgmres_forget(rte_batch* b);
 void rom_scratch_forget(const rte_batch* b);

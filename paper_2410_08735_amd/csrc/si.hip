@@ -77,7 +77,9 @@ extern "C" int si_solve(const rte_batch* cb, const double* sigma_t, const double
   const rte_solve_opts& o = *opts;
   if (o.max_cycles < 1 || !(o.rtol > 0.0) || (o.sweep_dtype != RTE_F32 && o.sweep_dtype != RTE_F64) ||
       (o.precond != RTE_PC_NONE && o.precond != RTE_PC_DSA && o.precond != RTE_PC_ROMSAD) || o.window < 0 ||
-      o.dsa_inner_max < 1 || o.dsa_restart < 0 || o.dsa_restart > 500)
+      o.dsa_inner_max < 1 || o.dsa_restart < 0 || o.dsa_restart > 500 ||
+      (o.dsa_variant != RTE_DSA_FC && o.dsa_variant != RTE_DSA_PC) ||
+      (o.dsa_variant == RTE_DSA_PC && o.dsa_restart == 0))
     return RTE_EINVAL;
   if (o.precond == RTE_PC_ROMSAD && (!rom || !rom_matches(rom, b))) return RTE_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -139,7 +141,7 @@ extern "C" int si_solve(const rte_batch* cb, const double* sigma_t, const double
       RTE_TRY(kcopy(w->sp, w->r, w->z, w->act, s));
     } else if (kind == RTE_PC_DSA) {
       RTE_TRY(dsa_apply(b, sigma_t, sigma_s, w->r, w->z, o.dsa_inner_tol, o.dsa_inner_max, o.dsa_restart, w->act,
-                        nullptr, s, !dsa_prepared));
+                        nullptr, s, !dsa_prepared, o.dsa_variant));
       dsa_prepared = true;
     } else {
       const int st = romsad_apply_internal(rom, b, sigma_t, sigma_s, w->r, w->z, w->act, s);

@@ -88,22 +88,92 @@ def test_dsa_apply_parity_1d():
         assert rel(B.unpack(z)[k], ref) <= 1e-11
 
 
+@pytest.mark.gpu
+def test_pc_dsa_apply_parity():
+    """Partially consistent DSA (App. A: no D_J terms in the first-moment rows)
+    against the oracle's PC system, on general and reflection-symmetric rules
+    and in slab geometry; the PC correction differs from the FC one."""
+    import paper_2410_08735_amd as rt
+    for specs in ([tiny_2d(seed=1, nx=6, ny=5, quad=("cl", 8, 4, True), n_regions=3),
+                   tiny_2d(seed=2, nx=4, ny=7, quad=("cl", 3, 2, False), n_regions=2),
+                   tiny_2d(seed=6, nx=12, ny=12, quad=("cl", 16, 4, True), n_regions=2)],
+                  # reflection-symmetric rules only: the structured multigrid kernels
+                  [tiny_2d(seed=5, nx=16, ny=8, quad=("cl", 8, 4, True), n_regions=3),
+                   tiny_2d(seed=6, nx=12, ny=12, quad=("cl", 16, 4, True), n_regions=2)],
+                  [tiny_1d(seed=1, nx=12, n_ord=8), tiny_1d(seed=2, nx=7, n_ord=4)]):
+        B = rt.Batch(specs)
+        st, ss = B.sigma()
+        rng = np.random.default_rng(8)
+        v = [rng.standard_normal(n) for n in B.ndofs]
+        z, iters = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=1e-14, inner_max=3000, restart=60,
+                                variant="pc")
+        zf, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=1e-14, inner_max=3000, restart=60)
+        for k, spec in enumerate(specs):
+            P = tr.Problem(spec)
+            ref = odsa.DSA(P, "pc").apply(v[k])
+            err = rel(B.unpack(z)[k], ref)
+            print(f"PC-DSA {spec['dim']}D instance {k}: rel err {err:.2e}, iterations {iters[k]}")
+            assert err <= 1e-11, (k, err, iters)
+            assert rel(B.unpack(zf)[k], odsa.DSA(P).apply(v[k])) <= 1e-11
+            assert rel(B.unpack(z)[k], B.unpack(zf)[k]) > 1e-6
+
+
+@pytest.mark.gpu
+def test_fc_dsa_needs_fewer_iterations_than_pc_dsa():
+    """FC-DSA preconditioning takes fewer GMRES iterations than PC-DSA (the
+    paper's remark opening section 5 and its variable-scattering table); on
+    the section 5.2 pin-cell problem the ordering holds with exact DSA solves."""
+    import paper_2410_08735_amd as rt
+    from synth import pincell_problem, pincell_sets
+    _, te_mu = pincell_sets()
+    B = rt.Batch([pincell_problem(m) for m in te_mu])
+    st, ss = B.sigma()
+    common = dict(m=60, max_cycles=10, sweep_dtype="f64", rtol=1e-11, dsa_inner_max=1000, dsa_restart=60,
+                  dsa_inner_tol=1e-12)
+    it = {}
+    for var in ("fc", "pc"):
+        print(f"pin-cell GMRES-{var.upper()}-DSA", flush=True)
+        _, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None,
+                                        rt.SolveOptions(precond="dsa", dsa_variant=var, **common))
+        assert ret == 0 and all(s["true_relres"] <= common["rtol"] for s in stats)
+        it[var] = float(np.mean([s["iterations"] for s in stats]))
+    print(f"pin-cell, exact DSA: mean iterations FC {it['fc']:.1f}, PC {it['pc']:.1f}")
+    assert it["fc"] < it["pc"], it
+
+
+@pytest.mark.gpu
+def test_pc_dsa_rejects_unknown_variant_and_stationary_cycles():
+    import paper_2410_08735_amd as rt
+    B = rt.Batch([tiny_2d(seed=1, nx=4, ny=4, quad=("cl", 8, 4, True))])
+    st, ss = B.sigma()
+    with pytest.raises(rt.RteError):
+        rt.check(rt.L.lib().rte_dsa_apply(B.h, rt._ptr(st), rt._ptr(ss), rt._ptr(B.zeros()),
+                                          rt._ptr(B.zeros()), 1e-10, 10, 10, 2, None,
+                                          rt._stream()), "rte_dsa_apply")
+    # PC solves need the Krylov method: no stationary V-cycles
+    with pytest.raises(rt.RteError):
+        rt.dsa_apply(B, st, ss, B.zeros(), inner_tol=0.0, inner_max=1, restart=0, variant="pc")
+    with pytest.raises(rt.RteError):
+        rt.fgmres_solve(B, st, ss, B.source(), None,
+                        rt.SolveOptions(precond="dsa", dsa_restart=0, dsa_inner_max=1, dsa_variant="pc"))
+
+
 # ------------------------------------------------------------------ FGMRES
-def _oracle_solve(spec, precond="dsa", rtol=1e-13, m=60, U=None, window=2):
+def _oracle_solve(spec, precond="dsa", rtol=1e-13, m=60, U=None, window=2, dsa_variant="fc"):
     P = tr.Problem(spec)
     b = tr.b_tilde(P)
     if precond == "none":
         pc = lambda j, v: v
-    elif precond == "dsa":
-        D = odsa.DSA(P)
+    elif precond in ("dsa", "pc-dsa"):
+        D = odsa.DSA(P, "pc" if precond == "pc-dsa" else "fc")
         pc = lambda j, v: D.apply(v)
     else:
-        pc = orom.Romsad(P, U, odsa.DSA(P), window)
+        pc = orom.Romsad(P, U, odsa.DSA(P, dsa_variant), window)
     return ofg.fgmres(lambda x: tr.A_tilde_apply(P, x), b, pc, m=m, rtol=rtol)
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precond", ["none", "dsa"])
+@pytest.mark.parametrize("precond", ["none", "dsa", "pc-dsa"])
 def test_fgmres_fp64_parity(precond):
     import paper_2410_08735_amd as rt
     specs = [tiny_2d(seed=1, nx=7, ny=6, quad=("cl", 8, 4, True), n_regions=3, inflow=0.2),
@@ -111,8 +181,9 @@ def test_fgmres_fp64_parity(precond):
              tiny_2d(seed=3, nx=4, ny=6, quad=("cl", 3, 2, False), n_regions=2)]
     B = rt.Batch(specs)
     st, ss = B.sigma()
-    opts = rt.SolveOptions(precond=precond, m=60, max_cycles=5, sweep_dtype="f64", rtol=1e-13,
-                           dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    opts = rt.SolveOptions(precond="dsa" if precond == "pc-dsa" else precond, m=60, max_cycles=5,
+                           sweep_dtype="f64", rtol=1e-13, dsa_inner_max=2000, dsa_restart=60,
+                           dsa_inner_tol=1e-14, dsa_variant="pc" if precond == "pc-dsa" else "fc")
     phi, stats, _ = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), opts)
     for k, spec in enumerate(specs):
         ref = _oracle_solve(spec, precond)
@@ -215,7 +286,10 @@ def test_romsad_apply_parity_many_instances_long_vectors():
 
 
 @pytest.mark.gpu
-def test_fgmres_romsad_parity(oracle_rom):
+@pytest.mark.parametrize("dsa_variant", ["fc", "pc"])
+def test_fgmres_romsad_parity(oracle_rom, dsa_variant):
+    """FGMRES-ROMSAD with FC-DSA, and with PC-DSA after the window (the
+    FGMRES-PC-ROMSAD of the variable-scattering comparison)."""
     import torch
 
     import paper_2410_08735_amd as rt
@@ -226,11 +300,12 @@ def test_fgmres_romsad_parity(oracle_rom):
     st, ss = B.sigma()
     rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
     opts = rt.SolveOptions(precond="romsad", m=40, max_cycles=5, sweep_dtype="f64", rtol=1e-12,
-                           window=2, dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+                           window=2, dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14,
+                           dsa_variant=dsa_variant)
     phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts, rom=rom)
     assert ret == 0
     for k, spec in enumerate(B.problems):
-        ref = _oracle_solve(spec, "romsad", rtol=1e-12, U=U)
+        ref = _oracle_solve(spec, "romsad", rtol=1e-12, U=U, dsa_variant=dsa_variant)
         assert rel(B.unpack(phi)[k], ref.x) <= 1e-10
         assert abs(stats[k]["iterations"] - ref.iterations) <= 1
         assert stats[k]["pc_rom"] >= 1
