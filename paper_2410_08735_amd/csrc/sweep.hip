@@ -475,10 +475,13 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         store_partial<real, G>(c, g, mx, my, P, cell);
       }
       // source of this row's cell on the next diagonal (issued after the last
-      // use of the current one, so it can land in the same registers)
-      const int c = phys(i + 1, r);
-      rn[kk] = reg[c];
-      qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)c);
+      // use of the current one, so it can land in the same registers); none
+      // while the row's next step has no cell, so whole waves skip it
+      if (r < ny && i + 1 >= 0 && i + 1 < nx) {
+        const int c = phys(i + 1, r);
+        rn[kk] = reg[c];
+        qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)c);
+      }
     }
     lds_barrier();
   }
