@@ -23,11 +23,12 @@ if ROOT not in sys.path:
 METRIC = "FGMRES solves/s to rel-res 1e-8 (MLP vs ROMSAD vs plain); sweep GDoF/s"
 # FP32 sweep arithmetic per cell and ordinate as the kernel's algorithm needs
 # it, counting an FMA as two operations: 8 FMA for the right-hand side (source
-# plus inflow traces), 16 for the local 4x4 solve with the per-(region,
-# ordinate) coefficients, 4 for the outgoing traces, 4 for the weighted sum.
-# The per-cell work shared by all ordinates (Sigma_s scaling, the cross-lane
-# quadrature sum) is below one flop per cell-ordinate and not counted.
-SWEEP_FLOPS_PER_CELL_ORD = 64.0
+# plus inflow traces), 10 FMA and 6 multiplies for the local 4x4 solve with the
+# per-(region, ordinate) coefficients, 4 FMA for the outgoing traces, 4 FMA for
+# the weighted sum: 16 + 26 + 8 + 8 = 58.  The per-cell work shared by all
+# ordinates (Sigma_s scaling, the cross-lane quadrature sum) is below one flop
+# per cell-ordinate and not counted.
+SWEEP_FLOPS_PER_CELL_ORD = 58.0
 # FP32 ALU ceiling from the chip's units and clock for the instructions the
 # kernels use: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.  (The published
 # 157.3 TFLOP/s counts packed two-wide FP32 FMAs, which this library does not

@@ -66,6 +66,11 @@ __device__ __forceinline__ real group_sum(real c) {
   return c;
 }
 
+// a * b + c as one fused multiply-add (written out so that a product shared by
+// two sums is not formed once and added twice).
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // 1/x: the hardware reciprocal (1 ulp) in FP32, a correctly rounded division in FP64.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
@@ -206,10 +211,10 @@ __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g,
     rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
     real x[4];
     local_solve<real>(sig, a, b, rhs, x);
-    xtr[xo] = x[0] + r3 * x[1];
-    xtr[xo + 1] = x[2] + r3 * x[3];
-    ytr[yo] = x[0] + r3 * x[2];
-    ytr[yo + 1] = x[1] + r3 * x[3];
+    xtr[xo] = fmadd(r3, x[1], x[0]);
+    xtr[xo + 1] = fmadd(r3, x[3], x[2]);
+    ytr[yo] = fmadd(r3, x[2], x[0]);
+    ytr[yo + 1] = fmadd(r3, x[3], x[1]);
 #pragma unroll
     for (int d = 0; d < 4; ++d) c[d] += L.wt[o] * x[d];
     if (L.psi[o]) {
@@ -251,10 +256,10 @@ __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, i
     const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
     real x[4];
     solve_apply<real>(cf, r3 * b, rhs, x);
-    xt[o][0] = x[0] + r3 * x[1];
-    xt[o][1] = x[2] + r3 * x[3];
-    ytr[yo] = x[0] + r3 * x[2];
-    ytr[yo + 1] = x[1] + r3 * x[3];
+    xt[o][0] = fmadd(r3, x[1], x[0]);
+    xt[o][1] = fmadd(r3, x[3], x[2]);
+    ytr[yo] = fmadd(r3, x[2], x[0]);
+    ytr[yo + 1] = fmadd(r3, x[3], x[1]);
 #pragma unroll
     for (int d = 0; d < 4; ++d) c[d] += L.wt[o] * x[d];
     if (L.psi[o]) {

@@ -480,9 +480,10 @@ def test_pincell_problem_reproduces_the_papers_sweep_counts():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precond", ["none", "dsa", "romsad"])
+@pytest.mark.parametrize("precond", ["none", "dsa", "pc-dsa", "romsad"])
 def test_si_solve_parity(oracle_rom, precond):
-    """Source iteration with synthetic acceleration against the oracle's SI."""
+    """Source iteration with synthetic acceleration against the oracle's SI
+    (FC-DSA, PC-DSA, ROMSAD)."""
     import torch
 
     from oracle import si as osi
@@ -493,16 +494,17 @@ def test_si_solve_parity(oracle_rom, precond):
     B = rt.Batch(test)
     st, ss = B.sigma()
     rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda()) if precond == "romsad" else None
-    opts = rt.SolveOptions(precond=precond, max_cycles=400, sweep_dtype="f64", rtol=1e-11, window=1,
-                           dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    opts = rt.SolveOptions(precond="dsa" if precond == "pc-dsa" else precond, max_cycles=400,
+                           sweep_dtype="f64", rtol=1e-11, window=1, dsa_inner_max=2000, dsa_restart=60,
+                           dsa_inner_tol=1e-14, dsa_variant="pc" if precond == "pc-dsa" else "fc")
     phi, stats, ret = rt.si_solve(B, st, ss, B.source(), None, opts, rom=rom)
     assert ret == 0
     for k, spec in enumerate(test):
         P = tr.Problem(spec)
-        D = odsa.DSA(P)
+        D = odsa.DSA(P, "pc" if precond == "pc-dsa" else "fc")
         if precond == "none":
             pc = lambda l, r: r
-        elif precond == "dsa":
+        elif precond in ("dsa", "pc-dsa"):
             pc = lambda l, r: D.apply(r)
         else:
             R = orom.Romsad(P, U, D, 1)

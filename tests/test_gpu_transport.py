@@ -48,6 +48,8 @@ def test_invalid_batch_rejected():
     bad = dict(tiny_2d(nx=3, ny=3), nx=0)
     with pytest.raises(rt.RteError):
         rt.Batch([bad])
+    with pytest.raises(rt.RteError):  # an empty batch
+        rt.Batch([])
 
 
 # ------------------------------------------------------------ GPU parity
