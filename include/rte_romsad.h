@@ -181,7 +181,10 @@ int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma
  *                correction as fallback and DSA after the window.
  * Stopping: Givens estimate <= rtol * ||b~|| ends a cycle; the FP64 true
  * residual ||b~ - A~ phi|| / ||b~|| <= rtol ends the solve.  sweep_dtype sets
- * the arithmetic of the inner A~ applies; b~ and true residuals are FP64.
+ * the arithmetic of the inner A~ applies.  True residuals are FP64, formed
+ * as T (G~ + Sigma_s phi) - phi with RTE_F32 (whose b~, which starts the first
+ * cycle and scales the stopping test, comes from an FP32 sweep) and as
+ * b~ - A~ phi with an FP64 b~ with RTE_F64.
  * phi (device, packed) receives the solution.  stats (host [n_inst]).        */
 typedef struct {
   int32_t precond;       /* RTE_PC_*                                         */

@@ -114,6 +114,25 @@ void Fgmres::rec_release() {
   rec_w = 0;
 }
 
+// q = G + Sigma_s phi on every DoF of the active instances (Sigma_s of the
+// DoF's cell region): the source whose sweep gives T (G + Sigma_s phi), so that
+// the true residual b~ - A~ phi = T (G + Sigma_s phi) - phi takes one sweep.
+__global__ void k_source_plus(const InstDev* __restrict__ insts, const int32_t* __restrict__ region,
+                              const double* __restrict__ sigma_s, int max_regions,
+                              const double* __restrict__ G, const double* __restrict__ phi,
+                              double* __restrict__ q, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const InstDev I = insts[b];
+  const int64_t nd = (int64_t)I.nx * I.ny * I.nloc;
+  const double* __restrict__ ss = sigma_s + (int64_t)b * max_regions;
+  const int32_t* __restrict__ reg = region + I.region_off;
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = I.dof_off + d;
+    q[o] = G[o] + ss[reg[d / I.nloc]] * phi[o];
+  }
+}
+
 __global__ void k_tolabs(int n, const double* __restrict__ bnorm, double rtol, double* __restrict__ tol) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < n) tol[b] = rtol * bnorm[b];
@@ -188,12 +207,18 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     RTE_HIP(hipStreamSynchronize(s));
   }
   RTE_HIP(hipMemcpyAsync(cyc, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-  // b~ = T G~ (FP64) and ||b~||
-  RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, c.G, c.inflow, nullptr, s, cyc,
-                       batch_cell_ordinates(b, live.data())));
-  RTE_TRY(reduce_partials(b, 0, 1.0, nullptr, 0.0, btil, s, cyc));
+  // b~ = T G~ and ||b~||.  With FP32 sweeps b~ only starts the first cycle and
+  // scales the stopping test, so an FP32 sweep suffices: every true residual
+  // is formed in FP64 from its definition, T (G~ + Sigma_s phi) - phi, and the
+  // restarts refine away b~'s rounding.  With FP64 sweeps b~ is FP64 and the
+  // residual b~ - (phi - T Sigma_s phi).
+  const bool f32_btil = o.sweep_dtype == RTE_F32;
+  const int btil_prec = f32_btil ? 1 : 0;
+  RTE_TRY(sweep_launch(b, btil_prec, c.sigma_t, nullptr, nullptr, c.G, c.inflow, nullptr, s, cyc,
+                       f32_btil ? -2.0 : batch_cell_ordinates(b, live.data())));
+  RTE_TRY(reduce_partials(b, btil_prec, 1.0, nullptr, 0.0, btil, s, cyc));
   for (int q = 0; q < n; ++q)
-    if (live[q]) stats[q].sweeps_f64 += 1;
+    if (live[q]) (f32_btil ? stats[q].sweeps_f32 : stats[q].sweeps_f64) += 1;
   RTE_TRY(knorm(K.sp, btil, K.partA, bnorm, 1, cyc, s));
   hipLaunchKernelGGL(k_tolabs, dim3((n + 63) / 64), dim3(64), 0, s, n, bnorm, o.rtol, tolabs);
   RTE_HIP(hipMemsetAsync(phi, 0, sizeof(double) * b->total_dof, s));
@@ -298,9 +323,20 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     }
     // phi += Z y ; r = b~ - A~ phi in FP64
     RTE_TRY(kylov_solve_update(K, K.Z, phi, s));
-    RTE_TRY(sweep_launch(b, 0, c.sigma_t, c.sigma_s, phi, nullptr, nullptr, nullptr, s, cyc,
-                         batch_cell_ordinates(b, cm.data())));
-    RTE_TRY(reduce_partials(b, 0, 1.0, btil, 1.0, r, s, cyc, phi, -1.0));
+    if (f32_btil) {
+      int max_nd = 0;
+      for (const auto& I : b->inst) max_nd = std::max(max_nd, I.nx * I.ny * I.nloc);
+      hipLaunchKernelGGL(k_source_plus, dim3(std::min((max_nd + 255) / 256, 1024), n), dim3(256), 0, s,
+                         b->d_inst, b->d_region, c.sigma_s, b->max_regions, c.G, phi, r, cyc);
+      RTE_HIP(hipGetLastError());
+      RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, r, c.inflow, nullptr, s, cyc,
+                           batch_cell_ordinates(b, cm.data())));
+      RTE_TRY(reduce_partials(b, 0, 1.0, phi, -1.0, r, s, cyc));
+    } else {
+      RTE_TRY(sweep_launch(b, 0, c.sigma_t, c.sigma_s, phi, nullptr, nullptr, nullptr, s, cyc,
+                           batch_cell_ordinates(b, cm.data())));
+      RTE_TRY(reduce_partials(b, 0, 1.0, btil, 1.0, r, s, cyc, phi, -1.0));
+    }
     RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
     RTE_HIP(hipMemcpyAsync(rn.data(), rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipMemcpyAsync(sc.data(), K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
