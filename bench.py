@@ -42,7 +42,7 @@ PEAK_HBM = 8.0e12             # MI355X published HBM3E bandwidth, B/s
 # (scaled by a 512 MiB copy; profiles/sweep2d_f32_cfg3_96sq_b256_hbm_traffic.md),
 # keyed by (variant, G, ordinates per lane, threads); valid for the kernel
 # version those passes measured.
-SWEEP_F32_TRAFFIC_BYTES = {(1, 8, 4, 512): 2.992e8}
+SWEEP_F32_TRAFFIC_BYTES = {(1, 8, 4, 512): 2.993e8}
 # Algorithmic HBM bytes per cell and instance of one sweep: read the 4 source
 # moments (FP64, 32 B), write the 4 scalar-flux moments (FP64, 32 B), and the
 # cell's cross-section data (8 B).  Angular fluxes never leave the chip.
