@@ -969,34 +969,54 @@ __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const 
   // even rows: the threads take only this colour's cells (nc / 2 of them)
   const bool compact = (nx & 1) == 0;
   const int nwork = compact ? nc / 2 : nc;
-  for (int t = threadIdx.x; t < nwork; t += blockDim.x) {
-    int i, k;
-    if (compact) {
-      rb_cell(t, nx, color, i, k);
-    } else {
-      i = t % nx;
-      k = t / nx;
-      if (((i + k) & 1) != color) continue;
+  const int stride = blockDim.x;
+  // two cells per thread and pass, both read before either is written (cells
+  // of one colour do not read each other), so that their loads overlap
+  for (int t0 = threadIdx.x; t0 < nwork; t0 += 2 * stride) {
+    bool on[2];
+    int cellv[2];
+    real d[2][12];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int t = t0 + j * stride;
+      int i = 0, k = 0;
+      on[j] = t < nwork;
+      if (on[j]) {
+        if (compact) {
+          rb_cell(t, nx, color, i, k);
+        } else {
+          i = t % nx;
+          k = t / nx;
+          on[j] = ((i + k) & 1) == color;
+        }
+      }
+      cellv[j] = k * nx + i;
+      if (!on[j]) continue;
+      const int cell = cellv[j];
+      const CellPos P = cell_pos(i, k, nx, ny);
+      const real tt = st[cell], uu = ss[cell];
+      real r[12];
+      if (mode == 1) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell];
+      } else {
+        real yy[12];
+        if (mode == 2)
+          sym_cell_apply<real, false>(S, tt, uu, x, P, yy);
+        else
+          sym_cell_apply(S, tt, uu, x, P, yy);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell] - yy[q];
+      }
+      sym_block_solve(S, tt, uu, r, d[j]);
     }
-    const int cell = k * nx + i;
-    const CellPos P = cell_pos(i, k, nx, ny);
-    const real tt = st[cell], uu = ss[cell];
-    real r[12], d[12];
-    if (mode == 1) {
 #pragma unroll
-      for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell];
-    } else {
-      real yy[12];
-      if (mode == 2)
-        sym_cell_apply<real, false>(S, tt, uu, x, P, yy);
-      else
-        sym_cell_apply(S, tt, uu, x, P, yy);
+    for (int j = 0; j < 2; ++j) {
+      if (!on[j]) continue;
+      const int cell = cellv[j];
 #pragma unroll
-      for (int q = 0; q < 12; ++q) r[q] = bv[q * nc + cell] - yy[q];
+      for (int q = 0; q < 12; ++q) x[q * nc + cell] = mode == 0 ? x[q * nc + cell] + d[j][q] : d[j][q];
     }
-    sym_block_solve(S, tt, uu, r, d);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) x[q * nc + cell] = mode == 0 ? x[q * nc + cell] + d[q] : d[q];
   }
   __syncthreads();
 }
@@ -1010,35 +1030,53 @@ __device__ __forceinline__ void tail_sweep(const SymCoef<real>& S, const LvlInst
   tail_half_sweep(S, L, st, ss, bv, x, 1, from_zero ? 2 : 0);
 }
 
+// g0 = 1: the first level's x and b stay in global memory (x_first, b_first;
+// only its cross sections are staged in LDS) and it is smoothed nu0 times
+// before and after the coarse correction; this takes a level too large for
+// LDS into the launch (its global data is touched by this work group only,
+// and the work group's barriers order those accesses as they order LDS).
+// g0 = 0: b_first is copied into LDS and x_first receives the first level's x.
 template <typename real, int NT>
 __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restrict__ tl, int nlev, int nu_smooth,
                                                      int coarse_sweeps, const real* __restrict__ b_first,
                                                      real* __restrict__ x_first,
-                                                     const int32_t* __restrict__ active) {
+                                                     const int32_t* __restrict__ active, int g0, int nu0) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   extern __shared__ unsigned char smem_raw[];
   real* lds = reinterpret_cast<real*>(smem_raw);
-  // per level: x [12][nc], b [12][nc], sigma_t [nc], sigma_s [nc]
+  // per level: x [12][nc], b [12][nc], sigma_t [nc], sigma_s [nc] (g0 level:
+  // sigma_t, sigma_s only)
   __shared__ int off[MG_TAIL_MAX + 1];
   if (threadIdx.x == 0) {
     off[0] = 0;
     for (int l = 0; l < nlev; ++l) {
       const LvlInst Li = tl[l].li[b];
-      off[l + 1] = off[l] + 26 * Li.nx * Li.ny;
+      off[l + 1] = off[l] + ((g0 && l == 0) ? 2 : 26) * Li.nx * Li.ny;
     }
   }
   __syncthreads();
+  // the level's x, b and cross sections
+  auto lvl_x = [&](int l, const LvlInst& Li) -> real* {
+    return (g0 && l == 0) ? x_first + Li.cell_off * 12 : lds + off[l];
+  };
+  auto lvl_b = [&](int l, const LvlInst& Li) -> real* {
+    return (g0 && l == 0) ? const_cast<real*>(b_first) + Li.cell_off * 12
+                          : lds + off[l] + 12 * Li.nx * Li.ny;
+  };
+  auto lvl_sg = [&](int l, const LvlInst& Li) -> real* {
+    return lds + off[l] + ((g0 && l == 0) ? 0 : 24 * Li.nx * Li.ny);
+  };
   for (int l = 0; l < nlev; ++l) {  // cross sections of every level, once
     const LvlInst Li = tl[l].li[b];
     const int nc = Li.nx * Li.ny;
-    real* sg = lds + off[l] + 24 * nc;
+    real* sg = lvl_sg(l, Li);
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
       sg[c] = (real)tl[l].sigt[Li.cell_off + c];
       sg[nc + c] = (real)tl[l].sigs[Li.cell_off + c];
     }
   }
-  {  // load b of the first level
+  if (!g0) {  // load b of the first level
     const LvlInst L0 = tl[0].li[b];
     const int n0 = 12 * L0.nx * L0.ny;
     const real* src = b_first + L0.cell_off * 12;
@@ -1050,12 +1088,13 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
     const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
-    real* x = lds + off[l];
-    real* bv = x + 12 * nc;
-    const real* sgt = x + 24 * nc;
+    real* x = lvl_x(l, L);
+    real* bv = lvl_b(l, L);
+    const real* sgt = lvl_sg(l, L);
     const real* sgs = sgt + nc;
-    for (int k = 0; k < nu_smooth; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
-    real* bc = lds + off[l + 1] + 12 * ncc;
+    const int nu_l = (g0 && l == 0) ? nu0 : nu_smooth;
+    for (int k = 0; k < nu_l; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
+    real* bc = lvl_b(l + 1, C);
     for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
       const int I = c % C.nx, K = c / C.nx;
       real acc[12];
@@ -1087,9 +1126,9 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     const LvlInst L = tl[l].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
     const int nc = L.nx * L.ny;
-    real* x = lds + off[l];
-    real* bv = x + 12 * nc;
-    const real* sgt = x + 24 * nc;
+    real* x = lvl_x(l, L);
+    real* bv = lvl_b(l, L);
+    const real* sgt = lvl_sg(l, L);
     const real* sgs = sgt + nc;
     for (int k = 0; k < coarse_sweeps; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
   }
@@ -1098,11 +1137,22 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
     const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
-    real* x = lds + off[l];
-    real* bv = x + 12 * nc;
-    const real* xc = lds + off[l + 1];
+    real* x = lvl_x(l, L);
+    real* bv = lvl_b(l, L);
+    const real* xc = lvl_x(l + 1, C);
     for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
       const int I = c % C.nx, K = c / C.nx;
+      real xcv[12], xf[4][12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) xcv[q] = xc[q * ncc + c];
+      // the four children's values first (their loads overlap), then the sums
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const int f = (2 * K + (ch >> 1)) * L.nx + 2 * I + (ch & 1);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) xf[ch][q] = x[q * nc + f];
+      }
+#pragma unroll
       for (int ch = 0; ch < 4; ++ch) {
         const int di = ch & 1, dk = ch >> 1;
         const int f = (2 * K + dk) * L.nx + 2 * I + di;
@@ -1113,20 +1163,21 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
             real v = (real)0;
 #pragma unroll
             for (int L2 = 0; L2 < 4; ++L2)
-              v += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * xc[(4 * fld + L2) * ncc + c];
-            x[(4 * fld + m) * nc + f] += v;
+              v += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * xcv[4 * fld + L2];
+            x[(4 * fld + m) * nc + f] = xf[ch][4 * fld + m] + v;
           }
       }
     }
     __syncthreads();
-    const real* sgt = x + 24 * nc;
+    const real* sgt = lvl_sg(l, L);
     const real* sgs = sgt + nc;
-    for (int k = 0; k < nu_smooth; ++k) {
+    const int nu_l = (g0 && l == 0) ? nu0 : nu_smooth;
+    for (int k = 0; k < nu_l; ++k) {
       tail_half_sweep(S, L, sgt, sgs, bv, x, 1, 0);
       tail_half_sweep(S, L, sgt, sgs, bv, x, 0, 0);
     }
   }
-  {  // store x of the first level
+  if (!g0) {  // store x of the first level
     const LvlInst L0 = tl[0].li[b];
     const int n0 = 12 * L0.nx * L0.ny;
     real* dst = x_first + L0.cell_off * 12;
@@ -1164,6 +1215,7 @@ struct DsaSolver {
   // the LDS-resident tail of the hierarchy (structured kernels only)
   int tail_first = -1;
   size_t tail_lds = 0;
+  int tail_g0 = 0;  // the tail's first level keeps x and b in HBM (FP32 only)
   MgTailLevel* d_tail = nullptr;
   // smoothing sweeps before and after the coarse correction: nu_smooth on the
   // LDS-resident levels; on the levels streamed through HBM of the FP32
@@ -1284,12 +1336,24 @@ int DsaSolver::init(rte_batch* batch, int restart_, int pc_) {
     auto pick = [&](size_t cap) {
       tail_first = -1;
       tail_lds = 0;
+      tail_g0 = 0;
       size_t need = 0;
       for (int l = nlev - 1; l >= 1; --l) {
         need += (size_t)26 * lv[l].max_nx * lv[l].max_ny * es;
         if (need > cap || nlev - l > MG_TAIL_MAX) break;
         tail_first = l;
         tail_lds = need;
+      }
+      // FP32: one more level (from level 1 on) whose x and b stay in HBM and
+      // whose cross sections alone go to LDS
+      const int l = tail_first - 1;
+      if (f32 && tail_first >= 2 && nlev - l <= MG_TAIL_MAX) {
+        const size_t extra = (size_t)2 * lv[l].max_nx * lv[l].max_ny * es;
+        if (tail_lds + extra <= cap) {
+          tail_first = l;
+          tail_lds += extra;
+          tail_g0 = 1;
+        }
       }
     };
     pick(budget);
@@ -1339,6 +1403,7 @@ void DsaSolver::release() {
     (void)hipFree(p);
   d_tail = nullptr;
   tail_first = -1;
+  tail_g0 = 0;
   inv0 = X = T = rhs = tol = rn = nullptr;
   d_live = nullptr;
 }
@@ -1417,10 +1482,11 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     const int nt = (int)lv.size() - l;
     if (f32)
       hipLaunchKernelGGL((k_mg_tail_sym<float, MG_TAIL_THREADS_F32>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F32), tail_lds, s, d_tail, nt, nu_smooth,
-                         coarse_sweeps, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x), act);
+                         coarse_sweeps, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x), act,
+                         tail_g0, nu_hbm);
     else
       hipLaunchKernelGGL((k_mg_tail_sym<double, MG_TAIL_THREADS_F64>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F64), tail_lds, s, d_tail, nt, nu_smooth,
-                         coarse_sweeps, bv, x, act);
+                         coarse_sweeps, bv, x, act, 0, nu_smooth);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
