@@ -142,6 +142,7 @@ __global__ void k_dsa_setup(int n_inst, const InstDev* __restrict__ insts,
         for (int g = 0; g < 2; ++g) sy = sy && fabs(t[e][f][g]) < tz;
       }
     S.sym = sy ? 1 : 0;
+    if (sy) S.m[0] = S.m[1] = 0.0;  // a reflection-symmetric rule's first moments vanish exactly
     S.ax = a[0][0];
     S.ay = a[1][1];
     S.bex = be[0];
@@ -686,7 +687,9 @@ __device__ __forceinline__ void rb_cell(int t, int nx, int color, int& i, int& k
 //         colour 1 with its own x taken as zero (only colour 0 is read).
 // vsrc (modes 3 and 4 on level 0 only, nullable): b is formed from the DG
 // vector v as [ss v, m_x ss v, m_y ss v] instead of read, and mode 3 stores
-// its colour-0 part in bout for the restriction that follows.
+// its colour-0 part in bout for the restriction that follows (the scalar-flux
+// field only: with a reflection-symmetric rule m_x = m_y = 0, so the
+// current fields of b vanish).
 template <typename real>
 __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, const LvlInst* __restrict__ li,
                                  const DsaStencil* __restrict__ st_, const double* __restrict__ st,
@@ -732,7 +735,7 @@ __global__ void __launch_bounds__(256) k_mg_stencil_sym(int mode, int color, con
       if (mode == 3 && bout) {
         real* __restrict__ bo = bout + vo;
 #pragma unroll
-        for (int q = 0; q < 12; ++q) bo[(int64_t)q * nc + P.cell] = r[q];
+        for (int q = 0; q < 4; ++q) bo[(int64_t)q * nc + P.cell] = r[q];
       }
     } else if (mode >= 3) {
 #pragma unroll
@@ -900,12 +903,15 @@ __global__ void k_dsa_out_prolong(const InstDev* __restrict__ insts, const LvlIn
 // After a red-black half sweep of colour 1 the residual of every colour-1 cell
 // is zero (its neighbours all have colour 0 and did not change since), so with
 // zero_c1 only the two colour-0 children, (0, 0) and (1, 1), are formed.
+// bphi: only the scalar-flux field of b is stored (its current fields are
+// zero; the fine right-hand side formed from v with a reflection-symmetric
+// rule).
 template <typename real>
 __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
                                      const DsaStencil* __restrict__ st_f, const double* __restrict__ st,
                                      const double* __restrict__ ss, const real* __restrict__ bvec,
                                      const real* __restrict__ x, real* __restrict__ coarse_b, int zero_c1,
-                                     const int32_t* __restrict__ active) {
+                                     const int32_t* __restrict__ active, int bphi = 0) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const LvlInst F = lf[b], Cc = lc[b];
@@ -930,7 +936,8 @@ __global__ void __launch_bounds__(256) k_mg_resrestrict_sym(const LvlInst* __res
         for (int fld = 0; fld < 3; ++fld)
 #pragma unroll
           for (int l = 0; l < 4; ++l) {
-            const real rv = bb[(int64_t)(4 * fld + l) * nfc + P.cell] - yy[4 * fld + l];
+            const real bq = (bphi && fld > 0) ? (real)0 : bb[(int64_t)(4 * fld + l) * nfc + P.cell];
+            const real rv = bq - yy[4 * fld + l];
             const int p = l & 1, q = l >> 1;
 #pragma unroll
             for (int L2 = 0; L2 < 4; ++L2)
@@ -1514,7 +1521,7 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     // the pre-smoothing ended with a colour-1 half sweep
     hipLaunchKernelGGL(k_mg_resrestrict_sym<float>, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss,
                        reinterpret_cast<const float*>(bv), reinterpret_cast<const float*>(x),
-                       reinterpret_cast<float*>(C.b), 1, act);
+                       reinterpret_cast<float*>(C.b), 1, act, (rhs_from_v && l == 0) ? 1 : 0);
   } else if (sym) {
     hipLaunchKernelGGL(k_mg_resrestrict_sym<double>, g, dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st, L.ss,
                        bv, x, C.b, 1, act);
@@ -1563,8 +1570,11 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
   const int n = b->n_inst;
   const int mr = b->max_regions;
   if (prep) RTE_TRY(prepare(sigma_t, sigma_s, active, s));
+  // one V-cycle whose finest level sees b only in its single from-zero sweep
+  // (formed from v there; only the scalar-flux field is kept for the
+  // restriction) and whose fine correction goes straight into z
   const bool fused_out = restart == 0 && inner_max == 1 && f32 && sym && lv.size() >= 2 &&
-                         nu_hbm_finest_post == 0 && tail_first != 0 && nu_hbm >= 1;
+                         nu_hbm_finest_post == 0 && tail_first != 0 && nu_hbm == 1;
   if (fused_out) {
     // the V-cycle forms the right-hand side itself
   } else if (f32)
