@@ -969,8 +969,8 @@ struct MgTailLevel {
 // 1 (colour 0, x = 0 beforehand) sets x = D^{-1} b and leaves colour 1
 // unwritten; mode 2 (colour 1 after mode 1) sets x = D^{-1} (b - K x) with its
 // own x taken as zero.
-template <typename real>
-__device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const real* st, const real* ss,
+template <typename real, typename sreal>
+__device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const sreal* st, const sreal* ss,
                                 const real* bv, real* x, int color, int mode) {
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   // even rows: the threads take only this colour's cells (nc / 2 of them)
@@ -1001,7 +1001,7 @@ __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const 
       if (!on[j]) continue;
       const int cell = cellv[j];
       const CellPos P = cell_pos(i, k, nx, ny);
-      const real tt = st[cell], uu = ss[cell];
+      const real tt = (real)st[cell], uu = (real)ss[cell];
       real r[12];
       if (mode == 1) {
 #pragma unroll
@@ -1030,64 +1030,157 @@ __device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const 
 
 // One red-black sweep of a tail level (colour 0, then colour 1); the first
 // of a smoothing from x = 0 knows x = 0 beforehand in both half sweeps.
-template <typename real>
-__device__ __forceinline__ void tail_sweep(const SymCoef<real>& S, const LvlInst& L, const real* st,
-                                           const real* ss, const real* bv, real* x, bool from_zero) {
+template <typename real, typename sreal>
+__device__ __forceinline__ void tail_sweep(const SymCoef<real>& S, const LvlInst& L, const sreal* st,
+                                           const sreal* ss, const real* bv, real* x, bool from_zero) {
   tail_half_sweep(S, L, st, ss, bv, x, 0, from_zero ? 1 : 0);
   tail_half_sweep(S, L, st, ss, bv, x, 1, from_zero ? 2 : 0);
 }
 
-// g0 = 1: the first level's x and b stay in global memory (x_first, b_first;
-// only its cross sections are staged in LDS) and it is smoothed nu0 times
-// before and after the coarse correction; this takes a level too large for
-// LDS into the launch (its global data is touched by this work group only,
-// and the work group's barriers order those accesses as they order LDS).
-// g0 = 0: b_first is copied into LDS and x_first receives the first level's x.
+// Residual of a tail level after a sweep that ended with colour 1 (so only
+// the colour-0 children (0, 0) and (1, 1) have one), restricted into the next
+// level's b.
+template <typename real, typename sreal>
+__device__ void tail_restrict(const SymCoef<real>& S, const LvlInst& L, const LvlInst& C, const sreal* sgt,
+                              const sreal* sgs, const real* x, const real* bv, real* bc) {
+  const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
+  for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
+    const int I = c % C.nx, K = c / C.nx;
+    real acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = (real)0;
+#pragma unroll 1
+    for (int ch = 0; ch < 4; ch += 3) {
+      const int di = ch & 1, dk = ch >> 1;
+      const CellPos P = cell_pos(2 * I + di, 2 * K + dk, L.nx, L.ny);
+      real yy[12];
+      sym_cell_apply(S, (real)sgt[P.cell], (real)sgs[P.cell], x, P, yy);
+#pragma unroll
+      for (int fld = 0; fld < 3; ++fld)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const real rv = bv[(4 * fld + m) * nc + P.cell] - yy[4 * fld + m];
+#pragma unroll
+          for (int L2 = 0; L2 < 4; ++L2)
+            acc[4 * fld + L2] += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * rv;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) bc[q * ncc + c] = acc[q];
+  }
+  __syncthreads();
+}
+
+// x_dst = x_src + P xc on a tail level (x_src may be x_dst): the four
+// children's values are read first, so their loads overlap.
+template <typename real>
+__device__ void tail_prolong(const LvlInst& L, const LvlInst& C, const real* xc, const real* x_src, real* x_dst) {
+  const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
+  for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
+    const int I = c % C.nx, K = c / C.nx;
+    real xcv[12], xf[4][12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) xcv[q] = xc[q * ncc + c];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      const int f = (2 * K + (ch >> 1)) * L.nx + 2 * I + (ch & 1);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) xf[ch][q] = x_src[q * nc + f];
+    }
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      const int di = ch & 1, dk = ch >> 1;
+      const int f = (2 * K + dk) * L.nx + 2 * I + di;
+#pragma unroll
+      for (int fld = 0; fld < 3; ++fld)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          real v = (real)0;
+#pragma unroll
+          for (int L2 = 0; L2 < 4; ++L2)
+            v += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * xcv[4 * fld + L2];
+          x_dst[(4 * fld + m) * nc + f] = xf[ch][4 * fld + m] + v;
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// g0 = 0: every level's x, b and cross sections live in LDS ([x|b|sigma]
+// per level); b_first is copied in and x_first receives the first level's x.
+// g0 = 1: the first level is too large to sit in LDS next to the others.  Its
+// b and cross sections are read from global memory (b_first, the level's
+// FP64 arrays) and its x lives in LDS only while the coarser levels do not:
+// LDS = [sigma of levels 1..][x of level 1][R], where R holds the first
+// level's x during its smoothing and the coarser levels' b (and x from level
+// 2 on) in between.  The first level's residual goes to level 1 through
+// b1_scratch (global) and its x through x_first; it is smoothed nu0 times
+// before and after the coarse correction.
 template <typename real, int NT>
 __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restrict__ tl, int nlev, int nu_smooth,
                                                      int coarse_sweeps, const real* __restrict__ b_first,
                                                      real* __restrict__ x_first,
-                                                     const int32_t* __restrict__ active, int g0, int nu0) {
+                                                     const int32_t* __restrict__ active, int g0, int nu0,
+                                                     real* __restrict__ b1_scratch) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   extern __shared__ unsigned char smem_raw[];
   real* lds = reinterpret_cast<real*>(smem_raw);
-  // per level: x [12][nc], b [12][nc], sigma_t [nc], sigma_s [nc] (g0 level:
-  // sigma_t, sigma_s only)
-  __shared__ int off[MG_TAIL_MAX + 1];
+  // per level: offsets of x, b and the cross sections in LDS (-1: not in LDS)
+  __shared__ int xo[MG_TAIL_MAX], bo[MG_TAIL_MAX], so[MG_TAIL_MAX], r_off;
   if (threadIdx.x == 0) {
-    off[0] = 0;
-    for (int l = 0; l < nlev; ++l) {
-      const LvlInst Li = tl[l].li[b];
-      off[l + 1] = off[l] + ((g0 && l == 0) ? 2 : 26) * Li.nx * Li.ny;
+    if (!g0) {
+      int o = 0;
+      for (int l = 0; l < nlev; ++l) {
+        const LvlInst Li = tl[l].li[b];
+        const int nc = Li.nx * Li.ny;
+        xo[l] = o;
+        bo[l] = o + 12 * nc;
+        so[l] = o + 24 * nc;
+        o += 26 * nc;
+      }
+      r_off = 0;
+    } else {
+      int o = 0;
+      for (int l = 1; l < nlev; ++l) {
+        const LvlInst Li = tl[l].li[b];
+        so[l] = o;
+        o += 2 * Li.nx * Li.ny;
+      }
+      const LvlInst L1 = tl[1].li[b];
+      xo[1] = o;
+      o += 12 * L1.nx * L1.ny;
+      r_off = o;  // R: the first level's x, later the coarser levels' b and x
+      for (int l = 1; l < nlev; ++l) {
+        const LvlInst Li = tl[l].li[b];
+        const int nc = Li.nx * Li.ny;
+        bo[l] = o;
+        o += 12 * nc;
+        if (l >= 2) {
+          xo[l] = o;
+          o += 12 * nc;
+        }
+      }
+      xo[0] = r_off;
+      bo[0] = -1;
+      so[0] = -1;
     }
   }
   __syncthreads();
-  // the level's x, b and cross sections
-  auto lvl_x = [&](int l, const LvlInst& Li) -> real* {
-    return (g0 && l == 0) ? x_first + Li.cell_off * 12 : lds + off[l];
-  };
-  auto lvl_b = [&](int l, const LvlInst& Li) -> real* {
-    return (g0 && l == 0) ? const_cast<real*>(b_first) + Li.cell_off * 12
-                          : lds + off[l] + 12 * Li.nx * Li.ny;
-  };
-  auto lvl_sg = [&](int l, const LvlInst& Li) -> real* {
-    return lds + off[l] + ((g0 && l == 0) ? 0 : 24 * Li.nx * Li.ny);
-  };
-  for (int l = 0; l < nlev; ++l) {  // cross sections of every level, once
+  for (int l = g0 ? 1 : 0; l < nlev; ++l) {  // cross sections of the LDS levels, once
     const LvlInst Li = tl[l].li[b];
     const int nc = Li.nx * Li.ny;
-    real* sg = lvl_sg(l, Li);
+    real* sg = lds + so[l];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
       sg[c] = (real)tl[l].sigt[Li.cell_off + c];
       sg[nc + c] = (real)tl[l].sigs[Li.cell_off + c];
     }
   }
-  if (!g0) {  // load b of the first level
-    const LvlInst L0 = tl[0].li[b];
-    const int n0 = 12 * L0.nx * L0.ny;
+  const LvlInst L0 = tl[0].li[b];
+  const int nc0 = L0.nx * L0.ny;
+  if (!g0) {  // b of the first level
     const real* src = b_first + L0.cell_off * 12;
-    for (int e = threadIdx.x; e < n0; e += blockDim.x) lds[off[0] + n0 + e] = src[e];
+    for (int e = threadIdx.x; e < 12 * nc0; e += blockDim.x) lds[bo[0] + e] = src[e];
   }
   __syncthreads();
   // down: pre-smooth from zero, then residual -> next level's b
@@ -1095,100 +1188,70 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
     const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
-    real* x = lvl_x(l, L);
-    real* bv = lvl_b(l, L);
-    const real* sgt = lvl_sg(l, L);
-    const real* sgs = sgt + nc;
-    const int nu_l = (g0 && l == 0) ? nu0 : nu_smooth;
-    for (int k = 0; k < nu_l; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
-    real* bc = lvl_b(l + 1, C);
-    for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
-      const int I = c % C.nx, K = c / C.nx;
-      real acc[12];
-#pragma unroll
-      for (int q = 0; q < 12; ++q) acc[q] = (real)0;
-#pragma unroll 1
-      for (int ch = 0; ch < 4; ch += 3) {  // colour-0 children: colour 1 was smoothed last
-        const int di = ch & 1, dk = ch >> 1;
-        const CellPos P = cell_pos(2 * I + di, 2 * K + dk, L.nx, L.ny);
-        real yy[12];
-        sym_cell_apply(S, sgt[P.cell], sgs[P.cell], x, P, yy);
-#pragma unroll
-        for (int fld = 0; fld < 3; ++fld)
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const real rv = bv[(4 * fld + m) * nc + P.cell] - yy[4 * fld + m];
-#pragma unroll
-            for (int L2 = 0; L2 < 4; ++L2)
-              acc[4 * fld + L2] += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * rv;
-          }
-      }
-#pragma unroll
-      for (int q = 0; q < 12; ++q) bc[q * ncc + c] = acc[q];
+    real* x = lds + xo[l];
+    if (g0 && l == 0) {
+      const real* bv = b_first + L.cell_off * 12;
+      const double* sgt = tl[0].sigt + L.cell_off;
+      const double* sgs = tl[0].sigs + L.cell_off;
+      for (int k = 0; k < nu0; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
+      // level 1's b cannot sit in LDS next to this level's x: through global
+      real* bs = b1_scratch + C.cell_off * 12;
+      tail_restrict(S, L, C, sgt, sgs, x, bv, bs);
+      real* xg = x_first + L.cell_off * 12;
+      for (int e = threadIdx.x; e < 12 * nc; e += blockDim.x) xg[e] = x[e];
+      __syncthreads();
+      real* bc = lds + bo[1];
+      for (int e = threadIdx.x; e < 12 * ncc; e += blockDim.x) bc[e] = bs[e];
+      __syncthreads();
+    } else {
+      real* bv = lds + bo[l];
+      const real* sgt = lds + so[l];
+      const real* sgs = sgt + nc;
+      for (int k = 0; k < nu_smooth; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
+      tail_restrict(S, L, C, sgt, sgs, x, bv, lds + bo[l + 1]);
     }
-    __syncthreads();
   }
   {  // coarsest: red-black sweeps from zero
     const int l = nlev - 1;
     const LvlInst L = tl[l].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
     const int nc = L.nx * L.ny;
-    real* x = lvl_x(l, L);
-    real* bv = lvl_b(l, L);
-    const real* sgt = lvl_sg(l, L);
-    const real* sgs = sgt + nc;
-    for (int k = 0; k < coarse_sweeps; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
+    const real* sgt = lds + so[l];
+    for (int k = 0; k < coarse_sweeps; ++k) tail_sweep(S, L, sgt, sgt + nc, lds + bo[l], lds + xo[l], k == 0);
   }
   // up: prolong the correction, post-smooth in reverse colour order
   for (int l = nlev - 2; l >= 0; --l) {
     const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
-    const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
-    real* x = lvl_x(l, L);
-    real* bv = lvl_b(l, L);
-    const real* xc = lvl_x(l + 1, C);
-    for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
-      const int I = c % C.nx, K = c / C.nx;
-      real xcv[12], xf[4][12];
-#pragma unroll
-      for (int q = 0; q < 12; ++q) xcv[q] = xc[q * ncc + c];
-      // the four children's values first (their loads overlap), then the sums
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        const int f = (2 * K + (ch >> 1)) * L.nx + 2 * I + (ch & 1);
-#pragma unroll
-        for (int q = 0; q < 12; ++q) xf[ch][q] = x[q * nc + f];
+    const int nc = L.nx * L.ny;
+    real* x = lds + xo[l];
+    const real* xc = lds + xo[l + 1];
+    if (g0 && l == 0) {
+      // x comes back from global memory plus the correction, into R (the
+      // coarser levels are done with it)
+      real* xg = x_first + L.cell_off * 12;
+      tail_prolong(L, C, xc, xg, x);
+      const real* bv = b_first + L.cell_off * 12;
+      const double* sgt = tl[0].sigt + L.cell_off;
+      const double* sgs = tl[0].sigs + L.cell_off;
+      for (int k = 0; k < nu0; ++k) {
+        tail_half_sweep(S, L, sgt, sgs, bv, x, 1, 0);
+        tail_half_sweep(S, L, sgt, sgs, bv, x, 0, 0);
       }
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        const int di = ch & 1, dk = ch >> 1;
-        const int f = (2 * K + dk) * L.nx + 2 * I + di;
-#pragma unroll
-        for (int fld = 0; fld < 3; ++fld)
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            real v = (real)0;
-#pragma unroll
-            for (int L2 = 0; L2 < 4; ++L2)
-              v += (real)(inj1d(di, m & 1, L2 & 1) * inj1d(dk, m >> 1, L2 >> 1)) * xcv[4 * fld + L2];
-            x[(4 * fld + m) * nc + f] = xf[ch][4 * fld + m] + v;
-          }
+      for (int e = threadIdx.x; e < 12 * nc; e += blockDim.x) xg[e] = x[e];
+    } else {
+      tail_prolong(L, C, xc, x, x);
+      const real* sgt = lds + so[l];
+      const real* bv = lds + bo[l];
+      for (int k = 0; k < nu_smooth; ++k) {
+        tail_half_sweep(S, L, sgt, sgt + nc, bv, x, 1, 0);
+        tail_half_sweep(S, L, sgt, sgt + nc, bv, x, 0, 0);
       }
-    }
-    __syncthreads();
-    const real* sgt = lvl_sg(l, L);
-    const real* sgs = sgt + nc;
-    const int nu_l = (g0 && l == 0) ? nu0 : nu_smooth;
-    for (int k = 0; k < nu_l; ++k) {
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 1, 0);
-      tail_half_sweep(S, L, sgt, sgs, bv, x, 0, 0);
     }
   }
-  if (!g0) {  // store x of the first level
-    const LvlInst L0 = tl[0].li[b];
-    const int n0 = 12 * L0.nx * L0.ny;
+  if (!g0) {  // x of the first level
     real* dst = x_first + L0.cell_off * 12;
-    for (int e = threadIdx.x; e < n0; e += blockDim.x) dst[e] = lds[off[0] + e];
+    for (int e = threadIdx.x; e < 12 * nc0; e += blockDim.x) dst[e] = lds[xo[0] + e];
   }
 }
 
@@ -1351,14 +1414,21 @@ int DsaSolver::init(rte_batch* batch, int restart_, int pc_) {
         tail_first = l;
         tail_lds = need;
       }
-      // FP32: one more level (from level 1 on) whose x and b stay in HBM and
-      // whose cross sections alone go to LDS
-      const int l = tail_first - 1;
-      if (f32 && tail_first >= 2 && nlev - l <= MG_TAIL_MAX) {
-        const size_t extra = (size_t)2 * lv[l].max_nx * lv[l].max_ny * es;
-        if (tail_lds + extra <= cap) {
-          tail_first = l;
-          tail_lds += extra;
+      // FP32: one more level (from level 1 on) whose b and cross sections
+      // stay in HBM and whose x shares LDS with the coarser levels' b and x
+      // (the launch's g0 layout)
+      const int l0 = tail_first - 1;
+      if (f32 && tail_first >= 2 && nlev - l0 <= MG_TAIL_MAX) {
+        auto cells = [&](int l) { return (size_t)lv[l].max_nx * lv[l].max_ny; };
+        size_t sg = 0, rest = 0;
+        for (int l = l0 + 1; l < nlev; ++l) {
+          sg += 2 * cells(l);
+          rest += 12 * cells(l) * (l >= l0 + 2 ? 2 : 1);
+        }
+        const size_t g0_need = (sg + 12 * cells(l0 + 1) + std::max(12 * cells(l0), rest)) * es;
+        if (g0_need <= cap) {
+          tail_first = l0;
+          tail_lds = g0_need;
           tail_g0 = 1;
         }
       }
@@ -1490,10 +1560,10 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     if (f32)
       hipLaunchKernelGGL((k_mg_tail_sym<float, MG_TAIL_THREADS_F32>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F32), tail_lds, s, d_tail, nt, nu_smooth,
                          coarse_sweeps, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x), act,
-                         tail_g0, nu_hbm);
+                         tail_g0, nu_hbm, tail_g0 ? reinterpret_cast<float*>(lv[l + 1].b) : (float*)nullptr);
     else
       hipLaunchKernelGGL((k_mg_tail_sym<double, MG_TAIL_THREADS_F64>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F64), tail_lds, s, d_tail, nt, nu_smooth,
-                         coarse_sweeps, bv, x, act, 0, nu_smooth);
+                         coarse_sweeps, bv, x, act, 0, nu_smooth, (double*)nullptr);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }

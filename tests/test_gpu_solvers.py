@@ -75,6 +75,29 @@ def test_dsa_apply_parity_symmetric_rules():
 
 
 @pytest.mark.gpu
+def test_dsa_fp32_vcycles_with_an_hbm_backed_tail_level():
+    """96 x 48 cells: the 48 x 24 level is too large for LDS next to the coarser
+    ones, so the V-cycle's LDS launch keeps its x in LDS only while it smooths
+    and its b in global memory; stationary FP32 V-cycles still converge to the
+    oracle's exact DSA correction (slowly on these optically thin cells: a
+    contraction of about 0.95 per cycle, as a CPU model of the same cycle
+    shows, so 400 cycles)."""
+    import paper_2410_08735_amd as rt
+    spec = tiny_2d(seed=5, nx=96, ny=48, quad=("cl", 8, 4, True), n_regions=3)
+    B = rt.Batch([spec, spec])
+    st, ss = B.sigma()
+    rng = np.random.default_rng(11)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    ref = odsa.DSA(tr.Problem(spec))
+    for n_cyc, bound in ((400, 2e-5), (40, 0.05), (1, 0.9)):
+        z, _ = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=0.0, inner_max=n_cyc, restart=0)
+        for k in range(2):
+            err = rel(B.unpack(z)[k] - v[k], ref.apply(v[k]) - v[k])
+            print(f"{n_cyc} FP32 V-cycles, 96 x 48, instance {k}: rel err {err:.2e}", flush=True)
+            assert err <= bound, (n_cyc, k, err)
+
+
+@pytest.mark.gpu
 def test_dsa_apply_parity_1d():
     import paper_2410_08735_amd as rt
     specs = [tiny_1d(seed=1, nx=12, n_ord=8), tiny_1d(seed=2, nx=7, n_ord=2)]
