@@ -898,6 +898,125 @@ __global__ void k_dsa_out_prolong(const InstDev* __restrict__ insts, const LvlIn
   }
 }
 
+// The finest level's part of the FP32 V-cycle of one DSA application
+// (reflection-symmetric rules, one from-zero sweep), in one pass over tiles
+// of FF_T x FF_T cells: b = [sigma_s v, 0, 0] (the rule's first moments are
+// zero), the colour-0 half sweep x = D^{-1} b on the tile and a two-cell halo,
+// the colour-1 half sweep x = D^{-1} (b - K x) on the tile and a one-cell halo,
+// then the residual of the tile's colour-0 cells (colour 1 has none after its
+// half sweep) restricted into the coarse b, and the scalar-flux field of x
+// for the output pass.  The same values as the separate half sweeps and the
+// residual-restriction pass, with x and b kept in LDS instead of HBM.
+constexpr int FF_T = 24;
+constexpr int FF_W = FF_T + 4;
+constexpr int FF_N = FF_W * FF_W;
+
+__global__ void __launch_bounds__(256) k_mg_fine_fused(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
+                                                       const DsaStencil* __restrict__ st_f,
+                                                       const double* __restrict__ st, const double* __restrict__ ss,
+                                                       const InstDev* __restrict__ insts, const double* __restrict__ v,
+                                                       float* __restrict__ xphi, float* __restrict__ coarse_b,
+                                                       const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const LvlInst F = lf[b], Cc = lc[b];
+  const int nx = F.nx, ny = F.ny, nfc = nx * ny;
+  const int tiles_x = (nx + FF_T - 1) / FF_T, tiles_y = (ny + FF_T - 1) / FF_T;
+  if ((int)blockIdx.x >= tiles_x * tiles_y) return;
+  const int ox = ((int)blockIdx.x % tiles_x) * FF_T, oy = ((int)blockIdx.x / tiles_x) * FF_T;
+  const int tw = min(FF_T, nx - ox), th = min(FF_T, ny - oy);  // even: the grid coarsens
+  const SymCoef<float> S = sym_coef<float>(st_f[b]);
+  __shared__ float lx[12 * FF_N];  // x on the tile and its halo, [field mode][local cell]
+  __shared__ float lb[4 * FF_N];   // scalar-flux field of b
+  __shared__ float lsg[2 * FF_N];  // sigma_t, sigma_s
+  const double* __restrict__ vb = v + insts[b].dof_off;
+  // local cell e <-> grid cell (ox - 2 + e % FF_W, oy - 2 + e / FF_W)
+  auto lpos = [&](int i, int k) {
+    CellPos p;
+    p.cell = (i - ox + 2) + FF_W * (k - oy + 2);
+    p.nx = FF_W;
+    p.nc = FF_N;
+    p.hl = i > 0;
+    p.hr = i < nx - 1;
+    p.hb = k > 0;
+    p.ht = k < ny - 1;
+    return p;
+  };
+  for (int e = threadIdx.x; e < FF_N; e += blockDim.x) {
+    const int i = ox - 2 + e % FF_W, k = oy - 2 + e / FF_W;
+    if (i < 0 || i >= nx || k < 0 || k >= ny) continue;
+    const int cell = k * nx + i;
+    const double sd = ss[F.cell_off + cell];
+    lsg[e] = (float)st[F.cell_off + cell];
+    lsg[FF_N + e] = (float)sd;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) lb[m * FF_N + e] = (float)(sd * vb[4 * cell + m]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < FF_N; e += blockDim.x) {  // colour 0, halo 2
+    const int i = ox - 2 + e % FF_W, k = oy - 2 + e / FF_W;
+    if (i < 0 || i >= nx || k < 0 || k >= ny || ((i + k) & 1) != 0) continue;
+    float r[12], d[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) r[q] = q < 4 ? lb[q * FF_N + e] : 0.f;
+    sym_block_solve(S, lsg[e], lsg[FF_N + e], r, d);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) lx[q * FF_N + e] = d[q];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < FF_N; e += blockDim.x) {  // colour 1, halo 1
+    const int li = e % FF_W, lk = e / FF_W;
+    const int i = ox - 2 + li, k = oy - 2 + lk;
+    if (li < 1 || li > FF_W - 2 || lk < 1 || lk > FF_W - 2) continue;
+    if (i < 0 || i >= nx || k < 0 || k >= ny || ((i + k) & 1) != 1) continue;
+    const CellPos P = lpos(i, k);
+    float yy[12], r[12], d[12];
+    sym_cell_apply<float, false>(S, lsg[e], lsg[FF_N + e], lx, P, yy);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) r[q] = (q < 4 ? lb[q * FF_N + e] : 0.f) - yy[q];
+    sym_block_solve(S, lsg[e], lsg[FF_N + e], r, d);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) lx[q * FF_N + e] = d[q];
+  }
+  __syncthreads();
+  const int ncc = Cc.nx * Cc.ny;
+  const int cw = tw / 2, ch_ = th / 2;
+  for (int c = threadIdx.x; c < cw * ch_; c += blockDim.x) {  // the tile's coarse cells
+    const int I = ox / 2 + c % cw, K = oy / 2 + c / cw;
+    float acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.f;
+#pragma unroll 1
+    for (int ch = 0; ch < 4; ch += 3) {  // the colour-0 children (0, 0) and (1, 1)
+      const int di = ch & 1, dk = ch >> 1;
+      const CellPos P = lpos(2 * I + di, 2 * K + dk);
+      const int e = P.cell;
+      float yy[12];
+      sym_cell_apply(S, lsg[e], lsg[FF_N + e], lx, P, yy);
+#pragma unroll
+      for (int fld = 0; fld < 3; ++fld)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const float bq = fld == 0 ? lb[l * FF_N + e] : 0.f;
+          const float rv = bq - yy[4 * fld + l];
+          const int p = l & 1, q = l >> 1;
+#pragma unroll
+          for (int L2 = 0; L2 < 4; ++L2)
+            acc[4 * fld + L2] += (float)(inj1d(di, p, L2 & 1) * inj1d(dk, q, L2 >> 1)) * rv;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) coarse_b[Cc.cell_off * 12 + (int64_t)q * ncc + K * Cc.nx + I] = acc[q];
+  }
+  float* __restrict__ xo = xphi + F.cell_off * 12;
+  for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {  // scalar-flux field of x on the tile
+    const int i = ox + e % tw, k = oy + e / tw;
+    const int l = (i - ox + 2) + FF_W * (k - oy + 2);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) xo[(int64_t)m * nfc + k * nx + i] = lx[m * FF_N + l];
+  }
+}
+
 // Residual and restriction in one pass (reflection-symmetric rules): each
 // coarse cell forms b - K x on its 2 x 2 children and accumulates P_f^T of it.
 // After a red-black half sweep of colour 1 the residual of every colour-1 cell
@@ -1580,6 +1699,18 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
       return RTE_OK;
     }
     return smooth(l, coarse_sweeps, false, true, bv, x, act, s);
+  }
+  if (l == 0 && sym && f32 && rhs_from_v && defer_fine_prolong && nu_hbm == 1) {
+    // the finest level's part (right-hand side from v, one from-zero sweep,
+    // residual and restriction) in one pass over tiles
+    MgLevel& C = lv[1];
+    int tiles = 0;
+    for (const auto& q : L.li) tiles = std::max(tiles, ((q.nx + FF_T - 1) / FF_T) * ((q.ny + FF_T - 1) / FF_T));
+    hipLaunchKernelGGL(k_mg_fine_fused, dim3(tiles, b->n_inst), dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st,
+                       L.ss, b->d_inst, rhs_from_v, reinterpret_cast<float*>(x), reinterpret_cast<float*>(C.b),
+                       act);
+    RTE_HIP(hipGetLastError());
+    return vcycle(1, C.b, C.x, act, s);
   }
   // smoothing sweeps before and after the coarse correction on this level
   const int pre = f32 ? nu_hbm : nu_smooth;
