@@ -152,6 +152,10 @@ class Batch:
         torch = _torch()
         return torch.zeros(self.total_dof if n is None else n, dtype=torch.float64, device="cuda")
 
+    def empty(self, n=None):
+        torch = _torch()
+        return torch.empty(self.total_dof if n is None else n, dtype=torch.float64, device="cuda")
+
 
 def sweep(batch, sigma_t, q, inflow=None, phi=True, psi=False, dtype="f64"):
     torch = _torch()
@@ -240,7 +244,7 @@ def _stats_array(stats):
 
 def fgmres_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None, mlp=None, mu=None):
     opts = opts or SolveOptions()
-    phi = batch.zeros()
+    phi = batch.empty()  # the library starts from phi = 0
     stats = (L.SolveStats * batch.n)()
     co = opts.c()
     mu_dim = 0 if mu is None else int(mu.shape[1])
@@ -254,7 +258,7 @@ def fgmres_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None, m
 def si_solve(batch, sigma_t, sigma_s, G, inflow=None, opts=None, rom=None):
     """Source iteration with synthetic acceleration; opts.max_cycles bounds the iterations."""
     opts = opts or SolveOptions()
-    phi = batch.zeros()
+    phi = batch.empty()  # the library starts from phi = 0
     stats = (L.SolveStats * batch.n)()
     co = opts.c()
     st = L.lib().si_solve(batch.h, _ptr(sigma_t), _ptr(sigma_s), _ptr(G), _ptr(inflow), C.byref(co),
