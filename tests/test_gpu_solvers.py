@@ -220,8 +220,11 @@ def test_fgmres_fp64_parity(precond):
 
 @pytest.mark.gpu
 def test_fgmres_fp32_sweeps_refined_to_1e8():
+    """FP32 cycles (b~ from an FP32 sweep), FP64 true residuals T (G + Sigma_s phi) - phi,
+    with and without inflow."""
     import paper_2410_08735_amd as rt
-    specs = [tiny_2d(seed=s, nx=12, ny=10, quad=("cl", 16, 4, True), n_regions=2) for s in range(4)]
+    specs = [tiny_2d(seed=s, nx=12, ny=10, quad=("cl", 16, 4, True), n_regions=2, inflow=0.3 * (s % 2))
+             for s in range(4)]
     B = rt.Batch(specs)
     st, ss = B.sigma()
     opts = rt.SolveOptions(precond="dsa", m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8,
