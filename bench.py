@@ -402,8 +402,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
-              "part of it", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (--gpus 1); runs on several GPUs "
+              "are not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
