@@ -908,7 +908,7 @@ __global__ void k_dsa_out_prolong(const InstDev* __restrict__ insts, const LvlIn
 // for the output pass.  The same values as the separate half sweeps and the
 // residual-restriction pass, with x and b kept in LDS instead of HBM.
 constexpr int FF_T = 24;
-constexpr int FF_W = FF_T + 4;
+constexpr int FF_W = FF_T + 4;  // even: each local row holds FF_W / 2 cells of each colour
 constexpr int FF_N = FF_W * FF_W;
 
 __global__ void __launch_bounds__(256) k_mg_fine_fused(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
@@ -953,9 +953,13 @@ __global__ void __launch_bounds__(256) k_mg_fine_fused(const LvlInst* __restrict
     for (int m = 0; m < 4; ++m) lb[m * FF_N + e] = (float)(sd * vb[4 * cell + m]);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < FF_N; e += blockDim.x) {  // colour 0, halo 2
-    const int i = ox - 2 + e % FF_W, k = oy - 2 + e / FF_W;
-    if (i < 0 || i >= nx || k < 0 || k >= ny || ((i + k) & 1) != 0) continue;
+  // the half sweeps take one colour's local cells only (tile origins are even,
+  // so a local cell's colour is that of its local coordinates)
+  for (int t = threadIdx.x; t < FF_N / 2; t += blockDim.x) {  // colour 0, halo 2
+    const int lk = t / (FF_W / 2), li = 2 * (t % (FF_W / 2)) + (lk & 1);
+    const int e = lk * FF_W + li;
+    const int i = ox - 2 + li, k = oy - 2 + lk;
+    if (i < 0 || i >= nx || k < 0 || k >= ny) continue;
     float r[12], d[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) r[q] = q < 4 ? lb[q * FF_N + e] : 0.f;
@@ -964,11 +968,12 @@ __global__ void __launch_bounds__(256) k_mg_fine_fused(const LvlInst* __restrict
     for (int q = 0; q < 12; ++q) lx[q * FF_N + e] = d[q];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < FF_N; e += blockDim.x) {  // colour 1, halo 1
-    const int li = e % FF_W, lk = e / FF_W;
+  for (int t = threadIdx.x; t < FF_N / 2; t += blockDim.x) {  // colour 1, halo 1
+    const int lk = t / (FF_W / 2), li = 2 * (t % (FF_W / 2)) + ((lk + 1) & 1);
+    const int e = lk * FF_W + li;
     const int i = ox - 2 + li, k = oy - 2 + lk;
     if (li < 1 || li > FF_W - 2 || lk < 1 || lk > FF_W - 2) continue;
-    if (i < 0 || i >= nx || k < 0 || k >= ny || ((i + k) & 1) != 1) continue;
+    if (i < 0 || i >= nx || k < 0 || k >= ny) continue;
     const CellPos P = lpos(i, k);
     float yy[12], r[12], d[12];
     sym_cell_apply<float, false>(S, lsg[e], lsg[FF_N + e], lx, P, yy);
