@@ -911,7 +911,7 @@ constexpr int FF_T = 24;
 constexpr int FF_W = FF_T + 4;  // even: each local row holds FF_W / 2 cells of each colour
 constexpr int FF_N = FF_W * FF_W;
 
-__global__ void __launch_bounds__(256) k_mg_fine_fused(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
+__global__ void __launch_bounds__(512) k_mg_fine_fused(const LvlInst* __restrict__ lf, const LvlInst* __restrict__ lc,
                                                        const DsaStencil* __restrict__ st_f,
                                                        const double* __restrict__ st, const double* __restrict__ ss,
                                                        const InstDev* __restrict__ insts, const double* __restrict__ v,
@@ -1711,7 +1711,7 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     MgLevel& C = lv[1];
     int tiles = 0;
     for (const auto& q : L.li) tiles = std::max(tiles, ((q.nx + FF_T - 1) / FF_T) * ((q.ny + FF_T - 1) / FF_T));
-    hipLaunchKernelGGL(k_mg_fine_fused, dim3(tiles, b->n_inst), dim3(256), 0, s, L.d_li, C.d_li, L.d_st, L.st,
+    hipLaunchKernelGGL(k_mg_fine_fused, dim3(tiles, b->n_inst), dim3(512), 0, s, L.d_li, C.d_li, L.d_st, L.st,
                        L.ss, b->d_inst, rhs_from_v, reinterpret_cast<float*>(x), reinterpret_cast<float*>(C.b),
                        act);
     RTE_HIP(hipGetLastError());
