@@ -155,10 +155,28 @@ __global__ void k_mgs_step(const int64_t* __restrict__ off, const int64_t* __res
   const double h = hs;
   const int64_t end = min(n, start + (int64_t)KCHUNK);
   double acc = 0.0;
-  for (int64_t e = start + threadIdx.x; e < end; e += blockDim.x) {
-    const double wv = w[base + e] - h * vi[base + e];
-    w[base + e] = wv;
-    acc += wv * (vnext ? vnext[base + e] : wv);
+  if (((base | start | end) & 1) == 0) {
+    // pairs of DoFs per load (16 B): offsets and lengths are even (whole cells)
+    for (int64_t e = start + 2 * threadIdx.x; e < end; e += 2 * blockDim.x) {
+      const double2 wp = *reinterpret_cast<const double2*>(w + base + e);
+      const double2 vp = *reinterpret_cast<const double2*>(vi + base + e);
+      double2 o;
+      o.x = wp.x - h * vp.x;
+      o.y = wp.y - h * vp.y;
+      *reinterpret_cast<double2*>(w + base + e) = o;
+      if (vnext) {
+        const double2 np = *reinterpret_cast<const double2*>(vnext + base + e);
+        acc += o.x * np.x + o.y * np.y;
+      } else {
+        acc += o.x * o.x + o.y * o.y;
+      }
+    }
+  } else {
+    for (int64_t e = start + threadIdx.x; e < end; e += blockDim.x) {
+      const double wv = w[base + e] - h * vi[base + e];
+      w[base + e] = wv;
+      acc += wv * (vnext ? vnext[base + e] : wv);
+    }
   }
   acc = block_sum256(acc, sh);
   if (threadIdx.x == 0) part_out[(int64_t)b * maxc + c] = acc;
