@@ -88,9 +88,17 @@ __global__ void k_dot_part(const int64_t* __restrict__ off, const int64_t* __res
   if (start >= n) return;
   const int64_t end = min(n, start + (int64_t)KCHUNK);
   double acc = 0.0;
-  for (int64_t e = start + threadIdx.x; e < end; e += blockDim.x) {
-    const double xv = x[base + e];
-    acc += xv * (y ? y[base + e] : xv);
+  if (((base | start | end) & 1) == 0) {  // pairs of DoFs per 16-byte load
+    for (int64_t e = start + 2 * threadIdx.x; e < end; e += 2 * blockDim.x) {
+      const double2 xv = *reinterpret_cast<const double2*>(x + base + e);
+      const double2 yv = y ? *reinterpret_cast<const double2*>(y + base + e) : xv;
+      acc += xv.x * yv.x + xv.y * yv.y;
+    }
+  } else {
+    for (int64_t e = start + threadIdx.x; e < end; e += blockDim.x) {
+      const double xv = x[base + e];
+      acc += xv * (y ? y[base + e] : xv);
+    }
   }
   acc = block_sum256(acc, sh);
   if (threadIdx.x == 0) part[(int64_t)b * maxc + c] = acc;
@@ -115,9 +123,17 @@ __global__ void k_scale(const int64_t* __restrict__ off, const int64_t* __restri
   const int64_t n = len[b], base = off[b];
   const double d = sc[(int64_t)b * stride];
   const double f = d != 0.0 ? 1.0 / d : 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    y[base + e] = x[base + e] * f;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  if (((base | n) & 1) == 0) {  // pairs of DoFs per 16-byte access
+    for (int64_t p = t0; 2 * p < n; p += step) {
+      double2 v = *reinterpret_cast<const double2*>(x + base + 2 * p);
+      v.x *= f;
+      v.y *= f;
+      *reinterpret_cast<double2*>(y + base + 2 * p) = v;
+    }
+  } else {
+    for (int64_t e = t0; e < n; e += step) y[base + e] = x[base + e] * f;
+  }
 }
 
 __global__ void k_axpby(const int64_t* __restrict__ off, const int64_t* __restrict__ len, double a,
@@ -268,11 +284,24 @@ __global__ void k_update(const int64_t* __restrict__ off, const int64_t* __restr
   if (jd == 0) return;
   const int64_t n = len[b], base = off[b];
   const double* yb = y + (int64_t)b * m;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double acc = X[base + e];
-    for (int i = 0; i < jd; ++i) acc += yb[i] * basis[(int64_t)i * total + base + e];
-    X[base + e] = acc;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  if (((base | n | total) & 1) == 0) {  // pairs of DoFs per 16-byte access
+    for (int64_t p = t0; 2 * p < n; p += step) {
+      const int64_t e = base + 2 * p;
+      double2 acc = *reinterpret_cast<const double2*>(X + e);
+      for (int i = 0; i < jd; ++i) {
+        const double2 v = *reinterpret_cast<const double2*>(basis + (int64_t)i * total + e);
+        acc.x += yb[i] * v.x;
+        acc.y += yb[i] * v.y;
+      }
+      *reinterpret_cast<double2*>(X + e) = acc;
+    }
+  } else {
+    for (int64_t e = t0; e < n; e += step) {
+      double acc = X[base + e];
+      for (int i = 0; i < jd; ++i) acc += yb[i] * basis[(int64_t)i * total + base + e];
+      X[base + e] = acc;
+    }
   }
 }
 
