@@ -610,12 +610,48 @@ __global__ void __launch_bounds__(256) reduce_partials_dot_kernel(
   const int64_t end = min(nd, start + (int64_t)chunk);
   const InstPart pp = parts[inst];
   double acc = 0.0;
-  for (int64_t d = start + threadIdx.x; d < end; d += blockDim.x) {
-    const double t = sum_partials(part + pp.off + d, pp.n, nd);
-    double v = alpha * t;
-    if (x) v += beta * x[I.dof_off + d];
-    out[I.dof_off + d] = v;
-    acc += v * dotv[I.dof_off + d];
+  if (((pp.off | I.dof_off | start | end) & 1) == 0) {
+    // pairs of DoFs per access (whole cells keep every offset even); each
+    // DoF's partials are summed in the same order as below
+    using P2 = typename Pair2<real>::T;
+    for (int64_t d = start + 2 * threadIdx.x; d < end; d += 2 * blockDim.x) {
+      const P2* q = reinterpret_cast<const P2*>(part + pp.off + d);
+      const int64_t st2 = nd / 2;
+      double t0 = 0.0, t1 = 0.0;
+      int k = 0;
+      for (; k + 4 <= pp.n; k += 4) {
+        const P2 a0 = q[(int64_t)k * st2], a1 = q[(int64_t)(k + 1) * st2];
+        const P2 a2 = q[(int64_t)(k + 2) * st2], a3 = q[(int64_t)(k + 3) * st2];
+        t0 += (double)a0.x; t1 += (double)a0.y;
+        t0 += (double)a1.x; t1 += (double)a1.y;
+        t0 += (double)a2.x; t1 += (double)a2.y;
+        t0 += (double)a3.x; t1 += (double)a3.y;
+      }
+      for (; k < pp.n; ++k) {
+        const P2 a = q[(int64_t)k * st2];
+        t0 += (double)a.x;
+        t1 += (double)a.y;
+      }
+      double2 v;
+      v.x = alpha * t0;
+      v.y = alpha * t1;
+      if (x) {
+        const double2 xv = *reinterpret_cast<const double2*>(x + I.dof_off + d);
+        v.x += beta * xv.x;
+        v.y += beta * xv.y;
+      }
+      *reinterpret_cast<double2*>(out + I.dof_off + d) = v;
+      const double2 dv = *reinterpret_cast<const double2*>(dotv + I.dof_off + d);
+      acc += v.x * dv.x + v.y * dv.y;
+    }
+  } else {
+    for (int64_t d = start + threadIdx.x; d < end; d += blockDim.x) {
+      const double t = sum_partials(part + pp.off + d, pp.n, nd);
+      double v = alpha * t;
+      if (x) v += beta * x[I.dof_off + d];
+      out[I.dof_off + d] = v;
+      acc += v * dotv[I.dof_off + d];
+    }
   }
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
