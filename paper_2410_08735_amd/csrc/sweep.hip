@@ -582,13 +582,52 @@ __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
   const InstDev I = insts[inst];
   const int64_t nd = (int64_t)I.nx * I.ny * I.nloc;
   const InstPart pp = parts[inst];
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd;
-       d += (int64_t)gridDim.x * blockDim.x) {
-    const double acc = sum_partials(part + pp.off + d, pp.n, nd);
-    double v = alpha * acc;
-    if (x) v += beta * x[I.dof_off + d];
-    if (y) v += gamma * y[I.dof_off + d];
-    out[I.dof_off + d] = v;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  if (((pp.off | I.dof_off | nd) & 1) == 0) {
+    // pairs of DoFs per access; each DoF's partials summed in the same order
+    using P2 = typename Pair2<real>::T;
+    const int64_t st2 = nd / 2;
+    for (int64_t q2 = t0; 2 * q2 < nd; q2 += step) {
+      const int64_t d = 2 * q2;
+      const P2* q = reinterpret_cast<const P2*>(part + pp.off + d);
+      double a0s = 0.0, a1s = 0.0;
+      int k = 0;
+      for (; k + 4 <= pp.n; k += 4) {
+        const P2 u0 = q[(int64_t)k * st2], u1 = q[(int64_t)(k + 1) * st2];
+        const P2 u2 = q[(int64_t)(k + 2) * st2], u3 = q[(int64_t)(k + 3) * st2];
+        a0s += (double)u0.x; a1s += (double)u0.y;
+        a0s += (double)u1.x; a1s += (double)u1.y;
+        a0s += (double)u2.x; a1s += (double)u2.y;
+        a0s += (double)u3.x; a1s += (double)u3.y;
+      }
+      for (; k < pp.n; ++k) {
+        const P2 u = q[(int64_t)k * st2];
+        a0s += (double)u.x;
+        a1s += (double)u.y;
+      }
+      double2 v;
+      v.x = alpha * a0s;
+      v.y = alpha * a1s;
+      if (x) {
+        const double2 xv = *reinterpret_cast<const double2*>(x + I.dof_off + d);
+        v.x += beta * xv.x;
+        v.y += beta * xv.y;
+      }
+      if (y) {
+        const double2 yv = *reinterpret_cast<const double2*>(y + I.dof_off + d);
+        v.x += gamma * yv.x;
+        v.y += gamma * yv.y;
+      }
+      *reinterpret_cast<double2*>(out + I.dof_off + d) = v;
+    }
+  } else {
+    for (int64_t d = t0; d < nd; d += step) {
+      const double acc = sum_partials(part + pp.off + d, pp.n, nd);
+      double v = alpha * acc;
+      if (x) v += beta * x[I.dof_off + d];
+      if (y) v += gamma * y[I.dof_off + d];
+      out[I.dof_off + d] = v;
+    }
   }
 }
 
