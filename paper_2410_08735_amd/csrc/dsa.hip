@@ -886,15 +886,33 @@ __global__ void k_dsa_out_prolong(const InstDev* __restrict__ insts, const LvlIn
   const int nfc = F.nx * F.ny, ncc = Cc.nx * Cc.ny;
   const float* __restrict__ xb = xf + F.cell_off * 12;
   const float* __restrict__ cb = xc + Cc.cell_off * 12;
-  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < 4 * nfc; d += gridDim.x * blockDim.x) {
-    const int cell = d >> 2, m = d & 3;
+  // one cell (its 4 DoFs, contiguous in v and z) per thread
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < nfc; cell += gridDim.x * blockDim.x) {
     const int i = cell % F.nx, k = cell / F.nx;
     const int parent = (k >> 1) * Cc.nx + (i >> 1);
-    float corr = 0.f;
+    float xc[4];
 #pragma unroll
-    for (int L2 = 0; L2 < 4; ++L2)
-      corr += (float)(inj1d(i & 1, m & 1, L2 & 1) * inj1d(k & 1, m >> 1, L2 >> 1)) * cb[L2 * ncc + parent];
-    z[I.dof_off + d] = v[I.dof_off + d] + (double)(xb[m * nfc + cell] + corr);
+    for (int L2 = 0; L2 < 4; ++L2) xc[L2] = cb[L2 * ncc + parent];
+    const double2* vp = reinterpret_cast<const double2*>(v + I.dof_off + 4 * (int64_t)cell);
+    double2* zp = reinterpret_cast<double2*>(z + I.dof_off + 4 * (int64_t)cell);
+    double out[4];
+    const double2 v01 = vp[0], v23 = vp[1];
+    const double vv[4] = {v01.x, v01.y, v23.x, v23.y};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float corr = 0.f;
+#pragma unroll
+      for (int L2 = 0; L2 < 4; ++L2)
+        corr += (float)(inj1d(i & 1, m & 1, L2 & 1) * inj1d(k & 1, m >> 1, L2 >> 1)) * xc[L2];
+      out[m] = vv[m] + (double)(xb[m * nfc + cell] + corr);
+    }
+    double2 o01, o23;
+    o01.x = out[0];
+    o01.y = out[1];
+    o23.x = out[2];
+    o23.y = out[3];
+    zp[0] = o01;
+    zp[1] = o23;
   }
 }
 
