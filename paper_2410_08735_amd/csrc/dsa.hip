@@ -1434,7 +1434,7 @@ struct DsaSolver {
   // stationary V-cycle nu_hbm before and after, except none after on the
   // finest level (a sweep there costs more time than the extra FGMRES
   // iterations it saves); nu_smooth everywhere in the FP64 hierarchy
-  int nu_smooth = 2, nu_hbm = 1, nu_hbm_finest_post = 0, coarse_sweeps = 6;
+  int nu_smooth = 2, nu_hbm = 1, nu_hbm_finest_post = 0, coarse_sweeps = 4;
   // set by apply for one FP32 V-cycle: level 0 stops after the coarse
   // correction, which k_dsa_out_prolong then adds while writing the output
   bool defer_fine_prolong = false;
