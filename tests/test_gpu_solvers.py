@@ -242,6 +242,30 @@ def test_fgmres_fp32_sweeps_refined_to_1e8():
 
 
 @pytest.mark.gpu
+def test_fgmres_fp32_with_one_vcycle_dsa_on_partial_tiles():
+    """The production configuration (FP32 cycles, one FP32 V-cycle per DSA
+    application, whose finest level runs in 24 x 24 tiles) on grids that leave
+    partial tiles: the solution matches the oracle's FGMRES-DSA to FP32-cycle
+    accuracy."""
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=21, nx=40, ny=32, quad=("cl", 8, 4, True), n_regions=3, inflow=0.2),
+             tiny_2d(seed=22, nx=30, ny=26, quad=("cl", 8, 4, True), n_regions=2),
+             tiny_2d(seed=23, nx=18, ny=18, quad=("cl", 12, 2, True), n_regions=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    opts = rt.SolveOptions(precond="dsa", m=30, max_cycles=10, sweep_dtype="f32", rtol=1e-8,
+                           dsa_inner_max=1, dsa_restart=0)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), opts)
+    assert ret == 0
+    for k, spec in enumerate(specs):
+        assert stats[k]["true_relres"] <= 1e-8
+        ref = _oracle_solve(spec, "dsa", rtol=1e-12)
+        err = rel(B.unpack(phi)[k], ref.x)
+        print(f"instance {k}: {stats[k]['iterations']} iterations, rel err {err:.2e}")
+        assert err <= 1e-6, (k, err)
+
+
+@pytest.mark.gpu
 def test_cfg1_gmres30_dsa():
     """Slab, 128 P1 cells, S16, GMRES(30)-DSA to 1e-8 (FP64)."""
     import paper_2410_08735_amd as rt
