@@ -266,6 +266,50 @@ def test_fgmres_fp32_with_one_vcycle_dsa_on_partial_tiles():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("precond", ["none", "dsa"])
+@pytest.mark.parametrize("sweep_dtype", ["f64", "f32"])
+def test_fgmres_degenerate_instances_in_one_batch(precond, sweep_dtype):
+    """Degenerate instances beside an ordinary one: a zero right-hand side
+    (no source, no inflow) is solved by phi = 0 with no iteration; a pure
+    absorber (Sigma_s = 0) makes A~ the identity, so phi = b~ = T G~; a
+    problem driven by inflow alone matches the oracle."""
+    import paper_2410_08735_amd as rt
+    normal = tiny_2d(seed=31, nx=9, ny=7, quad=("cl", 8, 4, True), n_regions=3)
+    zero = dict(tiny_2d(seed=32, nx=6, ny=5, quad=("cl", 8, 4, True), n_regions=2))
+    zero["source"] = np.zeros_like(zero["source"])
+    absorber = dict(tiny_2d(seed=33, nx=7, ny=8, quad=("cl", 8, 4, True), n_regions=2))
+    absorber["sigma_t"] = absorber["sigma_t"] - absorber["sigma_s"]
+    absorber["sigma_s"] = np.zeros_like(absorber["sigma_s"])
+    inflow_only = dict(tiny_2d(seed=34, nx=8, ny=6, quad=("cl", 8, 4, True), n_regions=2, inflow=0.5))
+    inflow_only["source"] = np.zeros_like(inflow_only["source"])
+    specs = [normal, zero, absorber, inflow_only]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    f32 = sweep_dtype == "f32"
+    opts = rt.SolveOptions(precond=precond, m=60, max_cycles=10, sweep_dtype=sweep_dtype,
+                           rtol=1e-8 if f32 else 1e-13, dsa_inner_max=2000, dsa_restart=60,
+                           dsa_inner_tol=1e-14)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), opts)
+    assert ret == 0
+    out = B.unpack(phi)
+    print([(s["iterations"], s["cycles"], s["true_relres"]) for s in stats])
+    assert np.all(out[1] == 0.0)
+    assert stats[1]["iterations"] == 0 and stats[1]["true_relres"] == 0.0
+    assert stats[1]["status"] == 0
+    # A~ = I: one iteration per cycle; FP32 cycles need a second, FP64-residual cycle
+    assert stats[2]["status"] == 0
+    assert stats[2]["iterations"] == stats[2]["cycles"] == (2 if f32 else 1), stats[2]
+    b_abs = tr.b_tilde(tr.Problem(absorber))
+    assert rel(out[2], b_abs) <= (1e-8 if f32 else 1e-13)
+    for k in (0, 3):
+        assert stats[k]["status"] == 0 and stats[k]["true_relres"] <= (1e-8 if f32 else 1e-13)
+        ref = _oracle_solve(specs[k], precond, rtol=1e-13)
+        assert rel(out[k], ref.x) <= (1e-6 if f32 else 1e-11), k
+        if not f32:
+            assert abs(stats[k]["iterations"] - ref.iterations) <= 1, (k, stats[k], ref.iterations)
+
+
+@pytest.mark.gpu
 def test_cfg1_gmres30_dsa():
     """Slab, 128 P1 cells, S16, GMRES(30)-DSA to 1e-8 (FP64)."""
     import paper_2410_08735_amd as rt
