@@ -117,6 +117,30 @@ def test_sweep_parity_every_plan():
 
 
 @pytest.mark.gpu
+def test_row_slot_sweep_at_eight_rows_per_slot():
+    """The row-slot kernel at its limit: the tallest grid has exactly 8 rows per
+    slot (64 rows over 8 slots), a shorter one leaves its last slots part
+    empty; one row more is rejected."""
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=41, nx=11, ny=64, quad=("cl", 8, 4, True), n_regions=3, inflow=0.4),
+             tiny_2d(seed=42, nx=5, ny=61, quad=("cl", 6, 2, False), n_regions=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(43)
+    qs = [rng.standard_normal(n) for n in B.ndofs]
+    refs = [_oracle_sweep(spec, qs[k]) for k, spec in enumerate(specs)]
+    for G, opl, T in ((8, 4, 64), (8, 1, 64), (16, 2, 128)):
+        for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+            B.set_sweep_plan(dtype, 1, G, T, opl=opl)
+            phi, _ = rt.sweep(B, st, B.pack(qs), inflow=B.inflow(), phi=True, dtype=dtype)
+            for k in range(len(specs)):
+                assert rel(B.unpack(phi)[k], refs[k][0]) <= tol, (G, opl, T, dtype, k)
+    taller = rt.Batch([tiny_2d(seed=44, nx=4, ny=65, quad=("cl", 8, 4, True))])
+    with pytest.raises(rt.RteError):
+        taller.set_sweep_plan("f32", 1, 8, 64, opl=4)
+
+
+@pytest.mark.gpu
 def test_invalid_sweep_plans_rejected():
     import paper_2410_08735_amd as rt
     B = rt.Batch([tiny_2d(seed=1, nx=40, ny=40, quad=("cl", 8, 4, False))])
