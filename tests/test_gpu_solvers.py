@@ -616,6 +616,45 @@ def test_si_solve_parity(oracle_rom, precond):
 
 
 @pytest.mark.gpu
+def test_zero_right_hand_side_beside_an_ordinary_instance_romsad_and_si(oracle_rom):
+    """A zero right-hand side in a batch with an ordinary instance: FGMRES-ROMSAD
+    and source iteration (DSA, ROMSAD) return phi = 0 for it with no iteration
+    and solve the other as the oracle does."""
+    import torch
+
+    from oracle import si as osi
+
+    import paper_2410_08735_amd as rt
+    specs, U, _ = oracle_rom
+    zero = dict(specs[1], source=np.zeros_like(specs[1]["source"]))
+    test = [specs[0], zero]
+    B = rt.Batch(test)
+    st, ss = B.sigma()
+    rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    P = tr.Problem(specs[0])
+    D = odsa.DSA(P)
+    common = dict(sweep_dtype="f64", rtol=1e-11, dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    runs = [("fgmres", "romsad", rt.SolveOptions(precond="romsad", m=60, max_cycles=5, window=2, **common)),
+            ("si", "dsa", rt.SolveOptions(precond="dsa", max_cycles=400, **common)),
+            ("si", "romsad", rt.SolveOptions(precond="romsad", max_cycles=400, window=1, **common))]
+    for solver, precond, opts in runs:
+        fn = rt.fgmres_solve if solver == "fgmres" else rt.si_solve
+        phi, stats, ret = fn(B, st, ss, B.source(), None, opts, rom=rom if precond == "romsad" else None)
+        assert ret == 0, (solver, precond)
+        out = B.unpack(phi)
+        assert np.all(out[1] == 0.0), (solver, precond)
+        assert stats[1]["iterations"] == 0 and stats[1]["status"] == 0, (solver, precond, stats[1])
+        assert stats[0]["status"] == 0 and stats[0]["true_relres"] <= 1e-11, (solver, precond, stats[0])
+        if solver == "fgmres":
+            ref = _oracle_solve(specs[0], "romsad", rtol=1e-11, U=U, window=2)
+        else:
+            pc = (lambda l, r: D.apply(r)) if precond == "dsa" else orom.Romsad(P, U, D, 1)
+            ref = osi.si(lambda x: tr.A_tilde_apply(P, x), tr.b_tilde(P), pc, rtol=1e-11, max_iter=400)
+        assert abs(stats[0]["iterations"] - ref.iterations) <= 1, (solver, precond, stats[0], ref.iterations)
+        assert rel(out[0], ref.x) <= 1e-9, (solver, precond)
+
+
+@pytest.mark.gpu
 def test_pincell_fgmres_si_comparison_matches_the_paper():
     """Section 5.2's FGMRES / SI comparison (window 1, eps_ROM 1e-7, hardest test
     parameter): the sampled count, the relative residual after the first
