@@ -310,6 +310,39 @@ def test_fgmres_degenerate_instances_in_one_batch(precond, sweep_dtype):
 
 
 @pytest.mark.gpu
+def test_iteration_limit_reports_not_converged():
+    """Out of iterations: FGMRES (one cycle of 3) and SI (2 iterations) return
+    the not-converged warning, per instance and as the call's status, with the
+    iterate reached and its true residual: GMRES(3) after one cycle equals the
+    oracle's, and the reported residual is that of the returned phi."""
+    import paper_2410_08735_amd as rt
+    from paper_2410_08735_amd import _lib
+    specs = [tiny_2d(seed=51, nx=7, ny=6, quad=("cl", 8, 4, True), n_regions=3),
+             tiny_2d(seed=52, nx=5, ny=8, quad=("cl", 6, 2, False), n_regions=2, inflow=0.3)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    common = dict(sweep_dtype="f64", rtol=1e-12, dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    for solver, opts in (("fgmres", rt.SolveOptions(precond="none", m=3, max_cycles=1, **common)),
+                         ("si", rt.SolveOptions(precond="dsa", max_cycles=2, **common))):
+        fn = rt.fgmres_solve if solver == "fgmres" else rt.si_solve
+        phi, stats, ret = fn(B, st, ss, B.source(), B.inflow(), opts)
+        assert ret == _lib.RTE_WNOTCONV, solver
+        out = B.unpack(phi)
+        for k, spec in enumerate(specs):
+            assert stats[k]["status"] == _lib.RTE_WNOTCONV, (solver, k, stats[k])
+            assert stats[k]["iterations"] == (3 if solver == "fgmres" else 2), (solver, k, stats[k])
+            P = tr.Problem(spec)
+            b = tr.b_tilde(P)
+            res = np.linalg.norm(b - tr.A_tilde_apply(P, out[k])) / np.linalg.norm(b)
+            assert res > 1e-12
+            assert abs(stats[k]["true_relres"] - res) <= 1e-9 * res, (solver, k, stats[k], res)
+            if solver == "fgmres":
+                ref = ofg.fgmres(lambda x: tr.A_tilde_apply(P, x), b, lambda j, v: v, m=3, rtol=1e-12,
+                                 max_cycles=1)
+                assert rel(out[k], ref.x) <= 1e-11, k
+
+
+@pytest.mark.gpu
 def test_cfg1_gmres30_dsa():
     """Slab, 128 P1 cells, S16, GMRES(30)-DSA to 1e-8 (FP64)."""
     import paper_2410_08735_amd as rt
