@@ -63,6 +63,89 @@ def test_flexible_arnoldi_relation_and_sweep_count():
     assert all(np.diff(res.history) <= 1e-15)
 
 
+def test_fgmres_restarts_match_library_restarted_gmres():
+    """Restart branch: GMRES(4) for 4 cycles from the true residual of each
+    cycle's end (Alg. 1 with a non-zero initial guess) gives scipy's restarted
+    GMRES iterate and its per-step residual history across the restarts."""
+    P = tr.Problem(tiny_2d(seed=7, nx=3, ny=3, quad=("cl", 4, 2, False)))
+    At = tr.dense_A_tilde(P)
+    b = tr.b_tilde(P)
+    res = fg.fgmres(_At(P), b, lambda j, v: v, m=4, rtol=1e-15, max_cycles=4)
+    hist = []
+    x, _ = spla.gmres(At, b, rtol=1e-15, atol=0.0, restart=4, maxiter=4,
+                      callback=lambda r: hist.append(r), callback_type="pr_norm")
+    assert res.cycles == 4 and res.iterations == 16 and len(hist) == 16
+    np.testing.assert_allclose(res.history, hist, rtol=1e-4, atol=1e-14)
+    assert np.linalg.norm(res.x - x) <= 1e-12 * np.linalg.norm(x)
+    # every restart continues from the previous cycle's iterate: the history
+    # falls through each cycle boundary instead of starting over
+    assert res.history[4] < res.history[3] and res.history[8] < res.history[7]
+
+
+def test_fgmres_lucky_breakdown_pure_absorber():
+    """Breakdown branch: without scattering A~ = I, so the first Arnoldi step
+    gives H_21 = 0 and the cycle ends with one column and phi = b~."""
+    spec = tiny_2d(seed=3, nx=3, ny=3, quad=("cl", 4, 2, True))
+    spec = dict(spec, sigma_s=np.zeros_like(spec["sigma_s"]))
+    P = tr.Problem(spec)
+    b = tr.b_tilde(P)
+    res = fg.fgmres(_At(P), b, lambda j, v: v, m=10, rtol=1e-30, max_cycles=1, keep_first=True)
+    assert res.iterations == 1 and res.first_cycle["j"] == 1
+    assert abs(res.first_cycle["H"][1, 0]) <= 1e-14 * abs(res.first_cycle["H"][0, 0])
+    np.testing.assert_allclose(res.x, b, rtol=0, atol=1e-15 * np.abs(b).max())
+    assert res.true_relres <= 1e-15
+
+
+def test_fgmres_breakdown_on_an_invariant_subspace():
+    """b in a two-dimensional invariant subspace of A: the Krylov space stops
+    growing at step 2, the breakdown test ends the cycle there and the
+    two-column least-squares solve is the exact solution."""
+    n = 12
+    A = np.diag(np.arange(1.0, n + 1.0))
+    Q, _ = np.linalg.qr(np.random.default_rng(11).standard_normal((n, n)))
+    A = Q @ A @ Q.T
+    b = Q[:, 0] + Q[:, 1]
+    res = fg.fgmres(lambda x: A @ x, b, lambda j, v: v, m=10, rtol=1e-30, max_cycles=1, keep_first=True)
+    assert res.iterations == 2 and res.first_cycle["j"] == 2
+    exact = Q[:, 0] + 0.5 * Q[:, 1]
+    np.testing.assert_allclose(res.x, exact, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- Adam (Kingma and Ba)
+def _adam_run(grads, lr=1e-3, p0=0.25):
+    params = [[np.array([[p0]]), np.array([0.0])]]
+    state = {}
+    out = []
+    for g in grads:
+        mlp.adam_step(params, [[np.array([[g]]), np.array([0.0])]], state, lr=lr)
+        out.append(params[0][0][0, 0])
+    return np.array(out)
+
+
+def test_adam_first_step_is_a_signed_lr_step():
+    """Bias correction makes the first update -lr g / (|g| + eps) whatever the
+    gradient's size."""
+    for g in (3.0, -2e-3, 7e5):
+        p = _adam_run([g], lr=1e-2)
+        assert abs((0.25 - p[0]) - 1e-2 * g / (abs(g) + 1e-8)) <= 1e-16
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient the corrected moments are g and g^2 at every
+    step, so each of 6 steps moves the parameter by lr g / (|g| + eps)."""
+    p = _adam_run([0.5] * 6, lr=1e-3)
+    steps = -np.diff(np.concatenate([[0.25], p]))
+    np.testing.assert_allclose(steps, 1e-3 * 0.5 / (0.5 + 1e-8), rtol=1e-12)
+
+
+def test_adam_second_step_by_hand():
+    """g = 1 then g = -1 (beta1 = 0.9, beta2 = 0.999): m_2 = 0.09 - 0.1 = -0.01,
+    m_2 / (1 - 0.81) = -1/19; v_2 = 0.000999 + 0.001 = 0.001999 = 1 - 0.999^2,
+    so the corrected second moment is exactly 1 and the step is +lr/19."""
+    p = _adam_run([1.0, -1.0], lr=1e-2)
+    assert abs((p[1] - p[0]) - 1e-2 / 19.0 / (1.0 + 1e-8)) <= 1e-15
+
+
 # ---------------------------------------------------------------- DSA (App. A)
 @pytest.mark.parametrize("spec", [tiny_1d(nx=7, n_ord=2), tiny_2d(seed=3, nx=4, ny=3, quad=("cl", 3, 2, False))])
 def test_fc_dsa_exact_when_p1_is_exact(spec):
