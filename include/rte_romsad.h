@@ -16,6 +16,11 @@
  *    host-visible results (statistics, reports, ranks) synchronise the stream
  *    before returning.
  *  - Invalid arguments are rejected with RTE_EINVAL before any kernel launch.
+ *    The solvers (fgmres_solve, si_solve, romsad_build_greedy,
+ *    rte_mlp_snapshots) also read the cross sections on the host and reject
+ *    a sigma_t that is not finite and > 0 or a sigma_s that is not finite and
+ *    >= 0; the operator-level calls (rte_sweep, rte_apply_A, rte_rhs,
+ *    rte_dsa_apply, romsad_apply) stay asynchronous and do not read them.
  *  - Opaque handles (rte_batch, rte_rom, rte_mlp) are library-owned and are
  *    released with their destroy call.
  *
@@ -55,6 +60,7 @@ enum {
   RTE_EBREAKDOWN = -4,  /* Krylov breakdown with a singular least squares     */
   RTE_ESINGULAR = -5,   /* singular reduced operator                          */
   RTE_EIO = -6,         /* file read/write failed                             */
+  RTE_ENONFINITE = -7,  /* a non-finite (NaN / Inf) value reached a norm      */
   RTE_WNOTCONV = 1      /* not converged within the iteration limits          */
 };
 
@@ -180,12 +186,30 @@ int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma
  *   RTE_PC_MLP   the learned reduced correction for j <= window with the ROMSAD
  *                correction as fallback and DSA after the window.
  * Stopping: Givens estimate <= rtol * ||b~|| ends a cycle; the FP64 true
- * residual ||b~ - A~ phi|| / ||b~|| <= rtol ends the solve.  sweep_dtype sets
+ * residual ||b~ - A~ phi|| / ||b~|| <= rtol ends the solve.  A breakdown
+ * H_{j+1,j} <= breakdown_tol * ||H(:, j)|| also ends the cycle (Alg. 1 stops
+ * there): it is lucky when the rotated diagonal entry of column j is larger
+ * than breakdown_tol * ||H(:, j)|| (the j-column least squares is solved and
+ * the solve continues from its iterate), unhappy otherwise (the least squares
+ * is singular: column j is dropped, the instance stops with status
+ * RTE_EBREAKDOWN).  sweep_dtype sets
  * the arithmetic of the inner A~ applies.  True residuals are FP64, formed
  * as T (G~ + Sigma_s phi) - phi with RTE_F32 (whose b~, which starts the first
  * cycle and scales the stopping test, comes from an FP32 sweep) and as
  * b~ - A~ phi with an FP64 b~ with RTE_F64.
- * phi (device, packed) receives the solution.  stats (host [n_inst]).        */
+ * phi (device, packed) receives the solution.  stats (host [n_inst]).
+ * Failure conventions (per instance; they never abort the batch):
+ *  - every region's sigma_t must be finite and > 0 and sigma_s finite and
+ *    >= 0 (read on the host before any launch): RTE_EINVAL otherwise;
+ *  - a non-finite ||b~|| or true residual norm stops that instance with
+ *    status RTE_ENONFINITE (its phi is then unspecified); a non-finite Givens
+ *    estimate ends its cycle early;
+ *  - an unhappy breakdown stops it with status RTE_EBREAKDOWN (phi = the
+ *    iterate before the singular column);
+ *  - a singular reduced operator A_r(mu) (pivot below 1e-14 max |A_r|, found
+ *    once per solve) makes that instance use DSA wherever it would use the
+ *    ROM solve, with rom_singular = 1;
+ * the call then returns RTE_WNOTCONV (outputs and statistics written).     */
 typedef struct {
   int32_t precond;       /* RTE_PC_*                                         */
   int32_t m;             /* Krylov dimension per cycle                       */
@@ -207,6 +231,7 @@ typedef struct {
   int32_t dsa_variant;   /* RTE_DSA_FC or RTE_DSA_PC for every DSA application
                             (the DSA preconditioner and ROMSAD after the
                             window); RTE_DSA_PC needs dsa_restart >= 1      */
+  double breakdown_tol;  /* relative breakdown threshold (above); 0 = 1e-14 */
 } rte_solve_opts;
 
 typedef struct {
@@ -215,9 +240,12 @@ typedef struct {
   int32_t sweeps_f32;    /* transport sweeps by precision (b~ included)       */
   int32_t sweeps_f64;
   int32_t pc_rom, pc_dsa, pc_mlp, pc_fallback; /* preconditioner uses        */
-  int32_t status;        /* 0 converged, RTE_WNOTCONV, RTE_EBREAKDOWN         */
+  int32_t status;        /* 0 converged, RTE_WNOTCONV, RTE_EBREAKDOWN,
+                            RTE_ENONFINITE                                   */
   double true_relres;    /* final FP64 ||b~ - A~ phi|| / ||b~||              */
   double est_relres;     /* last Givens estimate / ||b~||                     */
+  int32_t rom_singular;  /* 1: A_r(mu) singular, DSA ran in place of the ROM  */
+  int32_t pad;
 } rte_solve_stats;
 
 int fgmres_solve(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* G,
@@ -336,6 +364,11 @@ int rte_mlp_grad(rte_mlp* m, const float* X, const float* T, int rows, int dtype
  * n rows in shuffled minibatches (SplitMix64-seeded Fisher-Yates).  standardize != 0
  * first sets the output shift/scale to T's column mean and standard deviation.
  * loss_hist (host [epochs], nullable) receives the mean minibatch loss.      */
+/* One Adam step (Kingma and Ba; lr, 0.9, 0.999, 1e-8, bias-corrected with the
+ * network's own step count, which it increments) on the parameters with the
+ * given gradient (device [num_params] FP32), e.g. one from rte_mlp_grad; the
+ * moments are the network's (cleared by init / set_params).                  */
+int rte_mlp_adam_step(rte_mlp* m, const float* grad, float lr, void* stream);
 int rte_mlp_train(rte_mlp* m, const float* X, const float* T, int n, int epochs, int batch,
                   float lr, uint64_t seed, int standardize, float* loss_hist, void* stream);
 /* Training data from FGMRES runs (section 4.4.1): solve every instance with
@@ -365,6 +398,11 @@ int rte_prof_read(int slot, int64_t* launches, double* total_ms, double* total_u
 /* Enqueues an empty kernel (rte::k_region_marker, argument id) on `stream`, so
  * that an external kernel trace can locate a region between two marks.      */
 int rte_prof_mark(int id, void* stream);
+/* Operator applications captured into HIP graphs by fgmres_solve (use_graph)
+ * since the library was loaded: a new capture is made whenever a cached graph
+ * would refer to reallocated buffers (a new sweep plan, grown partial buffers)
+ * or to other arguments.                                                     */
+int64_t rte_graph_captures(void);
 
 #ifdef __cplusplus
 }

@@ -202,7 +202,7 @@ def dsa_apply(batch, sigma_t, sigma_s, v, inner_tol=1e-13, inner_max=2000, resta
 class SolveOptions:
     def __init__(self, precond="dsa", m=30, max_cycles=20, sweep_dtype="f64", rtol=1e-8, window=2,
                  dsa_inner_max=30, dsa_restart=30, dsa_inner_tol=1e-10, window_cycles=0, use_graph=False,
-                 dsa_variant="fc"):
+                 dsa_variant="fc", breakdown_tol=0.0):
         self.precond = {"none": RTE_PC_NONE, "dsa": RTE_PC_DSA, "romsad": RTE_PC_ROMSAD,
                         "mlp": RTE_PC_MLP}[precond] if isinstance(precond, str) else precond
         self.m, self.max_cycles, self.sweep_dtype, self.rtol = m, max_cycles, sweep_dtype, rtol
@@ -211,6 +211,7 @@ class SolveOptions:
         self.window_cycles = window_cycles
         self.use_graph = use_graph
         self.dsa_variant = dsa_variant
+        self.breakdown_tol = breakdown_tol
 
     def c(self):
         o = L.SolveOpts()
@@ -222,6 +223,7 @@ class SolveOptions:
         o.window_cycles = self.window_cycles
         o.use_graph = 1 if self.use_graph else 0
         o.dsa_variant = _DSA_VARIANTS[self.dsa_variant]
+        o.breakdown_tol = self.breakdown_tol
         return o
 
 
@@ -348,6 +350,11 @@ def romsad_apply(rom, batch, sigma_t, sigma_s, v):
     return z
 
 
+def graph_captures():
+    """Operator applications captured into HIP graphs since the library loaded."""
+    return int(L.lib().rte_graph_captures())
+
+
 def prof_enable(on=True):
     check(L.lib().rte_prof_enable(1 if on else 0), "rte_prof_enable")
 
@@ -419,6 +426,10 @@ class Mlp:
         check(L.lib().rte_mlp_grad(self.h, _ptr(X.contiguous()), _ptr(T.contiguous()), int(X.shape[0]),
                                    _dt(dtype), C.byref(loss), _ptr(g), _stream()), "rte_mlp_grad")
         return loss.value, g
+
+    def adam_step(self, grad, lr=1e-3):
+        """One Adam step with a given device gradient (FP32, num_params)."""
+        check(L.lib().rte_mlp_adam_step(self.h, _ptr(grad.contiguous()), lr, _stream()), "rte_mlp_adam_step")
 
     def train(self, X, T, epochs=50, batch=256, lr=1e-3, seed=0, standardize=True):
         hist = np.zeros(epochs, dtype=np.float32)

@@ -10,6 +10,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librte_romsad.so")
 
 RTE_OK, RTE_EINVAL, RTE_EHIP, RTE_ENOMEM, RTE_EBREAKDOWN, RTE_ESINGULAR, RTE_EIO = 0, -1, -2, -3, -4, -5, -6
+RTE_ENONFINITE = -7
 RTE_WNOTCONV = 1
 RTE_F64, RTE_F32, RTE_BF16 = 0, 1, 2
 RTE_PC_NONE, RTE_PC_DSA, RTE_PC_ROMSAD, RTE_PC_MLP = 0, 1, 2, 3
@@ -33,13 +34,14 @@ class SolveOpts(C.Structure):
     _fields_ = [("precond", i32), ("m", i32), ("max_cycles", i32), ("sweep_dtype", i32),
                 ("rtol", dbl), ("window", i32), ("dsa_inner_max", i32), ("dsa_restart", i32),
                 ("dsa_inner_tol", dbl), ("keep_krylov", i32), ("window_cycles", i32),
-                ("use_graph", i32), ("dsa_variant", i32)]
+                ("use_graph", i32), ("dsa_variant", i32), ("breakdown_tol", dbl)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", i32), ("cycles", i32), ("sweeps_f32", i32), ("sweeps_f64", i32),
                 ("pc_rom", i32), ("pc_dsa", i32), ("pc_mlp", i32), ("pc_fallback", i32),
-                ("status", i32), ("true_relres", dbl), ("est_relres", dbl)]
+                ("status", i32), ("true_relres", dbl), ("est_relres", dbl), ("rom_singular", i32),
+                ("pad", i32)]
 
 
 class GreedyReport(C.Structure):
@@ -87,6 +89,8 @@ SIGNATURES = {
     "rte_mlp_get_params": (C.c_int, [vp, vp, vp, vp]),
     "rte_mlp_forward": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, vp]),
     "rte_mlp_grad": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.POINTER(C.c_float), vp, vp]),
+    "rte_mlp_adam_step": (C.c_int, [vp, vp, C.c_float, vp]),
+    "rte_graph_captures": (i64, []),
     "rte_mlp_train": (C.c_int, [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, C.c_uint64, C.c_int,
                                 vp, vp]),
     "rte_mlp_snapshots": (C.c_int, [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.c_int, vp, vp, vp,

@@ -14,6 +14,7 @@ extern "C" const char* rte_status_string(int s) {
     case RTE_EBREAKDOWN: return "Krylov breakdown";
     case RTE_ESINGULAR: return "singular reduced operator";
     case RTE_EIO: return "file I/O error";
+    case RTE_ENONFINITE: return "non-finite value";
     case RTE_WNOTCONV: return "not converged";
     default: return "unknown status";
   }
@@ -260,3 +261,22 @@ extern "C" int64_t rte_batch_psi_offset(const rte_batch* b, int k) {
 }
 extern "C" int64_t rte_batch_total_psi(const rte_batch* b) { return b ? b->total_psi : -1; }
 extern "C" int rte_batch_max_regions(const rte_batch* b) { return b ? b->max_regions : -1; }
+
+namespace rte {
+
+int validate_cross_sections(const rte_batch* b, const double* sigma_t, const double* sigma_s, hipStream_t s) {
+  const size_t n = (size_t)b->n_inst * b->max_regions;
+  std::vector<double> st(n), ss(n);
+  RTE_HIP(hipMemcpyAsync(st.data(), sigma_t, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  if (sigma_s) RTE_HIP(hipMemcpyAsync(ss.data(), sigma_s, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  RTE_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < b->n_inst; ++k)
+    for (int R = 0; R < b->inst[k].n_regions; ++R) {
+      const size_t e = (size_t)k * b->max_regions + R;
+      if (!(std::isfinite(st[e]) && st[e] > 0.0)) return RTE_EINVAL;
+      if (sigma_s && !(std::isfinite(ss[e]) && ss[e] >= 0.0)) return RTE_EINVAL;
+    }
+  return RTE_OK;
+}
+
+}  // namespace rte

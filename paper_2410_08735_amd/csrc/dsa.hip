@@ -1793,7 +1793,8 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
                      bool prep, hipStream_t s) {
   const int n = b->n_inst;
   const int mr = b->max_regions;
-  if (prep) RTE_TRY(prepare(sigma_t, sigma_s, active, s));
+  // every instance's data, so that later calls with other masks find it ready
+  if (prep) RTE_TRY(prepare(sigma_t, sigma_s, nullptr, s));
   // one V-cycle whose finest level sees b only in its single from-zero sweep
   // (formed from v there; only the scalar-flux field is kept for the
   // restriction) and whose fine correction goes straight into z

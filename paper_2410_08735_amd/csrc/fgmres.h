@@ -21,6 +21,7 @@ struct OpGraph {
   hipGraphExec_t exec = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};  // sigma_t, sigma_s, z, w
   int prec = -1, G = 0, threads = 0, variant = -1, opl = 0;
+  uint64_t gen = 0;  // the batch's plan / partial-buffer generation at capture
 };
 
 struct Fgmres {
@@ -30,6 +31,11 @@ struct Fgmres {
   Krylov K;
   double *btil = nullptr, *r = nullptr, *bnorm = nullptr, *tolabs = nullptr, *rnorm = nullptr;
   int32_t *cyc = nullptr, *cyc_step = nullptr, *flags = nullptr;
+  // instances whose reduced operator A_r(mu) is singular (DSA replaces the
+  // ROM solve there), and the split of the activity mask by it
+  int32_t *rsing = nullptr, *m_rom = nullptr, *m_dsa = nullptr;
+  std::vector<int32_t> sing_h;
+  bool any_sing = false;
   // pinned host copies of the activity mask after each Arnoldi step (two in
   // turn) and the events that mark them complete
   int32_t* mask_host = nullptr;
@@ -45,11 +51,14 @@ struct Fgmres {
   int precondition(int jj, int cycle, const double* v, double* z, const SolveCtx& c, hipStream_t s,
                    std::vector<int32_t>& which);
   int solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s);
+  int dsa_step(const double* v, double* z, const int32_t* mask, const SolveCtx& c, hipStream_t s);
   int apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s);
   void graphs_release();
 };
 
 Fgmres* fgmres_for(rte_batch* b, int m);
+// Number of operator applications captured into HIP graphs so far (all batches).
+int64_t graph_capture_count();
 void fgmres_forget(rte_batch* b);
 
 }  // namespace rte

@@ -23,6 +23,9 @@ int Fgmres::init(rte_batch* batch, int m_) {
       hipMalloc(&cyc, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&cyc_step, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&flags, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&rsing, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&m_rom, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&m_dsa, sizeof(int32_t) * n) != hipSuccess ||
       hipHostMalloc(&mask_host, sizeof(int32_t) * 2 * n) != hipSuccess)
     return RTE_ENOMEM;
   for (auto& e : mask_ev) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -33,10 +36,10 @@ void Fgmres::release() {
   graphs_release();
   K.release();
   for (void* p : {(void*)btil, (void*)r, (void*)bnorm, (void*)tolabs, (void*)rnorm, (void*)cyc,
-                  (void*)cyc_step, (void*)flags})
+                  (void*)cyc_step, (void*)flags, (void*)rsing, (void*)m_rom, (void*)m_dsa})
     (void)hipFree(p);
   btil = r = bnorm = tolabs = rnorm = nullptr;
-  cyc = cyc_step = flags = nullptr;
+  cyc = cyc_step = flags = rsing = m_rom = m_dsa = nullptr;
   if (mask_host) (void)hipHostFree(mask_host);
   mask_host = nullptr;
   for (auto& e : mask_ev) {
@@ -56,8 +59,13 @@ void Fgmres::graphs_release() {
 // partial-flux reduction, which also leaves the chunk partials of <w, v_0> in
 // K.partA for the first MGS projection.  With use_graph the pair is captured once per
 // (precision, j) into a HIP graph and replayed; a new capture is made when the
-// cross-section arrays, the plan or the buffers change.  The kernels read the
-// activity mask from device memory, so a replay follows the current mask.
+// cross-section arrays, the plan or the buffers change (the batch's generation
+// counts every reallocation of the plan tables and the partial buffer, whose
+// addresses the graph embeds).  The kernels read the activity mask from
+// device memory, so a replay follows the current mask.
+static int64_t g_graph_captures = 0;
+int64_t graph_capture_count() { return g_graph_captures; }
+
 int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s) {
   if (!use_graph) {
     RTE_TRY(sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, units));
@@ -69,7 +77,7 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double 
   const Plan& p = b->plan[prec];
   const void* key[4] = {c.sigma_t, c.sigma_s, K.z(j), K.v(j + 1)};
   const bool same = g.exec && g.prec == prec && g.G == p.G && g.threads == p.threads && g.variant == p.variant &&
-                    g.opl == p.opl && std::equal(key, key + 4, g.key);
+                    g.opl == p.opl && g.gen == b->gen && std::equal(key, key + 4, g.key);
   if (!same) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
@@ -91,6 +99,8 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double 
       g.exec = nullptr;
       return RTE_EHIP;
     }
+    ++g_graph_captures;
+    g.gen = b->gen;
     g.prec = prec;
     g.G = p.G;
     g.threads = p.threads;
@@ -158,6 +168,20 @@ __global__ void k_stall_check(int n, const double* __restrict__ scal, const int3
   if (prev > 0.0 && est > 0.5 * prev) off[b] = 1;
 }
 
+// Instances with a singular reduced operator take DSA where the ROM solve
+// would run: m_dsa = active & sing & off (off = 1 when not given), m_rom =
+// active & !m_dsa.
+__global__ void k_split_singular(int n, const int32_t* __restrict__ active, const int32_t* __restrict__ sing,
+                                 const int32_t* __restrict__ off, int32_t* __restrict__ m_rom,
+                                 int32_t* __restrict__ m_dsa) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const int a = active[b];
+  const int d = a && sing[b] && (!off || off[b]);
+  m_dsa[b] = d;
+  m_rom[b] = a && !d;
+}
+
 int Fgmres::precondition(int jj, int cycle, const double* v, double* z, const SolveCtx& c, hipStream_t s,
                          std::vector<int32_t>& which) {
   const rte_solve_opts& o = *c.opts;
@@ -169,28 +193,53 @@ int Fgmres::precondition(int jj, int cycle, const double* v, double* z, const So
   switch (kind) {
     case RTE_PC_NONE:
       return kcopy(K.sp, v, z, K.active, s);
-    case RTE_PC_DSA: {
-      const bool prep = !dsa_ready;
-      dsa_ready = true;
-      return dsa_apply(b, c.sigma_t, c.sigma_s, v, z, o.dsa_inner_tol, o.dsa_inner_max,
-                       o.dsa_restart, K.active, nullptr, s, prep, o.dsa_variant);
-    }
+    case RTE_PC_DSA:
+      return dsa_step(v, z, K.active, c, s);
     case RTE_PC_ROMSAD: {
-      int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, K.active, s);
-      return st == RTE_ESINGULAR ? RTE_OK : st;
+      const int32_t* mr = K.active;
+      if (any_sing) {
+        hipLaunchKernelGGL(k_split_singular, dim3((b->n_inst + 63) / 64), dim3(64), 0, s, b->n_inst, K.active,
+                           rsing, nullptr, m_rom, m_dsa);
+        RTE_HIP(hipGetLastError());
+        mr = m_rom;
+      }
+      const int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, mr, s);
+      if (st < 0 && st != RTE_ESINGULAR) return st;
+      if (any_sing) {
+        RTE_TRY(dsa_step(v, z, m_dsa, c, s));
+        for (int q = 0; q < b->n_inst; ++q)
+          if (sing_h[q]) which[q] = RTE_PC_DSA;
+      }
+      return RTE_OK;
     }
     case RTE_PC_MLP: {
       RTE_TRY(mlp_precond(c.mlp, c.rom, b, c.sigma_t, c.sigma_s, c.mu, c.mu_dim, v, z, K.active, s,
                           flags));
+      if (any_sing) {  // a stalled instance whose ROM solve is singular takes DSA
+        hipLaunchKernelGGL(k_split_singular, dim3((b->n_inst + 63) / 64), dim3(64), 0, s, b->n_inst, K.active,
+                           rsing, flags, m_rom, m_dsa);
+        RTE_HIP(hipGetLastError());
+        RTE_TRY(dsa_step(v, z, m_dsa, c, s));
+      }
       std::vector<int32_t> fb(b->n_inst);
       RTE_HIP(hipMemcpyAsync(fb.data(), flags, sizeof(int32_t) * b->n_inst, hipMemcpyDeviceToHost, s));
       RTE_HIP(hipStreamSynchronize(s));
       for (int q = 0; q < b->n_inst; ++q)
-        if (fb[q]) which[q] = -RTE_PC_ROMSAD;  // fell back to the ROM solve
+        if (fb[q]) which[q] = (any_sing && sing_h[q]) ? RTE_PC_DSA : -RTE_PC_ROMSAD;  // fell back
       return RTE_OK;
     }
   }
   return RTE_EINVAL;
+}
+
+// z = M_DSA^{-1} v on the masked instances; the first application of a solve
+// rebuilds the cross-section-dependent multigrid data for every instance.
+int Fgmres::dsa_step(const double* v, double* z, const int32_t* mask, const SolveCtx& c, hipStream_t s) {
+  const rte_solve_opts& o = *c.opts;
+  const bool prep = !dsa_ready;
+  dsa_ready = true;
+  return dsa_apply(b, c.sigma_t, c.sigma_s, v, z, o.dsa_inner_tol, o.dsa_inner_max, o.dsa_restart, mask,
+                   nullptr, s, prep, o.dsa_variant);
 }
 
 int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s) {
@@ -201,6 +250,21 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s, c.sigma_s));
   for (int q = 0; q < n; ++q) stats[q] = rte_solve_stats{};
   dsa_ready = false;  // the DSA hierarchy is rebuilt for this call's cross sections
+  K.bt = o.breakdown_tol > 0.0 ? o.breakdown_tol : 1e-14;
+  RTE_TRY(fill_i32(K.fail, n, 0, s));
+  // A_r(mu) depends on mu only: its singularity is decided once per solve
+  any_sing = false;
+  sing_h.assign(n, 0);
+  if ((o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && c.rom) {
+    RTE_TRY(rom_singular_check(c.rom, b, c.sigma_t, c.sigma_s, rsing, s));
+    RTE_HIP(hipMemcpyAsync(sing_h.data(), rsing, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < n; ++q)
+      if (sing_h[q]) {
+        any_sing = true;
+        stats[q].rom_singular = 1;
+      }
+  }
   std::vector<int32_t> live(n, 1);
   if (c.init_active) {
     RTE_HIP(hipMemcpyAsync(live.data(), c.init_active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
@@ -226,11 +290,14 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   std::vector<double> bn(n), rn(n), sc(8 * n);
   RTE_HIP(hipMemcpyAsync(bn.data(), bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   RTE_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> conv(n, 0);
+  std::vector<int32_t> conv(n, 0), stop(n, 0), fl(n, 0);  // stop: status code of a stopped instance
   for (int q = 0; q < n; ++q) {
     if (!live[q] || bn[q] == 0.0) {
       conv[q] = 1;
       stats[q].true_relres = 0.0;
+    } else if (!std::isfinite(bn[q])) {
+      stop[q] = RTE_ENONFINITE;
+      stats[q].true_relres = bn[q];
     }
   }
   std::vector<int32_t> act(n), which;
@@ -239,7 +306,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     std::vector<int32_t> cm(n);
     int n_live = 0;
     for (int q = 0; q < n; ++q) {
-      cm[q] = conv[q] ? 0 : 1;
+      cm[q] = (conv[q] || stop[q]) ? 0 : 1;
       n_live += cm[q];
     }
     if (!n_live) break;
@@ -340,21 +407,25 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
     RTE_HIP(hipMemcpyAsync(rn.data(), rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipMemcpyAsync(sc.data(), K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipMemcpyAsync(fl.data(), K.fail, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
     bool all = true;
     for (int q = 0; q < n; ++q) {
-      if (!cm[q]) continue;
-      stats[q].sweeps_f64 += 1;
-      stats[q].true_relres = rn[q] / bn[q];
-      stats[q].est_relres = sc[8 * q + 2] / bn[q];
-      if (stats[q].true_relres <= o.rtol) conv[q] = 1;
-      all = all && conv[q];
+      if (cm[q]) {
+        stats[q].sweeps_f64 += 1;
+        stats[q].true_relres = rn[q] / bn[q];
+        stats[q].est_relres = sc[8 * q + 2] / bn[q];
+        if (!std::isfinite(rn[q]) || fl[q] == KFAIL_NONFINITE) stop[q] = RTE_ENONFINITE;
+        else if (stats[q].true_relres <= o.rtol) conv[q] = 1;
+        else if (fl[q] == KFAIL_BREAKDOWN) stop[q] = RTE_EBREAKDOWN;
+      }
+      all = all && (conv[q] || stop[q]);
     }
     if (all) break;
   }
   int ret = RTE_OK;
   for (int q = 0; q < n; ++q) {
-    stats[q].status = conv[q] ? RTE_OK : RTE_WNOTCONV;
+    stats[q].status = conv[q] ? RTE_OK : (stop[q] ? stop[q] : RTE_WNOTCONV);
     if (!conv[q]) ret = RTE_WNOTCONV;
   }
   return ret;
@@ -412,6 +483,8 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
   if (rom && !rte::rom_matches(rom, b)) return RTE_EINVAL;
   if (o.precond == RTE_PC_MLP && rom && rom->is_set()) return RTE_EINVAL;  // one network per ROM basis
   if (o.precond == RTE_PC_MLP && (!mlp || !mu || mu_dim < 1)) return RTE_EINVAL;
+  if (!(o.breakdown_tol >= 0.0) || o.breakdown_tol >= 1e3) return RTE_EINVAL;
+  RTE_TRY(rte::validate_cross_sections(b, sigma_t, sigma_s, reinterpret_cast<hipStream_t>(stream)));
   rte::Fgmres* f = rte::fgmres_for(b, o.m);
   if (!f) return RTE_ENOMEM;
   rte::SolveCtx c{};
@@ -426,3 +499,5 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
   c.mu_dim = mu_dim;
   return f->solve(c, phi, stats, reinterpret_cast<hipStream_t>(stream));
 }
+
+extern "C" int64_t rte_graph_captures(void) { return rte::graph_capture_count(); }

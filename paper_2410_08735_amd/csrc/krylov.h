@@ -8,6 +8,10 @@ namespace rte {
 
 constexpr int KCHUNK = 4096;   // elements per work group in reductions
 constexpr int KTHREADS = 256;
+// Krylov::fail codes: an unhappy breakdown (singular least squares at a
+// breakdown: the column is dropped), a non-finite estimate (column dropped).
+constexpr int KFAIL_BREAKDOWN = 1;
+constexpr int KFAIL_NONFINITE = 2;
 
 // A family of per-instance vectors: instance b occupies [off[b], off[b]+len[b]).
 struct Space {
@@ -39,6 +43,8 @@ struct Krylov {
   double* scal = nullptr;   // [n][8]: 0 beta, 1 tol_abs, 2 est, 3 wnorm_pre, 4 tmp
   int32_t* active = nullptr;  // [n] 1 = iterate in this cycle
   int32_t* jdone = nullptr;   // [n] columns built in this cycle
+  int32_t* fail = nullptr;    // [n] 0, KFAIL_BREAKDOWN or KFAIL_NONFINITE (sticky)
+  double bt = 1e-14;          // breakdown: H_{j+1,j} <= bt ||H(:, j)||
   int init(const std::vector<int64_t>& lens, int m, bool flexible);
   void release();
   double* v(int j) const { return V + (int64_t)j * sp.total; }

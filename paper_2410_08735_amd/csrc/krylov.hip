@@ -49,8 +49,9 @@ int Krylov::init(const std::vector<int64_t>& lens, int m_, bool flex) {
             al((void**)&partA, sizeof(double) * n * mc) &&
             al((void**)&partB, sizeof(double) * n * mc) &&
             al((void**)&scal, sizeof(double) * n * 8) && al((void**)&active, sizeof(int32_t) * n) &&
-            al((void**)&jdone, sizeof(int32_t) * n);
+            al((void**)&jdone, sizeof(int32_t) * n) && al((void**)&fail, sizeof(int32_t) * n);
   if (!ok) return RTE_ENOMEM;
+  RTE_HIP(hipMemset(fail, 0, sizeof(int32_t) * n));
   RTE_HIP(hipMemset(H, 0, sizeof(double) * n * (m + 1) * m));
   RTE_HIP(hipMemset(scal, 0, sizeof(double) * n * 8));
   return RTE_OK;
@@ -58,10 +59,10 @@ int Krylov::init(const std::vector<int64_t>& lens, int m_, bool flex) {
 
 void Krylov::release() {
   for (void* p : {(void*)V, (void*)Z, (void*)H, (void*)R, (void*)cs, (void*)sn, (void*)g, (void*)y,
-                  (void*)partA, (void*)partB, (void*)scal, (void*)active, (void*)jdone})
+                  (void*)partA, (void*)partB, (void*)scal, (void*)active, (void*)jdone, (void*)fail})
     (void)hipFree(p);
   V = Z = H = R = cs = sn = g = y = partA = partB = scal = nullptr;
-  active = jdone = nullptr;
+  active = jdone = fail = nullptr;
   sp.release();
 }
 
@@ -213,11 +214,16 @@ __global__ void k_arnoldi_tail(int n, const int64_t* __restrict__ len, const dou
 }
 
 // Givens update of column j; est = |g_{j+1}|; stop the instance when
-// est <= tol_abs or on a (lucky) breakdown H_{j+1,j} <= 1e-14 ||w_before||.
+// est <= tol_abs or on a breakdown H_{j+1,j} <= bt ||H(:, j)|| (Alg. 1 ends
+// there).  A breakdown whose rotated diagonal entry rho is not above
+// bt ||H(:, j)|| leaves the least squares singular (unhappy breakdown): column
+// j is dropped and fail = KFAIL_BREAKDOWN.  A non-finite rho or estimate
+// drops the column as well (fail = KFAIL_NONFINITE), so the update keeps the
+// last finite iterate.
 __global__ void k_givens(int n, const double* __restrict__ H, double* __restrict__ R,
                          double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
                          int m, int j, double* __restrict__ scal, int32_t* __restrict__ active,
-                         int32_t* __restrict__ jdone) {
+                         int32_t* __restrict__ jdone, int32_t* __restrict__ fail, double bt) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n || !active[b]) return;
   const double* Hb = H + (int64_t)b * (m + 1) * m;
@@ -250,11 +256,23 @@ __global__ void k_givens(int n, const double* __restrict__ H, double* __restrict
   gb[j] = cj * gj;
   gb[j + 1] = -sj * gj;
   const double est = fabs(gb[j + 1]);
+  const double cn = sqrt(colsq);
+  const bool finite = isfinite(rho) && isfinite(est) && isfinite(cn);
+  const bool breakdown = Hb[(j + 1) * m + j] <= bt * cn;
+  const bool unhappy = finite && breakdown && !(rho > bt * cn);
   scal[b * 8 + 5] = scal[b * 8 + 2];  // previous estimate
+  if (!finite || unhappy) {
+    // the least squares keeps columns 0 .. j-1, whose residual is |g_j| before this rotation
+    jdone[b] = j;
+    scal[b * 8 + 2] = fabs(gj);
+    gb[j] = gj;
+    fail[b] = finite ? KFAIL_BREAKDOWN : KFAIL_NONFINITE;
+    active[b] = 0;
+    return;
+  }
   scal[b * 8 + 2] = est;
   jdone[b] = j + 1;
-  const bool breakdown = Hb[(j + 1) * m + j] <= 1e-14 * sqrt(colsq);
-  if (est <= scal[b * 8 + 1] || breakdown || rho == 0.0) active[b] = 0;
+  if (est <= scal[b * 8 + 1] || breakdown) active[b] = 0;
 }
 
 __global__ void k_backsolve(int n, const double* __restrict__ R, const double* __restrict__ g, int m,
@@ -405,7 +423,7 @@ int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready) {
                      K.H, K.m, j, K.scal, K.active);
   RTE_TRY(kscale(sp, w, K.scal + 4, 8, w, K.active, s));
   hipLaunchKernelGGL(k_givens, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, K.H, K.R, K.cs, K.sn,
-                     K.g, K.m, j, K.scal, K.active, K.jdone);
+                     K.g, K.m, j, K.scal, K.active, K.jdone, K.fail, K.bt);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }

@@ -488,6 +488,18 @@ extern "C" int rte_mlp_grad(rte_mlp* m, const float* X, const float* T, int rows
   return RTE_OK;
 }
 
+extern "C" int rte_mlp_adam_step(rte_mlp* m, const float* grad, float lr, void* stream) {
+  if (!m || !grad || !(lr > 0.f)) return RTE_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  m->adam_t++;
+  const float c1 = 1.f - std::pow(b1, (float)m->adam_t), c2 = 1.f - std::pow(b2, (float)m->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3(1024), dim3(256), 0, s, m->nparams, m->P, grad, m->M, m->V, lr, b1, b2, eps, c1,
+                     c2);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
 // SplitMix64 (Steele, Lea and Flood), used for the epoch shuffles
 static uint64_t splitmix64(uint64_t& x) {
   uint64_t z = (x += 0x9E3779B97F4A7C15ull);
@@ -696,6 +708,7 @@ extern "C" int rte_mlp_snapshots(const rte_batch* cb, const double* sigma_t, con
       opts->precond == RTE_PC_MLP)
     return RTE_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  RTE_TRY(validate_cross_sections(b, sigma_t, sigma_s, s));
   const int n = b->n_inst, w = opts->window, r = rom->r;
   Fgmres* f = fgmres_for(b, opts->m);
   if (!f) return RTE_ENOMEM;

@@ -44,6 +44,9 @@ int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_
                           hipStream_t s, double* gout = nullptr, double* cout = nullptr,
                           int32_t* singular = nullptr);
 bool rom_matches(const rte_rom* rom, const rte_batch* b);
+// sing[b] (device [n_inst]) = 1 where the reduced operator A_r(mu_b) is singular
+int rom_singular_check(const rte_rom* rom, rte_batch* b, const double* sigma_t, const double* sigma_s,
+                       int32_t* sing, hipStream_t s);
 // z = v + W_w c for given coefficients c [n][rcap] (no solve)
 int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c, double* z,
              const int32_t* active, hipStream_t s);

@@ -915,6 +915,24 @@ int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_
   return rom_lift(rom, b, v, c, z, active, s);
 }
 
+// sing[b] = 1 where A_r(mu_b) has a pivot below 1e-14 max |A_r| (the test of
+// k_rom_solve), for every instance; the operator depends on mu only, so one
+// factorisation (with a zero right-hand side) per solve decides it.
+int rom_singular_check(const rte_rom* rom, rte_batch* b, const double* sigma_t, const double* sigma_s,
+                       int32_t* sing, hipStream_t s) {
+  RTE_HIP(hipMemsetAsync(sing, 0, sizeof(int32_t) * b->n_inst, s));
+  if (rom_max_rank(rom) == 0) return RTE_OK;
+  RomScratch* sc = scratch_for(b, rom_part_elems(b, rom_max_ndof(rom)));
+  if (!sc) return RTE_ENOMEM;
+  const RomDev* tab = rom_table(rom, sc, b, s);
+  if (!tab) return RTE_EHIP;
+  RTE_HIP(hipMemsetAsync(sc->g, 0, sizeof(double) * b->n_inst * ROM_RMAX, s));
+  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, tab, sigma_t, sigma_s,
+                     b->max_regions, sc->g, sc->c, ROM_RMAX, sing, nullptr);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
 }  // namespace rte
 
 // ------------------------------------------------------------------ C ABI
@@ -1144,6 +1162,7 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
       (int64_t)n_giter * window > ROM_RMAX || !b->uniform || b->inst[0].n_regions > ROM_REGMAX)
     return RTE_EINVAL;
   hipStream_t s = as_stream(stream);
+  RTE_TRY(validate_cross_sections(b, sigma_t, sigma_s, s));
   const int n = b->n_inst;
   double t_step[5] = {0, 0, 0, 0, 0};
   auto* rom = new rte_rom();

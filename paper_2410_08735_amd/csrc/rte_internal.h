@@ -97,19 +97,28 @@ struct rte_batch {
   int64_t part_capacity = 0;
   bool uniform = true;      // every instance has the same grid and ordinates
   int dim = 2;
+  // bumped whenever a plan's device tables or the partial buffer are
+  // (re)allocated: captured graphs that embed their addresses are stale then
+  uint64_t gen = 1;
 };
 
 namespace rte {
 
 int ensure_partials(rte_batch* b, int64_t elems);
+// RTE_EINVAL unless every region of every instance has a finite sigma_t > 0
+// and a finite sigma_s >= 0 (reads both device arrays on the host; syncs s).
+int validate_cross_sections(const rte_batch* b, const double* sigma_t, const double* sigma_s, hipStream_t s);
 int make_plan(rte_batch* b, int prec, int G, int threads, int opl = 1);
 int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int threads);
 // prof_units: cell-ordinates processed by this launch (for the event profiler);
 // -1 = every instance of the batch; below -1.5 = no profiler events (used
-// while a stream is being captured into a graph).
+// while a stream is being captured into a graph).  part_buf: where the
+// partial scalar fluxes go (plan.part_elems entries of the sweep's precision);
+// null = the batch's own buffer.
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
-                 hipStream_t s, const int32_t* active = nullptr, double prof_units = -1.0);
+                 hipStream_t s, const int32_t* active = nullptr, double prof_units = -1.0,
+                 void* part_buf = nullptr);
 
 // Event profiler: per-slot HIP event pairs around kernel launches.
 enum { PROF_SWEEP_F64 = 0, PROF_SWEEP_F32 = 1, PROF_DSA_OP = 2, PROF_MGS = 3, PROF_ROM = 4,
@@ -131,7 +140,7 @@ int reduce_partials_dot(rte_batch* b, int prec, double alpha, const double* x, d
                         const int32_t* active);
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
                     hipStream_t s, const int32_t* active = nullptr, const double* y = nullptr,
-                    double gamma = 0.0);
+                    double gamma = 0.0, const void* part_buf = nullptr);
 // sigma_s (nullable): time the plans on the operator's sigma_s-scaled source
 int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
                    const double* sigma_s = nullptr);

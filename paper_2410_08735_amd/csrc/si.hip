@@ -83,6 +83,7 @@ extern "C" int si_solve(const rte_batch* cb, const double* sigma_t, const double
     return RTE_EINVAL;
   if (o.precond == RTE_PC_ROMSAD && (!rom || !rom_matches(rom, b))) return RTE_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  RTE_TRY(validate_cross_sections(b, sigma_t, sigma_s, s));
   SiWork* w = si_for(b);
   if (!w) return RTE_ENOMEM;
   const int n = b->n_inst;

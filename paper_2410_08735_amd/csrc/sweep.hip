@@ -727,6 +727,7 @@ int ensure_partials(rte_batch* b, int64_t elems) {
   (void)hipFree(b->d_part);
   b->d_part = nullptr;
   b->part_capacity = 0;
+  ++b->gen;
   if (hipMalloc(&b->d_part, sizeof(double) * elems) != hipSuccess) return RTE_ENOMEM;
   b->part_capacity = elems;
   return RTE_OK;
@@ -769,6 +770,7 @@ int make_plan(rte_batch* b, int prec, int G, int threads, int opl) {
   }
   p.part_elems = off;
   p.n_items = (int)p.items.size();
+  ++b->gen;
   (void)hipFree(p.d_items);
   (void)hipFree(p.d_parts);
   p.d_items = nullptr;
@@ -804,7 +806,7 @@ static size_t sweep_lds(const rte_batch* b, int G, int opl, int variant, size_t 
 template <typename real, int G, int OPL>
 static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const double* sigma_s,
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
-                    hipStream_t s, const int32_t* active) {
+                    hipStream_t s, const int32_t* active, void* part) {
   const int per_xcd = (p.n_items + 7) / 8;
   if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, OPL, p.threads)) {
     const int slots = p.threads / G;
@@ -815,7 +817,7 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
 #define RTE_ROWS_LAUNCH(R, SC)                                                                               \
   hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, OPL, R, SC>), dim3(8 * per_xcd), dim3(p.threads), lds, s,  \
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t,        \
-                     sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(b->d_part), psi_out,      \
+                     sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(part), psi_out,           \
                      active, p.n_items, per_xcd)
     if (qx) {
       if (nr <= 2) RTE_ROWS_LAUNCH(2, true);
@@ -835,7 +837,7 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
   hipLaunchKernelGGL((sweep2d_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(p.threads), lds, s,
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
                      sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
-                     reinterpret_cast<real*>(b->d_part), psi_out, active, p.n_items, per_xcd);
+                     reinterpret_cast<real*>(part), psi_out, active, p.n_items, per_xcd);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }
@@ -849,45 +851,46 @@ static bool plan_shape_ok(int G, int opl) {
 template <typename real>
 static int launch2d_g(rte_batch* b, const Plan& p, const double* st, const double* ss,
                       const double* qx, const double* qa, const double* inf, double* psi,
-                      hipStream_t s, const int32_t* act) {
+                      hipStream_t s, const int32_t* act, void* part) {
   if (p.opl == 4) {
     switch (p.G) {
-      case 4: return launch2d<real, 4, 4>(b, p, st, ss, qx, qa, inf, psi, s, act);
-      case 8: return launch2d<real, 8, 4>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      case 4: return launch2d<real, 4, 4>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+      case 8: return launch2d<real, 8, 4>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
       default: return RTE_EINVAL;
     }
   }
   if (p.opl == 2) {
     switch (p.G) {
-      case 4: return launch2d<real, 4, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
-      case 8: return launch2d<real, 8, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
-      case 16: return launch2d<real, 16, 2>(b, p, st, ss, qx, qa, inf, psi, s, act);
+      case 4: return launch2d<real, 4, 2>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+      case 8: return launch2d<real, 8, 2>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+      case 16: return launch2d<real, 16, 2>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
       default: return RTE_EINVAL;
     }
   }
   switch (p.G) {
-    case 1: return launch2d<real, 1, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 2: return launch2d<real, 2, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 4: return launch2d<real, 4, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 8: return launch2d<real, 8, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 16: return launch2d<real, 16, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
-    case 32: return launch2d<real, 32, 1>(b, p, st, ss, qx, qa, inf, psi, s, act);
+    case 1: return launch2d<real, 1, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    case 2: return launch2d<real, 2, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    case 4: return launch2d<real, 4, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    case 8: return launch2d<real, 8, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    case 16: return launch2d<real, 16, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    case 32: return launch2d<real, 32, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
     default: return RTE_EINVAL;
   }
 }
 
 static int sweep_launch_impl(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                              const double* qx, const double* qadd, const double* inflow,
-                             double* psi_out, hipStream_t s, const int32_t* active);
+                             double* psi_out, hipStream_t s, const int32_t* active, void* part);
 
 int sweep_launch(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                  const double* qx, const double* qadd, const double* inflow, double* psi_out,
-                 hipStream_t s, const int32_t* active, double prof_units) {
+                 hipStream_t s, const int32_t* active, double prof_units, void* part_buf) {
+  void* part = part_buf ? part_buf : b->d_part;
   if (!prof_enabled() || prof_units < -1.5)
-    return sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+    return sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active, part);
   const int slot = prec == 0 ? PROF_SWEEP_F64 : PROF_SWEEP_F32;
   prof_begin(slot, s);
-  const int st = sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+  const int st = sweep_launch_impl(b, prec, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active, part);
   prof_end(slot, s, prof_units >= 0.0 ? prof_units : batch_cell_ordinates(b, nullptr));
   return st;
 }
@@ -901,7 +904,7 @@ double batch_cell_ordinates(const rte_batch* b, const int32_t* mask) {
 
 static int sweep_launch_impl(rte_batch* b, int prec, const double* sigma_t, const double* sigma_s,
                              const double* qx, const double* qadd, const double* inflow,
-                             double* psi_out, hipStream_t s, const int32_t* active) {
+                             double* psi_out, hipStream_t s, const int32_t* active, void* part) {
   const Plan& p = b->plan[prec];
   if (b->dim == 1) {
     if (b->max_ord > 1024) return RTE_EINVAL;
@@ -909,34 +912,35 @@ static int sweep_launch_impl(rte_batch* b, int prec, const double* sigma_t, cons
     if (prec == 0)
       hipLaunchKernelGGL(sweep1d_kernel<double>, dim3(b->n_inst), dim3(threads), 0, s, b->d_inst,
                          p.d_parts, b->d_ox, b->d_w, b->d_perm, b->d_region, sigma_t, sigma_s,
-                         b->max_regions, qx, qadd, inflow, reinterpret_cast<double*>(b->d_part),
+                         b->max_regions, qx, qadd, inflow, reinterpret_cast<double*>(part),
                          psi_out, active);
     else
       hipLaunchKernelGGL(sweep1d_kernel<float>, dim3(b->n_inst), dim3(threads), 0, s, b->d_inst,
                          p.d_parts, b->d_ox, b->d_w, b->d_perm, b->d_region, sigma_t, sigma_s,
-                         b->max_regions, qx, qadd, inflow, reinterpret_cast<float*>(b->d_part),
+                         b->max_regions, qx, qadd, inflow, reinterpret_cast<float*>(part),
                          psi_out, active);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
   if (prec == 0)
-    return launch2d_g<double>(b, p, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
-  return launch2d_g<float>(b, p, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active);
+    return launch2d_g<double>(b, p, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active, part);
+  return launch2d_g<float>(b, p, sigma_t, sigma_s, qx, qadd, inflow, psi_out, s, active, part);
 }
 
 int reduce_partials(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
-                    hipStream_t s, const int32_t* active, const double* y, double gamma) {
+                    hipStream_t s, const int32_t* active, const double* y, double gamma, const void* part_buf) {
   const Plan& p = b->plan[prec];
+  const void* part = part_buf ? part_buf : b->d_part;
   int64_t maxnd = 0;
   for (const auto& I : b->inst) maxnd = std::max<int64_t>(maxnd, (int64_t)I.nx * I.ny * I.nloc);
   dim3 grid((unsigned)std::min<int64_t>((maxnd + 255) / 256, 1024), b->n_inst);
   if (prec == 0)
     hipLaunchKernelGGL(reduce_partials_kernel<double>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
-                       reinterpret_cast<const double*>(b->d_part), alpha, x, beta, y, gamma, out,
+                       reinterpret_cast<const double*>(part), alpha, x, beta, y, gamma, out,
                        active);
   else
     hipLaunchKernelGGL(reduce_partials_kernel<float>, grid, dim3(256), 0, s, b->d_inst, p.d_parts,
-                       reinterpret_cast<const float*>(b->d_part), alpha, x, beta, y, gamma, out,
+                       reinterpret_cast<const float*>(part), alpha, x, beta, y, gamma, out,
                        active);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
