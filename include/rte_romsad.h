@@ -139,6 +139,21 @@ int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out);
 int rte_sweep(const rte_batch* b, const double* sigma_t, const double* q, const double* inflow,
               double* phi_out, double* psi_out, int dtype, void* stream);
 
+/* rte_sweep_noalloc: rte_sweep with phi_out only (psi is not stored), for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  It allocates
+ * nothing: the partial scalar fluxes go to a static 64 MiB device array that
+ * each GPU the library runs on holds until the process ends, and it does not
+ * autotune (it launches the batch's current plan: the default one, one set
+ * with rte_batch_set_sweep_plan, or one an earlier rte_sweep tuned).
+ * RTE_EINVAL (nothing launched, a message on stderr) when the plan's partial
+ * fluxes exceed 64 MiB (entries = sum over instances of ndof times the
+ * ordinate blocks of the plan; FP64 8 B, FP32 4 B each).  Every call
+ * overwrites the part of the array it uses before reading it; calls that
+ * overlap on one GPU (other streams or threads) share the array and race.   */
+int rte_sweep_noalloc(const rte_batch* b, const double* sigma_t, const double* q, const double* inflow,
+                      double* phi_out, int dtype, void* stream);
+
 /* rte_scalar_flux: phi = sum_j w_j psi_j for stored angular fluxes (the
  * discrete integration operator Q of section 2.3).                            */
 int rte_scalar_flux(const rte_batch* b, const double* psi, double* phi_out, void* stream);

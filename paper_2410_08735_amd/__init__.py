@@ -166,6 +166,13 @@ def sweep(batch, sigma_t, q, inflow=None, phi=True, psi=False, dtype="f64"):
     return phi_t, psi_t
 
 
+def sweep_noalloc(batch, sigma_t, q, phi, inflow=None, dtype="f64"):
+    """rte_sweep_noalloc into the caller's phi (the library allocates nothing)."""
+    check(L.lib().rte_sweep_noalloc(batch.h, _ptr(sigma_t), _ptr(q), _ptr(inflow), _ptr(phi), _dt(dtype),
+                                    _stream()), "rte_sweep_noalloc")
+    return phi
+
+
 def scalar_flux(batch, psi):
     out = batch.zeros()
     check(L.lib().rte_scalar_flux(batch.h, _ptr(psi), _ptr(out), _stream()), "rte_scalar_flux")

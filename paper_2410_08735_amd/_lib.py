@@ -64,6 +64,7 @@ SIGNATURES = {
     "rte_batch_total_psi": (i64, [vp]),
     "rte_batch_max_regions": (C.c_int, [vp]),
     "rte_sweep": (C.c_int, [vp, vp, vp, vp, vp, vp, C.c_int, vp]),
+    "rte_sweep_noalloc": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, vp]),
     "rte_scalar_flux": (C.c_int, [vp, vp, vp, vp]),
     "rte_apply_A": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, vp]),
     "rte_rhs": (C.c_int, [vp, vp, vp, vp, vp, C.c_int, vp]),
