@@ -139,6 +139,34 @@ def sigma_matrix(mesh, sigma_cell):
     return sp.csr_matrix((V.ravel(), (R.ravel(), C.ravel())), shape=(mesh.ndof, mesh.ndof))
 
 
+def field_matrix(mesh, func, nq=6):
+    """(Sigma)_{kl} = sum_i int_{T_i} f eta_k eta_l for a cross section f(x, y)
+    that varies inside the cells (section 5.3), each cell integrated with the
+    nq x nq Gauss-Legendre product rule (nq = 6 is exact for polynomials of
+    degree 10 per axis: f of degree 8 times the degree-2 products of the
+    basis)."""
+    xq, wq = np.polynomial.legendre.leggauss(nq)
+    if mesh.dim == 1:
+        sx, sy, w = xq, np.zeros_like(xq), wq * mesh.hx / 2
+    else:
+        SX, SY = np.meshgrid(xq, xq, indexing="xy")
+        sx, sy = SX.ravel(), SY.ravel()
+        w = np.outer(wq, wq).ravel() * (mesh.hx / 2) * (mesh.hy / 2)
+    B = _basis_at(mesh, sx, sy)
+    i, k = _cells(mesh)
+    x0, _, y0, _ = mesh.box
+    X = x0 + (i[:, None] + 0.5 + 0.5 * sx[None]) * mesh.hx
+    Y = (y0 + (k[:, None] + 0.5 + 0.5 * sy[None]) * mesh.hy) if mesh.dim == 2 else 0 * X
+    F = func(X, Y)                                   # [ncell, npts]
+    V = np.einsum("cq,kq,lq->ckl", F * w[None], B, B)  # [ncell, nloc, nloc]
+    c = np.arange(mesh.ncell)
+    nl = mesh.nloc
+    R = (c[:, None, None] * nl + np.arange(nl)[None, :, None])
+    C = (c[:, None, None] * nl + np.arange(nl)[None, None, :])
+    R, C = np.broadcast_arrays(R, C)
+    return sp.csr_matrix((V.ravel(), (R.ravel(), C.ravel())), shape=(mesh.ndof, mesh.ndof))
+
+
 def advection(mesh, ox, oy):
     """(D_j)_{kl} = -sum_i int_{T_i} (Omega . grad eta_k) eta_l
                     + sum over cell faces not on the inflow boundary of

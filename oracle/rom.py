@@ -62,21 +62,26 @@ class Romsad:
 
 
 def affine_terms(P, U, n_regions):
-    """Region-wise affine pieces of U^T A(mu) U for piecewise-constant cross
-    sections (eq. of the affine assumption with a_s(mu) = sigma_{t,R},
-    sigma_{s,R}):  U^T A U = A_D + sum_R sigma_{t,R} G_R - sum_R sigma_{s,R} S_R,
-    A_D = sum_j U_j^T D_j U_j, G_R = sum_j U_j^T M_R U_j, S_R = W_1^T M_R W_w,
-    M_R the mass matrix restricted to region R."""
+    """Affine pieces of U^T A(mu) U (eq. of the affine assumption):
+    U^T A U = A_D + sum_R a_{t,R} G_R - sum_R a_{s,R} S_R,
+    A_D = sum_j U_j^T D_j U_j, G_R = sum_j U_j^T M_R U_j, S_R = W_1^T M_R W_w.
+    Piecewise-constant cross sections: a = sigma_{t,R}, sigma_{s,R} and M_R the
+    mass matrix restricted to region R.  Cross sections varying inside the
+    cells (section 5.3): a = the coefficients of the shape functions s_R and
+    M_R the mass matrix weighted by s_R."""
     from . import dg
-    region = np.asarray(P.spec["region"])
     r = U.shape[0]
     AD = np.zeros((r, r))
     for j in range(P.nord):
         AD += U[:, j, :] @ (P.D(j) @ U[:, j, :].T)
     Gs, Ss = [], []
     w1, ww = W1(U), Ww(P, U)
-    for R in range(n_regions):
-        MR = dg.sigma_matrix(P.mesh, (region == R).astype(np.float64))
+    if "sigma_fields" in P.spec:
+        mats = P.field_mats
+    else:
+        region = np.asarray(P.spec["region"])
+        mats = [dg.sigma_matrix(P.mesh, (region == R).astype(np.float64)) for R in range(n_regions)]
+    for MR in mats:
         Gs.append(sum(U[:, j, :] @ (MR @ U[:, j, :].T) for j in range(P.nord)))
         Ss.append(w1 @ (MR @ ww.T))
     return AD, np.array(Gs), np.array(Ss)

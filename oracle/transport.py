@@ -25,11 +25,21 @@ class Problem:
         self.mesh = dg.Mesh.of(spec)
         self.ox, self.oy, self.w = make_rule(spec["quad"])
         self.nord = len(self.w)
-        region = np.asarray(spec["region"])
-        self.sig_t_cell = np.asarray(spec["sigma_t"], dtype=np.float64)[region]
-        self.sig_s_cell = np.asarray(spec["sigma_s"], dtype=np.float64)[region]
-        self.St = dg.sigma_matrix(self.mesh, self.sig_t_cell)
-        self.Ss = dg.sigma_matrix(self.mesh, self.sig_s_cell)
+        if "sigma_fields" in spec:
+            # cross sections that vary inside the cells (section 5.3): sigma_t(x) =
+            # sum_f theta_t,f s_f(x), sigma_s(x) = sum_f theta_s,f s_f(x) with the
+            # shape functions s_f and coefficients sigma_t / sigma_s of the spec
+            self.field_mats = [dg.field_matrix(self.mesh, f) for f in spec["sigma_fields"]]
+            tt = np.asarray(spec["sigma_t"], dtype=np.float64)
+            ts = np.asarray(spec["sigma_s"], dtype=np.float64)
+            self.St = sum(t * M for t, M in zip(tt, self.field_mats))
+            self.Ss = sum(t * M for t, M in zip(ts, self.field_mats))
+        else:
+            region = np.asarray(spec["region"])
+            self.sig_t_cell = np.asarray(spec["sigma_t"], dtype=np.float64)[region]
+            self.sig_s_cell = np.asarray(spec["sigma_s"], dtype=np.float64)[region]
+            self.St = dg.sigma_matrix(self.mesh, self.sig_t_cell)
+            self.Ss = dg.sigma_matrix(self.mesh, self.sig_s_cell)
         self.G = np.asarray(spec["source"], dtype=np.float64)
         self.g = spec.get("inflow", 0.0)
         self._D = [None] * self.nord

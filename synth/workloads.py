@@ -31,7 +31,8 @@ __all__ = [
     "source_moments", "cfg1", "cfg2", "cfg3_mu", "cfg3_problem", "cfg3_train_test",
     "cfg4_batch", "tiny_2d", "tiny_1d", "CFG3_BOX_LO", "CFG3_BOX_HI", "cfg3_box_centre",
     "cfg3_sigma", "cfg3_sources", "cfg3_features", "cfg5_sets", "pincell_problem", "pincell_sets",
-    "twomat_problem", "twomat_sets",
+    "twomat_problem", "twomat_sets", "varscat_shape", "varscat_problem", "varscat_sets",
+    "field_point_values", "FIELD_NQ",
 ]
 
 _GL4_X, _GL4_W = np.polynomial.legendre.leggauss(4)
@@ -299,3 +300,58 @@ def tiny_1d(seed=0, nx=4, n_ord=4, n_regions=2, inflow=0.0):
     return dict(dim=1, nx=nx, ny=1, box=box, quad=("gl", n_ord), region=region,
                 sigma_t=sig_s + sig_a, sigma_s=sig_s, source=G, inflow=inflow,
                 mu=np.concatenate([sig_s, sig_a]))
+
+
+# ---------------------------------------------------------------- variable scattering (section 5.3)
+FIELD_NQ = 6  # Gauss-Legendre points per axis at which a varying cross section is sampled per cell
+
+
+def varscat_shape(x, y):
+    """The spatial shape of the section-5.3 scattering cross section:
+    r^4 (2 - r^2)^2 inside the unit disk, 1 outside (r^2 = x^2 + y^2)."""
+    r2 = x * x + y * y
+    return np.where(r2 <= 1.0, r2 * r2 * (2.0 - r2) ** 2, 1.0)
+
+
+def _one(x, y):
+    return np.ones_like(x)
+
+
+def varscat_problem(mu_s, n=80, n_theta=30, n_z=6):
+    """The variable-scattering problem of section 5.3: [-1,1]^2, zero inflow,
+    sigma_a = 0, sigma_s(x) = mu_s s(x) + 0.1 with s = varscat_shape, source
+    (10 / pi) exp(-100 (x^2 + y^2)); CL(30, 6) z-folded (90 ordinates).  The
+    cross sections vary inside the cells: they are given as coefficients
+    (sigma_t, sigma_s) of the shape functions (s, 1) in sigma_fields."""
+    box = (-1.0, 1.0, -1.0, 1.0)
+    G = source_moments(lambda x, y: 10.0 / np.pi * np.exp(-100.0 * (x ** 2 + y ** 2)), 2, n, n, box)
+    coef = np.array([float(mu_s), 0.1])
+    return dict(dim=2, nx=n, ny=n, box=box, quad=("cl", n_theta, n_z, True),
+                region=np.zeros(n * n, dtype=np.int32), sigma_fields=[varscat_shape, _one],
+                sigma_t=coef.copy(), sigma_s=coef.copy(), source=G, inflow=0.0,
+                mu=np.array([float(mu_s)]))
+
+
+def varscat_sets(n_test=10, seed=90):
+    """51 uniformly spaced training values of mu_s on [49.9, 99.9] (the first
+    sample mu_s = 74.9 is index 25) and n_test fresh uniform draws."""
+    tr = np.linspace(49.9, 99.9, 51)
+    te = np.random.default_rng(seed).uniform(49.9, 99.9, n_test)
+    return tr, te
+
+
+def field_point_values(spec, nq=FIELD_NQ):
+    """Values of each shape function of spec["sigma_fields"] at the nq x nq
+    Gauss-Legendre points of every cell: [n_fields][ncell][nq * nq], point
+    index gy * nq + gx, cell = k * nx + i."""
+    x0, x1, y0, y1 = spec["box"]
+    nx, ny = spec["nx"], spec["ny"]
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    g, _ = np.polynomial.legendre.leggauss(nq)
+    xc = x0 + (np.arange(nx) + 0.5) * hx
+    yc = y0 + (np.arange(ny) + 0.5) * hy
+    X = xc[None, :, None, None] + 0.5 * hx * g[None, None, None, :]
+    Y = yc[:, None, None, None] + 0.5 * hy * g[None, None, :, None]
+    X, Y = np.broadcast_arrays(X, Y)   # [k, i, gy, gx]
+    return np.stack([np.asarray(f(X, Y), dtype=np.float64).reshape(nx * ny, nq * nq)
+                     for f in spec["sigma_fields"]])

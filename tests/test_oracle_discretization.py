@@ -257,3 +257,98 @@ def test_side_inflow_is_linear_and_matches_constant_inflow():
         assert (np.abs(parts[1]).max() > 0) == (P.ox[j] < 0)
         assert (np.abs(parts[2]).max() > 0) == (P.oy[j] > 0)
         assert (np.abs(parts[3]).max() > 0) == (P.oy[j] < 0)
+
+
+# ---------------------------------------------------------------- cross sections varying inside cells (5.3)
+def _poly_sigma(x, y):
+    return 1.0 + 0.5 * x * x + 0.3 * x * y * y + 0.2 * y
+
+
+def _field_spec(seed=3, nx=5, ny=4, quad=("cl", 6, 2, False), fields=None, coef_t=(1.3, 0.4), coef_s=(0.6, 0.2),
+                box=(0.0, 1.0, 0.0, 1.0)):
+    spec = tiny_2d(seed=seed, nx=nx, ny=ny, quad=quad)
+    spec = dict(spec, box=box, sigma_fields=fields or [_poly_sigma, lambda x, y: np.ones_like(x)],
+                sigma_t=np.array(coef_t), sigma_s=np.array(coef_s))
+    return spec
+
+
+def test_field_matrix_constant_and_piecewise_constant():
+    """A shape function constant on every cell gives the piecewise-constant
+    mass matrix sigma_matrix of the cell values (the quadrature integrates
+    the degree-2 basis products exactly)."""
+    m = dg.Mesh(2, 5, 4, (0.0, 1.0, 0.0, 2.0))
+    vals = 1.0 + 0.1 * np.arange(m.ncell)
+    f = lambda x, y: 1.0 + 0.1 * (np.floor(y / m.hy) * m.nx + np.floor(x / m.hx))
+    A = dg.field_matrix(m, f).toarray()
+    B = dg.sigma_matrix(m, vals).toarray()
+    assert np.abs(A - B).max() < 1e-13
+
+
+def test_field_matrix_linear_shape_closed_form():
+    """f = x: the cell block is x_c I plus h_x / (2 sqrt 3) coupling the x-even
+    and x-odd Legendre modes with the same y-mode (int s (sqrt3 s) ds / 2 =
+    1/sqrt3 on [-1, 1] scaled by h_x / 2)."""
+    m = dg.Mesh(2, 3, 2, (0.0, 1.5, -1.0, 1.0))
+    A = dg.field_matrix(m, lambda x, y: x).toarray()
+    for c in range(m.ncell):
+        i = c % m.nx
+        xc = (i + 0.5) * m.hx
+        blk = A[4 * c:4 * c + 4, 4 * c:4 * c + 4]
+        want = xc * np.eye(4)
+        for p0, p1 in ((0, 1), (2, 3)):  # dof p + 2q: (0,1) and (2,3) differ in the x-mode
+            want[p0, p1] = want[p1, p0] = m.hx / (2.0 * np.sqrt(3.0))
+        np.testing.assert_allclose(blk, want, atol=1e-14)
+
+
+def test_sweep_mms_bilinear_with_varying_sigma():
+    """Upwind DG with a cross section varying inside the cells (a polynomial
+    sigma_t, integrated exactly) still reproduces a continuous bilinear psi*
+    whose source is Omega.grad psi* + sigma_t psi* (projected from its strong
+    form, independently of the assembled Sigma_t)."""
+    spec = _field_spec()
+    P = tr.Problem(spec)
+    m = P.mesh
+    ct = spec["sigma_t"]
+    sig = lambda x, y: ct[0] * _poly_sigma(x, y) + ct[1]
+    coef = np.random.default_rng(2).standard_normal((P.nord, 4))
+    q = np.empty((P.nord, P.ndof))
+    exact = np.empty((P.nord, P.ndof))
+    for j in range(P.nord):
+        a, b, c, d = coef[j]
+        f = lambda x, y: a + b * x + c * y + d * x * y
+        src = lambda x, y: P.ox[j] * (b + d * y) + P.oy[j] * (c + d * x) + sig(x, y) * f(x, y)
+        q[j] = dg.project(m, src) + P.gbc(j, f)
+        exact[j] = dg.project(m, f)
+    _, psi = tr.sweep(P, q, store_psi=True)
+    np.testing.assert_allclose(psi, exact, rtol=0, atol=1e-12 * np.abs(exact).max())
+
+
+def test_sweep_particle_balance_with_varying_sigma():
+    """sum_j w_j outflow_j + int sigma_t phi_h = int q + inflow, with the
+    absorption integrated from the DG function and sigma_t(x) pointwise (an
+    8 x 8 Gauss rule, exact for this polynomial sigma_t)."""
+    spec = dict(_field_spec(seed=5, quad=("cl", 8, 4, True)), inflow=0.4)
+    P = tr.Problem(spec)
+    m = P.mesh
+    vol = np.sqrt(m.hx * m.hy)
+    phi_in = np.random.default_rng(7).uniform(0, 1, P.ndof)
+    q0 = P.Ss @ phi_in + P.G
+    qs = np.stack([q0 + P.gbc(j) for j in range(P.nord)])
+    phi, psi = tr.sweep(P, qs, store_psi=True)
+    outflow = sum(P.w[j] * _boundary_outflow(P, psi[j], j) for j in range(P.nord))
+    g8, w8 = np.polynomial.legendre.leggauss(8)
+    r3 = np.sqrt(3.0)
+    ct = spec["sigma_t"]
+    absorb = 0.0
+    for c in range(m.ncell):
+        i, k = c % m.nx, c // m.nx
+        co = phi[4 * c:4 * c + 4]
+        for a_, wa in zip(g8, w8):
+            for b_, wb in zip(g8, w8):
+                x = (i + 0.5 + 0.5 * a_) * m.hx
+                y = (k + 0.5 + 0.5 * b_) * m.hy
+                val = (co[0] + r3 * a_ * co[1] + r3 * b_ * co[2] + 3 * a_ * b_ * co[3]) / vol
+                absorb += wa * wb * m.hx * m.hy / 4 * (ct[0] * _poly_sigma(x, y) + ct[1]) * val
+    src = q0.reshape(-1, m.nloc)[:, 0].sum() * vol
+    inflow = sum(P.w[j] * P.gbc(j).reshape(-1, m.nloc)[:, 0].sum() * vol for j in range(P.nord))
+    assert abs(outflow + absorb - src - inflow) < 1e-12 * (abs(src) + abs(inflow))

@@ -389,3 +389,39 @@ def test_si_dsa_exact_for_slab_s2():
     D = dsa.DSA(P)
     res = si.si(_At(P), tr.b_tilde(P), lambda l, r: D.apply(r), rtol=1e-12)
     assert res.iterations == 1
+
+
+# ---------------------------------------------------------------- cross sections varying inside cells (5.3)
+def _vs_spec(seed, nx, ny, quad, mu):
+    spec = tiny_2d(seed=seed, nx=nx, ny=ny, quad=quad)
+    shape = lambda x, y: 0.5 + x * x + 0.3 * x * y
+    return dict(spec, sigma_fields=[shape, lambda x, y: np.ones_like(x)],
+                sigma_t=np.array([mu, 0.1]), sigma_s=np.array([0.9 * mu, 0.05]))
+
+
+def test_fc_dsa_exact_with_varying_sigma():
+    """CL(3,2): the P1 ansatz spans every angular flux whatever the cross
+    sections, so FC-DSA with the varying mass matrices is still the ideal
+    correction (M_DSA^{-1} A~ = I)."""
+    P = tr.Problem(_vs_spec(3, 4, 3, ("cl", 3, 2, False), 5.0))
+    D = dsa.DSA(P)
+    At = tr.dense_A_tilde(P)
+    Minv = np.stack([D.apply(e) for e in np.eye(P.ndof)], 1)
+    assert np.abs(Minv @ At - np.eye(P.ndof)).max() < 1e-12
+
+
+def test_affine_terms_with_shape_fields_equal_dense_projection():
+    """sigma_t = mu s + 0.1, sigma_s = 0.9 mu s + 0.05 with s varying inside
+    the cells: A_D + sum_f theta_t,f G_f - theta_s,f S_f equals U^T A(mu) U,
+    and the greedy ROM is exact on its sampled parameters."""
+    fam = [_vs_spec(4, 5, 4, ("cl", 8, 4, True), mu) for mu in (2.0, 4.0, 6.0, 8.0)]
+    U, rep = rom.greedy(fam, window=2, eps_rom=0.0, n_giter=2)
+    for mu in (3.0, 7.5):
+        P = tr.Problem(_vs_spec(4, 5, 4, ("cl", 8, 4, True), mu))
+        Ar = rom.reduced_operator(P, U)
+        AD, G, S = rom.affine_terms(P, U, 2)
+        Aff = AD + sum(P.spec["sigma_t"][f] * G[f] - P.spec["sigma_s"][f] * S[f] for f in range(2))
+        assert np.abs(Ar - Aff).max() < 1e-12 * np.abs(Ar).max()
+    P = tr.Problem(fam[rep.sampled[1]])
+    res = fg.fgmres(_At(P), tr.b_tilde(P), rom.Romsad(P, U, dsa.DSA(P), window=2), m=20, rtol=1e-8)
+    assert res.iterations == 1
