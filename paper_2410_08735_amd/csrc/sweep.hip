@@ -227,42 +227,54 @@ __device__ __forceinline__ void cell_update(const LaneOrds<real, OPL>& L, int g,
   }
 }
 
+// Reals per column of the row-slot kernel's y-trace buffer: the 2 G OPL
+// traces of the column, padded in FP32 so that consecutive columns (the ones
+// the slots of a wave touch together, one column apart) start 2 G banks apart
+// and the slots of a wave read disjoint banks.  FP64 keeps the unpadded
+// layout (its buffer would not fit the LDS budget at 96 columns).
+template <typename real, int G, int OPL>
+__host__ __device__ constexpr int ytr_stride() {
+  return sizeof(real) == 4 ? 2 * G * OPL + ((2 * G - 2 * G * OPL) % 64 + 64) % 64 : 2 * G * OPL;
+}
+
 // The same for the row-slot kernel, where a slot owns whole rows: the x trace
 // passes to the slot's next cell of the row in registers (xt, holding the
 // inflow trace before the first column), the y trace to the next row through
 // LDS (ytr, preloaded with the inflow trace), and the local solve reads its
-// precomputed coefficients (ctab: this cell's region in the three planes of
-// Pair2 entries [plane][region][OPL][G], planes plane_stride apart).
-template <typename real, int G, int OPL>
+// precomputed coefficients (ctab: this cell's region's block of Pair2 entries
+// [plane 0..2][OPL][G], so every address is a compile-time offset from the
+// lane's base).  q0..q3 arrive scaled and already in mirrored orientation.
+template <typename real, int G, int OPL, bool PSI>
 __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, int g, int i, int64_t cell,
                                                  real q0, real q1, real q2, real q3, real mx, real my,
                                                  real xt[OPL][2], real* ytr, real c[4],
-                                                 const typename Pair2<real>::T* ctab, int plane_stride) {
+                                                 const typename Pair2<real>::T* ctab) {
   const real r3 = (real)1.7320508075688772935;
   c[0] = c[1] = c[2] = c[3] = (real)0;
 #pragma unroll
   for (int o = 0; o < OPL; ++o) {
-    const int yo = ((i * OPL + o) * G + g) * 2;  // [column][o][g][2], as in cell_update
+    const int yo = i * ytr_stride<real, G, OPL>() + (o * G + g) * 2;  // [column (padded)][o][g][2]
     const real a = L.a[o], b = L.b[o];
+    const real ra = r3 * a, rb = r3 * b;
     const real tx0 = xt[o][0], tx1 = xt[o][1];
     const real ty0 = ytr[yo], ty1 = ytr[yo + 1];
     real rhs[4];
-    rhs[0] = q0 + a * tx0 + b * ty0;
-    rhs[1] = mx * q1 - r3 * a * tx0 + b * ty1;
-    rhs[2] = my * q2 + a * tx1 - r3 * b * ty0;
-    rhs[3] = mx * my * q3 - r3 * (a * tx1 + b * ty1);
-    const typename Pair2<real>::T* e = ctab + o * G + g;
-    const typename Pair2<real>::T p0 = e[0], p1 = e[plane_stride], p2 = e[2 * plane_stride];
+    rhs[0] = fmadd(b, ty0, fmadd(a, tx0, q0));
+    rhs[1] = fmadd(b, ty1, fmadd(-ra, tx0, q1));
+    rhs[2] = fmadd(-rb, ty0, fmadd(a, tx1, q2));
+    rhs[3] = fmadd(-rb, ty1, fmadd(-ra, tx1, q3));
+    const typename Pair2<real>::T* e = ctab + o * G;
+    const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G];
     const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
     real x[4];
-    solve_apply<real>(cf, r3 * b, rhs, x);
+    solve_apply<real>(cf, rb, rhs, x);
     xt[o][0] = fmadd(r3, x[1], x[0]);
     xt[o][1] = fmadd(r3, x[3], x[2]);
     ytr[yo] = fmadd(r3, x[2], x[0]);
     ytr[yo + 1] = fmadd(r3, x[3], x[1]);
 #pragma unroll
-    for (int d = 0; d < 4; ++d) c[d] += L.wt[o] * x[d];
-    if (L.psi[o]) {
+    for (int d = 0; d < 4; ++d) c[d] = fmadd(L.wt[o], x[d], c[d]);
+    if (PSI && L.psi[o]) {
       double* out = L.psi[o] + 4 * cell;
       out[0] = (double)x[0];
       out[1] = (double)(mx * x[1]);
@@ -379,7 +391,7 @@ constexpr int SWEEP_COEF_ENTRIES = 512;  // (region, lane ordinate) solve-coeffi
 // (formed once from sigma_t, a and b, instead of once per cell) in LDS
 // (n_regions <= SWEEP_SIGMA_TAB, n_regions * G * OPL <= SWEEP_COEF_ENTRIES).
 // SCALED: the source is sigma_s * q, else q as is (qsrc must be given).
-template <typename real, int G, int OPL, int MAXR, bool SCALED>
+template <typename real, int G, int OPL, int MAXR, bool SCALED, bool PSI>
 __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
     const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
     const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
@@ -405,50 +417,57 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
   const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
   extern __shared__ unsigned char smem_raw[];
-  real* ytr = reinterpret_cast<real*>(smem_raw);  // [nx][OPL][G][2]
-  real* tab = ytr + (size_t)nx * G * OPL * 2;     // [SWEEP_SIGMA_TAB]: sigma_s
-  using P2 = typename Pair2<real>::T;
-  P2* ctab = reinterpret_cast<P2*>(tab + SWEEP_SIGMA_TAB);  // [3][n_regions][OPL][G]
+  constexpr int YS = ytr_stride<real, G, OPL>();
+  real* ytr = reinterpret_cast<real*>(smem_raw);  // [nx][YS]: [OPL][G][2] and padding
+  // per region the source scaling with the quadrant's mirror signs folded in:
+  // (s, mx s, my s, mx my s), s = sigma_s (SCALED) or 1
   const int nreg = I.n_regions;
-  const int pstride = nreg * OPL * G;
+  real* tab = ytr + (size_t)nx * YS;               // [n_regions][4]
+  using P2 = typename Pair2<real>::T;
+  P2* ctab = reinterpret_cast<P2*>(tab + 4 * nreg);  // [n_regions][3][OPL][G]
+  const int per_reg = 3 * OPL * G;
   {
     const double* st = sigma_t + (size_t)it.inst * max_regions;
     const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
-    for (int e = tid; e < nreg; e += blockDim.x) tab[e] = SCALED ? (real)ss[e] : (real)1;
-    for (int e = tid; e < pstride; e += blockDim.x) {
+    for (int e = tid; e < nreg; e += blockDim.x) {
+      const real sv = SCALED ? (real)ss[e] : (real)1;
+      tab[4 * e] = sv;
+      tab[4 * e + 1] = mx * sv;
+      tab[4 * e + 2] = my * sv;
+      tab[4 * e + 3] = mx * my * sv;
+    }
+    for (int e = tid; e < nreg * OPL * G; e += blockDim.x) {
       const int rg = e / (G * OPL), j = e % (G * OPL);  // lane j / OPL, its ordinate j % OPL
       const bool on = j < it.count;
       const int js = I.ord_off + it.first + (on ? j : 0);
       double cf[6];
       solve_coef(st[rg], fabs(ox[js]) / I.hx, fabs(oy[js]) / I.hy, cf);
-      P2* d = ctab + (rg * OPL + j % OPL) * G + j / OPL;
+      P2* d = ctab + rg * per_reg + (j % OPL) * G + j / OPL;
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         P2 v;
         v.x = (real)cf[2 * p];
         v.y = (real)cf[2 * p + 1];
-        d[p * pstride] = v;
+        d[p * OPL * G] = v;
       }
     }
     // inflow traces (g, 0) where each column enters the grid
     for (int e = tid; e < nx * G * OPL; e += blockDim.x) {
-      ytr[2 * e] = gy;
-      ytr[2 * e + 1] = (real)0;
+      real* t = ytr + (e / (G * OPL)) * YS + 2 * (e % (G * OPL));
+      t[0] = gy;
+      t[1] = (real)0;
     }
   }
   __syncthreads();
   const int32_t* reg = region + I.region_off;
   const double* qi = qsrc + I.dof_off;
   real* P = part + it.part_off;
-  // physical cell of (mirrored column i, mirrored row r), both clamped into the grid
-  auto phys = [&](int i, int r) {
-    i = min(max(i, 0), nx - 1);
-    r = min(r, ny - 1);
-    return (fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 - i : i);
-  };
+  // a row's cells in sweep order are consecutive physical cells, dx apart
+  const int dx = fx ? -1 : 1;
 
   double4 qn[MAXR];
   int rn[MAXR];
+  int cn[MAXR];           // physical index of each row's next cell
   real xt[MAXR][OPL][2];  // x traces of the slot's rows, the inflow trace first
 #pragma unroll
   for (int kk = 0; kk < MAXR; ++kk)
@@ -458,10 +477,11 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
       xt[kk][o][1] = (real)0;
     }
 #pragma unroll
-  for (int kk = 0; kk < MAXR; ++kk) {
-    const int c = phys(-kk * S - slot, slot + kk * S);  // the cell each row needs on diagonal 0
-    rn[kk] = reg[c];
-    qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)c);
+  for (int kk = 0; kk < MAXR; ++kk) {  // each row's first cell (rows past the grid: the last row's)
+    const int r = min(slot + kk * S, ny - 1);
+    cn[kk] = (fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 : 0);
+    rn[kk] = reg[cn[kk]];
+    qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)cn[kk]);
   }
 
   for (int s = 0; s < nx + ny - 1; ++s) {
@@ -472,20 +492,20 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
       if (r < ny && i >= 0 && i < nx) {
         const double4 v = qn[kk];
         const int rg = rn[kk];
-        const int cell = phys(i, r);
-        const real sc = tab[rg];
+        const int cell = cn[kk];
+        const real* sc = tab + 4 * rg;
         real c[4];
-        cell_update_rows<real, G, OPL>(L, g, i, cell, sc * (real)v.x, sc * (real)v.y, sc * (real)v.z,
-                                       sc * (real)v.w, mx, my, xt[kk], ytr, c, ctab + rg * OPL * G, pstride);
+        cell_update_rows<real, G, OPL, PSI>(L, g, i, cell, sc[0] * (real)v.x, sc[1] * (real)v.y, sc[2] * (real)v.z,
+                                       sc[3] * (real)v.w, mx, my, xt[kk], ytr, c, ctab + rg * per_reg + g);
         store_partial<real, G>(c, g, mx, my, P, cell);
-      }
-      // source of this row's cell on the next diagonal (issued after the last
-      // use of the current one, so it can land in the same registers); none
-      // while the row's next step has no cell, so whole waves skip it
-      if (r < ny && i + 1 >= 0 && i + 1 < nx) {
-        const int c = phys(i + 1, r);
-        rn[kk] = reg[c];
-        qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)c);
+        // source of the row's next cell (issued after the last use of the
+        // current one, so it can land in the same registers); none after the
+        // row's last cell, so whole waves skip it
+        if (i + 1 < nx) {
+          cn[kk] = cell + dx;
+          rn[kk] = reg[cell + dx];
+          qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)(cell + dx));
+        }
       }
     }
     lds_barrier();
@@ -798,8 +818,11 @@ static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T) {
 // y only for the row-slot kernel, which also stages the sigma_s table and the
 // solve coefficients).
 static size_t sweep_lds(const rte_batch* b, int G, int opl, int variant, size_t es) {
-  size_t n = (size_t)(variant == 1 ? b->max_nx : b->max_nx + b->max_ny) * G * opl * 2;
-  if (variant == 1) n += SWEEP_SIGMA_TAB + (size_t)6 * b->max_regions * G * opl;
+  size_t n = (size_t)(b->max_nx + b->max_ny) * G * opl * 2;
+  if (variant == 1) {
+    const int ys = es == 4 ? 2 * G * opl + ((2 * G - 2 * G * opl) % 64 + 64) % 64 : 2 * G * opl;
+    n = (size_t)b->max_nx * ys + 4 * (size_t)b->max_regions + (size_t)6 * b->max_regions * G * opl;
+  }
   return n * es;
 }
 
@@ -814,21 +837,29 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
     const size_t lds = sweep_lds(b, G, OPL, 1, sizeof(real));
     if (lds > 64 * 1024) return RTE_EINVAL;
     const double* src = qx ? qx : qadd;
-#define RTE_ROWS_LAUNCH(R, SC)                                                                               \
-  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, OPL, R, SC>), dim3(8 * per_xcd), dim3(p.threads), lds, s,  \
+#define RTE_ROWS_LAUNCH1(R, SC, PS)                                                                          \
+  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, OPL, R, SC, PS>), dim3(8 * per_xcd), dim3(p.threads), lds, s, \
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t,        \
                      sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(part), psi_out,           \
                      active, p.n_items, per_xcd)
+#define RTE_ROWS_LAUNCH(R, SC)              \
+  do {                                      \
+    if (psi_out) RTE_ROWS_LAUNCH1(R, SC, true); \
+    else RTE_ROWS_LAUNCH1(R, SC, false);    \
+  } while (0)
     if (qx) {
-      if (nr <= 2) RTE_ROWS_LAUNCH(2, true);
+      if (nr <= 1) RTE_ROWS_LAUNCH(1, true);
+      else if (nr <= 2) RTE_ROWS_LAUNCH(2, true);
       else if (nr <= 4) RTE_ROWS_LAUNCH(4, true);
       else RTE_ROWS_LAUNCH(8, true);
     } else {
-      if (nr <= 2) RTE_ROWS_LAUNCH(2, false);
+      if (nr <= 1) RTE_ROWS_LAUNCH(1, false);
+      else if (nr <= 2) RTE_ROWS_LAUNCH(2, false);
       else if (nr <= 4) RTE_ROWS_LAUNCH(4, false);
       else RTE_ROWS_LAUNCH(8, false);
     }
 #undef RTE_ROWS_LAUNCH
+#undef RTE_ROWS_LAUNCH1
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
@@ -845,13 +876,18 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
 // The (G, OPL) pairs that have kernels: G lanes per cell, OPL ordinates per lane.
 static bool plan_shape_ok(int G, int opl) {
   const bool g_ok = G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32;
-  return g_ok && (opl == 1 || (opl == 2 && G >= 4 && G <= 16) || (opl == 4 && G >= 4 && G <= 8));
+  return g_ok && (opl == 1 || (opl == 2 && G >= 4 && G <= 16) || (opl == 4 && G >= 4 && G <= 8) ||
+                  (opl == 8 && G == 4));
 }
 
 template <typename real>
 static int launch2d_g(rte_batch* b, const Plan& p, const double* st, const double* ss,
                       const double* qx, const double* qa, const double* inf, double* psi,
                       hipStream_t s, const int32_t* act, void* part) {
+  if (p.opl == 8) {
+    if (p.G == 4) return launch2d<real, 4, 8>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    return RTE_EINVAL;
+  }
   if (p.opl == 4) {
     switch (p.G) {
       case 4: return launch2d<real, 4, 4>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
@@ -1040,7 +1076,7 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
     return RTE_OK;
   };
   for (int V = 0; V < 2; ++V) {
-    for (int O = 1; O <= 4; O *= 2) {
+    for (int O = 1; O <= 8; O *= 2) {
       for (int G : cand_G) {
         if (!plan_shape_ok(G, O) || G * O > 32) continue;
         for (int T : cand_T) {

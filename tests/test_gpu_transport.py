@@ -87,13 +87,13 @@ def test_sweep_parity_uneven_batch(dtype, tol):
 
 PLANS = [(0, 4, 1, 128), (0, 16, 1, 512), (0, 32, 1, 256), (1, 8, 1, 512), (1, 16, 1, 64), (1, 32, 1, 64),
          (1, 4, 1, 256), (0, 8, 2, 256), (0, 16, 2, 512), (1, 4, 2, 128), (1, 16, 2, 64), (0, 4, 4, 256),
-         (1, 8, 4, 512)]
+         (1, 8, 4, 512), (1, 8, 4, 256), (0, 4, 8, 128), (1, 4, 8, 64), (1, 4, 8, 128)]
 
 
 @pytest.mark.gpu
 def test_sweep_parity_every_plan():
-    """Both 2D kernel variants, several lane-group sizes, one or two ordinates
-    per lane, and work-group sizes (1, 3 and 6 rows per slot for the row-slot
+    """Both 2D kernel variants, several lane-group sizes, 1, 2, 4 or 8 ordinates
+    per lane, and work-group sizes (1 to 6 rows per slot for the row-slot
     kernel), through rte_sweep
     (unscaled source, psi stored) and rte_apply_A (sigma_s-scaled source)."""
     import paper_2410_08735_amd as rt
