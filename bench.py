@@ -232,6 +232,9 @@ def learned_leg(args, common):
         if name == "mlp":
             res[name]["fallbacks"] = int(sum(s["pc_fallback"] for s in stats))
             res[name]["mlp_applies"] = int(sum(s["pc_mlp"] for s in stats))
+            jd = np.array([s["mlp_judge"] for s in stats])
+            res[name]["judge_rel_diff_vs_rom_mean"] = float(jd.mean())
+            res[name]["judge_rel_diff_vs_rom_max"] = float(jd.max())
         log(f"learned: {name}: {ok / dt:.1f} solves/s, iterations mean {its.mean():.2f} max {its.max()}, "
             f"converged {ok}/{len(stats)}")
     out.update(res)
@@ -422,6 +425,93 @@ def twomat_leg(args):
     return out
 
 
+def sweep_leg(args):
+    """Full-batch FP32 operator sweeps (every instance active) of the main
+    workload for kernel traces and counter passes: `steps` applications of
+    A~ = I - T Sigma_s between the region markers 1 and 2, and optionally the
+    512 MiB calibration copy between markers 3 and 4."""
+    import torch
+
+    import paper_2410_08735_amd as rt
+    from synth import cfg3_problem, cfg3_train_test
+    _, te_mu = cfg3_train_test(n_train=args.n_train, n_test=args.n_test)
+    B = rt.Batch([cfg3_problem(m, n=args.grid) for m in te_mu])
+    st, ss = B.sigma()
+    x = B.source()
+    if args.sweep_plan:
+        v, g, o, t = (int(q) for q in args.sweep_plan.split(","))
+        B.set_sweep_plan("f32", v, g, t, opl=o)
+    for _ in range(max(args.warmup, 1)):
+        rt.apply_A(B, st, ss, x, dtype="f32")
+    torch.cuda.synchronize()
+    rt.prof_enable(True)
+    rt.prof_mark(1)
+    for _ in range(args.steps):
+        rt.apply_A(B, st, ss, x, dtype="f32")
+    rt.prof_mark(2)
+    torch.cuda.synchronize()
+    n, ms, units = rt.prof_read("sweep_f32")
+    rt.prof_enable(False)
+    if args.pmc_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        rt.prof_mark(3)
+        dst.copy_(src)
+        rt.prof_mark(4)
+        torch.cuda.synchronize()
+    avg = ms / max(n, 1)
+    return {"plan": B.sweep_plan("f32"), "launches": n, "avg_launch_ms": avg,
+            "cell_ordinates_per_launch": units / max(n, 1),
+            "tflops_at_70": units / max(n, 1) * SWEEP_FLOPS_PER_CELL_ORD / (avg * 1e-3) / 1e12 if avg > 0 else 0.0}
+
+
+def varscat_leg(args):
+    """The paper's variable-scattering problem (section 5.3): [-1,1]^2, 80^2
+    cells, CL(30,6), sigma_s = mu_s r^4 (2 - r^2)^2 + 0.1 inside the unit disk
+    (mu_s + 0.1 outside), sigma_a = 0; 51 training values of mu_s on [49.9,
+    99.9], mu_s,1 = 74.9, window 2, eps_ROM = 1e-9 (in the paper's basis
+    scaling), rtol 1e-11, 10 test values, exact-solve DSA, FC and PC.  The
+    paper's table: GMRES-PC-DSA 15.0, GMRES-FC-DSA 11.0, FGMRES-PC-ROMSAD 4.7,
+    FGMRES-FC-ROMSAD 4.6 sweeps; 8 sampled, rank 16."""
+    import numpy as np
+    import torch
+
+    import paper_2410_08735_amd as rt
+    from synth import varscat_problem, varscat_sets
+    tr_mu, te_mu = varscat_sets()
+    h = 2.0 / 80
+    Btr = rt.Batch([varscat_problem(m) for m in tr_mu])
+    st, ss = Btr.sigma()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=2, mu1_index=25, eps_rom=1e-9 / h,
+                                      n_giter=25, eps_qr=1e-13, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+    torch.cuda.synchronize()
+    out = {"greedy_s": time.perf_counter() - t, "sampled": len(rep["sampled"]), "rank": rep["rank"],
+           "sampled_mu_s": [float(tr_mu[i]) for i in rep["sampled"]],
+           "paper": {"gmres_pc_dsa_nsweep": 15.0, "gmres_fc_dsa_nsweep": 11.0, "fgmres_pc_romsad_nsweep": 4.7,
+                     "fgmres_fc_romsad_nsweep": 4.6, "sampled": 8, "rank": 16}}
+    del Btr, st, ss
+    log(f"variable scattering: greedy sampled {out['sampled']}, rank {out['rank']}, {out['greedy_s']:.1f} s")
+    B = rt.Batch([varscat_problem(m) for m in te_mu])
+    st, ss = B.sigma()
+    G = B.source()
+    exact = dict(m=60, max_cycles=10, sweep_dtype="f64", rtol=1e-11, window=2, dsa_inner_max=2000, dsa_restart=60,
+                 dsa_inner_tol=1e-12)
+    for name, pc, kw, var in (("gmres_pc_dsa", "dsa", {}, "pc"), ("gmres_fc_dsa", "dsa", {}, "fc"),
+                              ("fgmres_pc_romsad", "romsad", dict(rom=rom), "pc"),
+                              ("fgmres_fc_romsad", "romsad", dict(rom=rom), "fc")):
+        dt, ok, stats = _solve_timed(rt, torch, B, st, ss, G, rt.SolveOptions(precond=pc, dsa_variant=var, **exact),
+                                     reps=1, **kw)
+        its = np.array([s["iterations"] for s in stats])
+        rr = np.array([s["true_relres"] for s in stats])
+        out[name] = {"nsweep_mean": float(1 + its.mean()), "ms": dt * 1e3, "max_true_relres": float(rr.max()),
+                     "converged": int((rr <= 1e-11).sum())}
+        log(f"variable scattering: {name}: n_sweep {1 + its.mean():.2f}, {dt * 1e3:.1f} ms, max relres {rr.max():.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +535,9 @@ def main():
     ap.add_argument("--only-pincell", action="store_true", help="the paper's pin-cell problem only")
     ap.add_argument("--only-twomat", action="store_true", help="the paper's two-material problem only")
     ap.add_argument("--only-uneven", action="store_true")
+    ap.add_argument("--only-varscat", action="store_true", help="the paper's variable-scattering problem only")
+    ap.add_argument("--only-sweep", action="store_true",
+                    help="full-batch FP32 operator sweeps of the main workload only (for traces and counters)")
     ap.add_argument("--only-mlp", action="store_true")
     ap.add_argument("--sweep-plan", type=str, default=None,
                     help="fix the FP32 sweep plan of the main workload: variant,G,opl,threads (default: autotuned)")
@@ -479,6 +572,12 @@ def main():
         return
     if args.only_pincell:
         print(json.dumps({"pincell": pincell_leg(args)}), flush=True)
+        return
+    if args.only_varscat:
+        print(json.dumps({"varscat": varscat_leg(args)}), flush=True)
+        return
+    if args.only_sweep:
+        print(json.dumps({"sweep": sweep_leg(args)}), flush=True)
         return
     if args.only_uneven:
         print(json.dumps({"uneven": uneven_leg(args, common)}), flush=True)

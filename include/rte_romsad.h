@@ -126,6 +126,28 @@ int rte_batch_max_regions(const rte_batch* b);
  * ceil(max_ny / (threads / G)) <= 8 rows per slot and at most 256 regions).
  * get: out[5] = {variant, G, opl, threads, tuned}.                          */
 int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int opl, int threads);
+
+/* Cross sections that vary inside the cells (the variable-scattering problem
+ * of section 5.3): sigma_t(x) = sum_f theta_t,f s_f(x) and sigma_s(x) =
+ * sum_f theta_s,f s_f(x) with n_fields shape functions s_f, given by their
+ * values at the nq x nq Gauss-Legendre points of every cell (host
+ * [n_fields][ncell][nq * nq], point index gy * nq + gx with gx, gy the
+ * ascending nodes along x and y, cell = k * nx + i).  The library forms every
+ * cell's 4 x 4 mass block int_T s_f e_a e_b with the same rule; from then on
+ * the per-instance sigma_t / sigma_s arrays hold the coefficients theta
+ * ([n_inst][max_regions], first n_fields entries) and the region map is not
+ * used.  Needs an X-Y batch whose instances share one grid, rule and region
+ * map, with n_regions >= n_fields each (RTE_EINVAL otherwise).  Supported
+ * afterwards:
+ * rte_sweep, rte_rhs, rte_apply_A (the sweep's local matrices use the full
+ * blocks), rte_dsa_apply and the DSA inside the solvers with restart >= 1
+ * on reflection-symmetric rules (the multigrid hierarchy works with the cell
+ * averages, the GMRES around it with the full blocks), romsad_apply,
+ * fgmres_solve (preconditioners none, DSA, ROMSAD), romsad_build_greedy with
+ * hf_dsa_tol > 0; si_solve, the learned correction and rte_mlp_snapshots
+ * return RTE_EINVAL.  The sweep plan's variant is reset to 0 (the row-slot
+ * kernel needs region-wise cross sections).                                 */
+int rte_batch_set_fields(rte_batch* b, int n_fields, int nq, const double* values);
 int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out);
 
 /* ---------------------------------------------------------------- transport
@@ -261,6 +283,9 @@ typedef struct {
   double est_relres;     /* last Givens estimate / ||b~||                     */
   int32_t rom_singular;  /* 1: A_r(mu) singular, DSA ran in place of the ROM  */
   int32_t pad;
+  double mlp_judge;      /* RTE_PC_MLP: mean over the network's steps of
+                            ||W_w (c_MLP - c_ROM)|| / ||W_w c_ROM||, the ROM
+                            solve judging the learned correction; else 0    */
 } rte_solve_stats;
 
 int fgmres_solve(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* G,

@@ -89,6 +89,12 @@ class Batch:
         self.total_psi = lib.rte_batch_total_psi(h)
         self.max_regions = lib.rte_batch_max_regions(h)
         self.n_ords = [len(self._keep[4 * k + 2]) for k in range(n)]
+        fv = self.problems[0].get("field_values") if n else None
+        if fv is not None:  # cross sections varying inside the cells: shape values at the Gauss points
+            fv = np.ascontiguousarray(fv, dtype=np.float64)
+            nq = int(round(np.sqrt(fv.shape[2])))
+            check(lib.rte_batch_set_fields(h, int(fv.shape[0]), nq, fv.ctypes.data_as(L.pdbl)),
+                  "rte_batch_set_fields")
 
     def set_sweep_plan(self, dtype, variant, G, threads, opl=1):
         check(L.lib().rte_batch_set_sweep_plan(self.h, _dt(dtype), variant, G, opl, threads),

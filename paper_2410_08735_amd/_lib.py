@@ -41,7 +41,7 @@ class SolveStats(C.Structure):
     _fields_ = [("iterations", i32), ("cycles", i32), ("sweeps_f32", i32), ("sweeps_f64", i32),
                 ("pc_rom", i32), ("pc_dsa", i32), ("pc_mlp", i32), ("pc_fallback", i32),
                 ("status", i32), ("true_relres", dbl), ("est_relres", dbl), ("rom_singular", i32),
-                ("pad", i32)]
+                ("pad", i32), ("mlp_judge", dbl)]
 
 
 class GreedyReport(C.Structure):
@@ -97,6 +97,7 @@ SIGNATURES = {
     "rte_mlp_snapshots": (C.c_int, [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), vp, C.c_int, vp, vp, vp,
                                     vp]),
     "rte_batch_set_sweep_plan": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "rte_batch_set_fields": (C.c_int, [vp, C.c_int, C.c_int, pdbl]),
     "rte_batch_sweep_plan": (C.c_int, [vp, C.c_int, C.POINTER(i32)]),
     "rte_prof_enable": (C.c_int, [C.c_int]),
     "rte_prof_mark": (C.c_int, [C.c_int, vp]),

@@ -237,6 +237,7 @@ extern "C" void rte_batch_destroy(rte_batch* b) {
   (void)hipFree(b->d_perm);
   (void)hipFree(b->d_region);
   (void)hipFree(b->d_part);
+  (void)hipFree(b->d_fblk);
   for (auto& p : b->plan) {
     (void)hipFree(p.d_items);
     (void)hipFree(p.d_parts);

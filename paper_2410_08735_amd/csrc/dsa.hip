@@ -319,6 +319,76 @@ __global__ void k_dsa_axpy(const int64_t* __restrict__ off, const int64_t* __res
     y[lo + e] += x[lo + e];
 }
 
+// Cross sections varying inside the cells (section 5.3): rhs = [Sigma_s v,
+// m_d Sigma_s v] with the cells' full scattering blocks.
+__global__ void k_dsa_rhs_field(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
+                                const double* __restrict__ fblk, int nf, int64_t fcell,
+                                const double* __restrict__ sigma_s, int max_regions, const int64_t* __restrict__ off,
+                                const double* __restrict__ v, double* __restrict__ rhs,
+                                const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const InstDev I = insts[b];
+  const DsaStencil& S = st_[b];
+  const int ncell = I.nx * I.ny;
+  const double* th = sigma_s + (int64_t)b * max_regions;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
+    double B[16];
+    field_block(fblk, nf, fcell, cell, th, B);
+    const double* vc = v + I.dof_off + 4 * (int64_t)cell;
+    for (int l = 0; l < 4; ++l) {
+      const double sv = B[4 * l] * vc[0] + B[4 * l + 1] * vc[1] + B[4 * l + 2] * vc[2] + B[4 * l + 3] * vc[3];
+      rhs[off[b] + (int64_t)l * ncell + cell] = sv;
+      for (int d = 0; d < 2; ++d) rhs[off[b] + (int64_t)((1 + d) * 4 + l) * ncell + cell] = S.m[d] * sv;
+    }
+  }
+}
+
+// y += sign (K - K_avg) x on level 0 of a field-mode DSA: the sigma terms of
+// the moment system with every cell's full mass blocks in place of the cell
+// averages (the (0, 0) entries) that the multigrid hierarchy uses.  The
+// coefficient of field F' in the rows of field F is the stencil's sigma
+// pattern (St, Ss: identity over the moments for piecewise-constant cross
+// sections).
+__global__ void k_dsa_field_corr(const InstDev* __restrict__ insts, const DsaStencil* __restrict__ st_,
+                                 const double* __restrict__ fblk, int nf, int64_t fcell,
+                                 const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                                 int max_regions, const int64_t* __restrict__ off, const double* __restrict__ x,
+                                 double* __restrict__ y, double sign, const int32_t* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const InstDev I = insts[b];
+  const DsaStencil& S = st_[b];
+  const int ncell = I.nx * I.ny;
+  const int nu = 12;
+  const double* tt = sigma_t + (int64_t)b * max_regions;
+  const double* ts = sigma_s + (int64_t)b * max_regions;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
+    double Bt[16], Bs[16];
+    field_block(fblk, nf, fcell, cell, tt, Bt);
+    field_block(fblk, nf, fcell, cell, ts, Bs);
+    const double at = Bt[0], as = Bs[0];
+    for (int k = 0; k < 4; ++k) {
+      Bt[5 * k] -= at;
+      Bs[5 * k] -= as;
+    }
+    const double* xb = x + off[b];
+    double* yb = y + off[b];
+    for (int F = 0; F < 3; ++F)
+      for (int Fp = 0; Fp < 3; ++Fp) {
+        const double ct = S.St[(F * 4) * nu + Fp * 4], cs = S.Ss[(F * 4) * nu + Fp * 4];
+        if (ct == 0.0 && cs == 0.0) continue;
+        double xv[4];
+        for (int l = 0; l < 4; ++l) xv[l] = xb[(int64_t)(Fp * 4 + l) * ncell + cell];
+        for (int k = 0; k < 4; ++k) {
+          double acc = 0.0;
+          for (int l = 0; l < 4; ++l) acc += (ct * Bt[4 * k + l] + cs * Bs[4 * k + l]) * xv[l];
+          yb[(int64_t)(F * 4 + k) * ncell + cell] += sign * acc;
+        }
+      }
+  }
+}
+
 // ------------------------------------------------------------------ multigrid
 struct LvlInst {
   int32_t nx, ny, dim, nloc;
@@ -339,6 +409,27 @@ __global__ void k_mg_sigma0(const InstDev* __restrict__ insts, const LvlInst* __
     const int rg = region[I.region_off + c];
     st[L.cell_off + c] = sigma_t[(int64_t)b * max_regions + rg];
     ss[L.cell_off + c] = sigma_s[(int64_t)b * max_regions + rg];
+  }
+}
+
+// Level-0 per-cell cross sections of a field-mode batch: the cell averages,
+// the (0, 0) entries of the full blocks.
+__global__ void k_mg_sigma0_field(const InstDev* __restrict__ insts, const LvlInst* __restrict__ li,
+                                  const double* __restrict__ fblk, int nf, int64_t fcell,
+                                  const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                                  int max_regions, double* __restrict__ st, double* __restrict__ ss) {
+  const int b = blockIdx.y;
+  const LvlInst L = li[b];
+  const int nc = L.nx * L.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    double t = 0.0, u = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      const double m00 = fblk[((int64_t)f * fcell + c) * 16];
+      t += sigma_t[(int64_t)b * max_regions + f] * m00;
+      u += sigma_s[(int64_t)b * max_regions + f] * m00;
+    }
+    st[L.cell_off + c] = t;
+    ss[L.cell_off + c] = u;
   }
 }
 
@@ -1112,7 +1203,7 @@ struct MgTailLevel {
 // unwritten; mode 2 (colour 1 after mode 1) sets x = D^{-1} (b - K x) with its
 // own x taken as zero.
 template <typename real, typename sreal>
-__device__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const sreal* st, const sreal* ss,
+__device__ __forceinline__ void tail_half_sweep(const SymCoef<real>& S, const LvlInst& L, const sreal* st, const sreal* ss,
                                 const real* bv, real* x, int color, int mode) {
   const int nx = L.nx, ny = L.ny, nc = nx * ny;
   // even rows: the threads take only this colour's cells (nc / 2 of them)
@@ -1183,7 +1274,7 @@ __device__ __forceinline__ void tail_sweep(const SymCoef<real>& S, const LvlInst
 // the colour-0 children (0, 0) and (1, 1) have one), restricted into the next
 // level's b.
 template <typename real, typename sreal>
-__device__ void tail_restrict(const SymCoef<real>& S, const LvlInst& L, const LvlInst& C, const sreal* sgt,
+__device__ __forceinline__ void tail_restrict(const SymCoef<real>& S, const LvlInst& L, const LvlInst& C, const sreal* sgt,
                               const sreal* sgs, const real* x, const real* bv, real* bc) {
   const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
   for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
@@ -1216,7 +1307,7 @@ __device__ void tail_restrict(const SymCoef<real>& S, const LvlInst& L, const Lv
 // x_dst = x_src + P xc on a tail level (x_src may be x_dst): the four
 // children's values are read first, so their loads overlap.
 template <typename real>
-__device__ void tail_prolong(const LvlInst& L, const LvlInst& C, const real* xc, const real* x_src, real* x_dst) {
+__device__ __forceinline__ void tail_prolong(const LvlInst& L, const LvlInst& C, const real* xc, const real* x_src, real* x_dst) {
   const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
   for (int c = threadIdx.x; c < ncc; c += blockDim.x) {
     const int I = c % C.nx, K = c / C.nx;
@@ -1451,6 +1542,8 @@ struct DsaSolver {
              const int32_t* act, hipStream_t s);
   int vcycle(int l, const double* bv, double* x, const int32_t* act, hipStream_t s);
   int precond(const double* in, double* out, const int32_t* act, hipStream_t s);
+  int field_corr(const double* sigma_t, const double* sigma_s, const double* x, double* y, double sign,
+                 const int32_t* act, hipStream_t s);
   int apply(const double* sigma_t, const double* sigma_s, const double* v, double* z, double inner_tol,
             int inner_max, const int32_t* active, int32_t* iters_host, bool prep, hipStream_t s);
   dim3 grid(int l) const {
@@ -1631,8 +1724,12 @@ int DsaSolver::prepare(const double* sigma_t, const double* sigma_s, const int32
                        hipStream_t s) {
   const int n = b->n_inst;
   const int mr = b->max_regions;
-  hipLaunchKernelGGL(k_mg_sigma0, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, b->d_region, sigma_t,
-                     sigma_s, mr, lv[0].st, lv[0].ss);
+  if (b->n_fields > 0)
+    hipLaunchKernelGGL(k_mg_sigma0_field, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, b->d_fblk, b->n_fields,
+                       b->field_ncell, sigma_t, sigma_s, mr, lv[0].st, lv[0].ss);
+  else
+    hipLaunchKernelGGL(k_mg_sigma0, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, b->d_region, sigma_t,
+                       sigma_s, mr, lv[0].st, lv[0].ss);
   if (!sym)
     hipLaunchKernelGGL(k_dsa_blockinv, dim3((n * mr + 63) / 64), dim3(64), 0, s, n, mr, b->d_inst,
                        lv[0].d_st, sigma_t, sigma_s, inv0);
@@ -1788,6 +1885,14 @@ __global__ void k_scale_tol(int n, const double* __restrict__ rn, double rtol, d
   if (b < n) tol[b] = rtol * rn[b];
 }
 
+int DsaSolver::field_corr(const double* sigma_t, const double* sigma_s, const double* x, double* y, double sign,
+                          const int32_t* act, hipStream_t s) {
+  hipLaunchKernelGGL(k_dsa_field_corr, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_fblk, b->n_fields,
+                     b->field_ncell, sigma_t, sigma_s, b->max_regions, sp.d_off, x, y, sign, act);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
 int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double* v, double* z,
                      double inner_tol, int inner_max, const int32_t* active, int32_t* iters_host,
                      bool prep, hipStream_t s) {
@@ -1802,7 +1907,10 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
                          nu_hbm_finest_post == 0 && tail_first != 0 && nu_hbm == 1;
   if (fused_out) {
     // the V-cycle forms the right-hand side itself
-  } else if (f32)
+  } else if (b->n_fields > 0)
+    hipLaunchKernelGGL(k_dsa_rhs_field, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_fblk, b->n_fields,
+                       b->field_ncell, sigma_s, mr, sp.d_off, v, rhs, active);
+  else if (f32)
     hipLaunchKernelGGL(k_dsa_rhs<float>, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_st, b->d_region, sigma_s,
                        mr, sp.d_off, v, reinterpret_cast<float*>(rhs), active);
   else
@@ -1848,6 +1956,7 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
         RTE_TRY(kcopy(sp, rhs, T, d_live, s));
       } else {
         RTE_TRY(stencil(0, 1, 0, rhs, X, T, d_live, s));
+        if (b->n_fields > 0) RTE_TRY(field_corr(sigma_t, sigma_s, X, T, -1.0, d_live, s));
       }
       RTE_HIP(hipMemcpyAsync(K.active, d_live, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
       RTE_TRY(kstart(K, T, tol, s));
@@ -1855,6 +1964,7 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
       for (; j < restart && done_iters + j < inner_max; ++j) {
         RTE_TRY(precond(K.v(j), T, K.active, s));
         RTE_TRY(stencil(0, 0, 0, nullptr, T, K.v(j + 1), K.active, s));
+        if (b->n_fields > 0) RTE_TRY(field_corr(sigma_t, sigma_s, T, K.v(j + 1), 1.0, K.active, s));
         RTE_TRY(arnoldi_mgs(K, j, s));
         if ((j + 1) % 4 == 0) {
           std::vector<int32_t> a(n);
@@ -1942,8 +2052,12 @@ void dsa_forget(rte_batch* b) {
 int dsa_apply(rte_batch* b, const double* sigma_t, const double* sigma_s, const double* v, double* z,
               double inner_tol, int inner_max, int restart, const int32_t* active, int32_t* iters,
               hipStream_t s, bool prepare, int variant) {
+  // cross sections varying inside the cells: only the exact solve (whose
+  // GMRES sees the full blocks) on the structured path of symmetric rules
+  if (b->n_fields > 0 && (restart < 1 || b->dim != 2)) return RTE_EINVAL;
   DsaSolver* d = dsa_for(b, restart, variant == RTE_DSA_PC ? 1 : 0);
   if (!d) return RTE_ENOMEM;
+  if (b->n_fields > 0 && !d->sym) return RTE_EINVAL;
   return d->apply(sigma_t, sigma_s, v, z, inner_tol, inner_max, active, iters, prepare, s);
 }
 

@@ -252,6 +252,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   dsa_ready = false;  // the DSA hierarchy is rebuilt for this call's cross sections
   K.bt = o.breakdown_tol > 0.0 ? o.breakdown_tol : 1e-14;
   RTE_TRY(fill_i32(K.fail, n, 0, s));
+  if (o.precond == RTE_PC_MLP) RTE_TRY(mlp_judge_reset(b, s));
   // A_r(mu) depends on mu only: its singularity is decided once per solve
   any_sing = false;
   sing_h.assign(n, 0);
@@ -391,11 +392,16 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     // phi += Z y ; r = b~ - A~ phi in FP64
     RTE_TRY(kylov_solve_update(K, K.Z, phi, s));
     if (f32_btil) {
-      int max_nd = 0;
-      for (const auto& I : b->inst) max_nd = std::max(max_nd, I.nx * I.ny * I.nloc);
-      hipLaunchKernelGGL(k_source_plus, dim3(std::min((max_nd + 255) / 256, 1024), n), dim3(256), 0, s,
-                         b->d_inst, b->d_region, c.sigma_s, b->max_regions, c.G, phi, r, cyc);
-      RTE_HIP(hipGetLastError());
+      if (b->n_fields > 0) {  // q = G + Sigma_s phi with the cells' full scattering blocks
+        RTE_TRY(kcopy(K.sp, c.G, r, cyc, s));
+        RTE_TRY(field_apply(b, c.sigma_s, phi, r, true, cyc, s));
+      } else {
+        int max_nd = 0;
+        for (const auto& I : b->inst) max_nd = std::max(max_nd, I.nx * I.ny * I.nloc);
+        hipLaunchKernelGGL(k_source_plus, dim3(std::min((max_nd + 255) / 256, 1024), n), dim3(256), 0, s,
+                           b->d_inst, b->d_region, c.sigma_s, b->max_regions, c.G, phi, r, cyc);
+        RTE_HIP(hipGetLastError());
+      }
       RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, r, c.inflow, nullptr, s, cyc,
                            batch_cell_ordinates(b, cm.data())));
       RTE_TRY(reduce_partials(b, 0, 1.0, phi, -1.0, r, s, cyc));
@@ -427,6 +433,11 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   for (int q = 0; q < n; ++q) {
     stats[q].status = conv[q] ? RTE_OK : (stop[q] ? stop[q] : RTE_WNOTCONV);
     if (!conv[q]) ret = RTE_WNOTCONV;
+  }
+  if (o.precond == RTE_PC_MLP) {
+    std::vector<double> jm;
+    RTE_TRY(mlp_judge_read(b, jm, s));
+    for (int q = 0; q < n; ++q) stats[q].mlp_judge = jm[q];
   }
   return ret;
 }
@@ -483,6 +494,11 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
   if (rom && !rte::rom_matches(rom, b)) return RTE_EINVAL;
   if (o.precond == RTE_PC_MLP && rom && rom->is_set()) return RTE_EINVAL;  // one network per ROM basis
   if (o.precond == RTE_PC_MLP && (!mlp || !mu || mu_dim < 1)) return RTE_EINVAL;
+  // cross sections varying inside the cells: the DSA must be the exact solve
+  // (its V-cycles use cell averages), and the learned correction is not offered
+  if (b->n_fields > 0 && (o.precond == RTE_PC_MLP ||
+                          ((o.precond == RTE_PC_DSA || o.precond == RTE_PC_ROMSAD) && o.dsa_restart < 1)))
+    return RTE_EINVAL;
   if (!(o.breakdown_tol >= 0.0) || o.breakdown_tol >= 1e3) return RTE_EINVAL;
   RTE_TRY(rte::validate_cross_sections(b, sigma_t, sigma_s, reinterpret_cast<hipStream_t>(stream)));
   rte::Fgmres* f = rte::fgmres_for(b, o.m);

@@ -109,6 +109,86 @@ __global__ void k_gemm(int Mr, int Nc, int Kd, const float* __restrict__ A, int6
   }
 }
 
+// The BF16 product on the matrix cores, LDS-tiled: a work group of 256
+// threads (4 waves) computes a 64 x 64 block of C.  Per K-chunk of 32 the
+// group loads the 64 x 32 block of A and the 32 x 64 block of B from global
+// memory once (consecutive threads along whichever operand index has unit
+// stride), rounds them to bfloat16 (nearest even) into LDS, and each wave
+// multiplies its 32 x 32 quarter as 2 x 2 v_mfma_f32_16x16x16_bf16 tiles per
+// 16-deep step, reading its fragments as 8-byte LDS words.  Epilogue as in
+// k_gemm.  Operand layout of one MFMA (lane = r + 16 g): A(m0 + r, k0 + 4 g + q),
+// B(k0 + 4 g + q, n0 + r) for q = 0..3; the result C(m0 + 4 g + q, n0 + r).
+constexpr int GT_BM = 64, GT_BN = 64, GT_BK = 32, GT_LD = GT_BK + 4;  // LDS row pitch (shorts)
+
+__global__ void __launch_bounds__(256) k_gemm_tiled(int Mr, int Nc, int Kd, const float* __restrict__ A, int64_t sam,
+                                                    int64_t sak, const float* __restrict__ Bm, int64_t sbk,
+                                                    int64_t sbn, float* __restrict__ C, int64_t scm, int64_t scn,
+                                                    const float* __restrict__ bias, int act,
+                                                    float* __restrict__ Zout, int accumulate) {
+  __shared__ short As[GT_BM * GT_LD];  // [m][k]
+  __shared__ short Bs[GT_BN * GT_LD];  // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int mb = blockIdx.y * GT_BM, nb = blockIdx.x * GT_BN;
+  const int r = lane & 15, g = lane >> 4;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool a_rowmajor = sak == 1, b_rowmajor = sbn == 1;
+  for (int k0 = 0; k0 < Kd; k0 += GT_BK) {
+#pragma unroll
+    for (int i = 0; i < (GT_BM * GT_BK) / 256; ++i) {
+      const int e = tid + 256 * i;
+      const int m = a_rowmajor ? e / GT_BK : e % GT_BM, k = a_rowmajor ? e % GT_BK : e / GT_BM;
+      const int gm = mb + m, gk = k0 + k;
+      const float v = (gm < Mr && gk < Kd) ? A[gm * sam + gk * sak] : 0.f;
+      As[m * GT_LD + k] = f2bf(v);
+    }
+#pragma unroll
+    for (int i = 0; i < (GT_BN * GT_BK) / 256; ++i) {
+      const int e = tid + 256 * i;
+      const int n = b_rowmajor ? e % GT_BN : e / GT_BK, k = b_rowmajor ? e / GT_BN : e % GT_BK;
+      const int gn = nb + n, gk = k0 + k;
+      const float v = (gn < Nc && gk < Kd) ? Bm[gk * sbk + gn * sbn] : 0.f;
+      Bs[n * GT_LD + k] = f2bf(v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GT_BK; kk += 16) {
+      bf16x4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const bf16x4*>(&As[(wm + 16 * i + r) * GT_LD + kk + 4 * g]);
+        b[i] = *reinterpret_cast<const bf16x4*>(&Bs[(wn + 16 * i + r) * GT_LD + kk + 4 * g]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = mb + wm + 16 * i + 4 * g + q, n = nb + wn + 16 * j + r;
+        if (m >= Mr || n >= Nc) continue;
+        float v = acc[i][j][q];
+        if (accumulate) v += C[m * scm + n * scn];
+        if (bias) v += bias[n];
+        if (act == 1) {
+          Zout[m * scm + n * scn] = v;
+          v = gelu_f(v);
+        }
+        C[m * scm + n * scn] = v;
+      }
+}
+
 // dY = 2 (Y_net * scale + shift - T) * scale / (rows * cols) in network units, loss partials
 __global__ void k_mse_grad(int rows, int cols, const float* __restrict__ Y, const float* __restrict__ T,
                            const float* __restrict__ scale, const float* __restrict__ shift,
@@ -212,9 +292,8 @@ static int gemm(bool bf16, int M, int N, int K, const float* A, int64_t sam, int
                 float* Z, int accumulate, hipStream_t s) {
   if (M <= 0 || N <= 0) return RTE_OK;
   if (bf16) {
-    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
-    hipLaunchKernelGGL(k_gemm<true>, dim3((tiles + 3) / 4), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk,
-                       sbn, C, scm, scn, bias, act, Z, accumulate);
+    hipLaunchKernelGGL(k_gemm_tiled, dim3((N + GT_BN - 1) / GT_BN, (M + GT_BM - 1) / GT_BM), dim3(256), 0, s, M, N,
+                       K, A, sam, sak, B, sbk, sbn, C, scm, scn, bias, act, Z, accumulate);
   } else {
     const int64_t n = (int64_t)M * N;
     hipLaunchKernelGGL(k_gemm<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, N, K, A, sam,
@@ -323,6 +402,13 @@ struct MlpScratch {
   const rte_batch* b = nullptr;
   double *g = nullptr, *c = nullptr, *gn = nullptr;
   int32_t *um = nullptr, *ur = nullptr;
+  // the judge of the learned correction: the ROM solve's coefficients, the
+  // Gram matrix of W_w (of gram_rom), and per-instance sums and counts of
+  // ||W_w (c_MLP - c_ROM)|| / ||W_w c_ROM|| over the network's steps
+  double *crom = nullptr, *gram = nullptr, *jsum = nullptr;
+  int32_t* jcnt = nullptr;
+  const rte_rom* gram_rom = nullptr;
+  int gram_r = 0;
 };
 static std::vector<MlpScratch> g_ms;
 
@@ -335,7 +421,11 @@ static MlpScratch* mlp_scratch(const rte_batch* b) {
   if (hipMalloc(&s.g, sizeof(double) * n * ROM_GSTRIDE) != hipSuccess ||
       hipMalloc(&s.c, sizeof(double) * n * ROM_GSTRIDE) != hipSuccess ||
       hipMalloc(&s.gn, sizeof(double) * n) != hipSuccess || hipMalloc(&s.um, sizeof(int32_t) * n) != hipSuccess ||
-      hipMalloc(&s.ur, sizeof(int32_t) * n) != hipSuccess)
+      hipMalloc(&s.ur, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&s.crom, sizeof(double) * n * ROM_GSTRIDE) != hipSuccess ||
+      hipMalloc(&s.gram, sizeof(double) * ROM_GSTRIDE * ROM_GSTRIDE) != hipSuccess ||
+      hipMalloc(&s.jsum, sizeof(double) * n) != hipSuccess || hipMalloc(&s.jcnt, sizeof(int32_t) * n) != hipSuccess ||
+      hipMemset(s.jsum, 0, sizeof(double) * n) != hipSuccess || hipMemset(s.jcnt, 0, sizeof(int32_t) * n) != hipSuccess)
     return nullptr;
   g_ms.push_back(s);
   return &g_ms.back();
@@ -344,13 +434,65 @@ static MlpScratch* mlp_scratch(const rte_batch* b) {
 void mlp_scratch_forget(const rte_batch* b) {
   for (size_t i = 0; i < g_ms.size();) {
     if (g_ms[i].b == b) {
-      for (void* p : {(void*)g_ms[i].g, (void*)g_ms[i].c, (void*)g_ms[i].gn, (void*)g_ms[i].um, (void*)g_ms[i].ur})
+      for (void* p : {(void*)g_ms[i].g, (void*)g_ms[i].c, (void*)g_ms[i].gn, (void*)g_ms[i].um, (void*)g_ms[i].ur,
+                      (void*)g_ms[i].crom, (void*)g_ms[i].gram, (void*)g_ms[i].jsum, (void*)g_ms[i].jcnt})
         (void)hipFree(p);
       g_ms.erase(g_ms.begin() + i);
     } else {
       ++i;
     }
   }
+}
+
+__global__ void k_gram(int r, int64_t nd, const double* __restrict__ W, double* __restrict__ G);
+
+// jsum[b] += ||W_w d|| / ||W_w c_ROM||, d = c_MLP - c_ROM, with the Gram matrix
+// of W_w (so the norms are those of the lifted scalar-flux corrections)
+__global__ void k_mlp_judge(int n, int r, const double* __restrict__ gram, const double* __restrict__ cm,
+                            const double* __restrict__ cr, int stride, double* __restrict__ jsum,
+                            int32_t* __restrict__ jcnt, const int32_t* __restrict__ on) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || !on[b]) return;
+  const double* x = cm + (int64_t)b * stride;
+  const double* y = cr + (int64_t)b * stride;
+  double dd = 0.0, rr = 0.0;
+  for (int i = 0; i < r; ++i) {
+    double gd = 0.0, gr = 0.0;
+    for (int k = 0; k < r; ++k) {
+      gd += gram[i * r + k] * (x[k] - y[k]);
+      gr += gram[i * r + k] * y[k];
+    }
+    dd += (x[i] - y[i]) * gd;
+    rr += y[i] * gr;
+  }
+  if (rr > 0.0) {
+    jsum[b] += sqrt(fmax(dd, 0.0) / rr);
+    jcnt[b] += 1;
+  }
+}
+
+int mlp_judge_reset(const rte_batch* b, hipStream_t s) {
+  for (auto& m : g_ms)
+    if (m.b == b) {
+      RTE_HIP(hipMemsetAsync(m.jsum, 0, sizeof(double) * b->n_inst, s));
+      RTE_HIP(hipMemsetAsync(m.jcnt, 0, sizeof(int32_t) * b->n_inst, s));
+    }
+  return RTE_OK;
+}
+
+// mean judge per instance (0 where the network made no step); syncs s
+int mlp_judge_read(const rte_batch* b, std::vector<double>& out, hipStream_t s) {
+  out.assign(b->n_inst, 0.0);
+  for (auto& m : g_ms)
+    if (m.b == b) {
+      std::vector<double> sm(b->n_inst);
+      std::vector<int32_t> ct(b->n_inst);
+      RTE_HIP(hipMemcpyAsync(sm.data(), m.jsum, sizeof(double) * b->n_inst, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipMemcpyAsync(ct.data(), m.jcnt, sizeof(int32_t) * b->n_inst, hipMemcpyDeviceToHost, s));
+      RTE_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < b->n_inst; ++q) out[q] = ct[q] ? sm[q] / ct[q] : 0.0;
+    }
+  return RTE_OK;
 }
 
 // z = v + W_w (MLP(mu, g/|g|) |g|) for instances with off[b] == 0, ROMSAD for off[b] == 1.
@@ -377,6 +519,17 @@ int mlp_precond(const rte_mlp* cm, const rte_rom* rom, rte_batch* b, const doubl
   hipLaunchKernelGGL(k_unscale, dim3(64), dim3(256), 0, s, n, r, m->H[L], m->yscale, m->yshift);
   hipLaunchKernelGGL(k_mlp_coeffs, dim3((n * r + 255) / 256), dim3(256), 0, s, n, r, m->H[L], sc->gn, sc->c,
                      ROM_GSTRIDE, sc->um);
+  RTE_HIP(hipGetLastError());
+  // the judge: the ROM solve's coefficients for the same reduced right-hand side
+  if (sc->gram_rom != rom || sc->gram_r != r) {
+    hipLaunchKernelGGL(k_gram, dim3(r * r), dim3(256), 0, s, r, rom->ndof, rom->Ww, sc->gram);
+    RTE_HIP(hipGetLastError());
+    sc->gram_rom = rom;
+    sc->gram_r = r;
+  }
+  RTE_TRY(rom_solve_coeffs(rom, b, sigma_t, sigma_s, sc->g, sc->crom, sc->um, s));
+  hipLaunchKernelGGL(k_mlp_judge, dim3((n + 63) / 64), dim3(64), 0, s, n, r, sc->gram, sc->c, sc->crom, ROM_GSTRIDE,
+                     sc->jsum, sc->jcnt, sc->um);
   RTE_HIP(hipGetLastError());
   return rom_lift(rom, b, v, sc->c, z, sc->um, s);
 }
@@ -705,7 +858,7 @@ extern "C" int rte_mlp_snapshots(const rte_batch* cb, const double* sigma_t, con
   auto* b = const_cast<rte_batch*>(cb);
   if (!b || !sigma_t || !sigma_s || !G || !rom || !opts || !mu || mu_dim < 0 || !X || !T || !valid ||
       rom->is_set() || rom->r < 1 || opts->window < 1 || opts->m < opts->window || !rom_matches(rom, b) ||
-      opts->precond == RTE_PC_MLP)
+      opts->precond == RTE_PC_MLP || b->n_fields > 0)
     return RTE_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   RTE_TRY(validate_cross_sections(b, sigma_t, sigma_s, s));

@@ -22,6 +22,10 @@ struct rte_rom {
   double hx = 1.0, hy = 1.0;
   // A ROM set (rte_rom_set_create): per-instance members of a batch with
   // instances of several grids / quadratures; the members are not owned.
+  // built on a batch whose cross sections vary inside the cells: the affine
+  // pieces G_R, S_R belong to the shape functions (M_R = the shape-weighted
+  // mass matrix) instead of regions
+  bool fields = false;
   std::vector<const rte_rom*> members;
   std::vector<int32_t> member_of;   // [n_inst of the batch it was made for]
   bool is_set() const { return !members.empty(); }
@@ -56,6 +60,11 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
 void rom_scratch_forget(const rte_batch* b);
 constexpr int ROM_GSTRIDE = 64;  // stride of per-instance reduced vectors g, c
 
+// c = A_r(mu)^{-1} g per masked instance (g, c [n][ROM_GSTRIDE]), no lift
+int rom_solve_coeffs(const rte_rom* rom, rte_batch* b, const double* sigma_t, const double* sigma_s,
+                     const double* g, double* c, const int32_t* active, hipStream_t s);
+int mlp_judge_reset(const rte_batch* b, hipStream_t s);
+int mlp_judge_read(const rte_batch* b, std::vector<double>& out, hipStream_t s);
 int mlp_precond(const rte_mlp* mlp, const rte_rom* rom, rte_batch* b, const double* sigma_t,
                 const double* sigma_s, const double* mu, int mu_dim, const double* v, double* z,
                 const int32_t* active, hipStream_t s, int32_t* fallback_flags);

@@ -564,6 +564,89 @@ __global__ void k_greedy_max(int nmu, int n_ord, int nch, const double* __restri
   out[m] = best;
 }
 
+// y_v = B_f x_v per cell for nvec vectors of nd = 4 ncell dofs (B_f the
+// mass block of shape function f alone)
+__global__ void k_field_apply_vecs(const double* __restrict__ fblk, int f, int64_t ncell, int nvec,
+                                   const double* __restrict__ x, double* __restrict__ y) {
+  const int v = blockIdx.y;
+  const int64_t nd = 4 * ncell;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x) {
+    const double* B = fblk + ((int64_t)f * ncell + c) * 16;
+    const double* xc = x + (int64_t)v * nd + 4 * c;
+    double* yc = y + (int64_t)v * nd + 4 * c;
+    const double x0 = xc[0], x1 = xc[1], x2 = xc[2], x3 = xc[3];
+    for (int a = 0; a < 4; ++a) yc[a] = B[4 * a] * x0 + B[4 * a + 1] * x1 + B[4 * a + 2] * x2 + B[4 * a + 3] * x3;
+  }
+}
+
+// out[i * nf + f] = col[i], i < n
+__global__ void k_put_col(int n, int nf, int f, const double* __restrict__ col, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i * nf + f] = col[i];
+}
+
+// The greedy residual indicator with cross sections varying inside the
+// cells: per listed parameter, ordinate j and cell, the 4 moments of
+//   sum_k c_k (D_j U_k,j) + Sigma_t(mu) (U c)_j - Sigma_s(mu) (W_w c) - eta0,
+// the full blocks applied to the accumulated vectors; partial sums of the
+// squares per chunk of 256 cells.
+constexpr int GRF_MB = 4;
+__global__ void k_greedy_res_field(int r, int rcap, int n_ord, int64_t ncell, const double* __restrict__ U,
+                                   const double* __restrict__ DU, const double* __restrict__ Ww, int nmu,
+                                   const int32_t* __restrict__ mu_idx, const double* __restrict__ c,
+                                   const double* __restrict__ fblk, int nf, const double* __restrict__ sigma_t,
+                                   const double* __restrict__ sigma_s, int max_regions,
+                                   const double* __restrict__ eta0, double* __restrict__ part, int nch) {
+  __shared__ double sh[4];
+  const int j = blockIdx.y, ch = blockIdx.x;
+  const int64_t cell = (int64_t)ch * 256 + threadIdx.x;
+  const bool on = cell < ncell;
+  const int64_t nd = 4 * ncell;
+  const int64_t pe = (int64_t)j * nd + 4 * cell;
+  for (int mb = 0; mb < nmu; mb += GRF_MB) {
+    double adu[GRF_MB][4], au[GRF_MB][4], aw[GRF_MB][4];
+#pragma unroll
+    for (int q = 0; q < GRF_MB; ++q)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) adu[q][a] = au[q][a] = aw[q][a] = 0.0;
+    if (on) {
+      for (int k = 0; k < r; ++k) {
+        const double* uk = U + (int64_t)k * n_ord * nd + pe;
+        const double* dk = DU + (int64_t)k * n_ord * nd + pe;
+        const double* wk = Ww + (int64_t)k * nd + 4 * cell;
+#pragma unroll
+        for (int q = 0; q < GRF_MB; ++q) {
+          const double ck = mb + q < nmu ? c[(int64_t)(mb + q) * rcap + k] : 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            adu[q][a] = fma(ck, dk[a], adu[q][a]);
+            au[q][a] = fma(ck, uk[a], au[q][a]);
+            aw[q][a] = fma(ck, wk[a], aw[q][a]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GRF_MB; ++q) {
+      double sq = 0.0;
+      if (on && mb + q < nmu) {
+        const int mi = mu_idx[mb + q];
+        double Bt[16], Bs[16];
+        field_block(fblk, nf, ncell, cell, sigma_t + (int64_t)mi * max_regions, Bt);
+        field_block(fblk, nf, ncell, cell, sigma_s + (int64_t)mi * max_regions, Bs);
+        const double* e0 = eta0 + (int64_t)mi * nd + 4 * cell;
+        for (int a = 0; a < 4; ++a) {
+          double v = adu[q][a] - e0[a];
+          for (int bb = 0; bb < 4; ++bb) v += Bt[4 * a + bb] * au[q][bb] - Bs[4 * a + bb] * aw[q][bb];
+          sq += v * v;
+        }
+      }
+      const double t = bsum256(sq, sh);
+      if (threadIdx.x == 0 && mb + q < nmu) part[((int64_t)(mb + q) * n_ord + j) * nch + ch] = t;
+    }
+  }
+}
+
 __global__ void k_scale_sigma(const InstDev* __restrict__ insts, const int32_t* __restrict__ region,
                               const double* __restrict__ sigma, int max_regions,
                               const double* __restrict__ x, double* __restrict__ y) {
@@ -589,6 +672,7 @@ struct RomScratch {
   const rte_batch* b = nullptr;
   int n = 0;
   double *g = nullptr, *c = nullptr, *part = nullptr;
+  double* sv = nullptr;  // Sigma_s v of a field-mode batch [total_dof]
   int32_t* sing = nullptr;
   int64_t part_elems = 0;
   // per-instance ROM table of the last ROM used on this batch
@@ -680,6 +764,7 @@ void rom_scratch_forget(const rte_batch* b) {
       (void)hipFree(g_rs[i].c);
       (void)hipFree(g_rs[i].part);
       (void)hipFree(g_rs[i].sing);
+      (void)hipFree(g_rs[i].sv);
       (void)hipFree(g_rs[i].d_tab);
       g_rs.erase(g_rs.begin() + i);
     } else {
@@ -711,8 +796,13 @@ int rom_alloc(rte_rom* rom, const rte_batch* b, int rcap) {
     rom->w[j] = b->w[I.ord_off + s];
   }
   rom->region.assign(I.nx * I.ny, 0);
-  RTE_HIP(hipMemcpy(rom->region.data(), b->d_region + I.region_off, sizeof(int32_t) * I.nx * I.ny,
-                    hipMemcpyDeviceToHost));
+  rom->fields = b->n_fields > 0;
+  if (rom->fields) {
+    rom->n_regions = b->n_fields;  // the affine pieces belong to the shape functions; no region map
+  } else {
+    RTE_HIP(hipMemcpy(rom->region.data(), b->d_region + I.region_off, sizeof(int32_t) * I.nx * I.ny,
+                      hipMemcpyDeviceToHost));
+  }
   const int R = rom->n_regions;
   if (hipMalloc(&rom->U, sizeof(double) * rcap * rom->npsi) != hipSuccess ||
       hipMalloc(&rom->DU, sizeof(double) * rcap * rom->npsi) != hipSuccess ||
@@ -747,15 +837,67 @@ void rom_free(rte_rom* rom) {
   rom->d_region = nullptr;
 }
 
-static int mdot(const rte_rom* rom, int64_t len, int64_t nd, const double* x, const double* Y,
-                int64_t ystride, int ny_, double* part, double* out, hipStream_t s) {
+static int mdot_n(const rte_rom* rom, int nreg, int64_t len, int64_t nd, const double* x, const double* Y,
+                  int64_t ystride, int ny_, double* part, double* out, hipStream_t s) {
   const int nch = (int)((len + MD_CHUNK - 1) / MD_CHUNK);
-  hipLaunchKernelGGL(k_mdot, dim3(nch, ny_), dim3(256), 0, s, len, nd, rom->nloc, rom->d_region,
-                     rom->n_regions, x, Y, ystride, part, nch);
-  hipLaunchKernelGGL(k_mdot_sum, dim3((ny_ * rom->n_regions + 63) / 64), dim3(64), 0, s, ny_, nch,
-                     rom->n_regions, part, out);
+  hipLaunchKernelGGL(k_mdot, dim3(nch, ny_), dim3(256), 0, s, len, nd, rom->nloc, rom->d_region, nreg, x, Y,
+                     ystride, part, nch);
+  hipLaunchKernelGGL(k_mdot_sum, dim3((ny_ * nreg + 63) / 64), dim3(64), 0, s, ny_, nch, nreg, part, out);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
+}
+
+static int mdot(const rte_rom* rom, int64_t len, int64_t nd, const double* x, const double* Y,
+                int64_t ystride, int ny_, double* part, double* out, hipStream_t s) {
+  return mdot_n(rom, rom->n_regions, len, nd, x, Y, ystride, ny_, part, out, s);
+}
+
+// The new row/column r of A_D, G_f, S_f of a field-mode ROM: plain inner
+// products (the region map is all zeros: one region) of the shape-weighted
+// vectors M_f u_r, M_f W_w,r and M_f W_1,r with the basis.
+static int field_columns(rte_rom* rom, const rte_batch* b, const double* u, const double* du, int r, double* part,
+                         double* adc, double* adr, double* gg, double* sc, double* sr, hipStream_t s) {
+  const int nf = rom->n_regions, ny_ = r + 1;
+  const int64_t nd = rom->ndof, np = rom->npsi, ncell = nd / 4;
+  double *mu = nullptr, *tmp = nullptr;
+  if (hipMalloc(&mu, sizeof(double) * np) != hipSuccess || hipMalloc(&tmp, sizeof(double) * ny_) != hipSuccess) {
+    (void)hipFree(mu);
+    return RTE_ENOMEM;
+  }
+  int st = RTE_OK;
+  const dim3 gpsi((unsigned)std::min<int64_t>((ncell + 255) / 256, 1024), rom->n_ord), gdof(gpsi.x, 1);
+  auto put = [&](double* out, int f) {
+    hipLaunchKernelGGL(k_put_col, dim3((ny_ + 63) / 64), dim3(64), 0, s, ny_, nf, f, tmp, out);
+    return hipGetLastError() == hipSuccess ? RTE_OK : RTE_EHIP;
+  };
+  if (hipMemsetAsync(adc, 0, sizeof(double) * ny_ * nf, s) != hipSuccess ||
+      hipMemsetAsync(adr, 0, sizeof(double) * ny_ * nf, s) != hipSuccess)
+    st = RTE_EHIP;
+  if (st == RTE_OK) st = mdot_n(rom, 1, np, nd, du, rom->U, np, ny_, part, tmp, s);   // <U_i, DU_r>
+  if (st == RTE_OK) st = put(adc, 0);
+  if (st == RTE_OK) st = mdot_n(rom, 1, np, nd, u, rom->DU, np, ny_, part, tmp, s);   // <U_r, DU_i>
+  if (st == RTE_OK) st = put(adr, 0);
+  for (int f = 0; f < nf && st == RTE_OK; ++f) {
+    hipLaunchKernelGGL(k_field_apply_vecs, gpsi, dim3(256), 0, s, b->d_fblk, f, ncell, rom->n_ord, u, mu);
+    st = mdot_n(rom, 1, np, nd, mu, rom->U, np, ny_, part, tmp, s);                    // <U_i, M_f U_r>
+    if (st == RTE_OK) st = put(gg, f);
+    if (st == RTE_OK) {
+      hipLaunchKernelGGL(k_field_apply_vecs, gdof, dim3(256), 0, s, b->d_fblk, f, ncell, 1,
+                         rom->Ww + (int64_t)r * nd, mu);
+      st = mdot_n(rom, 1, nd, nd, mu, rom->W1, nd, ny_, part, tmp, s);                 // <W1_i, M_f Ww_r>
+    }
+    if (st == RTE_OK) st = put(sc, f);
+    if (st == RTE_OK) {
+      hipLaunchKernelGGL(k_field_apply_vecs, gdof, dim3(256), 0, s, b->d_fblk, f, ncell, 1,
+                         rom->W1 + (int64_t)r * nd, mu);
+      st = mdot_n(rom, 1, nd, nd, mu, rom->Ww, nd, ny_, part, tmp, s);                 // <M_f W1_r, Ww_i>
+    }
+    if (st == RTE_OK) st = put(sr, f);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && st == RTE_OK) st = RTE_EHIP;
+  (void)hipFree(mu);
+  (void)hipFree(tmp);
+  return st;
 }
 
 int rom_add_column(rte_rom* rom, const rte_batch* b, hipStream_t s) {
@@ -785,6 +927,19 @@ int rom_add_column(rte_rom* rom, const rte_batch* b, hipStream_t s) {
   double* sc = res + 3 * ny_ * R;
   double* sr = res + 4 * ny_ * R;
   int st = RTE_OK;
+  if (rom->fields) {
+    if (!b || b->n_fields != R) st = RTE_EINVAL;
+    if (st == RTE_OK) st = field_columns(rom, b, u, du, r, part, adc, adr, gg, sc, sr, s);
+    if (st == RTE_OK) {
+      hipLaunchKernelGGL(k_place, dim3((ny_ + 63) / 64), dim3(64), 0, s, r, rom->rcap, R, adc, adr, gg, sc, sr,
+                         rom->AD, rom->G, rom->S);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) st = RTE_EHIP;
+    }
+    (void)hipFree(part);
+    (void)hipFree(res);
+    if (st == RTE_OK) rom->r = r + 1;
+    return st;
+  }
   if (st == RTE_OK) st = mdot(rom, np, nd, du, rom->U, np, ny_, part, adc, s);   // <U_i, DU_r>
   if (st == RTE_OK) st = mdot(rom, np, nd, u, rom->DU, np, ny_, part, adr, s);   // <U_r, DU_i>
   if (st == RTE_OK) st = mdot(rom, np, nd, u, rom->U, np, ny_, part, gg, s);     // <U_i, U_r>_R
@@ -815,6 +970,8 @@ static bool rom_matches_inst(const rte_rom* rom, const rte_batch* b, int k) {
 }
 
 bool rom_matches(const rte_rom* rom, const rte_batch* b) {
+  if (rom->is_set() ? b->n_fields > 0 : rom->fields != (b->n_fields > 0)) return false;
+  if (rom->fields && b->n_fields != rom->n_regions) return false;
   if (rom->is_set()) {
     if ((int)rom->member_of.size() != b->n_inst) return false;
     for (int k = 0; k < b->n_inst; ++k)
@@ -849,6 +1006,12 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
   if (!tab) return RTE_EHIP;
   const int which = (W && !rom->is_set() && W == rom->Ww) ? 1 : 0;
   if (W && !which) return RTE_EINVAL;  // only W_1 or W_w of the ROM itself
+  if (sigma_s && b->n_fields > 0) {  // Sigma_s v with the cells' full blocks, then the plain projection
+    if (!sc->sv && hipMalloc(&sc->sv, sizeof(double) * b->total_dof) != hipSuccess) return RTE_ENOMEM;
+    RTE_TRY(field_apply(b, sigma_s, v, sc->sv, false, active, s));
+    v = sc->sv;
+    sigma_s = nullptr;
+  }
   if (!rom->is_set() && nd < (1 << 30)) {
     const int nchm = (int)((nd + PM_DOF - 1) / PM_DOF);
     const dim3 grid((nchm + 3) / 4, (b->n_inst + 15) / 16);
@@ -913,6 +1076,19 @@ int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_
                      b->max_regions, g, c, ROM_RMAX, sing, active);
   RTE_HIP(hipGetLastError());
   return rom_lift(rom, b, v, c, z, active, s);
+}
+
+int rom_solve_coeffs(const rte_rom* rom, rte_batch* b, const double* sigma_t, const double* sigma_s,
+                     const double* g, double* c, const int32_t* active, hipStream_t s) {
+  if (rom_max_rank(rom) == 0) return RTE_OK;
+  RomScratch* sc = scratch_for(b, rom_part_elems(b, rom_max_ndof(rom)));
+  if (!sc) return RTE_ENOMEM;
+  const RomDev* tab = rom_table(rom, sc, b, s);
+  if (!tab) return RTE_EHIP;
+  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, tab, sigma_t, sigma_s,
+                     b->max_regions, g, c, ROM_RMAX, (int32_t*)nullptr, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
 }
 
 // sing[b] = 1 where A_r(mu_b) has a pivot below 1e-14 max |A_r| (the test of
@@ -1051,7 +1227,8 @@ extern "C" int rte_rom_save(const rte_rom* rom, const char* path) {
   FILE* f = std::fopen(path, "wb");
   if (!f) return RTE_EIO;
   RTE_HIP(hipDeviceSynchronize());
-  const char magic[8] = {'R', 'T', 'E', 'R', 'O', 'M', '1', 0};
+  // "RTEROM1": piecewise-constant cross sections; "RTEROMF": shape functions
+  const char magic[8] = {'R', 'T', 'E', 'R', 'O', 'M', rom->fields ? 'F' : '1', 0};
   int32_t hdr[8] = {rom->dim, rom->nx, rom->ny, rom->nloc, rom->n_ord, rom->n_regions, rom->r, rom->rcap};
   bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
   double hh[2] = {rom->hx, rom->hy};
@@ -1087,11 +1264,13 @@ extern "C" int rte_rom_load(const char* path, rte_rom** out) {
     delete rom;
     return code;
   };
-  if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "RTEROM1", 8) != 0 ||
+  if (std::fread(magic, 1, 8, f) != 8 ||
+      (std::memcmp(magic, "RTEROM1", 8) != 0 && std::memcmp(magic, "RTEROMF", 8) != 0) ||
       std::fread(hdr, sizeof(hdr), 1, f) != 1 || std::fread(hh, sizeof(hh), 1, f) != 1)
     return fail(RTE_EIO);
   rom->dim = hdr[0]; rom->nx = hdr[1]; rom->ny = hdr[2]; rom->nloc = hdr[3]; rom->n_ord = hdr[4];
   rom->n_regions = hdr[5]; rom->r = hdr[6]; rom->rcap = hdr[7];
+  rom->fields = magic[6] == 'F';
   if (rom->dim < 1 || rom->dim > 2 || rom->nx < 1 || rom->ny < 1 || rom->n_ord < 1 || rom->rcap < rom->r ||
       rom->r < 0 || rom->rcap > ROM_RMAX || rom->n_regions < 1 || rom->n_regions > ROM_REGMAX ||
       (int64_t)rom->nx * rom->ny > (1 << 26))
@@ -1161,6 +1340,7 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
       !(hf_dsa_tol >= 0.0) ||
       (int64_t)n_giter * window > ROM_RMAX || !b->uniform || b->inst[0].n_regions > ROM_REGMAX)
     return RTE_EINVAL;
+  if (b->n_fields > 0 && !(hf_dsa_tol > 0.0)) return RTE_EINVAL;  // field mode: exact-solve DSA only
   hipStream_t s = as_stream(stream);
   RTE_TRY(validate_cross_sections(b, sigma_t, sigma_s, s));
   const int n = b->n_inst;
@@ -1213,10 +1393,14 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
   if (st == RTE_OK) st = sweep_launch(b, 0, sigma_t, nullptr, nullptr, G, inflow, nullptr, s);
   if (st == RTE_OK) st = reduce_partials(b, 0, 1.0, nullptr, 0.0, btil, s);
   if (st == RTE_OK) {
-    dim3 grid((unsigned)std::min<int64_t>((nd + 255) / 256, 1024), n);
-    hipLaunchKernelGGL(k_scale_sigma, grid, dim3(256), 0, s, b->d_inst, b->d_region, sigma_s,
-                       b->max_regions, btil, eta0);
-    if (hipStreamSynchronize(s) != hipSuccess) st = RTE_EHIP;
+    if (b->n_fields > 0) {
+      st = field_apply(b, sigma_s, btil, eta0, false, nullptr, s);
+    } else {
+      dim3 grid((unsigned)std::min<int64_t>((nd + 255) / 256, 1024), n);
+      hipLaunchKernelGGL(k_scale_sigma, grid, dim3(256), 0, s, b->d_inst, b->d_region, sigma_s,
+                         b->max_regions, btil, eta0);
+    }
+    if (st == RTE_OK && hipStreamSynchronize(s) != hipSuccess) st = RTE_EHIP;
   }
   t_step[0] += now_s() - t0;
   std::vector<rte_solve_stats> stats(n);
@@ -1363,10 +1547,19 @@ extern "C" int romsad_build_greedy(const rte_batch* cb, const double* sigma_t, c
       break;
     }
     const int nmu = (int)unsampled.size();
-    hipLaunchKernelGGL(k_greedy_res, dim3(nch_res, rom->n_ord), dim3(256), 0, s, rom->r, ROM_GSTRIDE,
-                       rom->n_ord, nd, rom->nloc, rom->d_region, rom->U, rom->DU, rom->Ww, nmu, midx,
-                       gq, sigma_t, sigma_s, b->max_regions, eta0, part, nch_res);
-    hipLaunchKernelGGL(k_greedy_max, dim3((nmu + 63) / 64), dim3(64), 0, s, nmu, rom->n_ord, nch_res,
+    int nch_used = nch_res;
+    if (b->n_fields > 0) {
+      const int64_t ncell_f = nd / 4;
+      nch_used = (int)((ncell_f + 255) / 256);
+      hipLaunchKernelGGL(k_greedy_res_field, dim3(nch_used, rom->n_ord), dim3(256), 0, s, rom->r, ROM_GSTRIDE,
+                         rom->n_ord, ncell_f, rom->U, rom->DU, rom->Ww, nmu, midx, gq, b->d_fblk, b->n_fields,
+                         sigma_t, sigma_s, b->max_regions, eta0, part, nch_used);
+    } else {
+      hipLaunchKernelGGL(k_greedy_res, dim3(nch_res, rom->n_ord), dim3(256), 0, s, rom->r, ROM_GSTRIDE,
+                         rom->n_ord, nd, rom->nloc, rom->d_region, rom->U, rom->DU, rom->Ww, nmu, midx,
+                         gq, sigma_t, sigma_s, b->max_regions, eta0, part, nch_res);
+    }
+    hipLaunchKernelGGL(k_greedy_max, dim3((nmu + 63) / 64), dim3(64), 0, s, nmu, rom->n_ord, nch_used,
                        part, rmu);
     std::vector<double> rh(nmu);
     if (hipMemcpyAsync(rh.data(), rmu, sizeof(double) * nmu, hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -100,11 +100,36 @@ struct rte_batch {
   // bumped whenever a plan's device tables or the partial buffer are
   // (re)allocated: captured graphs that embed their addresses are stale then
   uint64_t gen = 1;
+  // cross sections that vary inside the cells (rte_batch_set_fields): the
+  // 4x4 mass blocks of n_fields shape functions on every cell of the common
+  // grid, [n_fields][ncell][16]; the per-instance cross-section arrays then
+  // hold the shapes' coefficients
+  int n_fields = 0;
+  int64_t field_ncell = 0;
+  double* d_fblk = nullptr;
 };
 
 namespace rte {
 
 int ensure_partials(rte_batch* b, int64_t elems);
+
+// The mass block of a cell for coefficients theta[0..nf): sum_f theta_f B_f(cell)
+// (row-major 4x4, orthonormal basis, dof p + 2 q).
+__device__ __forceinline__ void field_block(const double* __restrict__ fblk, int nf, int64_t ncell, int64_t cell,
+                                            const double* __restrict__ theta, double out[16]) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) out[e] = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const double t = theta[f];
+    const double* B = fblk + ((int64_t)f * ncell + cell) * 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[e] = fma(t, B[e], out[e]);
+  }
+}
+// y = Sigma(theta_b) x on every (masked) instance of a field-mode batch; with
+// add, y += Sigma x.  theta: [n_inst][max_regions].
+int field_apply(const rte_batch* b, const double* theta, const double* x, double* y, bool add,
+                const int32_t* active, hipStream_t s);
 // RTE_EINVAL unless every region of every instance has a finite sigma_t > 0
 // and a finite sigma_s >= 0 (reads both device arrays on the host; syncs s).
 int validate_cross_sections(const rte_batch* b, const double* sigma_t, const double* sigma_s, hipStream_t s);

@@ -82,6 +82,7 @@ extern "C" int si_solve(const rte_batch* cb, const double* sigma_t, const double
       (o.dsa_variant == RTE_DSA_PC && o.dsa_restart == 0))
     return RTE_EINVAL;
   if (o.precond == RTE_PC_ROMSAD && (!rom || !rom_matches(rom, b))) return RTE_EINVAL;
+  if (b->n_fields > 0) return RTE_EINVAL;  // cross sections varying inside cells: FGMRES only
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   RTE_TRY(validate_cross_sections(b, sigma_t, sigma_s, s));
   SiWork* w = si_for(b);

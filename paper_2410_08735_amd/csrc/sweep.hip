@@ -365,6 +365,162 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
   }
 }
 
+// Cross sections that vary inside the cells (section 5.3): the local matrix
+// of a cell-ordinate is the cell's full sigma_t mass block (mirrored with the
+// quadrant: entry (a, b) times s_a s_b, s = (1, mx, my, mx my)) plus the
+// upwind advection a K (x) I + b I (x) K, and is solved by Gaussian
+// elimination without pivoting (its symmetric part is positive definite:
+// that of the mass block and of K, diag(1, 3), are).
+template <typename real>
+__device__ __forceinline__ void solve4_nopivot(real A[16], real x[4]) {
+  real inv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    inv[k] = (real)1 / A[5 * k];
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i) {
+      const real f = A[4 * i + k] * inv[k];
+#pragma unroll
+      for (int j = k + 1; j < 4; ++j) A[4 * i + j] = fmadd(-f, A[4 * k + j], A[4 * i + j]);
+      x[i] = fmadd(-f, x[k], x[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    real t = x[i];
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) t = fmadd(-A[4 * i + j], x[j], t);
+    x[i] = t * inv[i];
+  }
+}
+
+// One cell of the field kernel for the lane's ordinates: Sm is the mirrored
+// sigma_t block, q0..q3 the mirrored source moments; traces and the weighted
+// sum as in cell_update.
+template <typename real, int G, int OPL>
+__device__ __forceinline__ void cell_update_field(const LaneOrds<real, OPL>& L, int g, int i, int r, int64_t cell,
+                                                  const real Sm[16], real q0, real q1, real q2, real q3, real gx,
+                                                  real gy, real mx, real my, real* xtr, real* ytr, real c[4]) {
+  const real r3 = (real)1.7320508075688772935;
+  c[0] = c[1] = c[2] = c[3] = (real)0;
+#pragma unroll
+  for (int o = 0; o < OPL; ++o) {
+    const int xo = ((r * OPL + o) * G + g) * 2, yo = ((i * OPL + o) * G + g) * 2;
+    const real a = L.a[o], b = L.b[o];
+    real tx0, tx1, ty0, ty1;
+    if (i == 0) { tx0 = gx; tx1 = 0; } else { tx0 = xtr[xo]; tx1 = xtr[xo + 1]; }
+    if (r == 0) { ty0 = gy; ty1 = 0; } else { ty0 = ytr[yo]; ty1 = ytr[yo + 1]; }
+    real x[4];
+    x[0] = q0 + a * tx0 + b * ty0;
+    x[1] = q1 - r3 * a * tx0 + b * ty1;
+    x[2] = q2 + a * tx1 - r3 * b * ty0;
+    x[3] = q3 - r3 * (a * tx1 + b * ty1);
+    real A[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) A[e] = Sm[e];
+    // a K on the x-mode pair of each y-mode, b K on the y-mode pair of each x-mode
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      A[(2 * q) * 4 + 2 * q] += a;
+      A[(2 * q) * 4 + 2 * q + 1] += r3 * a;
+      A[(2 * q + 1) * 4 + 2 * q] -= r3 * a;
+      A[(2 * q + 1) * 4 + 2 * q + 1] += (real)3 * a;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      A[p * 4 + p] += b;
+      A[p * 4 + p + 2] += r3 * b;
+      A[(p + 2) * 4 + p] -= r3 * b;
+      A[(p + 2) * 4 + p + 2] += (real)3 * b;
+    }
+    solve4_nopivot<real>(A, x);
+    xtr[xo] = fmadd(r3, x[1], x[0]);
+    xtr[xo + 1] = fmadd(r3, x[3], x[2]);
+    ytr[yo] = fmadd(r3, x[2], x[0]);
+    ytr[yo + 1] = fmadd(r3, x[3], x[1]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) c[d] = fmadd(L.wt[o], x[d], c[d]);
+    if (L.psi[o]) {
+      double* out = L.psi[o] + 4 * cell;
+      out[0] = (double)x[0];
+      out[1] = (double)(mx * x[1]);
+      out[2] = (double)(my * x[2]);
+      out[3] = (double)(mx * my * x[3]);
+    }
+  }
+}
+
+// The diagonal-slot sweep with cross sections that vary inside the cells:
+// per cell the lanes form the sigma_t block and (for the operator) the
+// source sigma_s z from the shape blocks and the instance's coefficients.
+template <typename real, int G, int OPL>
+__global__ void __launch_bounds__(512) sweep2d_field_kernel(
+    const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
+    const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
+    const int32_t* __restrict__ perm, const double* __restrict__ fblk, int nf, int64_t fcell,
+    const double* __restrict__ sigma_t, const double* __restrict__ sigma_s, int max_regions,
+    const double* __restrict__ qx, const double* __restrict__ qadd,
+    const double* __restrict__ inflow, real* __restrict__ part, double* __restrict__ psi_out,
+    const int32_t* __restrict__ active, int n_items, int per_xcd) {
+  const int item = (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+  if (item >= n_items) return;
+  const SweepItem it = items[item];
+  if (active && !active[it.inst]) return;
+  const InstDev I = insts[it.inst];
+  const int tid = threadIdx.x;
+  const int g = tid % G;
+  const int slot = tid / G;
+  const int S = blockDim.x / G;
+  const int nx = I.nx, ny = I.ny;
+  const LaneOrds<real, OPL> L = lane_ords<real, G, OPL>(it, I, g, ox, oy, w, perm, psi_out);
+  const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
+  const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
+  const double gsc = sqrt(I.hx * I.hy);
+  const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
+  const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
+  extern __shared__ unsigned char smem_raw[];
+  real* xtr = reinterpret_cast<real*>(smem_raw);  // [ny][OPL][G][2]
+  real* ytr = xtr + (size_t)ny * G * OPL * 2;     // [nx][OPL][G][2]
+  const double* tht = sigma_t + (size_t)it.inst * max_regions;
+  const double* ths = sigma_s ? sigma_s + (size_t)it.inst * max_regions : nullptr;
+  const double* qxi = qx ? qx + I.dof_off : nullptr;
+  const double* qai = qadd ? qadd + I.dof_off : nullptr;
+  real* P = part + it.part_off;
+  const double sgn[4] = {1.0, fx ? -1.0 : 1.0, fy ? -1.0 : 1.0, (fx != fy) ? -1.0 : 1.0};
+
+  for (int s = 0; s < nx + ny - 1; ++s) {
+    const int r_lo = max(0, s - nx + 1), r_hi = min(ny - 1, s);
+    for (int r = r_lo + slot; r <= r_hi; r += S) {
+      const int i = s - r;
+      const int ip = fx ? nx - 1 - i : i;
+      const int kp = fy ? ny - 1 - r : r;
+      const int cell = kp * nx + ip;
+      double B[16], q[4] = {0.0, 0.0, 0.0, 0.0};
+      if (qxi) {
+        field_block(fblk, nf, fcell, cell, ths, B);
+        const double4 v = *reinterpret_cast<const double4*>(qxi + 4 * (int64_t)cell);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) q[a] = B[4 * a] * v.x + B[4 * a + 1] * v.y + B[4 * a + 2] * v.z + B[4 * a + 3] * v.w;
+      }
+      if (qai) {
+        const double4 v = *reinterpret_cast<const double4*>(qai + 4 * (int64_t)cell);
+        q[0] += v.x; q[1] += v.y; q[2] += v.z; q[3] += v.w;
+      }
+      field_block(fblk, nf, fcell, cell, tht, B);
+      real Sm[16];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b2 = 0; b2 < 4; ++b2) Sm[4 * a + b2] = (real)(sgn[a] * sgn[b2] * B[4 * a + b2]);
+      real c[4];
+      cell_update_field<real, G, OPL>(L, g, i, r, cell, Sm, (real)q[0], (real)(sgn[1] * q[1]), (real)(sgn[2] * q[2]),
+                                      (real)(sgn[3] * q[3]), gx, gy, mx, my, xtr, ytr, c);
+      store_partial<real, G>(c, g, mx, my, P, cell);
+    }
+    __syncthreads();
+  }
+}
+
 // LDS-only work-group barrier: this wave's LDS operations complete, then
 // s_barrier.  Global loads stay in flight across it (they feed the next
 // diagonal); the empty asm statements stop the compiler from moving memory
@@ -810,7 +966,7 @@ int make_plan(rte_batch* b, int prec, int G, int threads, int opl) {
 // ordinates per lane and T threads (rows per slot, and the per-region tables).
 static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T) {
   const int slots = T / G;
-  return slots > 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB &&
+  return slots > 0 && b->n_fields == 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB &&
          b->max_regions * G * opl <= SWEEP_COEF_ENTRIES;
 }
 
@@ -831,6 +987,16 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
                     hipStream_t s, const int32_t* active, void* part) {
   const int per_xcd = (p.n_items + 7) / 8;
+  if (b->n_fields > 0) {  // cross sections varying inside the cells: the diagonal-slot field kernel
+    const size_t lds = sweep_lds(b, G, OPL, 0, sizeof(real));
+    if (lds > 64 * 1024) return RTE_EINVAL;
+    hipLaunchKernelGGL((sweep2d_field_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(p.threads), lds, s, b->d_inst,
+                       p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_fblk, b->n_fields, b->field_ncell,
+                       sigma_t, sigma_s, b->max_regions, qx, qadd, inflow, reinterpret_cast<real*>(part), psi_out,
+                       active, p.n_items, per_xcd);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, OPL, p.threads)) {
     const int slots = p.threads / G;
     const int nr = (b->max_ny + slots - 1) / slots;

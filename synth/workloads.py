@@ -32,7 +32,7 @@ __all__ = [
     "cfg4_batch", "tiny_2d", "tiny_1d", "CFG3_BOX_LO", "CFG3_BOX_HI", "cfg3_box_centre",
     "cfg3_sigma", "cfg3_sources", "cfg3_features", "cfg5_sets", "pincell_problem", "pincell_sets",
     "twomat_problem", "twomat_sets", "varscat_shape", "varscat_problem", "varscat_sets",
-    "field_point_values", "FIELD_NQ",
+    "field_point_values", "FIELD_NQ", "with_field_values",
 ]
 
 _GL4_X, _GL4_W = np.polynomial.legendre.leggauss(4)
@@ -326,10 +326,22 @@ def varscat_problem(mu_s, n=80, n_theta=30, n_z=6):
     box = (-1.0, 1.0, -1.0, 1.0)
     G = source_moments(lambda x, y: 10.0 / np.pi * np.exp(-100.0 * (x ** 2 + y ** 2)), 2, n, n, box)
     coef = np.array([float(mu_s), 0.1])
-    return dict(dim=2, nx=n, ny=n, box=box, quad=("cl", n_theta, n_z, True),
+    spec = dict(dim=2, nx=n, ny=n, box=box, quad=("cl", n_theta, n_z, True),
                 region=np.zeros(n * n, dtype=np.int32), sigma_fields=[varscat_shape, _one],
                 sigma_t=coef.copy(), sigma_s=coef.copy(), source=G, inflow=0.0,
                 mu=np.array([float(mu_s)]))
+    spec["field_values"] = _field_values_cached(n, box)
+    return spec
+
+
+_FV_CACHE = {}
+
+
+def _field_values_cached(n, box):
+    key = (n, box)
+    if key not in _FV_CACHE:
+        _FV_CACHE[key] = field_point_values(dict(nx=n, ny=n, box=box, sigma_fields=[varscat_shape, _one]))
+    return _FV_CACHE[key]
 
 
 def varscat_sets(n_test=10, seed=90):
@@ -355,3 +367,8 @@ def field_point_values(spec, nq=FIELD_NQ):
     X, Y = np.broadcast_arrays(X, Y)   # [k, i, gy, gx]
     return np.stack([np.asarray(f(X, Y), dtype=np.float64).reshape(nx * ny, nq * nq)
                      for f in spec["sigma_fields"]])
+
+
+def with_field_values(spec, nq=FIELD_NQ):
+    """spec with "field_values" (the library's input) sampled from its sigma_fields."""
+    return dict(spec, field_values=field_point_values(spec, nq))

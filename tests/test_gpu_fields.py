@@ -1,0 +1,188 @@
+"""Cross sections that vary inside the cells (the variable-scattering problem
+of section 5.3) on the GPU against the oracle: the sweep with full per-cell
+mass blocks, the DSA whose GMRES sees the full blocks, FGMRES with DSA and
+ROMSAD, the shape-weighted affine pieces of the ROM and the greedy."""
+import numpy as np
+import pytest
+
+from oracle import dsa as odsa
+from oracle import fgmres as ofg
+from oracle import rom as orom
+from oracle import transport as tr
+from synth import tiny_2d, varscat_shape, with_field_values
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def _one(x, y):
+    return np.ones_like(x)
+
+
+def _fspec(seed, mu, nx=9, ny=7, quad=("cl", 8, 4, True), inflow=0.0):
+    """A [-1,1]^2 instance with sigma_t = mu s + 0.3, sigma_s = 0.8 mu s + 0.1,
+    s the section 5.3 shape (non-polynomial across the unit circle)."""
+    spec = tiny_2d(seed=seed, nx=nx, ny=ny, quad=quad, n_regions=2, inflow=inflow)
+    # the fields replace the region map; a batch in this mode shares one geometry
+    spec = dict(spec, box=(-1.0, 1.0, -1.0, 1.0), region=np.zeros(nx * ny, np.int32),
+                sigma_fields=[varscat_shape, _one],
+                sigma_t=np.array([mu, 0.3]), sigma_s=np.array([0.8 * mu, 0.1]))
+    return with_field_values(spec)
+
+
+def _family(mus, **kw):
+    return [_fspec(3, m, **kw) for m in mus]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_field_sweep_parity(dtype, tol):
+    """rte_sweep (psi stored, with inflow), rte_apply_A and rte_rhs with full
+    per-cell blocks, for several lane shapes, against the oracle."""
+    import paper_2410_08735_amd as rt
+    specs = [_fspec(1, 20.0, inflow=0.4), _fspec(2, 3.0, inflow=0.0), _fspec(5, 60.0, inflow=1.0)]
+    for k in (1, 2):
+        specs[k]["source"] = specs[0]["source"] * (1.0 + 0.5 * k)
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(11)
+    qs = [rng.standard_normal(n) for n in B.ndofs]
+    for G, opl, T in ((8, 1, 256), (4, 2, 128), (8, 4, 512), (16, 1, 64)):
+        B.set_sweep_plan(dtype, 0, G, T, opl=opl)
+        phi, psi = rt.sweep(B, st, B.pack(qs), inflow=B.inflow(), phi=True, psi=True, dtype=dtype)
+        y = B.unpack(rt.apply_A(B, st, ss, B.pack(qs), dtype=dtype))
+        bt = B.unpack(rt.rhs(B, st, B.source(), inflow=B.inflow(), dtype=dtype))
+        for k, spec in enumerate(specs):
+            P = tr.Problem(spec)
+            qj = np.stack([qs[k] + P.gbc(j) for j in range(P.nord)])
+            ophi, opsi = tr.sweep(P, qj, store_psi=True)
+            assert rel(B.unpack(phi)[k], ophi) <= tol, (G, opl, k, rel(B.unpack(phi)[k], ophi))
+            assert rel(B.unpack_psi(psi)[k], opsi) <= 10 * tol, (G, opl, k)
+            assert rel(y[k], tr.A_tilde_apply(P, qs[k])) <= 10 * tol, (G, opl, k)
+            assert rel(bt[k], tr.b_tilde(P)) <= tol, (G, opl, k)
+    with pytest.raises(rt.RteError):  # the row-slot kernel needs region-wise cross sections
+        B.set_sweep_plan(dtype, 1, 8, 512, opl=4)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", ["fc", "pc"])
+def test_field_dsa_parity(variant):
+    """The DSA solve to 1e-14 equals the oracle's FC / PC DSA with the full
+    mass blocks; stationary V-cycles are rejected in this mode."""
+    import paper_2410_08735_amd as rt
+    specs = [_fspec(1, 20.0, nx=12, ny=8), _fspec(2, 80.0, nx=12, ny=8)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(4)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z, iters = rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=1e-14, inner_max=3000, restart=60, variant=variant)
+    for k, spec in enumerate(specs):
+        ref = odsa.DSA(tr.Problem(spec), variant).apply(v[k])
+        assert rel(B.unpack(z)[k], ref) <= 1e-11, (k, rel(B.unpack(z)[k], ref), iters)
+    with pytest.raises(rt.RteError):
+        rt.dsa_apply(B, st, ss, B.pack(v), inner_tol=0.0, inner_max=1, restart=0)
+
+
+def _oracle_solve(spec, pc="dsa", U=None, rtol=1e-13, variant="fc"):
+    P = tr.Problem(spec)
+    D = odsa.DSA(P, variant)
+    if pc == "dsa":
+        M = lambda j, v: D.apply(v)
+    else:
+        M = orom.Romsad(P, U, D, 2)
+    return ofg.fgmres(lambda x: tr.A_tilde_apply(P, x), tr.b_tilde(P), M, m=60, rtol=rtol)
+
+
+@pytest.mark.gpu
+def test_field_fgmres_dsa_parity_fp64_and_fp32():
+    import paper_2410_08735_amd as rt
+    specs = [_fspec(1, 20.0, nx=12, ny=10, inflow=0.2), _fspec(2, 70.0, nx=12, ny=10)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    exact = dict(precond="dsa", m=60, max_cycles=5, rtol=1e-13, dsa_inner_max=2000, dsa_restart=60,
+                 dsa_inner_tol=1e-14)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), rt.SolveOptions(sweep_dtype="f64", **exact))
+    assert ret == 0
+    refs = [_oracle_solve(spec) for spec in specs]
+    for k in range(2):
+        assert stats[k]["true_relres"] <= 1e-13
+        assert rel(B.unpack(phi)[k], refs[k].x) <= 1e-10
+        assert abs(stats[k]["iterations"] - refs[k].iterations) <= 1, (stats[k], refs[k].iterations)
+    f32 = dict(exact, rtol=1e-8, max_cycles=10, m=30, dsa_inner_tol=1e-10)
+    phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), rt.SolveOptions(sweep_dtype="f32", **f32))
+    assert ret == 0
+    for k in range(2):
+        assert stats[k]["true_relres"] <= 1e-8
+        assert rel(B.unpack(phi)[k], refs[k].x) <= 1e-6
+    with pytest.raises(rt.RteError):  # the DSA must be the exact solve here
+        rt.fgmres_solve(B, st, ss, B.source(), None, rt.SolveOptions(precond="dsa", dsa_restart=0, dsa_inner_max=1))
+    with pytest.raises(rt.RteError):
+        rt.si_solve(B, st, ss, B.source(), None, rt.SolveOptions(**exact))
+
+
+@pytest.fixture(scope="module")
+def field_rom():
+    fam = _family([10.0, 30.0, 50.0, 70.0, 90.0], nx=10, ny=8)
+    U, rep = orom.greedy(fam, window=2, eps_rom=0.0, n_giter=3, rtol_hf=1e-11)
+    return fam, U, rep
+
+
+@pytest.mark.gpu
+def test_field_rom_affine_terms_and_fgmres_romsad(field_rom):
+    """A ROM from the oracle's basis: its shape-weighted affine pieces equal the
+    oracle's, and FGMRES-ROMSAD matches the oracle (FC and PC DSA)."""
+    import torch
+
+    import paper_2410_08735_amd as rt
+    fam, U, rep = field_rom
+    test = _family([22.0, 61.0], nx=10, ny=8) + [fam[rep.sampled[1]]]
+    B = rt.Batch(test)
+    st, ss = B.sigma()
+    rom = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    P0 = tr.Problem(test[0])
+    ex = rom.export(P0.nord, P0.ndof, 2)
+    AD, G, S = orom.affine_terms(P0, U, 2)
+    assert np.abs(ex["AD"] - AD).max() <= 1e-12 * np.abs(AD).max()
+    assert np.abs(ex["G"] - G).max() <= 1e-12 * np.abs(G).max()
+    assert np.abs(ex["S"] - S).max() <= 1e-12 * np.abs(S).max()
+    rng = np.random.default_rng(8)
+    v = [rng.standard_normal(n) for n in B.ndofs]
+    z = B.unpack(rt.romsad_apply(rom, B, st, ss, B.pack(v)))
+    for k, spec in enumerate(test):
+        ref = orom.Romsad(tr.Problem(spec), U, None, 2).rom_apply(v[k])
+        assert rel(z[k], ref) <= 1e-12, (k, rel(z[k], ref))
+    for variant in ("fc", "pc"):
+        opts = rt.SolveOptions(precond="romsad", m=60, max_cycles=5, sweep_dtype="f64", rtol=1e-12, window=2,
+                               dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14, dsa_variant=variant)
+        phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, opts, rom=rom)
+        assert ret == 0
+        for k, spec in enumerate(test):
+            ref = _oracle_solve(spec, "romsad", U, rtol=1e-12, variant=variant)
+            assert rel(B.unpack(phi)[k], ref.x) <= 1e-10, (variant, k)
+            assert abs(stats[k]["iterations"] - ref.iterations) <= 1
+        # a sampled parameter: its snapshot (solved to 1e-11) is in the basis, so
+        # the ROM leaves a residual of that size and one more step reaches 1e-12
+        assert stats[-1]["iterations"] <= 2 < max(s["iterations"] for s in stats[:-1])
+
+
+@pytest.mark.gpu
+def test_field_greedy_matches_oracle(field_rom):
+    import torch
+
+    import paper_2410_08735_amd as rt
+    fam, U, rep = field_rom
+    B = rt.Batch(fam)
+    st, ss = B.sigma()
+    rom, grep = rt.romsad_build_greedy(B, st, ss, B.source(), None, window=2, mu1_index=0, eps_rom=0.0,
+                                       n_giter=3, hf_rtol=1e-11, hf_dsa_tol=1e-13)
+    assert grep["sampled"] == list(rep.sampled) and grep["rank"] == U.shape[0]
+    # the same span: both ROMs give the same preconditioned vector
+    ref = rt.Rom.from_basis(B, torch.from_numpy(U.reshape(-1)).cuda())
+    v = B.pack([np.random.default_rng(9).standard_normal(n) for n in B.ndofs])
+    a = B.unpack(rt.romsad_apply(rom, B, st, ss, v))
+    b = B.unpack(rt.romsad_apply(ref, B, st, ss, v))
+    for k in range(B.n):
+        assert rel(a[k], b[k]) <= 1e-7, (k, rel(a[k], b[k]))
+    with pytest.raises(rt.RteError):  # field mode needs the exact-solve DSA in the greedy
+        rt.romsad_build_greedy(B, st, ss, B.source(), None, window=2, n_giter=2, hf_dsa_tol=0.0)

@@ -607,7 +607,13 @@ def test_pincell_problem_reproduces_the_papers_sweep_counts():
     h = 2.0 / 80  # the paper's eps_ROM refers to a basis sqrt(h_x h_y) times the orthonormal one
     rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=gold["window"], mu1_index=0,
                                       eps_rom=gold["eps_rom"] / h, n_giter=25, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+    # the printed tolerance taken literally in this library's orthonormal basis
+    _, rep_lit = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=gold["window"], mu1_index=0,
+                                        eps_rom=gold["eps_rom"], n_giter=25, hf_rtol=1e-11, hf_dsa_tol=1e-12)
     del Btr, st, ss
+    print(f"pin-cell greedy: eps_ROM / h samples {len(rep['sampled'])} (rank {rep['rank']}), "
+          f"eps_ROM literal samples {len(rep_lit['sampled'])} (rank {rep_lit['rank']})")
+    assert len(rep_lit["sampled"]) >= len(rep["sampled"])
     assert abs(len(rep["sampled"]) - gold["greedy_sampled"]) <= 1, rep["sampled"]
     assert rep["rank"] == 2 * len(rep["sampled"]) - rep["truncated"]
     B = rt.Batch([pincell_problem(m) for m in te_mu])
@@ -762,8 +768,16 @@ def test_two_material_problem_reproduces_the_papers_table():
     h = 2.0 / 64
     rom, rep = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), Btr.inflow(), window=gold["window"], mu1_index=0,
                                       eps_rom=gold["eps_rom"] / h, n_giter=32, hf_rtol=1e-11, hf_dsa_tol=1e-12)
+    # the printed tolerance taken literally in this library's orthonormal basis
+    # (an empirical check of the basis-scaling reading: it samples more)
+    _, rep_lit = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), Btr.inflow(), window=gold["window"],
+                                        mu1_index=0, eps_rom=gold["eps_rom"], n_giter=32, hf_rtol=1e-11,
+                                        hf_dsa_tol=1e-12)
     del Btr, st, ss
+    print(f"two-material greedy: eps_ROM / h samples {len(rep['sampled'])} (rank {rep['rank']}), "
+          f"eps_ROM literal samples {len(rep_lit['sampled'])} (rank {rep_lit['rank']})")
     assert len(rep["sampled"]) == gold["greedy_sampled"] and rep["rank"] == gold["rom_dimension"]
+    assert len(rep_lit["sampled"]) >= len(rep["sampled"])
     B = rt.Batch([twomat_problem(m) for m in te_mu])
     st, ss = B.sigma()
     common = dict(m=60, max_cycles=10, sweep_dtype="f64", rtol=gold["rtol"], window=gold["window"],
