@@ -121,9 +121,11 @@ int rte_batch_max_regions(const rte_batch* b);
  * quadrant) and threads per work group.  The first sweep of a batch times
  * every admissible plan and keeps the fastest (the autotuner); setting a plan
  * fixes it.  set: RTE_EINVAL for a plan the batch cannot run (G in
- * {1,2,4,8,16,32}; opl 1, 2 with G in {4,8,16}, or 4 with G in {4,8}; threads a multiple of 64
- * up to 512 and of G; LDS within 64 KB; variant 1 needs
- * ceil(max_ny / (threads / G)) <= 8 rows per slot and at most 256 regions).
+ * {1,2,4,8,16,32}; opl 1, 2 with G in {4,8,16}, 4 with G in {4,8}, or 8
+ * with G = 4; threads a multiple of 64 and of G, up to 512; LDS within 64 KB;
+ * variant 1 needs ceil(max_ny / (threads / G)) <= 8 rows per slot and at
+ * most 256 regions, and takes up to 1024 threads when that is one row per
+ * slot, except in FP64 with opl 8).
  * get: out[5] = {variant, G, opl, threads, tuned}.                          */
 int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int opl, int threads);
 

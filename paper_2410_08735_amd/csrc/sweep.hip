@@ -114,8 +114,11 @@ __device__ __forceinline__ void local_solve(real sig, real a, real b, const real
 //   (al I - be K) v = ((al - be) v0 - sqrt3 be v1, (al - 3 be) v1 + sqrt3 be v0).
 // With M = adj0 / det0 and N = det0 adjS / detS the solve is
 //   v = M r_lo,  s = r_hi + sqrt3 b v,  x_hi = N s,  x_lo = M (r_lo - sqrt3 b x_hi),
-// c[0..2] = M, c[3..5] = N.  Coefficients in FP64 whatever the sweep's precision.
-__device__ __forceinline__ void solve_coef(double sig, double a, double b, double c[6]) {
+// c[0..2] = M, c[3..5] = N, and c[6..8] = sqrt3 b M, with which the last step
+// is x_lo = v - (sqrt3 b M) x_hi, the subtraction fused into its multiply-adds
+// (14 operations instead of 16); c[9] = 0 pads the table.  Coefficients in
+// FP64 whatever the sweep's precision.
+__device__ __forceinline__ void solve_coef(double sig, double a, double b, double c[10]) {
   const double r3 = 1.7320508075688772935;
   const double a0 = sig + b, a1 = sig + 3.0 * b;
   const double adj0a = a0 + 4.0 * a;
@@ -133,6 +136,10 @@ __device__ __forceinline__ void solve_coef(double sig, double a, double b, doubl
   c[3] = na - nb;
   c[4] = na - 3.0 * nb;
   c[5] = r3 * nb;
+  c[6] = r3 * b * c[0];
+  c[7] = r3 * b * c[1];
+  c[8] = r3 * b * c[2];
+  c[9] = 0.0;
 }
 
 template <typename real>
@@ -144,6 +151,24 @@ __device__ __forceinline__ void solve_apply(const real c[6], real br3, const rea
   const real e0 = r[0] - br3 * x[2], e1 = r[1] - br3 * x[3];
   x[0] = c[0] * e0 - c[2] * e1;
   x[1] = c[1] * e1 + c[2] * e0;
+}
+
+// The same with the last step as x_lo = v - Q x_hi, Q = sqrt3 b M in c[6..8].
+template <typename real>
+__device__ __forceinline__ void solve_apply_q(const real c[9], real br3, const real r[4], real x[4]) {
+  const real v0 = fmadd(-c[2], r[1], c[0] * r[0]), v1 = fmadd(c[2], r[0], c[1] * r[1]);
+  const real s0 = fmadd(br3, v0, r[2]), s1 = fmadd(br3, v1, r[3]);
+  x[2] = fmadd(-c[5], s1, c[3] * s0);
+  x[3] = fmadd(c[5], s0, c[4] * s1);
+  x[0] = fmadd(-c[6], x[2], fmadd(c[8], x[3], v0));
+  x[1] = fmadd(-c[7], x[3], fmadd(-c[8], x[2], v1));
+}
+
+// Planes of two reals per (region, lane ordinate) in the row-slot kernel's
+// coefficient table: M and N (three planes), and in FP32 also Q (two more).
+template <typename real>
+__host__ __device__ constexpr int coef_planes() {
+  return sizeof(real) == 4 ? 5 : 3;
 }
 
 // Two reals, the unit of the coefficient table in LDS.
@@ -242,7 +267,7 @@ __host__ __device__ constexpr int ytr_stride() {
 // inflow trace before the first column), the y trace to the next row through
 // LDS (ytr, preloaded with the inflow trace), and the local solve reads its
 // precomputed coefficients (ctab: this cell's region's block of Pair2 entries
-// [plane 0..2][OPL][G], so every address is a compile-time offset from the
+// [plane][OPL][G], so every address is a compile-time offset from the
 // lane's base).  q0..q3 arrive scaled and already in mirrored orientation.
 template <typename real, int G, int OPL, bool PSI>
 __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, int g, int i, int64_t cell,
@@ -264,10 +289,17 @@ __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, i
     rhs[2] = fmadd(-rb, ty0, fmadd(a, tx1, q2));
     rhs[3] = fmadd(-rb, ty1, fmadd(-ra, tx1, q3));
     const typename Pair2<real>::T* e = ctab + o * G;
-    const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G];
-    const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
     real x[4];
-    solve_apply<real>(cf, rb, rhs, x);
+    if constexpr (coef_planes<real>() == 5) {
+      const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G], p3 = e[3 * OPL * G],
+                                    p4 = e[4 * OPL * G];
+      const real cf[9] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y, p4.x};
+      solve_apply_q<real>(cf, rb, rhs, x);
+    } else {
+      const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G];
+      const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
+      solve_apply<real>(cf, rb, rhs, x);
+    }
     xt[o][0] = fmadd(r3, x[1], x[0]);
     xt[o][1] = fmadd(r3, x[3], x[2]);
     ytr[yo] = fmadd(r3, x[2], x[0]);
@@ -534,6 +566,12 @@ __device__ __forceinline__ void lds_barrier() {
 
 constexpr int SWEEP_SIGMA_TAB = 256;  // regions whose cross sections are staged in LDS
 constexpr int SWEEP_COEF_ENTRIES = 512;  // (region, lane ordinate) solve-coefficient entries in LDS
+// Largest work group of the row-slot kernel: 1024 threads with one row per
+// slot (512 for FP64 with 8 ordinates per lane, whose registers would not fit
+// the 128 per lane that 1024 threads leave), else 512.
+__host__ __device__ constexpr int rows_max_threads(int rows_per_slot, size_t elem, int opl) {
+  return rows_per_slot <= 1 && (elem == 4 || opl <= 4) ? 1024 : 512;
+}
 
 // The same sweep with a fixed row -> slot assignment (row r is handled by slot
 // r mod S), so a slot walks along its rows one cell per diagonal and loads the
@@ -548,7 +586,7 @@ constexpr int SWEEP_COEF_ENTRIES = 512;  // (region, lane ordinate) solve-coeffi
 // (n_regions <= SWEEP_SIGMA_TAB, n_regions * G * OPL <= SWEEP_COEF_ENTRIES).
 // SCALED: the source is sigma_s * q, else q as is (qsrc must be given).
 template <typename real, int G, int OPL, int MAXR, bool SCALED, bool PSI>
-__global__ void __launch_bounds__(512) sweep2d_rows_kernel(
+__global__ void __launch_bounds__(rows_max_threads(MAXR, sizeof(real), OPL)) sweep2d_rows_kernel(
     const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
     const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ region,
@@ -580,8 +618,9 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
   const int nreg = I.n_regions;
   real* tab = ytr + (size_t)nx * YS;               // [n_regions][4]
   using P2 = typename Pair2<real>::T;
-  P2* ctab = reinterpret_cast<P2*>(tab + 4 * nreg);  // [n_regions][3][OPL][G]
-  const int per_reg = 3 * OPL * G;
+  P2* ctab = reinterpret_cast<P2*>(tab + 4 * nreg);  // [n_regions][coef_planes][OPL][G]
+  constexpr int NPL = coef_planes<real>();
+  const int per_reg = NPL * OPL * G;
   {
     const double* st = sigma_t + (size_t)it.inst * max_regions;
     const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
@@ -596,11 +635,11 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
       const int rg = e / (G * OPL), j = e % (G * OPL);  // lane j / OPL, its ordinate j % OPL
       const bool on = j < it.count;
       const int js = I.ord_off + it.first + (on ? j : 0);
-      double cf[6];
+      double cf[10];
       solve_coef(st[rg], fabs(ox[js]) / I.hx, fabs(oy[js]) / I.hy, cf);
       P2* d = ctab + rg * per_reg + (j % OPL) * G + j / OPL;
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
+      for (int p = 0; p < NPL; ++p) {
         P2 v;
         v.x = (real)cf[2 * p];
         v.y = (real)cf[2 * p + 1];
@@ -623,7 +662,7 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
 
   double4 qn[MAXR];
   int rn[MAXR];
-  int cn[MAXR];           // physical index of each row's next cell
+  uint32_t cn[MAXR];      // physical index of each row's next cell
   real xt[MAXR][OPL][2];  // x traces of the slot's rows, the inflow trace first
 #pragma unroll
   for (int kk = 0; kk < MAXR; ++kk)
@@ -635,9 +674,9 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
 #pragma unroll
   for (int kk = 0; kk < MAXR; ++kk) {  // each row's first cell (rows past the grid: the last row's)
     const int r = min(slot + kk * S, ny - 1);
-    cn[kk] = (fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 : 0);
+    cn[kk] = (uint32_t)((fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 : 0));
     rn[kk] = reg[cn[kk]];
-    qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)cn[kk]);
+    qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * cn[kk]);
   }
 
   for (int s = 0; s < nx + ny - 1; ++s) {
@@ -648,7 +687,7 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
       if (r < ny && i >= 0 && i < nx) {
         const double4 v = qn[kk];
         const int rg = rn[kk];
-        const int cell = cn[kk];
+        const uint32_t cell = cn[kk];
         const real* sc = tab + 4 * rg;
         real c[4];
         cell_update_rows<real, G, OPL, PSI>(L, g, i, cell, sc[0] * (real)v.x, sc[1] * (real)v.y, sc[2] * (real)v.z,
@@ -660,7 +699,7 @@ __global__ void __launch_bounds__(512) sweep2d_rows_kernel(
         if (i + 1 < nx) {
           cn[kk] = cell + dx;
           rn[kk] = reg[cell + dx];
-          qn[kk] = *reinterpret_cast<const double4*>(qi + 4 * (int64_t)(cell + dx));
+          qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * (cell + dx));
         }
       }
     }
@@ -964,9 +1003,11 @@ int make_plan(rte_batch* b, int prec, int G, int threads, int opl) {
 
 // Whether the row-slot kernel can take this batch with G lanes per cell, OPL
 // ordinates per lane and T threads (rows per slot, and the per-region tables).
-static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T) {
+static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T, size_t es) {
   const int slots = T / G;
-  return slots > 0 && b->n_fields == 0 && (b->max_ny + slots - 1) / slots <= 8 && b->max_regions <= SWEEP_SIGMA_TAB &&
+  if (slots <= 0) return false;
+  const int nr = (b->max_ny + slots - 1) / slots;
+  return b->n_fields == 0 && nr <= 8 && T <= rows_max_threads(nr, es, opl) && b->max_regions <= SWEEP_SIGMA_TAB &&
          b->max_regions * G * opl <= SWEEP_COEF_ENTRIES;
 }
 
@@ -977,7 +1018,8 @@ static size_t sweep_lds(const rte_batch* b, int G, int opl, int variant, size_t 
   size_t n = (size_t)(b->max_nx + b->max_ny) * G * opl * 2;
   if (variant == 1) {
     const int ys = es == 4 ? 2 * G * opl + ((2 * G - 2 * G * opl) % 64 + 64) % 64 : 2 * G * opl;
-    n = (size_t)b->max_nx * ys + 4 * (size_t)b->max_regions + (size_t)6 * b->max_regions * G * opl;
+    const size_t planes = es == 4 ? coef_planes<float>() : coef_planes<double>();
+    n = (size_t)b->max_nx * ys + 4 * (size_t)b->max_regions + 2 * planes * b->max_regions * G * opl;
   }
   return n * es;
 }
@@ -987,17 +1029,18 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
                     hipStream_t s, const int32_t* active, void* part) {
   const int per_xcd = (p.n_items + 7) / 8;
+  const int tdiag = std::min(p.threads, 512);  // the diagonal-slot kernels take at most 512 threads
   if (b->n_fields > 0) {  // cross sections varying inside the cells: the diagonal-slot field kernel
     const size_t lds = sweep_lds(b, G, OPL, 0, sizeof(real));
     if (lds > 64 * 1024) return RTE_EINVAL;
-    hipLaunchKernelGGL((sweep2d_field_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(p.threads), lds, s, b->d_inst,
+    hipLaunchKernelGGL((sweep2d_field_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(tdiag), lds, s, b->d_inst,
                        p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_fblk, b->n_fields, b->field_ncell,
                        sigma_t, sigma_s, b->max_regions, qx, qadd, inflow, reinterpret_cast<real*>(part), psi_out,
                        active, p.n_items, per_xcd);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
-  if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, OPL, p.threads)) {
+  if (p.variant == 1 && (qx != nullptr) != (qadd != nullptr) && rows_variant_fits(b, G, OPL, p.threads, sizeof(real))) {
     const int slots = p.threads / G;
     const int nr = (b->max_ny + slots - 1) / slots;
     const size_t lds = sweep_lds(b, G, OPL, 1, sizeof(real));
@@ -1031,7 +1074,7 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
   }
   const size_t lds = sweep_lds(b, G, OPL, 0, sizeof(real));
   if (lds > 64 * 1024) return RTE_EINVAL;  // per-work-group LDS limit used by this library
-  hipLaunchKernelGGL((sweep2d_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(p.threads), lds, s,
+  hipLaunchKernelGGL((sweep2d_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(tdiag), lds, s,
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
                      sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
                      reinterpret_cast<real*>(part), psi_out, active, p.n_items, per_xcd);
@@ -1176,12 +1219,12 @@ int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s) {
 }
 
 int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int threads) {
-  if (!b || prec < 0 || prec > 1 || variant < 0 || variant > 1 || threads < 64 || threads > 512 ||
-      threads % 64 || !plan_shape_ok(G, opl) || threads % G)
+  if (!b || prec < 0 || prec > 1 || variant < 0 || variant > 1 || threads < 64 || threads > 1024 ||
+      threads % 64 || !plan_shape_ok(G, opl) || threads % G || (threads > 512 && (variant != 1 || b->dim != 2)))
     return RTE_EINVAL;
   if (b->dim == 2) {
     if (sweep_lds(b, G, opl, variant, prec == 0 ? 8 : 4) > 64 * 1024) return RTE_EINVAL;
-    if (variant == 1 && !rows_variant_fits(b, G, opl, threads)) return RTE_EINVAL;
+    if (variant == 1 && !rows_variant_fits(b, G, opl, threads, prec == 0 ? 8 : 4)) return RTE_EINVAL;
   }
   RTE_TRY(make_plan(b, prec, G, threads, opl));
   b->plan[prec].variant = variant;
@@ -1196,7 +1239,7 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
   Plan& cur = b->plan[prec];
   if (cur.tuned || b->dim == 1) return RTE_OK;
   const int cand_G[] = {4, 8, 16, 32};
-  const int cand_T[] = {128, 256, 512};
+  const int cand_T[] = {128, 256, 512, 768, 1024};  // above 512: row-slot kernel, one row per slot
   hipEvent_t e0, e1;
   RTE_HIP(hipEventCreate(&e0));
   RTE_HIP(hipEventCreate(&e1));
@@ -1246,8 +1289,8 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
       for (int G : cand_G) {
         if (!plan_shape_ok(G, O) || G * O > 32) continue;
         for (int T : cand_T) {
-          if (T % G || T / G < 1) continue;
-          if (V == 1 && !rows_variant_fits(b, G, O, T)) continue;
+          if (T % G || T / G < 1 || (V == 0 && T > 512)) continue;
+          if (V == 1 && !rows_variant_fits(b, G, O, T, prec == 0 ? 8 : 4)) continue;
           if (sweep_lds(b, G, O, V, prec == 0 ? 8 : 4) > 64 * 1024) continue;
           Cand c{V, O, G, T, 1e30f};
           RTE_TRY(time_plan(c, 3, c.ms));

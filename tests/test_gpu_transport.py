@@ -87,7 +87,8 @@ def test_sweep_parity_uneven_batch(dtype, tol):
 
 PLANS = [(0, 4, 1, 128), (0, 16, 1, 512), (0, 32, 1, 256), (1, 8, 1, 512), (1, 16, 1, 64), (1, 32, 1, 64),
          (1, 4, 1, 256), (0, 8, 2, 256), (0, 16, 2, 512), (1, 4, 2, 128), (1, 16, 2, 64), (0, 4, 4, 256),
-         (1, 8, 4, 512), (1, 8, 4, 256), (0, 4, 8, 128), (1, 4, 8, 64), (1, 4, 8, 128)]
+         (1, 8, 4, 512), (1, 8, 4, 256), (0, 4, 8, 128), (1, 4, 8, 64), (1, 4, 8, 128),
+         (1, 8, 4, 1024), (1, 16, 2, 768), (1, 8, 1, 768)]  # one row per slot above 512 threads
 
 
 @pytest.mark.gpu
@@ -145,9 +146,14 @@ def test_invalid_sweep_plans_rejected():
     import paper_2410_08735_amd as rt
     B = rt.Batch([tiny_2d(seed=1, nx=40, ny=40, quad=("cl", 8, 4, False))])
     for bad in [(0, 3, 128, 1), (0, 16, 96, 1), (2, 16, 128, 1), (0, 16, 1024, 1), (1, 32, 64, 1),  # 20 rows/slot
-                (0, 32, 256, 2), (0, 8, 256, 3), (0, 16, 256, 4)]:
+                (0, 32, 256, 2), (0, 8, 256, 3), (0, 16, 256, 4),
+                (1, 32, 1024, 1),   # 32 slots: 2 rows per slot above 512 threads
+                (1, 4, 768, 8),     # FP64 with 8 ordinates per lane: at most 512 threads
+                (1, 8, 1088, 4)]:   # above 1024 threads
         with pytest.raises(rt.RteError):
             B.set_sweep_plan("f64", *bad[:3], opl=bad[3])
+    B.set_sweep_plan("f32", 1, 4, 768, opl=8)  # the same shape in FP32 fits
+    B.set_sweep_plan("f64", 1, 8, 1024, opl=4)
 
 
 @pytest.mark.gpu
