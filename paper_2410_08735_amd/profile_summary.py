@@ -6,8 +6,10 @@
 For a kernel trace: two markdown tables, the kernels between the first two
 region markers (``rte::k_region_marker``, enqueued by ``rte_prof_mark``
 around a timed region) and the kernels of the whole process.  For a counter
-collection (``--pmc``): the mean counter value per dispatch of each kernel in
-the timed region, and of the copy between the third and fourth markers.
+collection (``--pmc``): the mean counter value per dispatch of each kernel
+between the first and second markers and between the third and fourth (in
+bench.py: the timed region and the calibration copy; in its learned leg, the
+network's training and the FGMRES-MLP solves).
 Kernel names are shortened to their qualified name and template arguments.
 """
 import collections
@@ -64,9 +66,11 @@ def summarise_counters(path, top=25):
     before it knows that every instance has converged); such dispatches are
     counted in their own column and left out of the mean."""
     rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
-    marks = [i for i, r in enumerate(rows) if MARKER in r["Kernel_Name"]]
+    # one row per (dispatch, counter): a marker is the first row of its dispatch
+    marks = [i for i, r in enumerate(rows) if MARKER in r["Kernel_Name"]
+             and (i == 0 or rows[i - 1]["Dispatch_Id"] != r["Dispatch_Id"])]
     out = []
-    for title, (a, b) in (("timed region (markers 1-2)", (0, 1)), ("copy probe (markers 3-4)", (2, 3))):
+    for title, (a, b) in (("between markers 1 and 2", (0, 1)), ("between markers 3 and 4", (2, 3))):
         if len(marks) <= b:
             continue
         per = collections.defaultdict(lambda: collections.defaultdict(dict))  # kernel -> dispatch -> counter
