@@ -30,6 +30,8 @@ struct rte_mlp {
   int cap = 0;
   std::vector<float*> H, Z;         // H[l]: layer-l input rows; Z[l]: pre-activations
   float *dA = nullptr, *dB = nullptr, *lossbuf = nullptr;
+  float* ws = nullptr;              // split-K partial sums of the weight-gradient products
+  int64_t ws_elems = 0;
 };
 
 namespace rte {
@@ -50,63 +52,24 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 }
 
 // C(m, n) = sum_k A(m, k) B(k, n) [+ bias(n)], strided operands, then an
-// optional epilogue: act 1 stores Z = C and C = gelu(C).
-// BF16 = true: one wave per 16 x 16 tile on the matrix cores.
-template <bool BF16>
-__global__ void k_gemm(int Mr, int Nc, int Kd, const float* __restrict__ A, int64_t sam, int64_t sak,
-                       const float* __restrict__ Bm, int64_t sbk, int64_t sbn, float* __restrict__ C,
-                       int64_t scm, int64_t scn, const float* __restrict__ bias, int act,
-                       float* __restrict__ Zout, int accumulate) {
-  if (BF16) {
-    const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int tn = (Nc + 15) / 16;
-    const int tm = (Mr + 15) / 16;
-    if (tile >= tm * tn) return;
-    const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
-    const int r = lane & 15, g = lane >> 4;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Kd; k0 += 16) {
-      bf16x4 a, b;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + 4 * g + q;
-        const int m = m0 + r, n = n0 + r;
-        const float av = (m < Mr && k < Kd) ? A[m * sam + k * sak] : 0.f;
-        const float bv = (n < Nc && k < Kd) ? Bm[k * sbk + n * sbn] : 0.f;
-        a[q] = f2bf(av);
-        b[q] = f2bf(bv);
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    // lane owns column n0 + r, rows m0 + 4 g + q
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = m0 + 4 * g + q, n = n0 + r;
-      if (m >= Mr || n >= Nc) continue;
-      float v = acc[q];
-      if (accumulate) v += C[m * scm + n * scn];
-      if (bias) v += bias[n];
-      if (act == 1) {
-        Zout[m * scm + n * scn] = v;
-        v = gelu_f(v);
-      }
-      C[m * scm + n * scn] = v;
-    }
-  } else {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (int64_t)Mr * Nc) return;
-    const int m = (int)(id / Nc), n = (int)(id % Nc);
-    float v = 0.f;
-    for (int k = 0; k < Kd; ++k) v += A[m * sam + k * sak] * Bm[k * sbk + n * sbn];
-    if (accumulate) v += C[m * scm + n * scn];
-    if (bias) v += bias[n];
-    if (act == 1) {
-      Zout[m * scm + n * scn] = v;
-      v = gelu_f(v);
-    }
-    C[m * scm + n * scn] = v;
+// optional epilogue: act 1 stores Z = C and C = gelu(C).  FP32 on the vector
+// units, one thread per entry (the exact path of the parity checks).
+__global__ void k_gemm_f32(int Mr, int Nc, int Kd, const float* __restrict__ A, int64_t sam, int64_t sak,
+                           const float* __restrict__ Bm, int64_t sbk, int64_t sbn, float* __restrict__ C,
+                           int64_t scm, int64_t scn, const float* __restrict__ bias, int act,
+                           float* __restrict__ Zout, int accumulate) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)Mr * Nc) return;
+  const int m = (int)(id / Nc), n = (int)(id % Nc);
+  float v = 0.f;
+  for (int k = 0; k < Kd; ++k) v += A[m * sam + k * sak] * Bm[k * sbk + n * sbn];
+  if (accumulate) v += C[m * scm + n * scn];
+  if (bias) v += bias[n];
+  if (act == 1) {
+    Zout[m * scm + n * scn] = v;
+    v = gelu_f(v);
   }
+  C[m * scm + n * scn] = v;
 }
 
 // The BF16 product on the matrix cores, LDS-tiled: a work group of 256
@@ -116,7 +79,7 @@ __global__ void k_gemm(int Mr, int Nc, int Kd, const float* __restrict__ A, int6
 // stride), rounds them to bfloat16 (nearest even) into LDS, and each wave
 // multiplies its 32 x 32 quarter as 2 x 2 v_mfma_f32_16x16x16_bf16 tiles per
 // 16-deep step, reading its fragments as 8-byte LDS words.  Epilogue as in
-// k_gemm.  Operand layout of one MFMA (lane = r + 16 g): A(m0 + r, k0 + 4 g + q),
+// k_gemm_f32.  Operand layout of one MFMA (lane = r + 16 g): A(m0 + r, k0 + 4 g + q),
 // B(k0 + 4 g + q, n0 + r) for q = 0..3; the result C(m0 + 4 g + q, n0 + r).
 constexpr int GT_BM = 64, GT_BN = 64, GT_BK = 32, GT_LD = GT_BK + 4;  // LDS row pitch (shorts)
 
@@ -189,6 +152,153 @@ __global__ void __launch_bounds__(256) k_gemm_tiled(int Mr, int Nc, int Kd, cons
       }
 }
 
+// The same product for operands whose unit-stride index is a multiple of 4
+// long with 16-byte aligned rows (every product of the network): a work group
+// of 256 threads (2 x 2 waves) computes a BM x BN block of C, each wave a
+// (BM / 2) x (BN / 2) part as (BM / 32) x (BN / 32) MFMA tiles.  Operands come
+// in as 16-byte loads along their unit-stride index, one K-chunk of 32 ahead:
+// the loads of chunk t + 1 are in flight while the matrix cores work on chunk
+// t from LDS, and are then rounded to bfloat16 into the other of two LDS
+// buffers (one barrier per chunk).  With part set, the work group takes the
+// K range [z kchunk, (z + 1) kchunk) of blockIdx.z and writes its raw sums to
+// part[z] (the epilogue is then k_splitk_reduce's).  Rounding and the order of
+// the 16-deep MFMA steps along K are those of k_gemm_tiled.
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) k_gemm_pipe(int Mr, int Nc, int Kd, const float* __restrict__ A, int64_t sam,
+                                                   int64_t sak, const float* __restrict__ Bm, int64_t sbk,
+                                                   int64_t sbn, float* __restrict__ C, int64_t scm, int64_t scn,
+                                                   const float* __restrict__ bias, int act,
+                                                   float* __restrict__ Zout, int accumulate, int kchunk,
+                                                   float* __restrict__ part) {
+  constexpr int BK = 32, LD = BK + 4;              // LDS row pitch in shorts (72 B: 8-byte aligned rows)
+  constexpr int TM = BM / 32, TN = BN / 32;        // MFMA tiles per wave along m and n
+  constexpr int NA = BM * BK / 4 / 256, NB = BN * BK / 4 / 256;  // float4 loads per thread
+  __shared__ short As[2][BM * LD];                 // [m][k]
+  __shared__ short Bs[2][BN * LD];                 // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int mb = blockIdx.y * BM, nb = blockIdx.x * BN;
+  const int r = lane & 15, g = lane >> 4;
+  const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * (BN / 2);
+  const int kbeg = blockIdx.z * kchunk, kend = min(Kd, kbeg + kchunk);
+  const bool a_k = sak == 1, b_k = sbk == 1;       // unit stride along k (else along m / n)
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float4 ra[NA], rb[NB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + 256 * i;
+      const int m = a_k ? e / (BK / 4) : (e % (BM / 4)) * 4, k = a_k ? (e % (BK / 4)) * 4 : e / (BM / 4);
+      const int gm = mb + m, gk = k0 + k;
+      ra[i] = (gm < Mr && gk < kend) ? *reinterpret_cast<const float4*>(A + gm * sam + gk * sak)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + 256 * i;
+      const int n = b_k ? e / (BK / 4) : (e % (BN / 4)) * 4, k = b_k ? (e % (BK / 4)) * 4 : e / (BN / 4);
+      const int gn = nb + n, gk = k0 + k;
+      rb[i] = (gn < Nc && gk < kend) ? *reinterpret_cast<const float4*>(Bm + gk * sbk + gn * sbn)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + 256 * i;
+      const bf16x4 v = {f2bf(ra[i].x), f2bf(ra[i].y), f2bf(ra[i].z), f2bf(ra[i].w)};
+      if (a_k) {
+        *reinterpret_cast<bf16x4*>(&As[buf][(e / (BK / 4)) * LD + (e % (BK / 4)) * 4]) = v;
+      } else {
+        const int m = (e % (BM / 4)) * 4, k = e / (BM / 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[buf][(m + q) * LD + k] = v[q];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int e = tid + 256 * i;
+      const bf16x4 v = {f2bf(rb[i].x), f2bf(rb[i].y), f2bf(rb[i].z), f2bf(rb[i].w)};
+      if (b_k) {
+        *reinterpret_cast<bf16x4*>(&Bs[buf][(e / (BK / 4)) * LD + (e % (BK / 4)) * 4]) = v;
+      } else {
+        const int n = (e % (BN / 4)) * 4, k = e / (BN / 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bs[buf][(n + q) * LD + k] = v[q];
+      }
+    }
+  };
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    stage(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);  // in flight during the products below
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x4 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf16x4*>(&As[buf][(wm + 16 * i + r) * LD + kk + 4 * g]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const bf16x4*>(&Bs[buf][(wn + 16 * j + r) * LD + kk + 4 * g]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stage(buf ^ 1);  // the other buffer: its last readers passed the previous barrier
+    __syncthreads();
+    buf ^= 1;
+  }
+  float* P = part ? part + (int64_t)blockIdx.z * Mr * Nc : nullptr;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = mb + wm + 16 * i + 4 * g + q, n = nb + wn + 16 * j + r;
+        if (m >= Mr || n >= Nc) continue;
+        float v = acc[i][j][q];
+        if (P) {
+          P[(int64_t)m * Nc + n] = v;
+          continue;
+        }
+        if (accumulate) v += C[m * scm + n * scn];
+        if (bias) v += bias[n];
+        if (act == 1) {
+          Zout[m * scm + n * scn] = v;
+          v = gelu_f(v);
+        }
+        C[m * scm + n * scn] = v;
+      }
+}
+
+// The split-K sums in the order z = 0, 1, ... and the epilogue of the product.
+__global__ void k_splitk_reduce(int Mr, int Nc, int nz, const float* __restrict__ part, float* __restrict__ C,
+                                int64_t scm, int64_t scn, const float* __restrict__ bias, int act,
+                                float* __restrict__ Zout, int accumulate) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)Mr * Nc;
+  if (id >= mn) return;
+  const int m = (int)(id / Nc), n = (int)(id % Nc);
+  float v = part[id];
+  for (int z = 1; z < nz; ++z) v += part[z * mn + id];
+  if (accumulate) v += C[m * scm + n * scn];
+  if (bias) v += bias[n];
+  if (act == 1) {
+    Zout[m * scm + n * scn] = v;
+    v = gelu_f(v);
+  }
+  C[m * scm + n * scn] = v;
+}
+
 // dY = 2 (Y_net * scale + shift - T) * scale / (rows * cols) in network units, loss partials
 __global__ void k_mse_grad(int rows, int cols, const float* __restrict__ Y, const float* __restrict__ T,
                            const float* __restrict__ scale, const float* __restrict__ shift,
@@ -228,13 +338,31 @@ __global__ void k_gelu_back(int64_t n, const float* __restrict__ Z, float* __res
     d[i] *= gelu_grad_f(Z[i]);
 }
 
-// db[o] = sum_rows d[row][o]
-__global__ void k_colsum(int rows, int cols, const float* __restrict__ d, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
-  float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += d[(int64_t)r * cols + c];
-  out[c] = s;
+// db[o] = sum_rows d[row][o]: a work group of 64 x 8 threads takes 64
+// columns; thread (c, y) sums rows y, y + 8, ... (four accumulators, so that
+// loads overlap), and the 8 partial sums are added in a fixed order.
+constexpr int COLSUM_ROWS = 8;
+__global__ void __launch_bounds__(64 * COLSUM_ROWS) k_colsum(int rows, int cols, const float* __restrict__ d,
+                                                              float* __restrict__ out) {
+  __shared__ float part[COLSUM_ROWS][64];
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  const int c = blockIdx.x * 64 + tx;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  if (c < cols) {
+    int r = ty;
+    for (; r + 3 * COLSUM_ROWS < rows; r += 4 * COLSUM_ROWS)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] += d[(int64_t)(r + k * COLSUM_ROWS) * cols + c];
+    for (; r < rows; r += COLSUM_ROWS) s[0] += d[(int64_t)r * cols + c];
+  }
+  part[ty][tx] = (s[0] + s[1]) + (s[2] + s[3]);
+  __syncthreads();
+  if (ty == 0 && c < cols) {
+    float t = part[0][tx];
+#pragma unroll
+    for (int k = 1; k < COLSUM_ROWS; ++k) t += part[k][tx];
+    out[c] = t;
+  }
 }
 
 // Adam (Kingma & Ba) on the flat parameter vector
@@ -287,16 +415,54 @@ __global__ void k_col_stats(int rows, int cols, const float* __restrict__ T, flo
   scale[c] = (float)(sd > 1e-12 ? sd : 1.0);
 }
 
+// Whether an operand suits k_gemm_pipe's 16-byte loads: a unit stride along
+// one of its indices, that index's length and the other stride multiples of
+// 4, and a 16-byte aligned base.
+static bool vec4_operand(const float* p, int64_t s_row, int64_t s_col, int rows, int cols) {
+  if (reinterpret_cast<uintptr_t>(p) % 16) return false;
+  if (s_col == 1) return cols % 4 == 0 && s_row % 4 == 0;
+  if (s_row == 1) return rows % 4 == 0 && s_col % 4 == 0;
+  return false;
+}
+
+// ws (ws_elems floats): room for split-K partial sums; without it no split.
 static int gemm(bool bf16, int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,
                 int64_t sbk, int64_t sbn, float* C, int64_t scm, int64_t scn, const float* bias, int act,
-                float* Z, int accumulate, hipStream_t s) {
+                float* Z, int accumulate, hipStream_t s, float* ws = nullptr, int64_t ws_elems = 0) {
   if (M <= 0 || N <= 0) return RTE_OK;
   if (bf16) {
-    hipLaunchKernelGGL(k_gemm_tiled, dim3((N + GT_BN - 1) / GT_BN, (M + GT_BM - 1) / GT_BM), dim3(256), 0, s, M, N,
-                       K, A, sam, sak, B, sbk, sbn, C, scm, scn, bias, act, Z, accumulate);
+    if (!vec4_operand(A, sam, sak, M, K) || !vec4_operand(B, sbk, sbn, K, N)) {
+      hipLaunchKernelGGL(k_gemm_tiled, dim3((N + GT_BN - 1) / GT_BN, (M + GT_BM - 1) / GT_BM), dim3(256), 0, s, M, N,
+                         K, A, sam, sak, B, sbk, sbn, C, scm, scn, bias, act, Z, accumulate);
+      RTE_HIP(hipGetLastError());
+      return RTE_OK;
+    }
+    const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+    const int64_t t64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+    // a long K with few output tiles (the weight gradients: K = rows) is
+    // split into chunks of whole 32-deep steps, summed in a fixed order
+    int nz = 1, kchunk = K;
+    if (ws && t64 < 128 && K >= 2048) {
+      nz = (int)std::min<int64_t>({16, K / 512, (256 + t64 - 1) / t64, ws_elems / ((int64_t)M * N)});
+      nz = std::max(nz, 1);
+      kchunk = ((K + nz - 1) / nz + 31) / 32 * 32;
+      nz = (K + kchunk - 1) / kchunk;
+    }
+    float* part = nz > 1 ? ws : nullptr;
+    if (t128 >= 256)
+      hipLaunchKernelGGL((k_gemm_pipe<128, 128>), dim3((N + 127) / 128, (M + 127) / 128, nz), dim3(256), 0, s, M, N,
+                         K, A, sam, sak, B, sbk, sbn, C, scm, scn, bias, act, Z, accumulate, kchunk, part);
+    else
+      hipLaunchKernelGGL((k_gemm_pipe<64, 64>), dim3((N + 63) / 64, (M + 63) / 64, nz), dim3(256), 0, s, M, N, K, A,
+                         sam, sak, B, sbk, sbn, C, scm, scn, bias, act, Z, accumulate, kchunk, part);
+    if (part) {
+      const int64_t mn = (int64_t)M * N;
+      hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, M, N, nz, part, C,
+                         scm, scn, bias, act, Z, accumulate);
+    }
   } else {
     const int64_t n = (int64_t)M * N;
-    hipLaunchKernelGGL(k_gemm<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, N, K, A, sam,
+    hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, N, K, A, sam,
                        sak, B, sbk, sbn, C, scm, scn, bias, act, Z, accumulate);
   }
   RTE_HIP(hipGetLastError());
@@ -323,6 +489,13 @@ static int mlp_reserve(rte_mlp* m, int rows) {
       hipMalloc(&m->dB, sizeof(float) * (size_t)rows * wmax) != hipSuccess ||
       hipMalloc(&m->lossbuf, sizeof(float) * 1024) != hipSuccess)
     return RTE_ENOMEM;
+  if (!m->ws) {
+    m->ws_elems = (int64_t)16 * wmax * wmax;
+    if (hipMalloc(&m->ws, sizeof(float) * (size_t)m->ws_elems) != hipSuccess) {
+      m->ws_elems = 0;
+      return RTE_ENOMEM;
+    }
+  }
   m->cap = rows;
   return RTE_OK;
 }
@@ -354,8 +527,9 @@ static int mlp_backward_ws(rte_mlp* m, int rows, const float* T, bool bf16, hipS
                          m->Z[l + 1], d);
     }
     // dW[o][i] = sum_r d[r][o] H[r][i];  db[o] = sum_r d[r][o]
-    RTE_TRY(gemm(bf16, o, in, rows, d, 1, o, m->H[l], in, 1, m->G + m->woff[l], in, 1, nullptr, 0, nullptr, 0, s));
-    hipLaunchKernelGGL(k_colsum, dim3((o + 255) / 256), dim3(256), 0, s, rows, o, d, m->G + m->boff[l]);
+    RTE_TRY(gemm(bf16, o, in, rows, d, 1, o, m->H[l], in, 1, m->G + m->woff[l], in, 1, nullptr, 0, nullptr, 0, s,
+                 m->ws, m->ws_elems));
+    hipLaunchKernelGGL(k_colsum, dim3((o + 63) / 64), dim3(64 * COLSUM_ROWS), 0, s, rows, o, d, m->G + m->boff[l]);
     if (l > 0)  // d_in[r][i] = sum_o d[r][o] W[o][i]
       RTE_TRY(gemm(bf16, rows, in, o, d, o, 1, m->P + m->woff[l], in, 1, dn, in, 1, nullptr, 0, nullptr, 0, s));
     std::swap(d, dn);
@@ -579,7 +753,7 @@ extern "C" int rte_mlp_create(int n_in, int width, int depth, int n_out, rte_mlp
 extern "C" void rte_mlp_destroy(rte_mlp* m) {
   if (!m) return;
   for (void* p : {(void*)m->P, (void*)m->M, (void*)m->V, (void*)m->G, (void*)m->yscale, (void*)m->yshift,
-                  (void*)m->dA, (void*)m->dB, (void*)m->lossbuf})
+                  (void*)m->dA, (void*)m->dB, (void*)m->lossbuf, (void*)m->ws})
     (void)hipFree(p);
   for (float* p : m->H) (void)hipFree(p);
   for (float* p : m->Z) (void)hipFree(p);
