@@ -26,11 +26,11 @@ METRIC = "FGMRES solves/s to rel-res 1e-8 (MLP vs ROMSAD vs plain); sweep GDoF/s
 # inflow right-hand side, 40-60 for the local 4x4 solve, 8 for the outgoing
 # traces, 8 for the weighted quadrature sum; an FMA counts as two).
 SWEEP_FLOPS_PER_CELL_ORD = 70.0
-# What the kernel executes per cell-ordinate: 8 FMA for the right-hand side,
-# 10 FMA and 6 multiplies for the local solve with its per-(region, ordinate)
-# coefficients formed once per work item, 4 FMA for the traces, 4 FMA for the
-# weighted sum (16 + 26 + 8 + 8).
-SWEEP_EXECUTED_FLOPS_PER_CELL_ORD = 58.0
+# What the FP32 kernel executes per cell-ordinate: 8 FMA for the right-hand
+# side, 10 FMA and 4 multiplies for the local solve with its per-(region,
+# ordinate) coefficients formed once per work item, 4 FMA for the traces, 4 FMA
+# for the weighted sum (16 + 24 + 8 + 8).
+SWEEP_EXECUTED_FLOPS_PER_CELL_ORD = 56.0
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak (packed two-wide FMA), FLOP/s
 # FP32 ALU ceiling of the unpacked instructions this library emits (it is built
 # without packed FP32): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
@@ -42,12 +42,23 @@ PEAK_HBM = 8.0e12             # MI355X published HBM3E bandwidth, B/s
 # counter passes scaled by what the counters read for a 512 MiB copy, keyed by
 # (variant, G, ordinates per lane, threads) and valid for the kernel version
 # SWEEP_KERNEL_VERSION the passes measured (profiles/sweep2d_f32_cfg3_96sq_b256_hbm_traffic.md).
-SWEEP_KERNEL_VERSION = "rows-v1"
-SWEEP_F32_TRAFFIC_BYTES = {}
+SWEEP_KERNEL_VERSION = "rows-v2"
+SWEEP_F32_TRAFFIC_BYTES = {
+    # FETCH_SIZE 107992.1 KiB x 1.9999 + WRITE_SIZE 193117.9 KiB x 1.0
+    ("rows-v2", 1, 8, 4, 768): 409091.7 * 1024,
+}
+# VALU lane instructions per cell-ordinate of a full launch (SQ_INSTS_VALU x 64
+# / cell-ordinates, profiles/sweep2d_f32_cfg3_96sq_b256_sq_counters.md)
+SWEEP_F32_VALU_LANE_INSTS = {("rows-v2", 1, 8, 4, 768): 210038784.0 * 64 / 301989888.0}
 # Algorithmic HBM bytes per cell and instance of one sweep: read the 4 source
 # moments (FP64, 32 B), write the 4 scalar-flux moments (FP64, 32 B), and the
 # cell's cross-section data (8 B).  Angular fluxes never leave the chip.
 SWEEP_ALG_BYTES_PER_CELL = 72.0
+
+
+def _json(obj):
+    """One JSON line; numpy scalars as plain numbers."""
+    return json.dumps(obj, default=lambda o: o.item() if hasattr(o, "item") else str(o))
 
 
 def plan_key(plan):
@@ -344,7 +355,7 @@ def pincell_leg(args):
            "paper": {"gmres_dsa_nsweep": 15.5, "fgmres_romsad_nsweep": 5.1, "sampled": 22, "rank": 44}}
     _, lit = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), None, window=2, mu1_index=0, eps_rom=1e-10,
                                     n_giter=25, eps_qr=1e-13, hf_rtol=1e-11, hf_dsa_tol=1e-12)
-    out["literal_eps"] = {"sampled": len(lit["sampled"]), "rank": lit["rank"]}
+    out["literal_eps"] = {"sampled": len(lit["sampled"]), "rank": int(lit["rank"])}
     del Btr, st, ss
     B = rt.Batch([pincell_problem(m) for m in te_mu])
     st, ss = B.sigma()
@@ -377,7 +388,7 @@ def pincell_leg(args):
     st, ss = B1.sigma()
     G = B1.source()
     cmp = {"sampled": len(rep1["sampled"]), "rank": rep1["rank"],
-           "literal_eps": {"sampled": len(lit1["sampled"]), "rank": lit1["rank"]},
+           "literal_eps": {"sampled": len(lit1["sampled"]), "rank": int(lit1["rank"])},
            "paper": {"gmres_dsa": 15, "si_dsa": 49, "fgmres_romsad": 10, "si_romsad": "100 (not converged)",
                      "first_correction_relres": {"gmres_dsa": 6.23e-2, "si_dsa": 1.17e-1,
                                                  "fgmres_romsad": 4.87e-6, "si_romsad": 4.90e-6},
@@ -390,8 +401,9 @@ def pincell_leg(args):
         _, stats, _ = solver(B1, st, ss, G, None, rt.SolveOptions(precond=pc, **full), **kw)
         first = dict(one, m=1, max_cycles=1)
         _, s1, _ = solver(B1, st, ss, G, None, rt.SolveOptions(precond=pc, **first), **kw)
-        cmp[name] = {"n_sweep": 1 + stats[0]["iterations"], "converged": stats[0]["true_relres"] <= 1e-11,
-                     "true_relres": stats[0]["true_relres"], "first_correction_relres": s1[0]["true_relres"]}
+        cmp[name] = {"n_sweep": 1 + int(stats[0]["iterations"]), "converged": bool(stats[0]["true_relres"] <= 1e-11),
+                     "true_relres": float(stats[0]["true_relres"]),
+                     "first_correction_relres": float(s1[0]["true_relres"])}
         log(f"pin-cell compare: {name}: n_sweep {1 + stats[0]['iterations']}, relres {stats[0]['true_relres']:.2e}, "
             f"after the first correction {s1[0]['true_relres']:.2e}")
     out["si_comparison"] = cmp
@@ -422,7 +434,7 @@ def twomat_leg(args):
            "paper": {"gmres_dsa_nsweep": 10.0, "fgmres_romsad_nsweep": 4.3, "sampled": 9, "rank": 18}}
     _, lit = rt.romsad_build_greedy(Btr, st, ss, Btr.source(), Btr.inflow(), window=2, mu1_index=0, eps_rom=1e-9,
                                     n_giter=32, eps_qr=1e-13, hf_rtol=1e-11, hf_dsa_tol=1e-12)
-    out["literal_eps"] = {"sampled": len(lit["sampled"]), "rank": lit["rank"]}
+    out["literal_eps"] = {"sampled": len(lit["sampled"]), "rank": int(lit["rank"])}
     del Btr, st, ss
     B = rt.Batch([twomat_problem(m) for m in te_mu])
     st, ss = B.sigma()
@@ -484,7 +496,7 @@ def sweep_leg(args):
 
 
 def _greedy_counts(rep):
-    return len(rep["sampled"]), rep["rank"]
+    return len(rep["sampled"]), int(rep["rank"])
 
 
 def varscat_leg(args):
@@ -602,23 +614,23 @@ def main():
                   window_cycles=args.window_cycles)
     if args.only_mlp:
         out = learned_leg(args, common)
-        print(json.dumps({"learned": {k: v for k, v in out.items() if not k.startswith("_")}}), flush=True)
+        print(_json({"learned": {k: v for k, v in out.items() if not k.startswith("_")}}), flush=True)
         return
     if args.only_twomat:
-        print(json.dumps({"twomat": twomat_leg(args)}), flush=True)
+        print(_json({"twomat": twomat_leg(args)}), flush=True)
         return
     if args.only_pincell:
-        print(json.dumps({"pincell": pincell_leg(args)}), flush=True)
+        print(_json({"pincell": pincell_leg(args)}), flush=True)
         return
     if args.only_varscat:
-        print(json.dumps({"varscat": varscat_leg(args)}), flush=True)
+        print(_json({"varscat": varscat_leg(args)}), flush=True)
         return
     if args.only_sweep:
-        print(json.dumps({"sweep": sweep_leg(args)}), flush=True)
+        print(_json({"sweep": sweep_leg(args)}), flush=True)
         return
     if args.only_uneven:
         out = uneven_leg(args, common)
-        print(json.dumps({"uneven": {k: v for k, v in out.items() if not k.startswith("_")}}), flush=True)
+        print(_json({"uneven": {k: v for k, v in out.items() if not k.startswith("_")}}), flush=True)
         return
     tr_mu, te_mu = cfg3_train_test(n_train=args.n_train, n_test=args.n_test)
     n = args.grid
@@ -709,6 +721,9 @@ def main():
                      "traffic": (SWEEP_F32_TRAFFIC_BYTES.get((SWEEP_KERNEL_VERSION,) + plan_key(B.sweep_plan("f32")))
                                  if (n == 96 and len(te_mu) == 256) else None),
                      "traffic_unit": "HBM B per full launch (256 instances active)",
+                     "valu_lane_instructions_per_cell_ordinate": (
+                         SWEEP_F32_VALU_LANE_INSTS.get((SWEEP_KERNEL_VERSION,) + plan_key(B.sweep_plan("f32")))
+                         if (n == 96 and len(te_mu) == 256) else None),
                      "flops_per_cell_ordinate": SWEEP_FLOPS_PER_CELL_ORD,
                      "executed_flops_per_cell_ordinate": SWEEP_EXECUTED_FLOPS_PER_CELL_ORD,
                      "peak_unpacked_fp32": PEAK_FP32_ALU / 1e12,
@@ -772,12 +787,19 @@ def main():
         for dt_name in ("f32", "f64"):
             rt.sweep(B2, st2, q2, dtype=dt_name)
             torch.cuda.synchronize()
+            rt.prof_enable(True)
             t = time.perf_counter()
             for _ in range(20):
                 rt.sweep(B2, st2, q2, dtype=dt_name)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t) / 20
+            nk, msk, _ = rt.prof_read("sweep_" + dt_name)
+            rt.prof_enable(False)
+            # per call of rte_sweep (host, launch and reduction included), and
+            # per sweep kernel launch (HIP events around the launch)
             gd[f"single64sq_{dt_name}"] = B2.ndofs[0] * B2.n_ords[0] / el / 1e9
+            gd[f"single64sq_{dt_name}_kernel"] = B2.ndofs[0] * B2.n_ords[0] / (msk / max(nk, 1) * 1e-3) / 1e9
+            gd[f"single64sq_{dt_name}_plan"] = B2.sweep_plan(dt_name)
         out["sweep_gdof_s"] = gd
         log(f"sweep GDoF/s: {gd}")
 
@@ -824,10 +846,10 @@ def main():
         if "cfg4" in gpu_phis:
             out["error_vs_oracle"]["cfg4_uneven_one_per_group"] = error_summary(gpu_phis["cfg4"], res, "cfg4")
         log(f"CPU baseline: {out['cpu_baseline']['value']:.4f} solves/s; error vs oracle "
-            f"{json.dumps(out['error_vs_oracle'])}")
+            f"{_json(out['error_vs_oracle'])}")
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+    print(_json(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -116,7 +116,9 @@ int64_t rte_batch_total_psi(const rte_batch* b);
 int rte_batch_max_regions(const rte_batch* b);
 /* The 2D sweep's launch plan per precision (dtype RTE_F64 / RTE_F32): kernel
  * variant (0: work-group slots follow the wavefront diagonal; 1: each slot
- * owns fixed rows and prefetches their next source values), G lanes per cell
+ * owns fixed rows and prefetches their next source values; 2: one wave per
+ * work item, one lane per row, y traces passed between lanes, no barrier:
+ * for batches of a few instances), G lanes per cell
  * group, opl ordinates per lane (a work group sweeps G * opl ordinates of one
  * quadrant) and threads per work group.  The first sweep of a batch times
  * every admissible plan and keeps the fastest (the autotuner); setting a plan
@@ -125,9 +127,18 @@ int rte_batch_max_regions(const rte_batch* b);
  * with G = 4; threads a multiple of 64 and of G, up to 512; LDS within 64 KB;
  * variant 1 needs ceil(max_ny / (threads / G)) <= 8 rows per slot and at
  * most 256 regions, and takes up to 1024 threads when that is one row per
- * slot, except in FP64 with opl 8).
- * get: out[5] = {variant, G, opl, threads, tuned}.                          */
+ * slot, except in FP64 with opl 8; variant 2 needs G = 1, threads = 64,
+ * opl 1, 2 or 4, max_ny <= 256 and at most 256 regions).
+ * Setting a plan resets the work-item order to 0.
+ * get: out[6] = {variant, G, opl, threads, tuned, order}.                   */
 int rte_batch_set_sweep_plan(rte_batch* b, int dtype, int variant, int G, int opl, int threads);
+/* The order in which a sweep's work items start (0: instance by instance,
+ * each XCD a contiguous run, so an instance's ordinate blocks share one L2;
+ * 1: by decreasing cell-ordinates, dealt round robin over the XCDs, so that
+ * in a batch of unequal instances the largest start first).  The autotuner
+ * times both on its best plans for such batches.  RTE_EINVAL for another
+ * value.                                                                   */
+int rte_batch_set_sweep_order(rte_batch* b, int dtype, int order);
 
 /* Cross sections that vary inside the cells (the variable-scattering problem
  * of section 5.3): sigma_t(x) = sum_f theta_t,f s_f(x) and sigma_s(x) =

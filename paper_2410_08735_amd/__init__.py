@@ -96,14 +96,17 @@ class Batch:
             check(lib.rte_batch_set_fields(h, int(fv.shape[0]), nq, fv.ctypes.data_as(L.pdbl)),
                   "rte_batch_set_fields")
 
-    def set_sweep_plan(self, dtype, variant, G, threads, opl=1):
+    def set_sweep_plan(self, dtype, variant, G, threads, opl=1, order=0):
         check(L.lib().rte_batch_set_sweep_plan(self.h, _dt(dtype), variant, G, opl, threads),
               "rte_batch_set_sweep_plan")
+        if order:
+            check(L.lib().rte_batch_set_sweep_order(self.h, _dt(dtype), order), "rte_batch_set_sweep_order")
 
     def sweep_plan(self, dtype):
-        out = (L.i32 * 5)()
+        out = (L.i32 * 6)()
         check(L.lib().rte_batch_sweep_plan(self.h, _dt(dtype), out), "rte_batch_sweep_plan")
-        return {"variant": out[0], "G": out[1], "opl": out[2], "threads": out[3], "tuned": bool(out[4])}
+        return {"variant": out[0], "G": out[1], "opl": out[2], "threads": out[3], "tuned": bool(out[4]),
+                "order": out[5]}
 
     def __del__(self):
         try:

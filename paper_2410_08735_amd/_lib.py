@@ -99,6 +99,7 @@ SIGNATURES = {
     "rte_batch_set_sweep_plan": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "rte_batch_set_fields": (C.c_int, [vp, C.c_int, C.c_int, pdbl]),
     "rte_batch_sweep_plan": (C.c_int, [vp, C.c_int, C.POINTER(i32)]),
+    "rte_batch_set_sweep_order": (C.c_int, [vp, C.c_int, C.c_int]),
     "rte_prof_enable": (C.c_int, [C.c_int]),
     "rte_prof_mark": (C.c_int, [C.c_int, vp]),
     "rte_prof_read": (C.c_int, [C.c_int, C.POINTER(i64), C.POINTER(dbl), C.POINTER(dbl)]),

@@ -61,5 +61,10 @@ extern "C" int rte_batch_sweep_plan(const rte_batch* b, int dtype, int32_t* out)
   out[2] = p.opl;
   out[3] = p.threads;
   out[4] = p.tuned ? 1 : 0;
+  out[5] = p.order;
   return RTE_OK;
+}
+
+extern "C" int rte_batch_set_sweep_order(rte_batch* b, int dtype, int order) {
+  return rte::set_sweep_order(b, prec_of(dtype), order);
 }

@@ -64,6 +64,9 @@ struct Plan {
   int threads = 256;
   int variant = 0;  // 2D kernel: 0 = diagonal-slot order, 1 = row-slot order with source prefetch
   int opl = 1;      // ordinates per lane (2D): a work item holds G * opl ordinates
+  int order = 0;    // work items: 0 = in instance order, each XCD a contiguous run (an
+                    // instance's blocks share one L2); 1 = by decreasing cell-ordinates,
+                    // dealt round robin over the XCDs (the largest start first)
   std::vector<SweepItem> items;
   std::vector<InstPart> parts;
   SweepItem* d_items = nullptr;
@@ -135,6 +138,7 @@ int field_apply(const rte_batch* b, const double* theta, const double* x, double
 int validate_cross_sections(const rte_batch* b, const double* sigma_t, const double* sigma_s, hipStream_t s);
 int make_plan(rte_batch* b, int prec, int G, int threads, int opl = 1);
 int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int threads);
+int set_sweep_order(rte_batch* b, int prec, int order);
 // prof_units: cell-ordinates processed by this launch (for the event profiler);
 // -1 = every instance of the batch; below -1.5 = no profiler events (used
 // while a stream is being captured into a graph).  part_buf: where the

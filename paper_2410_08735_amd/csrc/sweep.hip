@@ -53,6 +53,15 @@ __device__ __forceinline__ double dpp_move(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// The work item of this work group.  per_xcd > 0: the hardware deals work
+// groups to the 8 XCDs round robin, and this mapping gives each XCD a
+// contiguous run of per_xcd items (an instance's ordinate blocks share one
+// L2).  per_xcd = 0: work group b takes item b (items already in the order
+// they should start, dealt round robin over the XCDs by the hardware).
+__device__ __forceinline__ int work_item(int per_xcd) {
+  return per_xcd > 0 ? (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u) : (int)blockIdx.x;
+}
+
 // Sum over each aligned group of G adjacent lanes; every lane of the group
 // receives the group's sum.  Steps inside a row use DPP; across rows (G = 32)
 // a cross-lane shuffle.
@@ -269,6 +278,42 @@ __host__ __device__ constexpr int ytr_stride() {
 // precomputed coefficients (ctab: this cell's region's block of Pair2 entries
 // [plane][OPL][G], so every address is a compile-time offset from the
 // lane's base).  q0..q3 arrive scaled and already in mirrored orientation.
+// One ordinate o of one cell from its inflow traces (tx along x, ty along y):
+// the right-hand side, the local solve with the coefficients at e (planes
+// OPL * G apart), and the solution x in mirrored orientation.
+template <typename real, int G, int OPL>
+__device__ __forceinline__ void ordinate_solve(const LaneOrds<real, OPL>& L, int o, real q0, real q1, real q2,
+                                               real q3, real tx0, real tx1, real ty0, real ty1,
+                                               const typename Pair2<real>::T* e, real x[4]) {
+  const real r3 = (real)1.7320508075688772935;
+  const real a = L.a[o], b = L.b[o];
+  const real ra = r3 * a, rb = r3 * b;
+  real rhs[4];
+  rhs[0] = fmadd(b, ty0, fmadd(a, tx0, q0));
+  rhs[1] = fmadd(b, ty1, fmadd(-ra, tx0, q1));
+  rhs[2] = fmadd(-rb, ty0, fmadd(a, tx1, q2));
+  rhs[3] = fmadd(-rb, ty1, fmadd(-ra, tx1, q3));
+  if constexpr (coef_planes<real>() == 5) {
+    const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G], p3 = e[3 * OPL * G],
+                                  p4 = e[4 * OPL * G];
+    const real cf[9] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y, p4.x};
+    solve_apply_q<real>(cf, rb, rhs, x);
+  } else {
+    const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G];
+    const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
+    solve_apply<real>(cf, rb, rhs, x);
+  }
+}
+
+// The angular flux of one ordinate in physical orientation, in FP64.
+template <typename real>
+__device__ __forceinline__ void store_psi(double* out, const real x[4], real mx, real my) {
+  out[0] = (double)x[0];
+  out[1] = (double)(mx * x[1]);
+  out[2] = (double)(my * x[2]);
+  out[3] = (double)(mx * my * x[3]);
+}
+
 template <typename real, int G, int OPL, bool PSI>
 __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, int g, int i, int64_t cell,
                                                  real q0, real q1, real q2, real q3, real mx, real my,
@@ -279,40 +324,38 @@ __device__ __forceinline__ void cell_update_rows(const LaneOrds<real, OPL>& L, i
 #pragma unroll
   for (int o = 0; o < OPL; ++o) {
     const int yo = i * ytr_stride<real, G, OPL>() + (o * G + g) * 2;  // [column (padded)][o][g][2]
-    const real a = L.a[o], b = L.b[o];
-    const real ra = r3 * a, rb = r3 * b;
-    const real tx0 = xt[o][0], tx1 = xt[o][1];
-    const real ty0 = ytr[yo], ty1 = ytr[yo + 1];
-    real rhs[4];
-    rhs[0] = fmadd(b, ty0, fmadd(a, tx0, q0));
-    rhs[1] = fmadd(b, ty1, fmadd(-ra, tx0, q1));
-    rhs[2] = fmadd(-rb, ty0, fmadd(a, tx1, q2));
-    rhs[3] = fmadd(-rb, ty1, fmadd(-ra, tx1, q3));
-    const typename Pair2<real>::T* e = ctab + o * G;
     real x[4];
-    if constexpr (coef_planes<real>() == 5) {
-      const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G], p3 = e[3 * OPL * G],
-                                    p4 = e[4 * OPL * G];
-      const real cf[9] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y, p3.x, p3.y, p4.x};
-      solve_apply_q<real>(cf, rb, rhs, x);
-    } else {
-      const typename Pair2<real>::T p0 = e[0], p1 = e[OPL * G], p2 = e[2 * OPL * G];
-      const real cf[6] = {p0.x, p0.y, p1.x, p1.y, p2.x, p2.y};
-      solve_apply<real>(cf, rb, rhs, x);
-    }
+    ordinate_solve<real, G, OPL>(L, o, q0, q1, q2, q3, xt[o][0], xt[o][1], ytr[yo], ytr[yo + 1], ctab + o * G, x);
     xt[o][0] = fmadd(r3, x[1], x[0]);
     xt[o][1] = fmadd(r3, x[3], x[2]);
     ytr[yo] = fmadd(r3, x[2], x[0]);
     ytr[yo + 1] = fmadd(r3, x[3], x[1]);
 #pragma unroll
     for (int d = 0; d < 4; ++d) c[d] = fmadd(L.wt[o], x[d], c[d]);
-    if (PSI && L.psi[o]) {
-      double* out = L.psi[o] + 4 * cell;
-      out[0] = (double)x[0];
-      out[1] = (double)(mx * x[1]);
-      out[2] = (double)(my * x[2]);
-      out[3] = (double)(mx * my * x[3]);
-    }
+    if (PSI && L.psi[o]) store_psi<real>(L.psi[o] + 4 * cell, x, mx, my);
+  }
+}
+
+// The same for the wave-per-item kernel: the y traces in registers (yi in,
+// yo out; the kernel moves them between rows), one lane per cell.
+template <typename real, int OPL, bool PSI>
+__device__ __forceinline__ void cell_update_wave(const LaneOrds<real, OPL>& L, int64_t cell, real q0, real q1,
+                                                 real q2, real q3, real mx, real my, real xt[OPL][2],
+                                                 const real yi[OPL][2], real yo[OPL][2], real c[4],
+                                                 const typename Pair2<real>::T* ctab) {
+  const real r3 = (real)1.7320508075688772935;
+  c[0] = c[1] = c[2] = c[3] = (real)0;
+#pragma unroll
+  for (int o = 0; o < OPL; ++o) {
+    real x[4];
+    ordinate_solve<real, 1, OPL>(L, o, q0, q1, q2, q3, xt[o][0], xt[o][1], yi[o][0], yi[o][1], ctab + o, x);
+    xt[o][0] = fmadd(r3, x[1], x[0]);
+    xt[o][1] = fmadd(r3, x[3], x[2]);
+    yo[o][0] = fmadd(r3, x[2], x[0]);
+    yo[o][1] = fmadd(r3, x[3], x[1]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) c[d] = fmadd(L.wt[o], x[d], c[d]);
+    if (PSI && L.psi[o]) store_psi<real>(L.psi[o] + 4 * cell, x, mx, my);
   }
 }
 
@@ -341,7 +384,7 @@ __global__ void __launch_bounds__(512) sweep2d_kernel(
     const int32_t* __restrict__ active, int n_items, int per_xcd) {
   // Work groups are dealt to the 8 XCDs round robin; give each XCD a contiguous
   // run of items, so an instance's ordinate blocks share one L2.
-  const int item = (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+  const int item = work_item(per_xcd);
   if (item >= n_items) return;
   const SweepItem it = items[item];
   if (active && !active[it.inst]) return;
@@ -494,7 +537,7 @@ __global__ void __launch_bounds__(512) sweep2d_field_kernel(
     const double* __restrict__ qx, const double* __restrict__ qadd,
     const double* __restrict__ inflow, real* __restrict__ part, double* __restrict__ psi_out,
     const int32_t* __restrict__ active, int n_items, int per_xcd) {
-  const int item = (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+  const int item = work_item(per_xcd);
   if (item >= n_items) return;
   const SweepItem it = items[item];
   if (active && !active[it.inst]) return;
@@ -573,6 +616,46 @@ __host__ __device__ constexpr int rows_max_threads(int rows_per_slot, size_t ele
   return rows_per_slot <= 1 && (elem == 4 || opl <= 4) ? 1024 : 512;
 }
 
+// Stages a work item's per-region tables in LDS: the source scalings (s,
+// mx s, my s, mx my s), s = sigma_s (SCALED) or 1, at tab[4 * region], and
+// per (region, lane ordinate) the local-solve coefficients as coef_planes
+// planes of Pair2 at ctab[region][plane][OPL][G] (formed in FP64 from sigma_t
+// and the ordinate's a and b).
+template <typename real, int G, int OPL, bool SCALED>
+__device__ __forceinline__ void stage_region_tables(const SweepItem& it, const InstDev& I,
+                                                    const double* __restrict__ ox, const double* __restrict__ oy,
+                                                    const double* __restrict__ sigma_t,
+                                                    const double* __restrict__ sigma_s, int max_regions, real mx,
+                                                    real my, real* tab, typename Pair2<real>::T* ctab) {
+  using P2 = typename Pair2<real>::T;
+  constexpr int NPL = coef_planes<real>();
+  const int nreg = I.n_regions, per_reg = NPL * OPL * G;
+  const double* st = sigma_t + (size_t)it.inst * max_regions;
+  const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
+  for (int e = threadIdx.x; e < nreg; e += blockDim.x) {
+    const real sv = SCALED ? (real)ss[e] : (real)1;
+    tab[4 * e] = sv;
+    tab[4 * e + 1] = mx * sv;
+    tab[4 * e + 2] = my * sv;
+    tab[4 * e + 3] = mx * my * sv;
+  }
+  for (int e = threadIdx.x; e < nreg * OPL * G; e += blockDim.x) {
+    const int rg = e / (G * OPL), j = e % (G * OPL);  // lane j / OPL, its ordinate j % OPL
+    const bool on = j < it.count;
+    const int js = I.ord_off + it.first + (on ? j : 0);
+    double cf[10];
+    solve_coef(st[rg], fabs(ox[js]) / I.hx, fabs(oy[js]) / I.hy, cf);
+    P2* d = ctab + rg * per_reg + (j % OPL) * G + j / OPL;
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) {
+      P2 v;
+      v.x = (real)cf[2 * p];
+      v.y = (real)cf[2 * p + 1];
+      d[p * OPL * G] = v;
+    }
+  }
+}
+
 // The same sweep with a fixed row -> slot assignment (row r is handled by slot
 // r mod S), so a slot walks along its rows one cell per diagonal and loads the
 // source of its next cell while the current diagonal is processed: the global
@@ -594,7 +677,7 @@ __global__ void __launch_bounds__(rows_max_threads(MAXR, sizeof(real), OPL)) swe
     const double* __restrict__ qsrc, const double* __restrict__ inflow,
     real* __restrict__ part, double* __restrict__ psi_out, const int32_t* __restrict__ active, int n_items,
     int per_xcd) {
-  const int item = (int)(blockIdx.x % 8u) * per_xcd + (int)(blockIdx.x / 8u);
+  const int item = work_item(per_xcd);
   if (item >= n_items) return;
   const SweepItem it = items[item];
   if (active && !active[it.inst]) return;
@@ -619,33 +702,9 @@ __global__ void __launch_bounds__(rows_max_threads(MAXR, sizeof(real), OPL)) swe
   real* tab = ytr + (size_t)nx * YS;               // [n_regions][4]
   using P2 = typename Pair2<real>::T;
   P2* ctab = reinterpret_cast<P2*>(tab + 4 * nreg);  // [n_regions][coef_planes][OPL][G]
-  constexpr int NPL = coef_planes<real>();
-  const int per_reg = NPL * OPL * G;
+  const int per_reg = coef_planes<real>() * OPL * G;
   {
-    const double* st = sigma_t + (size_t)it.inst * max_regions;
-    const double* ss = SCALED ? sigma_s + (size_t)it.inst * max_regions : nullptr;
-    for (int e = tid; e < nreg; e += blockDim.x) {
-      const real sv = SCALED ? (real)ss[e] : (real)1;
-      tab[4 * e] = sv;
-      tab[4 * e + 1] = mx * sv;
-      tab[4 * e + 2] = my * sv;
-      tab[4 * e + 3] = mx * my * sv;
-    }
-    for (int e = tid; e < nreg * OPL * G; e += blockDim.x) {
-      const int rg = e / (G * OPL), j = e % (G * OPL);  // lane j / OPL, its ordinate j % OPL
-      const bool on = j < it.count;
-      const int js = I.ord_off + it.first + (on ? j : 0);
-      double cf[10];
-      solve_coef(st[rg], fabs(ox[js]) / I.hx, fabs(oy[js]) / I.hy, cf);
-      P2* d = ctab + rg * per_reg + (j % OPL) * G + j / OPL;
-#pragma unroll
-      for (int p = 0; p < NPL; ++p) {
-        P2 v;
-        v.x = (real)cf[2 * p];
-        v.y = (real)cf[2 * p + 1];
-        d[p * OPL * G] = v;
-      }
-    }
+    stage_region_tables<real, G, OPL, SCALED>(it, I, ox, oy, sigma_t, sigma_s, max_regions, mx, my, tab, ctab);
     // inflow traces (g, 0) where each column enters the grid
     for (int e = tid; e < nx * G * OPL; e += blockDim.x) {
       real* t = ytr + (e / (G * OPL)) * YS + 2 * (e % (G * OPL));
@@ -704,6 +763,132 @@ __global__ void __launch_bounds__(rows_max_threads(MAXR, sizeof(real), OPL)) swe
       }
     }
     lds_barrier();
+  }
+}
+
+// A wave-wide shift by one lane (lane l receives lane l - 1's value; lane 0
+// receives `first`): DPP wave_shr:1, whose lane 0 has no source and keeps the
+// old value when bound_ctrl is off.
+__device__ __forceinline__ float wave_shift_up(float v, float first) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double wave_shift_up(double v, double first) {
+  const long long a = __double_as_longlong(v), f = __double_as_longlong(first);
+  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffll), (int)(a & 0xffffffffll), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(a >> 32), 0x138, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Lane 63's value, in every lane.
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+__device__ __forceinline__ double lane63(double v) {
+  const long long a = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(a & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(a >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int SWEEP_WAVE_MAXR = 4;  // rows per lane of the wave-per-item kernel (ny <= 256)
+
+// Wave-per-item sweep for batches too small to fill the chip with work
+// groups of many slots (one instance: the single-instance sweep).  A work
+// item is one wave of 64 lanes; lane l owns rows l, l + 64, ... (up to MAXR),
+// one cell per diagonal and OPL ordinates per lane (G = 1).  The x trace of a
+// row stays in its lane's registers; the y trace that row r leaves on a
+// diagonal is the inflow of row r + 1 on the next one, handed over by a
+// wave-wide lane shift (lane 63 passes to lane 0 of the next row group), so
+// the wavefront needs no barrier and no LDS round trip.  LDS holds only the
+// per-region tables.  Each lane writes its own cell's weighted sum over the
+// item's OPL ordinates.
+template <typename real, int OPL, int MAXR, bool SCALED, bool PSI>
+__global__ void __launch_bounds__(64) sweep2d_wave_kernel(
+    const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
+    const double* __restrict__ ox, const double* __restrict__ oy, const double* __restrict__ w,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ region,
+    const double* __restrict__ sigma_t, const double* __restrict__ sigma_s, int max_regions,
+    const double* __restrict__ qsrc, const double* __restrict__ inflow,
+    real* __restrict__ part, double* __restrict__ psi_out, const int32_t* __restrict__ active, int n_items,
+    int per_xcd) {
+  const int item = work_item(per_xcd);
+  if (item >= n_items) return;
+  const SweepItem it = items[item];
+  if (active && !active[it.inst]) return;
+  const InstDev I = insts[it.inst];
+  const int lane = threadIdx.x;
+  const int nx = I.nx, ny = I.ny;
+  const LaneOrds<real, OPL> L = lane_ords<real, 1, OPL>(it, I, 0, ox, oy, w, perm, psi_out);
+  const bool fx = it.quadrant & 1, fy = it.quadrant & 2;
+  const real mx = fx ? (real)-1 : (real)1, my = fy ? (real)-1 : (real)1;
+  const double gsc = sqrt(I.hx * I.hy);
+  const real gx = inflow ? (real)(inflow[4 * it.inst + (fx ? 1 : 0)] * gsc) : (real)0;
+  const real gy = inflow ? (real)(inflow[4 * it.inst + (fy ? 3 : 2)] * gsc) : (real)0;
+  extern __shared__ unsigned char smem_raw[];
+  real* tab = reinterpret_cast<real*>(smem_raw);  // [n_regions][4]
+  using P2 = typename Pair2<real>::T;
+  P2* ctab = reinterpret_cast<P2*>(tab + 4 * I.n_regions);  // [n_regions][coef_planes][OPL]
+  const int per_reg = coef_planes<real>() * OPL;
+  stage_region_tables<real, 1, OPL, SCALED>(it, I, ox, oy, sigma_t, sigma_s, max_regions, mx, my, tab, ctab);
+  __syncthreads();
+  const int32_t* reg = region + I.region_off;
+  const double* qi = qsrc + I.dof_off;
+  real* P = part + it.part_off;
+  const int dx = fx ? -1 : 1;
+
+  double4 qn[MAXR];
+  int rn[MAXR];
+  uint32_t cn[MAXR];
+  real xt[MAXR][OPL][2];  // x traces of the lane's rows, the inflow trace first
+  real yo[MAXR][OPL][2];  // y traces the lane's rows left on the previous diagonal
+#pragma unroll
+  for (int kk = 0; kk < MAXR; ++kk) {
+#pragma unroll
+    for (int o = 0; o < OPL; ++o) {
+      xt[kk][o][0] = gx;
+      xt[kk][o][1] = (real)0;
+      yo[kk][o][0] = yo[kk][o][1] = (real)0;
+    }
+    const int r = min(lane + 64 * kk, ny - 1);
+    cn[kk] = (uint32_t)((fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 : 0));
+    rn[kk] = reg[cn[kk]];
+    qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * cn[kk]);
+  }
+
+  for (int s = 0; s < nx + ny - 1; ++s) {
+    // inflow y traces of this diagonal: the row below's outflow of the last one
+    real yi[MAXR][OPL][2];
+#pragma unroll
+    for (int kk = 0; kk < MAXR; ++kk)
+#pragma unroll
+      for (int o = 0; o < OPL; ++o)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const real first = kk == 0 ? (t == 0 ? gy : (real)0) : lane63(yo[kk - 1][o][t]);
+          yi[kk][o][t] = wave_shift_up(yo[kk][o][t], first);
+        }
+#pragma unroll
+    for (int kk = 0; kk < MAXR; ++kk) {
+      const int r = lane + 64 * kk;
+      const int i = s - r;
+      if (r < ny && i >= 0 && i < nx) {
+        const double4 v = qn[kk];
+        const int rg = rn[kk];
+        const uint32_t cell = cn[kk];
+        const real* sc = tab + 4 * rg;
+        real c[4];
+        cell_update_wave<real, OPL, PSI>(L, cell, sc[0] * (real)v.x, sc[1] * (real)v.y, sc[2] * (real)v.z,
+                                         sc[3] * (real)v.w, mx, my, xt[kk], yi[kk], yo[kk], c,
+                                         ctab + rg * per_reg);
+        real* o = P + 4u * cell;
+        o[0] = c[0];
+        o[1] = mx * c[1];
+        o[2] = my * c[2];
+        o[3] = mx * my * c[3];
+        if (i + 1 < nx) {
+          cn[kk] = cell + dx;
+          rn[kk] = reg[cell + dx];
+          qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * (cell + dx));
+        }
+      }
+    }
   }
 }
 
@@ -985,6 +1170,12 @@ int make_plan(rte_batch* b, int prec, int G, int threads, int opl) {
   }
   p.part_elems = off;
   p.n_items = (int)p.items.size();
+  if (p.order == 1)  // the largest items first (their partial-flux offsets stay as they are)
+    std::stable_sort(p.items.begin(), p.items.end(), [&](const SweepItem& x, const SweepItem& y) {
+      const InstDev& X = b->inst[x.inst];
+      const InstDev& Y = b->inst[y.inst];
+      return (int64_t)X.nx * X.ny * x.count > (int64_t)Y.nx * Y.ny * y.count;
+    });
   ++b->gen;
   (void)hipFree(p.d_items);
   (void)hipFree(p.d_parts);
@@ -1011,6 +1202,53 @@ static bool rows_variant_fits(const rte_batch* b, int G, int opl, int T, size_t 
          b->max_regions * G * opl <= SWEEP_COEF_ENTRIES;
 }
 
+// Whether the wave-per-item kernel (variant 2: G = 1, 64 threads) can take
+// this batch with OPL ordinates per lane.
+static bool wave_variant_fits(const rte_batch* b, int opl) {
+  return b->n_fields == 0 && (opl == 1 || opl == 2 || opl == 4) && b->max_ny <= 64 * SWEEP_WAVE_MAXR &&
+         b->max_regions <= SWEEP_SIGMA_TAB && b->max_regions * opl <= SWEEP_COEF_ENTRIES;
+}
+
+static size_t wave_lds(const rte_batch* b, int opl, size_t es) {
+  const size_t planes = es == 4 ? coef_planes<float>() : coef_planes<double>();
+  return (4 * (size_t)b->max_regions + 2 * planes * b->max_regions * opl) * es;
+}
+
+template <typename real, int OPL>
+static int launch_wave(rte_batch* b, const Plan& p, const double* sigma_t, const double* sigma_s, const double* qx,
+                       const double* qadd, const double* inflow, double* psi_out, hipStream_t s,
+                       const int32_t* active, void* part) {
+  if ((qx != nullptr) == (qadd != nullptr)) return RTE_EINVAL;  // one source form
+  const int per_xcd = p.order == 0 ? (p.n_items + 7) / 8 : 0;
+  const unsigned nwg = per_xcd > 0 ? 8u * per_xcd : (unsigned)p.n_items;
+  const int nr = (b->max_ny + 63) / 64;
+  const size_t lds = wave_lds(b, OPL, sizeof(real));
+  const double* src = qx ? qx : qadd;
+#define RTE_WAVE_LAUNCH1(R, SC, PS)                                                                           \
+  hipLaunchKernelGGL((sweep2d_wave_kernel<real, OPL, R, SC, PS>), dim3(nwg), dim3(64), lds, s, b->d_inst, \
+                     p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t, sigma_s,             \
+                     b->max_regions, src, inflow, reinterpret_cast<real*>(part), psi_out, active, p.n_items,   \
+                     per_xcd)
+#define RTE_WAVE_LAUNCH(R, SC)                      \
+  do {                                              \
+    if (psi_out) RTE_WAVE_LAUNCH1(R, SC, true);     \
+    else RTE_WAVE_LAUNCH1(R, SC, false);            \
+  } while (0)
+  if (qx) {
+    if (nr <= 1) RTE_WAVE_LAUNCH(1, true);
+    else if (nr <= 2) RTE_WAVE_LAUNCH(2, true);
+    else RTE_WAVE_LAUNCH(4, true);
+  } else {
+    if (nr <= 1) RTE_WAVE_LAUNCH(1, false);
+    else if (nr <= 2) RTE_WAVE_LAUNCH(2, false);
+    else RTE_WAVE_LAUNCH(4, false);
+  }
+#undef RTE_WAVE_LAUNCH
+#undef RTE_WAVE_LAUNCH1
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
 // LDS bytes of a 2D sweep work group (traces of G * OPL ordinates: x and y, or
 // y only for the row-slot kernel, which also stages the sigma_s table and the
 // solve coefficients).
@@ -1028,12 +1266,13 @@ template <typename real, int G, int OPL>
 static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const double* sigma_s,
                     const double* qx, const double* qadd, const double* inflow, double* psi_out,
                     hipStream_t s, const int32_t* active, void* part) {
-  const int per_xcd = (p.n_items + 7) / 8;
+  const int per_xcd = p.order == 0 ? (p.n_items + 7) / 8 : 0;
+  const unsigned nwg = per_xcd > 0 ? 8u * per_xcd : (unsigned)p.n_items;
   const int tdiag = std::min(p.threads, 512);  // the diagonal-slot kernels take at most 512 threads
   if (b->n_fields > 0) {  // cross sections varying inside the cells: the diagonal-slot field kernel
     const size_t lds = sweep_lds(b, G, OPL, 0, sizeof(real));
     if (lds > 64 * 1024) return RTE_EINVAL;
-    hipLaunchKernelGGL((sweep2d_field_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(tdiag), lds, s, b->d_inst,
+    hipLaunchKernelGGL((sweep2d_field_kernel<real, G, OPL>), dim3(nwg), dim3(tdiag), lds, s, b->d_inst,
                        p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_fblk, b->n_fields, b->field_ncell,
                        sigma_t, sigma_s, b->max_regions, qx, qadd, inflow, reinterpret_cast<real*>(part), psi_out,
                        active, p.n_items, per_xcd);
@@ -1047,7 +1286,7 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
     if (lds > 64 * 1024) return RTE_EINVAL;
     const double* src = qx ? qx : qadd;
 #define RTE_ROWS_LAUNCH1(R, SC, PS)                                                                          \
-  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, OPL, R, SC, PS>), dim3(8 * per_xcd), dim3(p.threads), lds, s, \
+  hipLaunchKernelGGL((sweep2d_rows_kernel<real, G, OPL, R, SC, PS>), dim3(nwg), dim3(p.threads), lds, s, \
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region, sigma_t,        \
                      sigma_s, b->max_regions, src, inflow, reinterpret_cast<real*>(part), psi_out,           \
                      active, p.n_items, per_xcd)
@@ -1074,7 +1313,7 @@ static int launch2d(rte_batch* b, const Plan& p, const double* sigma_t, const do
   }
   const size_t lds = sweep_lds(b, G, OPL, 0, sizeof(real));
   if (lds > 64 * 1024) return RTE_EINVAL;  // per-work-group LDS limit used by this library
-  hipLaunchKernelGGL((sweep2d_kernel<real, G, OPL>), dim3(8 * per_xcd), dim3(tdiag), lds, s,
+  hipLaunchKernelGGL((sweep2d_kernel<real, G, OPL>), dim3(nwg), dim3(tdiag), lds, s,
                      b->d_inst, p.d_items, b->d_ox, b->d_oy, b->d_w, b->d_perm, b->d_region,
                      sigma_t, sigma_s, b->max_regions, qx, qadd, inflow,
                      reinterpret_cast<real*>(part), psi_out, active, p.n_items, per_xcd);
@@ -1093,6 +1332,12 @@ template <typename real>
 static int launch2d_g(rte_batch* b, const Plan& p, const double* st, const double* ss,
                       const double* qx, const double* qa, const double* inf, double* psi,
                       hipStream_t s, const int32_t* act, void* part) {
+  if (p.variant == 2) {
+    if (p.G != 1 || p.threads != 64 || !wave_variant_fits(b, p.opl)) return RTE_EINVAL;
+    if (p.opl == 1) return launch_wave<real, 1>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    if (p.opl == 2) return launch_wave<real, 2>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+    return launch_wave<real, 4>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
+  }
   if (p.opl == 8) {
     if (p.G == 4) return launch2d<real, 4, 8>(b, p, st, ss, qx, qa, inf, psi, s, act, part);
     return RTE_EINVAL;
@@ -1218,9 +1463,32 @@ int scalar_flux(rte_batch* b, const double* psi, double* phi, hipStream_t s) {
   return RTE_OK;
 }
 
+int set_sweep_order(rte_batch* b, int prec, int order) {
+  if (!b || prec < 0 || prec > 1 || order < 0 || order > 1) return RTE_EINVAL;
+  Plan& p = b->plan[prec];
+  p.order = order;
+  const int variant = p.variant;
+  const bool tuned = p.tuned;
+  RTE_TRY(make_plan(b, prec, p.G, p.threads, p.opl));
+  p.variant = variant;
+  p.tuned = tuned;
+  return RTE_OK;
+}
+
 int set_sweep_plan(rte_batch* b, int prec, int variant, int G, int opl, int threads) {
-  if (!b || prec < 0 || prec > 1 || variant < 0 || variant > 1 || threads < 64 || threads > 1024 ||
-      threads % 64 || !plan_shape_ok(G, opl) || threads % G || (threads > 512 && (variant != 1 || b->dim != 2)))
+  if (!b || prec < 0 || prec > 1 || variant < 0 || variant > 2) return RTE_EINVAL;
+  b->plan[prec].order = 0;
+  if (variant == 2) {  // wave per item: one lane per cell, 64 threads
+    if (b->dim != 2 || G != 1 || threads != 64 || !wave_variant_fits(b, opl) ||
+        wave_lds(b, opl, prec == 0 ? 8 : 4) > 64 * 1024)
+      return RTE_EINVAL;
+    RTE_TRY(make_plan(b, prec, G, threads, opl));
+    b->plan[prec].variant = variant;
+    b->plan[prec].tuned = true;
+    return RTE_OK;
+  }
+  if (threads < 64 || threads > 1024 || threads % 64 || !plan_shape_ok(G, opl) || threads % G ||
+      (threads > 512 && (variant != 1 || b->dim != 2)))
     return RTE_EINVAL;
   if (b->dim == 2) {
     if (sweep_lds(b, G, opl, variant, prec == 0 ? 8 : 4) > 64 * 1024) return RTE_EINVAL;
@@ -1263,12 +1531,14 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
   struct Cand {
     int V, O, G, T;
     float ms;
+    int order = 0;
   };
   std::vector<Cand> cands;
   // the operator's form (sigma_s-scaled source) when sigma_s is given
   const double* qx = sigma_s ? q : nullptr;
   const double* qa = sigma_s ? nullptr : q;
   auto time_plan = [&](const Cand& c, int trials, float& ms) -> int {
+    b->plan[prec].order = c.order;
     RTE_TRY(make_plan(b, prec, c.G, c.T, c.O));
     b->plan[prec].variant = c.V;
     RTE_TRY(sweep_launch(b, prec, sigma_t, sigma_s, qx, qa, nullptr, nullptr, s, mask, -2.0));
@@ -1284,6 +1554,16 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
     }
     return RTE_OK;
   };
+  // wave per item (variant 2): for small batches, whose few work items
+  // leave the chip idle with the larger work groups (its partial fluxes,
+  // one vector per OPL ordinates, would cost large batches too much)
+  if (b->n_inst <= 16)
+    for (int O = 1; O <= 4; O *= 2) {
+      if (!wave_variant_fits(b, O) || wave_lds(b, O, prec == 0 ? 8 : 4) > 64 * 1024) continue;
+      Cand c{2, O, 1, 64, 1e30f};
+      RTE_TRY(time_plan(c, 3, c.ms));
+      cands.push_back(c);
+    }
   for (int V = 0; V < 2; ++V) {
     for (int O = 1; O <= 8; O *= 2) {
       for (int G : cand_G) {
@@ -1302,26 +1582,41 @@ int autotune_sweep(rte_batch* b, int prec, const double* sigma_t, hipStream_t s,
   // the three fastest again, in turn, so that drift between the first timings
   // cannot decide between near-equal plans
   std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& c) { return a.ms < c.ms; });
-  const size_t top = std::min<size_t>(3, cands.size());
+  size_t top = std::min<size_t>(3, cands.size());
+  cands.resize(top);
+  // in a batch of unequal instances, each of them also with its largest work
+  // items started first
+  bool uneven = false;
+  for (const auto& I : b->inst)
+    uneven = uneven || (int64_t)I.nx * I.ny * I.n_ord != (int64_t)b->inst[0].nx * b->inst[0].ny * b->inst[0].n_ord;
+  if (uneven)
+    for (size_t k = 0; k < top; ++k) {
+      Cand c = cands[k];
+      c.order = 1;
+      cands.push_back(c);
+    }
+  top = cands.size();
   for (size_t k = 0; k < top; ++k) cands[k].ms = 1e30f;
   for (int round = 0; round < 4; ++round)
     for (size_t k = 0; k < top; ++k) RTE_TRY(time_plan(cands[k], 1, cands[k].ms));
-  int bestG = cur.G, bestT = cur.threads, bestV = 0, bestO = 1;
-  float best = 1e30f;
-  for (size_t k = 0; k < top; ++k)
-    if (cands[k].ms < best) {
-      best = cands[k].ms;
-      bestG = cands[k].G;
-      bestT = cands[k].T;
-      bestV = cands[k].V;
-      bestO = cands[k].O;
-    }
+  size_t bk = 0;
+  for (size_t k = 1; k < top; ++k)
+    if (cands[k].ms < cands[bk].ms) bk = k;
   (void)hipFree(q);
   (void)hipFree(mask);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  RTE_TRY(make_plan(b, prec, bestG, bestT, bestO));
-  b->plan[prec].variant = bestV;
+  if (top == 0) {  // nothing admissible to time: the current shape, diagonal-slot kernel
+    cur.order = 0;
+    RTE_TRY(make_plan(b, prec, cur.G, cur.threads, cur.opl));
+    cur.variant = 0;
+    cur.tuned = true;
+    return RTE_OK;
+  }
+  const Cand& c = cands[bk];
+  b->plan[prec].order = c.order;
+  RTE_TRY(make_plan(b, prec, c.G, c.T, c.O));
+  b->plan[prec].variant = c.V;
   b->plan[prec].tuned = true;
   return RTE_OK;
 }

@@ -88,14 +88,15 @@ def test_sweep_parity_uneven_batch(dtype, tol):
 PLANS = [(0, 4, 1, 128), (0, 16, 1, 512), (0, 32, 1, 256), (1, 8, 1, 512), (1, 16, 1, 64), (1, 32, 1, 64),
          (1, 4, 1, 256), (0, 8, 2, 256), (0, 16, 2, 512), (1, 4, 2, 128), (1, 16, 2, 64), (0, 4, 4, 256),
          (1, 8, 4, 512), (1, 8, 4, 256), (0, 4, 8, 128), (1, 4, 8, 64), (1, 4, 8, 128),
-         (1, 8, 4, 1024), (1, 16, 2, 768), (1, 8, 1, 768)]  # one row per slot above 512 threads
+         (1, 8, 4, 1024), (1, 16, 2, 768), (1, 8, 1, 768),  # one row per slot above 512 threads
+         (2, 1, 1, 64), (2, 1, 2, 64), (2, 1, 4, 64)]       # a wave per work item, a lane per row
 
 
 @pytest.mark.gpu
 def test_sweep_parity_every_plan():
-    """Both 2D kernel variants, several lane-group sizes, 1, 2, 4 or 8 ordinates
-    per lane, and work-group sizes (1 to 6 rows per slot for the row-slot
-    kernel), through rte_sweep
+    """The three 2D kernel variants, several lane-group sizes, 1, 2, 4 or 8
+    ordinates per lane, work-group sizes (1 to 6 rows per slot for the
+    row-slot kernel) and both work-item orders, through rte_sweep
     (unscaled source, psi stored) and rte_apply_A (sigma_s-scaled source)."""
     import paper_2410_08735_amd as rt
     specs = _uneven_set()
@@ -105,10 +106,12 @@ def test_sweep_parity_every_plan():
     qs = [rng.standard_normal(n) for n in B.ndofs]
     refs = [_oracle_sweep(spec, qs[k]) for k, spec in enumerate(specs)]
     Ax = [tr.A_tilde_apply(tr.Problem(spec), qs[k]) for k, spec in enumerate(specs)]
-    for variant, G, opl, T in PLANS:
+    for idx, (variant, G, opl, T) in enumerate(PLANS):
+        order = idx % 2  # every other plan with its work items by decreasing size
         for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
-            B.set_sweep_plan(dtype, variant, G, T, opl=opl)
-            assert B.sweep_plan(dtype) == {"variant": variant, "G": G, "opl": opl, "threads": T, "tuned": True}
+            B.set_sweep_plan(dtype, variant, G, T, opl=opl, order=order)
+            assert B.sweep_plan(dtype) == {"variant": variant, "G": G, "opl": opl, "threads": T, "tuned": True,
+                                           "order": order}
             phi, psi = rt.sweep(B, st, B.pack(qs), inflow=B.inflow(), phi=True, psi=True, dtype=dtype)
             y = B.unpack(rt.apply_A(B, st, ss, B.pack(qs), dtype=dtype))
             for k in range(len(specs)):
@@ -142,6 +145,36 @@ def test_row_slot_sweep_at_eight_rows_per_slot():
 
 
 @pytest.mark.gpu
+def test_wave_per_item_sweep_row_groups():
+    """The wave-per-item kernel hands the y trace from lane 63 of one group of
+    64 rows to lane 0 of the next: grids of 64, 65 and 130 rows (one, two and
+    three row groups), with inflow and psi stored, FP64 and FP32; 257 rows
+    are rejected."""
+    import paper_2410_08735_amd as rt
+    specs = [tiny_2d(seed=51, nx=7, ny=130, quad=("cl", 8, 4, True), n_regions=3, inflow=0.4),
+             tiny_2d(seed=52, nx=12, ny=65, quad=("cl", 6, 2, False), n_regions=2, inflow=0.2),
+             tiny_2d(seed=53, nx=3, ny=64, quad=("cl", 8, 4, True), n_regions=2)]
+    B = rt.Batch(specs)
+    st, ss = B.sigma()
+    rng = np.random.default_rng(54)
+    qs = [rng.standard_normal(n) for n in B.ndofs]
+    refs = [_oracle_sweep(spec, qs[k]) for k, spec in enumerate(specs)]
+    Ax = [tr.A_tilde_apply(tr.Problem(spec), qs[k]) for k, spec in enumerate(specs)]
+    for opl in (1, 2, 4):
+        for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+            B.set_sweep_plan(dtype, 2, 1, 64, opl=opl)
+            phi, psi = rt.sweep(B, st, B.pack(qs), inflow=B.inflow(), phi=True, psi=True, dtype=dtype)
+            y = B.unpack(rt.apply_A(B, st, ss, B.pack(qs), dtype=dtype))
+            for k in range(len(specs)):
+                assert rel(B.unpack(phi)[k], refs[k][0]) <= tol, (opl, dtype, k)
+                assert rel(B.unpack_psi(psi)[k], refs[k][1]) <= 10 * tol, (opl, dtype, k)
+                assert rel(y[k], Ax[k]) <= 10 * tol, (opl, dtype, k)
+    taller = rt.Batch([tiny_2d(seed=55, nx=2, ny=257, quad=("cl", 4, 2, True))])
+    with pytest.raises(rt.RteError):
+        taller.set_sweep_plan("f32", 2, 1, 64, opl=1)
+
+
+@pytest.mark.gpu
 def test_invalid_sweep_plans_rejected():
     import paper_2410_08735_amd as rt
     B = rt.Batch([tiny_2d(seed=1, nx=40, ny=40, quad=("cl", 8, 4, False))])
@@ -149,7 +182,9 @@ def test_invalid_sweep_plans_rejected():
                 (0, 32, 256, 2), (0, 8, 256, 3), (0, 16, 256, 4),
                 (1, 32, 1024, 1),   # 32 slots: 2 rows per slot above 512 threads
                 (1, 4, 768, 8),     # FP64 with 8 ordinates per lane: at most 512 threads
-                (1, 8, 1088, 4)]:   # above 1024 threads
+                (1, 8, 1088, 4),    # above 1024 threads
+                (2, 1, 128, 4), (2, 4, 64, 1), (2, 1, 64, 8),  # wave per item: G 1, 64 threads, opl <= 4
+                (3, 1, 64, 1)]:
         with pytest.raises(rt.RteError):
             B.set_sweep_plan("f64", *bad[:3], opl=bad[3])
     B.set_sweep_plan("f32", 1, 4, 768, opl=8)  # the same shape in FP32 fits
