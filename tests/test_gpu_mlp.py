@@ -213,7 +213,7 @@ def test_trained_network_needs_fewer_iterations_than_romsad():
         _, stats, ret = rt.fgmres_solve(Bt, st, ss, G, None, rt.SolveOptions(precond=name, **common), **kw)
         assert ret == 0 and all(s["true_relres"] <= 1e-8 for s in stats)
         its[name] = float(np.mean([s["iterations"] for s in stats]))
-        if name == "mlp":  # the ROM solve's verdict on the network's corrections
+        if name == "mlp":  # the ROM solve's judgement of the network's corrections
             judge = np.array([s["mlp_judge"] for s in stats])
             assert np.all(np.isfinite(judge)) and np.all(judge > 0.0)
     print(f"rank {r}, {X.shape[0]} rows, loss {hist[0]:.3e} -> {hist[-1]:.3e}; mean iterations {its}; "
