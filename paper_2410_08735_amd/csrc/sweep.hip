@@ -833,9 +833,15 @@ __global__ void __launch_bounds__(64) sweep2d_wave_kernel(
   real* P = part + it.part_off;
   const int dx = fx ? -1 : 1;
 
-  double4 qn[MAXR];
-  int rn[MAXR];
-  uint32_t cn[MAXR];
+  // Sources and regions two cells ahead: a wave runs alone on its SIMD, so
+  // one diagonal is too short to hide a load.  Buffer A serves the steps of
+  // even parity, B the odd ones, so no register moves wait on a load: a row
+  // whose first step is even holds cells 0, 2, ... in A and 1, 3, ... in B
+  // (the other way round for an odd first step), and after using a cell the
+  // row loads the cell two ahead into the same buffer.
+  double4 qa[MAXR], qb[MAXR];
+  int ra[MAXR], rb[MAXR];
+  uint32_t cn[MAXR];      // physical index of each row's next cell
   real xt[MAXR][OPL][2];  // x traces of the lane's rows, the inflow trace first
   real yo[MAXR][OPL][2];  // y traces the lane's rows left on the previous diagonal
 #pragma unroll
@@ -848,11 +854,19 @@ __global__ void __launch_bounds__(64) sweep2d_wave_kernel(
     }
     const int r = min(lane + 64 * kk, ny - 1);
     cn[kk] = (uint32_t)((fy ? ny - 1 - r : r) * nx + (fx ? nx - 1 : 0));
-    rn[kk] = reg[cn[kk]];
-    qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * cn[kk]);
+    const uint32_t c1 = nx > 1 ? cn[kk] + dx : cn[kk];
+    const double4 q0 = *reinterpret_cast<const double4*>(qi + 4u * cn[kk]);
+    const double4 q1 = *reinterpret_cast<const double4*>(qi + 4u * c1);
+    const int r0 = reg[cn[kk]], r1 = reg[c1];
+    const bool even = ((lane + 64 * kk) & 1) == 0;
+    qa[kk] = even ? q0 : q1;
+    qb[kk] = even ? q1 : q0;
+    ra[kk] = even ? r0 : r1;
+    rb[kk] = even ? r1 : r0;
   }
 
-  for (int s = 0; s < nx + ny - 1; ++s) {
+  // one diagonal, the buffers of its parity
+  auto diagonal = [&](int s, double4 (&qn)[MAXR], int (&rn)[MAXR]) {
     // inflow y traces of this diagonal: the row below's outflow of the last one
     real yi[MAXR][OPL][2];
 #pragma unroll
@@ -882,13 +896,18 @@ __global__ void __launch_bounds__(64) sweep2d_wave_kernel(
         o[1] = mx * c[1];
         o[2] = my * c[2];
         o[3] = mx * my * c[3];
-        if (i + 1 < nx) {
-          cn[kk] = cell + dx;
-          rn[kk] = reg[cell + dx];
-          qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * (cell + dx));
+        cn[kk] = cell + dx;
+        if (i + 2 < nx) {
+          rn[kk] = reg[cell + 2 * dx];
+          qn[kk] = *reinterpret_cast<const double4*>(qi + 4u * (cell + 2 * dx));
         }
       }
     }
+  };
+  const int nd = nx + ny - 1;
+  for (int s = 0; s < nd; s += 2) {
+    diagonal(s, qa, ra);
+    if (s + 1 < nd) diagonal(s + 1, qb, rb);
   }
 }
 
