@@ -250,7 +250,9 @@ int rte_dsa_apply(const rte_batch* b, const double* sigma_t, const double* sigma
  * phi (device, packed) receives the solution.  stats (host [n_inst]).
  * Failure conventions (per instance; they never abort the batch):
  *  - every region's sigma_t must be finite and > 0 and sigma_s finite and
- *    >= 0 (read on the host before any launch): RTE_EINVAL otherwise;
+ *    >= 0: RTE_EINVAL otherwise, before phi is written (checked on the host
+ *    before a call that tunes the sweep plans, else by a kernel whose result
+ *    is read with ||b~||);
  *  - a non-finite ||b~|| or true residual norm stops that instance with
  *    status RTE_ENONFINITE (its phi is then unspecified); a non-finite Givens
  *    estimate ends its cycle early;

@@ -40,6 +40,20 @@ struct Fgmres {
   // turn) and the events that mark them complete
   int32_t* mask_host = nullptr;
   hipEvent_t mask_ev[2] = {nullptr, nullptr};
+  // pinned host staging of the per-solve and per-cycle reads and writes:
+  // hd = [bnorm | rnorm | scal (8 per instance)], hi = [rsing | fail | the
+  // mask after the cycle start | the cycle's mask | the cross-section check |
+  // the learned correction's flags];
+  // start_ev marks the cycle-start mask's copy complete
+  double* hd = nullptr;
+  int32_t* hi = nullptr;
+  int32_t* xs_bad = nullptr;  // device: cross sections out of range somewhere
+  hipEvent_t start_ev = nullptr;
+  // the learned correction's fall-back flags of the last step, copied to
+  // hi[4 n + 1 ..] behind it; flags_ev marks the copy complete
+  hipEvent_t flags_ev = nullptr;
+  bool flags_pending = false;
+  int apply_flags(std::vector<int32_t>& which);
   // record of cycle 0 (xi recurrence): Z_0..Z_{w-1}, H block [(w+1) x w], beta
   double *recZ = nullptr, *recH = nullptr, *recBeta = nullptr, *recV = nullptr;
   int rec_w = 0;

@@ -26,9 +26,27 @@ int Fgmres::init(rte_batch* batch, int m_) {
       hipMalloc(&rsing, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&m_rom, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&m_dsa, sizeof(int32_t) * n) != hipSuccess ||
-      hipHostMalloc(&mask_host, sizeof(int32_t) * 2 * n) != hipSuccess)
+      hipMalloc(&xs_bad, sizeof(int32_t)) != hipSuccess ||
+      hipHostMalloc(&mask_host, sizeof(int32_t) * 2 * n) != hipSuccess ||
+      hipHostMalloc(&hd, sizeof(double) * 10 * n) != hipSuccess ||
+      hipHostMalloc(&hi, sizeof(int32_t) * (5 * n + 1)) != hipSuccess)
     return RTE_ENOMEM;
   for (auto& e : mask_ev) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  RTE_HIP(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
+  RTE_HIP(hipEventCreateWithFlags(&flags_ev, hipEventDisableTiming));
+  return RTE_OK;
+}
+
+// The learned correction's fall-backs of the last preconditioning step,
+// copied behind it: instances that fell back count as ROMSAD (DSA where their
+// reduced operator is singular).
+int Fgmres::apply_flags(std::vector<int32_t>& which) {
+  if (!flags_pending) return RTE_OK;
+  flags_pending = false;
+  RTE_HIP(hipEventSynchronize(flags_ev));
+  const int32_t* fb = hi + 4 * b->n_inst + 1;
+  for (int q = 0; q < b->n_inst; ++q)
+    if (fb[q]) which[q] = (any_sing && sing_h[q]) ? RTE_PC_DSA : -RTE_PC_ROMSAD;
   return RTE_OK;
 }
 
@@ -36,15 +54,22 @@ void Fgmres::release() {
   graphs_release();
   K.release();
   for (void* p : {(void*)btil, (void*)r, (void*)bnorm, (void*)tolabs, (void*)rnorm, (void*)cyc,
-                  (void*)cyc_step, (void*)flags, (void*)rsing, (void*)m_rom, (void*)m_dsa})
+                  (void*)cyc_step, (void*)flags, (void*)rsing, (void*)m_rom, (void*)m_dsa, (void*)xs_bad})
     (void)hipFree(p);
   btil = r = bnorm = tolabs = rnorm = nullptr;
-  cyc = cyc_step = flags = rsing = m_rom = m_dsa = nullptr;
-  if (mask_host) (void)hipHostFree(mask_host);
+  cyc = cyc_step = flags = rsing = m_rom = m_dsa = xs_bad = nullptr;
+  for (void* p : {(void*)mask_host, (void*)hd, (void*)hi})
+    if (p) (void)hipHostFree(p);
   mask_host = nullptr;
+  hd = nullptr;
+  hi = nullptr;
   for (auto& e : mask_ev) {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
+  }
+  for (hipEvent_t* e : {&start_ev, &flags_ev}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
   }
   rec_release();
 }
@@ -143,6 +168,31 @@ __global__ void k_source_plus(const InstDev* __restrict__ insts, const int32_t* 
   }
 }
 
+// bad = 1 if some instance has a sigma_t that is not finite and positive or a
+// sigma_s that is not finite and non-negative in one of its regions.
+__global__ void k_check_sigma(const InstDev* __restrict__ insts, int n, int max_regions,
+                              const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                              int32_t* __restrict__ bad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * max_regions) return;
+  const int k = (int)(e / max_regions), R = (int)(e % max_regions);
+  if (R >= insts[k].n_regions) return;
+  const double t = sigma_t[e], a = sigma_s[e];
+  if (!(isfinite(t) && t > 0.0) || !(isfinite(a) && a >= 0.0)) atomicOr(bad, 1);
+}
+
+// cyc = active = the host's mask for this cycle (read from pinned host
+// memory), and the learned-correction flags cleared.
+__global__ void k_cycle_masks(int n, const int32_t* __restrict__ host_mask, int32_t* __restrict__ cyc,
+                              int32_t* __restrict__ active, int32_t* __restrict__ flags) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int32_t v = host_mask[q];
+  cyc[q] = v;
+  active[q] = v;
+  flags[q] = 0;
+}
+
 __global__ void k_tolabs(int n, const double* __restrict__ bnorm, double rtol, double* __restrict__ tol) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < n) tol[b] = rtol * bnorm[b];
@@ -221,11 +271,12 @@ int Fgmres::precondition(int jj, int cycle, const double* v, double* z, const So
         RTE_HIP(hipGetLastError());
         RTE_TRY(dsa_step(v, z, m_dsa, c, s));
       }
-      std::vector<int32_t> fb(b->n_inst);
-      RTE_HIP(hipMemcpyAsync(fb.data(), flags, sizeof(int32_t) * b->n_inst, hipMemcpyDeviceToHost, s));
-      RTE_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q < b->n_inst; ++q)
-        if (fb[q]) which[q] = (any_sing && sing_h[q]) ? RTE_PC_DSA : -RTE_PC_ROMSAD;  // fell back
+      // who fell back, for the statistics: read when the step's mask is
+      // (apply_flags), so the GPU does not wait for the host here
+      RTE_HIP(hipMemcpyAsync(hi + 4 * b->n_inst + 1, flags, sizeof(int32_t) * b->n_inst, hipMemcpyDeviceToHost,
+                             s));
+      RTE_HIP(hipEventRecord(flags_ev, s));
+      flags_pending = true;
       return RTE_OK;
     }
   }
@@ -246,8 +297,21 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   const rte_solve_opts& o = *c.opts;
   const int n = b->n_inst;
   const int pin = o.sweep_dtype == RTE_F32 ? 1 : 0;
-  RTE_TRY(autotune_sweep(b, 0, c.sigma_t, s, c.sigma_s));
-  if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s, c.sigma_s));
+  // The cross sections are checked on the host before a solve that tunes the
+  // sweep plans (the autotuner sweeps with them); otherwise on the device,
+  // the result read together with ||b~|| (one host synchronisation fewer).
+  const bool tune = !b->plan[0].tuned || (pin == 1 && !b->plan[1].tuned);
+  if (tune) {
+    RTE_TRY(validate_cross_sections(b, c.sigma_t, c.sigma_s, s));
+    RTE_TRY(autotune_sweep(b, 0, c.sigma_t, s, c.sigma_s));
+    if (pin == 1) RTE_TRY(autotune_sweep(b, 1, c.sigma_t, s, c.sigma_s));
+  } else {
+    RTE_TRY(fill_i32(xs_bad, 1, 0, s));
+    const int64_t ne = (int64_t)n * b->max_regions;
+    hipLaunchKernelGGL(k_check_sigma, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, b->d_inst, n,
+                       b->max_regions, c.sigma_t, c.sigma_s, xs_bad);
+    RTE_HIP(hipGetLastError());
+  }
   for (int q = 0; q < n; ++q) stats[q] = rte_solve_stats{};
   dsa_ready = false;  // the DSA hierarchy is rebuilt for this call's cross sections
   K.bt = o.breakdown_tol > 0.0 ? o.breakdown_tol : 1e-14;
@@ -256,22 +320,16 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   // A_r(mu) depends on mu only: its singularity is decided once per solve
   any_sing = false;
   sing_h.assign(n, 0);
-  if ((o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && c.rom) {
-    RTE_TRY(rom_singular_check(c.rom, b, c.sigma_t, c.sigma_s, rsing, s));
-    RTE_HIP(hipMemcpyAsync(sing_h.data(), rsing, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    RTE_HIP(hipStreamSynchronize(s));
-    for (int q = 0; q < n; ++q)
-      if (sing_h[q]) {
-        any_sing = true;
-        stats[q].rom_singular = 1;
-      }
-  }
+  const bool with_rom = (o.precond == RTE_PC_ROMSAD || o.precond == RTE_PC_MLP) && c.rom;
+  if (with_rom) RTE_TRY(rom_singular_check(c.rom, b, c.sigma_t, c.sigma_s, rsing, s));  // read with ||b~||
   std::vector<int32_t> live(n, 1);
   if (c.init_active) {
     RTE_HIP(hipMemcpyAsync(live.data(), c.init_active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
   }
-  RTE_HIP(hipMemcpyAsync(cyc, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  int32_t* h_cm = hi + 3 * n;  // the host's mask of a cycle, in pinned memory
+  std::copy(live.begin(), live.end(), h_cm);
+  RTE_HIP(hipMemcpyAsync(cyc, h_cm, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   // b~ = T G~ and ||b~||.  With FP32 sweeps b~ only starts the first cycle and
   // scales the stopping test, so an FP32 sweep suffices: every true residual
   // is formed in FP64 from its definition, T (G~ + Sigma_s phi) - phi, and the
@@ -286,12 +344,27 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
     if (live[q]) (f32_btil ? stats[q].sweeps_f32 : stats[q].sweeps_f64) += 1;
   RTE_TRY(knorm(K.sp, btil, K.partA, bnorm, 1, cyc, s));
   hipLaunchKernelGGL(k_tolabs, dim3((n + 63) / 64), dim3(64), 0, s, n, bnorm, o.rtol, tolabs);
-  RTE_HIP(hipMemsetAsync(phi, 0, sizeof(double) * b->total_dof, s));
   RTE_TRY(kcopy(K.sp, btil, r, cyc, s));
-  std::vector<double> bn(n), rn(n), sc(8 * n);
-  RTE_HIP(hipMemcpyAsync(bn.data(), bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  double* h_rn = hd + n;
+  double* h_sc = hd + 2 * n;
+  int32_t* h_fail = hi + n;
+  int32_t* h_start = hi + 2 * n;
+  RTE_HIP(hipMemcpyAsync(hd, bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  if (with_rom) RTE_HIP(hipMemcpyAsync(hi, rsing, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  if (!tune) RTE_HIP(hipMemcpyAsync(hi + 4 * n, xs_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   RTE_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> conv(n, 0), stop(n, 0), fl(n, 0);  // stop: status code of a stopped instance
+  if (!tune && hi[4 * n]) return RTE_EINVAL;  // nothing of the caller's written yet
+  if (with_rom)
+    for (int q = 0; q < n; ++q) {
+      sing_h[q] = hi[q];
+      if (sing_h[q]) {
+        any_sing = true;
+        stats[q].rom_singular = 1;
+      }
+    }
+  const std::vector<double> bn(hd, hd + n);
+  RTE_HIP(hipMemsetAsync(phi, 0, sizeof(double) * b->total_dof, s));
+  std::vector<int32_t> conv(n, 0), stop(n, 0);  // stop: status code of a stopped instance
   for (int q = 0; q < n; ++q) {
     if (!live[q] || bn[q] == 0.0) {
       conv[q] = 1;
@@ -311,23 +384,27 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       n_live += cm[q];
     }
     if (!n_live) break;
-    RTE_HIP(hipMemcpyAsync(cyc, cm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-    RTE_HIP(hipMemcpyAsync(K.active, cyc, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    // every earlier reader of the pinned mask finished before the last host
+    // synchronisation, so it can be rewritten here
+    std::copy(cm.begin(), cm.end(), h_cm);
+    hipLaunchKernelGGL(k_cycle_masks, dim3((n + 63) / 64), dim3(64), 0, s, n, h_cm, cyc, K.active, flags);
+    RTE_HIP(hipGetLastError());
     // With FP32 sweeps a cycle ends once the Givens estimate is 1e-4 of its
     // start (FP32 operators cannot take it much below ~1e-6, and measured on
     // the 96^2 checkerboard family an earlier restart from the FP64 true
     // residual also saves iterations: 9.4 at 1e-4 against 9.8 at 1e-6).
     RTE_TRY(kstart(K, r, tolabs, s, pin ? 1e-4 : 0.0));
-    RTE_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * n, s));  // learned correction on
+    flags_pending = false;
     for (int q = 0; q < n; ++q) stats[q].cycles += cm[q];
     // The device activity mask decides who iterates in each step.  The host
     // enqueues step j before it reads the mask step j - 1 left (copied to
     // pinned memory behind that step), so the GPU never idles on the read; a
     // step enqueued after the last instance converged finds nobody active.
-    RTE_HIP(hipMemcpyAsync(act.data(), K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    RTE_HIP(hipStreamSynchronize(s));
-    bool any0 = false;
-    for (int q = 0; q < n; ++q) any0 = any0 || act[q];
+    // Step 0 runs with the mask the cycle start left, read the same way.
+    RTE_HIP(hipMemcpyAsync(h_start, K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipEventRecord(start_ev, s));
+    act = cm;
+    const bool any0 = n_live > 0;
     const bool stall = o.precond == RTE_PC_MLP;
     for (int j = 0; j < m && any0; ++j) {
       const bool stall_j = stall && j + 1 <= o.window && (o.window_cycles <= 0 || cycle < o.window_cycles);
@@ -346,9 +423,9 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       int32_t* mh = mask_host + (j & 1) * n;
       RTE_HIP(hipMemcpyAsync(mh, K.active, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
       RTE_HIP(hipEventRecord(mask_ev[j & 1], s));
-      if (j > 0) {  // the mask step j ran with, left by step j - 1
-        RTE_HIP(hipEventSynchronize(mask_ev[(j - 1) & 1]));
-        const int32_t* prev = mask_host + ((j - 1) & 1) * n;
+      {  // the mask step j ran with, left by the cycle start (j = 0) or step j - 1
+        RTE_HIP(hipEventSynchronize(j > 0 ? mask_ev[(j - 1) & 1] : start_ev));
+        const int32_t* prev = j > 0 ? mask_host + ((j - 1) & 1) * n : h_start;
         bool any = false;
         for (int q = 0; q < n; ++q) {
           act[q] = prev[q];
@@ -360,6 +437,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
         }
         if (pidx >= 0) prof_set_units(pslot, pidx, batch_cell_ordinates(b, act.data()));
       }
+      RTE_TRY(apply_flags(which));
       for (int q = 0; q < n; ++q) {
         if (!act[q]) continue;
         stats[q].iterations += 1;
@@ -411,10 +489,13 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       RTE_TRY(reduce_partials(b, 0, 1.0, btil, 1.0, r, s, cyc, phi, -1.0));
     }
     RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
-    RTE_HIP(hipMemcpyAsync(rn.data(), rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    RTE_HIP(hipMemcpyAsync(sc.data(), K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
-    RTE_HIP(hipMemcpyAsync(fl.data(), K.fail, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipMemcpyAsync(h_rn, rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipMemcpyAsync(h_sc, K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipMemcpyAsync(h_fail, K.fail, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
+    const double* rn = h_rn;
+    const double* sc = h_sc;
+    const int32_t* fl = h_fail;
     bool all = true;
     for (int q = 0; q < n; ++q) {
       if (cm[q]) {
@@ -500,8 +581,7 @@ extern "C" int fgmres_solve(const rte_batch* cb, const double* sigma_t, const do
                           ((o.precond == RTE_PC_DSA || o.precond == RTE_PC_ROMSAD) && o.dsa_restart < 1)))
     return RTE_EINVAL;
   if (!(o.breakdown_tol >= 0.0) || o.breakdown_tol >= 1e3) return RTE_EINVAL;
-  RTE_TRY(rte::validate_cross_sections(b, sigma_t, sigma_s, reinterpret_cast<hipStream_t>(stream)));
-  rte::Fgmres* f = rte::fgmres_for(b, o.m);
+  rte::Fgmres* f = rte::fgmres_for(b, o.m);  // the solve checks the cross sections
   if (!f) return RTE_ENOMEM;
   rte::SolveCtx c{};
   c.opts = opts;

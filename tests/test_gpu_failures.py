@@ -54,10 +54,20 @@ def test_nan_source_stops_only_its_instance():
 
 @pytest.mark.gpu
 def test_invalid_cross_sections_rejected():
+    """Out-of-range cross sections give RTE_EINVAL: checked on the host by a
+    call that tunes the sweep plans (the first, on a fresh batch), and by a
+    kernel once the plans are tuned."""
     import paper_2410_08735_amd as rt
     specs = [tiny_2d(seed=1, nx=4, ny=4, quad=("cl", 8, 4, True), n_regions=2)]
     B = rt.Batch(specs)
     st, ss = B.sigma()
+    t = st.clone()
+    t[0, 1] = -1.0
+    with pytest.raises(rt.RteError) as e:  # host check (untuned plans)
+        rt.fgmres_solve(B, t, ss, B.source(), None, _dsa_opts(rt))
+    assert e.value.status == rt._lib.RTE_EINVAL
+    _, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), None, _dsa_opts(rt))  # tunes the plans
+    assert ret == 0 and B.sweep_plan("f64")["tuned"]
     for bad_t, bad_s in ((0.0, None), (-1.0, None), (float("nan"), None), (None, -0.5), (None, float("inf"))):
         t, s = st.clone(), ss.clone()
         if bad_t is not None:
