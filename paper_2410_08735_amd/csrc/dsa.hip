@@ -656,18 +656,23 @@ __device__ __forceinline__ CellPos cell_pos(int i, int k, int nx, int ny) {
 }
 
 // Field f (4 unknowns) of a cell and of its four neighbours (zeros where
-// absent; the cell's own values are zeros too unless OWN).
+// absent; the cell's own values are zeros too unless OWN).  An absent
+// neighbour reads the cell itself and the value is then replaced by zero:
+// with no branch around a load, the loads issue back to back and are waited
+// for once instead of one at a time.
 template <typename real, bool OWN = true>
 __device__ __forceinline__ void load_field(const real* __restrict__ x, const CellPos& P, int f, real c[4],
                                            real l[4], real r[4], real b[4], real t[4]) {
+  const int ol = P.hl ? -1 : 0, orr = P.hr ? 1 : 0, ob = P.hb ? -P.nx : 0, ot = P.ht ? P.nx : 0;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const real* q = x + (int64_t)(4 * f + m) * P.nc + P.cell;
+    const real vl = q[ol], vr = q[orr], vb = q[ob], vt = q[ot];
     c[m] = OWN ? q[0] : (real)0;
-    l[m] = P.hl ? q[-1] : (real)0;
-    r[m] = P.hr ? q[1] : (real)0;
-    b[m] = P.hb ? q[-P.nx] : (real)0;
-    t[m] = P.ht ? q[P.nx] : (real)0;
+    l[m] = P.hl ? vl : (real)0;
+    r[m] = P.hr ? vr : (real)0;
+    b[m] = P.hb ? vb : (real)0;
+    t[m] = P.ht ? vt : (real)0;
   }
 }
 
