@@ -66,6 +66,8 @@ int kaxpby(const Space& sp, double a, const double* x, double bcoef, double* y,
 int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hipStream_t s);
 // Arnoldi step j: w (= V[j+1] slot) orthogonalised against V[0..j] by MGS,
 // H[:, j] filled, w normalised, Givens rotation applied, est and active updated.
+// Instances of up to 48 Ki DoFs (even offsets and lengths) take one launch
+// with w held in registers; longer ones one launch per projection.
 // first_dot_ready: partA already holds the chunk partials of <w, v_0> (the
 // operator's reduction produced them)
 int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready = false);

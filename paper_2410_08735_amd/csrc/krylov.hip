@@ -1,6 +1,7 @@
-// Batched FP64 Krylov kernels: reductions are two-level and deterministic
-// (per-work-group partial sums, then a fixed-order sum per instance), every
-// kernel skips instances whose mask entry is 0.
+// Batched FP64 Krylov kernels: reductions are deterministic (per-work-group
+// partial sums, then a fixed-order sum per instance; or one work group per
+// instance, summing in a fixed order), every kernel skips instances whose mask
+// entry is 0.
 #include <algorithm>
 #include <cmath>
 
@@ -219,27 +220,24 @@ __global__ void k_arnoldi_tail(int n, const int64_t* __restrict__ len, const dou
 // bt ||H(:, j)|| leaves the least squares singular (unhappy breakdown): column
 // j is dropped and fail = KFAIL_BREAKDOWN.  A non-finite rho or estimate
 // drops the column as well (fail = KFAIL_NONFINITE), so the update keeps the
-// last finite iterate.
-__global__ void k_givens(int n, const double* __restrict__ H, double* __restrict__ R,
-                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                         int m, int j, double* __restrict__ scal, int32_t* __restrict__ active,
-                         int32_t* __restrict__ jdone, int32_t* __restrict__ fail, double bt) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n || !active[b]) return;
-  const double* Hb = H + (int64_t)b * (m + 1) * m;
-  double* Rb = R + (int64_t)b * (m + 1) * m;
-  double* c = cs + (int64_t)b * m;
-  double* s = sn + (int64_t)b * m;
-  double* gb = g + (int64_t)b * (m + 1);
+// last finite iterate.  hc: column j of H (entry i at hc[i * hs]); c_old,
+// s_old: the rotations of columns 0 .. j-1 (read before c and s are written).
+__device__ __forceinline__ void givens_column(int b, const double* hc, int hs, double* __restrict__ Rb,
+                                              const double* c_old, const double* s_old,
+                                              double* __restrict__ c, double* __restrict__ s,
+                                              double* __restrict__ gb, int m, int j,
+                                              double* __restrict__ scal, int32_t* __restrict__ active,
+                                              int32_t* __restrict__ jdone, int32_t* __restrict__ fail,
+                                              double bt) {
   double colsq = 0.0;
   for (int i = 0; i <= j + 1; ++i) {
-    Rb[i * m + j] = Hb[i * m + j];
-    colsq += Hb[i * m + j] * Hb[i * m + j];
+    Rb[i * m + j] = hc[i * hs];
+    colsq += hc[i * hs] * hc[i * hs];
   }
   for (int k = 0; k < j; ++k) {
     const double a = Rb[k * m + j], bb = Rb[(k + 1) * m + j];
-    Rb[k * m + j] = c[k] * a + s[k] * bb;
-    Rb[(k + 1) * m + j] = -s[k] * a + c[k] * bb;
+    Rb[k * m + j] = c_old[k] * a + s_old[k] * bb;
+    Rb[(k + 1) * m + j] = -s_old[k] * a + c_old[k] * bb;
   }
   const double a = Rb[j * m + j], bb = Rb[(j + 1) * m + j];
   const double rho = hypot(a, bb);
@@ -258,7 +256,7 @@ __global__ void k_givens(int n, const double* __restrict__ H, double* __restrict
   const double est = fabs(gb[j + 1]);
   const double cn = sqrt(colsq);
   const bool finite = isfinite(rho) && isfinite(est) && isfinite(cn);
-  const bool breakdown = Hb[(j + 1) * m + j] <= bt * cn;
+  const bool breakdown = hc[(j + 1) * hs] <= bt * cn;
   const bool unhappy = finite && breakdown && !(rho > bt * cn);
   scal[b * 8 + 5] = scal[b * 8 + 2];  // previous estimate
   if (!finite || unhappy) {
@@ -273,6 +271,167 @@ __global__ void k_givens(int n, const double* __restrict__ H, double* __restrict
   scal[b * 8 + 2] = est;
   jdone[b] = j + 1;
   if (est <= scal[b * 8 + 1] || breakdown) active[b] = 0;
+}
+
+__global__ void k_givens(int n, const double* __restrict__ H, double* __restrict__ R,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         int m, int j, double* __restrict__ scal, int32_t* __restrict__ active,
+                         int32_t* __restrict__ jdone, int32_t* __restrict__ fail, double bt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n || !active[b]) return;
+  double* c = cs + (int64_t)b * m;
+  double* s = sn + (int64_t)b * m;
+  givens_column(b, H + (int64_t)b * (m + 1) * m + j, m, R + (int64_t)b * (m + 1) * m, c, s, c, s,
+                g + (int64_t)b * (m + 1), m, j, scal, active, jdone, fail, bt);
+}
+
+// Sum over the work group, the same value in every thread (fixed order: a
+// butterfly within each wave, then the waves in turn).  sh holds one slot per
+// wave; alternate two such arrays between consecutive calls, so that no
+// second barrier is needed before the next call writes its slots.
+template <int NT>
+__device__ __forceinline__ double group_sum_all(double v, double* sh) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) t += sh[k];
+  return t;
+}
+
+// Arnoldi step j of every active instance, one work group per instance: w
+// (= V[j+1], PT values per thread, pairs of DoFs 2 (t + k NT)) stays in
+// registers through the MGS projections, each one pass that subtracts
+// h_i v_i and forms the next projection's dot, <w, v_{i+1}> (the squared norm
+// after the last); then w is normalised and stored once, and thread 0 applies
+// the Givens rotations of column j (the column and the earlier rotations
+// staged in LDS).  The MGS of the chunked kernels in one launch, with w read
+// and written once instead of once per projection.  part0 (nullable): chunk
+// partials of <w, v_0> that the operator's reduction left, else the first
+// dot is a pass of its own.  Needs len <= NT * PT and even offsets/lengths.
+constexpr int ARN_MAX_M = 500;
+template <int NT, int PT>
+__global__ void __launch_bounds__(NT) k_arnoldi_reg(
+    const int64_t* __restrict__ off, const int64_t* __restrict__ len, double* __restrict__ V, int64_t total,
+    const double* __restrict__ part0, int maxc, double* __restrict__ H, double* __restrict__ R,
+    double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g, int m, int j,
+    double* __restrict__ scal, int32_t* __restrict__ active, int32_t* __restrict__ jdone,
+    int32_t* __restrict__ fail, double bt) {
+  constexpr int NP = PT / 2;
+  // pairs per group of loads: fewer where w takes most registers
+  constexpr int ARN_GROUP = PT > 32 ? 2 : 4;
+  __shared__ double sh[2][NT / 64];
+  __shared__ double hcol[ARN_MAX_M + 1], c_old[ARN_MAX_M], s_old[ARN_MAX_M];
+  const int b = blockIdx.x;
+  if (!active[b]) return;
+  const int t = threadIdx.x;
+  const int64_t n = len[b], base = off[b];
+  for (int k = t; k < j; k += NT) {
+    c_old[k] = cs[(int64_t)b * m + k];
+    s_old[k] = sn[(int64_t)b * m + k];
+  }
+  // byte offsets (32-bit) of a thread's pairs from an instance's start: pair
+  // k at tb + k NT 16.  tb passes through an empty asm statement in every
+  // pass, so the compiler forms each pair's address where it is used rather
+  // than holding one per pair across the passes (their registers would
+  // spill).  A pair past the instance's end reads its first pair and takes
+  // zeros instead: no branch around a load, so the loads issue back to back.
+  const uint32_t nbytes = (uint32_t)(n * 8);
+  auto pair = [nbytes](const double* p, uint32_t ob) {
+    const bool in = ob < nbytes;
+    const double2 v = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(p) + (in ? ob : 0u));
+    return in ? v : make_double2(0.0, 0.0);
+  };
+  double* wp = V + (int64_t)(j + 1) * total + base;
+  double2 w[NP];
+  {
+    uint32_t tb = (uint32_t)t * 16u;
+    asm volatile("" : "+v"(tb));
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const uint32_t ob = tb + (uint32_t)(k * NT * 16);
+      w[k] = pair(wp, ob);
+    }
+  }
+  int par = 0;
+  double h;
+  if (part0) {
+    if (t == 0) {
+      const int nc = (int)((n + KCHUNK - 1) / KCHUNK);
+      double s0 = 0.0;
+      for (int c = 0; c < nc; ++c) s0 += part0[(int64_t)b * maxc + c];
+      sh[1][0] = s0;
+    }
+    __syncthreads();
+    h = sh[1][0];
+  } else {
+    const double* v0 = V + base;
+    uint32_t tb = (uint32_t)t * 16u;
+    asm volatile("" : "+v"(tb));
+    double acc = 0.0;
+#pragma unroll
+    for (int k0 = 0; k0 < NP; k0 += ARN_GROUP) {
+#pragma unroll
+      for (int k = k0; k < k0 + ARN_GROUP && k < NP; ++k) {
+        const double2 v = pair(v0, tb + (uint32_t)(k * NT * 16));
+        acc += w[k].x * v.x + w[k].y * v.y;
+      }
+      asm volatile("" : "+v"(acc)::"memory");
+    }
+    h = group_sum_all<NT>(acc, sh[par]);
+    par ^= 1;
+  }
+  for (int i = 0; i <= j; ++i) {
+    if (t == 0) hcol[i] = h;
+    const double* vi = V + (int64_t)i * total + base;
+    // the next dot: <w, v_{i+1}>, or <w, w> after the last projection (then
+    // u repeats v_i's loads, from the cache, and is not used)
+    const bool last = i == j;
+    const double* un = last ? vi : V + (int64_t)(i + 1) * total + base;
+    uint32_t tb = (uint32_t)t * 16u;
+    asm volatile("" : "+v"(tb));
+    double acc = 0.0;
+    // groups of ARN_GROUP pairs: the empty asm statement after each group
+    // takes the group's dot (so its arithmetic is done there) and orders
+    // memory, which keeps the compiler from hoisting every load of the pass
+    // ahead of the arithmetic
+#pragma unroll
+    for (int k0 = 0; k0 < NP; k0 += ARN_GROUP) {
+#pragma unroll
+      for (int k = k0; k < k0 + ARN_GROUP && k < NP; ++k) {
+        const uint32_t ob = tb + (uint32_t)(k * NT * 16);
+        const double2 v = pair(vi, ob), u = pair(un, ob);
+        w[k].x -= h * v.x;
+        w[k].y -= h * v.y;
+        acc += w[k].x * (last ? w[k].x : u.x) + w[k].y * (last ? w[k].y : u.y);
+      }
+      asm volatile("" : "+v"(acc)::"memory");
+    }
+    h = group_sum_all<NT>(acc, sh[par]);
+    par ^= 1;
+  }
+  const double nw = sqrt(h);
+  const double f = nw != 0.0 ? 1.0 / nw : 0.0;
+  {
+    uint32_t tb = (uint32_t)t * 16u;
+    asm volatile("" : "+v"(tb));
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const uint32_t ob = tb + (uint32_t)(k * NT * 16);
+      if (ob < nbytes)
+        *reinterpret_cast<double2*>(reinterpret_cast<char*>(wp) + ob) = make_double2(w[k].x * f, w[k].y * f);
+    }
+  }
+  if (t == 0) {
+    hcol[j + 1] = nw;
+    double* Hb = H + (int64_t)b * (m + 1) * m;
+    for (int i = 0; i <= j + 1; ++i) Hb[i * m + j] = hcol[i];
+    scal[b * 8 + 4] = nw;
+    givens_column(b, hcol, 1, R + (int64_t)b * (m + 1) * m, c_old, s_old, cs + (int64_t)b * m,
+                  sn + (int64_t)b * m, g + (int64_t)b * (m + 1), m, j, scal, active, jdone, fail, bt);
+  }
 }
 
 __global__ void k_backsolve(int n, const double* __restrict__ R, const double* __restrict__ g, int m,
@@ -404,10 +563,38 @@ int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s, dou
   return kscale(sp, r, K.scal + 0, 8, K.v(0), K.active, s);
 }
 
+// The register-resident step: NT threads of PT values each cover every
+// instance, all offsets and lengths even (whole pairs of DoFs).
+template <int NT, int PT>
+static void launch_arnoldi_reg(Krylov& K, int j, hipStream_t s, bool first_dot_ready) {
+  const Space& sp = K.sp;
+  hipLaunchKernelGGL((k_arnoldi_reg<NT, PT>), dim3(sp.n), dim3(NT), 0, s, sp.d_off, sp.d_len, K.V, sp.total,
+                     first_dot_ready ? (const double*)K.partA : nullptr, sp.max_chunks(), K.H, K.R, K.cs, K.sn,
+                     K.g, K.m, j, K.scal, K.active, K.jdone, K.fail, K.bt);
+}
+
+// Up to 1024 x 48 values (w in 96 of the 128 registers a thread has with
+// 1024 threads); longer vectors take the chunked kernels.
+constexpr int64_t ARN_MAX_LEN = 1024 * 48;
+
 int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready) {
   const Space& sp = K.sp;
   const int mc = sp.max_chunks();
   double* w = K.v(j + 1);
+  bool even = (sp.total & 1) == 0;
+  for (int q = 0; q < sp.n && even; ++q) even = ((sp.off[q] | sp.len[q]) & 1) == 0;
+  if (even && K.m <= ARN_MAX_M && sp.max_len <= ARN_MAX_LEN) {
+    const int64_t L = sp.max_len;
+    if (L <= 1024 * 8) launch_arnoldi_reg<1024, 8>(K, j, s, first_dot_ready);
+    else if (L <= 1024 * 16) launch_arnoldi_reg<1024, 16>(K, j, s, first_dot_ready);
+    else if (L <= 1024 * 24) launch_arnoldi_reg<1024, 24>(K, j, s, first_dot_ready);
+    else if (L <= 1024 * 32) launch_arnoldi_reg<1024, 32>(K, j, s, first_dot_ready);
+    else if (L <= 1024 * 36) launch_arnoldi_reg<1024, 36>(K, j, s, first_dot_ready);
+    else if (L <= 1024 * 40) launch_arnoldi_reg<1024, 40>(K, j, s, first_dot_ready);
+    else launch_arnoldi_reg<1024, 48>(K, j, s, first_dot_ready);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   if (!first_dot_ready)
     hipLaunchKernelGGL(k_dot_part, dim3(mc, sp.n), dim3(KTHREADS), 0, s, sp.d_off, sp.d_len, w, K.v(0),
                        K.partA, mc, K.active);
