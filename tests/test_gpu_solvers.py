@@ -310,6 +310,34 @@ def test_fgmres_degenerate_instances_in_one_batch(precond, sweep_dtype):
 
 
 @pytest.mark.gpu
+def test_arnoldi_in_registers_matches_the_chunked_kernels():
+    """The Arnoldi step keeps w in registers (one launch per step) for
+    instances of up to 48 Ki DoFs and runs one launch per projection above
+    that.  The same 110^2 instance (48,400 DoFs, the largest register tile)
+    solved alone and beside a 112^2 instance (50,176 DoFs, which sends the
+    whole batch to the chunked kernels) takes the same iterations and the two
+    fluxes agree to rounding; the exact FP64 DSA makes the preconditioner the
+    same in both batches."""
+    import paper_2410_08735_amd as rt
+    a = tiny_2d(seed=41, nx=110, ny=110, quad=("cl", 8, 2, True), n_regions=3, inflow=0.2)
+    b = tiny_2d(seed=42, nx=112, ny=112, quad=("cl", 8, 2, True), n_regions=2)
+    opts = rt.SolveOptions(precond="dsa", m=30, max_cycles=10, sweep_dtype="f64", rtol=1e-12,
+                           dsa_inner_max=2000, dsa_restart=60, dsa_inner_tol=1e-14)
+    out = []
+    for specs in ([a], [a, b]):
+        B = rt.Batch(specs)
+        assert max(B.ndofs) == (48400 if len(specs) == 1 else 50176)
+        st, ss = B.sigma()
+        phi, stats, ret = rt.fgmres_solve(B, st, ss, B.source(), B.inflow(), opts)
+        assert ret == 0 and all(s["true_relres"] <= 1e-12 for s in stats), stats
+        out.append((B.unpack(phi)[0], int(stats[0]["iterations"])))
+    print(f"iterations {out[0][1]} (registers) and {out[1][1]} (chunked), "
+          f"flux difference {rel(out[0][0], out[1][0]):.2e}")
+    assert abs(out[0][1] - out[1][1]) <= 1
+    assert rel(out[0][0], out[1][0]) <= 1e-10
+
+
+@pytest.mark.gpu
 def test_iteration_limit_reports_not_converged():
     """Out of iterations: FGMRES (one cycle of 3) and SI (2 iterations) return
     the not-converged warning, per instance and as the call's status, with the
