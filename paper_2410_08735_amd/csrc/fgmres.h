@@ -21,6 +21,7 @@ struct OpGraph {
   hipGraphExec_t exec = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};  // sigma_t, sigma_s, z, w
   int prec = -1, G = 0, threads = 0, variant = -1, opl = 0;
+  bool reduce = true;  // the partial-flux reduction is part of the graph
   uint64_t gen = 0;  // the batch's plan / partial-buffer generation at capture
 };
 
@@ -66,7 +67,10 @@ struct Fgmres {
                    std::vector<int32_t>& which);
   int solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStream_t s);
   int dsa_step(const double* v, double* z, const int32_t* mask, const SolveCtx& c, hipStream_t s);
-  int apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s);
+  // reduce = false: the sweep only; the Arnoldi step then forms w from the
+  // partial fluxes itself
+  int apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s,
+               bool reduce = true);
   void graphs_release();
 };
 

@@ -82,7 +82,9 @@ void Fgmres::graphs_release() {
 
 // w = z_j - T Sigma_s z_j into v_{j+1}: one batched sweep and the deterministic
 // partial-flux reduction, which also leaves the chunk partials of <w, v_0> in
-// K.partA for the first MGS projection.  With use_graph the pair is captured once per
+// K.partA for the first MGS projection (without reduce only the sweep: the
+// register-resident Arnoldi step forms w from the sweep's partial fluxes).
+// With use_graph the pair is captured once per
 // (precision, j) into a HIP graph and replayed; a new capture is made when the
 // cross-section arrays, the plan or the buffers change (the batch's generation
 // counts every reallocation of the plan tables and the partial buffer, whose
@@ -91,9 +93,11 @@ void Fgmres::graphs_release() {
 static int64_t g_graph_captures = 0;
 int64_t graph_capture_count() { return g_graph_captures; }
 
-int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s) {
+int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double units, hipStream_t s,
+                     bool reduce) {
   if (!use_graph) {
     RTE_TRY(sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, units));
+    if (!reduce) return RTE_OK;
     return reduce_partials_dot(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), K.v(0), K.partA, K.sp.max_chunks(),
                                KCHUNK, s, K.active);
   }
@@ -102,7 +106,7 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double 
   const Plan& p = b->plan[prec];
   const void* key[4] = {c.sigma_t, c.sigma_s, K.z(j), K.v(j + 1)};
   const bool same = g.exec && g.prec == prec && g.G == p.G && g.threads == p.threads && g.variant == p.variant &&
-                    g.opl == p.opl && g.gen == b->gen && std::equal(key, key + 4, g.key);
+                    g.opl == p.opl && g.reduce == reduce && g.gen == b->gen && std::equal(key, key + 4, g.key);
   if (!same) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
@@ -110,7 +114,7 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double 
     RTE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     // no profiler events inside the capture; they are recorded around the launch
     int st = sweep_launch(b, prec, c.sigma_t, c.sigma_s, K.z(j), nullptr, nullptr, nullptr, s, K.active, -2.0);
-    if (st == RTE_OK)
+    if (st == RTE_OK && reduce)
       st = reduce_partials_dot(b, prec, -1.0, K.z(j), 1.0, K.v(j + 1), K.v(0), K.partA, K.sp.max_chunks(),
                                KCHUNK, s, K.active);
     const hipError_t e = hipStreamEndCapture(s, &graph);
@@ -131,6 +135,7 @@ int Fgmres::apply_op(int j, int prec, const SolveCtx& c, bool use_graph, double 
     g.threads = p.threads;
     g.variant = p.variant;
     g.opl = p.opl;
+    g.reduce = reduce;
     std::copy(key, key + 4, g.key);
   }
   const bool prof = prof_enabled();
@@ -411,11 +416,19 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       if (stall_j)  // who is active in this step, for the stall check after it
         RTE_HIP(hipMemcpyAsync(cyc_step, K.active, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
       RTE_TRY(precondition(j + 1, cycle, K.v(j), K.z(j), c, s, which));
-      // w = A~ z_j = z_j - T Sigma_s z_j (work units of the previous step's mask, corrected below)
-      RTE_TRY(apply_op(j, pin, c, o.use_graph != 0 && s != nullptr, batch_cell_ordinates(b, act.data()), s));
+      // w = A~ z_j = z_j - T Sigma_s z_j (work units of the previous step's mask, corrected below);
+      // the register-resident Arnoldi step forms w from the sweep's partial fluxes itself
+      const bool fold = arnoldi_in_registers(K);
+      RTE_TRY(apply_op(j, pin, c, o.use_graph != 0 && s != nullptr, batch_cell_ordinates(b, act.data()), s,
+                       !fold));
       const int pslot = pin ? PROF_SWEEP_F32 : PROF_SWEEP_F64;
       const int pidx = prof_enabled() ? prof_last(pslot) : -1;
-      RTE_TRY(arnoldi_mgs(K, j, s, true));  // apply_op left <w, v_0> in partA
+      if (fold) {
+        const PartialSrc src{b->plan[pin].d_parts, b->d_part, pin, K.z(j)};
+        RTE_TRY(arnoldi_mgs(K, j, s, false, &src));
+      } else {
+        RTE_TRY(arnoldi_mgs(K, j, s, true));  // apply_op left <w, v_0> in partA
+      }
       if (stall_j) {
         hipLaunchKernelGGL(k_stall_check, dim3((n + 63) / 64), dim3(64), 0, s, n, K.scal, cyc_step, flags);
         RTE_HIP(hipGetLastError());

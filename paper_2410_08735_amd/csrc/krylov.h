@@ -64,13 +64,26 @@ int kscale(const Space& sp, const double* x, const double* sc, int stride, doubl
 int kaxpby(const Space& sp, double a, const double* x, double bcoef, double* y,
            const int32_t* active, hipStream_t s);
 int kcopy(const Space& sp, const double* x, double* y, const int32_t* active, hipStream_t s);
+// The operator's partial fluxes (one sweep's per-work-item partial sums, in
+// the plan's layout), from which the register-resident Arnoldi step forms
+// w = z - (their sum) itself instead of reading a reduced w.
+struct PartialSrc {
+  const InstPart* parts;  // device, per instance
+  const void* part;       // the partial buffer
+  int f32;                // partials in FP32 (else FP64)
+  const double* z;        // the vector the operator was applied to
+};
+// Whether arnoldi_mgs takes the register-resident step (one launch, w held in
+// registers): instances of up to 48 Ki DoFs, even offsets and lengths.
+bool arnoldi_in_registers(const Krylov& K);
 // Arnoldi step j: w (= V[j+1] slot) orthogonalised against V[0..j] by MGS,
 // H[:, j] filled, w normalised, Givens rotation applied, est and active updated.
-// Instances of up to 48 Ki DoFs (even offsets and lengths) take one launch
-// with w held in registers; longer ones one launch per projection.
-// first_dot_ready: partA already holds the chunk partials of <w, v_0> (the
-// operator's reduction produced them)
-int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready = false);
+// Register-resident where arnoldi_in_registers, else one launch per
+// projection.  first_dot_ready: partA already holds the chunk partials of
+// <w, v_0> (the operator's reduction produced them).  src (register-resident
+// step only, else RTE_EINVAL): w is formed from the operator's partials and
+// V[j+1] need not hold it.
+int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready = false, const PartialSrc* src = nullptr);
 // y = R^{-1} g per instance (jdone columns); X += sum_i y_i * basis_i
 int kylov_solve_update(Krylov& K, const double* basis, double* X, hipStream_t s);
 // start a cycle: V[0] = r / ||r||, g = (beta, 0, ...); the cycle stops at

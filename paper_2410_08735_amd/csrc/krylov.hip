@@ -4,6 +4,7 @@
 // entry is 0.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "krylov.h"
 
@@ -301,6 +302,58 @@ __device__ __forceinline__ double group_sum_all(double v, double* sh) {
   return t;
 }
 
+// w = z - sum_p part_p on a thread's pairs (pair k at byte offset
+// t 16 + k NT 16 of the FP64 arrays), the partials summed in order in FP64
+// (one pass over the pairs per partial, accumulating in w) and combined as
+// the partial-flux reduction combines them; returns the thread's share of
+// <w, v_0>.  Pairs past the end (nbytes) read the first pair and become zeros.
+template <int NT, int NP, int GROUP, typename preal>
+__device__ __forceinline__ double form_w(double2 (&w)[NP], const preal* __restrict__ pb, int np, int64_t n,
+                                         const double* __restrict__ zb, const double* __restrict__ v0, int t,
+                                         uint32_t nbytes) {
+  using P2 = typename std::conditional<sizeof(preal) == 4, float2, double2>::type;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) w[k] = make_double2(0.0, 0.0);
+  for (int q = 0; q < np; ++q) {
+    uint32_t tb = (uint32_t)t * 16u;
+    asm volatile("" : "+v"(tb));
+    const preal* pq = pb + (int64_t)q * n;
+#pragma unroll
+    for (int k0 = 0; k0 < NP; k0 += GROUP) {
+#pragma unroll
+      for (int k = k0; k < k0 + GROUP && k < NP; ++k) {
+        const uint32_t ob = tb + (uint32_t)(k * NT * 16);
+        const P2 a = *reinterpret_cast<const P2*>(pq + ((ob < nbytes ? ob : 0u) >> 3));
+        w[k].x += (double)a.x;
+        w[k].y += (double)a.y;
+      }
+#pragma unroll
+      for (int k = k0; k < k0 + GROUP && k < NP; ++k) asm volatile("" : "+v"(w[k].x), "+v"(w[k].y)::"memory");
+    }
+  }
+  uint32_t tb = (uint32_t)t * 16u;
+  asm volatile("" : "+v"(tb));
+  double acc = 0.0;
+#pragma unroll
+  for (int k0 = 0; k0 < NP; k0 += GROUP) {
+#pragma unroll
+    for (int k = k0; k < k0 + GROUP && k < NP; ++k) {
+      const uint32_t ob = tb + (uint32_t)(k * NT * 16);
+      const bool in = ob < nbytes;
+      const uint32_t e = (in ? ob : 0u) >> 3;
+      const double2 z = *reinterpret_cast<const double2*>(zb + e);
+      const double2 v = *reinterpret_cast<const double2*>(v0 + e);
+      double wx = -1.0 * w[k].x, wy = -1.0 * w[k].y;
+      wx += 1.0 * z.x;
+      wy += 1.0 * z.y;
+      w[k] = in ? make_double2(wx, wy) : make_double2(0.0, 0.0);
+      acc += w[k].x * v.x + w[k].y * v.y;
+    }
+    asm volatile("" : "+v"(acc)::"memory");
+  }
+  return acc;
+}
+
 // Arnoldi step j of every active instance, one work group per instance: w
 // (= V[j+1], PT values per thread, pairs of DoFs 2 (t + k NT)) stays in
 // registers through the MGS projections, each one pass that subtracts
@@ -312,13 +365,14 @@ __device__ __forceinline__ double group_sum_all(double v, double* sh) {
 // partials of <w, v_0> that the operator's reduction left, else the first
 // dot is a pass of its own.  Needs len <= NT * PT and even offsets/lengths.
 constexpr int ARN_MAX_M = 500;
-template <int NT, int PT>
+template <int NT, int PT, int FORM>
 __global__ void __launch_bounds__(NT) k_arnoldi_reg(
     const int64_t* __restrict__ off, const int64_t* __restrict__ len, double* __restrict__ V, int64_t total,
     const double* __restrict__ part0, int maxc, double* __restrict__ H, double* __restrict__ R,
     double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g, int m, int j,
     double* __restrict__ scal, int32_t* __restrict__ active, int32_t* __restrict__ jdone,
-    int32_t* __restrict__ fail, double bt) {
+    int32_t* __restrict__ fail, double bt, const InstPart* __restrict__ parts, const void* __restrict__ part,
+    const double* __restrict__ zsrc) {
   constexpr int NP = PT / 2;
   // pairs per group of loads: fewer where w takes most registers
   constexpr int ARN_GROUP = PT > 32 ? 2 : 4;
@@ -336,8 +390,8 @@ __global__ void __launch_bounds__(NT) k_arnoldi_reg(
   // k at tb + k NT 16.  tb passes through an empty asm statement in every
   // pass, so the compiler forms each pair's address where it is used rather
   // than holding one per pair across the passes (their registers would
-  // spill).  A pair past the instance's end reads its first pair and takes
-  // zeros instead: no branch around a load, so the loads issue back to back.
+  // spill).  A pair past the instance's end reads the instance's first pair
+  // and takes zeros instead, so every address stays in bounds.
   const uint32_t nbytes = (uint32_t)(n * 8);
   auto pair = [nbytes](const double* p, uint32_t ob) {
     const bool in = ob < nbytes;
@@ -346,42 +400,54 @@ __global__ void __launch_bounds__(NT) k_arnoldi_reg(
   };
   double* wp = V + (int64_t)(j + 1) * total + base;
   double2 w[NP];
-  {
-    uint32_t tb = (uint32_t)t * 16u;
-    asm volatile("" : "+v"(tb));
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const uint32_t ob = tb + (uint32_t)(k * NT * 16);
-      w[k] = pair(wp, ob);
-    }
-  }
   int par = 0;
   double h;
-  if (part0) {
-    if (t == 0) {
-      const int nc = (int)((n + KCHUNK - 1) / KCHUNK);
-      double s0 = 0.0;
-      for (int c = 0; c < nc; ++c) s0 += part0[(int64_t)b * maxc + c];
-      sh[1][0] = s0;
-    }
-    __syncthreads();
-    h = sh[1][0];
-  } else {
-    const double* v0 = V + base;
-    uint32_t tb = (uint32_t)t * 16u;
-    asm volatile("" : "+v"(tb));
-    double acc = 0.0;
-#pragma unroll
-    for (int k0 = 0; k0 < NP; k0 += ARN_GROUP) {
-#pragma unroll
-      for (int k = k0; k < k0 + ARN_GROUP && k < NP; ++k) {
-        const double2 v = pair(v0, tb + (uint32_t)(k * NT * 16));
-        acc += w[k].x * v.x + w[k].y * v.y;
-      }
-      asm volatile("" : "+v"(acc)::"memory");
-    }
+  if constexpr (FORM != 0) {
+    // w = z - (the sum of the operator's partial fluxes: FP32 with FORM 1,
+    // FP64 with FORM 2), formed as the partial-flux reduction forms it (same
+    // order, same rounding), and its dot with v_0 on the way
+    using preal = typename std::conditional<FORM == 1, float, double>::type;
+    const InstPart pp = parts[b];
+    const double acc = form_w<NT, NP, ARN_GROUP, preal>(w, reinterpret_cast<const preal*>(part) + pp.off, pp.n,
+                                                        n, zsrc + base, V + base, t, nbytes);
     h = group_sum_all<NT>(acc, sh[par]);
     par ^= 1;
+  } else {
+    {
+      uint32_t tb = (uint32_t)t * 16u;
+      asm volatile("" : "+v"(tb));
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const uint32_t ob = tb + (uint32_t)(k * NT * 16);
+        w[k] = pair(wp, ob);
+      }
+    }
+    if (part0) {
+      if (t == 0) {
+        const int nc = (int)((n + KCHUNK - 1) / KCHUNK);
+        double s0 = 0.0;
+        for (int c = 0; c < nc; ++c) s0 += part0[(int64_t)b * maxc + c];
+        sh[1][0] = s0;
+      }
+      __syncthreads();
+      h = sh[1][0];
+    } else {
+      const double* v0 = V + base;
+      uint32_t tb = (uint32_t)t * 16u;
+      asm volatile("" : "+v"(tb));
+      double acc = 0.0;
+#pragma unroll
+      for (int k0 = 0; k0 < NP; k0 += ARN_GROUP) {
+#pragma unroll
+        for (int k = k0; k < k0 + ARN_GROUP && k < NP; ++k) {
+          const double2 v = pair(v0, tb + (uint32_t)(k * NT * 16));
+          acc += w[k].x * v.x + w[k].y * v.y;
+        }
+        asm volatile("" : "+v"(acc)::"memory");
+      }
+      h = group_sum_all<NT>(acc, sh[par]);
+      par ^= 1;
+    }
   }
   for (int i = 0; i <= j; ++i) {
     if (t == 0) hcol[i] = h;
@@ -566,32 +632,52 @@ int kstart(Krylov& K, const double* r, const double* tol_abs, hipStream_t s, dou
 // The register-resident step: NT threads of PT values each cover every
 // instance, all offsets and lengths even (whole pairs of DoFs).
 template <int NT, int PT>
-static void launch_arnoldi_reg(Krylov& K, int j, hipStream_t s, bool first_dot_ready) {
+static void launch_arnoldi_reg(Krylov& K, int j, hipStream_t s, bool first_dot_ready, const PartialSrc* src) {
   const Space& sp = K.sp;
-  hipLaunchKernelGGL((k_arnoldi_reg<NT, PT>), dim3(sp.n), dim3(NT), 0, s, sp.d_off, sp.d_len, K.V, sp.total,
-                     first_dot_ready ? (const double*)K.partA : nullptr, sp.max_chunks(), K.H, K.R, K.cs, K.sn,
-                     K.g, K.m, j, K.scal, K.active, K.jdone, K.fail, K.bt);
+  const double* p0 = first_dot_ready ? (const double*)K.partA : nullptr;
+  const InstPart* parts = src ? src->parts : nullptr;
+  const void* part = src ? src->part : nullptr;
+  const double* z = src ? src->z : nullptr;
+  if (!src)
+    hipLaunchKernelGGL((k_arnoldi_reg<NT, PT, 0>), dim3(sp.n), dim3(NT), 0, s, sp.d_off, sp.d_len, K.V, sp.total, p0,
+                       sp.max_chunks(), K.H, K.R, K.cs, K.sn, K.g, K.m, j, K.scal, K.active, K.jdone, K.fail, K.bt,
+                       parts, part, z);
+  else if (src->f32)
+    hipLaunchKernelGGL((k_arnoldi_reg<NT, PT, 1>), dim3(sp.n), dim3(NT), 0, s, sp.d_off, sp.d_len, K.V, sp.total, p0,
+                       sp.max_chunks(), K.H, K.R, K.cs, K.sn, K.g, K.m, j, K.scal, K.active, K.jdone, K.fail, K.bt,
+                       parts, part, z);
+  else
+    hipLaunchKernelGGL((k_arnoldi_reg<NT, PT, 2>), dim3(sp.n), dim3(NT), 0, s, sp.d_off, sp.d_len, K.V, sp.total, p0,
+                       sp.max_chunks(), K.H, K.R, K.cs, K.sn, K.g, K.m, j, K.scal, K.active, K.jdone, K.fail, K.bt,
+                       parts, part, z);
 }
 
 // Up to 1024 x 48 values (w in 96 of the 128 registers a thread has with
 // 1024 threads); longer vectors take the chunked kernels.
 constexpr int64_t ARN_MAX_LEN = 1024 * 48;
 
-int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready) {
+bool arnoldi_in_registers(const Krylov& K) {
+  const Space& sp = K.sp;
+  bool even = (sp.total & 1) == 0;
+  for (int q = 0; q < sp.n && even; ++q) even = ((sp.off[q] | sp.len[q]) & 1) == 0;
+  return even && K.m <= ARN_MAX_M && sp.max_len <= ARN_MAX_LEN;
+}
+
+int arnoldi_mgs(Krylov& K, int j, hipStream_t s, bool first_dot_ready, const PartialSrc* src) {
   const Space& sp = K.sp;
   const int mc = sp.max_chunks();
   double* w = K.v(j + 1);
-  bool even = (sp.total & 1) == 0;
-  for (int q = 0; q < sp.n && even; ++q) even = ((sp.off[q] | sp.len[q]) & 1) == 0;
-  if (even && K.m <= ARN_MAX_M && sp.max_len <= ARN_MAX_LEN) {
+  const bool reg = arnoldi_in_registers(K);
+  if (src && !reg) return RTE_EINVAL;  // w from partials: the register-resident step only
+  if (reg) {
     const int64_t L = sp.max_len;
-    if (L <= 1024 * 8) launch_arnoldi_reg<1024, 8>(K, j, s, first_dot_ready);
-    else if (L <= 1024 * 16) launch_arnoldi_reg<1024, 16>(K, j, s, first_dot_ready);
-    else if (L <= 1024 * 24) launch_arnoldi_reg<1024, 24>(K, j, s, first_dot_ready);
-    else if (L <= 1024 * 32) launch_arnoldi_reg<1024, 32>(K, j, s, first_dot_ready);
-    else if (L <= 1024 * 36) launch_arnoldi_reg<1024, 36>(K, j, s, first_dot_ready);
-    else if (L <= 1024 * 40) launch_arnoldi_reg<1024, 40>(K, j, s, first_dot_ready);
-    else launch_arnoldi_reg<1024, 48>(K, j, s, first_dot_ready);
+    if (L <= 1024 * 8) launch_arnoldi_reg<1024, 8>(K, j, s, first_dot_ready, src);
+    else if (L <= 1024 * 16) launch_arnoldi_reg<1024, 16>(K, j, s, first_dot_ready, src);
+    else if (L <= 1024 * 24) launch_arnoldi_reg<1024, 24>(K, j, s, first_dot_ready, src);
+    else if (L <= 1024 * 32) launch_arnoldi_reg<1024, 32>(K, j, s, first_dot_ready, src);
+    else if (L <= 1024 * 36) launch_arnoldi_reg<1024, 36>(K, j, s, first_dot_ready, src);
+    else if (L <= 1024 * 40) launch_arnoldi_reg<1024, 40>(K, j, s, first_dot_ready, src);
+    else launch_arnoldi_reg<1024, 48>(K, j, s, first_dot_ready, src);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
   }
