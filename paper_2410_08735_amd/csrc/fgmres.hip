@@ -258,7 +258,9 @@ int Fgmres::precondition(int jj, int cycle, const double* v, double* z, const So
         RTE_HIP(hipGetLastError());
         mr = m_rom;
       }
-      const int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, mr, s);
+      // A_r(mu) was factorised by the singularity check at the start of this solve
+      const int st = romsad_apply_internal(c.rom, b, c.sigma_t, c.sigma_s, v, z, mr, s, nullptr, nullptr, nullptr,
+                                           true);
       if (st < 0 && st != RTE_ESINGULAR) return st;
       if (any_sing) {
         RTE_TRY(dsa_step(v, z, m_dsa, c, s));

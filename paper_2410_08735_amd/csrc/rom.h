@@ -43,12 +43,16 @@ void rom_free(rte_rom* rom);
 int rom_add_column(rte_rom* rom, const rte_batch* b, hipStream_t s);
 // z = v + W_w A_r(mu)^{-1} W_1^T Sigma_s v for the masked instances.
 // gout (nullable, [n][rcap]) receives W_1^T Sigma_s v; cout (nullable) the solve.
+// use_factors: solve with the factors that the last rom_singular_check on
+// this batch kept (the caller guarantees the same ROM and cross sections;
+// singular is then not written).
 int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_t,
                           const double* sigma_s, const double* v, double* z, const int32_t* active,
                           hipStream_t s, double* gout = nullptr, double* cout = nullptr,
-                          int32_t* singular = nullptr);
+                          int32_t* singular = nullptr, bool use_factors = false);
 bool rom_matches(const rte_rom* rom, const rte_batch* b);
-// sing[b] (device [n_inst]) = 1 where the reduced operator A_r(mu_b) is singular
+// sing[b] (device [n_inst]) = 1 where the reduced operator A_r(mu_b) is singular;
+// the factors of every A_r(mu_b) are kept for romsad_apply_internal(use_factors)
 int rom_singular_check(const rte_rom* rom, rte_batch* b, const double* sigma_t, const double* sigma_s,
                        int32_t* sing, hipStream_t s);
 // z = v + W_w c for given coefficients c [n][rcap] (no solve)

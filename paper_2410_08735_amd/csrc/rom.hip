@@ -326,12 +326,18 @@ __global__ void k_rom_gsum(int n, int nch, const RomDev* __restrict__ tab, const
 // c = (A_D + sum_R st_R G_R - ss_R S_R)^{-1} g, LU with partial pivoting on
 // the matrix augmented by g, one work group of 256 threads per instance: the
 // pivot search in one wave, row swaps and the elimination over all threads.
+// lu_out / piv_out (nullable, [n][ROM_RMAX][ROM_RMAX] and [n][ROM_RMAX]) keep
+// the factors: L (unit, below the diagonal) and U in the final row order, and
+// the row permutation (row i of the factors is row piv[i] of A_r; piv[0] =
+// -1: singular).
 __global__ void __launch_bounds__(256) k_rom_solve(int n, const RomDev* __restrict__ tab,
                                                    const double* __restrict__ sigma_t,
                                                    const double* __restrict__ sigma_s, int max_regions,
                                                    const double* __restrict__ g, double* __restrict__ c,
                                                    int gstride, int32_t* __restrict__ singular,
-                                                   const int32_t* __restrict__ active) {
+                                                   const int32_t* __restrict__ active,
+                                                   double* __restrict__ lu_out = nullptr,
+                                                   int32_t* __restrict__ piv_out = nullptr) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const RomDev Rd = tab[b];
@@ -342,7 +348,7 @@ __global__ void __launch_bounds__(256) k_rom_solve(int n, const RomDev* __restri
   __shared__ double A[ROM_RMAX][ROM_RMAX + 1];  // column r holds the right-hand side
   __shared__ double st_s[ROM_REGMAX], ss_s[ROM_REGMAX];
   __shared__ double amax_s, cb[ROM_RMAX];
-  __shared__ int piv_s;
+  __shared__ int piv_s, perm_s[ROM_RMAX];
   const int t = threadIdx.x;
   for (int R = t; R < nreg; R += blockDim.x) {
     st_s[R] = sigma_t[(int64_t)b * max_regions + R];
@@ -387,6 +393,13 @@ __global__ void __launch_bounds__(256) k_rom_solve(int n, const RomDev* __restri
     }
     __syncthreads();
     const int p = piv_s;
+    if (t == 0) {  // the row permutation so far
+      if (col == 0)
+        for (int i = 0; i < r; ++i) perm_s[i] = i;
+      const int q = perm_s[col];
+      perm_s[col] = perm_s[p];
+      perm_s[p] = q;
+    }
     if (p != col)
       for (int k = t; k <= r; k += blockDim.x) {
         const double tmp = A[col][k];
@@ -408,6 +421,15 @@ __global__ void __launch_bounds__(256) k_rom_solve(int n, const RomDev* __restri
     }
     __syncthreads();
   }
+  if (lu_out) {
+    if (sing) {
+      if (t == 0) piv_out[(int64_t)b * ROM_RMAX] = -1;
+    } else {
+      double* f = lu_out + (int64_t)b * ROM_RMAX * ROM_RMAX;
+      for (int idx = t; idx < r * r; idx += blockDim.x) f[(idx / r) * ROM_RMAX + idx % r] = A[idx / r][idx % r];
+      for (int i = t; i < r; i += blockDim.x) piv_out[(int64_t)b * ROM_RMAX + i] = perm_s[i];
+    }
+  }
   if (t == 0) {
     double* out = c + (int64_t)b * gstride;
     if (sing) {
@@ -422,6 +444,47 @@ __global__ void __launch_bounds__(256) k_rom_solve(int n, const RomDev* __restri
       }
     }
   }
+}
+
+// c = A_r^{-1} g from the factors k_rom_solve kept, one wave per instance,
+// lane i holding row i of the factors in registers and entry i of the
+// solution: x = P g, then forward substitution with the unit L and back
+// substitution with U, column by column (each column's entry broadcast across
+// the wave).  An instance whose factorisation was singular gets c = 0.
+__global__ void __launch_bounds__(64) k_rom_lusolve(int n, const RomDev* __restrict__ tab,
+                                                    const double* __restrict__ lu, const int32_t* __restrict__ piv,
+                                                    const double* __restrict__ g, double* __restrict__ c,
+                                                    int gstride, const int32_t* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const int r = tab[b].r, t = threadIdx.x;
+  const int32_t* pv = piv + (int64_t)b * ROM_RMAX;
+  double* out = c + (int64_t)b * gstride;
+  if (pv[0] < 0) {
+    if (t < r) out[t] = 0.0;
+    return;
+  }
+  const int ti = t < r ? t : 0;  // lanes past the rank read row 0 and take no part
+  const double* f = lu + (int64_t)b * ROM_RMAX * ROM_RMAX + (int64_t)ti * ROM_RMAX;
+  double row[ROM_RMAX];
+#pragma unroll
+  for (int k = 0; k < ROM_RMAX; ++k) row[k] = k < r ? f[k] : 0.0;
+  double xi = g[(int64_t)b * gstride + pv[ti]];
+#pragma unroll
+  for (int col = 0; col + 1 < ROM_RMAX; ++col) {
+    if (col + 1 < r) {
+      const double xc = __shfl(xi, col, 64);
+      if (t > col) xi -= row[col] * xc;
+    }
+  }
+#pragma unroll
+  for (int k = ROM_RMAX - 1; k >= 0; --k) {
+    if (k >= r) continue;
+    if (t == k) xi = xi / row[k];
+    const double xk = __shfl(xi, k, 64);
+    if (t < k) xi -= row[k] * xk;
+  }
+  if (t < r) out[t] = xi;
 }
 
 // z = v + sum_k c[b][k] Ww[k]
@@ -675,6 +738,10 @@ struct RomScratch {
   double* sv = nullptr;  // Sigma_s v of a field-mode batch [total_dof]
   int32_t* sing = nullptr;
   int64_t part_elems = 0;
+  // factors of A_r(mu) kept by the per-solve singularity check ([n][ROM_RMAX]^2,
+  // [n][ROM_RMAX]), allocated on first use
+  double* lu = nullptr;
+  int32_t* piv = nullptr;
   // per-instance ROM table of the last ROM used on this batch
   RomDev* d_tab = nullptr;
   std::vector<RomDev> h_tab;
@@ -764,6 +831,8 @@ void rom_scratch_forget(const rte_batch* b) {
       (void)hipFree(g_rs[i].c);
       (void)hipFree(g_rs[i].part);
       (void)hipFree(g_rs[i].sing);
+      (void)hipFree(g_rs[i].lu);
+      (void)hipFree(g_rs[i].piv);
       (void)hipFree(g_rs[i].sv);
       (void)hipFree(g_rs[i].d_tab);
       g_rs.erase(g_rs.begin() + i);
@@ -1057,7 +1126,7 @@ int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c,
 
 int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_t,
                           const double* sigma_s, const double* v, double* z, const int32_t* active,
-                          hipStream_t s, double* gout, double* cout, int32_t* singular) {
+                          hipStream_t s, double* gout, double* cout, int32_t* singular, bool use_factors) {
   if (rom_max_rank(rom) == 0) {
     RTE_HIP(hipMemcpyAsync(z, v, sizeof(double) * b->total_dof, hipMemcpyDeviceToDevice, s));
     return RTE_OK;
@@ -1071,9 +1140,15 @@ int romsad_apply_internal(const rte_rom* rom, rte_batch* b, const double* sigma_
   double* c = cout ? cout : sc->c;
   int32_t* sing = singular ? singular : sc->sing;
   RTE_TRY(rom_project(rom, b, sigma_s, v, g, active, s));
-  RTE_HIP(hipMemsetAsync(sing, 0, sizeof(int32_t) * b->n_inst, s));
-  hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, tab, sigma_t, sigma_s,
-                     b->max_regions, g, c, ROM_RMAX, sing, active);
+  if (use_factors) {
+    if (!sc->lu) return RTE_EINVAL;  // no singularity check kept factors
+    hipLaunchKernelGGL(k_rom_lusolve, dim3(b->n_inst), dim3(64), 0, s, b->n_inst, tab, sc->lu, sc->piv, g, c,
+                       ROM_RMAX, active);
+  } else {
+    RTE_HIP(hipMemsetAsync(sing, 0, sizeof(int32_t) * b->n_inst, s));
+    hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, tab, sigma_t, sigma_s,
+                       b->max_regions, g, c, ROM_RMAX, sing, active);
+  }
   RTE_HIP(hipGetLastError());
   return rom_lift(rom, b, v, c, z, active, s);
 }
@@ -1102,9 +1177,15 @@ int rom_singular_check(const rte_rom* rom, rte_batch* b, const double* sigma_t, 
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
+  if (!sc->lu && (hipMalloc(&sc->lu, sizeof(double) * sc->n * ROM_RMAX * ROM_RMAX) != hipSuccess ||
+                  hipMalloc(&sc->piv, sizeof(int32_t) * sc->n * ROM_RMAX) != hipSuccess)) {
+    (void)hipFree(sc->lu);
+    sc->lu = nullptr;
+    return RTE_ENOMEM;
+  }
   RTE_HIP(hipMemsetAsync(sc->g, 0, sizeof(double) * b->n_inst * ROM_RMAX, s));
   hipLaunchKernelGGL(k_rom_solve, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, tab, sigma_t, sigma_s,
-                     b->max_regions, sc->g, sc->c, ROM_RMAX, sing, nullptr);
+                     b->max_regions, sc->g, sc->c, ROM_RMAX, sing, nullptr, sc->lu, sc->piv);
   RTE_HIP(hipGetLastError());
   return RTE_OK;
 }
