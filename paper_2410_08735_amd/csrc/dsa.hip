@@ -1266,6 +1266,148 @@ __device__ __forceinline__ void tail_half_sweep(const SymCoef<real>& S, const Lv
   __syncthreads();
 }
 
+// A value from another lane of the same quad (aligned group of 4 lanes):
+// quad_perm [1,0,3,2] (lane xor 1) or [2,3,0,1] (lane xor 2).  The lanes of a
+// quad are active together wherever these are used.
+template <int X>
+__device__ __forceinline__ float quad_xor(float v) {
+  constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, true));
+}
+template <int X>
+__device__ __forceinline__ double quad_xor(double v) {
+  constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), ctrl, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One moment m of axis_cj's outputs: the lane's pair along the axis is
+// (i0, i1) with m one of them (hi: i1 = m); xc, xh, xl: the pair's own, upper
+// and lower neighbour values (x0 the i0 entry, x1 the i1 entry).  The same
+// expressions as axis_cj.
+template <typename real>
+__device__ __forceinline__ void axis_cj_m(real xc0, real xc1, real xh0, real xh1, real xl0, real xl1, bool hi,
+                                          real ih, real& C, real& J) {
+  const real r3 = (real)1.7320508075688772935;
+  const real dl = (xh0 - r3 * xh1) * ih;
+  const real dr = (xl0 + r3 * xl1) * ih;
+  if (!hi) {
+    C = r3 * ih * xc1 + (real)0.5 * (dl - dr);
+    J = (real)-2 * ih * xc0 + dl + dr;
+  } else {
+    C = -r3 * ih * xc0 + (real)0.5 * r3 * (dl + dr);
+    J = (real)-6 * ih * xc1 + r3 * (dl - dr);
+  }
+}
+
+// A red-black half sweep on a small LDS level (at most blockDim / 4 cells of
+// the colour): four lanes per cell, lane m computing moment m of the three
+// fields of the cell's apply and block solve (the partners of its moment
+// along x and y, m ^ 1 and m ^ 2, exchanged within the quad), so a lane's
+// chain of dependent operations is about a third of a whole cell's.  Modes
+// and results as tail_half_sweep.
+template <typename real>
+__device__ __forceinline__ void tail_half_sweep_quad(const SymCoef<real>& S, const LvlInst& L, const real* st,
+                                                     const real* ss, const real* bv, real* x, int color,
+                                                     int mode) {
+  const int nx = L.nx, ny = L.ny, nc = nx * ny;
+  const bool compact = (nx & 1) == 0;
+  const int nwork = compact ? nc / 2 : nc;
+  const int m = threadIdx.x & 3, p = m & 1, q = m >> 1;
+  const int mx = m ^ 1, my = m ^ 2;
+  // the lane's pairs: along x (i0x, i1x) = (m & ~1, m | 1); along y
+  // (i0y, i1y) = (m & 1, (m & 1) + 2)
+  const int i0x = m & 2, i1x = (m & 2) | 1, i0y = p, i1y = p + 2;
+  for (int t = threadIdx.x >> 2; t < nwork; t += blockDim.x >> 2) {
+    int i = 0, k = 0;
+    bool on = true;
+    if (compact) {
+      rb_cell(t, nx, color, i, k);
+    } else {
+      i = t % nx;
+      k = t / nx;
+      on = ((i + k) & 1) == color;
+    }
+    if (!on) continue;
+    const int cell = k * nx + i;
+    const CellPos P = cell_pos(i, k, nx, ny);
+    const real tt = st[cell], uu = ss[cell];
+    real r0, r1, r2;  // moment m of the residual's phi, J_x, J_y rows
+    if (mode == 1) {
+      r0 = bv[m * nc + cell];
+      r1 = bv[(4 + m) * nc + cell];
+      r2 = bv[(8 + m) * nc + cell];
+    } else {
+      const bool own = mode == 0;
+      const int ol = P.hl ? -1 : 0, orr = P.hr ? 1 : 0, ob = P.hb ? -nx : 0, ot = P.ht ? nx : 0;
+      real y0 = (real)0, y1 = (real)0, y2 = (real)0;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const real* xf = x + 4 * f * nc + cell;
+        // own values (zero when !own) and the neighbours of the lane's pairs
+        const real c_m = own ? xf[m * nc] : (real)0;
+        const real cx0 = own ? xf[i0x * nc] : (real)0, cx1 = own ? xf[i1x * nc] : (real)0;
+        const real cy0 = own ? xf[i0y * nc] : (real)0, cy1 = own ? xf[i1y * nc] : (real)0;
+        const real rv0 = xf[i0x * nc + orr], rv1 = xf[i1x * nc + orr];
+        const real lv0 = xf[i0x * nc + ol], lv1 = xf[i1x * nc + ol];
+        const real tv0 = xf[i0y * nc + ot], tv1 = xf[i1y * nc + ot];
+        const real bv0 = xf[i0y * nc + ob], bv1 = xf[i1y * nc + ob];
+        real Cx, Jx, Cy, Jy;
+        axis_cj_m(cx0, cx1, P.hr ? rv0 : (real)0, P.hr ? rv1 : (real)0, P.hl ? lv0 : (real)0,
+                  P.hl ? lv1 : (real)0, p == 1, S.ihx, Cx, Jx);
+        axis_cj_m(cy0, cy1, P.ht ? tv0 : (real)0, P.ht ? tv1 : (real)0, P.hb ? bv0 : (real)0,
+                  P.hb ? bv1 : (real)0, q == 1, S.ihy, Cy, Jy);
+        if (f == 0) {
+          y0 = (tt - uu) * c_m - S.bex * Jx - S.bey * Jy;
+          y1 = S.ax * Cx;
+          y2 = S.ay * Cy;
+        } else if (f == 1) {
+          y0 += (real)3 * S.ax * Cx;
+          y1 += (real)3 * S.ax * tt * c_m - (real)1.5 * (S.cxx * Jx + S.cxy * Jy);
+        } else {
+          y0 += (real)3 * S.ay * Cy;
+          y2 += (real)3 * S.ay * tt * c_m - (real)1.5 * (S.cyx * Jx + S.cyy * Jy);
+        }
+      }
+      r0 = bv[m * nc + cell] - y0;
+      r1 = bv[(4 + m) * nc + cell] - y1;
+      r2 = bv[(8 + m) * nc + cell] - y2;
+    }
+    // the block solve of sym_block_solve, moment m
+    const real r3 = (real)1.7320508075688772935;
+    const real sx = r3 * S.ihx, sy = r3 * S.ihy;
+    const real gx = (real)(p ? 6 : 2) * S.ihx, gy = (real)(q ? 6 : 2) * S.ihy;
+    const real dphi = (tt - uu) + S.bex * gx + S.bey * gy;
+    const real ijx = blk_inv((real)3 * S.ax * tt + (real)1.5 * (S.kxx * gx + S.kxy * gy));
+    const real ijy = blk_inv((real)3 * S.ay * tt + (real)1.5 * (S.kyx * gx + S.kyy * gy));
+    const real tx = r1 * ijx, ty = r2 * ijy;
+    const real tx_p = quad_xor<1>(tx), ijx_p = quad_xor<1>(ijx);
+    const real ty_p = quad_xor<2>(ty), ijy_p = quad_xor<2>(ijy);
+    const real ax3 = (real)3 * S.ax * sx, ay3 = (real)3 * S.ay * sy;
+    real rhs = r0 + (p ? ax3 : -ax3) * tx_p;
+    rhs = rhs + (q ? ay3 : -ay3) * ty_p;
+    const real kx = (real)3 * S.ax * S.ax * sx * sx, ky = (real)3 * S.ay * S.ay * sy * sy;
+    const real o0 = rhs * blk_inv(dphi + kx * ijx_p + ky * ijy_p);
+    const real o0x = quad_xor<1>(o0), o0y = quad_xor<2>(o0);
+    const real axs = S.ax * sx, ays = S.ay * sy;
+    const real o1 = (r1 + (p ? axs : -axs) * o0x) * ijx;
+    const real o2 = (r2 + (q ? ays : -ays) * o0y) * ijy;
+    real* xm = x + m * nc + cell;
+    if (mode == 0) {
+      xm[0] += o0;
+      xm[4 * nc] += o1;
+      xm[8 * nc] += o2;
+    } else {
+      xm[0] = o0;
+      xm[4 * nc] = o1;
+      xm[8 * nc] = o2;
+    }
+  }
+  __syncthreads();
+}
+
 // One red-black sweep of a tail level (colour 0, then colour 1); the first
 // of a smoothing from x = 0 knows x = 0 beforehand in both half sweeps.
 template <typename real, typename sreal>
@@ -1273,6 +1415,26 @@ __device__ __forceinline__ void tail_sweep(const SymCoef<real>& S, const LvlInst
                                            const sreal* ss, const real* bv, real* x, bool from_zero) {
   tail_half_sweep(S, L, st, ss, bv, x, 0, from_zero ? 1 : 0);
   tail_half_sweep(S, L, st, ss, bv, x, 1, from_zero ? 2 : 0);
+}
+
+// A half sweep of an LDS level: four lanes per cell where the colour has at
+// most a quarter of the work group's threads in cells.
+template <typename real>
+__device__ __forceinline__ void tail_half_sweep_lds(const SymCoef<real>& S, const LvlInst& L, const real* st,
+                                                    const real* ss, const real* bv, real* x, int color, int mode) {
+  const int nc = L.nx * L.ny;
+  const int nwork = (L.nx & 1) == 0 ? nc / 2 : nc;
+  if (4 * nwork <= (int)blockDim.x)
+    tail_half_sweep_quad(S, L, st, ss, bv, x, color, mode);
+  else
+    tail_half_sweep(S, L, st, ss, bv, x, color, mode);
+}
+
+template <typename real>
+__device__ __forceinline__ void tail_sweep_lds(const SymCoef<real>& S, const LvlInst& L, const real* st,
+                                               const real* ss, const real* bv, real* x, bool from_zero) {
+  tail_half_sweep_lds(S, L, st, ss, bv, x, 0, from_zero ? 1 : 0);
+  tail_half_sweep_lds(S, L, st, ss, bv, x, 1, from_zero ? 2 : 0);
 }
 
 // Residual of a tail level after a sweep that ended with colour 1 (so only
@@ -1445,7 +1607,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
       real* bv = lds + bo[l];
       const real* sgt = lds + so[l];
       const real* sgs = sgt + nc;
-      for (int k = 0; k < nu_smooth; ++k) tail_sweep(S, L, sgt, sgs, bv, x, k == 0);
+      for (int k = 0; k < nu_smooth; ++k) tail_sweep_lds(S, L, sgt, sgs, bv, x, k == 0);
       tail_restrict(S, L, C, sgt, sgs, x, bv, lds + bo[l + 1]);
     }
   }
@@ -1455,7 +1617,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
     const int nc = L.nx * L.ny;
     const real* sgt = lds + so[l];
-    for (int k = 0; k < coarse_sweeps; ++k) tail_sweep(S, L, sgt, sgt + nc, lds + bo[l], lds + xo[l], k == 0);
+    for (int k = 0; k < coarse_sweeps; ++k) tail_sweep_lds(S, L, sgt, sgt + nc, lds + bo[l], lds + xo[l], k == 0);
   }
   // up: prolong the correction, post-smooth in reverse colour order
   for (int l = nlev - 2; l >= 0; --l) {
@@ -1482,8 +1644,8 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
       const real* sgt = lds + so[l];
       const real* bv = lds + bo[l];
       for (int k = 0; k < nu_smooth; ++k) {
-        tail_half_sweep(S, L, sgt, sgt + nc, bv, x, 1, 0);
-        tail_half_sweep(S, L, sgt, sgt + nc, bv, x, 0, 0);
+        tail_half_sweep_lds(S, L, sgt, sgt + nc, bv, x, 1, 0);
+        tail_half_sweep_lds(S, L, sgt, sgt + nc, bv, x, 0, 0);
       }
     }
   }
