@@ -346,10 +346,12 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   const int btil_prec = f32_btil ? 1 : 0;
   RTE_TRY(sweep_launch(b, btil_prec, c.sigma_t, nullptr, nullptr, c.G, c.inflow, nullptr, s, cyc,
                        f32_btil ? -2.0 : batch_cell_ordinates(b, live.data())));
-  RTE_TRY(reduce_partials(b, btil_prec, 1.0, nullptr, 0.0, btil, s, cyc));
+  // b~ and the chunk partials of ||b~||^2 in one pass
+  RTE_TRY(reduce_partials_dot(b, btil_prec, 1.0, nullptr, 0.0, btil, nullptr, K.partA, K.sp.max_chunks(), KCHUNK,
+                              s, cyc));
   for (int q = 0; q < n; ++q)
     if (live[q]) (f32_btil ? stats[q].sweeps_f32 : stats[q].sweeps_f64) += 1;
-  RTE_TRY(knorm(K.sp, btil, K.partA, bnorm, 1, cyc, s));
+  RTE_TRY(knorm_finish(K.sp, K.partA, bnorm, 1, cyc, s));
   hipLaunchKernelGGL(k_tolabs, dim3((n + 63) / 64), dim3(64), 0, s, n, bnorm, o.rtol, tolabs);
   RTE_TRY(kcopy(K.sp, btil, r, cyc, s));
   double* h_rn = hd + n;
@@ -497,13 +499,15 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
       }
       RTE_TRY(sweep_launch(b, 0, c.sigma_t, nullptr, nullptr, r, c.inflow, nullptr, s, cyc,
                            batch_cell_ordinates(b, cm.data())));
-      RTE_TRY(reduce_partials(b, 0, 1.0, phi, -1.0, r, s, cyc));
+      // r and the chunk partials of ||r||^2 in one pass
+      RTE_TRY(reduce_partials_dot(b, 0, 1.0, phi, -1.0, r, nullptr, K.partA, K.sp.max_chunks(), KCHUNK, s, cyc));
+      RTE_TRY(knorm_finish(K.sp, K.partA, rnorm, 1, cyc, s));
     } else {
       RTE_TRY(sweep_launch(b, 0, c.sigma_t, c.sigma_s, phi, nullptr, nullptr, nullptr, s, cyc,
                            batch_cell_ordinates(b, cm.data())));
       RTE_TRY(reduce_partials(b, 0, 1.0, btil, 1.0, r, s, cyc, phi, -1.0));
+      RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
     }
-    RTE_TRY(knorm(K.sp, r, K.partA, rnorm, 1, cyc, s));
     RTE_HIP(hipMemcpyAsync(h_rn, rnorm, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipMemcpyAsync(h_sc, K.scal, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, s));
     RTE_HIP(hipMemcpyAsync(h_fail, K.fail, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));

@@ -54,6 +54,10 @@ struct Krylov {
 // out[b] = ||x_b||_2 (device, indexed scal-style with stride), masked
 int knorm(const Space& sp, const double* x, double* part, double* out, int out_stride,
           const int32_t* active, hipStream_t s);
+// out[b] = sqrt of the sum of part[b][0 .. chunks of len[b]) (chunk partials
+// of a squared norm in the layout of knorm)
+int knorm_finish(const Space& sp, const double* part, double* out, int out_stride, const int32_t* active,
+                 hipStream_t s);
 // out[b] = <x_b, y_b>
 int kdot(const Space& sp, const double* x, const double* y, double* part, double* out,
          int out_stride, const int32_t* active, hipStream_t s);

@@ -590,6 +590,14 @@ int knorm(const Space& sp, const double* x, double* part, double* out, int strid
   return RTE_OK;
 }
 
+int knorm_finish(const Space& sp, const double* part, double* out, int stride, const int32_t* active,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3((sp.n + 63) / 64), dim3(64), 0, s, sp.n, sp.d_len, part, sp.max_chunks(),
+                     out, stride, 1, active);
+  RTE_HIP(hipGetLastError());
+  return RTE_OK;
+}
+
 int kdot(const Space& sp, const double* x, const double* y, double* part, double* out, int stride,
          const int32_t* active, hipStream_t s) {
   const int mc = sp.max_chunks();

@@ -161,9 +161,10 @@ int prof_last(int slot);
 void prof_set_units(int slot, int idx, double units);
 double batch_cell_ordinates(const rte_batch* b, const int32_t* host_mask);
 // out = alpha * sum_partials + beta * x + gamma * y   (x, y nullable)
-// The same (y unused) with the partial sums of <out, dotv> per instance and
-// chunk of `chunk` DoFs written to part[inst * maxc + chunk index], in the
-// order of the Krylov dot-product kernel (the first MGS projection's input).
+// The same (y unused) with the partial sums of <out, dotv> (<out, out> when
+// dotv is null) per instance and chunk of `chunk` DoFs written to
+// part[inst * maxc + chunk index], in the order of the Krylov dot-product
+// kernel.
 int reduce_partials_dot(rte_batch* b, int prec, double alpha, const double* x, double beta, double* out,
                         const double* dotv, double* part, int maxc, int chunk, hipStream_t s,
                         const int32_t* active);

@@ -1050,9 +1050,10 @@ __global__ void reduce_partials_kernel(const InstDev* __restrict__ insts,
   }
 }
 
-// reduce_partials_kernel fused with the partial dot products <out, dotv>: one
-// work group per chunk of `chunk` DoFs, threads strided over it, then a
-// wave-shuffle and cross-wave sum (256 threads).
+// reduce_partials_kernel fused with the partial dot products <out, dotv>
+// (<out, out> when dotv is null): one work group per chunk of `chunk` DoFs,
+// threads strided over it, then a wave-shuffle and cross-wave sum (256
+// threads).
 template <typename real>
 __global__ void __launch_bounds__(256) reduce_partials_dot_kernel(
     const InstDev* __restrict__ insts, const InstPart* __restrict__ parts, const real* __restrict__ part,
@@ -1099,7 +1100,7 @@ __global__ void __launch_bounds__(256) reduce_partials_dot_kernel(
         v.y += beta * xv.y;
       }
       *reinterpret_cast<double2*>(out + I.dof_off + d) = v;
-      const double2 dv = *reinterpret_cast<const double2*>(dotv + I.dof_off + d);
+      const double2 dv = dotv ? *reinterpret_cast<const double2*>(dotv + I.dof_off + d) : v;
       acc += v.x * dv.x + v.y * dv.y;
     }
   } else {
@@ -1108,7 +1109,7 @@ __global__ void __launch_bounds__(256) reduce_partials_dot_kernel(
       double v = alpha * t;
       if (x) v += beta * x[I.dof_off + d];
       out[I.dof_off + d] = v;
-      acc += v * dotv[I.dof_off + d];
+      acc += v * (dotv ? dotv[I.dof_off + d] : v);
     }
   }
 #pragma unroll
