@@ -1516,12 +1516,22 @@ __device__ __forceinline__ void tail_prolong(const LvlInst& L, const LvlInst& C,
 // 2 on) in between.  The first level's residual goes to level 1 through
 // b1_scratch (global) and its x through x_first; it is smoothed nu0 times
 // before and after the coarse correction.
+// zout (nullable; the FP32 V-cycle whose tail starts at level 1): instead of
+// storing the first level's x, the launch writes the DSA output z = v +
+// (x_fine + P x) on the finest level's scalar-flux unknowns (x_fine: the
+// finest level's scalar-flux field in xfine, v and z in the DG layout of
+// insts), the pass the separate output kernel would make.
 template <typename real, int NT>
 __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restrict__ tl, int nlev, int nu_smooth,
                                                      int coarse_sweeps, const real* __restrict__ b_first,
                                                      real* __restrict__ x_first,
                                                      const int32_t* __restrict__ active, int g0, int nu0,
-                                                     real* __restrict__ b1_scratch) {
+                                                     real* __restrict__ b1_scratch,
+                                                     const InstDev* __restrict__ insts = nullptr,
+                                                     const LvlInst* __restrict__ lf0 = nullptr,
+                                                     const float* __restrict__ xfine = nullptr,
+                                                     const double* __restrict__ vout = nullptr,
+                                                     double* __restrict__ zout = nullptr) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   extern __shared__ unsigned char smem_raw[];
@@ -1638,7 +1648,8 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
         tail_half_sweep(S, L, sgt, sgs, bv, x, 1, 0);
         tail_half_sweep(S, L, sgt, sgs, bv, x, 0, 0);
       }
-      for (int e = threadIdx.x; e < 12 * nc; e += blockDim.x) xg[e] = x[e];
+      if (!zout)
+        for (int e = threadIdx.x; e < 12 * nc; e += blockDim.x) xg[e] = x[e];
     } else {
       tail_prolong(L, C, xc, x, x);
       const real* sgt = lds + so[l];
@@ -1649,7 +1660,37 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
       }
     }
   }
-  if (!g0) {  // x of the first level
+  if (zout) {
+    // z = v + (x_fine + P x) on the finest level's scalar-flux unknowns (the
+    // arithmetic of k_dsa_out_prolong, with the first level's x from LDS)
+    const InstDev I = insts[b];
+    const LvlInst F = lf0[b];
+    const int nfc = F.nx * F.ny;
+    const float* __restrict__ xb = xfine + F.cell_off * 12;
+    const real* xl = lds + xo[0];
+    for (int cell = threadIdx.x; cell < nfc; cell += blockDim.x) {
+      const int i = cell % F.nx, k = cell / F.nx;
+      const int parent = (k >> 1) * L0.nx + (i >> 1);
+      float xc[4];
+#pragma unroll
+      for (int L2 = 0; L2 < 4; ++L2) xc[L2] = (float)xl[L2 * nc0 + parent];
+      const double2* vp = reinterpret_cast<const double2*>(vout + I.dof_off + 4 * (int64_t)cell);
+      double2* zp = reinterpret_cast<double2*>(zout + I.dof_off + 4 * (int64_t)cell);
+      const double2 v01 = vp[0], v23 = vp[1];
+      const double vv[4] = {v01.x, v01.y, v23.x, v23.y};
+      double o[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        float corr = 0.f;
+#pragma unroll
+        for (int L2 = 0; L2 < 4; ++L2)
+          corr += (float)(inj1d(i & 1, m & 1, L2 & 1) * inj1d(k & 1, m >> 1, L2 >> 1)) * xc[L2];
+        o[m] = vv[m] + (double)(xb[m * nfc + cell] + corr);
+      }
+      zp[0] = make_double2(o[0], o[1]);
+      zp[1] = make_double2(o[2], o[3]);
+    }
+  } else if (!g0) {  // x of the first level
     real* dst = x_first + L0.cell_off * 12;
     for (int e = threadIdx.x; e < 12 * nc0; e += blockDim.x) dst[e] = lds[xo[0] + e];
   }
@@ -1696,6 +1737,10 @@ struct DsaSolver {
   // set by apply for one FP32 V-cycle: level 0 stops after the coarse
   // correction, which k_dsa_out_prolong then adds while writing the output
   bool defer_fine_prolong = false;
+  // set by apply when the tail (starting at level 1) writes the output z itself
+  const double* tail_out_v = nullptr;
+  double* tail_out_z = nullptr;
+  const float* tail_out_xf = nullptr;
   // set by apply for that V-cycle too: level 0's first two half sweeps form
   // the right-hand side from v (the first stores its colour-0 part)
   const double* rhs_from_v = nullptr;
@@ -1966,7 +2011,8 @@ int DsaSolver::vcycle(int l, const double* bv, double* x, const int32_t* act, hi
     if (f32)
       hipLaunchKernelGGL((k_mg_tail_sym<float, MG_TAIL_THREADS_F32>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F32), tail_lds, s, d_tail, nt, nu_smooth,
                          coarse_sweeps, reinterpret_cast<const float*>(bv), reinterpret_cast<float*>(x), act,
-                         tail_g0, nu_hbm, tail_g0 ? reinterpret_cast<float*>(lv[l + 1].b) : (float*)nullptr);
+                         tail_g0, nu_hbm, tail_g0 ? reinterpret_cast<float*>(lv[l + 1].b) : (float*)nullptr,
+                         b->d_inst, lv[0].d_li, tail_out_xf, tail_out_v, tail_out_z);
     else
       hipLaunchKernelGGL((k_mg_tail_sym<double, MG_TAIL_THREADS_F64>), dim3(b->n_inst), dim3(MG_TAIL_THREADS_F64), tail_lds, s, d_tail, nt, nu_smooth,
                          coarse_sweeps, bv, x, act, 0, nu_smooth, (double*)nullptr);
@@ -2072,6 +2118,8 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
   // restriction) and whose fine correction goes straight into z
   const bool fused_out = restart == 0 && inner_max == 1 && f32 && sym && lv.size() >= 2 &&
                          nu_hbm_finest_post == 0 && tail_first != 0 && nu_hbm == 1;
+  // the V-cycle's tail starts at level 1: it writes z itself
+  const bool tail_out = fused_out && tail_first == 1;
   if (fused_out) {
     // the V-cycle forms the right-hand side itself
   } else if (b->n_fields > 0)
@@ -2091,9 +2139,17 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
       if (k == 0) {
         defer_fine_prolong = fused_out;
         rhs_from_v = fused_out ? v : nullptr;
+        if (tail_out) {
+          tail_out_v = v;
+          tail_out_z = z;
+          tail_out_xf = reinterpret_cast<const float*>(X);
+        }
         const int st = precond(rhs, X, active, s);
         defer_fine_prolong = false;
         rhs_from_v = nullptr;
+        tail_out_v = nullptr;
+        tail_out_z = nullptr;
+        tail_out_xf = nullptr;
         RTE_TRY(st);
       } else {
         RTE_TRY(stencil(0, 1, 0, rhs, X, lv[0].b, active, s));
@@ -2166,7 +2222,9 @@ int DsaSolver::apply(const double* sigma_t, const double* sigma_s, const double*
       RTE_HIP(hipMemcpyAsync(d_live, live_h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     }
   }
-  if (fused_out)
+  if (tail_out) {
+    // z written by the tail
+  } else if (fused_out)
     hipLaunchKernelGGL(k_dsa_out_prolong, grid(0), dim3(256), 0, s, b->d_inst, lv[0].d_li, lv[1].d_li,
                        reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(lv[1].x), v, z, active);
   else if (f32)
