@@ -312,6 +312,153 @@ __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restr
   }
 }
 
+// Stages the chunk [e0, e0 + ne) of r basis vectors in LDS in the order the
+// projection's matrix-core steps read them: the value for column block c,
+// step st, item i, lane (kq, row) (basis row 16 c + row, DoF
+// e0 + 32 st + 8 kq + i) at (((c NS + st) 8 + i) 4 + kq) 16 + row, so that
+// one read of item i by the 64 lanes of a wave covers 64 consecutive doubles
+// (no bank conflicts); zeros past ne and for rows at or past r.  Eight
+// global reads in flight per thread.
+template <int CH>
+__device__ __forceinline__ void stage_basis_mfma_b(const double* __restrict__ W, int r, int nd, int e0, int ne,
+                                                   double* Wl) {
+  constexpr int NS = CH / 32;
+  const int ncb = (r + 15) >> 4;
+  const int total = ncb * NS * 8 * 64;  // slots
+  // thread by slot: the LDS writes of a wave are 64 consecutive doubles; the
+  // reads gather 16 basis rows (from the cache after the first touch)
+  for (int base = 0; base < total; base += 8 * (int)blockDim.x) {
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int sl = base + u * (int)blockDim.x + (int)threadIdx.x;
+      const int row = sl & 15, kq = (sl >> 4) & 3, i = (sl >> 6) & 7, cst = sl >> 9;
+      const int st = cst % NS, c = cst / NS;
+      const int k = 16 * c + row, el = 32 * st + 8 * kq + i;
+      const bool in = sl < total && k < r && el < ne;
+      const double x = W[(int64_t)(in ? k : 0) * nd + e0 + (in ? el : 0)];
+      w[u] = in ? x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int sl = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (sl < total) Wl[sl] = w[u];
+    }
+  }
+}
+
+// The same projection with each basis chunk shared by the four waves of a
+// work group: a work group takes 64 instances (16 per wave, as above) and one
+// chunk of PM_DOF DoFs, stages the chunk of every basis vector (r x PM_DOF
+// values) in LDS once and lets the four waves read it there, so the basis is
+// read once per 64 instances instead of once per 16.  The runs of v are read
+// as 16-byte pairs at clamped addresses (a pair past the end, or of an
+// inactive instance, reads the instance's first pair and becomes zero), each
+// cell's region with its run and sigma_s from the instance's table.
+template <int NL>
+__global__ void __launch_bounds__(256) k_rom_project_lds(const InstDev* __restrict__ insts,
+                                                         const int32_t* __restrict__ region,
+                                                         const double* __restrict__ sigma_s, int max_regions,
+                                                         const double* __restrict__ W, int r, int nd, int n,
+                                                         const double* __restrict__ v, double* __restrict__ part,
+                                                         int nch, const int32_t* __restrict__ active) {
+  extern __shared__ double Wl[];  // the basis chunk in the order of the steps (stage_basis_mfma_b)
+  const int chunk = blockIdx.x;
+  const int e0 = chunk * PM_DOF;
+  const int ne = min(PM_DOF, nd - e0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  const int b = blockIdx.y * 64 + wave * 16 + row;
+  const bool on = b < n && (!active || active[b]);
+  const double* vb = v;
+  const int32_t* rb = region;
+  const double* sb = sigma_s;
+  if (on) {
+    const InstDev I = insts[b];
+    vb = v + I.dof_off;
+    rb = region + I.region_off;
+    if (sigma_s) sb = sigma_s + (int64_t)b * max_regions;
+  }
+  const int ncb = (r + 15) >> 4;
+  // every run of v the wave needs first (clamped addresses), then the
+  // regions of their cells, then sigma_s: three rounds of loads, each all in
+  // flight together, and the basis chunk while the last is
+  constexpr int NS = PM_DOF / 32, NC = 8 / NL;  // steps; cells per run
+  double a[NS][8];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {  // steps past the chunk's end add zeros
+    const int el = st * 32 + kq * 8;  // multiple of 8, so of NL
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = e0 + el + 2 * i;
+      const bool in = on && e < nd;
+      const double2 x = *reinterpret_cast<const double2*>(vb + (in ? e : 0));
+      a[st][2 * i] = in ? x.x : 0.0;
+      a[st][2 * i + 1] = in ? x.y : 0.0;
+    }
+  }
+  if (sigma_s) {
+    int rg[NS][NC];
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int cell = (e0 + st * 32 + kq * 8) / NL + q;
+        rg[st][q] = rb[(on && cell * NL < nd) ? cell : 0];
+      }
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int cell = (e0 + st * 32 + kq * 8) / NL + q;
+        const double sg = (on && cell * NL < nd) ? sb[rg[st][q]] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) a[st][q * NL + i] *= sg;
+      }
+  }
+  stage_basis_mfma_b<PM_DOF>(W, r, nd, e0, ne, Wl);
+  __syncthreads();
+  rom_d4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = rom_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < NS; ++st) {
+    const int el = st * 32 + kq * 8;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < ncb) {
+        const double* wr = Wl + ((c * NS + st) * 8 * 4 + kq) * 16 + row;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], wr[i * 64], acc[c], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= ncb) break;
+    const int k = 16 * c + row;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int bi = blockIdx.y * 64 + wave * 16 + kq + 4 * j;
+      if (bi < n && k < r) part[((int64_t)bi * nch + chunk) * ROM_RMAX + k] = acc[c][j];
+    }
+  }
+}
+
+// g[b][k] = the sum over chunks of part, one wave per instance (lane k), the
+// chunks summed in order (the result of k_rom_gsum).
+__global__ void __launch_bounds__(64) k_rom_gsum_wave(int n, int nch, const RomDev* __restrict__ tab,
+                                                      const double* __restrict__ part, double* __restrict__ g,
+                                                      const int32_t* __restrict__ active) {
+  const int b = blockIdx.x, k = threadIdx.x;
+  if ((active && !active[b]) || k >= tab[b].r) return;
+  const double* pb = part + (int64_t)b * nch * ROM_RMAX + k;
+  double t = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < nch; ++c) t += pb[(int64_t)c * ROM_RMAX];
+  g[(int64_t)b * ROM_RMAX + k] = t;
+}
+
 __global__ void k_rom_gsum(int n, int nch, const RomDev* __restrict__ tab, const double* __restrict__ part,
                            double* __restrict__ g, const int32_t* __restrict__ active) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -558,6 +705,104 @@ __global__ void __launch_bounds__(256) k_rom_lift_mfma(const InstDev* __restrict
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (on[j] && e < nd) z[off[j] + e] = (v ? v[off[j] + e] : 0.0) + acc[j];
+  }
+}
+
+// Stages the chunk [e0, e0 + ne) of r basis vectors in LDS in the order the
+// lift's matrix-core steps read them: for DoF step t, basis step st and lane
+// (kq, row) (basis row 4 st + kq, DoF e0 + 16 t + row) at
+// ((t ns + st) 4 + kq) 16 + row with ns = ceil(r / 4), so that one read by
+// the 64 lanes of a wave covers 64 consecutive doubles; zeros past ne and
+// for rows at or past r.
+template <int CH>
+__device__ __forceinline__ void stage_basis_mfma_lift(const double* __restrict__ W, int r, int nd, int e0, int ne,
+                                                      double* Wl) {
+  const int ns = (r + 3) >> 2;
+  const int total = (CH / 16) * ns * 64;
+  for (int base = 0; base < total; base += 8 * (int)blockDim.x) {
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int sl = base + u * (int)blockDim.x + (int)threadIdx.x;
+      const int row = sl & 15, kq = (sl >> 4) & 3, tst = sl >> 6;
+      const int st = tst % ns, t = tst / ns;
+      const int k = 4 * st + kq, el = 16 * t + row;
+      const bool in = sl < total && k < r && el < ne;
+      const double x = W[(int64_t)(in ? k : 0) * nd + e0 + (in ? el : 0)];
+      w[u] = in ? x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int sl = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (sl < total) Wl[sl] = w[u];
+    }
+  }
+}
+
+// The lift with each basis chunk shared by the four waves of a work group:
+// 64 instances (16 per wave, as k_rom_lift_mfma) and one chunk of PL_DOF
+// DoFs per work group, the chunk of every basis vector staged in LDS once.
+// v is read at clamped addresses (no branch around a load); only the stores
+// of z are conditional.
+__global__ void __launch_bounds__(256) k_rom_lift_lds(const InstDev* __restrict__ insts,
+                                                      const double* __restrict__ W, int r, int nd, int n,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ c, double* __restrict__ z,
+                                                      const int32_t* __restrict__ active) {
+  extern __shared__ double Wl[];  // the basis chunk in the order of the steps (stage_basis_mfma_lift)
+  const int e0 = blockIdx.x * PL_DOF;
+  const int ne = min(PL_DOF, nd - e0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  const int g0 = blockIdx.y * 64 + wave * 16;
+  const int ba = g0 + row;
+  double ca[ROM_RMAX / 4];
+#pragma unroll
+  for (int st = 0; st < ROM_RMAX / 4; ++st) {
+    const int k = 4 * st + kq;
+    ca[st] = (ba < n && k < r) ? c[(int64_t)ba * ROM_RMAX + k] : 0.0;
+  }
+  int64_t off[4];
+  bool on[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int bo = g0 + kq + 4 * j;
+    on[j] = bo < n && (!active || active[bo]);
+    off[j] = on[j] ? insts[bo].dof_off : 0;
+  }
+  const int ns = (r + 3) >> 2;
+  // every value of v the wave needs first (clamped addresses), so that the
+  // loads are all in flight together
+  double vv[PL_DOF / 16][4];
+  const double* vs = v ? v : z;  // without v: any valid address, the values are dropped
+#pragma unroll
+  for (int t = 0; t < PL_DOF / 16; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + t * 16 + row;
+      const int64_t o = (on[j] && e < nd) ? off[j] + e : 0;
+      vv[t][j] = vs[o];
+    }
+  if (!v)
+#pragma unroll
+    for (int t = 0; t < PL_DOF / 16; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vv[t][j] = 0.0;
+  // the basis chunk while those loads are in flight
+  stage_basis_mfma_lift<PL_DOF>(W, r, nd, e0, ne, Wl);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < PL_DOF / 16; ++t) {  // past the chunk's end no store
+    const int el = t * 16 + row;
+    const int e = e0 + el;
+    rom_d4 acc = rom_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < ROM_RMAX / 4; ++st)
+      if (st < ns)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[st], Wl[((t * ns + st) * 4 + kq) * 16 + row], acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (on[j] && e < nd) z[off[j] + e] = vv[t][j] + acc[j];
   }
 }
 
@@ -1081,6 +1326,35 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
     v = sc->sv;
     sigma_s = nullptr;
   }
+  // the LDS-staged kernel may take up to ROM_RMAX x PM_DOF doubles (128 KiB)
+  static int lds_ok = -1;
+  if (lds_ok < 0) {
+    const int bytes = (int)(sizeof(double) * ROM_RMAX * PM_DOF);
+    lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rom_project_lds<4>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess &&
+                     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rom_project_lds<2>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess
+                 ? 1
+                 : 0;
+    if (!lds_ok) (void)hipGetLastError();
+  }
+  if (lds_ok && !rom->is_set() && nd < (1 << 30) && (nd & 1) == 0) {
+    // the basis chunk staged in LDS, shared by 64 instances
+    const int nchm = (int)((nd + PM_DOF - 1) / PM_DOF);
+    const dim3 grid(nchm, (b->n_inst + 63) / 64);
+    const size_t lds = sizeof(double) * 16 * ((rom->r + 15) / 16) * PM_DOF;
+    const double* Wp = which ? rom->Ww : rom->W1;
+    if (b->inst[0].nloc == 4)
+      hipLaunchKernelGGL(k_rom_project_lds<4>, grid, dim3(256), lds, s, b->d_inst, b->d_region, sigma_s,
+                         b->max_regions, Wp, rom->r, (int)nd, b->n_inst, v, sc->part, nchm, active);
+    else
+      hipLaunchKernelGGL(k_rom_project_lds<2>, grid, dim3(256), lds, s, b->d_inst, b->d_region, sigma_s,
+                         b->max_regions, Wp, rom->r, (int)nd, b->n_inst, v, sc->part, nchm, active);
+    hipLaunchKernelGGL(k_rom_gsum_wave, dim3(b->n_inst), dim3(64), 0, s, b->n_inst, nchm, tab, sc->part, g,
+                       active);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   if (!rom->is_set() && nd < (1 << 30)) {
     const int nchm = (int)((nd + PM_DOF - 1) / PM_DOF);
     const dim3 grid((nchm + 3) / 4, (b->n_inst + 15) / 16);
@@ -1111,6 +1385,24 @@ int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c,
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
+  static int lds_ok = -1;  // up to ROM_RMAX x PL_DOF doubles (128 KiB) of LDS
+  if (lds_ok < 0) {
+    lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rom_lift_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(sizeof(double) * ROM_RMAX * PL_DOF)) == hipSuccess
+                 ? 1
+                 : 0;
+    if (!lds_ok) (void)hipGetLastError();
+  }
+  if (lds_ok && !rom->is_set() && nd < (1 << 30) && (nd & 1) == 0) {
+    // the basis chunk staged in LDS, shared by 64 instances
+    const int nw = (int)((nd + PL_DOF - 1) / PL_DOF);
+    hipLaunchKernelGGL(k_rom_lift_lds, dim3(nw, (b->n_inst + 63) / 64), dim3(256),
+                       sizeof(double) * 4 * ((rom->r + 3) / 4) * PL_DOF,
+                       s, b->d_inst, rom->Ww, rom->r, (int)nd, b->n_inst, v, c, z, active);
+    RTE_HIP(hipGetLastError());
+    return RTE_OK;
+  }
   if (!rom->is_set() && nd < (1 << 30)) {
     const int nw = (int)((nd + PL_DOF - 1) / PL_DOF);
     hipLaunchKernelGGL(k_rom_lift_mfma, dim3((nw + 3) / 4, (b->n_inst + 15) / 16), dim3(256), 0, s, b->d_inst,
