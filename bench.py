@@ -251,9 +251,9 @@ def learned_leg(args, common):
         if name == "mlp":
             res[name]["fallbacks"] = int(sum(s["pc_fallback"] for s in stats))
             res[name]["mlp_applies"] = int(sum(s["pc_mlp"] for s in stats))
-            jd = np.array([s["mlp_judge"] for s in stats])
-            res[name]["judge_rel_diff_vs_rom_mean"] = float(jd.mean())
-            res[name]["judge_rel_diff_vs_rom_max"] = float(jd.max())
+            jd = np.array([s["mlp_rom_diff"] for s in stats])
+            res[name]["mlp_rom_rel_diff_mean"] = float(jd.mean())
+            res[name]["mlp_rom_rel_diff_max"] = float(jd.max())
         log(f"learned: {name}: {ok / dt:.1f} solves/s, iterations mean {its.mean():.2f} max {its.max()}, "
             f"converged {ok}/{len(stats)}")
     out.update(res)

@@ -298,9 +298,9 @@ typedef struct {
   double est_relres;     /* last Givens estimate / ||b~||                     */
   int32_t rom_singular;  /* 1: A_r(mu) singular, DSA ran in place of the ROM  */
   int32_t pad;
-  double mlp_judge;      /* RTE_PC_MLP: mean over the network's steps of
-                            ||W_w (c_MLP - c_ROM)|| / ||W_w c_ROM||, the ROM
-                            solve judging the learned correction; else 0    */
+  double mlp_rom_diff;   /* RTE_PC_MLP: mean over the network's steps of
+                            ||W_w (c_MLP - c_ROM)|| / ||W_w c_ROM||, the
+                            learned correction against the ROM solve; else 0 */
 } rte_solve_stats;
 
 int fgmres_solve(const rte_batch* b, const double* sigma_t, const double* sigma_s, const double* G,

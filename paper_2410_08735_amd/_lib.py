@@ -41,7 +41,7 @@ class SolveStats(C.Structure):
     _fields_ = [("iterations", i32), ("cycles", i32), ("sweeps_f32", i32), ("sweeps_f64", i32),
                 ("pc_rom", i32), ("pc_dsa", i32), ("pc_mlp", i32), ("pc_fallback", i32),
                 ("status", i32), ("true_relres", dbl), ("est_relres", dbl), ("rom_singular", i32),
-                ("pad", i32), ("mlp_judge", dbl)]
+                ("pad", i32), ("mlp_rom_diff", dbl)]
 
 
 class GreedyReport(C.Structure):

@@ -323,7 +323,7 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   dsa_ready = false;  // the DSA hierarchy is rebuilt for this call's cross sections
   K.bt = o.breakdown_tol > 0.0 ? o.breakdown_tol : 1e-14;
   RTE_TRY(fill_i32(K.fail, n, 0, s));
-  if (o.precond == RTE_PC_MLP) RTE_TRY(mlp_judge_reset(b, s));
+  if (o.precond == RTE_PC_MLP) RTE_TRY(mlp_rom_diff_reset(b, s));
   // A_r(mu) depends on mu only: its singularity is decided once per solve
   any_sing = false;
   sing_h.assign(n, 0);
@@ -536,8 +536,8 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
   }
   if (o.precond == RTE_PC_MLP) {
     std::vector<double> jm;
-    RTE_TRY(mlp_judge_read(b, jm, s));
-    for (int q = 0; q < n; ++q) stats[q].mlp_judge = jm[q];
+    RTE_TRY(mlp_rom_diff_read(b, jm, s));
+    for (int q = 0; q < n; ++q) stats[q].mlp_rom_diff = jm[q];
   }
   return ret;
 }

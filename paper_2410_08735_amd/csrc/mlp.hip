@@ -576,7 +576,7 @@ struct MlpScratch {
   const rte_batch* b = nullptr;
   double *g = nullptr, *c = nullptr, *gn = nullptr;
   int32_t *um = nullptr, *ur = nullptr;
-  // the judge of the learned correction: the ROM solve's coefficients, the
+  // comparison of the learned correction with the ROM: the ROM solve's coefficients, the
   // Gram matrix of W_w (of gram_rom), and per-instance sums and counts of
   // ||W_w (c_MLP - c_ROM)|| / ||W_w c_ROM|| over the network's steps
   double *crom = nullptr, *gram = nullptr, *jsum = nullptr;
@@ -622,7 +622,7 @@ __global__ void k_gram(int r, int64_t nd, const double* __restrict__ W, double* 
 
 // jsum[b] += ||W_w d|| / ||W_w c_ROM||, d = c_MLP - c_ROM, with the Gram matrix
 // of W_w (so the norms are those of the lifted scalar-flux corrections)
-__global__ void k_mlp_judge(int n, int r, const double* __restrict__ gram, const double* __restrict__ cm,
+__global__ void k_mlp_rom_diff(int n, int r, const double* __restrict__ gram, const double* __restrict__ cm,
                             const double* __restrict__ cr, int stride, double* __restrict__ jsum,
                             int32_t* __restrict__ jcnt, const int32_t* __restrict__ on) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -645,7 +645,7 @@ __global__ void k_mlp_judge(int n, int r, const double* __restrict__ gram, const
   }
 }
 
-int mlp_judge_reset(const rte_batch* b, hipStream_t s) {
+int mlp_rom_diff_reset(const rte_batch* b, hipStream_t s) {
   for (auto& m : g_ms)
     if (m.b == b) {
       RTE_HIP(hipMemsetAsync(m.jsum, 0, sizeof(double) * b->n_inst, s));
@@ -654,8 +654,8 @@ int mlp_judge_reset(const rte_batch* b, hipStream_t s) {
   return RTE_OK;
 }
 
-// mean judge per instance (0 where the network made no step); syncs s
-int mlp_judge_read(const rte_batch* b, std::vector<double>& out, hipStream_t s) {
+// mean relative difference per instance (0 where the network made no step); syncs s
+int mlp_rom_diff_read(const rte_batch* b, std::vector<double>& out, hipStream_t s) {
   out.assign(b->n_inst, 0.0);
   for (auto& m : g_ms)
     if (m.b == b) {
@@ -694,7 +694,7 @@ int mlp_precond(const rte_mlp* cm, const rte_rom* rom, rte_batch* b, const doubl
   hipLaunchKernelGGL(k_mlp_coeffs, dim3((n * r + 255) / 256), dim3(256), 0, s, n, r, m->H[L], sc->gn, sc->c,
                      ROM_GSTRIDE, sc->um);
   RTE_HIP(hipGetLastError());
-  // the judge: the ROM solve's coefficients for the same reduced right-hand side
+  // the comparison: the ROM solve's coefficients for the same reduced right-hand side
   if (sc->gram_rom != rom || sc->gram_r != r) {
     hipLaunchKernelGGL(k_gram, dim3(r * r), dim3(256), 0, s, r, rom->ndof, rom->Ww, sc->gram);
     RTE_HIP(hipGetLastError());
@@ -702,7 +702,7 @@ int mlp_precond(const rte_mlp* cm, const rte_rom* rom, rte_batch* b, const doubl
     sc->gram_r = r;
   }
   RTE_TRY(rom_solve_coeffs(rom, b, sigma_t, sigma_s, sc->g, sc->crom, sc->um, s));
-  hipLaunchKernelGGL(k_mlp_judge, dim3((n + 63) / 64), dim3(64), 0, s, n, r, sc->gram, sc->c, sc->crom, ROM_GSTRIDE,
+  hipLaunchKernelGGL(k_mlp_rom_diff, dim3((n + 63) / 64), dim3(64), 0, s, n, r, sc->gram, sc->c, sc->crom, ROM_GSTRIDE,
                      sc->jsum, sc->jcnt, sc->um);
   RTE_HIP(hipGetLastError());
   return rom_lift(rom, b, v, sc->c, z, sc->um, s);

@@ -67,8 +67,8 @@ constexpr int ROM_GSTRIDE = 64;  // stride of per-instance reduced vectors g, c
 // c = A_r(mu)^{-1} g per masked instance (g, c [n][ROM_GSTRIDE]), no lift
 int rom_solve_coeffs(const rte_rom* rom, rte_batch* b, const double* sigma_t, const double* sigma_s,
                      const double* g, double* c, const int32_t* active, hipStream_t s);
-int mlp_judge_reset(const rte_batch* b, hipStream_t s);
-int mlp_judge_read(const rte_batch* b, std::vector<double>& out, hipStream_t s);
+int mlp_rom_diff_reset(const rte_batch* b, hipStream_t s);
+int mlp_rom_diff_read(const rte_batch* b, std::vector<double>& out, hipStream_t s);
 int mlp_precond(const rte_mlp* mlp, const rte_rom* rom, rte_batch* b, const double* sigma_t,
                 const double* sigma_s, const double* mu, int mu_dim, const double* v, double* z,
                 const int32_t* active, hipStream_t s, int32_t* fallback_flags);

@@ -213,9 +213,9 @@ def test_trained_network_needs_fewer_iterations_than_romsad():
         _, stats, ret = rt.fgmres_solve(Bt, st, ss, G, None, rt.SolveOptions(precond=name, **common), **kw)
         assert ret == 0 and all(s["true_relres"] <= 1e-8 for s in stats)
         its[name] = float(np.mean([s["iterations"] for s in stats]))
-        if name == "mlp":  # the ROM solve's judgement of the network's corrections
-            judge = np.array([s["mlp_judge"] for s in stats])
-            assert np.all(np.isfinite(judge)) and np.all(judge > 0.0)
+        if name == "mlp":  # the ROM solve's comparison with the network's corrections
+            diff = np.array([s["mlp_rom_diff"] for s in stats])
+            assert np.all(np.isfinite(diff)) and np.all(diff > 0.0)
     print(f"rank {r}, {X.shape[0]} rows, loss {hist[0]:.3e} -> {hist[-1]:.3e}; mean iterations {its}; "
-          f"judge ||dphi_MLP - dphi_ROM|| / ||dphi_ROM|| mean {judge.mean():.3f}")
+          f"MLP vs ROM ||dphi_MLP - dphi_ROM|| / ||dphi_ROM|| mean {diff.mean():.3f}")
     assert its["mlp"] < its["romsad"], its
