@@ -237,6 +237,10 @@ __global__ void k_rom_project(const InstDev* __restrict__ insts, const int32_t* 
 // holds, in lane l and item j, instance l / 16 + 4 j and rank column
 // 16 c + l % 16.  Partial sums per (instance, DoF chunk) as above.
 constexpr int PM_DOF = 256;
+// DoFs per work group of the LDS-staged projection and lift: short chunks give
+// a launch many work groups (16 KiB of LDS each at rank 32) to hide the load
+// latency, at the cost of more partial sums for the projection
+constexpr int PJL_DOF = 64, LFL_DOF = 64;
 typedef double rom_d4 __attribute__((ext_vector_type(4)));
 template <int NL>  // moments per cell (4 in X-Y, 2 in slab geometry)
 __global__ void __launch_bounds__(256) k_rom_project_mfma(const InstDev* __restrict__ insts,
@@ -349,7 +353,7 @@ __device__ __forceinline__ void stage_basis_mfma_b(const double* __restrict__ W,
 
 // The same projection with each basis chunk shared by the four waves of a
 // work group: a work group takes 64 instances (16 per wave, as above) and one
-// chunk of PM_DOF DoFs, stages the chunk of every basis vector (r x PM_DOF
+// chunk of PJL_DOF DoFs, stages the chunk of every basis vector (r x PJL_DOF
 // values) in LDS once and lets the four waves read it there, so the basis is
 // read once per 64 instances instead of once per 16.  The runs of v are read
 // as 16-byte pairs at clamped addresses (a pair past the end, or of an
@@ -364,8 +368,8 @@ __global__ void __launch_bounds__(256) k_rom_project_lds(const InstDev* __restri
                                                          int nch, const int32_t* __restrict__ active) {
   extern __shared__ double Wl[];  // the basis chunk in the order of the steps (stage_basis_mfma_b)
   const int chunk = blockIdx.x;
-  const int e0 = chunk * PM_DOF;
-  const int ne = min(PM_DOF, nd - e0);
+  const int e0 = chunk * PJL_DOF;
+  const int ne = min(PJL_DOF, nd - e0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
   const int b = blockIdx.y * 64 + wave * 16 + row;
@@ -383,7 +387,7 @@ __global__ void __launch_bounds__(256) k_rom_project_lds(const InstDev* __restri
   // every run of v the wave needs first (clamped addresses), then the
   // regions of their cells, then sigma_s: three rounds of loads, each all in
   // flight together, and the basis chunk while the last is
-  constexpr int NS = PM_DOF / 32, NC = 8 / NL;  // steps; cells per run
+  constexpr int NS = PJL_DOF / 32, NC = 8 / NL;  // steps; cells per run
   double a[NS][8];
 #pragma unroll
   for (int st = 0; st < NS; ++st) {  // steps past the chunk's end add zeros
@@ -416,7 +420,7 @@ __global__ void __launch_bounds__(256) k_rom_project_lds(const InstDev* __restri
         for (int i = 0; i < NL; ++i) a[st][q * NL + i] *= sg;
       }
   }
-  stage_basis_mfma_b<PM_DOF>(W, r, nd, e0, ne, Wl);
+  stage_basis_mfma_b<PJL_DOF>(W, r, nd, e0, ne, Wl);
   __syncthreads();
   rom_d4 acc[4];
 #pragma unroll
@@ -445,18 +449,26 @@ __global__ void __launch_bounds__(256) k_rom_project_lds(const InstDev* __restri
   }
 }
 
-// g[b][k] = the sum over chunks of part, one wave per instance (lane k), the
-// chunks summed in order (the result of k_rom_gsum).
-__global__ void __launch_bounds__(64) k_rom_gsum_wave(int n, int nch, const RomDev* __restrict__ tab,
-                                                      const double* __restrict__ part, double* __restrict__ g,
-                                                      const int32_t* __restrict__ active) {
-  const int b = blockIdx.x, k = threadIdx.x;
-  if ((active && !active[b]) || k >= tab[b].r) return;
-  const double* pb = part + (int64_t)b * nch * ROM_RMAX + k;
+// g[b][k] = the sum over chunks of part, four waves per instance: wave q sums
+// the q-th quarter of the chunks in order (lane k: basis column k), and wave
+// 0 adds the four quarter sums in order.
+__global__ void __launch_bounds__(256) k_rom_gsum4(int n, int nch, const RomDev* __restrict__ tab,
+                                                   const double* __restrict__ part, double* __restrict__ g,
+                                                   const int32_t* __restrict__ active) {
+  __shared__ double qs[3][64];
+  const int b = blockIdx.x, k = threadIdx.x & 63, q = threadIdx.x >> 6;
+  if (active && !active[b]) return;  // the whole work group
+  const int r = tab[b].r;
+  const int c0 = (int)((int64_t)nch * q / 4), c1 = (int)((int64_t)nch * (q + 1) / 4);
   double t = 0.0;
+  if (k < r) {
+    const double* pb = part + (int64_t)b * nch * ROM_RMAX + k;
 #pragma unroll 8
-  for (int c = 0; c < nch; ++c) t += pb[(int64_t)c * ROM_RMAX];
-  g[(int64_t)b * ROM_RMAX + k] = t;
+    for (int c = c0; c < c1; ++c) t += pb[(int64_t)c * ROM_RMAX];
+  }
+  if (q > 0) qs[q - 1][k] = t;
+  __syncthreads();
+  if (q == 0 && k < r) g[(int64_t)b * ROM_RMAX + k] = ((t + qs[0][k]) + qs[1][k]) + qs[2][k];
 }
 
 __global__ void k_rom_gsum(int n, int nch, const RomDev* __restrict__ tab, const double* __restrict__ part,
@@ -740,7 +752,7 @@ __device__ __forceinline__ void stage_basis_mfma_lift(const double* __restrict__
 }
 
 // The lift with each basis chunk shared by the four waves of a work group:
-// 64 instances (16 per wave, as k_rom_lift_mfma) and one chunk of PL_DOF
+// 64 instances (16 per wave, as k_rom_lift_mfma) and one chunk of LFL_DOF
 // DoFs per work group, the chunk of every basis vector staged in LDS once.
 // v is read at clamped addresses (no branch around a load); only the stores
 // of z are conditional.
@@ -750,8 +762,8 @@ __global__ void __launch_bounds__(256) k_rom_lift_lds(const InstDev* __restrict_
                                                       const double* __restrict__ c, double* __restrict__ z,
                                                       const int32_t* __restrict__ active) {
   extern __shared__ double Wl[];  // the basis chunk in the order of the steps (stage_basis_mfma_lift)
-  const int e0 = blockIdx.x * PL_DOF;
-  const int ne = min(PL_DOF, nd - e0);
+  const int e0 = blockIdx.x * LFL_DOF;
+  const int ne = min(LFL_DOF, nd - e0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, kq = lane >> 4;
   const int g0 = blockIdx.y * 64 + wave * 16;
@@ -773,10 +785,10 @@ __global__ void __launch_bounds__(256) k_rom_lift_lds(const InstDev* __restrict_
   const int ns = (r + 3) >> 2;
   // every value of v the wave needs first (clamped addresses), so that the
   // loads are all in flight together
-  double vv[PL_DOF / 16][4];
+  double vv[LFL_DOF / 16][4];
   const double* vs = v ? v : z;  // without v: any valid address, the values are dropped
 #pragma unroll
-  for (int t = 0; t < PL_DOF / 16; ++t)
+  for (int t = 0; t < LFL_DOF / 16; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int e = e0 + t * 16 + row;
@@ -785,14 +797,14 @@ __global__ void __launch_bounds__(256) k_rom_lift_lds(const InstDev* __restrict_
     }
   if (!v)
 #pragma unroll
-    for (int t = 0; t < PL_DOF / 16; ++t)
+    for (int t = 0; t < LFL_DOF / 16; ++t)
 #pragma unroll
       for (int j = 0; j < 4; ++j) vv[t][j] = 0.0;
   // the basis chunk while those loads are in flight
-  stage_basis_mfma_lift<PL_DOF>(W, r, nd, e0, ne, Wl);
+  stage_basis_mfma_lift<LFL_DOF>(W, r, nd, e0, ne, Wl);
   __syncthreads();
 #pragma unroll
-  for (int t = 0; t < PL_DOF / 16; ++t) {  // past the chunk's end no store
+  for (int t = 0; t < LFL_DOF / 16; ++t) {  // past the chunk's end no store
     const int el = t * 16 + row;
     const int e = e0 + el;
     rom_d4 acc = rom_d4{0.0, 0.0, 0.0, 0.0};
@@ -1307,7 +1319,7 @@ bool rom_matches(const rte_rom* rom, const rte_batch* b) {
 
 // partial sums per instance of either projection kernel
 static int64_t rom_part_elems(const rte_batch* b, int64_t nd) {
-  return (int64_t)b->n_inst * ((nd + PM_DOF - 1) / PM_DOF) * ROM_RMAX;
+  return (int64_t)b->n_inst * ((nd + PJL_DOF - 1) / PJL_DOF) * ROM_RMAX;  // the shorter chunk
 }
 
 int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const double* v, double* g,
@@ -1326,10 +1338,10 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
     v = sc->sv;
     sigma_s = nullptr;
   }
-  // the LDS-staged kernel may take up to ROM_RMAX x PM_DOF doubles (128 KiB)
+  // the LDS-staged kernel may take up to ROM_RMAX x PJL_DOF doubles
   static int lds_ok = -1;
   if (lds_ok < 0) {
-    const int bytes = (int)(sizeof(double) * ROM_RMAX * PM_DOF);
+    const int bytes = (int)(sizeof(double) * ROM_RMAX * PJL_DOF);
     lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rom_project_lds<4>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess &&
                      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rom_project_lds<2>),
@@ -1340,9 +1352,9 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
   }
   if (lds_ok && !rom->is_set() && nd < (1 << 30) && (nd & 1) == 0) {
     // the basis chunk staged in LDS, shared by 64 instances
-    const int nchm = (int)((nd + PM_DOF - 1) / PM_DOF);
+    const int nchm = (int)((nd + PJL_DOF - 1) / PJL_DOF);
     const dim3 grid(nchm, (b->n_inst + 63) / 64);
-    const size_t lds = sizeof(double) * 16 * ((rom->r + 15) / 16) * PM_DOF;
+    const size_t lds = sizeof(double) * 16 * ((rom->r + 15) / 16) * PJL_DOF;
     const double* Wp = which ? rom->Ww : rom->W1;
     if (b->inst[0].nloc == 4)
       hipLaunchKernelGGL(k_rom_project_lds<4>, grid, dim3(256), lds, s, b->d_inst, b->d_region, sigma_s,
@@ -1350,7 +1362,7 @@ int rom_project(const rte_rom* rom, rte_batch* b, const double* sigma_s, const d
     else
       hipLaunchKernelGGL(k_rom_project_lds<2>, grid, dim3(256), lds, s, b->d_inst, b->d_region, sigma_s,
                          b->max_regions, Wp, rom->r, (int)nd, b->n_inst, v, sc->part, nchm, active);
-    hipLaunchKernelGGL(k_rom_gsum_wave, dim3(b->n_inst), dim3(64), 0, s, b->n_inst, nchm, tab, sc->part, g,
+    hipLaunchKernelGGL(k_rom_gsum4, dim3(b->n_inst), dim3(256), 0, s, b->n_inst, nchm, tab, sc->part, g,
                        active);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
@@ -1385,20 +1397,20 @@ int rom_lift(const rte_rom* rom, rte_batch* b, const double* v, const double* c,
   if (!sc) return RTE_ENOMEM;
   const RomDev* tab = rom_table(rom, sc, b, s);
   if (!tab) return RTE_EHIP;
-  static int lds_ok = -1;  // up to ROM_RMAX x PL_DOF doubles (128 KiB) of LDS
+  static int lds_ok = -1;  // up to ROM_RMAX x LFL_DOF doubles of LDS
   if (lds_ok < 0) {
     lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rom_lift_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)(sizeof(double) * ROM_RMAX * PL_DOF)) == hipSuccess
+                                 (int)(sizeof(double) * ROM_RMAX * LFL_DOF)) == hipSuccess
                  ? 1
                  : 0;
     if (!lds_ok) (void)hipGetLastError();
   }
   if (lds_ok && !rom->is_set() && nd < (1 << 30) && (nd & 1) == 0) {
     // the basis chunk staged in LDS, shared by 64 instances
-    const int nw = (int)((nd + PL_DOF - 1) / PL_DOF);
+    const int nw = (int)((nd + LFL_DOF - 1) / LFL_DOF);
     hipLaunchKernelGGL(k_rom_lift_lds, dim3(nw, (b->n_inst + 63) / 64), dim3(256),
-                       sizeof(double) * 4 * ((rom->r + 3) / 4) * PL_DOF,
+                       sizeof(double) * 4 * ((rom->r + 3) / 4) * LFL_DOF,
                        s, b->d_inst, rom->Ww, rom->r, (int)nd, b->n_inst, v, c, z, active);
     RTE_HIP(hipGetLastError());
     return RTE_OK;
