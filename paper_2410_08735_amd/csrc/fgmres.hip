@@ -164,12 +164,24 @@ __global__ void k_source_plus(const InstDev* __restrict__ insts, const int32_t* 
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const InstDev I = insts[b];
-  const int64_t nd = (int64_t)I.nx * I.ny * I.nloc;
+  const int ncell = I.nx * I.ny, nl = I.nloc;
   const double* __restrict__ ss = sigma_s + (int64_t)b * max_regions;
   const int32_t* __restrict__ reg = region + I.region_off;
-  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t o = I.dof_off + d;
-    q[o] = G[o] + ss[reg[d / I.nloc]] * phi[o];
+  // a cell per thread: its region's sigma_s once, its DoFs as 16-byte pairs
+  // where they are aligned
+  const bool pairs = (nl & 1) == 0 && (I.dof_off & 1) == 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+    const double sc = ss[reg[c]];
+    const int64_t o = I.dof_off + (int64_t)c * nl;
+    if (pairs) {
+      for (int k = 0; k < nl; k += 2) {
+        const double2 g = *reinterpret_cast<const double2*>(G + o + k);
+        const double2 f = *reinterpret_cast<const double2*>(phi + o + k);
+        *reinterpret_cast<double2*>(q + o + k) = make_double2(g.x + sc * f.x, g.y + sc * f.y);
+      }
+    } else {
+      for (int k = 0; k < nl; ++k) q[o + k] = G[o + k] + sc * phi[o + k];
+    }
   }
 }
 
@@ -491,9 +503,9 @@ int Fgmres::solve(const SolveCtx& c, double* phi, rte_solve_stats* stats, hipStr
         RTE_TRY(kcopy(K.sp, c.G, r, cyc, s));
         RTE_TRY(field_apply(b, c.sigma_s, phi, r, true, cyc, s));
       } else {
-        int max_nd = 0;
-        for (const auto& I : b->inst) max_nd = std::max(max_nd, I.nx * I.ny * I.nloc);
-        hipLaunchKernelGGL(k_source_plus, dim3(std::min((max_nd + 255) / 256, 1024), n), dim3(256), 0, s,
+        int max_cells = 0;
+        for (const auto& I : b->inst) max_cells = std::max(max_cells, I.nx * I.ny);
+        hipLaunchKernelGGL(k_source_plus, dim3(std::min((max_cells + 255) / 256, 1024), n), dim3(256), 0, s,
                            b->d_inst, b->d_region, c.sigma_s, b->max_regions, c.G, phi, r, cyc);
         RTE_HIP(hipGetLastError());
       }
