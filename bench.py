@@ -42,14 +42,14 @@ PEAK_HBM = 8.0e12             # MI355X published HBM3E bandwidth, B/s
 # counter passes scaled by what the counters read for a 512 MiB copy, keyed by
 # (variant, G, ordinates per lane, threads) and valid for the kernel version
 # SWEEP_KERNEL_VERSION the passes measured (profiles/sweep2d_f32_cfg3_96sq_b256_hbm_traffic.md).
-SWEEP_KERNEL_VERSION = "rows-v2"
+SWEEP_KERNEL_VERSION = "rows-v3"
 SWEEP_F32_TRAFFIC_BYTES = {
-    # FETCH_SIZE 107992.1 KiB x 1.9999 + WRITE_SIZE 193117.9 KiB x 1.0
-    ("rows-v2", 1, 8, 4, 768): 409091.7 * 1024,
+    # FETCH_SIZE 109901.9 KiB x 1.9999 + WRITE_SIZE 199229.4 KiB x 1.0
+    ("rows-v3", 1, 8, 4, 768): 419019.4 * 1024,
 }
 # VALU lane instructions per cell-ordinate of a full launch (SQ_INSTS_VALU x 64
 # / cell-ordinates, profiles/sweep2d_f32_cfg3_96sq_b256_sq_counters.md)
-SWEEP_F32_VALU_LANE_INSTS = {("rows-v2", 1, 8, 4, 768): 210038784.0 * 64 / 301989888.0}
+SWEEP_F32_VALU_LANE_INSTS = {("rows-v3", 1, 8, 4, 768): 201327616.0 * 64 / 301989888.0}
 # Algorithmic HBM bytes per cell and instance of one sweep: read the 4 source
 # moments (FP64, 32 B), write the 4 scalar-flux moments (FP64, 32 B), and the
 # cell's cross-section data (8 B).  Angular fluxes never leave the chip.

@@ -362,14 +362,47 @@ __device__ __forceinline__ void cell_update_wave(const LaneOrds<real, OPL>& L, i
 // The group's quadrature sum, written once per cell in physical orientation.
 template <typename real, int G>
 __device__ __forceinline__ void store_partial(real c[4], int g, real mx, real my, real* P, int64_t cell) {
+  if constexpr (G == 4 || G == 8) {
+    // a reduce-scatter: each exchange halves the moments a lane carries (4
+    // exchanges for G = 8 instead of 12), and the lanes that end with a
+    // moment's sum store it.  First exchange: the partner differs in the
+    // group's top lane bit; a lane keeps moments {0, 1} (bit clear) or {2, 3}.
+    const bool hi = (g & (G / 2)) != 0;
+    real ka = hi ? c[2] : c[0], kb = hi ? c[3] : c[1];
+    const real sa = hi ? c[0] : c[2], sb = hi ? c[1] : c[3];
+    if constexpr (G == 8) {  // half-row mirror: lane g with 7 - g
+      ka += dpp_move<0x141>(sa);
+      kb += dpp_move<0x141>(sb);
+    } else {  // lane g with g ^ 2
+      ka += dpp_move<0x4E>(sa);
+      kb += dpp_move<0x4E>(sb);
+    }
+    // second exchange: the partner differs in the next bit; a lane keeps
+    // moment 2 hi + mid
+    const bool mid = (g & (G / 4)) != 0;
+    real k = mid ? kb : ka;
+    const real sk = mid ? ka : kb;
+    if constexpr (G == 8) {
+      k += dpp_move<0x4E>(sk);
+      k += dpp_move<0xB1>(k);  // the two lanes of a pair hold the same moment
+    } else {
+      k += dpp_move<0xB1>(sk);
+    }
+    const int m = (hi ? 2 : 0) + (mid ? 1 : 0);
+    if (G == 4 || (g & 1) == 0) {
+      const real f = ((m & 1) ? mx : (real)1) * ((m & 2) ? my : (real)1);
+      P[4 * cell + m] = f * k;
+    }
+  } else {
 #pragma unroll
-  for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(c[d]);
-  if (g == 0) {
-    real* o = P + 4 * cell;
-    o[0] = c[0];
-    o[1] = mx * c[1];
-    o[2] = my * c[2];
-    o[3] = mx * my * c[3];
+    for (int d = 0; d < 4; ++d) c[d] = group_sum<G, real>(c[d]);
+    if (g == 0) {
+      real* o = P + 4 * cell;
+      o[0] = c[0];
+      o[1] = mx * c[1];
+      o[2] = my * c[2];
+      o[3] = mx * my * c[3];
+    }
   }
 }
 
