@@ -1534,6 +1534,16 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
                                                      double* __restrict__ zout = nullptr) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
+  // every level's descriptor and stencil scalars, loaded once by one thread
+  // per level (the phases below would otherwise each start with a chain of
+  // dependent global loads)
+  __shared__ LvlInst lvl[MG_TAIL_MAX];
+  __shared__ SymCoef<real> scf[MG_TAIL_MAX];
+  if ((int)threadIdx.x < nlev) {
+    lvl[threadIdx.x] = tl[threadIdx.x].li[b];
+    scf[threadIdx.x] = sym_coef<real>(tl[threadIdx.x].st[b]);
+  }
+  __syncthreads();
   extern __shared__ unsigned char smem_raw[];
   real* lds = reinterpret_cast<real*>(smem_raw);
   // per level: offsets of x, b and the cross sections in LDS (-1: not in LDS)
@@ -1542,7 +1552,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     if (!g0) {
       int o = 0;
       for (int l = 0; l < nlev; ++l) {
-        const LvlInst Li = tl[l].li[b];
+        const LvlInst Li = lvl[l];
         const int nc = Li.nx * Li.ny;
         xo[l] = o;
         bo[l] = o + 12 * nc;
@@ -1553,16 +1563,16 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
     } else {
       int o = 0;
       for (int l = 1; l < nlev; ++l) {
-        const LvlInst Li = tl[l].li[b];
+        const LvlInst Li = lvl[l];
         so[l] = o;
         o += 2 * Li.nx * Li.ny;
       }
-      const LvlInst L1 = tl[1].li[b];
+      const LvlInst L1 = lvl[1];
       xo[1] = o;
       o += 12 * L1.nx * L1.ny;
       r_off = o;  // R: the first level's x, later the coarser levels' b and x
       for (int l = 1; l < nlev; ++l) {
-        const LvlInst Li = tl[l].li[b];
+        const LvlInst Li = lvl[l];
         const int nc = Li.nx * Li.ny;
         bo[l] = o;
         o += 12 * nc;
@@ -1578,7 +1588,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
   }
   __syncthreads();
   for (int l = g0 ? 1 : 0; l < nlev; ++l) {  // cross sections of the LDS levels, once
-    const LvlInst Li = tl[l].li[b];
+    const LvlInst Li = lvl[l];
     const int nc = Li.nx * Li.ny;
     real* sg = lds + so[l];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -1586,7 +1596,7 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
       sg[nc + c] = (real)tl[l].sigs[Li.cell_off + c];
     }
   }
-  const LvlInst L0 = tl[0].li[b];
+  const LvlInst L0 = lvl[0];
   const int nc0 = L0.nx * L0.ny;
   if (!g0) {  // b of the first level
     const real* src = b_first + L0.cell_off * 12;
@@ -1595,8 +1605,8 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
   __syncthreads();
   // down: pre-smooth from zero, then residual -> next level's b
   for (int l = 0; l + 1 < nlev; ++l) {
-    const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
-    const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    const LvlInst L = lvl[l], C = lvl[l + 1];
+    const SymCoef<real> S = scf[l];
     const int nc = L.nx * L.ny, ncc = C.nx * C.ny;
     real* x = lds + xo[l];
     if (g0 && l == 0) {
@@ -1623,16 +1633,16 @@ __global__ void __launch_bounds__(NT) k_mg_tail_sym(const MgTailLevel* __restric
   }
   {  // coarsest: red-black sweeps from zero
     const int l = nlev - 1;
-    const LvlInst L = tl[l].li[b];
-    const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    const LvlInst L = lvl[l];
+    const SymCoef<real> S = scf[l];
     const int nc = L.nx * L.ny;
     const real* sgt = lds + so[l];
     for (int k = 0; k < coarse_sweeps; ++k) tail_sweep_lds(S, L, sgt, sgt + nc, lds + bo[l], lds + xo[l], k == 0);
   }
   // up: prolong the correction, post-smooth in reverse colour order
   for (int l = nlev - 2; l >= 0; --l) {
-    const LvlInst L = tl[l].li[b], C = tl[l + 1].li[b];
-    const SymCoef<real> S = sym_coef<real>(tl[l].st[b]);
+    const LvlInst L = lvl[l], C = lvl[l + 1];
+    const SymCoef<real> S = scf[l];
     const int nc = L.nx * L.ny;
     real* x = lds + xo[l];
     const real* xc = lds + xo[l + 1];
